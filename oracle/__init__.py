@@ -1,0 +1,219 @@
+"""FP64 CPU oracle for the log-polar thin-disk self-gravity method.
+
+TEST INFRASTRUCTURE ONLY.  This package is the independent checker of the HIP
+library: only the test suite, ``__graft_entry__.smoke()`` and the CPU baseline
+leg of ``bench.py`` may import it.  It shares no code with the library and the
+library never imports it.
+
+The arithmetic lives in ``pf_oracle.c`` (plain C + OpenMP, FP64); this module
+only builds and loads it and marshals numpy arrays.  Each wrapper names the
+paper passage that the C function follows (Wang, Yen & Taam,
+arXiv:1509.01450).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "pf_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+TABLE_NAMES = ("r0", "rr", "rphi", "phi0", "phir", "phiphi")
+
+
+def build(force: bool = True) -> str:
+    """Compile ``pf_oracle.c`` into ``liboracle.so`` (gcc, -O2, OpenMP)."""
+    if not force and os.path.exists(_LIB_PATH):
+        return _LIB_PATH
+    tmp = _LIB_PATH + ".tmp%d" % os.getpid()
+    cmd = ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c11",
+           "-Wall", "-Wno-unknown-pragmas", _SRC, "-o", tmp, "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        build()
+    lib = ctypes.CDLL(_LIB_PATH)
+    d, i, i64 = ctypes.c_double, ctypes.c_int, ctypes.c_int64
+    P = ctypes.c_void_p
+    lib.or_geometry.argtypes = [i, i, d, d, P, P, P, P]
+    lib.or_gauss_legendre.argtypes = [i, P, P]
+    lib.or_selfcell_cover.argtypes = [d, d, i, P, P]
+    lib.or_table_entry.argtypes = [i, i, d, d, i, i, i, P, P]
+    lib.or_tables.argtypes = [i, i, d, d, i, P, P]
+    lib.or_channels.argtypes = [i, i, P, d, P, P, P]
+    lib.or_forward.argtypes = [i, i, d, d, P, P, P, i64, P, P]
+    lib.or_adjoint.argtypes = [i, i, d, d, P, P, P, P, i64, P]
+    for f in ("or_geometry", "or_gauss_legendre", "or_selfcell_cover",
+              "or_table_entry", "or_tables", "or_channels", "or_forward",
+              "or_adjoint", "or_num_threads"):
+        getattr(lib, f).restype = i
+    _lib = lib
+    return lib
+
+
+def _p(a):
+    return a.ctypes.data_as(ctypes.c_void_p) if a is not None else None
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def num_threads() -> int:
+    """OpenMP threads the oracle uses."""
+    return int(_load().or_num_threads())
+
+
+def gauss_legendre(n: int):
+    """n-point Gauss-Legendre nodes and weights on [-1, 1]."""
+    x = np.empty(n)
+    w = np.empty(n)
+    if _load().or_gauss_legendre(n, _p(x), _p(w)):
+        raise ValueError("n out of range")
+    return x, w
+
+
+class Grid:
+    """Log-polar grid of Sec. 3.2.1 generalised to N_r x N_phi."""
+
+    def __init__(self, n_r: int, n_phi: int, r_min: float, r_max: float):
+        self.n_r, self.n_phi = int(n_r), int(n_phi)
+        self.r_min, self.r_max = float(r_min), float(r_max)
+        rc = np.empty(self.n_r)
+        re = np.empty(self.n_r + 1)
+        b = np.empty(1)
+        dp = np.empty(1)
+        if _load().or_geometry(self.n_r, self.n_phi, self.r_min, self.r_max,
+                               _p(rc), _p(re), _p(b), _p(dp)):
+            raise ValueError("bad grid")
+        self.r_centres, self.r_edges = rc, re
+        self.beta, self.dphi = float(b[0]), float(dp[0])
+        self.phi_centres = (np.arange(self.n_phi) + 0.5) * self.dphi
+
+    @property
+    def shape(self):
+        return (self.n_r, self.n_phi)
+
+    def cell_areas(self):
+        """Exact polar cell areas (r_out^2 - r_in^2) dphi / 2."""
+        re = self.r_edges
+        a = 0.5 * (re[1:] ** 2 - re[:-1] ** 2) * self.dphi
+        return np.repeat(a[:, None], self.n_phi, axis=1)
+
+    def xy(self):
+        r = self.r_centres[:, None]
+        p = self.phi_centres[None, :]
+        return r * np.cos(p), r * np.sin(p)
+
+
+def selfcell_cover(beta: float, dphi: float, per: int = 10):
+    """Self-cell kernels by the Cartesian cover (Sec. 4, Eq. 44-46).
+
+    Returns (K^{r,0}_{00}, K^{r,r}_{00}, K^{phi,phi}_{00}, n_cells)."""
+    out = np.empty(3)
+    n = np.zeros(1, dtype=np.int64)
+    if _load().or_selfcell_cover(float(beta), float(dphi), int(per), _p(out), _p(n)):
+        raise ValueError("bad cover arguments")
+    return float(out[0]), float(out[1]), float(out[2]), int(n[0])
+
+
+def table_entry(grid: Grid, m: int, n_rep: int, n_tpz: int = 19, self_k=None):
+    """All six kernels for offset (m, n_rep) (Eq. 30-32, 41-43, A22-A24).
+
+    ``self_k`` supplies the three self-cell constants used at (0, 0)."""
+    sk = _f64(self_k if self_k is not None else np.zeros(3))
+    t = np.empty(6)
+    if _load().or_table_entry(grid.n_r, grid.n_phi, grid.r_min, grid.r_max,
+                              int(n_tpz), int(m), int(n_rep), _p(sk), _p(t)):
+        raise ValueError("bad arguments")
+    return t
+
+
+def tables(grid: Grid, n_tpz: int = 19, cover_per: int = 10, self_k=None):
+    """Six kernel tables, shape (6, 2 N_r - 1, N_phi); row m + N_r - 1,
+    column n = (j - j') mod N_phi; order r0, rr, rphi, phi0, phir, phiphi.
+
+    The self cell comes from :func:`selfcell_cover` unless ``self_k`` is
+    given."""
+    if self_k is None:
+        self_k = selfcell_cover(grid.beta, grid.dphi, cover_per)[:3]
+    sk = _f64(self_k)
+    T = np.empty((6, 2 * grid.n_r - 1, grid.n_phi))
+    if _load().or_tables(grid.n_r, grid.n_phi, grid.r_min, grid.r_max,
+                         int(n_tpz), _p(sk), _p(T)):
+        raise ValueError("bad arguments")
+    return T
+
+
+def channels(grid: Grid, sigma):
+    """Radial and azimuthal slopes of Eq. 25 by central differences
+    (one-sided on the first and last rows)."""
+    s = _f64(sigma)
+    dr = np.empty_like(s)
+    dp = np.empty_like(s)
+    if _load().or_channels(grid.n_r, grid.n_phi, _p(grid.r_centres),
+                           grid.dphi, _p(s), _p(dr), _p(dp)):
+        raise ValueError("bad grid")
+    return dr, dp
+
+
+def forward(grid: Grid, T, sigma, dest=None):
+    """F_r, F_phi by the plain double sums of Eq. 27-29 and A19-A21.
+
+    ``dest``: optional flat destination indices i * N_phi + j; returns the
+    forces at those cells (1-D) or on the whole grid (2-D)."""
+    s = _f64(sigma)
+    T = _f64(T)
+    assert s.shape == grid.shape and T.shape == (6, 2 * grid.n_r - 1, grid.n_phi)
+    if dest is None:
+        fr = np.empty(grid.shape)
+        fp = np.empty(grid.shape)
+        d, nd = None, 0
+    else:
+        d = np.ascontiguousarray(dest, dtype=np.int64)
+        nd = d.size
+        fr = np.empty(nd)
+        fp = np.empty(nd)
+    rc = _load().or_forward(grid.n_r, grid.n_phi, grid.r_min, grid.r_max,
+                            _p(T), _p(s), _p(d), nd, _p(fr), _p(fp))
+    if rc:
+        raise RuntimeError("or_forward failed (%d)" % rc)
+    return fr, fp
+
+
+def adjoint(grid: Grid, T, v_r, v_phi, src=None):
+    """Transpose of :func:`forward` applied to cotangents (v_r, v_phi), as a
+    plain double sum, at flat source indices ``src`` (or every cell)."""
+    vr, vp, T = _f64(v_r), _f64(v_phi), _f64(T)
+    assert vr.shape == grid.shape and vp.shape == grid.shape
+    if src is None:
+        g = np.empty(grid.shape)
+        s, ns = None, 0
+    else:
+        s = np.ascontiguousarray(src, dtype=np.int64)
+        ns = s.size
+        g = np.empty(ns)
+    rc = _load().or_adjoint(grid.n_r, grid.n_phi, grid.r_min, grid.r_max,
+                            _p(T), _p(vr), _p(vp), _p(s), ns, _p(g))
+    if rc:
+        raise RuntimeError("or_adjoint failed (%d)" % rc)
+    return g
+
+
+def error_norms(num, ana):
+    """L1, L2 and L-infinity error norms of Eq. 47-49 over all cells."""
+    e = np.abs(np.asarray(num, dtype=np.float64) - np.asarray(ana, dtype=np.float64))
+    n = e.size
+    return float(e.sum() / n), float(np.sqrt((e * e).sum() / n)), float(e.max())

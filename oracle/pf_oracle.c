@@ -1,0 +1,748 @@
+/*
+ * pf_oracle.c -- plain, slow FP64 CPU reference for the log-polar thin-disk
+ * self-gravity method of Wang, Yen & Taam, "Self-Gravitational Force
+ * Calculation of Second Order Accuracy for Infinitesimally Thin Gaseous Disks
+ * in Polar Coordinates" (arXiv:1509.01450).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the independent checker of the HIP
+ * library.  Only the test suite, the smoke check and the benchmark's CPU
+ * baseline may load it.  It shares no code, header, table or constant
+ * generator with the library, and the library never calls it.
+ *
+ * What it computes (all FP64, G = 1):
+ *   - the log-polar grid (Sec. 3.2.1);
+ *   - the six force-kernel tables K^{r,0}, K^{r,r}, K^{r,phi}, K^{phi,0},
+ *     K^{phi,r}, K^{phi,phi} (Eq. 30-32, A22-A24) as the paper's singular
+ *     integration method (SIM, Sec. 4) defines them: N_tpz trapezoids in the
+ *     azimuth applied to the exact radial integral (Eq. 41-43), exact double
+ *     antiderivatives for K^{phi,0} and K^{phi,r} (A30-A31), and the self cell
+ *     from a Cartesian cover evaluated with the Cartesian second-order method
+ *     (Eq. 44-46, Eq. 9-15, A8-A13);
+ *   - the cell density and slopes (Eq. 25, central differences);
+ *   - the forces as the plain double sums of Eq. 27-29 and A19-A21,
+ *     O((N_r N_phi)^2), at any chosen set of destination cells;
+ *   - the transpose of that linear map, as a plain double sum, at any chosen
+ *     set of source cells.
+ *
+ * Index conventions (0-based).  Radial cell i spans
+ * [r_min beta^i, r_min beta^(i+1)], centre r_i = r_min beta^i (1+beta)/2 (the
+ * arithmetic mean of its edges, Sec. 3.2.1).  Azimuthal cell j spans
+ * [j dphi, (j+1) dphi], centre (j+1/2) dphi.  Tables are indexed by the offset
+ * m = i - i' (destination minus source), m in [-(N_r-1), N_r-1], stored at row
+ * m + N_r - 1, and by n = (j - j') mod N_phi.  With eta = rbar / r_i and
+ * xi = phibar - phi_j (Eq. 33), source cell (i', j') maps to
+ *   eta in [2 beta^-m/(1+beta), 2 beta^(1-m)/(1+beta)],
+ *   xi  in [xi_c - dphi/2, xi_c + dphi/2],  xi_c = -n_rep dphi,
+ * where n_rep is the representative of n in (-N_phi/2, N_phi/2].  The local
+ * slope weight (phibar - phi_j') is xi - xi_c.
+ *
+ * Readings of the paper that this file takes (every one is listed in the
+ * design notes of the repository):
+ *   - a rectangular N_r x N_phi grid: beta from N_r, dphi from N_phi;
+ *   - one grid [r_min, r_max]; mass inside r_min is not modelled;
+ *   - one-sided two-point radial differences on the first and last rows;
+ *   - the trapezoid rule acts on the whole azimuthal integrand including the
+ *     local weight (xi - xi_c), so every table depends on (m, n) only;
+ *   - H^phi_2 uses cos(xi) (the printed cos(phi) is a typo);
+ *   - Cartesian cover of the self cell: cell sizes Delta x / per and
+ *     Delta y / per (per = 10 by default), grid aligned so the fan centre is a
+ *     cell centre, a cell kept iff its centre lies in the closed fan, and the
+ *     test densities' slopes taken analytically at the Cartesian centres.
+ *
+ * Numerical evaluation of the exact integrals.  Where the paper's closed
+ * antiderivatives lose digits to cancellation (far from the singular point
+ * eta = 1, xi = 0, or near xi = +-pi for H^phi_3), the same exact integral is
+ * evaluated by Gauss-Legendre quadrature of an integrand that is analytic on
+ * the interval; the rule used is stated at each function.
+ */
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#include <stdint.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define OR_PI 3.14159265358979323846264338327950288
+
+/* ------------------------------------------------------------------------ */
+/* Gauss-Legendre nodes on [-1, 1] by Newton iteration on P_n (textbook).    */
+/* ------------------------------------------------------------------------ */
+#define GL_MAX 32
+static double gl_x[GL_MAX + 1][GL_MAX];
+static double gl_w[GL_MAX + 1][GL_MAX];
+static int gl_ready = 0;
+
+static void gl_compute(int n, double *x, double *w)
+{
+    for (int i = 0; i < n; ++i) {
+        long double z = cosl((long double)OR_PI * (i + 0.75L) / (n + 0.5L));
+        long double dp = 0;
+        for (int it = 0; it < 100; ++it) {
+            long double p0 = 1, p1 = z;
+            for (int k = 2; k <= n; ++k) {
+                long double p2 = ((2 * k - 1) * z * p1 - (k - 1) * p0) / k;
+                p0 = p1;
+                p1 = p2;
+            }
+            if (n == 1) { p1 = z; p0 = 1; }
+            dp = n * (z * p1 - p0) / (z * z - 1);
+            long double dz = p1 / dp;
+            z -= dz;
+            if (fabsl(dz) < 1e-19L) break;
+        }
+        {
+            long double p0 = 1, p1 = z;
+            for (int k = 2; k <= n; ++k) {
+                long double p2 = ((2 * k - 1) * z * p1 - (k - 1) * p0) / k;
+                p0 = p1;
+                p1 = p2;
+            }
+            if (n == 1) { p1 = z; p0 = 1; }
+            dp = n * (z * p1 - p0) / (z * z - 1);
+        }
+        x[i] = (double)z;
+        w[i] = (double)(2 / ((1 - z * z) * dp * dp));
+    }
+}
+
+static void gl_init(void)
+{
+    if (gl_ready) return;
+#ifdef _OPENMP
+#pragma omp critical(or_gl_init)
+#endif
+    {
+        if (!gl_ready) {
+            for (int n = 1; n <= GL_MAX; ++n) gl_compute(n, gl_x[n], gl_w[n]);
+            gl_ready = 1;
+        }
+    }
+}
+
+int or_gauss_legendre(int n, double *x, double *w)
+{
+    if (n < 1 || n > GL_MAX) return -1;
+    gl_init();
+    memcpy(x, gl_x[n], sizeof(double) * n);
+    memcpy(w, gl_w[n], sizeof(double) * n);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Compensated (Neumaier) accumulator.                                       */
+/* ------------------------------------------------------------------------ */
+typedef struct { double s, c; } acc_t;
+static inline void acc_add(acc_t *a, double x)
+{
+    double t = a->s + x;
+    if (fabs(a->s) >= fabs(x)) a->c += (a->s - t) + x;
+    else a->c += (x - t) + a->s;
+    a->s = t;
+}
+static inline double acc_get(const acc_t *a) { return a->s + a->c; }
+
+/* ------------------------------------------------------------------------ */
+/* Grid (Sec. 3.2.1, generalised to N_r x N_phi).                             */
+/* ------------------------------------------------------------------------ */
+int or_geometry(int n_r, int n_phi, double r_min, double r_max,
+                double *r_centres, double *r_edges, double *beta_out,
+                double *dphi_out)
+{
+    if (n_r < 1 || n_phi < 1 || !(r_min > 0) || !(r_max > r_min)) return -1;
+    double beta = pow(r_max / r_min, 1.0 / n_r);
+    if (r_edges)
+        for (int i = 0; i <= n_r; ++i) r_edges[i] = r_min * pow(beta, i);
+    if (r_centres)
+        for (int i = 0; i < n_r; ++i) {
+            double lo = r_min * pow(beta, i), hi = r_min * pow(beta, i + 1);
+            r_centres[i] = 0.5 * (lo + hi);
+        }
+    if (beta_out) *beta_out = beta;
+    if (dphi_out) *dphi_out = 2.0 * OR_PI / n_phi;
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Polar kernel pieces in eta = rbar/r_i, xi = phibar - phi_j (Eq. 33).       */
+/* F(eta, xi) = sqrt(eta^2 - 2 eta cos xi + 1), written as                   */
+/* sqrt((eta-1)^2 + 4 eta sin^2(xi/2)) so it keeps its digits near eta = 1.  */
+/* ------------------------------------------------------------------------ */
+static inline double Fpol(double eta, double s_half)
+{
+    double d = eta - 1.0;
+    return sqrt(d * d + 4.0 * eta * s_half * s_half);
+}
+
+/* ln(eta - cos xi + F).  For eta < cos xi the sum cancels, so it is
+ * rationalised with F^2 = (eta - c)^2 + sin^2 xi:
+ * eta - c + F = sin^2 xi / (F - (eta - c)). */
+static inline double Lpol(double eta, double c, double s, double F)
+{
+    double d = eta - c;
+    if (d >= 0) return log(d + F);
+    return log(s * s / (F - d));
+}
+
+/* Antiderivatives of Appendix A (A25-A29), each verified by differentiation:
+ *   d/deta  Hr1 = eta (1 - eta c) / F^3
+ *   d/deta  Hr2 = eta^2 (1 - eta c) / F^3
+ *   d/deta  G3  = eta^2 sin(xi) / F^3       (H^phi_3 = xi * G3)
+ *   d2/deta dxi Hp1 = eta^2 sin(xi) / F^3
+ *   d2/deta dxi Hp2 = eta^3 sin(xi) / F^3                              */
+static inline double Hr1(double eta, double c, double s, double sh)
+{
+    double F = Fpol(eta, sh);
+    return -c * Lpol(eta, c, s, F) + (2.0 * c * eta - 1.0) / F;
+}
+static inline double Hr2(double eta, double c, double s, double sh)
+{
+    double F = Fpol(eta, sh);
+    return -((3.0 * c * c - 1.0) * Lpol(eta, c, s, F)
+             + (-6.0 * eta * c * c + 3.0 * c + eta * eta * c + eta) / F);
+}
+static inline double G3(double eta, double c, double s, double sh)
+{
+    double F = Fpol(eta, sh);
+    double cot2 = (c * c) / (s * s);
+    return s * ((-eta - c + eta * cot2 - c * cot2) / F + Lpol(eta, c, s, F));
+}
+static inline double Hp1(double eta, double xi)
+{
+    double c = cos(xi), s = sin(xi), sh = sin(0.5 * xi);
+    double F = Fpol(eta, sh);
+    return -(F + c * Lpol(eta, c, s, F));
+}
+static inline double Hp2(double eta, double xi)
+{
+    double c = cos(xi), s = sin(xi), sh = sin(0.5 * xi);
+    double F = Fpol(eta, sh);
+    return -((0.5 * eta + 1.5 * c) * F + (1.5 * c * c - 0.5) * Lpol(eta, c, s, F));
+}
+
+/* Exact radial integrals at a fixed azimuth xi:
+ *   Ir  = int eta (1 - eta c)/F^3 deta,
+ *   Ir2 = int eta^2 (1 - eta c)/F^3 deta,
+ *   Iph = int eta^2 sin(xi)/F^3 deta,   over [eta_l, eta_u].
+ * use_closed = 1: differences of Hr1, Hr2, G3 (valid when the radial
+ * interval may contain the singular point but sin(xi) is not small);
+ * use_closed = 0: 24-point Gauss-Legendre, exact to rounding whenever the
+ * interval stays away from eta = 1 by a cell width (|m| >= 1) or xi is far
+ * from 0. */
+static void radial_integrals(double eta_l, double eta_u, double xi,
+                             int use_closed, double *Ir, double *Ir2,
+                             double *Iph)
+{
+    double c = cos(xi), s = sin(xi), sh = sin(0.5 * xi);
+    if (use_closed) {
+        *Ir = Hr1(eta_u, c, s, sh) - Hr1(eta_l, c, s, sh);
+        *Ir2 = Hr2(eta_u, c, s, sh) - Hr2(eta_l, c, s, sh);
+        *Iph = G3(eta_u, c, s, sh) - G3(eta_l, c, s, sh);
+        return;
+    }
+    const int n = 24;
+    const double *x = gl_x[n], *w = gl_w[n];
+    double mid = 0.5 * (eta_u + eta_l), half = 0.5 * (eta_u - eta_l);
+    double a = 0, b = 0, d = 0;
+    for (int k = 0; k < n; ++k) {
+        double eta = mid + half * x[k];
+        double F = Fpol(eta, sh);
+        double iF3 = 1.0 / (F * F * F);
+        double fr = eta * (1.0 - eta * c) * iF3;
+        a += w[k] * fr;
+        b += w[k] * eta * fr;
+        d += w[k] * eta * eta * s * iF3;
+    }
+    *Ir = a * half;
+    *Ir2 = b * half;
+    *Iph = d * half;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Self cell by the Cartesian cover (Sec. 4, Eq. 44-46; Fig. 1).             */
+/* ------------------------------------------------------------------------ */
+
+/* ln(y + sqrt(x^2+y^2)) with the rationalised form for y < 0. */
+static inline double lnp(double y, double x, double rho)
+{
+    if (y >= 0) return log(y + rho);
+    return log(x * x / (rho - y));
+}
+
+/* Closed-form Cartesian cell kernels (A8-A13) for one cell whose edges,
+ * relative to the destination point, are [xl, xu] x [yl, yu]; (X, Y) is the
+ * cell centre relative to the destination.  Output order:
+ * Kx0, Kxx, Kxy, Ky0, Kyy, Kyx. */
+static void cart_closed(double xl, double xu, double yl, double yu, double X,
+                        double Y, double K[6])
+{
+    double xs[2] = {xl, xu}, ys[2] = {yl, yu};
+    double ly = 0, lx = 0, ylx = 0, xly = 0, rr = 0;
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b) {
+            double sgn = (a == b) ? 1.0 : -1.0; /* f|^{xu}_{xl}|^{yu}_{yl} */
+            double x = xs[a], y = ys[b];
+            double rho = sqrt(x * x + y * y);
+            double Ly = lnp(y, x, rho), Lx = lnp(x, y, rho);
+            ly += sgn * Ly;
+            lx += sgn * Lx;
+            ylx += sgn * y * Lx;
+            xly += sgn * x * Ly;
+            rr += sgn * rho;
+        }
+    double Kx0 = -ly, Ky0 = -lx;
+    K[0] = Kx0;
+    K[1] = -X * Kx0 + ylx;
+    K[2] = -Y * Kx0 - rr;
+    K[3] = Ky0;
+    K[4] = -Y * Ky0 + xly;
+    K[5] = -X * Ky0 - rr;
+}
+
+/* Gauss-Legendre order for one direction of a cell of width h whose centre
+ * lies at distance d from the singular point: the error of an n-point rule
+ * falls like (h / 2d)^(2n); the smallest n reaching 1e-17 is taken. */
+static int cover_order(double d, double h)
+{
+    static const int ns[6] = {2, 3, 4, 6, 8, 12};
+    double q = 0.5 * h / d;
+    for (int k = 0; k < 6; ++k)
+        if (pow(q, 2 * ns[k]) < 1e-17) return ns[k];
+    return 0;
+}
+
+/* beta, dphi: grid ratio and azimuthal width; per: Cartesian cells per
+ * Delta x and per Delta y (the paper's rule of thumb is 10).
+ * out[0] = K^{r,0}_{00}, out[1] = K^{r,r}_{00}, out[2] = K^{phi,phi}_{00};
+ * n_cells (optional) = number of Cartesian cells inside the fan. */
+int or_selfcell_cover(double beta, double dphi, int per, double *out,
+                      int64_t *n_cells)
+{
+    if (!(beta > 1) || !(dphi > 0) || per < 1) return -1;
+    gl_init();
+    const double rm = 1.0;                      /* invariance, Eq. 33 */
+    const double dr = 2.0 * (beta - 1.0) / (1.0 + beta);
+    const double r_in = rm - 0.5 * dr, r_out = rm + 0.5 * dr;
+    const double sq = sin(0.25 * dphi);
+    const double Dx = r_in * 2.0 * sq * sq;      /* (r_m - dr/2)(1 - cos(dphi/2)) */
+    const double Dy = dr * sin(0.5 * dphi);      /* dr sin(dphi/2)                */
+    const double hx = Dx / per, hy = Dy / per;
+    const double ch = cos(0.5 * dphi), shf = sin(0.5 * dphi);
+    const long kx0 = (long)ceil((r_in * ch - rm) / hx);
+    const long kx1 = (long)floor((r_out - rm) / hx);
+    const long ky1 = (long)floor(r_out * shf / hy);
+    const double rin2 = r_in * r_in, rout2 = r_out * r_out;
+    const double tanh_ = shf / ch;
+
+    int nth = 1;
+#ifdef _OPENMP
+    nth = omp_get_max_threads();
+#endif
+    acc_t *part = (acc_t *)calloc((size_t)nth * 3, sizeof(acc_t));
+    int64_t *cnt = (int64_t *)calloc((size_t)nth, sizeof(int64_t));
+    if (!part || !cnt) { free(part); free(cnt); return -2; }
+
+#ifdef _OPENMP
+#pragma omp parallel
+#endif
+    {
+        int tid = 0;
+#ifdef _OPENMP
+        tid = omp_get_thread_num();
+#endif
+        acc_t s1 = {0, 0}, s2 = {0, 0}, s3 = {0, 0};
+        int64_t c = 0;
+#ifdef _OPENMP
+#pragma omp for schedule(static)
+#endif
+        for (long kx = kx0; kx <= kx1; ++kx) {
+            double X = kx * hx;
+            double xc = rm + X;
+            for (long ky = -ky1; ky <= ky1; ++ky) {
+                double Y = ky * hy;
+                double yc = Y;
+                double r2 = xc * xc + yc * yc;
+                if (r2 < rin2 || r2 > rout2) continue;
+                if (fabs(yc) > xc * tanh_) continue;
+                ++c;
+                double rc = sqrt(r2);
+                /* test densities (Fig. 1): (a) 1, (b) rbar - r_m, (c) phibar;
+                 * value and analytic slopes at the Cartesian centre */
+                double sig2 = rc - rm, dx2 = xc / rc, dy2 = yc / rc;
+                double sig3 = atan2(yc, xc), dx3 = -yc / r2, dy3 = xc / r2;
+                double d = sqrt(X * X + Y * Y);
+                int nx = 0, ny = 0;
+                if (d > 4.0 * (hx > hy ? hx : hy)) {
+                    nx = cover_order(d, hx);
+                    ny = cover_order(d, hy);
+                }
+                if (nx == 0 || ny == 0) {
+                    double K[6];
+                    cart_closed(X - 0.5 * hx, X + 0.5 * hx, Y - 0.5 * hy,
+                                Y + 0.5 * hy, X, Y, K);
+                    acc_add(&s1, K[0]);
+                    acc_add(&s2, sig2 * K[0] + dx2 * K[1] + dy2 * K[2]);
+                    acc_add(&s3, sig3 * K[3] + dy3 * K[4] + dx3 * K[5]);
+                } else {
+                    /* the same cell integrals by an nx x ny Gauss rule of the
+                     * kernel times the cell's linear density (Eq. 8) */
+                    double a1 = 0, a2 = 0, a3 = 0;
+                    for (int p = 0; p < nx; ++p) {
+                        double u = 0.5 * hx * gl_x[nx][p];
+                        double xb = X + u;
+                        double t1 = 0, t2 = 0, t3 = 0;
+                        for (int q = 0; q < ny; ++q) {
+                            double v = 0.5 * hy * gl_x[ny][q];
+                            double yb = Y + v;
+                            double rho2 = xb * xb + yb * yb;
+                            double ir3 = 1.0 / (rho2 * sqrt(rho2));
+                            double wq = gl_w[ny][q];
+                            t1 += wq * xb * ir3;
+                            t2 += wq * xb * ir3 * (sig2 + dx2 * u + dy2 * v);
+                            t3 += wq * yb * ir3 * (sig3 + dx3 * u + dy3 * v);
+                        }
+                        double wp = gl_w[nx][p];
+                        a1 += wp * t1;
+                        a2 += wp * t2;
+                        a3 += wp * t3;
+                    }
+                    double jac = 0.25 * hx * hy;
+                    acc_add(&s1, a1 * jac);
+                    acc_add(&s2, a2 * jac);
+                    acc_add(&s3, a3 * jac);
+                }
+            }
+        }
+        part[3 * tid + 0] = s1;
+        part[3 * tid + 1] = s2;
+        part[3 * tid + 2] = s3;
+        cnt[tid] = c;
+    }
+    acc_t t[3] = {{0, 0}, {0, 0}, {0, 0}};
+    int64_t total = 0;
+    for (int k = 0; k < nth; ++k) {
+        for (int q = 0; q < 3; ++q) {
+            acc_add(&t[q], part[3 * k + q].s);
+            acc_add(&t[q], part[3 * k + q].c);
+        }
+        total += cnt[k];
+    }
+    out[0] = acc_get(&t[0]);             /* K^{r,0}_{00}           */
+    out[1] = acc_get(&t[1]) / rm;        /* K^{r,r}_{00}  (Eq. 46) */
+    out[2] = acc_get(&t[2]);             /* K^{phi,phi}_{00}       */
+    if (n_cells) *n_cells = total;
+    free(part);
+    free(cnt);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* One table entry (all six kernels) for offset (m, n_rep).                   */
+/* Output order: r0, rr, rphi, phi0, phir, phiphi.                            */
+/* self = K^{r,0}_{00}, K^{r,r}_{00}, K^{phi,phi}_{00} (used at m = n = 0).   */
+/* ------------------------------------------------------------------------ */
+static void table_entry(double beta, double dphi, int n_tpz, int m, int nrep,
+                        const double self[3], double T[6])
+{
+    if (m == 0 && nrep == 0) {
+        T[0] = self[0];
+        T[1] = self[1];
+        T[2] = 0.0; /* odd integrand about the cell centre (Eq. 37 text) */
+        T[3] = 0.0;
+        T[4] = 0.0;
+        T[5] = self[2];
+        return;
+    }
+    const double rho = pow(beta, -m);                  /* r_i' / r_i     */
+    const double eta_l = 2.0 * rho / (1.0 + beta);
+    const double eta_u = beta * eta_l;
+    const double xic = -nrep * dphi;
+    const double dth = dphi / n_tpz;
+
+    /* Eq. 41-43 with the weight (xi - xi_c) inside the trapezoid */
+    double r0 = 0, rr = 0, rph = 0, pp = 0;
+    for (int k = 0; k <= n_tpz; ++k) {
+        double xi = xic - 0.5 * dphi + k * dth;
+        double wk = (k == 0 || k == n_tpz) ? 0.5 * dth : dth;
+        int closed = (m == 0) && (fabs(xi) < 0.5 * OR_PI);
+        double Ir, Ir2, Iph;
+        radial_integrals(eta_l, eta_u, xi, closed, &Ir, &Ir2, &Iph);
+        double wl = xi - xic;
+        r0 += wk * Ir;
+        rr += wk * (Ir2 - rho * Ir);
+        rph += wk * wl * Ir;
+        pp += wk * wl * Iph;
+    }
+    T[0] = -r0;
+    T[1] = -rr;
+    T[2] = -rph;
+    T[5] = pp;
+
+    /* K^{phi,0}, K^{phi,r}: exact double integrals (A30-A31) */
+    double xl = xic - 0.5 * dphi, xu = xic + 0.5 * dphi;
+    if (m == 0) {
+        double p1 = Hp1(eta_u, xu) - Hp1(eta_u, xl) - Hp1(eta_l, xu) + Hp1(eta_l, xl);
+        double p2 = Hp2(eta_u, xu) - Hp2(eta_u, xl) - Hp2(eta_l, xu) + Hp2(eta_l, xl);
+        T[3] = p1;
+        T[4] = p2 - rho * p1;
+    } else {
+        /* exact azimuthal integral: int eta^2 sin xi / F^3 dxi = -eta / F,
+         * and 1/F_l - 1/F_u = 4 eta sin(xi_c) sin(dphi/2) /
+         * (F_l F_u (F_l + F_u)); then 24-point Gauss-Legendre in eta */
+        const int n = 24;
+        double mid = 0.5 * (eta_u + eta_l), half = 0.5 * (eta_u - eta_l);
+        double shl = sin(0.5 * xl), shu = sin(0.5 * xu);
+        double num = 4.0 * sin(xic) * sin(0.5 * dphi);
+        double a = 0, b = 0;
+        for (int k = 0; k < n; ++k) {
+            double eta = mid + half * gl_x[n][k];
+            double Fl = Fpol(eta, shl), Fu = Fpol(eta, shu);
+            double D = num * eta / (Fl * Fu * (Fl + Fu));
+            a += gl_w[n][k] * eta * D;
+            b += gl_w[n][k] * eta * (eta - rho) * D;
+        }
+        T[3] = a * half;
+        T[4] = b * half;
+    }
+}
+
+int or_table_entry(int n_r, int n_phi, double r_min, double r_max, int n_tpz,
+                   int m, int nrep, const double *self, double *T)
+{
+    double beta, dphi;
+    if (or_geometry(n_r, n_phi, r_min, r_max, NULL, NULL, &beta, &dphi)) return -1;
+    if (n_tpz < 1) return -1;
+    gl_init();
+    table_entry(beta, dphi, n_tpz, m, nrep, self, T);
+    return 0;
+}
+
+/* All six tables, each (2 N_r - 1) x N_phi, row m + N_r - 1, column n.
+ * Entries are computed for n_rep in [0, N_phi/2] and mirrored to -n_rep by
+ * the parity of each integrand in xi (even: r0, rr, phiphi; odd: rphi,
+ * phi0, phir), which holds for every cell of the periodic grid. */
+int or_tables(int n_r, int n_phi, double r_min, double r_max, int n_tpz,
+              const double *self, double *T)
+{
+    double beta, dphi;
+    if (or_geometry(n_r, n_phi, r_min, r_max, NULL, NULL, &beta, &dphi)) return -1;
+    if (n_tpz < 1 || (n_phi % 2) != 0) return -1;
+    gl_init();
+    const long rows = 2L * n_r - 1;
+    const long plane = rows * (long)n_phi;
+    static const double par[6] = {1, 1, -1, -1, -1, 1};
+#ifdef _OPENMP
+#pragma omp parallel for collapse(2) schedule(dynamic, 16)
+#endif
+    for (long row = 0; row < rows; ++row)
+        for (int nrep = 0; nrep <= n_phi / 2; ++nrep) {
+            int m = (int)(row - (n_r - 1));
+            double t[6];
+            table_entry(beta, dphi, n_tpz, m, nrep, self, t);
+            long cpos = nrep, cneg = (n_phi - nrep) % n_phi;
+            for (int k = 0; k < 6; ++k) {
+                T[k * plane + row * n_phi + cpos] = t[k];
+                if (cneg != cpos) T[k * plane + row * n_phi + cneg] = par[k] * t[k];
+            }
+        }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Density channels (Eq. 25; central differences, P. 5.3).                    */
+/* sigma, s, dr, dph are [n_r][n_phi].                                        */
+/* ------------------------------------------------------------------------ */
+int or_channels(int n_r, int n_phi, const double *r_c, double dphi,
+                const double *sigma, double *dr, double *dph)
+{
+    if (n_r < 2 || n_phi < 3) return -1;
+    for (int i = 0; i < n_r; ++i)
+        for (int j = 0; j < n_phi; ++j) {
+            const double *row = sigma + (long)i * n_phi;
+            int jp = (j + 1) % n_phi, jm = (j + n_phi - 1) % n_phi;
+            dph[(long)i * n_phi + j] = (row[jp] - row[jm]) / (2.0 * dphi);
+            double v;
+            if (i == 0)
+                v = (sigma[(long)1 * n_phi + j] - sigma[j]) / (r_c[1] - r_c[0]);
+            else if (i == n_r - 1)
+                v = (sigma[(long)i * n_phi + j] - sigma[(long)(i - 1) * n_phi + j])
+                    / (r_c[i] - r_c[i - 1]);
+            else
+                v = (sigma[(long)(i + 1) * n_phi + j] - sigma[(long)(i - 1) * n_phi + j])
+                    / (r_c[i + 1] - r_c[i - 1]);
+            dr[(long)i * n_phi + j] = v;
+        }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Forward direct sums (Eq. 27-29 and A19-A21) at chosen destinations.        */
+/* dest: n_dest flat indices i*n_phi + j (NULL = every cell, in order).       */
+/* ------------------------------------------------------------------------ */
+int or_forward(int n_r, int n_phi, double r_min, double r_max, const double *T,
+               const double *sigma, const int64_t *dest, int64_t n_dest,
+               double *f_r, double *f_phi)
+{
+    double beta, dphi;
+    double *rc = (double *)malloc(sizeof(double) * n_r);
+    if (!rc) return -2;
+    if (or_geometry(n_r, n_phi, r_min, r_max, rc, NULL, &beta, &dphi)) { free(rc); return -1; }
+    const long N = (long)n_r * n_phi;
+    double *dr = (double *)malloc(sizeof(double) * N);
+    double *dp = (double *)malloc(sizeof(double) * N);
+    int *live = (int *)malloc(sizeof(int) * n_r);
+    if (!dr || !dp || !live) { free(rc); free(dr); free(dp); free(live); return -2; }
+    or_channels(n_r, n_phi, rc, dphi, sigma, dr, dp);
+    /* rows whose three channels are all zero contribute nothing */
+    for (int i = 0; i < n_r; ++i) {
+        live[i] = 0;
+        for (int j = 0; j < n_phi; ++j) {
+            long p = (long)i * n_phi + j;
+            if (sigma[p] != 0 || dr[p] != 0 || dp[p] != 0) { live[i] = 1; break; }
+        }
+    }
+    const long rows = 2L * n_r - 1;
+    const long plane = rows * (long)n_phi;
+    const double *Tr0 = T, *Trr = T + plane, *Trp = T + 2 * plane;
+    const double *Tp0 = T + 3 * plane, *Tpr = T + 4 * plane, *Tpp = T + 5 * plane;
+    const int64_t nd = dest ? n_dest : (int64_t)N;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 4)
+#endif
+    for (int64_t q = 0; q < nd; ++q) {
+        long d = dest ? (long)dest[q] : (long)q;
+        int i = (int)(d / n_phi), j = (int)(d % n_phi);
+        acc_t a0 = {0, 0}, ar = {0, 0}, ap = {0, 0};  /* F^{r,0}+F^{r,phi}, F^{r,r} */
+        acc_t b0 = {0, 0}, br = {0, 0}, bp = {0, 0};
+        for (int ip = 0; ip < n_r; ++ip) {
+            if (!live[ip]) continue;
+            long row = (long)(i - ip) + (n_r - 1);
+            const double *t0 = Tr0 + row * n_phi, *tr = Trr + row * n_phi, *tp = Trp + row * n_phi;
+            const double *u0 = Tp0 + row * n_phi, *ur = Tpr + row * n_phi, *up = Tpp + row * n_phi;
+            const double *sg = sigma + (long)ip * n_phi, *gr = dr + (long)ip * n_phi,
+                         *gp = dp + (long)ip * n_phi;
+            double x0 = 0, xr = 0, xp = 0, y0 = 0, yr = 0, yp = 0;
+            for (int jp = 0; jp < n_phi; ++jp) {
+                int n = j - jp;
+                if (n < 0) n += n_phi;
+                x0 += sg[jp] * t0[n];
+                xr += gr[jp] * tr[n];
+                xp += gp[jp] * tp[n];
+                y0 += sg[jp] * u0[n];
+                yr += gr[jp] * ur[n];
+                yp += gp[jp] * up[n];
+            }
+            acc_add(&a0, x0); acc_add(&ar, xr); acc_add(&ap, xp);
+            acc_add(&b0, y0); acc_add(&br, yr); acc_add(&bp, yp);
+        }
+        /* F = F^{.,0} + r_i [sum delta^r K^{.,r}] + F^{.,phi}  (Eq. 26-29) */
+        f_r[q] = acc_get(&a0) + rc[i] * acc_get(&ar) + acc_get(&ap);
+        f_phi[q] = acc_get(&b0) + rc[i] * acc_get(&br) + acc_get(&bp);
+    }
+    free(rc); free(dr); free(dp); free(live);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Transpose of the forward map, as a plain double sum, at chosen sources.    */
+/* Given cotangents v_r, v_phi on every destination, returns                  */
+/*   g[p] = sum_q v_r[q] dF_r[q]/dsigma[p] + v_phi[q] dF_phi[q]/dsigma[p].    */
+/* ------------------------------------------------------------------------ */
+static void adj_u(int n_r, int n_phi, const double *rc, const double *T,
+                  const double *v_r, const double *v_p, int ip, int jp,
+                  double *us, double *ug, double *uh)
+{
+    const long rows = 2L * n_r - 1;
+    const long plane = rows * (long)n_phi;
+    acc_t s = {0, 0}, g = {0, 0}, h = {0, 0};
+    for (int i = 0; i < n_r; ++i) {
+        long row = (long)(i - ip) + (n_r - 1);
+        const double *t0 = T + row * n_phi, *tr = T + plane + row * n_phi,
+                     *tp = T + 2 * plane + row * n_phi;
+        const double *u0 = T + 3 * plane + row * n_phi, *ur = T + 4 * plane + row * n_phi,
+                     *up = T + 5 * plane + row * n_phi;
+        const double *vr = v_r + (long)i * n_phi, *vp = v_p + (long)i * n_phi;
+        double xs = 0, xg = 0, xh = 0;
+        for (int j = 0; j < n_phi; ++j) {
+            int n = j - jp;
+            if (n < 0) n += n_phi;
+            xs += vr[j] * t0[n] + vp[j] * u0[n];
+            xg += vr[j] * tr[n] + vp[j] * ur[n];
+            xh += vr[j] * tp[n] + vp[j] * up[n];
+        }
+        acc_add(&s, xs);
+        acc_add(&g, rc[i] * xg);
+        acc_add(&h, xh);
+    }
+    *us = acc_get(&s);
+    *ug = acc_get(&g);
+    *uh = acc_get(&h);
+}
+
+/* coefficient of sigma[i] in delta^r[i2] (Eq. 25 slopes, one-sided ends) */
+static double dr_coef(int n_r, const double *rc, int i2, int i)
+{
+    if (i2 == 0) {
+        double inv = 1.0 / (rc[1] - rc[0]);
+        return i == 1 ? inv : (i == 0 ? -inv : 0.0);
+    }
+    if (i2 == n_r - 1) {
+        double inv = 1.0 / (rc[n_r - 1] - rc[n_r - 2]);
+        return i == n_r - 1 ? inv : (i == n_r - 2 ? -inv : 0.0);
+    }
+    double inv = 1.0 / (rc[i2 + 1] - rc[i2 - 1]);
+    return i == i2 + 1 ? inv : (i == i2 - 1 ? -inv : 0.0);
+}
+
+int or_adjoint(int n_r, int n_phi, double r_min, double r_max, const double *T,
+               const double *v_r, const double *v_phi, const int64_t *src,
+               int64_t n_src, double *g)
+{
+    double beta, dphi;
+    double *rc = (double *)malloc(sizeof(double) * n_r);
+    if (!rc) return -2;
+    if (or_geometry(n_r, n_phi, r_min, r_max, rc, NULL, &beta, &dphi)) { free(rc); return -1; }
+    if (n_r < 2 || n_phi < 3) { free(rc); return -1; }
+    const long N = (long)n_r * n_phi;
+    const int64_t ns = src ? n_src : (int64_t)N;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 1)
+#endif
+    for (int64_t q = 0; q < ns; ++q) {
+        long p = src ? (long)src[q] : (long)q;
+        int ip = (int)(p / n_phi), jp = (int)(p % n_phi);
+        double us, ug, uh, tot = 0;
+        adj_u(n_r, n_phi, rc, T, v_r, v_phi, ip, jp, &us, &ug, &uh);
+        tot = us;
+        /* radial slope channel: sum over i2 of coef(i2, ip) * u_g(i2, jp) */
+        for (int i2 = ip - 1; i2 <= ip + 1; ++i2) {
+            if (i2 < 0 || i2 >= n_r) continue;
+            double cf = dr_coef(n_r, rc, i2, ip);
+            if (cf == 0.0) continue;
+            double a, b, c;
+            adj_u(n_r, n_phi, rc, T, v_r, v_phi, i2, jp, &a, &b, &c);
+            tot += cf * b;
+        }
+        /* azimuthal slope channel: delta^phi[j2] has +1/(2 dphi) on j2+1 and
+         * -1/(2 dphi) on j2-1, so sigma[jp] meets u_h at jp-1 and jp+1 */
+        {
+            int jm = (jp + n_phi - 1) % n_phi, jq = (jp + 1) % n_phi;
+            double a, b, hm, hq;
+            adj_u(n_r, n_phi, rc, T, v_r, v_phi, ip, jm, &a, &b, &hm);
+            adj_u(n_r, n_phi, rc, T, v_r, v_phi, ip, jq, &a, &b, &hq);
+            tot += (hm - hq) / (2.0 * dphi);
+        }
+        g[q] = tot;
+    }
+    free(rc);
+    return 0;
+}
+
+int or_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

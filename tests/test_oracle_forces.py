@@ -1,0 +1,226 @@
+"""Pins of the oracle's force sums (Eq. 26-29, A18-A21) and their transpose.
+
+Checked against: brute-force 2-D quadrature of the force integrals (Eq. 23-24)
+over the piecewise-linear density of Eq. 25 on a tiny grid; exact symmetries
+of the log-polar convolution; momentum balance; the Kuzmin closed form; the
+analytic sigma_Dn disks with the second-order convergence the paper reports
+(Table 1); and, for the transpose, the dot-product identity.
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy import integrate
+
+import oracle
+import workloads
+from oracle import analytic
+
+
+def _brute_force(g, T, sig, i, j):
+    """F_r, F_phi at cell (i, j): every other source cell integrated by 2-D
+    adaptive quadrature of the kernel times the cell's linear density (in
+    physical r, phi), plus the self-cell terms of Eq. 37 with the oracle's
+    self constants (the self cell itself is pinned by the principal-value
+    test)."""
+    dr, dp = oracle.channels(g, sig)
+    ri, pj = g.r_centres[i], g.phi_centres[j]
+    fr = fp = 0.0
+    for a in range(g.n_r):
+        for b in range(g.n_phi):
+            if a == i and b == j:
+                continue
+            rl, ru = g.r_edges[a], g.r_edges[a + 1]
+            pl, pu = b * g.dphi, (b + 1) * g.dphi
+            ra, pb = g.r_centres[a], g.phi_centres[b]
+
+            def lin(rb, phb):
+                return sig[a, b] + dr[a, b] * (rb - ra) + dp[a, b] * (phb - pb)
+
+            def D3(rb, phb):
+                return (rb * rb + ri * ri - 2 * rb * ri * math.cos(phb - pj)) ** 1.5
+
+            kr = lambda rb, phb: -lin(rb, phb) * rb * (ri - rb * math.cos(phb - pj)) / D3(rb, phb)
+            kp = lambda rb, phb: lin(rb, phb) * rb * rb * math.sin(phb - pj) / D3(rb, phb)
+            opts = dict(epsabs=1e-13, epsrel=1e-11)
+            fr += integrate.dblquad(kr, pl, pu, rl, ru, **opts)[0]
+            fp += integrate.dblquad(kp, pl, pu, rl, ru, **opts)[0]
+    n0 = g.n_r - 1
+    fr += sig[i, j] * T[0, n0, 0] + ri * dr[i, j] * T[1, n0, 0]
+    fp += dp[i, j] * T[5, n0, 0]
+    return fr, fp
+
+
+@pytest.mark.slow
+def test_forward_matches_brute_force_quadrature():
+    g = oracle.Grid(5, 8, 0.5, 2.0)
+    sig = workloads.random_field(g.shape, seed_k=11)
+    sk = oracle.selfcell_cover(g.beta, g.dphi)[:3]
+    cells = [(0, 0), (2, 5), (4, 3)]
+    dest = [i * g.n_phi + j for i, j in cells]
+    errs = {}
+    for ntpz in (19, 39, 399):
+        T = oracle.tables(g, ntpz, self_k=sk)
+        fr, fp = oracle.forward(g, T, sig, dest)
+        errs[ntpz] = (fr, fp)
+    T = oracle.tables(g, 19, self_k=sk)
+    bf = np.array([_brute_force(g, T, sig, i, j) for i, j in cells])
+    e = {k: np.abs(np.stack(v, 1) - bf) for k, v in errs.items()}
+    scale = np.abs(bf).max()
+    # the only difference is the N_tpz trapezoid error of Eq. 41-43
+    assert e[399].max() < 2e-6 * scale
+    assert e[19].max() < 3e-3 * scale
+    ratio = e[19].sum() / e[39].sum()
+    assert 3.5 < ratio < 4.8, ratio
+
+
+@pytest.fixture(scope="module")
+def small():
+    g = oracle.Grid(24, 32, 0.1, 10.0)
+    T = oracle.tables(g, 19)
+    return g, T
+
+
+def test_axisymmetric_density_has_no_azimuthal_force(small):
+    g, T = small
+    sig = workloads.kuzmin(g.r_centres, g.phi_centres)
+    fr, fp = oracle.forward(g, T, sig)
+    assert np.abs(fp).max() < 1e-14 * np.abs(fr).max()
+    assert np.abs(fr - fr[:, :1]).max() < 1e-13 * np.abs(fr).max()
+
+
+def test_rotation_and_mirror(small):
+    g, T = small
+    sig = workloads.single_disk_blobs(g.r_centres, g.phi_centres)
+    fr, fp = oracle.forward(g, T, sig)
+    k = 5
+    fr2, fp2 = oracle.forward(g, T, np.roll(sig, k, axis=1))
+    s = np.abs(fr).max()
+    np.testing.assert_allclose(fr2, np.roll(fr, k, axis=1), rtol=0, atol=1e-13 * s)
+    np.testing.assert_allclose(fp2, np.roll(fp, k, axis=1), rtol=0, atol=1e-13 * s)
+    # phi -> -phi maps cell j to N - 1 - j
+    fr3, fp3 = oracle.forward(g, T, sig[:, ::-1])
+    np.testing.assert_allclose(fr3, fr[:, ::-1], rtol=0, atol=1e-13 * s)
+    np.testing.assert_allclose(fp3, -fp[:, ::-1], rtol=0, atol=1e-13 * s)
+
+
+def test_radial_shift_for_compact_density(small):
+    # log-polar self-similarity: the kernels and r_i delta^r depend only on
+    # index offsets, so a compact density shifted by k rows shifts F
+    g, T = small
+    sig = np.zeros(g.shape)
+    sig[6:12] = workloads.random_field((6, g.n_phi), seed_k=12)
+    k = 4
+    fr, fp = oracle.forward(g, T, sig)
+    fr2, fp2 = oracle.forward(g, T, np.roll(sig, k, axis=0))
+    s = np.abs(fr).max()
+    np.testing.assert_allclose(fr2[k:], fr[:-k], rtol=0, atol=1e-13 * s)
+    np.testing.assert_allclose(fp2[k:], fp[:-k], rtol=0, atol=1e-13 * s)
+
+
+def _net_force(g, sig, fr, fp):
+    m = sig * g.cell_areas()
+    P = g.phi_centres[None, :]
+    fx = fr * np.cos(P) - fp * np.sin(P)
+    fy = fr * np.sin(P) + fp * np.cos(P)
+    net = np.hypot((m * fx).sum(), (m * fy).sum())
+    return net / (np.abs(m) * np.hypot(fx, fy)).sum()
+
+
+def test_net_self_force_vanishes_with_resolution():
+    vals = []
+    for N in (32, 64, 128):
+        g = oracle.Grid(N, N, 0.01, 1.0)
+        T = oracle.tables(g, 19)
+        sig = workloads.finite_disk(g.r_centres, g.phi_centres, n=5)
+        fr, fp = oracle.forward(g, T, sig)
+        vals.append(_net_force(g, sig, fr, fp))
+    assert vals[-1] < 2e-3
+    assert vals[0] / vals[1] > 3 and vals[1] / vals[2] > 3
+
+
+def test_kuzmin_disk_closed_form():
+    # wide domain [1e-3, 1e3] so that the missing core (r < r_min) and the
+    # missing envelope stay below the discretisation error on [0.1, 10];
+    # near-square cells (dphi ~ ln beta), the shape the method is built for
+    errs = []
+    for N, nphi in ((64, 32), (128, 64)):
+        g = oracle.Grid(N, nphi, 1e-3, 1e3)
+        T = oracle.tables(g, 19)
+        sig = workloads.kuzmin(g.r_centres, g.phi_centres)
+        fr, fp = oracle.forward(g, T, sig)
+        sel = (g.r_centres > 0.1) & (g.r_centres < 10)
+        ana = analytic.kuzmin_force(g.r_centres[sel])
+        errs.append((np.abs(fr[sel] - ana[:, None]) / np.abs(ana[:, None])).max())
+        assert np.abs(fp).max() < 1e-14
+    assert errs[1] < 5e-3
+    assert errs[0] / errs[1] > 3.3
+
+
+def _disk_errors(N, n):
+    g = oracle.Grid(N, N, 0.01, 1.0)
+    T = oracle.tables(g, 19)
+    sig = workloads.finite_disk(g.r_centres, g.phi_centres, n=n)
+    fr, fp = oracle.forward(g, T, sig)
+    R, P = np.meshgrid(g.r_centres, g.phi_centres, indexing="ij")
+    ar, ap = analytic.offcentre_forces(R, P, n, 0.25, 0.5, 0.1)
+    return np.array(oracle.error_norms(fr, ar) + oracle.error_norms(fp, ap))
+
+
+def test_convergence_sigma_d2():
+    # Table 1 (SIM, sigma_D2): L1, L2 orders about 2; L-infinity about 1.5
+    e = [_disk_errors(N, 2) for N in (64, 128, 256)]
+    o = np.log2(e[1] / e[2])
+    assert np.all(o[[0, 1, 3, 4]] > 1.85) and np.all(o[[0, 1, 3, 4]] < 2.3), o
+    assert np.all(o[[2, 5]] > 1.3), o
+
+
+@pytest.mark.slow
+def test_convergence_sigma_d5():
+    # Table 1 (SIM, sigma_D5): orders 1.9-2.0 over N = 64..1024
+    e = [_disk_errors(N, 5) for N in (256, 512)]
+    o = np.log2(e[0] / e[1])
+    assert np.all(o > 1.78) and np.all(o < 2.3), o
+
+
+# --------------------------------------------------------------------------
+# transpose
+# --------------------------------------------------------------------------
+def test_adjoint_dot_product(small):
+    g, T = small
+    sig = workloads.random_field(g.shape, seed_k=13)
+    vr = workloads.random_field(g.shape, seed_k=14)
+    vp = workloads.random_field(g.shape, seed_k=15)
+    fr, fp = oracle.forward(g, T, sig)
+    gs = oracle.adjoint(g, T, vr, vp)
+    lhs = (fr * vr).sum() + (fp * vp).sum()
+    rhs = (sig * gs).sum()
+    assert abs(lhs - rhs) < 1e-12 * (np.abs(fr * vr).sum() + np.abs(fp * vp).sum())
+
+
+def test_adjoint_sampled_equals_full(small):
+    g, T = small
+    vr = workloads.random_field(g.shape, seed_k=16)
+    vp = workloads.random_field(g.shape, seed_k=17)
+    full = oracle.adjoint(g, T, vr, vp)
+    idx = np.array([0, 1, 31, 32, 33, 400, g.n_r * g.n_phi - 1, (g.n_r - 2) * g.n_phi + 3])
+    samp = oracle.adjoint(g, T, vr, vp, idx)
+    np.testing.assert_array_equal(samp, full.reshape(-1)[idx])
+
+
+def test_adjoint_matches_central_differences(small):
+    # L = sum (F - F*)^2 is quadratic, so central differences are exact up
+    # to rounding for any step
+    g, T = small
+    sig = workloads.start_density(g.r_centres, g.phi_centres)
+    tgt_r, tgt_p = oracle.forward(g, T, workloads.hidden_density(g.r_centres, g.phi_centres, 0.1, 10.0))
+    fr, fp = oracle.forward(g, T, sig)
+    grad = oracle.adjoint(g, T, 2 * (fr - tgt_r), 2 * (fp - tgt_p))
+    for p in (5, 200, 767):
+        e = np.zeros(g.n_r * g.n_phi)
+        e[p] = 1e-3
+        e = e.reshape(g.shape)
+        lp = sum(((a - b) ** 2).sum() for a, b in zip(oracle.forward(g, T, sig + e), (tgt_r, tgt_p)))
+        lm = sum(((a - b) ** 2).sum() for a, b in zip(oracle.forward(g, T, sig - e), (tgt_r, tgt_p)))
+        fd = (lp - lm) / 2e-3
+        assert abs(fd - grad.reshape(-1)[p]) < 1e-7 * max(1.0, abs(fd))
