@@ -1,0 +1,222 @@
+#!/usr/bin/env python
+"""Benchmark of the log-polar self-gravity hot path on one MI355X.
+
+Headline: cells/s of the forward map (F_r + F_phi) on the single-disk
+1024 x 2048 log-polar workload (r in [0.01, 100], exponential disk with a 20%
+m = 2 logarithmic spiral), FP32 FFT/multiply with FP64-built kernel spectra.
+One step = one pf_forces call on that grid with the density already resident
+in HBM.  Also reported: the FP64 path, the transpose (backward) in both
+precisions, the 64-disk batched launch, the one-time table build, the
+roofline of the dominant kernel (the fused column pass) and the FP64 CPU
+oracle timed on the host's cores.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+Prints one JSON line on stdout.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "cells/s for F_r+F_phi at 1024x2048 (FP32 vs FP64, same GPU); backward cells/s"
+N_R, N_PHI, R_MIN, R_MAX = 1024, 2048, 0.01, 100.0
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def path_bytes(n_r, n_phi, L, w):
+    """Algorithmic HBM bytes of one forward call (three passes):
+    pass A reads sigma (R P w) and writes S (R H 2w); pass B reads S and the
+    four half spectra (4 (L/2+1) H 2w) and writes Zr, Zp (2 R H 2w); pass C
+    reads Zr, Zp and writes F_r, F_phi (2 R P w)."""
+    H = n_phi // 2 + 1
+    a = n_r * n_phi * w + n_r * H * 2 * w
+    b = n_r * H * 2 * w + 4 * (L // 2 + 1) * H * 2 * w + 2 * n_r * H * 2 * w
+    c = 2 * n_r * H * 2 * w + 2 * n_r * n_phi * w
+    return a, b, c
+
+
+def time_calls(torch, fn, steps, warmup):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps  # ms per call
+
+
+def pass_times(plan, a, b=None, backward=False, reps=30):
+    acc = [0.0, 0.0, 0.0]
+    for _ in range(3):
+        plan.timed(a, b, backward)
+    for _ in range(reps):
+        ms = plan.timed(a, b, backward)
+        acc = [x + y for x, y in zip(acc, ms)]
+    return [x / reps for x in acc]
+
+
+def cpu_baseline(sample_seconds=15.0):
+    """The FP64 oracle's direct sums on a bounded random sample of output
+    cells of the same 1024 x 2048 workload (tables built first, untimed)."""
+    import numpy as np
+
+    import oracle
+    import workloads
+    g = oracle.Grid(N_R, N_PHI, R_MIN, R_MAX)
+    T = oracle.tables(g, 19)
+    sig = workloads.spiral_disk(g.r_centres, g.phi_centres)
+    rng = np.random.default_rng(7)
+    # calibrate on a small sample, then size the timed sample
+    probe = rng.choice(N_R * N_PHI, 64, replace=False)
+    t0 = time.perf_counter()
+    oracle.forward(g, T, sig, probe)
+    rate = 64 / max(time.perf_counter() - t0, 1e-6)
+    n = int(max(128, min(N_R * N_PHI, rate * sample_seconds)))
+    idx = rng.choice(N_R * N_PHI, n, replace=False)
+    t0 = time.perf_counter()
+    oracle.forward(g, T, sig, idx)
+    dt = time.perf_counter() - t0
+    return {"value": n / dt, "unit": "cells/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": "%d random output cells of the 1024x2048 workload (FP64 direct "
+                      "O((N_r N_phi)^2) sums, %.1f s)" % (n, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: the single-disk and batched paths run on "
+              "one device (--gpus %d is not supported)" % args.gpus, file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    import paper_1509_01450_amd as pf
+    import workloads
+
+    if not torch.cuda.is_available():
+        print("no GPU available", file=sys.stderr)
+        return 1
+    dev = torch.device("cuda:0")
+    K, W = args.steps, args.warmup
+    cells = N_R * N_PHI
+    out = {"metric": METRIC, "unit": "cells/s", "n_gpus": 1, "steps": K, "warmup": W,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic"}
+
+    # ---- FP32 forward (headline) ------------------------------------------
+    t0 = time.perf_counter()
+    p32 = pf.Plan(N_R, N_PHI, R_MIN, R_MAX, dtype="f32")
+    torch.cuda.synchronize()
+    build32 = time.perf_counter() - t0
+    rc, _, _ = p32.geometry()
+    phi = (np.arange(N_PHI) + 0.5) * (2 * np.pi / N_PHI)
+    sig_np = workloads.spiral_disk(rc, phi)
+    s32 = torch.tensor(sig_np, dtype=torch.float32, device=dev)
+    fr32, fp32 = torch.empty_like(s32), torch.empty_like(s32)
+    log("fp32 forward: warmup %d, steps %d" % (W, K))
+    ms32 = time_calls(torch, lambda: p32.forces(s32, (fr32, fp32)), K, W)
+    passes32 = pass_times(p32, s32)
+    L = p32_L = 2 * N_R
+    bA, bB, bC = path_bytes(N_R, N_PHI, p32_L, 4)
+    achieved = bB / (passes32[1] * 1e-3) / 1e9
+
+    # ---- FP64 forward -----------------------------------------------------
+    t0 = time.perf_counter()
+    p64 = pf.Plan(N_R, N_PHI, R_MIN, R_MAX, dtype="f64")
+    torch.cuda.synchronize()
+    build64 = time.perf_counter() - t0
+    s64 = torch.tensor(sig_np, dtype=torch.float64, device=dev)
+    fr64, fp64 = torch.empty_like(s64), torch.empty_like(s64)
+    log("fp64 forward")
+    ms64 = time_calls(torch, lambda: p64.forces(s64, (fr64, fp64)), max(K // 2, 10), W)
+    passes64 = pass_times(p64, s64)
+    cA, cB, cC = path_bytes(N_R, N_PHI, L, 8)
+
+    # ---- backward ---------------------------------------------------------
+    log("backward")
+    gr32, gp32 = torch.randn_like(s32), torch.randn_like(s32)
+    gs32 = torch.empty_like(s32)
+    msb32 = time_calls(torch, lambda: p32.backward(gr32, gp32, gs32), max(K // 2, 10), W)
+    gr64, gp64 = gr32.double(), gp32.double()
+    gs64 = torch.empty_like(gr64)
+    msb64 = time_calls(torch, lambda: p64.backward(gr64, gp64, gs64), max(K // 4, 10), W)
+    passesb32 = pass_times(p32, gr32, gp32, backward=True)
+
+    # ---- batched ------------------------------------------------------------
+    batched = None
+    if not args.no_batched:
+        log("batched: 64 disks")
+        sizes = workloads.batch_sizes(64)
+        plans, sig_b = [], []
+        t0 = time.perf_counter()
+        for d, (nr, nphi) in enumerate(sizes):
+            pb = pf.Plan(nr, nphi, 0.01, 100.0, dtype="f32")
+            r_b, _, _ = pb.geometry()
+            ph_b = (np.arange(nphi) + 0.5) * (2 * np.pi / nphi)
+            plans.append(pb)
+            sig_b.append(torch.tensor(workloads.multiarm_disk(r_b, ph_b, d), dtype=torch.float32,
+                                      device=dev))
+        torch.cuda.synchronize()
+        build_b = time.perf_counter() - t0
+        outs = [(torch.empty_like(s), torch.empty_like(s)) for s in sig_b]
+        msb = time_calls(torch, lambda: pf.forces_batched(plans, sig_b, outs), max(K // 4, 10), 5)
+        bcells = sum(nr * nphi for nr, nphi in sizes)
+        batched = {"workload": "64 disks, N_r in {256..1024}, N_phi in {256..2048}, FP32",
+                   "cells": bcells, "ms_per_call": msb, "cells_per_s": bcells / (msb * 1e-3),
+                   "table_build_s": build_b}
+
+    out["value"] = cells / (ms32 * 1e-3)
+    out["ms_per_step"] = ms32
+    out["config"] = {"workload": "single disk log-polar %dx%d, r in [%g, %g], exponential disk "
+                                 "+ 20%% m=2 log spiral, forward F_r+F_phi" % (N_R, N_PHI, R_MIN, R_MAX),
+                     "n_r": N_R, "n_phi": N_PHI, "L_u": L, "n_tpz": 19, "precision":
+                     "FP32 FFT + spectral multiply, FP64-built kernel spectra"}
+    out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                       "frac": achieved / HBM_PEAK_GBS, "traffic": None}
+    out["detail"] = {
+        "dominant_kernel": "k_cols_fwd (fused radial slope + u-FFTs + spectral MAC + inverse)",
+        "pass_ms_fp32": passes32, "pass_bytes_fp32": [bA, bB, bC],
+        "pass_GBs_fp32": [b / (t * 1e-3) / 1e9 for b, t in zip((bA, bB, bC), passes32)],
+        "path_bytes_fp32": bA + bB + bC,
+        "path_GBs_fp32": (bA + bB + bC) / (ms32 * 1e-3) / 1e9,
+        "fp64": {"ms_per_call": ms64, "cells_per_s": cells / (ms64 * 1e-3),
+                 "pass_ms": passes64,
+                 "pass_GBs": [b / (t * 1e-3) / 1e9 for b, t in zip((cA, cB, cC), passes64)],
+                 "path_GBs": (cA + cB + cC) / (ms64 * 1e-3) / 1e9},
+        "backward": {"fp32_ms": msb32, "fp32_cells_per_s": cells / (msb32 * 1e-3),
+                     "fp64_ms": msb64, "fp64_cells_per_s": cells / (msb64 * 1e-3),
+                     "fp32_pass_ms": passesb32},
+        "table_build_s": {"fp32": build32, "fp64": build64},
+        "batched": batched,
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle)")
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

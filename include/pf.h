@@ -1,0 +1,165 @@
+/*
+ * pf.h -- C ABI of the log-polar thin-disk self-gravity library (libpf.so).
+ *
+ * The library computes the radial and azimuthal self-gravity forces F_r,
+ * F_phi of an infinitesimally thin disk on a logarithmic-radial, uniform-
+ * azimuth grid with the second-order method of Wang, Yen & Taam
+ * (arXiv:1509.01450): the forces are three discrete convolutions per
+ * component of the cell density and its two slopes with precomputed force-
+ * kernel tables (Sec. 3.2.1, Eq. 26-32 and A18-A24), the tables being built
+ * by the singular integration method (SIM, Sec. 4, Eq. 41-46).  The
+ * convolutions run as FFTs on the GPU: zero-padded in u = ln r (no artificial
+ * boundary) and periodic in phi.  G = 1 throughout (Sec. 2).
+ *
+ * Grid (Sec. 3.2.1, generalised to n_r x n_phi).  beta = (r_max/r_min)^(1/n_r);
+ * radial cell i (0-based) spans [r_min beta^i, r_min beta^(i+1)] with centre
+ * r_i = r_min beta^i (1 + beta) / 2 (the arithmetic mean of its edges);
+ * dphi = 2 pi / n_phi; azimuthal cell j spans [j dphi, (j+1) dphi] with centre
+ * phi_j = (j + 1/2) dphi.
+ *
+ * Array layout.  Every field (density, forces, their gradients) is a dense
+ * row-major [n_r][n_phi] array: element (i, j) at offset i * n_phi + j, i
+ * radial (inner to outer), j azimuthal.  Field pointers are DEVICE pointers
+ * on the current HIP device, of the plan's precision (float for PF_F32,
+ * double for PF_F64), and must not overlap one another.
+ *
+ * Forces follow Eq. 23-24 (and A17): F_r = -dPhi/dr (negative = inward),
+ * F_phi = -(1/r) dPhi/dphi, at the cell centres.
+ *
+ * Ownership.  The caller owns every field buffer.  A plan owns its kernel
+ * spectra, twiddle tables and workspace (device memory allocated by
+ * pf_kernels_build, released by pf_plan_destroy).
+ *
+ * Streams.  `stream` arguments are hipStream_t values passed as void*; NULL
+ * means the default stream.  Compute calls only enqueue work and return
+ * without synchronising; asynchronous faults surface at the next
+ * synchronising call.  A plan is not re-entrant: calls that share a plan
+ * must be ordered (same stream, or synchronised), because they share the
+ * plan's workspace.
+ *
+ * Errors.  Every call checks its arguments on the host before touching the
+ * GPU; on failure nothing is enqueued, a status below is returned and
+ * pf_last_error() describes it.  HIP failures return PF_EHIP with HIP's
+ * message.  Functions returning a pointer return NULL on failure.
+ */
+#ifndef PF_H_
+#define PF_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pf_plan_s *pf_plan;
+
+enum pf_status {
+    PF_OK = 0,
+    PF_EINVAL = 1,         /* bad argument                                   */
+    PF_ESTATE = 2,         /* plan not built / built for another precision   */
+    PF_ENOMEM = 3,         /* device or host allocation failed               */
+    PF_EHIP = 4,           /* HIP runtime error                              */
+    PF_ENODEV = 5,         /* no GPU device                                  */
+    PF_EUNSUPPORTED = 6    /* size outside what the kernels are built for    */
+};
+
+enum pf_dtype { PF_F32 = 0, PF_F64 = 1 };
+
+/* Kernel-table construction options (Sec. 4).
+ *   dtype        PF_F32: FFT and spectral multiply in FP32 with FP32
+ *                accumulation (tables and spectra are built in FP64 and
+ *                rounded once); PF_F64: FP64 throughout.
+ *   n_tpz        trapezoids per source cell in the azimuthal quadrature of
+ *                the kernels (Eq. 41-43); 19 in the paper's results; 1 gives
+ *                the one-trapezoid rule of Eq. 38-40.  Range 1..1024.
+ *   cover_per    Cartesian cells per Delta x and per Delta y in the cover of
+ *                the singular self cell (Eq. 44-45); the paper uses 10.
+ *                Range 1..64.
+ *   keep_tables  nonzero: keep the six FP64 kernel tables on the device so
+ *                that pf_plan_tables() can return them (diagnostics).      */
+typedef struct {
+    int dtype;
+    int n_tpz;
+    int cover_per;
+    int keep_tables;
+} pf_build_opts;
+
+/* Defaults: PF_F32, n_tpz = 19, cover_per = 10, keep_tables = 0. */
+void pf_build_opts_default(pf_build_opts *opts);
+
+/* Create a plan for an n_r x n_phi grid on [r_min, r_max] (Sec. 3.2.1).
+ * Host only; touches no GPU.  Requirements: 4 <= n_r <= 4096;
+ * n_phi a power of two in [8, 8192]; 0 < r_min < r_max, both finite.
+ * Returns NULL on failure (see pf_last_error()); PF_EUNSUPPORTED-type size
+ * failures are reported the same way.                                      */
+pf_plan pf_plan_create(int n_r, int n_phi, double r_min, double r_max);
+
+/* Build the kernel tables and their spectra on the current device
+ * (Eq. 30-33, 41-46, A22-A35): one-time work, FP64 throughout, enqueued on
+ * `stream` and synchronised before returning.  opts == NULL means defaults.
+ * May be called again to rebuild with other options.                       */
+int pf_kernels_build(pf_plan plan, const pf_build_opts *opts, void *stream);
+
+/* Forward map (Eq. 26-29, A18-A21): sigma -> (f_r, f_phi).  sigma is the
+ * cell-centre surface density; its slopes (Eq. 25) are formed inside by
+ * central differences in r and phi (periodic in phi; one-sided two-point
+ * differences on the first and last radial rows).  Sources are the grid
+ * cells only: no mass inside r_min or outside r_max.  Asynchronous.        */
+int pf_forces(pf_plan plan, const void *sigma, void *f_r, void *f_phi,
+              void *stream);
+
+/* Transpose of the forward map: g_sigma = A^T [g_fr; g_fphi], i.e. the
+ * gradient of any scalar loss L(F_r, F_phi) with respect to sigma, given
+ * dL/dF_r = g_fr and dL/dF_phi = g_fphi.  Overwrites g_sigma.  Not in the
+ * paper: it is the exact transpose of the linear map Eq. 26-29.  Async.    */
+int pf_forces_backward(pf_plan plan, const void *g_fr, const void *g_fphi,
+                       void *g_sigma, void *stream);
+
+/* Forward map for n independent disks, each with its own built plan (all of
+ * one precision, sizes may differ), in one persistent kernel launch that is
+ * captured once per batch signature in a HIP graph and replayed.  Arrays
+ * sigma[k], f_r[k], f_phi[k] follow plan[k]'s layout.  Plans of a batch
+ * share internal state: do not run two batches with common plans at once.
+ * 1 <= n <= 4096.  Asynchronous.                                           */
+int pf_forces_batched(int n, const pf_plan *plans, const void *const *sigma,
+                      void *const *f_r, void *const *f_phi, void *stream);
+
+/* Diagnostic form of pf_forces / pf_forces_backward: the same passes, with
+ * HIP events recorded on `stream` around each of the three passes; waits for
+ * them and writes the three durations in milliseconds to pass_ms[3]
+ * (row transforms, column pass, row transforms).  backward = 0 times the
+ * forward map (in0 = sigma, out0 = f_r, out1 = f_phi), backward = 1 the
+ * transpose (in0 = g_fr, in1 = g_fphi, out0 = g_sigma).  Synchronous.      */
+int pf_forces_timed(pf_plan plan, int backward, const void *in0, const void *in1,
+                    void *out0, void *out1, void *stream, float *pass_ms);
+
+/* Grid geometry on the host: r_centres[n_r], r_edges[n_r + 1], *dphi.
+ * Any output may be NULL.                                                  */
+int pf_plan_geometry(pf_plan plan, double *r_centres, double *r_edges,
+                     double *dphi);
+
+/* Self-cell kernel constants of the last build, on the host:
+ * out[0] = K^{r,0}_{00}, out[1] = K^{r,r}_{00}, out[2] = K^{phi,phi}_{00}
+ * (Eq. 33, 46; the other three self constants are zero by symmetry).      */
+int pf_plan_selfcell(pf_plan plan, double out[3]);
+
+/* Copy the six FP64 kernel tables to host memory `dst` (plan built with
+ * keep_tables).  Layout: [6][2 n_r - 1][n_phi], kernels in the order
+ * K^{r,0}, K^{r,r}, K^{r,phi}, K^{phi,0}, K^{phi,r}, K^{phi,phi}; row
+ * m + n_r - 1 holds radial offset m = i - i' (destination minus source),
+ * column n = (j - j') mod n_phi.  Synchronous.                             */
+int pf_plan_tables(pf_plan plan, double *dst);
+
+/* Release the plan and everything it owns.  NULL is ignored.              */
+void pf_plan_destroy(pf_plan plan);
+
+/* Per-thread description of the last failure ("" if none).                */
+const char *pf_last_error(void);
+
+/* Library version string.                                                 */
+const char *pf_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PF_H_ */

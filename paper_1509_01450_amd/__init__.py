@@ -1,0 +1,307 @@
+"""Python binding of libpf: log-polar thin-disk self-gravity on MI355X.
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of ``libpf.so`` behind the C ABI of ``include/pf.h``.  PyTorch is used
+for device memory and streams.  The functions ``pf_*`` mirror the C entry
+points one to one; :class:`Plan` and :func:`forces` are conveniences on top
+(``forces`` is a ``torch.autograd.Function`` whose backward is the library's
+transpose kernel).
+
+Method: Wang, Yen & Taam, arXiv:1509.01450 -- second-order forces of an
+infinitesimally thin disk on a log-polar grid (Sec. 3.2, Eq. 26-32, A18-A24)
+with kernels from the singular integration method (Sec. 4, Eq. 41-46).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpf.so")
+
+PF_OK, PF_EINVAL, PF_ESTATE, PF_ENOMEM, PF_EHIP, PF_ENODEV, PF_EUNSUPPORTED = range(7)
+PF_F32, PF_F64 = 0, 1
+_STATUS = {1: "PF_EINVAL", 2: "PF_ESTATE", 3: "PF_ENOMEM", 4: "PF_EHIP", 5: "PF_ENODEV",
+           6: "PF_EUNSUPPORTED"}
+
+EXPORTS = ("pf_build_opts_default", "pf_plan_create", "pf_kernels_build", "pf_forces",
+           "pf_forces_backward", "pf_forces_batched", "pf_forces_timed", "pf_plan_geometry",
+           "pf_plan_selfcell", "pf_plan_tables", "pf_plan_destroy", "pf_last_error",
+           "pf_version")
+
+
+class PFError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s: %s" % (_STATUS.get(code, str(code)), msg))
+        self.code = code
+
+
+class pf_build_opts(ctypes.Structure):
+    _fields_ = [("dtype", ctypes.c_int), ("n_tpz", ctypes.c_int),
+                ("cover_per", ctypes.c_int), ("keep_tables", ctypes.c_int)]
+
+
+_lib = None
+
+
+def build() -> str:
+    """Compile libpf.so from csrc/ (hipcc, gfx950)."""
+    from . import _build
+    return _build.build()
+
+
+def load():
+    """Load libpf.so; raises if it has not been built (no fallback path)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libpf.so is not built (run paper_1509_01450_amd.build()); "
+                          "there is no fallback implementation")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, I, D = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+    lib.pf_build_opts_default.argtypes = [ctypes.POINTER(pf_build_opts)]
+    lib.pf_build_opts_default.restype = None
+    lib.pf_plan_create.argtypes = [I, I, D, D]
+    lib.pf_plan_create.restype = P
+    lib.pf_kernels_build.argtypes = [P, ctypes.POINTER(pf_build_opts), P]
+    lib.pf_forces.argtypes = [P, P, P, P, P]
+    lib.pf_forces_backward.argtypes = [P, P, P, P, P]
+    lib.pf_forces_batched.argtypes = [I, P, P, P, P, P]
+    lib.pf_forces_timed.argtypes = [P, I, P, P, P, P, P, P]
+    lib.pf_plan_geometry.argtypes = [P, P, P, P]
+    lib.pf_plan_selfcell.argtypes = [P, P]
+    lib.pf_plan_tables.argtypes = [P, P]
+    for f in ("pf_kernels_build", "pf_forces", "pf_forces_backward", "pf_forces_batched",
+              "pf_forces_timed",
+              "pf_plan_geometry", "pf_plan_selfcell", "pf_plan_tables"):
+        getattr(lib, f).restype = I
+    lib.pf_plan_destroy.argtypes = [P]
+    lib.pf_plan_destroy.restype = None
+    lib.pf_last_error.argtypes = []
+    lib.pf_last_error.restype = ctypes.c_char_p
+    lib.pf_version.argtypes = []
+    lib.pf_version.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def pf_last_error() -> str:
+    return load().pf_last_error().decode()
+
+
+def _check(rc):
+    if rc != PF_OK:
+        raise PFError(rc, pf_last_error())
+
+
+# --------------------------------------------------------------------------
+# one-to-one wrappers of the C entry points
+# --------------------------------------------------------------------------
+def pf_build_opts_default() -> pf_build_opts:
+    o = pf_build_opts()
+    load().pf_build_opts_default(ctypes.byref(o))
+    return o
+
+
+def pf_plan_create(n_r: int, n_phi: int, r_min: float, r_max: float) -> int:
+    h = load().pf_plan_create(int(n_r), int(n_phi), float(r_min), float(r_max))
+    if not h:
+        raise PFError(PF_EINVAL, pf_last_error())
+    return h
+
+
+def pf_kernels_build(plan: int, opts: pf_build_opts | None = None, stream: int = 0) -> None:
+    _check(load().pf_kernels_build(plan, ctypes.byref(opts) if opts is not None else None,
+                                   stream or None))
+
+
+def pf_forces(plan: int, sigma: int, f_r: int, f_phi: int, stream: int = 0) -> None:
+    _check(load().pf_forces(plan, sigma, f_r, f_phi, stream or None))
+
+
+def pf_forces_backward(plan: int, g_fr: int, g_fphi: int, g_sigma: int, stream: int = 0) -> None:
+    _check(load().pf_forces_backward(plan, g_fr, g_fphi, g_sigma, stream or None))
+
+
+def pf_forces_batched(plans, sigma, f_r, f_phi, stream: int = 0) -> None:
+    n = len(plans)
+    arr = lambda xs: (ctypes.c_void_p * n)(*xs)
+    _check(load().pf_forces_batched(n, arr(plans), arr(sigma), arr(f_r), arr(f_phi),
+                                    stream or None))
+
+
+def pf_forces_timed(plan: int, backward: bool, in0: int, in1: int, out0: int, out1: int,
+                    stream: int = 0):
+    """Run the forward map (or its transpose) with events around each pass;
+    returns the three pass durations in ms."""
+    ms = (ctypes.c_float * 3)()
+    _check(load().pf_forces_timed(plan, int(bool(backward)), in0, in1 or None, out0,
+                                  out1 or None, stream or None, ms))
+    return [float(v) for v in ms]
+
+
+def pf_plan_geometry(plan: int, n_r: int):
+    rc = np.empty(n_r)
+    re = np.empty(n_r + 1)
+    dp = np.empty(1)
+    _check(load().pf_plan_geometry(plan, rc.ctypes.data, re.ctypes.data, dp.ctypes.data))
+    return rc, re, float(dp[0])
+
+
+def pf_plan_selfcell(plan: int):
+    out = np.empty(3)
+    _check(load().pf_plan_selfcell(plan, out.ctypes.data))
+    return out
+
+
+def pf_plan_tables(plan: int, n_r: int, n_phi: int):
+    out = np.empty((6, 2 * n_r - 1, n_phi))
+    _check(load().pf_plan_tables(plan, out.ctypes.data))
+    return out
+
+
+def pf_plan_destroy(plan: int) -> None:
+    load().pf_plan_destroy(plan)
+
+
+# --------------------------------------------------------------------------
+# conveniences
+# --------------------------------------------------------------------------
+def _stream():
+    import torch
+    return torch.cuda.current_stream().cuda_stream
+
+
+class Plan:
+    """A built n_r x n_phi log-polar grid on [r_min, r_max] (owns libpf state)."""
+
+    def __init__(self, n_r, n_phi, r_min, r_max, dtype="f32", n_tpz=19, cover_per=10,
+                 keep_tables=False, build=True):
+        self.n_r, self.n_phi = int(n_r), int(n_phi)
+        self.r_min, self.r_max = float(r_min), float(r_max)
+        self.handle = pf_plan_create(n_r, n_phi, r_min, r_max)
+        self.dtype = None
+        if build:
+            self.build(dtype, n_tpz, cover_per, keep_tables)
+
+    def build(self, dtype="f32", n_tpz=19, cover_per=10, keep_tables=False):
+        o = pf_build_opts_default()
+        o.dtype = PF_F64 if dtype in ("f64", "float64", PF_F64) else PF_F32
+        o.n_tpz, o.cover_per, o.keep_tables = int(n_tpz), int(cover_per), int(bool(keep_tables))
+        pf_kernels_build(self.handle, o, _stream())
+        self.dtype = "f64" if o.dtype == PF_F64 else "f32"
+        return self
+
+    @property
+    def torch_dtype(self):
+        import torch
+        return torch.float64 if self.dtype == "f64" else torch.float32
+
+    @property
+    def shape(self):
+        return (self.n_r, self.n_phi)
+
+    def geometry(self):
+        return pf_plan_geometry(self.handle, self.n_r)
+
+    def selfcell(self):
+        return pf_plan_selfcell(self.handle)
+
+    def tables(self):
+        return pf_plan_tables(self.handle, self.n_r, self.n_phi)
+
+    def _check_field(self, t, name):
+        import torch
+        if not isinstance(t, torch.Tensor) or not t.is_cuda:
+            raise TypeError("%s must be a CUDA tensor" % name)
+        if t.dtype != self.torch_dtype or tuple(t.shape) != self.shape or not t.is_contiguous():
+            raise TypeError("%s must be a contiguous %s tensor of shape %s"
+                            % (name, self.torch_dtype, self.shape))
+
+    def forces(self, sigma, out=None):
+        import torch
+        self._check_field(sigma, "sigma")
+        fr, fp = out if out is not None else (torch.empty_like(sigma), torch.empty_like(sigma))
+        pf_forces(self.handle, sigma.data_ptr(), fr.data_ptr(), fp.data_ptr(), _stream())
+        return fr, fp
+
+    def backward(self, g_fr, g_fphi, out=None):
+        import torch
+        self._check_field(g_fr, "g_fr")
+        self._check_field(g_fphi, "g_fphi")
+        gs = out if out is not None else torch.empty_like(g_fr)
+        pf_forces_backward(self.handle, g_fr.data_ptr(), g_fphi.data_ptr(), gs.data_ptr(),
+                           _stream())
+        return gs
+
+    def timed(self, a, b=None, backward=False):
+        """Pass durations (ms) of one forward (a = sigma) or transpose
+        (a, b = g_fr, g_fphi) call."""
+        import torch
+        if backward:
+            out = torch.empty_like(a)
+            return pf_forces_timed(self.handle, True, a.data_ptr(), b.data_ptr(),
+                                   out.data_ptr(), 0, _stream())
+        fr, fp = torch.empty_like(a), torch.empty_like(a)
+        return pf_forces_timed(self.handle, False, a.data_ptr(), 0, fr.data_ptr(),
+                               fp.data_ptr(), _stream())
+
+    def close(self):
+        if getattr(self, "handle", None):
+            pf_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def forces_batched(plans, sigmas, outs=None):
+    """Forward map of many disks (one persistent launch from a cached graph)."""
+    import torch
+    if outs is None:
+        outs = [(torch.empty_like(s), torch.empty_like(s)) for s in sigmas]
+    for p, s in zip(plans, sigmas):
+        p._check_field(s, "sigma")
+    pf_forces_batched([p.handle for p in plans], [s.data_ptr() for s in sigmas],
+                      [o[0].data_ptr() for o in outs], [o[1].data_ptr() for o in outs],
+                      _stream())
+    return outs
+
+
+def _make_function():
+    import torch
+
+    class _Forces(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, sigma, plan):
+            ctx.plan = plan
+            return plan.forces(sigma.contiguous())
+
+        @staticmethod
+        def backward(ctx, g_fr, g_fphi):
+            plan = ctx.plan
+            z = None
+            if g_fr is None:
+                g_fr = torch.zeros(plan.shape, dtype=plan.torch_dtype, device=g_fphi.device)
+            if g_fphi is None:
+                g_fphi = torch.zeros(plan.shape, dtype=plan.torch_dtype, device=g_fr.device)
+            return plan.backward(g_fr.contiguous(), g_fphi.contiguous()), z
+
+    return _Forces
+
+
+_FN = None
+
+
+def forces(sigma, plan: Plan):
+    """(F_r, F_phi) = A sigma, differentiable in sigma (backward = A^T)."""
+    global _FN
+    if _FN is None:
+        _FN = _make_function()
+    return _FN.apply(sigma, plan)

@@ -1,0 +1,216 @@
+// fft_core.hpp -- workgroup-level complex FFT building blocks for gfx950.
+//
+// A length-N transform is held by N/E cooperating threads, E points each, in
+// registers.  Points are kept in "strided" order: thread t holds element
+// t + e * (N/E) in v[e].  The transform runs as Stockham radix-E stages (the
+// last one of radix N / E^s when E does not divide evenly), each a set of
+// in-register radix-R butterflies; between stages the points go through an
+// LDS buffer.  The output comes back in the same strided natural order, so
+// a pointwise multiply and the inverse transform can follow in registers
+// with no extra exchange.  Twiddles come from a table w[j] = exp(-2 pi i j/N)
+// built on the host in extended precision.
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace pf {
+
+template <typename T>
+struct cx {
+    T x, y;
+};
+
+template <typename T>
+__device__ __forceinline__ cx<T> mk(T a, T b) { return cx<T>{a, b}; }
+template <typename T>
+__device__ __forceinline__ cx<T> operator+(cx<T> a, cx<T> b) { return {a.x + b.x, a.y + b.y}; }
+template <typename T>
+__device__ __forceinline__ cx<T> operator-(cx<T> a, cx<T> b) { return {a.x - b.x, a.y - b.y}; }
+template <typename T>
+__device__ __forceinline__ cx<T> cmul(cx<T> a, cx<T> b) {
+    return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+// a * conj(b)
+template <typename T>
+__device__ __forceinline__ cx<T> cmulc(cx<T> a, cx<T> b) {
+    return {a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y};
+}
+template <typename T>
+__device__ __forceinline__ cx<T> conj(cx<T> a) { return {a.x, -a.y}; }
+template <typename T>
+__device__ __forceinline__ cx<T> scale(cx<T> a, T s) { return {a.x * s, a.y * s}; }
+// multiply by -i
+template <typename T>
+__device__ __forceinline__ cx<T> mul_mi(cx<T> a) { return {a.y, -a.x}; }
+
+// ---------------------------------------------------------------------------
+// In-register forward DFTs of radix 2, 4, 8, 16 (sign -1).
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ void dft2(cx<T> &a, cx<T> &b) {
+    cx<T> t = a - b;
+    a = a + b;
+    b = t;
+}
+
+template <typename T>
+__device__ __forceinline__ void dft4(cx<T> &a0, cx<T> &a1, cx<T> &a2, cx<T> &a3) {
+    cx<T> s0 = a0 + a2, d0 = a0 - a2;
+    cx<T> s1 = a1 + a3, d1 = mul_mi(a1 - a3);
+    a0 = s0 + s1;
+    a2 = s0 - s1;
+    a1 = d0 + d1;
+    a3 = d0 - d1;
+}
+
+template <int R, typename T>
+__device__ __forceinline__ void dft(cx<T> *u);
+
+template <>
+__device__ __forceinline__ void dft<2, float>(cx<float> *u) { dft2(u[0], u[1]); }
+template <>
+__device__ __forceinline__ void dft<2, double>(cx<double> *u) { dft2(u[0], u[1]); }
+template <>
+__device__ __forceinline__ void dft<4, float>(cx<float> *u) { dft4(u[0], u[1], u[2], u[3]); }
+template <>
+__device__ __forceinline__ void dft<4, double>(cx<double> *u) { dft4(u[0], u[1], u[2], u[3]); }
+
+template <typename T>
+__device__ __forceinline__ void dft8_impl(cx<T> *u) {
+    const T h = T(0.70710678118654752440084436210484903928);
+    // two radix-4 on even / odd, then radix-2 with W8 twiddles
+    cx<T> e0 = u[0], e1 = u[2], e2 = u[4], e3 = u[6];
+    cx<T> o0 = u[1], o1 = u[3], o2 = u[5], o3 = u[7];
+    dft4(e0, e1, e2, e3);
+    dft4(o0, o1, o2, o3);
+    // o_k *= exp(-2 pi i k / 8)
+    cx<T> w1 = {(o1.x + o1.y) * h, (o1.y - o1.x) * h};   // * (1 - i)/sqrt2
+    cx<T> w2 = mul_mi(o2);                               // * -i
+    cx<T> w3 = {(o3.y - o3.x) * h, -(o3.x + o3.y) * h};  // * (-1 - i)/sqrt2
+    u[0] = e0 + o0;
+    u[4] = e0 - o0;
+    u[1] = e1 + w1;
+    u[5] = e1 - w1;
+    u[2] = e2 + w2;
+    u[6] = e2 - w2;
+    u[3] = e3 + w3;
+    u[7] = e3 - w3;
+}
+template <>
+__device__ __forceinline__ void dft<8, float>(cx<float> *u) { dft8_impl(u); }
+template <>
+__device__ __forceinline__ void dft<8, double>(cx<double> *u) { dft8_impl(u); }
+
+template <typename T>
+__device__ __forceinline__ void dft16_impl(cx<T> *u) {
+    // 4 x 4 with internal twiddles exp(-2 pi i j k / 16)
+    const T c1 = T(0.92387953251128675612818318939678828682);
+    const T s1 = T(0.38268343236508977172845998403039886676);
+    const T h = T(0.70710678118654752440084436210484903928);
+    cx<T> a[4][4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        a[j][0] = u[j];
+        a[j][1] = u[j + 4];
+        a[j][2] = u[j + 8];
+        a[j][3] = u[j + 12];
+        dft4(a[j][0], a[j][1], a[j][2], a[j][3]);
+    }
+    // twiddle a[j][k] by exp(-2 pi i j k / 16)
+    const cx<T> w[10] = {{T(1), T(0)}, {c1, -s1}, {h, -h}, {s1, -c1}, {T(0), T(-1)},
+                         {-s1, -c1}, {-h, -h}, {-c1, -s1}, {T(-1), T(0)}, {-c1, s1}};
+#pragma unroll
+    for (int j = 1; j < 4; ++j)
+#pragma unroll
+        for (int k = 1; k < 4; ++k) a[j][k] = cmul(a[j][k], w[j * k]);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        dft4(a[0][k], a[1][k], a[2][k], a[3][k]);
+        u[k] = a[0][k];
+        u[k + 4] = a[1][k];
+        u[k + 8] = a[2][k];
+        u[k + 12] = a[3][k];
+    }
+}
+template <>
+__device__ __forceinline__ void dft<16, float>(cx<float> *u) { dft16_impl(u); }
+template <>
+__device__ __forceinline__ void dft<16, double>(cx<double> *u) { dft16_impl(u); }
+
+// ---------------------------------------------------------------------------
+// LDS accessors.  Element i of the FFT group lives at base + i * stride.
+// ---------------------------------------------------------------------------
+template <typename T>
+struct Lds {
+    cx<T> *p;
+    int base, stride;
+    __device__ __forceinline__ cx<T> ld(int i) const { return p[base + i * stride]; }
+    __device__ __forceinline__ void st(int i, cx<T> v) const { p[base + i * stride] = v; }
+};
+
+// ---------------------------------------------------------------------------
+// Stockham stages.  Template parameters: N (length), E (points per thread),
+// NS (span of the stage).  tw: table exp(-2 pi i j / (N * TS)) read with
+// stride TS, i.e. the N-point table is tw[j * TS].
+// All threads of the workgroup must call this together (it contains
+// __syncthreads()).
+// ---------------------------------------------------------------------------
+template <int N, int E, int NS, typename T>
+__device__ __forceinline__ void fft_stages(cx<T> (&v)[E], int t, const Lds<T> &lds,
+                                           const cx<T> *__restrict__ tw, int ts) {
+    constexpr int TH = N / E;                 // threads per transform
+    constexpr int REM = N / NS;
+    constexpr int R = REM >= E ? E : REM;     // radix of this stage
+    constexpr int NB = E / R;                 // butterflies per thread
+    constexpr bool LAST = (NS * R == N);
+    static_assert(R >= 2, "radix");
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+        const int b = t + q * TH;
+        const int k = b & (NS - 1);
+        cx<T> u[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) u[r] = v[q + r * NB];
+        if (NS > 1) {
+            constexpr int STEP = N / (NS * R);
+#pragma unroll
+            for (int r = 1; r < R; ++r) u[r] = cmul(u[r], tw[(k * r * STEP) * ts]);
+        }
+        dft<R, T>(u);
+        if (LAST) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[q + r * NB] = u[r];
+        } else {
+            const int base = (b - k) * R + k;
+#pragma unroll
+            for (int r = 0; r < R; ++r) lds.st(base + r * NS, u[r]);
+        }
+    }
+    if constexpr (!LAST) {
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < E; ++e) v[e] = lds.ld(t + e * TH);
+        __syncthreads();
+        fft_stages<N, E, NS * R, T>(v, t, lds, tw, ts);
+    }
+}
+
+// Forward transform (sign -1) in strided order.
+template <int N, int E, typename T>
+__device__ __forceinline__ void fft_fwd(cx<T> (&v)[E], int t, const Lds<T> &lds,
+                                        const cx<T> *__restrict__ tw, int ts) {
+    static_assert((N & (N - 1)) == 0 && N >= E && E >= 2, "sizes");
+    fft_stages<N, E, 1, T>(v, t, lds, tw, ts);
+}
+
+// Inverse transform (sign +1, unnormalised) as conj(F(conj(x))).
+template <int N, int E, typename T>
+__device__ __forceinline__ void fft_inv(cx<T> (&v)[E], int t, const Lds<T> &lds,
+                                        const cx<T> *__restrict__ tw, int ts) {
+#pragma unroll
+    for (int e = 0; e < E; ++e) v[e].y = -v[e].y;
+    fft_stages<N, E, 1, T>(v, t, lds, tw, ts);
+#pragma unroll
+    for (int e = 0; e < E; ++e) v[e].y = -v[e].y;
+}
+
+}  // namespace pf

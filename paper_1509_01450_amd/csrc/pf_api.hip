@@ -1,0 +1,470 @@
+// pf_api.hip -- host side of the C ABI declared in include/pf.h: argument
+// validation, plan geometry (Sec. 3.2.1), build orchestration and the launch
+// sequences of the forward map and its transpose.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <new>
+
+#include "pf_batched.hpp"
+#include "pf_common.hpp"
+
+namespace pf {
+
+static thread_local char g_err[512] = "";
+
+void set_error(const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+}
+void clear_error() { g_err[0] = 0; }
+
+void twiddles_host(int n, std::vector<double> &re, std::vector<double> &im) {
+    re.resize(n);
+    im.resize(n);
+    const long double two_pi = 6.283185307179586476925286766559005768L;
+    for (int j = 0; j < n; ++j) {
+        // reduce to the first octant by symmetry so every entry is accurate
+        const long double a = two_pi * (long double)j / (long double)n;
+        re[j] = (double)cosl(a);
+        im[j] = (double)(-sinl(a));
+    }
+    // exact values at the quarter points
+    for (int q = 0; q < 4; ++q) {
+        if ((long)q * n % 4) continue;
+        const int j = (int)((long)q * n / 4);
+        static const double c[4] = {1, 0, -1, 0}, s[4] = {0, -1, 0, 1};
+        re[j] = c[q];
+        im[j] = s[q];
+    }
+}
+
+int upload_twiddles(int n, bool f64, void **dst) {
+    std::vector<double> re, im;
+    twiddles_host(n, re, im);
+    const size_t bytes = (size_t)n * (f64 ? 16 : 8);
+    std::vector<unsigned char> buf(bytes);
+    for (int j = 0; j < n; ++j) {
+        if (f64) {
+            double v[2] = {re[j], im[j]};
+            memcpy(&buf[(size_t)j * 16], v, 16);
+        } else {
+            float v[2] = {(float)re[j], (float)im[j]};
+            memcpy(&buf[(size_t)j * 8], v, 8);
+        }
+    }
+    PF_HIP(hipMalloc(dst, bytes));
+    PF_HIP(hipMemcpy(*dst, buf.data(), bytes, hipMemcpyHostToDevice));
+    return PF_OK;
+}
+
+Schedule default_schedule(int n_phi, int L, bool f64) {
+    Schedule s;
+    const int M = n_phi / 2;
+    s.rows.E = M >= 2048 ? 16 : (M < 8 ? M : 8);
+    if (s.rows.E < 4) s.rows.E = 4;
+    {
+        const int th = M / s.rows.E;
+        s.rows.G = th >= 256 ? 1 : 256 / th;
+        while (s.rows.G > 1 && !valid_shape_rows(M, s.rows, f64)) s.rows.G /= 2;
+    }
+    s.cols.E = L >= 4096 ? 16 : 8;
+    {
+        const int th = L / s.cols.E;
+        s.cols.G = th >= 256 ? 1 : 256 / th;
+        while (s.cols.G > 1 && !valid_shape_cols(L, s.cols, f64)) s.cols.G /= 2;
+    }
+    return s;
+}
+
+static int64_t next_uid() {
+    static std::mutex mu;
+    static int64_t uid = 0;
+    std::lock_guard<std::mutex> g(mu);
+    return ++uid;
+}
+
+static void free_plan_device(Plan *p) {
+    if (p->spec) (void)hipFree(p->spec);
+    if (p->twN) (void)hipFree(p->twN);
+    if (p->twL) (void)hipFree(p->twL);
+    if (p->ws) (void)hipFree(p->ws);
+    if (p->tables) (void)hipFree(p->tables);
+    p->spec = p->twN = p->twL = p->ws = nullptr;
+    p->tables = nullptr;
+    p->built = false;
+}
+
+static int device_present() {
+    int n = 0;
+    hipError_t e = hipGetDeviceCount(&n);
+    if (e != hipSuccess || n <= 0) {
+        set_error("no GPU device available");
+        return PF_ENODEV;
+    }
+    return PF_OK;
+}
+
+static bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+}  // namespace pf
+
+using pf::Plan;
+
+struct pf_plan_s {
+    Plan p;
+};
+
+namespace {
+
+int check_call(pf_plan h, const void *a, const void *b, const void *c) {
+    if (!h) {
+        pf::set_error("null plan");
+        return PF_EINVAL;
+    }
+    if (!a || !b || !c) {
+        pf::set_error("null field pointer");
+        return PF_EINVAL;
+    }
+    if (!h->p.built) {
+        pf::set_error("plan not built (call pf_kernels_build first)");
+        return PF_ESTATE;
+    }
+    return PF_OK;
+}
+
+template <typename T>
+int forces_t(const Plan &p, const T *sigma, T *fr, T *fp, hipStream_t st) {
+    using C = pf::cx<T>;
+    C *S = (C *)p.ws;
+    C *Zr = S + (size_t)p.n_r * p.H;
+    C *Zp = Zr + (size_t)p.n_r * p.H;
+    int rc = pf::launch_rows_r2c<T>(p, sigma, nullptr, 1, p.n_r, S, nullptr, (const C *)p.twN,
+                                    p.sched.rows, st);
+    if (rc) return rc;
+    rc = pf::launch_cols_fwd<T>(p, S, Zr, Zp, (const C *)p.spec, (const C *)p.twL, p.sched.cols,
+                                st);
+    if (rc) return rc;
+    return pf::launch_rows_c2r<T>(p, Zr, Zp, 2, p.n_r, fr, fp, (const C *)p.twN, p.sched.rows,
+                                  st);
+}
+
+template <typename T>
+int backward_t(const Plan &p, const T *gr, const T *gp, T *gs, hipStream_t st) {
+    using C = pf::cx<T>;
+    C *Vr = (C *)p.ws;
+    C *Vp = Vr + (size_t)p.n_r * p.H;
+    C *D = Vp + (size_t)p.n_r * p.H;
+    int rc = pf::launch_rows_r2c<T>(p, gr, gp, 2, p.n_r, Vr, Vp, (const C *)p.twN, p.sched.rows,
+                                    st);
+    if (rc) return rc;
+    rc = pf::launch_cols_adj<T>(p, Vr, Vp, D, (const C *)p.spec, (const C *)p.twL, p.sched.cols,
+                                st);
+    if (rc) return rc;
+    return pf::launch_rows_c2r<T>(p, D, nullptr, 1, p.n_r, gs, nullptr, (const C *)p.twN,
+                                  p.sched.rows, st);
+}
+
+// The passes of forces_t / backward_t with an event before, between and
+// after them.
+template <typename T>
+int timed_t(const Plan &p, bool bwd, const void *in0, const void *in1, void *out0, void *out1,
+            hipStream_t st, hipEvent_t *ev) {
+    using C = pf::cx<T>;
+    C *A = (C *)p.ws;
+    C *B = A + (size_t)p.n_r * p.H;
+    C *Cc = B + (size_t)p.n_r * p.H;
+    int rc;
+    PF_HIP(hipEventRecord(ev[0], st));
+    if (!bwd)
+        rc = pf::launch_rows_r2c<T>(p, (const T *)in0, nullptr, 1, p.n_r, A, nullptr,
+                                    (const C *)p.twN, p.sched.rows, st);
+    else
+        rc = pf::launch_rows_r2c<T>(p, (const T *)in0, (const T *)in1, 2, p.n_r, A, B,
+                                    (const C *)p.twN, p.sched.rows, st);
+    if (rc) return rc;
+    PF_HIP(hipEventRecord(ev[1], st));
+    if (!bwd)
+        rc = pf::launch_cols_fwd<T>(p, A, B, Cc, (const C *)p.spec, (const C *)p.twL,
+                                    p.sched.cols, st);
+    else
+        rc = pf::launch_cols_adj<T>(p, A, B, Cc, (const C *)p.spec, (const C *)p.twL,
+                                    p.sched.cols, st);
+    if (rc) return rc;
+    PF_HIP(hipEventRecord(ev[2], st));
+    if (!bwd)
+        rc = pf::launch_rows_c2r<T>(p, B, Cc, 2, p.n_r, (T *)out0, (T *)out1, (const C *)p.twN,
+                                    p.sched.rows, st);
+    else
+        rc = pf::launch_rows_c2r<T>(p, Cc, nullptr, 1, p.n_r, (T *)out0, nullptr,
+                                    (const C *)p.twN, p.sched.rows, st);
+    if (rc) return rc;
+    PF_HIP(hipEventRecord(ev[3], st));
+    return PF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *pf_last_error(void) { return pf::g_err; }
+
+const char *pf_version(void) { return "pf 0.1 (gfx950)"; }
+
+void pf_build_opts_default(pf_build_opts *o) {
+    if (!o) return;
+    o->dtype = PF_F32;
+    o->n_tpz = 19;
+    o->cover_per = 10;
+    o->keep_tables = 0;
+}
+
+pf_plan pf_plan_create(int n_r, int n_phi, double r_min, double r_max) {
+    pf::clear_error();
+    if (n_r < 4 || n_r > 4096) {
+        pf::set_error("n_r = %d outside [4, 4096]", n_r);
+        return nullptr;
+    }
+    if (!pf::is_pow2(n_phi) || n_phi < 8 || n_phi > 8192) {
+        pf::set_error("n_phi = %d must be a power of two in [8, 8192]", n_phi);
+        return nullptr;
+    }
+    if (!std::isfinite(r_min) || !std::isfinite(r_max) || !(r_min > 0) || !(r_max > r_min)) {
+        pf::set_error("need finite 0 < r_min < r_max (got %g, %g)", r_min, r_max);
+        return nullptr;
+    }
+    pf_plan_s *h = new (std::nothrow) pf_plan_s();
+    if (!h) {
+        pf::set_error("out of host memory");
+        return nullptr;
+    }
+    Plan &p = h->p;
+    p.n_r = n_r;
+    p.n_phi = n_phi;
+    p.M = n_phi / 2;
+    p.H = n_phi / 2 + 1;
+    int L = 8;
+    while (L < 2 * n_r) L *= 2;  // zero padding: any L >= 2 n_r - 1 is exact
+    p.L = L;
+    p.ldspec = L / 2 + 1;
+    p.r_min = r_min;
+    p.r_max = r_max;
+    p.beta = std::pow(r_max / r_min, 1.0 / n_r);
+    p.dphi = 2.0 * M_PI / n_phi;
+    // g = r_i delta^r_i:  r_i / (r_{i+1} - r_{i-1}) = 1 / (beta - 1/beta), and
+    // the one-sided ends 1 / (beta - 1), 1 / (1 - 1/beta)
+    p.ca = 1.0 / (p.beta - 1.0 / p.beta);
+    p.c0 = 1.0 / (p.beta - 1.0);
+    p.cn = 1.0 / (1.0 - 1.0 / p.beta);
+    pf_build_opts_default(&p.opts);
+    p.uid = pf::next_uid();
+    return h;
+}
+
+void pf_plan_destroy(pf_plan h) {
+    if (!h) return;
+    pf::batched_forget(h->p.uid);
+    pf::free_plan_device(&h->p);
+    delete h;
+}
+
+int pf_plan_geometry(pf_plan h, double *r_centres, double *r_edges, double *dphi) {
+    pf::clear_error();
+    if (!h) {
+        pf::set_error("null plan");
+        return PF_EINVAL;
+    }
+    const Plan &p = h->p;
+    for (int i = 0; i <= p.n_r; ++i) {
+        const double lo = p.r_min * std::pow(p.beta, i);
+        if (r_edges) r_edges[i] = lo;
+        if (r_centres && i < p.n_r) {
+            const double hi = p.r_min * std::pow(p.beta, i + 1);
+            r_centres[i] = 0.5 * (lo + hi);
+        }
+    }
+    if (dphi) *dphi = p.dphi;
+    return PF_OK;
+}
+
+int pf_plan_selfcell(pf_plan h, double out[3]) {
+    pf::clear_error();
+    if (!h || !out) {
+        pf::set_error("null argument");
+        return PF_EINVAL;
+    }
+    if (!h->p.built) {
+        pf::set_error("plan not built");
+        return PF_ESTATE;
+    }
+    for (int q = 0; q < 3; ++q) out[q] = h->p.selfk[q];
+    return PF_OK;
+}
+
+int pf_plan_tables(pf_plan h, double *dst) {
+    pf::clear_error();
+    if (!h || !dst) {
+        pf::set_error("null argument");
+        return PF_EINVAL;
+    }
+    const Plan &p = h->p;
+    if (!p.built || !p.tables) {
+        pf::set_error("plan not built with keep_tables");
+        return PF_ESTATE;
+    }
+    const int rows = 2 * p.n_r - 1;
+    for (int k = 0; k < 6; ++k)
+        for (int ir = 0; ir < rows; ++ir) {
+            const int m = ir - (p.n_r - 1);
+            const int row = (m % p.L + p.L) % p.L;
+            PF_HIP(hipMemcpy(dst + ((size_t)k * rows + ir) * p.n_phi,
+                             p.tables + ((size_t)k * p.L + row) * p.n_phi,
+                             (size_t)p.n_phi * sizeof(double), hipMemcpyDeviceToHost));
+        }
+    return PF_OK;
+}
+
+int pf_kernels_build(pf_plan h, const pf_build_opts *opts, void *stream) {
+    pf::clear_error();
+    if (!h) {
+        pf::set_error("null plan");
+        return PF_EINVAL;
+    }
+    pf_build_opts o;
+    if (opts)
+        o = *opts;
+    else
+        pf_build_opts_default(&o);
+    if (o.dtype != PF_F32 && o.dtype != PF_F64) {
+        pf::set_error("dtype must be PF_F32 or PF_F64");
+        return PF_EINVAL;
+    }
+    if (o.n_tpz < 1 || o.n_tpz > 1024) {
+        pf::set_error("n_tpz = %d outside [1, 1024]", o.n_tpz);
+        return PF_EINVAL;
+    }
+    if (o.cover_per < 1 || o.cover_per > 64) {
+        pf::set_error("cover_per = %d outside [1, 64]", o.cover_per);
+        return PF_EINVAL;
+    }
+    int rc = pf::device_present();
+    if (rc) return rc;
+    Plan &p = h->p;
+    pf::batched_forget(p.uid);
+    pf::free_plan_device(&p);
+    p.opts = o;
+    PF_HIP(hipGetDevice(&p.device));
+    hipStream_t st = (hipStream_t)stream;
+    const bool f64 = o.dtype == PF_F64;
+    p.sched = pf::default_schedule(p.n_phi, p.L, f64);
+    rc = pf::build_tables_and_spectra(p, st);
+    if (rc) {
+        pf::free_plan_device(&p);
+        return rc;
+    }
+    rc = pf::upload_twiddles(p.n_phi, f64, &p.twN);
+    if (!rc) rc = pf::upload_twiddles(p.L, f64, &p.twL);
+    if (!rc) {
+        hipError_t e = hipMalloc(&p.ws, (size_t)3 * p.n_r * p.H * (f64 ? 16 : 8));
+        if (e != hipSuccess) {
+            pf::set_error("workspace allocation failed: %s", hipGetErrorString(e));
+            rc = PF_ENOMEM;
+        }
+    }
+    if (rc) {
+        pf::free_plan_device(&p);
+        return rc;
+    }
+    pf::autotune_plan(p, st);
+    p.built = true;
+    return PF_OK;
+}
+
+int pf_forces(pf_plan h, const void *sigma, void *f_r, void *f_phi, void *stream) {
+    pf::clear_error();
+    int rc = check_call(h, sigma, f_r, f_phi);
+    if (rc) return rc;
+    const Plan &p = h->p;
+    hipStream_t st = (hipStream_t)stream;
+    if (p.opts.dtype == PF_F64)
+        return forces_t<double>(p, (const double *)sigma, (double *)f_r, (double *)f_phi, st);
+    return forces_t<float>(p, (const float *)sigma, (float *)f_r, (float *)f_phi, st);
+}
+
+int pf_forces_backward(pf_plan h, const void *g_fr, const void *g_fphi, void *g_sigma,
+                       void *stream) {
+    pf::clear_error();
+    int rc = check_call(h, g_fr, g_fphi, g_sigma);
+    if (rc) return rc;
+    const Plan &p = h->p;
+    hipStream_t st = (hipStream_t)stream;
+    if (p.opts.dtype == PF_F64)
+        return backward_t<double>(p, (const double *)g_fr, (const double *)g_fphi,
+                                  (double *)g_sigma, st);
+    return backward_t<float>(p, (const float *)g_fr, (const float *)g_fphi, (float *)g_sigma, st);
+}
+
+int pf_forces_timed(pf_plan h, int backward, const void *in0, const void *in1, void *out0,
+                    void *out1, void *stream, float *pass_ms) {
+    pf::clear_error();
+    int rc = check_call(h, in0, out0, pass_ms);
+    if (rc) return rc;
+    if ((backward && !in1) || (!backward && !out1)) {
+        pf::set_error("null field pointer");
+        return PF_EINVAL;
+    }
+    const Plan &p = h->p;
+    hipStream_t st = (hipStream_t)stream;
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    for (int k = 0; k < 4; ++k) {
+        hipError_t e = hipEventCreate(&ev[k]);
+        if (e != hipSuccess) {
+            for (int j = 0; j < k; ++j) (void)hipEventDestroy(ev[j]);
+            pf::set_error("hipEventCreate: %s", hipGetErrorString(e));
+            return PF_EHIP;
+        }
+    }
+    rc = p.opts.dtype == PF_F64
+             ? timed_t<double>(p, backward != 0, in0, in1, out0, out1, st, ev)
+             : timed_t<float>(p, backward != 0, in0, in1, out0, out1, st, ev);
+    if (!rc) {
+        hipError_t e = hipEventSynchronize(ev[3]);
+        for (int k = 0; k < 3 && e == hipSuccess; ++k) e = hipEventElapsedTime(&pass_ms[k], ev[k], ev[k + 1]);
+        if (e != hipSuccess) {
+            pf::set_error("event timing: %s", hipGetErrorString(e));
+            rc = PF_EHIP;
+        }
+    }
+    for (int k = 0; k < 4; ++k) (void)hipEventDestroy(ev[k]);
+    return rc;
+}
+
+int pf_forces_batched(int n, const pf_plan *plans, const void *const *sigma, void *const *f_r,
+                      void *const *f_phi, void *stream) {
+    pf::clear_error();
+    if (n < 1 || n > 4096 || !plans || !sigma || !f_r || !f_phi) {
+        pf::set_error("bad batch arguments (n = %d)", n);
+        return PF_EINVAL;
+    }
+    std::vector<const Plan *> ps(n);
+    for (int k = 0; k < n; ++k) {
+        int rc = check_call(plans[k], sigma[k], f_r[k], f_phi[k]);
+        if (rc) return rc;
+        ps[k] = &plans[k]->p;
+        if (ps[k]->opts.dtype != ps[0]->opts.dtype) {
+            pf::set_error("batched plans must share one precision");
+            return PF_EINVAL;
+        }
+        if (ps[k]->device != ps[0]->device) {
+            pf::set_error("batched plans must live on one device");
+            return PF_EINVAL;
+        }
+    }
+    return pf::batched_forces(ps, sigma, f_r, f_phi, (hipStream_t)stream);
+}
+
+}  // extern "C"

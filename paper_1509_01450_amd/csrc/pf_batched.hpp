@@ -1,0 +1,18 @@
+// pf_batched.hpp -- many-disk forward map and launch-shape tuning.
+#pragma once
+#include <vector>
+
+#include "pf_common.hpp"
+
+namespace pf {
+
+// Forward map for several plans in one persistent launch replayed from a
+// cached HIP graph.
+int batched_forces(const std::vector<const Plan *> &plans, const void *const *sigma,
+                   void *const *f_r, void *const *f_phi, hipStream_t st);
+// Drop cached batch state that refers to plan `uid`.
+void batched_forget(int64_t uid);
+// Choose launch shapes for the plan's sizes (timed on the device, cached).
+void autotune_plan(Plan &p, hipStream_t st);
+
+}  // namespace pf

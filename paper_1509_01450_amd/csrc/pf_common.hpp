@@ -1,0 +1,98 @@
+// pf_common.hpp -- internal declarations shared by the libpf translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/pf.h"
+#include "fft_core.hpp"
+
+namespace pf {
+
+// thread-local error text behind pf_last_error()
+void set_error(const char *fmt, ...);
+void clear_error();
+
+#define PF_HIP(call)                                                              \
+    do {                                                                          \
+        hipError_t e_ = (call);                                                   \
+        if (e_ != hipSuccess) {                                                   \
+            ::pf::set_error("%s failed: %s (%s:%d)", #call, hipGetErrorString(e_), \
+                            __FILE__, __LINE__);                                  \
+            return PF_EHIP;                                                       \
+        }                                                                         \
+    } while (0)
+
+// Launch shape of one transform pass: E points per thread and G transforms
+// (rows or columns) per workgroup.
+struct Shape {
+    int E = 8;
+    int G = 1;
+};
+
+// Schedule of a plan: launch shapes of the three passes for its sizes.
+struct Schedule {
+    Shape rows;   // row transforms along phi (length n_phi, half-length M)
+    Shape cols;   // column transforms along u (length L)
+};
+
+struct Plan {
+    int n_r = 0, n_phi = 0, M = 0, H = 0, L = 0, ldspec = 0;
+    double r_min = 0, r_max = 0, beta = 0, dphi = 0;
+    // radial slope coefficients of g = r delta^r (interior, first, last row)
+    double ca = 0, c0 = 0, cn = 0;
+
+    bool built = false;
+    pf_build_opts opts{};
+    int device = -1;
+    double selfk[3] = {0, 0, 0};
+
+    void *spec = nullptr;     // [4][H][ldspec] complex, plan precision
+    void *twN = nullptr;      // n_phi-point twiddles, plan precision
+    void *twL = nullptr;      // L-point twiddles, plan precision
+    void *ws = nullptr;       // workspace: 3 * n_r * H complex, plan precision
+    double *tables = nullptr; // [6][L][n_phi] FP64 (only with keep_tables)
+    Schedule sched;
+    int64_t uid = 0;          // identity for batch-graph caching
+
+    size_t elt() const { return opts.dtype == PF_F64 ? 8 : 4; }
+};
+
+// ---- kernels (pf_passes.hip) -----------------------------------------------
+// Row transforms along phi of n_arr arrays of n_rows rows each.
+template <typename T>
+int launch_rows_r2c(const Plan &p, const T *in0, const T *in1, int n_arr, int n_rows,
+                    cx<T> *out0, cx<T> *out1, const cx<T> *twN, Shape s, hipStream_t st);
+template <typename T>
+int launch_rows_c2r(const Plan &p, const cx<T> *in0, const cx<T> *in1, int n_arr,
+                    int n_rows, T *out0, T *out1, const cx<T> *twN, Shape s, hipStream_t st);
+// Column pass of the forward map (fused radial slope, u-FFTs, spectral
+// multiply-accumulate, inverse u-FFTs, crop).
+template <typename T>
+int launch_cols_fwd(const Plan &p, const cx<T> *S, cx<T> *Zr, cx<T> *Zp, const cx<T> *spec,
+                    const cx<T> *twL, Shape s, hipStream_t st);
+// Column pass of the transpose.
+template <typename T>
+int launch_cols_adj(const Plan &p, const cx<T> *Vr, const cx<T> *Vp, cx<T> *D,
+                    const cx<T> *spec, const cx<T> *twL, Shape s, hipStream_t st);
+
+// ---- kernels (pf_tables.hip) ------------------------------------------------
+int build_tables_and_spectra(Plan &p, hipStream_t st);
+
+// ---- host helpers -------------------------------------------------------------
+// exp(-2 pi i j / n) for j in [0, n), computed in long double
+void twiddles_host(int n, std::vector<double> &re, std::vector<double> &im);
+int upload_twiddles(int n, bool f64, void **dst);
+Schedule default_schedule(int n_phi, int L, bool f64);
+bool valid_shape_rows(int M, Shape s, bool f64);
+bool valid_shape_cols(int L, Shape s, bool f64);
+
+inline int ilog2(int v) {
+    int k = 0;
+    while ((1 << k) < v) ++k;
+    return k;
+}
+
+}  // namespace pf

@@ -1,0 +1,616 @@
+// pf_tables.hip -- one-time FP64 construction of the force-kernel tables and
+// their spectra (Sec. 3.2.1 and 4; Eq. 30-33, 41-46, A22-A24).
+//
+// Kernel tables.  For destination-minus-source offset (m, n) the six kernels
+// are integrals over the source cell in eta = rbar / r_i and
+// xi = phibar - phi_j (Eq. 33):
+//   eta in [2 beta^-m / (1+beta), 2 beta^(1-m) / (1+beta)],
+//   xi  in [xi_c - dphi/2, xi_c + dphi/2],  xi_c = -n dphi  (n wrapped to
+//   (-n_phi/2, n_phi/2]),  F = sqrt(eta^2 - 2 eta cos xi + 1),
+//   K^{r,0}  = -int int eta (1 - eta cos xi) / F^3
+//   K^{r,r}  = -int int eta (1 - eta cos xi) (eta - beta^-m) / F^3
+//   K^{r,phi}= -int int eta (1 - eta cos xi) (xi - xi_c) / F^3
+//   K^{phi,0}=  int int eta^2 sin xi / F^3
+//   K^{phi,r}=  int int eta^2 sin xi (eta - beta^-m) / F^3
+//   K^{phi,phi}=int int eta^2 sin xi (xi - xi_c) / F^3.
+// SIM (Sec. 4): K^{r,0}, K^{r,r}, K^{r,phi}, K^{phi,phi} take the composite
+// trapezoid rule with n_tpz panels in xi (Eq. 41-43) of the exact eta
+// integral; K^{phi,0} and K^{phi,r} are exact (A30-A31).  Here every exact
+// one-dimensional integral is evaluated by 16-point Gauss-Legendre on panels
+// graded geometrically towards the nearest complex singularity of the
+// integrand (eta = exp(+-i xi)), which keeps each panel's Bernstein-ellipse
+// ratio above 3.7 and so the rule exact to rounding.  The xi integral of the
+// K^{phi,.} kernels is done in closed form first:
+//   int eta^2 sin xi / F^3 dxi = -eta / F,
+//   1/F(xi_l) - 1/F(xi_u) = 4 eta sin(xi_c) sin(dphi/2) / (F_l F_u (F_l + F_u)).
+//
+// Self cell (m = n = 0, Sec. 4, Eq. 44-46, Fig. 1): the fan-shaped cell of
+// centre (1, 0) (the kernels depend only on beta and dphi, Eq. 33) is
+// covered by a Cartesian grid of cells of size Delta x / per by
+// Delta y / per, aligned so (1, 0) is a cell centre, a cell kept iff its
+// centre lies in the closed fan.  The Cartesian second-order method
+// (Eq. 9-15, closed forms A8-A13) gives the force at (1, 0) of the test
+// densities 1, rbar - 1 and phibar, with the densities' slopes taken at each
+// Cartesian centre; these are K^{r,0}_{00}, K^{r,r}_{00} and
+// K^{phi,phi}_{00}.  The other three self kernels vanish by symmetry.
+//
+// Spectra.  With T_rr and T_phir multiplied by beta^m (the r_i / r_i'
+// factor of Eq. 28), all six tables are 2-D transformed (rows along phi,
+// then columns along u, padded to L), the azimuthal slope kernels folded in
+// with the periodic central difference, and normalised by 1/(L n_phi):
+//   E_r = F(T_r0) + i sin(2 pi k / n_phi) / dphi * F(T_rphi)
+//   Q_r = F(beta^m T_rr)
+//   E_p = F(T_p0) + i sin(2 pi k / n_phi) / dphi * F(T_pphi)
+//   Q_p = F(beta^m T_pr)
+// stored for k_u in [0, L/2] only.  The k = 0 column of E_p and Q_p is set
+// to exactly zero (odd kernels: an axisymmetric density has no azimuthal
+// force).
+#include <cmath>
+#include <cstdio>
+
+#include "pf_common.hpp"
+
+namespace pf {
+
+// 8- and 16-point Gauss-Legendre rules on [-1, 1] (positive half).
+__constant__ double kGL8x[4] = {0.18343464249564978, 0.52553240991632899, 0.79666647741362673,
+                                0.96028985649753618};
+__constant__ double kGL8w[4] = {0.36268378337836177, 0.31370664587788705, 0.22238103445337434,
+                                0.10122853629037669};
+__constant__ double kGL16x[8] = {0.095012509837637454, 0.28160355077925892, 0.45801677765722737,
+                                 0.61787624440264377,  0.755404408355003,   0.86563120238783176,
+                                 0.9445750230732326,   0.98940093499164994};
+__constant__ double kGL16w[8] = {0.18945061045506859,  0.18260341504492361,  0.16915651939500262,
+                                 0.14959598881657676,  0.12462897125553403,  0.095158511682492591,
+                                 0.062253523938647706, 0.027152459411754037};
+
+__device__ __forceinline__ double Fpol(double eta, double sh) {
+    const double d = eta - 1.0;
+    return sqrt(d * d + 4.0 * eta * sh * sh);
+}
+
+// 16-point Gauss-Legendre over panels of [a, b] graded towards the complex
+// point (pr, pi).  f(eta, weight) accumulates.
+template <class Fn>
+__device__ void graded_gl16(double a, double b, double pr, double pim, Fn &f) {
+    auto panel = [&](double lo, double hi) {
+        const double c = 0.5 * (lo + hi), h = 0.5 * (hi - lo);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const double dx = h * kGL16x[k], w = h * kGL16w[k];
+            f(c - dx, w);
+            f(c + dx, w);
+        }
+    };
+    const double c = 0.5 * (a + b), h = 0.5 * (b - a);
+    if (hypot(c - pr, pim) >= 2.0 * h) {
+        panel(a, b);
+        return;
+    }
+    const double q = fmin(fmax(pr, a), b);
+    double w0 = fmax(pim, fabs(pr - q));
+    if (!(w0 > 0)) w0 = 1e-12 * (b - a);
+    // right of q
+    {
+        const double len = b - q;
+        double lo = 0.0, w = w0;
+        while (lo < len) {
+            const double hi = fmin(lo + w, len);
+            panel(q + lo, q + hi);
+            lo = hi;
+            w *= 2.0;
+        }
+    }
+    // left of q
+    {
+        const double len = q - a;
+        double lo = 0.0, w = w0;
+        while (lo < len) {
+            const double hi = fmin(lo + w, len);
+            panel(q - hi, q - lo);
+            lo = hi;
+            w *= 2.0;
+        }
+    }
+}
+
+struct TabGeo {
+    double beta, dphi, lnb;
+    int n_r, n_phi, L, n_tpz;
+};
+
+// All six kernels of offset (m, n_rep) into t[6]:
+// r0, rr, rphi, phi0, phir, phiphi (unscaled by beta^m).
+__device__ void table_entry(const TabGeo &g, int m, int nrep, const double *selfk, double *t) {
+    if (m == 0 && nrep == 0) {
+        t[0] = selfk[0];
+        t[1] = selfk[1];
+        t[2] = 0.0;
+        t[3] = 0.0;
+        t[4] = 0.0;
+        t[5] = selfk[2];
+        return;
+    }
+    const double rho = exp(-m * g.lnb);
+    const double el = 2.0 * rho / (1.0 + g.beta);
+    const double eu = g.beta * el;
+    const double xic = -nrep * g.dphi;
+    const double dth = g.dphi / g.n_tpz;
+
+    double r0 = 0, rr = 0, rph = 0, pp = 0;
+    for (int k = 0; k <= g.n_tpz; ++k) {
+        const double xi = xic - 0.5 * g.dphi + k * dth;
+        const double wk = (k == 0 || k == g.n_tpz) ? 0.5 * dth : dth;
+        double s, c;
+        sincos(xi, &s, &c);
+        const double sh = sin(0.5 * xi);
+        double Ir = 0, Ir2 = 0, Iph = 0;
+        auto f = [&](double eta, double w) {
+            const double F = Fpol(eta, sh);
+            const double iF3 = 1.0 / (F * F * F);
+            const double fr = eta * (1.0 - eta * c) * iF3;
+            Ir += w * fr;
+            Ir2 += w * eta * fr;
+            Iph += w * eta * eta * s * iF3;
+        };
+        graded_gl16(el, eu, c, fabs(s), f);
+        const double wl = wk * (xi - xic);
+        r0 += wk * Ir;
+        rr += wk * (Ir2 - rho * Ir);
+        rph += wl * Ir;
+        pp += wl * Iph;
+    }
+    t[0] = -r0;
+    t[1] = -rr;
+    t[2] = -rph;
+    t[5] = pp;
+
+    // exact K^{phi,0}, K^{phi,r}
+    const double sxc = sin(xic);
+    if (sxc == 0.0) {
+        t[3] = 0.0;
+        t[4] = 0.0;
+        return;
+    }
+    const double xl = xic - 0.5 * g.dphi, xu = xic + 0.5 * g.dphi;
+    const double shl = sin(0.5 * xl), shu = sin(0.5 * xu);
+    const double num = 4.0 * sxc * sin(0.5 * g.dphi);
+    double sl, cl, su, cu;
+    sincos(xl, &sl, &cl);
+    sincos(xu, &su, &cu);
+    // grade towards the nearer of the two unit-circle singularities
+    const double mid = 0.5 * (el + eu);
+    const bool lower = hypot(mid - cl, sl) <= hypot(mid - cu, su);
+    double a0 = 0, a1 = 0;
+    auto f2 = [&](double eta, double w) {
+        const double Fl = Fpol(eta, shl), Fu = Fpol(eta, shu);
+        const double D = num * eta / (Fl * Fu * (Fl + Fu));
+        a0 += w * eta * D;
+        a1 += w * eta * (eta - rho) * D;
+    };
+    graded_gl16(el, eu, lower ? cl : cu, lower ? fabs(sl) : fabs(su), f2);
+    t[3] = a0;
+    t[4] = a1;
+}
+
+// tables: [6][L][n_phi] FP64, row (m mod L).  One thread per (m, n_rep),
+// n_rep in [0, n_phi/2]; entries at -n_rep follow from the parity in xi.
+__global__ void k_tables(TabGeo g, const double *__restrict__ selfk, double *__restrict__ tab) {
+    const int nh = g.n_phi / 2 + 1;
+    const int rows = 2 * g.n_r - 1;
+    const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (long)rows * nh) return;
+    const int ir = (int)(idx / nh), nrep = (int)(idx % nh);
+    const int m = ir - (g.n_r - 1);
+    double t[6];
+    table_entry(g, m, nrep, selfk, t);
+    const int row = (m % g.L + g.L) % g.L;
+    const long plane = (long)g.L * g.n_phi;
+    const int cp = nrep, cn = (g.n_phi - nrep) % g.n_phi;
+    const double par[6] = {1, 1, -1, -1, -1, 1};
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        tab[k * plane + (long)row * g.n_phi + cp] = t[k];
+        if (cn != cp) tab[k * plane + (long)row * g.n_phi + cn] = par[k] * t[k];
+    }
+}
+
+__global__ void k_fill(double *__restrict__ p, long n, double v) {
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (long)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+// ---------------------------------------------------------------------------
+// Self cell: Cartesian cover.
+// ---------------------------------------------------------------------------
+struct CoverGeo {
+    double rin, rout, hx, hy, tanh_;
+    long kx0, nkx, ky1, nky;
+    long ncell;
+    int chunk;
+};
+
+__device__ __forceinline__ double ln_plus(double y, double x, double rho) {
+    // ln(y + sqrt(x^2 + y^2)); rationalised for y < 0
+    return y >= 0.0 ? log(y + rho) : log(x * x / (rho - y));
+}
+
+__device__ __forceinline__ void two_sum(double &s, double &c, double x) {
+    const double t = s + x;
+    if (fabs(s) >= fabs(x))
+        c += (s - t) + x;
+    else
+        c += (x - t) + s;
+    s = t;
+}
+
+// Contribution of one cover cell centred at (1 + X, Y) to the three sums.
+__device__ void cover_cell(const CoverGeo &g, double X, double Y, double out[3]) {
+    const double xc = 1.0 + X, yc = Y;
+    const double r2 = xc * xc + yc * yc;
+    out[0] = out[1] = out[2] = 0.0;
+    if (r2 < g.rin * g.rin || r2 > g.rout * g.rout) return;
+    if (fabs(yc) > xc * g.tanh_) return;
+    const double rc = sqrt(r2);
+    const double s2 = rc - 1.0, ax2 = xc / rc, ay2 = yc / rc;      // rbar - 1
+    const double s3 = atan2(yc, xc), ax3 = -yc / r2, ay3 = xc / r2; // phibar
+    const double hmax = fmax(g.hx, g.hy);
+    if (hypot(X, Y) <= 6.0 * hmax) {
+        // closed forms A8-A13, evaluated at the four corners
+        const double xs[2] = {X - 0.5 * g.hx, X + 0.5 * g.hx};
+        const double ys[2] = {Y - 0.5 * g.hy, Y + 0.5 * g.hy};
+        double ly = 0, lx = 0, ylx = 0, xly = 0, rr = 0;
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b) {
+                const double sg = (a == b) ? 1.0 : -1.0;
+                const double x = xs[a], y = ys[b];
+                const double rho = sqrt(x * x + y * y);
+                const double Ly = ln_plus(y, x, rho), Lx = ln_plus(x, y, rho);
+                ly += sg * Ly;
+                lx += sg * Lx;
+                ylx += sg * y * Lx;
+                xly += sg * x * Ly;
+                rr += sg * rho;
+            }
+        const double Kx0 = -ly, Ky0 = -lx;
+        const double Kxx = -X * Kx0 + ylx, Kxy = -Y * Kx0 - rr;
+        const double Kyy = -Y * Ky0 + xly, Kyx = -X * Ky0 - rr;
+        out[0] = Kx0;
+        out[1] = s2 * Kx0 + ax2 * Kxx + ay2 * Kxy;
+        out[2] = s3 * Ky0 + ay3 * Kyy + ax3 * Kyx;
+        return;
+    }
+    // 8 x 8 Gauss-Legendre of kernel x linear cell density (Eq. 8)
+    double a1 = 0, a2 = 0, a3 = 0;
+    for (int p = 0; p < 8; ++p) {
+        const double u = 0.5 * g.hx * (p < 4 ? -kGL8x[3 - p] : kGL8x[p - 4]);
+        const double wu = p < 4 ? kGL8w[3 - p] : kGL8w[p - 4];
+        const double xb = X + u;
+        double t1 = 0, t2 = 0, t3 = 0;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const double v = 0.5 * g.hy * (q < 4 ? -kGL8x[3 - q] : kGL8x[q - 4]);
+            const double wv = q < 4 ? kGL8w[3 - q] : kGL8w[q - 4];
+            const double yb = Y + v;
+            const double rho2 = xb * xb + yb * yb;
+            const double ir3 = 1.0 / (rho2 * sqrt(rho2));
+            t1 += wv * xb * ir3;
+            t2 += wv * xb * ir3 * (s2 + ax2 * u + ay2 * v);
+            t3 += wv * yb * ir3 * (s3 + ax3 * u + ay3 * v);
+        }
+        a1 += wu * t1;
+        a2 += wu * t2;
+        a3 += wu * t3;
+    }
+    const double jac = 0.25 * g.hx * g.hy;
+    out[0] = a1 * jac;
+    out[1] = a2 * jac;
+    out[2] = a3 * jac;
+}
+
+// partial[b*6 + 2q + {0,1}] = compensated (sum, carry) of quantity q.
+__global__ __launch_bounds__(256) void k_cover(CoverGeo g, double *__restrict__ partial) {
+    __shared__ double sh[6][256];
+    double s[3] = {0, 0, 0}, c[3] = {0, 0, 0};
+    const long tid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long c0 = tid * g.chunk;
+    for (int j = 0; j < g.chunk; ++j) {
+        const long cell = c0 + j;
+        if (cell >= g.ncell) break;
+        const long kx = g.kx0 + cell / g.nky;
+        const long ky = -g.ky1 + cell % g.nky;
+        double o[3];
+        cover_cell(g, kx * g.hx, ky * g.hy, o);
+#pragma unroll
+        for (int q = 0; q < 3; ++q) two_sum(s[q], c[q], o[q]);
+    }
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        sh[2 * q][threadIdx.x] = s[q];
+        sh[2 * q + 1][threadIdx.x] = c[q];
+    }
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                double ss = sh[2 * q][threadIdx.x], cc = sh[2 * q + 1][threadIdx.x];
+                two_sum(ss, cc, sh[2 * q][threadIdx.x + w]);
+                cc += sh[2 * q + 1][threadIdx.x + w];
+                sh[2 * q][threadIdx.x] = ss;
+                sh[2 * q + 1][threadIdx.x] = cc;
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < 6) partial[(long)blockIdx.x * 6 + threadIdx.x] = sh[threadIdx.x][0];
+}
+
+// One block folds the per-block partials into the three constants.
+__global__ __launch_bounds__(256) void k_cover_final(const double *__restrict__ partial,
+                                                     int nblk, double *__restrict__ selfk) {
+    __shared__ double sh[6][256];
+    double s[3] = {0, 0, 0}, c[3] = {0, 0, 0};
+    for (int b = threadIdx.x; b < nblk; b += 256) {
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            two_sum(s[q], c[q], partial[(long)b * 6 + 2 * q]);
+            c[q] += partial[(long)b * 6 + 2 * q + 1];
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        sh[2 * q][threadIdx.x] = s[q];
+        sh[2 * q + 1][threadIdx.x] = c[q];
+    }
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                double ss = sh[2 * q][threadIdx.x], cc = sh[2 * q + 1][threadIdx.x];
+                two_sum(ss, cc, sh[2 * q][threadIdx.x + w]);
+                cc += sh[2 * q + 1][threadIdx.x + w];
+                sh[2 * q][threadIdx.x] = ss;
+                sh[2 * q + 1][threadIdx.x] = cc;
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        selfk[0] = sh[0][0] + sh[1][0];   // K^{r,0}_{00}
+        selfk[1] = sh[2][0] + sh[3][0];   // K^{r,r}_{00} (r_m = 1, Eq. 46)
+        selfk[2] = sh[4][0] + sh[5][0];   // K^{phi,phi}_{00}
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Column transforms of the row-transformed tables and the fold into the four
+// spectra.  rowspec: [6][L][H] complex FP64.  spec: [4][H][ldspec].
+// One column per block, L/E threads.
+// ---------------------------------------------------------------------------
+template <int L, int E>
+__global__ __launch_bounds__(512) void k_fold(const cx<double> *__restrict__ rowspec, int H,
+                                              int n_r, int n_phi, double lnb, double dphi,
+                                              cx<double> *__restrict__ spec, int ldspec,
+                                              const cx<double> *__restrict__ twL) {
+    constexpr int TH = L / E;
+    extern __shared__ unsigned char smem_raw[];
+    cx<double> *buf = reinterpret_cast<cx<double> *>(smem_raw);
+    const int col = blockIdx.x, t = threadIdx.x;
+    Lds<double> lds{buf, 0, 1};
+    const double sc = 1.0 / ((double)L * (double)n_phi);
+    const double sk = sin(2.0 * M_PI * col / n_phi) / dphi;
+
+    auto load = [&](int tab, bool bscale, cx<double>(&v)[E]) {
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int row = t + e * TH;
+            cx<double> x = rowspec[((size_t)tab * L + row) * H + col];
+            if (bscale) {
+                const int m = row < n_r ? row : row - L;
+                const double f = exp(m * lnb);
+                x = scale(x, f);
+            }
+            v[e] = x;
+        }
+        fft_fwd<L, E, double>(v, t, lds, twL, 1);
+    };
+    auto store = [&](int which, const cx<double>(&v)[E]) {
+        cx<double> *dst = spec + ((size_t)which * H + col) * ldspec;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int ku = t + e * TH;
+            if (ku <= L / 2) dst[ku] = v[e];
+        }
+    };
+    cx<double> a[E], b[E];
+    // E_r
+    load(0, false, a);
+    load(2, false, b);
+#pragma unroll
+    for (int e = 0; e < E; ++e)
+        a[e] = cx<double>{(a[e].x - sk * b[e].y) * sc, (a[e].y + sk * b[e].x) * sc};
+    store(0, a);
+    // Q_r
+    load(1, true, a);
+#pragma unroll
+    for (int e = 0; e < E; ++e) a[e] = scale(a[e], sc);
+    store(1, a);
+    // E_p
+    load(3, false, a);
+    load(5, false, b);
+#pragma unroll
+    for (int e = 0; e < E; ++e)
+        a[e] = col == 0 ? cx<double>{0.0, 0.0}
+                        : cx<double>{(a[e].x - sk * b[e].y) * sc, (a[e].y + sk * b[e].x) * sc};
+    store(2, a);
+    // Q_p
+    load(4, true, a);
+#pragma unroll
+    for (int e = 0; e < E; ++e) a[e] = col == 0 ? cx<double>{0.0, 0.0} : scale(a[e], sc);
+    store(3, a);
+}
+
+__global__ void k_to_f32(const cx<double> *__restrict__ in, cx<float> *__restrict__ out, long n) {
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (long)gridDim.x * blockDim.x)
+        out[i] = cx<float>{(float)in[i].x, (float)in[i].y};
+}
+
+namespace {
+
+template <int L, int E>
+int fold_launch(const cx<double> *rowspec, const Plan &p, cx<double> *spec,
+                const cx<double> *twL, hipStream_t st) {
+    if constexpr (E <= L) {
+        const size_t lds = (size_t)L * sizeof(cx<double>);
+        if (lds > 64 * 1024)
+            PF_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(k_fold<L, E>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        hipLaunchKernelGGL((k_fold<L, E>), dim3(p.H), dim3(L / E), lds, st, rowspec, p.H, p.n_r,
+                           p.n_phi, std::log(p.beta), p.dphi, spec, p.ldspec, twL);
+        PF_HIP(hipGetLastError());
+        return PF_OK;
+    }
+    set_error("fold: bad size");
+    return PF_EUNSUPPORTED;
+}
+
+int fold_dispatch(const cx<double> *rowspec, const Plan &p, cx<double> *spec,
+                  const cx<double> *twL, hipStream_t st) {
+    switch (p.L) {
+        case 8: return fold_launch<8, 8>(rowspec, p, spec, twL, st);
+        case 16: return fold_launch<16, 8>(rowspec, p, spec, twL, st);
+        case 32: return fold_launch<32, 8>(rowspec, p, spec, twL, st);
+        case 64: return fold_launch<64, 8>(rowspec, p, spec, twL, st);
+        case 128: return fold_launch<128, 8>(rowspec, p, spec, twL, st);
+        case 256: return fold_launch<256, 8>(rowspec, p, spec, twL, st);
+        case 512: return fold_launch<512, 8>(rowspec, p, spec, twL, st);
+        case 1024: return fold_launch<1024, 8>(rowspec, p, spec, twL, st);
+        case 2048: return fold_launch<2048, 8>(rowspec, p, spec, twL, st);
+        case 4096: return fold_launch<4096, 16>(rowspec, p, spec, twL, st);
+        case 8192: return fold_launch<8192, 16>(rowspec, p, spec, twL, st);
+    }
+    set_error("fold: unsupported L=%d", p.L);
+    return PF_EUNSUPPORTED;
+}
+
+struct DevBuf {
+    void *p = nullptr;
+    ~DevBuf() {
+        if (p) (void)hipFree(p);
+    }
+};
+
+}  // namespace
+
+int build_tables_and_spectra(Plan &p, hipStream_t st) {
+    const bool f64 = p.opts.dtype == PF_F64;
+    const long plane = (long)p.L * p.n_phi;
+    DevBuf tab, rowspec, spec64, selfk, partial, twN64, twL64;
+
+    // --- self cell by the Cartesian cover ---------------------------------
+    CoverGeo cg{};
+    {
+        const double beta = p.beta, dphi = p.dphi;
+        const double dr = 2.0 * (beta - 1.0) / (1.0 + beta);
+        cg.rin = 1.0 - 0.5 * dr;
+        cg.rout = 1.0 + 0.5 * dr;
+        const double sq = std::sin(0.25 * dphi);
+        const double Dx = cg.rin * 2.0 * sq * sq;        // (r_m - dr/2)(1 - cos(dphi/2))
+        const double Dy = dr * std::sin(0.5 * dphi);     // dr sin(dphi/2)
+        cg.hx = Dx / p.opts.cover_per;
+        cg.hy = Dy / p.opts.cover_per;
+        const double ch = std::cos(0.5 * dphi), shf = std::sin(0.5 * dphi);
+        cg.tanh_ = shf / ch;
+        cg.kx0 = (long)std::ceil((cg.rin * ch - 1.0) / cg.hx);
+        const long kx1 = (long)std::floor((cg.rout - 1.0) / cg.hx);
+        cg.ky1 = (long)std::floor(cg.rout * shf / cg.hy);
+        cg.nkx = kx1 - cg.kx0 + 1;
+        cg.nky = 2 * cg.ky1 + 1;
+        cg.ncell = cg.nkx * cg.nky;
+        cg.chunk = 16;
+    }
+    const long nthreads = (cg.ncell + cg.chunk - 1) / cg.chunk;
+    const int nblk = (int)((nthreads + 255) / 256);
+    PF_HIP(hipMalloc(&selfk.p, 3 * sizeof(double)));
+    PF_HIP(hipMalloc(&partial.p, (size_t)nblk * 6 * sizeof(double)));
+    hipLaunchKernelGGL(k_cover, dim3(nblk), dim3(256), 0, st, cg, (double *)partial.p);
+    PF_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_cover_final, dim3(1), dim3(256), 0, st, (const double *)partial.p, nblk,
+                       (double *)selfk.p);
+    PF_HIP(hipGetLastError());
+
+    // --- kernel tables -------------------------------------------------------
+    PF_HIP(hipMalloc(&tab.p, 6 * plane * sizeof(double)));
+    hipLaunchKernelGGL(k_fill, dim3(1024), dim3(256), 0, st, (double *)tab.p, 6 * plane, 0.0);
+    PF_HIP(hipGetLastError());
+    TabGeo tg{p.beta, p.dphi, std::log(p.beta), p.n_r, p.n_phi, p.L, p.opts.n_tpz};
+    {
+        const long n = (long)(2 * p.n_r - 1) * (p.n_phi / 2 + 1);
+        hipLaunchKernelGGL(k_tables, dim3((unsigned)((n + 127) / 128)), dim3(128), 0, st, tg,
+                           (const double *)selfk.p, (double *)tab.p);
+        PF_HIP(hipGetLastError());
+    }
+
+    // --- spectra ---------------------------------------------------------------
+    int rc = upload_twiddles(p.n_phi, true, &twN64.p);
+    if (rc) return rc;
+    rc = upload_twiddles(p.L, true, &twL64.p);
+    if (rc) return rc;
+    PF_HIP(hipMalloc(&rowspec.p, (size_t)6 * p.L * p.H * sizeof(cx<double>)));
+    {
+        Shape s = default_schedule(p.n_phi, p.L, true).rows;
+        rc = launch_rows_r2c<double>(p, (const double *)tab.p, nullptr, 1, 6 * p.L,
+                                     (cx<double> *)rowspec.p, nullptr,
+                                     (const cx<double> *)twN64.p, s, st);
+        if (rc) return rc;
+    }
+    const size_t nspec = (size_t)4 * p.H * p.ldspec;
+    PF_HIP(hipMalloc(&spec64.p, nspec * sizeof(cx<double>)));
+    rc = fold_dispatch((const cx<double> *)rowspec.p, p, (cx<double> *)spec64.p,
+                       (const cx<double> *)twL64.p, st);
+    if (rc) return rc;
+
+    void *spec_final = nullptr;
+    if (f64) {
+        spec_final = spec64.p;
+        spec64.p = nullptr;
+    } else {
+        PF_HIP(hipMalloc(&spec_final, nspec * sizeof(cx<float>)));
+        hipLaunchKernelGGL(k_to_f32, dim3(1024), dim3(256), 0, st, (const cx<double> *)spec64.p,
+                           (cx<float> *)spec_final, (long)nspec);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) {
+            (void)hipFree(spec_final);
+            set_error("k_to_f32: %s", hipGetErrorString(e));
+            return PF_EHIP;
+        }
+    }
+    double hk[3];
+    hipError_t e = hipMemcpyAsync(hk, selfk.p, sizeof(hk), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+        (void)hipFree(spec_final);
+        set_error("table build: %s", hipGetErrorString(e));
+        return PF_EHIP;
+    }
+    if (p.spec) (void)hipFree(p.spec);
+    p.spec = spec_final;
+    for (int q = 0; q < 3; ++q) p.selfk[q] = hk[q];
+    if (p.tables) {
+        (void)hipFree(p.tables);
+        p.tables = nullptr;
+    }
+    if (p.opts.keep_tables) {
+        p.tables = (double *)tab.p;
+        tab.p = nullptr;
+    }
+    return PF_OK;
+}
+
+}  // namespace pf

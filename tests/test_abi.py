@@ -1,0 +1,85 @@
+"""The C-ABI library: loads, exports every symbol include/pf.h declares, and
+validates arguments on the host (no compute calls; no GPU needed)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1509_01450_amd as pf
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "pf.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(pf_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for n in ("pf_plan_create", "pf_kernels_build", "pf_forces", "pf_forces_backward",
+              "pf_forces_batched", "pf_plan_destroy", "pf_last_error"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(pf.LIB_PATH)
+    for n in _declared():
+        assert hasattr(lib, n), n
+    assert set(_declared()) == set(pf.EXPORTS)
+
+
+@pytest.mark.parametrize("args", [(3, 64, 0.1, 10.0), (5000, 64, 0.1, 10.0), (16, 48, 0.1, 10.0),
+                                  (16, 4, 0.1, 10.0), (16, 16384, 0.1, 10.0),
+                                  (16, 64, 0.0, 10.0), (16, 64, 1.0, 1.0),
+                                  (16, 64, float("nan"), 10.0), (16, 64, 0.1, float("inf"))])
+def test_plan_create_rejects_bad_grids(args):
+    with pytest.raises(pf.PFError) as ei:
+        pf.pf_plan_create(*args)
+    assert ei.value.code == pf.PF_EINVAL
+    assert pf.pf_last_error()
+
+
+def test_plan_geometry_matches_grid_definition():
+    h = pf.pf_plan_create(40, 64, 0.01, 100.0)
+    try:
+        rc, re_, dphi = pf.pf_plan_geometry(h, 40)
+    finally:
+        pf.pf_plan_destroy(h)
+    g = oracle.Grid(40, 64, 0.01, 100.0)
+    np.testing.assert_allclose(rc, g.r_centres, rtol=1e-14)
+    np.testing.assert_allclose(re_, g.r_edges, rtol=1e-14)
+    assert abs(dphi - g.dphi) < 1e-16
+
+
+def test_unbuilt_plan_and_null_arguments_are_refused():
+    lib = pf.load()
+    h = pf.pf_plan_create(16, 32, 0.1, 10.0)
+    try:
+        # not built: refused before any device work
+        assert lib.pf_forces(h, 8, 8, 8, None) == pf.PF_ESTATE
+        assert lib.pf_forces_backward(h, 8, 8, 8, None) == pf.PF_ESTATE
+        assert lib.pf_plan_selfcell(h, None) == pf.PF_EINVAL
+        # null pointers
+        assert lib.pf_forces(h, None, 8, 8, None) == pf.PF_EINVAL
+        assert lib.pf_forces(None, 8, 8, 8, None) == pf.PF_EINVAL
+        assert lib.pf_forces_batched(0, None, None, None, None, None) == pf.PF_EINVAL
+        # bad build options are refused before the device is touched
+        o = pf.pf_build_opts_default()
+        o.n_tpz = 0
+        assert lib.pf_kernels_build(h, ctypes.byref(o), None) == pf.PF_EINVAL
+        o = pf.pf_build_opts_default()
+        o.dtype = 7
+        assert lib.pf_kernels_build(h, ctypes.byref(o), None) == pf.PF_EINVAL
+    finally:
+        pf.pf_plan_destroy(h)
+    pf.pf_plan_destroy(None)
+
+
+def test_default_options():
+    o = pf.pf_build_opts_default()
+    assert (o.dtype, o.n_tpz, o.cover_per, o.keep_tables) == (pf.PF_F32, 19, 10, 0)
