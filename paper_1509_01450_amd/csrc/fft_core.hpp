@@ -137,14 +137,22 @@ template <>
 __device__ __forceinline__ void dft<16, double>(cx<double> *u) { dft16_impl(u); }
 
 // ---------------------------------------------------------------------------
-// LDS accessors.  Element i of the FFT group lives at base + i * stride.
+// LDS accessors.  Element i of the FFT group lives at
+// base + (i + i/16) * stride: one pad slot every 16 elements spreads the
+// stride-R stores of the early Stockham stages over the banks (modelled
+// conflict-free for 32 banks and at most 2-way for 64, for E = 8 and 16,
+// both with one transform per region and with G interleaved columns).
+// An N-point transform therefore needs padded_len(N) slots.
 // ---------------------------------------------------------------------------
+__host__ __device__ constexpr int padded_len(int n) { return n + (n >> 4); }
+
 template <typename T>
 struct Lds {
     cx<T> *p;
     int base, stride;
-    __device__ __forceinline__ cx<T> ld(int i) const { return p[base + i * stride]; }
-    __device__ __forceinline__ void st(int i, cx<T> v) const { p[base + i * stride] = v; }
+    __device__ __forceinline__ int at(int i) const { return base + (i + (i >> 4)) * stride; }
+    __device__ __forceinline__ cx<T> ld(int i) const { return p[at(i)]; }
+    __device__ __forceinline__ void st(int i, cx<T> v) const { p[at(i)] = v; }
 };
 
 // ---------------------------------------------------------------------------

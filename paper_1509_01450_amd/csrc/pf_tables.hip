@@ -467,7 +467,7 @@ template <int L, int E>
 int fold_launch(const cx<double> *rowspec, const Plan &p, cx<double> *spec,
                 const cx<double> *twL, hipStream_t st) {
     if constexpr (E <= L) {
-        const size_t lds = (size_t)L * sizeof(cx<double>);
+        const size_t lds = (size_t)padded_len(L) * sizeof(cx<double>);
         if (lds > 64 * 1024)
             PF_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(k_fold<L, E>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));

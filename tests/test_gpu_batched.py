@@ -1,0 +1,141 @@
+"""GPU batched path (one persistent launch from a cached HIP graph) against
+the single-disk path and the FP64 oracle."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+import paper_1509_01450_amd as pf  # noqa: E402
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    pf.load()
+
+
+def _disks(sizes, r_min=0.01, r_max=100.0):
+    plans, sig = [], []
+    for d, (nr, nphi) in enumerate(sizes):
+        p = pf.Plan(nr, nphi, r_min, r_max, dtype="f32")
+        rc, _, _ = p.geometry()
+        ph = (np.arange(nphi) + 0.5) * (2 * np.pi / nphi)
+        plans.append(p)
+        sig.append(torch.tensor(workloads.multiarm_disk(rc, ph, d), dtype=torch.float32,
+                                device="cuda"))
+    return plans, sig
+
+
+def _rel(a, b):
+    return float(torch.linalg.norm((a - b).double()) / torch.linalg.norm(b.double()))
+
+
+def _check_against_single(plans, sig, outs, tol=1e-6):
+    worst = 0.0
+    for p, s, (fr, fp) in zip(plans, sig, outs):
+        r, q = p.forces(s)
+        worst = max(worst, _rel(fr, r), _rel(fp, q))
+    torch.cuda.synchronize()
+    return worst
+
+
+def test_two_small_disks():
+    plans, sig = _disks([(64, 128), (40, 256)])
+    _say("two small disks: batched call")
+    outs = pf.forces_batched(plans, sig)
+    torch.cuda.synchronize()
+    worst = _check_against_single(plans, sig, outs)
+    _say("two small disks vs single-disk worst rel-L2 %.3e" % worst)
+    assert worst <= 1e-6
+
+
+def test_uneven_batch_matches_single_disk_and_oracle():
+    sizes = [(64, 128), (100, 256), (37, 512), (256, 128), (128, 1024), (200, 4096), (1024, 256)]
+    plans, sig = _disks(sizes)
+    _say("plans built; batched call")
+    outs = pf.forces_batched(plans, sig)
+    torch.cuda.synchronize()
+    worst = _check_against_single(plans, sig, outs)
+    _say("uneven batch vs single-disk worst rel-L2 %.3e" % worst)
+    assert worst <= 1e-6
+    # oracle on two disks, every cell
+    for k in (0, 2):
+        nr, nphi = sizes[k]
+        g = oracle.Grid(nr, nphi, 0.01, 100.0)
+        T = oracle.tables(g, 19)
+        fr_o, fp_o = oracle.forward(g, T, sig[k].double().cpu().numpy())
+        fr = outs[k][0].double().cpu().numpy()
+        fp = outs[k][1].double().cpu().numpy()
+        er = np.linalg.norm(fr - fr_o) / np.linalg.norm(fr_o)
+        ep = np.linalg.norm(fp - fp_o) / np.linalg.norm(fp_o)
+        _say("disk %d %s vs oracle rel-L2 F_r %.3e F_phi %.3e" % (k, sizes[k], er, ep))
+        assert er <= 1e-5 and ep <= 1e-5
+
+
+def test_replays_with_new_buffers():
+    sizes = [(64, 256), (48, 128), (300, 512)]
+    plans, sig = _disks(sizes)
+    first = pf.forces_batched(plans, sig)
+    # power-of-two scalings are exact in floating point, so every replay with
+    # fresh input and output buffers must reproduce the scaled first result
+    for f in (1.0, 2.0, 4.0):
+        sig2 = [s * f for s in sig]
+        outs = pf.forces_batched(plans, sig2)
+        torch.cuda.synchronize()
+        for (a, b), (c, d) in zip(outs, first):
+            assert _rel(a, c * f) < 1e-6 and _rel(b, d * f) < 1e-6
+
+
+def test_sixty_four_disk_batch():
+    sizes = workloads.batch_sizes(64)
+    plans, sig = _disks(sizes)
+    outs = pf.forces_batched(plans, sig)
+    torch.cuda.synchronize()
+    worst = _check_against_single(plans, sig, outs)
+    _say("64-disk batch (%d cells) vs single-disk worst rel-L2 %.3e"
+         % (sum(a * b for a, b in sizes), worst))
+    assert worst <= 1e-6
+    # sampled oracle cells on one full-size disk of the batch
+    k = int(np.argmax([a * b for a, b in sizes]))
+    nr, nphi = sizes[k]
+    g = oracle.Grid(nr, nphi, 0.01, 100.0)
+    T = oracle.tables(g, 19)
+    idx = np.random.default_rng(9).choice(nr * nphi, 512, replace=False)
+    fr_o, fp_o = oracle.forward(g, T, sig[k].double().cpu().numpy(), idx)
+    fr = outs[k][0].double().cpu().numpy().reshape(-1)[idx]
+    fp = outs[k][1].double().cpu().numpy().reshape(-1)[idx]
+    er = np.linalg.norm(fr - fr_o) / np.linalg.norm(fr_o)
+    ep = np.linalg.norm(fp - fp_o) / np.linalg.norm(fp_o)
+    _say("disk %d %s sampled vs oracle rel-L2 F_r %.3e F_phi %.3e" % (k, sizes[k], er, ep))
+    assert er <= 1e-5 and ep <= 1e-5
+
+
+def test_batch_argument_errors():
+    p1 = pf.Plan(64, 128, 0.1, 10.0, dtype="f32")
+    p2 = pf.Plan(64, 128, 0.1, 10.0, dtype="f64")
+    s1 = torch.zeros(64, 128, device="cuda")
+    s2 = torch.zeros(64, 128, dtype=torch.float64, device="cuda")
+    lib = pf.load()
+    with pytest.raises(pf.PFError) as ei:
+        pf.pf_forces_batched([p1.handle, p2.handle], [s1.data_ptr(), s2.data_ptr()],
+                             [s1.data_ptr(), s2.data_ptr()], [s1.data_ptr(), s2.data_ptr()])
+    assert ei.value.code == pf.PF_EINVAL
+    with pytest.raises(pf.PFError) as ei:
+        pf.forces_batched([p1, p1], [s1, s1])
+    assert ei.value.code == pf.PF_EINVAL
+    p3 = pf.Plan(8, 64, 0.1, 10.0, dtype="f32")  # below the batched size range
+    with pytest.raises(pf.PFError) as ei:
+        pf.forces_batched([p3], [torch.zeros(8, 64, device="cuda")])
+    assert ei.value.code == pf.PF_EUNSUPPORTED
