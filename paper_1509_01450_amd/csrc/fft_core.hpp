@@ -8,14 +8,16 @@
 // LDS buffer.  The output comes back in the same strided natural order, so
 // a pointwise multiply and the inverse transform can follow in registers
 // with no extra exchange.  Twiddles come from a table w[j] = exp(-2 pi i j/N)
-// built on the host in extended precision.
+// built on the host in extended precision, held per thread in registers.
 #pragma once
 #include <hip/hip_runtime.h>
 
 namespace pf {
 
+// complex value, aligned to its full size so that loads, stores and LDS
+// accesses are single 64-bit (float) or 128-bit (double) operations
 template <typename T>
-struct cx {
+struct alignas(2 * sizeof(T)) cx {
     T x, y;
 };
 
@@ -138,33 +140,112 @@ __device__ __forceinline__ void dft<16, double>(cx<double> *u) { dft16_impl(u); 
 
 // ---------------------------------------------------------------------------
 // LDS accessors.  Element i of the FFT group lives at
-// base + (i + i/16) * stride: one pad slot every 16 elements spreads the
-// stride-R stores of the early Stockham stages over the banks (modelled
-// conflict-free for 32 banks and at most 2-way for 64, for E = 8 and 16,
-// both with one transform per region and with G interleaved columns).
-// An N-point transform therefore needs padded_len(N) slots.
+// base + swz(i) * stride with swz(i) = i ^ ((i >> 4) & 15): the XOR of the
+// low four index bits with the next four spreads the stride-R stores of the
+// early Stockham stages over the banks (modelled at most 1.33-way for 64
+// banks of 4 bytes and conflict-free for 32, for 8- and 16-byte elements,
+// E = 8 and 16, one transform per region or G interleaved columns).  It is
+// a permutation of every aligned block of 256 indices, so an N-point
+// transform needs exactly N slots.
 // ---------------------------------------------------------------------------
-__host__ __device__ constexpr int padded_len(int n) { return n + (n >> 4); }
+__host__ __device__ constexpr int padded_len(int n) { return n; }
 
 template <typename T>
 struct Lds {
     cx<T> *p;
     int base, stride;
-    __device__ __forceinline__ int at(int i) const { return base + (i + (i >> 4)) * stride; }
+    __device__ __forceinline__ int at(int i) const { return base + (i ^ ((i >> 4) & 15)) * stride; }
     __device__ __forceinline__ cx<T> ld(int i) const { return p[at(i)]; }
     __device__ __forceinline__ void st(int i, cx<T> v) const { p[at(i)] = v; }
 };
 
 // ---------------------------------------------------------------------------
+// Twiddles.  A thread's twiddles depend only on its index t and the stage,
+// so they are loaded once from the table into registers (Twiddles::load)
+// and reused by every transform the thread runs: no stage waits on a
+// global load.  For a stage of radix R and span NS > 1 the thread's
+// butterfly q (index b = t + q*TH, k = b mod NS) needs
+// w^r = w_{NS R}^{k r} = table[k r N / (NS R)], r = 1..R-1.  Only the
+// powers w^1, w^2, w^4, w^8 (log2 R of them) are held; the others are
+// formed with at most two complex products (a few ulp), which halves the
+// registers the twiddles take.
+// ---------------------------------------------------------------------------
+__host__ __device__ constexpr int ilog2c(int v) { return v <= 1 ? 0 : 1 + ilog2c(v >> 1); }
+
+template <int N, int E>
+__host__ __device__ constexpr int tw_count() {
+    int c = 0, ns = 1;
+    while (true) {
+        const int rem = N / ns;
+        const int R = rem >= E ? E : rem;
+        const int NB = E / R;
+        if (ns > 1) c += NB * ilog2c(R);
+        if (ns * R == N) break;
+        ns *= R;
+    }
+    return c;
+}
+
+template <int N, int E, typename T>
+struct Twiddles {
+    static constexpr int COUNT = tw_count<N, E>();
+    cx<T> w[COUNT > 0 ? COUNT : 1];
+
+    template <int NS, int OFF>
+    __device__ __forceinline__ void load_stage(int t, const cx<T> *__restrict__ tab, int ts) {
+        constexpr int TH = N / E;
+        constexpr int REM = N / NS;
+        constexpr int R = REM >= E ? E : REM;
+        constexpr int NB = E / R;
+        constexpr int LR = ilog2c(R);
+        constexpr bool LAST = (NS * R == N);
+        if constexpr (NS > 1) {
+            constexpr int STEP = N / (NS * R);
+#pragma unroll
+            for (int q = 0; q < NB; ++q) {
+                const int k = (t + q * TH) & (NS - 1);
+#pragma unroll
+                for (int j = 0; j < LR; ++j) w[OFF + q * LR + j] = tab[(k * (1 << j) * STEP) * ts];
+            }
+        }
+        if constexpr (!LAST) load_stage<NS * R, OFF + (NS > 1 ? NB * LR : 0)>(t, tab, ts);
+    }
+    // tab: table exp(-2 pi i j / (N ts)), read with stride ts
+    __device__ __forceinline__ void load(int t, const cx<T> *__restrict__ tab, int ts) {
+        load_stage<1, 0>(t, tab, ts);
+    }
+};
+
+// The R-1 twiddles w^1..w^{R-1} of one butterfly from the stored powers
+// p[j] = w^(2^j).
+template <int R, typename T>
+__device__ __forceinline__ void tw_expand(const cx<T> *p, cx<T> *o) {
+    o[1] = p[0];
+    if constexpr (R > 2) {
+        o[2] = p[1];
+        o[3] = cmul(p[0], p[1]);
+    }
+    if constexpr (R > 4) {
+        o[4] = p[2];
+#pragma unroll
+        for (int r = 5; r < 8; ++r) o[r] = cmul(o[r - 4], p[2]);
+    }
+    if constexpr (R > 8) {
+        o[8] = p[3];
+#pragma unroll
+        for (int r = 9; r < 16; ++r) o[r] = cmul(o[r - 8], p[3]);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Stockham stages.  Template parameters: N (length), E (points per thread),
-// NS (span of the stage).  tw: table exp(-2 pi i j / (N * TS)) read with
-// stride TS, i.e. the N-point table is tw[j * TS].
+// NS (span of the stage), OFF (offset of the stage's twiddles).
 // All threads of the workgroup must call this together (it contains
 // __syncthreads()).
 // ---------------------------------------------------------------------------
-template <int N, int E, int NS, typename T>
+template <int N, int E, int NS, int OFF, typename T>
 __device__ __forceinline__ void fft_stages(cx<T> (&v)[E], int t, const Lds<T> &lds,
-                                           const cx<T> *__restrict__ tw, int ts) {
+                                           const Twiddles<N, E, T> &tw) {
     constexpr int TH = N / E;                 // threads per transform
     constexpr int REM = N / NS;
     constexpr int R = REM >= E ? E : REM;     // radix of this stage
@@ -178,13 +259,14 @@ __device__ __forceinline__ void fft_stages(cx<T> (&v)[E], int t, const Lds<T> &l
         cx<T> u[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) u[r] = v[q + r * NB];
-        if (NS > 1) {
-            constexpr int STEP = N / (NS * R);
+        if constexpr (NS > 1) {
+            cx<T> wr[R];
+            tw_expand<R, T>(&tw.w[OFF + q * ilog2c(R)], wr);
 #pragma unroll
-            for (int r = 1; r < R; ++r) u[r] = cmul(u[r], tw[(k * r * STEP) * ts]);
+            for (int r = 1; r < R; ++r) u[r] = cmul(u[r], wr[r]);
         }
         dft<R, T>(u);
-        if (LAST) {
+        if constexpr (LAST) {
 #pragma unroll
             for (int r = 0; r < R; ++r) v[q + r * NB] = u[r];
         } else {
@@ -198,25 +280,25 @@ __device__ __forceinline__ void fft_stages(cx<T> (&v)[E], int t, const Lds<T> &l
 #pragma unroll
         for (int e = 0; e < E; ++e) v[e] = lds.ld(t + e * TH);
         __syncthreads();
-        fft_stages<N, E, NS * R, T>(v, t, lds, tw, ts);
+        fft_stages<N, E, NS * R, OFF + (NS > 1 ? NB * ilog2c(R) : 0), T>(v, t, lds, tw);
     }
 }
 
 // Forward transform (sign -1) in strided order.
 template <int N, int E, typename T>
 __device__ __forceinline__ void fft_fwd(cx<T> (&v)[E], int t, const Lds<T> &lds,
-                                        const cx<T> *__restrict__ tw, int ts) {
+                                        const Twiddles<N, E, T> &tw) {
     static_assert((N & (N - 1)) == 0 && N >= E && E >= 2, "sizes");
-    fft_stages<N, E, 1, T>(v, t, lds, tw, ts);
+    fft_stages<N, E, 1, 0, T>(v, t, lds, tw);
 }
 
 // Inverse transform (sign +1, unnormalised) as conj(F(conj(x))).
 template <int N, int E, typename T>
 __device__ __forceinline__ void fft_inv(cx<T> (&v)[E], int t, const Lds<T> &lds,
-                                        const cx<T> *__restrict__ tw, int ts) {
+                                        const Twiddles<N, E, T> &tw) {
 #pragma unroll
     for (int e = 0; e < E; ++e) v[e].y = -v[e].y;
-    fft_stages<N, E, 1, T>(v, t, lds, tw, ts);
+    fft_stages<N, E, 1, 0, T>(v, t, lds, tw);
 #pragma unroll
     for (int e = 0; e < E; ++e) v[e].y = -v[e].y;
 }

@@ -43,16 +43,22 @@ __device__ __forceinline__ void body_rows_r2c(int unit, int G, cx<T> *__restrict
     const int row = unit * G + gi;
     const bool active = row < total_rows;
     const int arr = active ? row / n_rows : 0;
-    const int i = active ? row % n_rows : 0;
+    const int i = active ? row % n_rows : 0;   // inactive lanes read row 0
     const T *x = (arr == 0 ? in0 : in1) + (size_t)i * N;
     cx<T> *out = (arr == 0 ? out0 : out1) + (size_t)i * H;
     Lds<T> lds{buf, gi * padded_len(M), 1};
 
+    // unconditional loads (in bounds for every lane) so they issue together
     cx<T> v[E];
     const cx<T> *xz = reinterpret_cast<const cx<T> *>(x);
 #pragma unroll
-    for (int e = 0; e < E; ++e) v[e] = active ? xz[t + e * TH] : cx<T>{T(0), T(0)};
-    fft_fwd<M, E, T>(v, t, lds, twN, 2);
+    for (int e = 0; e < E; ++e) v[e] = xz[t + e * TH];
+    Twiddles<M, E, T> tw;
+    tw.load(t, twN, 2);
+#pragma unroll
+    for (int e = 0; e < E; ++e)
+        if (!active) v[e] = cx<T>{T(0), T(0)};
+    fft_fwd<M, E, T>(v, t, lds, tw);
 #pragma unroll
     for (int e = 0; e < E; ++e) lds.st(t + e * TH, v[e]);
     __syncthreads();
@@ -91,27 +97,31 @@ __device__ __forceinline__ void body_rows_c2r(int unit, int G, cx<T> *__restrict
     const int row = unit * G + gi;
     const bool active = row < total_rows;
     const int arr = active ? row / n_rows : 0;
-    const int i = active ? row % n_rows : 0;
+    const int i = active ? row % n_rows : 0;   // inactive lanes read row 0
     const cx<T> *X = (arr == 0 ? in0 : in1) + (size_t)i * H;
     T *y = (arr == 0 ? out0 : out1) + (size_t)i * N;
     Lds<T> lds{buf, gi * padded_len(M), 1};
 
-    cx<T> v[E];
+    // unconditional loads (in bounds for every lane) so they issue together
+    cx<T> xk[E], xm[E], wk[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         const int k = t + e * TH;
-        if (active) {
-            cx<T> xk = X[k], xm = X[M - k];
-            cx<T> s = {xk.x + xm.x, xk.y - xm.y};   // X[k] + conj X[M-k]
-            cx<T> d = {xk.x - xm.x, xk.y + xm.y};   // X[k] - conj X[M-k]
-            cx<T> w = twN[k];                        // exp(-2 pi i k / N)
-            cx<T> dw = cmulc(d, w);                  // d * exp(+2 pi i k / N)
-            v[e] = cx<T>{s.x - dw.y, s.y + dw.x};    // s + i dw
-        } else {
-            v[e] = cx<T>{T(0), T(0)};
-        }
+        xk[e] = X[k];
+        xm[e] = X[M - k];
+        wk[e] = twN[k];                          // exp(-2 pi i k / N)
     }
-    fft_inv<M, E, T>(v, t, lds, twN, 2);
+    Twiddles<M, E, T> tw;
+    tw.load(t, twN, 2);
+    cx<T> v[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        cx<T> s = {xk[e].x + xm[e].x, xk[e].y - xm[e].y};   // X[k] + conj X[M-k]
+        cx<T> d = {xk[e].x - xm[e].x, xk[e].y + xm[e].y};   // X[k] - conj X[M-k]
+        cx<T> dw = cmulc(d, wk[e]);                           // d * exp(+2 pi i k / N)
+        v[e] = active ? cx<T>{s.x - dw.y, s.y + dw.x} : cx<T>{T(0), T(0)};   // s + i dw
+    }
+    fft_inv<M, E, T>(v, t, lds, tw);
     if (active) {
         cx<T> *yz = reinterpret_cast<cx<T> *>(y);
 #pragma unroll
@@ -126,8 +136,9 @@ __device__ __forceinline__ void body_rows_c2r(int unit, int G, cx<T> *__restrict
 template <typename T, int L>
 __device__ __forceinline__ cx<T> spec_at(const cx<T> *__restrict__ col, int ku, bool odd) {
     constexpr int HL = L / 2;
-    if (ku <= HL) return col[ku];
-    cx<T> s = col[L - ku];
+    const bool lo = ku <= HL;
+    const cx<T> s = col[lo ? ku : L - ku];   // one load, no branch
+    if (lo) return s;
     return odd ? cx<T>{-s.x, s.y} : cx<T>{s.x, -s.y};
 }
 
@@ -150,11 +161,24 @@ __device__ __forceinline__ void body_cols_fwd(int unit, int G, cx<T> *__restrict
     const bool valid = col < H;
     Lds<T> lds{buf, gi, G};
 
-    // stage the column in LDS to form the radial slope channel
+    Twiddles<L, E, T> tw;
+    tw.load(t, twL, 1);
+    // stage the column in LDS to form the radial slope channel.  Only the
+    // first E/2 points of a thread can be data rows (L >= 2 n_r); the loads
+    // use clamped, always valid addresses so they issue back to back.
+    {
+        const int cl = valid ? col : 0;
+        cx<T> g[E / 2];
 #pragma unroll
-    for (int e = 0; e < E; ++e) {
-        const int i = t + e * TH;
-        if (i < n_r) lds.st(i, valid ? S[(size_t)i * H + col] : cx<T>{T(0), T(0)});
+        for (int e = 0; e < E / 2; ++e) {
+            const int i = t + e * TH;
+            g[e] = S[(size_t)(i < n_r ? i : n_r - 1) * H + cl];
+        }
+#pragma unroll
+        for (int e = 0; e < E / 2; ++e) {
+            const int i = t + e * TH;
+            if (i < n_r) lds.st(i, valid ? g[e] : cx<T>{T(0), T(0)});
+        }
     }
     __syncthreads();
     cx<T> vc[E], vg[E];
@@ -175,24 +199,31 @@ __device__ __forceinline__ void body_cols_fwd(int unit, int G, cx<T> *__restrict
         vg[e] = g;
     }
     __syncthreads();
-    fft_fwd<L, E, T>(vc, t, lds, twL, 1);
-    fft_fwd<L, E, T>(vg, t, lds, twL, 1);
+    fft_fwd<L, E, T>(vc, t, lds, tw);
+    fft_fwd<L, E, T>(vg, t, lds, tw);
     const int cs = valid ? col : 0;
     const cx<T> *er = spec + (size_t)(0 * H + cs) * ldspec;
     const cx<T> *qr = spec + (size_t)(1 * H + cs) * ldspec;
     const cx<T> *ep = spec + (size_t)(2 * H + cs) * ldspec;
     const cx<T> *qp = spec + (size_t)(3 * H + cs) * ldspec;
+    // all spectrum loads of the unit in one batch (one memory round trip)
+    cx<T> sa[E], sb[E], sc[E], sd[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         const int ku = t + e * TH;
-        cx<T> a = spec_at<T, L>(er, ku, false), b = spec_at<T, L>(qr, ku, false);
-        cx<T> c = spec_at<T, L>(ep, ku, true), d = spec_at<T, L>(qp, ku, true);
-        cx<T> x = vc[e], y = vg[e];
-        vc[e] = cmul(a, x) + cmul(b, y);
-        vg[e] = cmul(c, x) + cmul(d, y);
+        sa[e] = spec_at<T, L>(er, ku, false);
+        sb[e] = spec_at<T, L>(qr, ku, false);
+        sc[e] = spec_at<T, L>(ep, ku, true);
+        sd[e] = spec_at<T, L>(qp, ku, true);
     }
-    fft_inv<L, E, T>(vc, t, lds, twL, 1);
-    fft_inv<L, E, T>(vg, t, lds, twL, 1);
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        cx<T> x = vc[e], y = vg[e];
+        vc[e] = cmul(sa[e], x) + cmul(sb[e], y);
+        vg[e] = cmul(sc[e], x) + cmul(sd[e], y);
+    }
+    fft_inv<L, E, T>(vc, t, lds, tw);
+    fft_inv<L, E, T>(vg, t, lds, tw);
     if (valid) {
 #pragma unroll
         for (int e = 0; e < E; ++e) {
@@ -224,32 +255,55 @@ __device__ __forceinline__ void body_cols_adj(int unit, int G, cx<T> *__restrict
     const bool valid = col < H;
     Lds<T> lds{buf, gi, G};
 
+    Twiddles<L, E, T> tw;
+    tw.load(t, twL, 1);
+    // clamped, always valid addresses so the loads issue back to back; only
+    // the first E/2 points of a thread can be data rows (L >= 2 n_r)
     cx<T> va[E], vb[E];
+    {
+        const int cl = valid ? col : 0;
 #pragma unroll
-    for (int e = 0; e < E; ++e) {
-        const int i = t + e * TH;
-        const bool in = valid && i < n_r;
-        va[e] = in ? Vr[(size_t)i * H + col] : cx<T>{T(0), T(0)};
-        vb[e] = in ? Vp[(size_t)i * H + col] : cx<T>{T(0), T(0)};
+        for (int e = 0; e < E / 2; ++e) {
+            const int i = t + e * TH;
+            const size_t o = (size_t)(i < n_r ? i : n_r - 1) * H + cl;
+            va[e] = Vr[o];
+            vb[e] = Vp[o];
+        }
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int i = t + e * TH;
+            const bool in = valid && i < n_r && e < E / 2;
+            if (!in) {
+                va[e] = cx<T>{T(0), T(0)};
+                vb[e] = cx<T>{T(0), T(0)};
+            }
+        }
     }
-    fft_fwd<L, E, T>(va, t, lds, twL, 1);
-    fft_fwd<L, E, T>(vb, t, lds, twL, 1);
+    fft_fwd<L, E, T>(va, t, lds, tw);
+    fft_fwd<L, E, T>(vb, t, lds, tw);
     const int cs = valid ? col : 0;
     const cx<T> *er = spec + (size_t)(0 * H + cs) * ldspec;
     const cx<T> *qr = spec + (size_t)(1 * H + cs) * ldspec;
     const cx<T> *ep = spec + (size_t)(2 * H + cs) * ldspec;
     const cx<T> *qp = spec + (size_t)(3 * H + cs) * ldspec;
+    // all spectrum loads of the unit in one batch (one memory round trip)
+    cx<T> sa[E], sb[E], sc[E], sd[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         const int ku = t + e * TH;
-        cx<T> a = spec_at<T, L>(er, ku, false), b = spec_at<T, L>(qr, ku, false);
-        cx<T> c = spec_at<T, L>(ep, ku, true), d = spec_at<T, L>(qp, ku, true);
-        cx<T> x = va[e], y = vb[e];
-        va[e] = cmulc(x, a) + cmulc(y, c);   // conj(E_r) v_r + conj(E_p) v_p
-        vb[e] = cmulc(x, b) + cmulc(y, d);   // conj(Q_r) v_r + conj(Q_p) v_p
+        sa[e] = spec_at<T, L>(er, ku, false);
+        sb[e] = spec_at<T, L>(qr, ku, false);
+        sc[e] = spec_at<T, L>(ep, ku, true);
+        sd[e] = spec_at<T, L>(qp, ku, true);
     }
-    fft_inv<L, E, T>(va, t, lds, twL, 1);
-    fft_inv<L, E, T>(vb, t, lds, twL, 1);
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        cx<T> x = va[e], y = vb[e];
+        va[e] = cmulc(x, sa[e]) + cmulc(y, sc[e]);   // conj(E_r) v_r + conj(E_p) v_p
+        vb[e] = cmulc(x, sb[e]) + cmulc(y, sd[e]);   // conj(Q_r) v_r + conj(Q_p) v_p
+    }
+    fft_inv<L, E, T>(va, t, lds, tw);
+    fft_inv<L, E, T>(vb, t, lds, tw);
     // transposed stencil on the slope channel
 #pragma unroll
     for (int e = 0; e < E; ++e) {

@@ -402,6 +402,8 @@ __global__ __launch_bounds__(512) void k_fold(const cx<double> *__restrict__ row
     cx<double> *buf = reinterpret_cast<cx<double> *>(smem_raw);
     const int col = blockIdx.x, t = threadIdx.x;
     Lds<double> lds{buf, 0, 1};
+    Twiddles<L, E, double> tw;
+    tw.load(t, twL, 1);
     const double sc = 1.0 / ((double)L * (double)n_phi);
     const double sk = sin(2.0 * M_PI * col / n_phi) / dphi;
 
@@ -417,7 +419,7 @@ __global__ __launch_bounds__(512) void k_fold(const cx<double> *__restrict__ row
             }
             v[e] = x;
         }
-        fft_fwd<L, E, double>(v, t, lds, twL, 1);
+        fft_fwd<L, E, double>(v, t, lds, tw);
     };
     auto store = [&](int which, const cx<double>(&v)[E]) {
         cx<double> *dst = spec + ((size_t)which * H + col) * ldspec;
