@@ -35,11 +35,12 @@ def log(*a):
 
 
 def path_bytes(n_r, n_phi, L, w):
-    """Algorithmic HBM bytes of one forward call (three passes):
+    """Algorithmic HBM bytes of one forward call (three passes), with
+    H = P/2 columns of the packed half spectrum:
     pass A reads sigma (R P w) and writes S (R H 2w); pass B reads S and the
     four half spectra (4 (L/2+1) H 2w) and writes Zr, Zp (2 R H 2w); pass C
     reads Zr, Zp and writes F_r, F_phi (2 R P w)."""
-    H = n_phi // 2 + 1
+    H = n_phi // 2
     a = n_r * n_phi * w + n_r * H * 2 * w
     b = n_r * H * 2 * w + 4 * (L // 2 + 1) * H * 2 * w + 2 * n_r * H * 2 * w
     c = 2 * n_r * H * 2 * w + 2 * n_r * n_phi * w
@@ -60,14 +61,36 @@ def time_calls(torch, fn, steps, warmup):
     return e0.elapsed_time(e1) / steps  # ms per call
 
 
-def pass_times(plan, a, b=None, backward=False, reps=30):
-    acc = [0.0, 0.0, 0.0]
-    for _ in range(3):
-        plan.timed(a, b, backward)
-    for _ in range(reps):
-        ms = plan.timed(a, b, backward)
-        acc = [x + y for x, y in zip(acc, ms)]
-    return [x / reps for x in acc]
+def sched(plan):
+    s = plan.schedule()
+    return {"rows_E_G": list(s[0:2]), "cols_E_G": list(s[2:4]), "cols_adj_E_G": list(s[4:6])}
+
+
+def time_graph(torch, fn, steps, warmup):
+    """ms per step with the step captured once in a HIP graph (through
+    torch.cuda.CUDAGraph on the current stream) and replayed `steps` times:
+    the launch cost of a compiled caller, without the Python call path."""
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        for _ in range(3):
+            fn()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        fn()
+    torch.cuda.synchronize()
+    ms = time_calls(torch, g.replay, steps, warmup)
+    del g
+    return ms
+
+
+def pass_times(plan, a, b=None, backward=False, reps=100):
+    """Mean duration (ms) of one launch of each pass, from HIP events on the
+    launch stream around `reps` back-to-back launches of that pass."""
+    plan.timed(a, b, backward, reps=5)
+    return plan.timed(a, b, backward, reps=reps)
 
 
 def cpu_baseline(sample_seconds=15.0):
@@ -136,7 +159,9 @@ def main():
     s32 = torch.tensor(sig_np, dtype=torch.float32, device=dev)
     fr32, fp32 = torch.empty_like(s32), torch.empty_like(s32)
     log("fp32 forward: warmup %d, steps %d" % (W, K))
-    ms32 = time_calls(torch, lambda: p32.forces(s32, (fr32, fp32)), K, W)
+    f32 = lambda: p32.forces(s32, (fr32, fp32))
+    ms32 = time_calls(torch, f32, K, W)
+    ms32_graph = time_graph(torch, f32, K, W)
     passes32 = pass_times(p32, s32)
     L = p32_L = 2 * N_R
     bA, bB, bC = path_bytes(N_R, N_PHI, p32_L, 4)
@@ -196,7 +221,13 @@ def main():
     out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                        "frac": achieved / HBM_PEAK_GBS, "traffic": None}
     out["detail"] = {
-        "dominant_kernel": "k_cols_fwd (fused radial slope + u-FFTs + spectral MAC + inverse)",
+        "dominant_kernel": "k_cols_fwd (u-FFT + spectral MAC with spectral radial slope + "
+                           "two inverse u-FFTs)",
+        "step_timing": "K back-to-back pf_forces calls between events on the launch stream",
+        "graph_ms_per_step_fp32": ms32_graph,
+        "graph_cells_per_s_fp32": cells / (ms32_graph * 1e-3),
+        "schedule_fp32": sched(p32),
+        "schedule_fp64": sched(p64),
         "pass_ms_fp32": passes32, "pass_bytes_fp32": [bA, bB, bC],
         "pass_GBs_fp32": [b / (t * 1e-3) / 1e9 for b, t in zip((bA, bB, bC), passes32)],
         "path_bytes_fp32": bA + bB + bC,

@@ -124,14 +124,16 @@ int pf_forces_backward(pf_plan plan, const void *g_fr, const void *g_fphi,
 int pf_forces_batched(int n, const pf_plan *plans, const void *const *sigma,
                       void *const *f_r, void *const *f_phi, void *stream);
 
-/* Diagnostic form of pf_forces / pf_forces_backward: the same passes, with
- * HIP events recorded on `stream` around each of the three passes; waits for
- * them and writes the three durations in milliseconds to pass_ms[3]
- * (row transforms, column pass, row transforms).  backward = 0 times the
- * forward map (in0 = sigma, out0 = f_r, out1 = f_phi), backward = 1 the
- * transpose (in0 = g_fr, in1 = g_fphi, out0 = g_sigma).  Synchronous.      */
+/* Diagnostic form of pf_forces / pf_forces_backward: the same passes, each
+ * launched `reps` times back to back (1 <= reps <= 10000; every pass reads
+ * only its predecessor's output, so repeats leave the result unchanged)
+ * between HIP events recorded on `stream`; waits for them and writes the
+ * mean duration of one launch in milliseconds to pass_ms[3] (row
+ * transforms, column pass, row transforms).  backward = 0 times the forward
+ * map (in0 = sigma, out0 = f_r, out1 = f_phi), backward = 1 the transpose
+ * (in0 = g_fr, in1 = g_fphi, out0 = g_sigma).  Synchronous.                */
 int pf_forces_timed(pf_plan plan, int backward, const void *in0, const void *in1,
-                    void *out0, void *out1, void *stream, float *pass_ms);
+                    void *out0, void *out1, int reps, void *stream, float *pass_ms);
 
 /* Grid geometry on the host: r_centres[n_r], r_edges[n_r + 1], *dphi.
  * Any output may be NULL.                                                  */
@@ -142,6 +144,13 @@ int pf_plan_geometry(pf_plan plan, double *r_centres, double *r_edges,
  * out[0] = K^{r,0}_{00}, out[1] = K^{r,r}_{00}, out[2] = K^{phi,phi}_{00}
  * (Eq. 33, 46; the other three self constants are zero by symmetry).      */
 int pf_plan_selfcell(pf_plan plan, double out[3]);
+
+/* Launch shapes chosen for the plan by the last build (autotuned unless
+ * PF_AUTOTUNE=0): out[0], out[1] = points per thread and rows per workgroup
+ * of the row transforms; out[2], out[3] = points per thread and columns per
+ * workgroup of the forward column pass; out[4], out[5] the same for the
+ * transpose column pass.  Not in the paper: a diagnostic.                  */
+int pf_plan_schedule(pf_plan plan, int out[6]);
 
 /* Copy the six FP64 kernel tables to host memory `dst` (plan built with
  * keep_tables).  Layout: [6][2 n_r - 1][n_phi], kernels in the order

@@ -28,8 +28,8 @@ _STATUS = {1: "PF_EINVAL", 2: "PF_ESTATE", 3: "PF_ENOMEM", 4: "PF_EHIP", 5: "PF_
 
 EXPORTS = ("pf_build_opts_default", "pf_plan_create", "pf_kernels_build", "pf_forces",
            "pf_forces_backward", "pf_forces_batched", "pf_forces_timed", "pf_plan_geometry",
-           "pf_plan_selfcell", "pf_plan_tables", "pf_plan_destroy", "pf_last_error",
-           "pf_version")
+           "pf_plan_schedule", "pf_plan_selfcell", "pf_plan_tables", "pf_plan_destroy",
+           "pf_last_error", "pf_version")
 
 
 class PFError(RuntimeError):
@@ -70,13 +70,14 @@ def load():
     lib.pf_forces.argtypes = [P, P, P, P, P]
     lib.pf_forces_backward.argtypes = [P, P, P, P, P]
     lib.pf_forces_batched.argtypes = [I, P, P, P, P, P]
-    lib.pf_forces_timed.argtypes = [P, I, P, P, P, P, P, P]
+    lib.pf_forces_timed.argtypes = [P, I, P, P, P, P, I, P, P]
     lib.pf_plan_geometry.argtypes = [P, P, P, P]
     lib.pf_plan_selfcell.argtypes = [P, P]
+    lib.pf_plan_schedule.argtypes = [P, P]
     lib.pf_plan_tables.argtypes = [P, P]
     for f in ("pf_kernels_build", "pf_forces", "pf_forces_backward", "pf_forces_batched",
               "pf_forces_timed",
-              "pf_plan_geometry", "pf_plan_selfcell", "pf_plan_tables"):
+              "pf_plan_geometry", "pf_plan_selfcell", "pf_plan_schedule", "pf_plan_tables"):
         getattr(lib, f).restype = I
     lib.pf_plan_destroy.argtypes = [P]
     lib.pf_plan_destroy.restype = None
@@ -134,12 +135,13 @@ def pf_forces_batched(plans, sigma, f_r, f_phi, stream: int = 0) -> None:
 
 
 def pf_forces_timed(plan: int, backward: bool, in0: int, in1: int, out0: int, out1: int,
-                    stream: int = 0):
-    """Run the forward map (or its transpose) with events around each pass;
-    returns the three pass durations in ms."""
+                    reps: int = 1, stream: int = 0):
+    """Run the forward map (or its transpose), each pass launched `reps`
+    times back to back between events; returns the mean duration of one
+    launch of each of the three passes in ms."""
     ms = (ctypes.c_float * 3)()
     _check(load().pf_forces_timed(plan, int(bool(backward)), in0, in1 or None, out0,
-                                  out1 or None, stream or None, ms))
+                                  out1 or None, int(reps), stream or None, ms))
     return [float(v) for v in ms]
 
 
@@ -155,6 +157,14 @@ def pf_plan_selfcell(plan: int):
     out = np.empty(3)
     _check(load().pf_plan_selfcell(plan, out.ctypes.data))
     return out
+
+
+def pf_plan_schedule(plan: int):
+    """(row E, row G, column E, column G, transpose column E, transpose
+    column G) launch shapes of a built plan."""
+    out = np.zeros(6, dtype=np.int32)
+    _check(load().pf_plan_schedule(plan, out.ctypes.data))
+    return tuple(int(v) for v in out)
 
 
 def pf_plan_tables(plan: int, n_r: int, n_phi: int):
@@ -213,6 +223,9 @@ class Plan:
     def tables(self):
         return pf_plan_tables(self.handle, self.n_r, self.n_phi)
 
+    def schedule(self):
+        return pf_plan_schedule(self.handle)
+
     def _check_field(self, t, name):
         import torch
         if not isinstance(t, torch.Tensor) or not t.is_cuda:
@@ -237,17 +250,18 @@ class Plan:
                            _stream())
         return gs
 
-    def timed(self, a, b=None, backward=False):
-        """Pass durations (ms) of one forward (a = sigma) or transpose
-        (a, b = g_fr, g_fphi) call."""
+    def timed(self, a, b=None, backward=False, reps=1):
+        """Mean duration (ms) of one launch of each pass of the forward map
+        (a = sigma) or its transpose (a, b = g_fr, g_fphi), each pass
+        launched `reps` times back to back."""
         import torch
         if backward:
             out = torch.empty_like(a)
             return pf_forces_timed(self.handle, True, a.data_ptr(), b.data_ptr(),
-                                   out.data_ptr(), 0, _stream())
+                                   out.data_ptr(), 0, reps, _stream())
         fr, fp = torch.empty_like(a), torch.empty_like(a)
         return pf_forces_timed(self.handle, False, a.data_ptr(), 0, fr.data_ptr(),
-                               fp.data_ptr(), _stream())
+                               fp.data_ptr(), reps, _stream())
 
     def close(self):
         if getattr(self, "handle", None):

@@ -5,20 +5,39 @@
 // call it (the bodies contain barriers).
 //
 // Forward map (Eq. 26-29, A18-A21) as a 2-D convolution:
-//   pass A  S = R2C_phi(sigma)                         rows,    [n_r][H]
-//   pass B  per column k:  c = S[:, k], g = D_r c (radial slope, Eq. 25)
-//           Zr = crop IFFT_u(E_r FFT_u(pad c) + Q_r FFT_u(pad g))
-//           Zp = crop IFFT_u(E_p FFT_u(pad c) + Q_p FFT_u(pad g))
+//   pass A  S = R2C_phi(sigma)                         rows,    [n_r][M]
+//   pass B  per column k:  c = S[:, k]
+//           Zr = crop IFFT_u(E'_r FFT_u(pad c) + Q_r B(c))
+//           Zp = crop IFFT_u(E'_p FFT_u(pad c) + Q_p B(c))
 //   pass C  F_r = C2R_phi(Zr), F_phi = C2R_phi(Zp)
 // The azimuthal slope channel is folded into E_r, E_p (exact for the
 // periodic central difference), the r_i / r_i' = beta^(i-i') factor of
-// Eq. 28 into Q_r, Q_p; g = r delta^r.  Padding to L >= 2 n_r in u makes the
-// circular convolution equal the linear one on the n_r output rows, so no
-// artificial boundary condition enters (Sec. 2).
+// Eq. 28 into Q_r, Q_p.  The radial slope g = r delta^r c (Eq. 25, constant
+// coefficients on the logarithmic grid) is applied in the spectral domain:
+// on the zero-padded column it equals the circular central difference
+// ca (c[i+1] - c[i-1]) except at four rows (0, n-1, n, L-1), so
+//   FFT_u(pad g)[k] = 2i ca sin(2 pi k / L) FFT_u(pad c)[k] + B(c)[k]
+// with B(c) the transform of that four-row correction.  The first term is
+// folded into the spectra, E' = E + Q * 2i ca sin(2 pi k / L); B(c) costs a
+// few complex products per point instead of a second column transform.
+// Padding to L >= 2 n_r in u makes the circular convolution equal the
+// linear one on the n_r output rows, so no artificial boundary condition
+// enters (Sec. 2).
 //
-// Layouts: S, Zr, Zp, Vr, Vp, D are row-major [n_r][H] complex, H = n_phi/2+1;
-// spectra are [4][H][L/2+1] complex (E_r, Q_r, E_p, Q_p), column-contiguous,
-// holding k_u in [0, L/2]; the rest follows from the kernels' symmetry in phi.
+// Packed half spectrum: a real row of N = 2M points has M + 1 independent
+// bins of which bin 0 and bin M are real; they travel together as the one
+// complex value (X_0, X_M) in column 0, so every row holds exactly M complex
+// values.  Along u the column 0 data are then c_0 + i c_M with c_0, c_M real
+// sequences; pass B separates their transforms with the conjugate mirror
+// k -> L - k.  The azimuthal spectra vanish at bins 0 and M (the kernels
+// K^{phi,*} are odd in phi - phi'), so column 0 carries the radial spectra
+// of both bins and its F_phi output is zero.
+//
+// Layouts: S, Zr, Zp, Vr, Vp, D are row-major [n_r][M] complex, M = n_phi/2;
+// spectra are [4][M][L/2+1] complex (slots E'_r, Q_r, E'_p, Q_p; for
+// column 0: E'_r, Q_r of bin 0, E'_r, Q_r of bin M), column-contiguous,
+// holding k_u in [0, L/2]; the rest follows from the kernels' symmetry in
+// phi.
 #pragma once
 #include "fft_core.hpp"
 
@@ -26,7 +45,8 @@ namespace pf {
 
 // ---------------------------------------------------------------------------
 // Pass A: real-to-complex transforms of rows of length N = 2M via one
-// M-point complex transform of z[n] = x[2n] + i x[2n+1].
+// M-point complex transform of z[n] = x[2n] + i x[2n+1]; output in the
+// packed half spectrum (bin 0 = (X_0, X_M)).
 // Workgroup: G rows x (M/E) threads; LDS buf: G*padded_len(M) complex.
 // ---------------------------------------------------------------------------
 template <typename T, int M, int E>
@@ -38,7 +58,7 @@ __device__ __forceinline__ void body_rows_r2c(int unit, int G, cx<T> *__restrict
                                                   const cx<T> *__restrict__ twN) {
     constexpr int TH = M / E;
     constexpr int N = 2 * M;
-    constexpr int H = M + 1;
+    constexpr int H = M;
     const int gi = threadIdx.x / TH, t = threadIdx.x % TH;
     const int row = unit * G + gi;
     const bool active = row < total_rows;
@@ -70,18 +90,16 @@ __device__ __forceinline__ void body_rows_r2c(int unit, int G, cx<T> *__restrict
             cx<T> ev = {T(0.5) * (zk.x + zm.x), T(0.5) * (zk.y - zm.y)};
             // (zk - conj zm) / (2i)
             cx<T> od = {T(0.5) * (zk.y + zm.y), -T(0.5) * (zk.x - zm.x)};
-            out[k] = ev + cmul(twN[k], od);
-        }
-        if (t == 0) {
-            cx<T> z0 = lds.ld(0);
-            out[M] = cx<T>{z0.x - z0.y, T(0)};
+            cx<T> o = ev + cmul(twN[k], od);
+            if (k == 0) o = cx<T>{zk.x + zk.y, zk.x - zk.y};   // (X_0, X_M), both real
+            out[k] = o;
         }
     }
 }
 
 // ---------------------------------------------------------------------------
-// Pass C: complex-to-real transforms of Hermitian half rows (H values) to
-// real rows of length N = 2M (unnormalised inverse).
+// Pass C: complex-to-real transforms of packed half rows (M values, bin 0 =
+// (X_0, X_M)) to real rows of length N = 2M (unnormalised inverse).
 // ---------------------------------------------------------------------------
 template <typename T, int M, int E>
 __device__ __forceinline__ void body_rows_c2r(int unit, int G, cx<T> *__restrict__ buf,
@@ -92,7 +110,7 @@ __device__ __forceinline__ void body_rows_c2r(int unit, int G, cx<T> *__restrict
                                                   const cx<T> *__restrict__ twN) {
     constexpr int TH = M / E;
     constexpr int N = 2 * M;
-    constexpr int H = M + 1;
+    constexpr int H = M;
     const int gi = threadIdx.x / TH, t = threadIdx.x % TH;
     const int row = unit * G + gi;
     const bool active = row < total_rows;
@@ -108,8 +126,13 @@ __device__ __forceinline__ void body_rows_c2r(int unit, int G, cx<T> *__restrict
     for (int e = 0; e < E; ++e) {
         const int k = t + e * TH;
         xk[e] = X[k];
-        xm[e] = X[M - k];
+        xm[e] = X[(M - k) & (M - 1)];
         wk[e] = twN[k];                          // exp(-2 pi i k / N)
+    }
+    if (t == 0) {   // unpack bin 0 = (X_0, X_M)
+        const cx<T> p = xk[0];
+        xk[0] = cx<T>{p.x, T(0)};
+        xm[0] = cx<T>{p.y, T(0)};
     }
     Twiddles<M, E, T> tw;
     tw.load(t, twN, 2);
@@ -143,184 +166,317 @@ __device__ __forceinline__ cx<T> spec_at(const cx<T> *__restrict__ col, int ku, 
 }
 
 // ---------------------------------------------------------------------------
+// Four-row correction of the radial slope (see the header).  For the column
+// c (n = n_r rows, zero beyond) the slope differs from the circular central
+// difference at
+//   row 0      a0  = c0 (c1 - c0) - ca c1
+//   row n - 1  an1 = cn (c[n-1] - c[n-2]) + ca c[n-2]
+//   row n      an  = ca c[n-1]
+//   row L - 1  am1 = -ca c0
+// (c0, ca, cn: the first, interior and last row coefficients).  Its
+// transform at k, with u = W^k and v = W^(n k), W = exp(-2 pi i / L), is
+//   a0 + am1 conj(u) + v (an + an1 conj(u)).
+// ---------------------------------------------------------------------------
+template <typename T>
+struct SlopeFix {
+    cx<T> a0, am1, an, an1;
+};
+
+template <typename T>
+__device__ __forceinline__ SlopeFix<T> slope_fix(cx<T> x0, cx<T> x1, cx<T> xm2, cx<T> xm1, T ca,
+                                                 T c0, T cn) {
+    SlopeFix<T> s;
+    s.a0 = scale(x1 - x0, c0) - scale(x1, ca);
+    s.an1 = scale(xm1 - xm2, cn) + scale(xm2, ca);
+    s.an = scale(xm1, ca);
+    s.am1 = scale(x0, -ca);
+    return s;
+}
+
+template <typename T>
+__device__ __forceinline__ cx<T> slope_fix_at(const SlopeFix<T> &s, cx<T> u, cx<T> v) {
+    const cx<T> uc = conj(u);
+    return s.a0 + cmul(s.am1, uc) + cmul(v, s.an + cmul(s.an1, uc));
+}
+
+// the same with real coefficients (one bin of the packed column 0)
+template <typename T>
+__device__ __forceinline__ cx<T> slope_fix_at_real(T a0, T am1, T an, T an1, cx<T> u, cx<T> v) {
+    const cx<T> in = {an + an1 * u.x, -an1 * u.y};
+    return cx<T>{a0 + am1 * u.x, -am1 * u.y} + cmul(v, in);
+}
+
+// Transforms of the two real sequences packed as p = c_0 + i c_M, from p and
+// its conjugate mirror m = p[L - k]:  c_0 -> (p + conj m) / 2,
+// c_M -> (p - conj m) / (2i).
+template <typename T>
+__device__ __forceinline__ cx<T> unpack_even(cx<T> p, cx<T> m) {
+    return {T(0.5) * (p.x + m.x), T(0.5) * (p.y - m.y)};
+}
+template <typename T>
+__device__ __forceinline__ cx<T> unpack_odd(cx<T> p, cx<T> m) {
+    return {T(0.5) * (p.y + m.y), T(0.5) * (m.x - p.x)};
+}
+
+// Points per batch of spectrum loads in the multiply-accumulate of pass B,
+// sized so that a batch's loads (six complex values per point) fit in the
+// registers beside the transform data: 64 / E in FP32 (E <= 8: all E),
+// 2 in FP64.
+template <typename T, int E>
+__host__ __device__ constexpr int mac_batch() { return sizeof(T) == 8 ? 2 : (E < 8 ? E : 64 / E); }
+
+// ---------------------------------------------------------------------------
 // Pass B, forward.  Workgroup: G columns x (L/E) threads, lane -> (t, column)
 // with the G columns interleaved (consecutive lanes read consecutive
 // columns of a row).  LDS buf: G*padded_len(L) complex.
 // ---------------------------------------------------------------------------
 template <typename T, int L, int E>
 __device__ __forceinline__ void body_cols_fwd(int unit, int G, cx<T> *__restrict__ buf,
-                                           const cx<T> *__restrict__ S,
-                                                  cx<T> *__restrict__ Zr, cx<T> *__restrict__ Zp,
-                                                  const cx<T> *__restrict__ spec, int H, int n_r,
-                                                  int ldspec, T ca, T c0, T cn,
-                                                  const cx<T> *__restrict__ twL) {
+                                              const cx<T> *__restrict__ S,
+                                              cx<T> *__restrict__ Zr, cx<T> *__restrict__ Zp,
+                                              const cx<T> *__restrict__ spec, int H, int n_r,
+                                              int ldspec, T ca, T c0, T cn,
+                                              const cx<T> *__restrict__ twL) {
     constexpr int TH = L / E;
-    const int grp = unit;
     const int gi = threadIdx.x % G, t = threadIdx.x / G;
-    const int col = grp * G + gi;
+    const int col = unit * G + gi;
     const bool valid = col < H;
+    const int cl = valid ? col : 0;
+    const bool packed = unit == 0;          // workgroup-uniform: the group holding column 0
+    const bool is0 = packed && gi == 0;
     Lds<T> lds{buf, gi, G};
 
+    // The column.  Only the first E/2 strided points of a thread can be data
+    // rows (L >= 2 n_r); clamped, always valid addresses so the loads issue
+    // back to back.
+    cx<T> v[E];
+#pragma unroll
+    for (int e = 0; e < E / 2; ++e) {
+        const int i = t + e * TH;
+        v[e] = S[(size_t)(i < n_r ? i : n_r - 1) * H + cl];
+    }
+    // the four rows entering the slope correction
+    const cx<T> x0 = S[cl], x1 = S[(size_t)H + cl];
+    const cx<T> xm2 = S[(size_t)(n_r - 2) * H + cl], xm1 = S[(size_t)(n_r - 1) * H + cl];
     Twiddles<L, E, T> tw;
     tw.load(t, twL, 1);
-    // stage the column in LDS to form the radial slope channel.  Only the
-    // first E/2 points of a thread can be data rows (L >= 2 n_r); the loads
-    // use clamped, always valid addresses so they issue back to back.
-    {
-        const int cl = valid ? col : 0;
-        cx<T> g[E / 2];
-#pragma unroll
-        for (int e = 0; e < E / 2; ++e) {
-            const int i = t + e * TH;
-            g[e] = S[(size_t)(i < n_r ? i : n_r - 1) * H + cl];
-        }
-#pragma unroll
-        for (int e = 0; e < E / 2; ++e) {
-            const int i = t + e * TH;
-            if (i < n_r) lds.st(i, valid ? g[e] : cx<T>{T(0), T(0)});
-        }
-    }
-    __syncthreads();
-    cx<T> vc[E], vg[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         const int i = t + e * TH;
-        cx<T> c = {T(0), T(0)}, g = {T(0), T(0)};
-        if (i < n_r) {
-            c = lds.ld(i);
-            if (i == 0)
-                g = scale(lds.ld(1) - c, c0);
-            else if (i == n_r - 1)
-                g = scale(c - lds.ld(i - 1), cn);
-            else
-                g = scale(lds.ld(i + 1) - lds.ld(i - 1), ca);
+        if (e >= E / 2 || !valid || i >= n_r) v[e] = cx<T>{T(0), T(0)};
+    }
+    fft_fwd<L, E, T>(v, t, lds, tw);
+    if (packed) {   // column 0 reads the conjugate mirror points from LDS
+#pragma unroll
+        for (int e = 0; e < E; ++e) lds.st(t + e * TH, v[e]);
+        __syncthreads();
+    }
+
+    const cx<T> *er = spec + (size_t)(0 * H + cl) * ldspec;
+    const cx<T> *qr = spec + (size_t)(1 * H + cl) * ldspec;
+    const cx<T> *ep = spec + (size_t)(2 * H + cl) * ldspec;
+    const cx<T> *qp = spec + (size_t)(3 * H + cl) * ldspec;
+    const SlopeFix<T> a = slope_fix(x0, x1, xm2, xm1, ca, c0, cn);
+    constexpr int CH = mac_batch<T, E>();
+    cx<T> yr[E], yp[E];
+#pragma unroll
+    for (int cb = 0; cb < E; cb += CH) {
+        // spectra and correction twiddles of the batch issued together;
+        // column 0's slots 2, 3 hold bin M's radial (even) spectra
+        cx<T> sa[CH], sb[CH], sc[CH], sd[CH], uu[CH], vv[CH];
+#pragma unroll
+        for (int j = 0; j < CH; ++j) {
+            const int ku = t + (cb + j) * TH;
+            sa[j] = spec_at<T, L>(er, ku, false);
+            sb[j] = spec_at<T, L>(qr, ku, false);
+            sc[j] = spec_at<T, L>(ep, ku, !is0);
+            sd[j] = spec_at<T, L>(qp, ku, !is0);
+            uu[j] = twL[ku];
+            vv[j] = twL[(int)(((unsigned)n_r * (unsigned)ku) & (unsigned)(L - 1))];
         }
-        vc[e] = c;
-        vg[e] = g;
-    }
-    __syncthreads();
-    fft_fwd<L, E, T>(vc, t, lds, tw);
-    fft_fwd<L, E, T>(vg, t, lds, tw);
-    const int cs = valid ? col : 0;
-    const cx<T> *er = spec + (size_t)(0 * H + cs) * ldspec;
-    const cx<T> *qr = spec + (size_t)(1 * H + cs) * ldspec;
-    const cx<T> *ep = spec + (size_t)(2 * H + cs) * ldspec;
-    const cx<T> *qp = spec + (size_t)(3 * H + cs) * ldspec;
-    // all spectrum loads of the unit in one batch (one memory round trip)
-    cx<T> sa[E], sb[E], sc[E], sd[E];
 #pragma unroll
-    for (int e = 0; e < E; ++e) {
-        const int ku = t + e * TH;
-        sa[e] = spec_at<T, L>(er, ku, false);
-        sb[e] = spec_at<T, L>(qr, ku, false);
-        sc[e] = spec_at<T, L>(ep, ku, true);
-        sd[e] = spec_at<T, L>(qp, ku, true);
+        for (int j = 0; j < CH; ++j) {
+            const int e = cb + j;
+            if (is0) {
+                const cx<T> m = lds.ld((L - (t + e * TH)) & (L - 1));
+                const cx<T> A = unpack_even(v[e], m), B = unpack_odd(v[e], m);
+                const cx<T> f0 = slope_fix_at_real(a.a0.x, a.am1.x, a.an.x, a.an1.x, uu[j], vv[j]);
+                const cx<T> fM = slope_fix_at_real(a.a0.y, a.am1.y, a.an.y, a.an1.y, uu[j], vv[j]);
+                const cx<T> y0 = cmul(sa[j], A) + cmul(sb[j], f0);
+                const cx<T> yM = cmul(sc[j], B) + cmul(sd[j], fM);
+                yr[e] = cx<T>{y0.x - yM.y, y0.y + yM.x};   // y0 + i yM
+                yp[e] = cx<T>{T(0), T(0)};
+            } else {
+                const cx<T> f = slope_fix_at(a, uu[j], vv[j]);
+                yr[e] = cmul(sa[j], v[e]) + cmul(sb[j], f);
+                yp[e] = cmul(sc[j], v[e]) + cmul(sd[j], f);
+            }
+        }
     }
-#pragma unroll
-    for (int e = 0; e < E; ++e) {
-        cx<T> x = vc[e], y = vg[e];
-        vc[e] = cmul(sa[e], x) + cmul(sb[e], y);
-        vg[e] = cmul(sc[e], x) + cmul(sd[e], y);
-    }
-    fft_inv<L, E, T>(vc, t, lds, tw);
-    fft_inv<L, E, T>(vg, t, lds, tw);
+    if (packed) __syncthreads();
+    fft_inv<L, E, T>(yr, t, lds, tw);
+    fft_inv<L, E, T>(yp, t, lds, tw);
     if (valid) {
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             const int i = t + e * TH;
             if (i < n_r) {
-                Zr[(size_t)i * H + col] = vc[e];
-                Zp[(size_t)i * H + col] = vg[e];
+                Zr[(size_t)i * H + col] = yr[e];
+                Zp[(size_t)i * H + col] = yp[e];
             }
         }
     }
 }
 
+// Sum of x over the threads of each column of the workgroup (the G columns
+// are interleaved lane by lane: column gi = thread % G); every thread gets
+// its column's sum.  Within a wave the lanes of a column combine by lane
+// exchange; across waves through the first n_grp * G * Q complex slots of
+// buf.  The caller's previous LDS use must be fenced by a barrier.
+template <typename T, int Q>
+__device__ __forceinline__ void column_sums(cx<T> (&x)[Q], int G, cx<T> *__restrict__ buf) {
+    const int nthr = blockDim.x;
+    const int width = nthr < 64 ? nthr : 64;
+    for (int off = G; off < width; off <<= 1) {
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            x[q].x += __shfl_xor(x[q].x, off);
+            x[q].y += __shfl_xor(x[q].y, off);
+        }
+    }
+    if (nthr > 64) {
+        const int gi = threadIdx.x % G;
+        // one partial per (group, column): per wave when G < 64 (every wave
+        // then holds all G columns), per thread otherwise
+        const bool wide = G >= 64;
+        const int grp = wide ? (int)threadIdx.x / G : (int)(threadIdx.x >> 6);
+        const int n_grp = wide ? nthr / G : nthr >> 6;
+        if (wide || (int)(threadIdx.x & 63) < G) {
+#pragma unroll
+            for (int q = 0; q < Q; ++q) buf[(grp * G + gi) * Q + q] = x[q];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            cx<T> s = buf[gi * Q + q];
+            for (int g = 1; g < n_grp; ++g) s = s + buf[(g * G + gi) * Q + q];
+            x[q] = s;
+        }
+        __syncthreads();
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Pass B, transpose: correlate with the kernels (conjugate spectra), then
-// apply the transposed radial-slope stencil: d = c_s + D_r^T c_g.
+// the transposed slope: the transposed central difference is in E'; the
+// four-row correction needs the inverse transform of R = conj(Q_r) V_r +
+// conj(Q_p) V_p at rows 0, n-1, n and L-1 only, four sums over k.
 // ---------------------------------------------------------------------------
 template <typename T, int L, int E>
 __device__ __forceinline__ void body_cols_adj(int unit, int G, cx<T> *__restrict__ buf,
-                                           const cx<T> *__restrict__ Vr,
-                                                  const cx<T> *__restrict__ Vp,
-                                                  cx<T> *__restrict__ D,
-                                                  const cx<T> *__restrict__ spec, int H, int n_r,
-                                                  int ldspec, T ca, T c0, T cn,
-                                                  const cx<T> *__restrict__ twL) {
+                                              const cx<T> *__restrict__ Vr,
+                                              const cx<T> *__restrict__ Vp,
+                                              cx<T> *__restrict__ D,
+                                              const cx<T> *__restrict__ spec, int H, int n_r,
+                                              int ldspec, T ca, T c0, T cn,
+                                              const cx<T> *__restrict__ twL) {
     constexpr int TH = L / E;
-    const int grp = unit;
     const int gi = threadIdx.x % G, t = threadIdx.x / G;
-    const int col = grp * G + gi;
+    const int col = unit * G + gi;
     const bool valid = col < H;
+    const int cl = valid ? col : 0;
+    const bool packed = unit == 0;
+    const bool is0 = packed && gi == 0;
     Lds<T> lds{buf, gi, G};
 
-    Twiddles<L, E, T> tw;
-    tw.load(t, twL, 1);
     // clamped, always valid addresses so the loads issue back to back; only
     // the first E/2 points of a thread can be data rows (L >= 2 n_r)
     cx<T> va[E], vb[E];
-    {
-        const int cl = valid ? col : 0;
 #pragma unroll
-        for (int e = 0; e < E / 2; ++e) {
-            const int i = t + e * TH;
-            const size_t o = (size_t)(i < n_r ? i : n_r - 1) * H + cl;
-            va[e] = Vr[o];
-            vb[e] = Vp[o];
-        }
+    for (int e = 0; e < E / 2; ++e) {
+        const int i = t + e * TH;
+        const size_t o = (size_t)(i < n_r ? i : n_r - 1) * H + cl;
+        va[e] = Vr[o];
+        vb[e] = Vp[o];
+    }
+    Twiddles<L, E, T> tw;
+    tw.load(t, twL, 1);
 #pragma unroll
-        for (int e = 0; e < E; ++e) {
-            const int i = t + e * TH;
-            const bool in = valid && i < n_r && e < E / 2;
-            if (!in) {
-                va[e] = cx<T>{T(0), T(0)};
-                vb[e] = cx<T>{T(0), T(0)};
-            }
+    for (int e = 0; e < E; ++e) {
+        const int i = t + e * TH;
+        if (e >= E / 2 || !valid || i >= n_r) {
+            va[e] = cx<T>{T(0), T(0)};
+            vb[e] = cx<T>{T(0), T(0)};
         }
     }
     fft_fwd<L, E, T>(va, t, lds, tw);
     fft_fwd<L, E, T>(vb, t, lds, tw);
-    const int cs = valid ? col : 0;
-    const cx<T> *er = spec + (size_t)(0 * H + cs) * ldspec;
-    const cx<T> *qr = spec + (size_t)(1 * H + cs) * ldspec;
-    const cx<T> *ep = spec + (size_t)(2 * H + cs) * ldspec;
-    const cx<T> *qp = spec + (size_t)(3 * H + cs) * ldspec;
-    // all spectrum loads of the unit in one batch (one memory round trip)
-    cx<T> sa[E], sb[E], sc[E], sd[E];
+    if (packed) {   // column 0 reads the conjugate mirror points from LDS
 #pragma unroll
-    for (int e = 0; e < E; ++e) {
-        const int ku = t + e * TH;
-        sa[e] = spec_at<T, L>(er, ku, false);
-        sb[e] = spec_at<T, L>(qr, ku, false);
-        sc[e] = spec_at<T, L>(ep, ku, true);
-        sd[e] = spec_at<T, L>(qp, ku, true);
+        for (int e = 0; e < E; ++e) lds.st(t + e * TH, va[e]);
+        __syncthreads();
     }
+
+    const cx<T> *er = spec + (size_t)(0 * H + cl) * ldspec;
+    const cx<T> *qr = spec + (size_t)(1 * H + cl) * ldspec;
+    const cx<T> *ep = spec + (size_t)(2 * H + cl) * ldspec;
+    const cx<T> *qp = spec + (size_t)(3 * H + cl) * ldspec;
+    // w[0] = sum R, w[1] = sum R u, w[2] = sum R conj(v), w[3] = sum R conj(v) u:
+    // the unnormalised inverse transform of R at rows 0, L-1, n, n-1
+    cx<T> w[4] = {{T(0), T(0)}, {T(0), T(0)}, {T(0), T(0)}, {T(0), T(0)}};
+    constexpr int CH = mac_batch<T, E>();
 #pragma unroll
-    for (int e = 0; e < E; ++e) {
-        cx<T> x = va[e], y = vb[e];
-        va[e] = cmulc(x, sa[e]) + cmulc(y, sc[e]);   // conj(E_r) v_r + conj(E_p) v_p
-        vb[e] = cmulc(x, sb[e]) + cmulc(y, sd[e]);   // conj(Q_r) v_r + conj(Q_p) v_p
+    for (int cb = 0; cb < E; cb += CH) {
+        cx<T> sa[CH], sb[CH], sc[CH], sd[CH], uu[CH], vv[CH];
+#pragma unroll
+        for (int j = 0; j < CH; ++j) {
+            const int ku = t + (cb + j) * TH;
+            sa[j] = spec_at<T, L>(er, ku, false);
+            sb[j] = spec_at<T, L>(qr, ku, false);
+            sc[j] = spec_at<T, L>(ep, ku, !is0);
+            sd[j] = spec_at<T, L>(qp, ku, !is0);
+            uu[j] = twL[ku];
+            vv[j] = twL[(int)(((unsigned)n_r * (unsigned)ku) & (unsigned)(L - 1))];
+        }
+#pragma unroll
+        for (int j = 0; j < CH; ++j) {
+            const int e = cb + j;
+            cx<T> x, r;
+            if (is0) {
+                // bins 0 and M of the packed column; V_p's bins 0 and M do
+                // not enter (the azimuthal spectra vanish there)
+                const cx<T> m = lds.ld((L - (t + e * TH)) & (L - 1));
+                const cx<T> A = unpack_even(va[e], m), B = unpack_odd(va[e], m);
+                const cx<T> x0 = cmulc(A, sa[j]), xM = cmulc(B, sc[j]);
+                const cx<T> r0 = cmulc(A, sb[j]), rM = cmulc(B, sd[j]);
+                x = cx<T>{x0.x - xM.y, x0.y + xM.x};
+                r = cx<T>{r0.x - rM.y, r0.y + rM.x};
+            } else {
+                x = cmulc(va[e], sa[j]) + cmulc(vb[e], sc[j]);   // conj(E'_r) V_r + conj(E'_p) V_p
+                r = cmulc(va[e], sb[j]) + cmulc(vb[e], sd[j]);   // conj(Q_r) V_r + conj(Q_p) V_p
+            }
+            va[e] = x;
+            const cx<T> rv = cmulc(r, vv[j]);
+            w[0] = w[0] + r;
+            w[1] = w[1] + cmul(r, uu[j]);
+            w[2] = w[2] + rv;
+            w[3] = w[3] + cmul(rv, uu[j]);
+        }
     }
+    if (packed) __syncthreads();
+    column_sums<T, 4>(w, G, buf);
     fft_inv<L, E, T>(va, t, lds, tw);
-    fft_inv<L, E, T>(vb, t, lds, tw);
-    // transposed stencil on the slope channel
-#pragma unroll
-    for (int e = 0; e < E; ++e) {
-        const int i = t + e * TH;
-        if (i < n_r) lds.st(i, vb[e]);
-    }
-    __syncthreads();
     if (valid) {
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             const int i = t + e * TH;
             if (i < n_r) {
+                // transposed four-row correction
                 cx<T> acc = va[e];
-                if (i >= 1) acc = acc + scale(lds.ld(i - 1), i == 1 ? c0 : ca);
-                if (i <= n_r - 2) acc = acc - scale(lds.ld(i + 1), i == n_r - 2 ? cn : ca);
-                if (i == 0) acc = acc - scale(lds.ld(0), c0);
-                if (i == n_r - 1) acc = acc + scale(lds.ld(n_r - 1), cn);
+                if (i == 0) acc = acc - scale(w[0], c0) - scale(w[1], ca);
+                if (i == 1) acc = acc + scale(w[0], c0 - ca);
+                if (i == n_r - 2) acc = acc + scale(w[3], ca - cn);
+                if (i == n_r - 1) acc = acc + scale(w[3], cn) + scale(w[2], ca);
                 D[(size_t)i * H + col] = acc;
             }
         }

@@ -72,11 +72,15 @@ Schedule default_schedule(int n_phi, int L, bool f64) {
         s.rows.G = th >= 256 ? 1 : 256 / th;
         while (s.rows.G > 1 && !valid_shape_rows(M, s.rows, f64)) s.rows.G /= 2;
     }
-    s.cols.E = L >= 4096 ? 16 : 8;
-    {
-        const int th = L / s.cols.E;
-        s.cols.G = th >= 256 ? 1 : 256 / th;
-        while (s.cols.G > 1 && !valid_shape_cols(L, s.cols, f64)) s.cols.G /= 2;
+    // column pass: 16 points per thread in FP32 from L = 2048 on (fewer LDS
+    // exchanges, two columns per workgroup), 8 otherwise; the transpose pass
+    // holds two input channels and takes 8
+    s.cols.E = (!f64 && L >= 2048) || L >= 4096 ? 16 : 8;
+    s.cols_adj.E = L >= 4096 ? 16 : 8;
+    for (Shape *c : {&s.cols, &s.cols_adj}) {
+        const int th = L / c->E;
+        c->G = th >= 256 ? 1 : 256 / th;
+        while (c->G > 1 && !valid_shape_cols(L, *c, f64)) c->G /= 2;
     }
     return s;
 }
@@ -162,7 +166,7 @@ int backward_t(const Plan &p, const T *gr, const T *gp, T *gs, hipStream_t st) {
     int rc = pf::launch_rows_r2c<T>(p, gr, gp, 2, p.n_r, Vr, Vp, (const C *)p.twN, p.sched.rows,
                                     st);
     if (rc) return rc;
-    rc = pf::launch_cols_adj<T>(p, Vr, Vp, D, (const C *)p.spec, (const C *)p.twL, p.sched.cols,
+    rc = pf::launch_cols_adj<T>(p, Vr, Vp, D, (const C *)p.spec, (const C *)p.twL, p.sched.cols_adj,
                                 st);
     if (rc) return rc;
     return pf::launch_rows_c2r<T>(p, D, nullptr, 1, p.n_r, gs, nullptr, (const C *)p.twN,
@@ -173,35 +177,41 @@ int backward_t(const Plan &p, const T *gr, const T *gp, T *gs, hipStream_t st) {
 // after them.
 template <typename T>
 int timed_t(const Plan &p, bool bwd, const void *in0, const void *in1, void *out0, void *out1,
-            hipStream_t st, hipEvent_t *ev) {
+            int reps, hipStream_t st, hipEvent_t *ev) {
     using C = pf::cx<T>;
     C *A = (C *)p.ws;
     C *B = A + (size_t)p.n_r * p.H;
     C *Cc = B + (size_t)p.n_r * p.H;
-    int rc;
+    int rc = PF_OK;
     PF_HIP(hipEventRecord(ev[0], st));
-    if (!bwd)
-        rc = pf::launch_rows_r2c<T>(p, (const T *)in0, nullptr, 1, p.n_r, A, nullptr,
-                                    (const C *)p.twN, p.sched.rows, st);
-    else
-        rc = pf::launch_rows_r2c<T>(p, (const T *)in0, (const T *)in1, 2, p.n_r, A, B,
-                                    (const C *)p.twN, p.sched.rows, st);
+    for (int k = 0; k < reps && !rc; ++k) {
+        if (!bwd)
+            rc = pf::launch_rows_r2c<T>(p, (const T *)in0, nullptr, 1, p.n_r, A, nullptr,
+                                        (const C *)p.twN, p.sched.rows, st);
+        else
+            rc = pf::launch_rows_r2c<T>(p, (const T *)in0, (const T *)in1, 2, p.n_r, A, B,
+                                        (const C *)p.twN, p.sched.rows, st);
+    }
     if (rc) return rc;
     PF_HIP(hipEventRecord(ev[1], st));
-    if (!bwd)
-        rc = pf::launch_cols_fwd<T>(p, A, B, Cc, (const C *)p.spec, (const C *)p.twL,
-                                    p.sched.cols, st);
-    else
-        rc = pf::launch_cols_adj<T>(p, A, B, Cc, (const C *)p.spec, (const C *)p.twL,
-                                    p.sched.cols, st);
+    for (int k = 0; k < reps && !rc; ++k) {
+        if (!bwd)
+            rc = pf::launch_cols_fwd<T>(p, A, B, Cc, (const C *)p.spec, (const C *)p.twL,
+                                        p.sched.cols, st);
+        else
+            rc = pf::launch_cols_adj<T>(p, A, B, Cc, (const C *)p.spec, (const C *)p.twL,
+                                        p.sched.cols_adj, st);
+    }
     if (rc) return rc;
     PF_HIP(hipEventRecord(ev[2], st));
-    if (!bwd)
-        rc = pf::launch_rows_c2r<T>(p, B, Cc, 2, p.n_r, (T *)out0, (T *)out1, (const C *)p.twN,
-                                    p.sched.rows, st);
-    else
-        rc = pf::launch_rows_c2r<T>(p, Cc, nullptr, 1, p.n_r, (T *)out0, nullptr,
-                                    (const C *)p.twN, p.sched.rows, st);
+    for (int k = 0; k < reps && !rc; ++k) {
+        if (!bwd)
+            rc = pf::launch_rows_c2r<T>(p, B, Cc, 2, p.n_r, (T *)out0, (T *)out1,
+                                        (const C *)p.twN, p.sched.rows, st);
+        else
+            rc = pf::launch_rows_c2r<T>(p, Cc, nullptr, 1, p.n_r, (T *)out0, nullptr,
+                                        (const C *)p.twN, p.sched.rows, st);
+    }
     if (rc) return rc;
     PF_HIP(hipEventRecord(ev[3], st));
     return PF_OK;
@@ -246,7 +256,7 @@ pf_plan pf_plan_create(int n_r, int n_phi, double r_min, double r_max) {
     p.n_r = n_r;
     p.n_phi = n_phi;
     p.M = n_phi / 2;
-    p.H = n_phi / 2 + 1;
+    p.H = n_phi / 2;   // packed half spectrum: bins 0 and n_phi/2 share column 0
     int L = 8;
     while (L < 2 * n_r) L *= 2;  // zero padding: any L >= 2 n_r - 1 is exact
     p.L = L;
@@ -302,6 +312,26 @@ int pf_plan_selfcell(pf_plan h, double out[3]) {
         return PF_ESTATE;
     }
     for (int q = 0; q < 3; ++q) out[q] = h->p.selfk[q];
+    return PF_OK;
+}
+
+int pf_plan_schedule(pf_plan h, int out[6]) {
+    pf::clear_error();
+    if (!h || !out) {
+        pf::set_error("null argument");
+        return PF_EINVAL;
+    }
+    if (!h->p.built) {
+        pf::set_error("plan not built");
+        return PF_ESTATE;
+    }
+    const pf::Schedule &s = h->p.sched;
+    out[0] = s.rows.E;
+    out[1] = s.rows.G;
+    out[2] = s.cols.E;
+    out[3] = s.cols.G;
+    out[4] = s.cols_adj.E;
+    out[5] = s.cols_adj.G;
     return PF_OK;
 }
 
@@ -409,12 +439,16 @@ int pf_forces_backward(pf_plan h, const void *g_fr, const void *g_fphi, void *g_
 }
 
 int pf_forces_timed(pf_plan h, int backward, const void *in0, const void *in1, void *out0,
-                    void *out1, void *stream, float *pass_ms) {
+                    void *out1, int reps, void *stream, float *pass_ms) {
     pf::clear_error();
     int rc = check_call(h, in0, out0, pass_ms);
     if (rc) return rc;
     if ((backward && !in1) || (!backward && !out1)) {
         pf::set_error("null field pointer");
+        return PF_EINVAL;
+    }
+    if (reps < 1 || reps > 10000) {
+        pf::set_error("reps = %d outside [1, 10000]", reps);
         return PF_EINVAL;
     }
     const Plan &p = h->p;
@@ -429,11 +463,14 @@ int pf_forces_timed(pf_plan h, int backward, const void *in0, const void *in1, v
         }
     }
     rc = p.opts.dtype == PF_F64
-             ? timed_t<double>(p, backward != 0, in0, in1, out0, out1, st, ev)
-             : timed_t<float>(p, backward != 0, in0, in1, out0, out1, st, ev);
+             ? timed_t<double>(p, backward != 0, in0, in1, out0, out1, reps, st, ev)
+             : timed_t<float>(p, backward != 0, in0, in1, out0, out1, reps, st, ev);
     if (!rc) {
         hipError_t e = hipEventSynchronize(ev[3]);
-        for (int k = 0; k < 3 && e == hipSuccess; ++k) e = hipEventElapsedTime(&pass_ms[k], ev[k], ev[k + 1]);
+        for (int k = 0; k < 3 && e == hipSuccess; ++k) {
+            e = hipEventElapsedTime(&pass_ms[k], ev[k], ev[k + 1]);
+            pass_ms[k] /= (float)reps;
+        }
         if (e != hipSuccess) {
             pf::set_error("event timing: %s", hipGetErrorString(e));
             rc = PF_EHIP;

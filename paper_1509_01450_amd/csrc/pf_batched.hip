@@ -456,14 +456,18 @@ void tune_t(Plan &p, hipStream_t st) {
                              std::to_string(2 * p.n_r);
     const std::string kcol = pre + "cols|L=" + std::to_string(p.L) + "|H=" + std::to_string(p.H) +
                              "|n_r=" + std::to_string(p.n_r);
+    const std::string kadj = pre + "adj|L=" + std::to_string(p.L) + "|H=" + std::to_string(p.H) +
+                             "|n_r=" + std::to_string(p.n_r);
     {
         std::lock_guard<std::mutex> g(g_tune_mu);
         load_cache();
-        auto a = g_tune.find(krow), b = g_tune.find(kcol);
-        if (a != g_tune.end() && b != g_tune.end() && valid_shape_rows(p.M, a->second, f64) &&
-            valid_shape_cols(p.L, b->second, f64)) {
+        auto a = g_tune.find(krow), b = g_tune.find(kcol), c = g_tune.find(kadj);
+        if (a != g_tune.end() && b != g_tune.end() && c != g_tune.end() &&
+            valid_shape_rows(p.M, a->second, f64) && valid_shape_cols(p.L, b->second, f64) &&
+            valid_shape_cols(p.L, c->second, f64)) {
             p.sched.rows = a->second;
             p.sched.cols = b->second;
+            p.sched.cols_adj = c->second;
             return;
         }
     }
@@ -477,7 +481,7 @@ void tune_t(Plan &p, hipStream_t st) {
     (void)hipEventCreate(&e0);
     (void)hipEventCreate(&e1);
     // rows: forward R2C of n_r rows + inverse C2R of 2 n_r rows
-    Shape best_r = p.sched.rows, best_c = p.sched.cols;
+    Shape best_r = p.sched.rows, best_c = p.sched.cols, best_a = p.sched.cols_adj;
     float tbest = 1e30f;
     for (int E : {4, 8, 16})
         for (int thr : {64, 128, 256, 512}) {
@@ -517,6 +521,23 @@ void tune_t(Plan &p, hipStream_t st) {
                 best_c = s;
             }
         }
+    tbest = 1e30f;
+    for (int E : {8, 16})
+        for (int thr : {64, 128, 256, 512}) {
+            if (E > p.L || (p.L / E) > thr) continue;
+            Shape s{E, thr / (p.L / E)};
+            if (!valid_shape_cols(p.L, s, f64)) continue;
+            float t = time_ms(
+                [&]() {
+                    return launch_cols_adj<T>(p, S, Zr, Zp, (const C *)p.spec, (const C *)p.twL,
+                                              s, st);
+                },
+                st, e0, e1);
+            if (t > 0 && t < tbest) {
+                tbest = t;
+                best_a = s;
+            }
+        }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     (void)hipStreamSynchronize(st);
@@ -524,9 +545,11 @@ void tune_t(Plan &p, hipStream_t st) {
     clear_error();
     p.sched.rows = best_r;
     p.sched.cols = best_c;
+    p.sched.cols_adj = best_a;
     std::lock_guard<std::mutex> g(g_tune_mu);
     g_tune[krow] = best_r;
     g_tune[kcol] = best_c;
+    g_tune[kadj] = best_a;
     save_cache();
 }
 

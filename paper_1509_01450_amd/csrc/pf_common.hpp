@@ -34,11 +34,15 @@ struct Shape {
 
 // Schedule of a plan: launch shapes of the three passes for its sizes.
 struct Schedule {
-    Shape rows;   // row transforms along phi (length n_phi, half-length M)
-    Shape cols;   // column transforms along u (length L)
+    Shape rows;       // row transforms along phi (length n_phi, half-length M)
+    Shape cols;       // forward column pass along u (length L)
+    Shape cols_adj;   // transpose column pass along u
 };
 
 struct Plan {
+    // M = n_phi / 2; H = M stored columns of the packed half spectrum (column
+    // 0 holds the real bins 0 and M); L = transform length along u; ldspec =
+    // L / 2 + 1 stored k_u per spectrum column
     int n_r = 0, n_phi = 0, M = 0, H = 0, L = 0, ldspec = 0;
     double r_min = 0, r_max = 0, beta = 0, dphi = 0;
     // radial slope coefficients of g = r delta^r (interior, first, last row)
@@ -68,8 +72,8 @@ int launch_rows_r2c(const Plan &p, const T *in0, const T *in1, int n_arr, int n_
 template <typename T>
 int launch_rows_c2r(const Plan &p, const cx<T> *in0, const cx<T> *in1, int n_arr,
                     int n_rows, T *out0, T *out1, const cx<T> *twN, Shape s, hipStream_t st);
-// Column pass of the forward map (fused radial slope, u-FFTs, spectral
-// multiply-accumulate, inverse u-FFTs, crop).
+// Column pass of the forward map (u-FFT, spectral multiply-accumulate with
+// the spectral radial slope, inverse u-FFTs, crop).
 template <typename T>
 int launch_cols_fwd(const Plan &p, const cx<T> *S, cx<T> *Zr, cx<T> *Zp, const cx<T> *spec,
                     const cx<T> *twL, Shape s, hipStream_t st);

@@ -389,72 +389,82 @@ __global__ __launch_bounds__(256) void k_cover_final(const double *__restrict__ 
 
 // ---------------------------------------------------------------------------
 // Column transforms of the row-transformed tables and the fold into the four
-// spectra.  rowspec: [6][L][H] complex FP64.  spec: [4][H][ldspec].
-// One column per block, L/E threads.
+// spectra.  rowspec: [6][L][M] complex FP64 in the packed half spectrum
+// (column 0 = (bin 0, bin M)).  spec: [4][M][ldspec].
+// One block per azimuthal bin kb in [0, M] (bins 0 and M read the real and
+// imaginary parts of packed column 0), L/E threads.  With s = 1/(L n_phi),
+// sk = sin(2 pi kb / n_phi) / dphi (the azimuthal central difference) and
+// D(k) = 2i ca sin(2 pi k / L) (the circular radial central difference):
+//   Q_r  = s FFT(beta^m T_rr)         E_r = s (FFT(T_r0) + i sk FFT(T_rphi))
+//   Q_p  = s FFT(beta^m T_phir)       E_p = s (FFT(T_phi0) + i sk FFT(T_phiphi))
+//   E'   = E + D Q
+// Bins 1..M-1 store (E'_r, Q_r, E'_p, Q_p) in their column; bin 0 stores
+// (E'_r, Q_r) in slots 0, 1 of column 0 and bin M in slots 2, 3 (the
+// azimuthal spectra vanish at both: the kernels K^{phi,*} are odd in phi).
 // ---------------------------------------------------------------------------
 template <int L, int E>
-__global__ __launch_bounds__(512) void k_fold(const cx<double> *__restrict__ rowspec, int H,
+__global__ __launch_bounds__(512) void k_fold(const cx<double> *__restrict__ rowspec, int M,
                                               int n_r, int n_phi, double lnb, double dphi,
-                                              cx<double> *__restrict__ spec, int ldspec,
-                                              const cx<double> *__restrict__ twL) {
+                                              double ca, cx<double> *__restrict__ spec,
+                                              int ldspec, const cx<double> *__restrict__ twL) {
     constexpr int TH = L / E;
     extern __shared__ unsigned char smem_raw[];
     cx<double> *buf = reinterpret_cast<cx<double> *>(smem_raw);
-    const int col = blockIdx.x, t = threadIdx.x;
+    const int kb = blockIdx.x, t = threadIdx.x;
+    const int src = kb == M ? 0 : kb;
+    const int part = kb == 0 ? 1 : (kb == M ? 2 : 0);   // 1: real, 2: imaginary part of column 0
     Lds<double> lds{buf, 0, 1};
     Twiddles<L, E, double> tw;
     tw.load(t, twL, 1);
     const double sc = 1.0 / ((double)L * (double)n_phi);
-    const double sk = sin(2.0 * M_PI * col / n_phi) / dphi;
+    const double sk = sinpi(2.0 * kb / n_phi) / dphi;
 
     auto load = [&](int tab, bool bscale, cx<double>(&v)[E]) {
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             const int row = t + e * TH;
-            cx<double> x = rowspec[((size_t)tab * L + row) * H + col];
+            cx<double> x = rowspec[((size_t)tab * L + row) * M + src];
+            if (part == 1) x = cx<double>{x.x, 0.0};
+            if (part == 2) x = cx<double>{x.y, 0.0};
             if (bscale) {
                 const int m = row < n_r ? row : row - L;
-                const double f = exp(m * lnb);
-                x = scale(x, f);
+                x = scale(x, exp(m * lnb));
             }
             v[e] = x;
         }
         fft_fwd<L, E, double>(v, t, lds, tw);
     };
-    auto store = [&](int which, const cx<double>(&v)[E]) {
-        cx<double> *dst = spec + ((size_t)which * H + col) * ldspec;
+    auto store = [&](int slot, const cx<double>(&v)[E]) {
+        cx<double> *dst = spec + ((size_t)slot * M + src) * ldspec;
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             const int ku = t + e * TH;
             if (ku <= L / 2) dst[ku] = v[e];
         }
     };
-    cx<double> a[E], b[E];
-    // E_r
-    load(0, false, a);
-    load(2, false, b);
+    // (E', Q) of one channel from the tables (t0, tr, tphi)
+    auto channel = [&](int t0, int tr, int tphi, int slot_e, int slot_q) {
+        cx<double> q[E], a[E], b[E];
+        load(tr, true, q);
+        load(t0, false, a);
+        load(tphi, false, b);
 #pragma unroll
-    for (int e = 0; e < E; ++e)
-        a[e] = cx<double>{(a[e].x - sk * b[e].y) * sc, (a[e].y + sk * b[e].x) * sc};
-    store(0, a);
-    // Q_r
-    load(1, true, a);
-#pragma unroll
-    for (int e = 0; e < E; ++e) a[e] = scale(a[e], sc);
-    store(1, a);
-    // E_p
-    load(3, false, a);
-    load(5, false, b);
-#pragma unroll
-    for (int e = 0; e < E; ++e)
-        a[e] = col == 0 ? cx<double>{0.0, 0.0}
-                        : cx<double>{(a[e].x - sk * b[e].y) * sc, (a[e].y + sk * b[e].x) * sc};
-    store(2, a);
-    // Q_p
-    load(4, true, a);
-#pragma unroll
-    for (int e = 0; e < E; ++e) a[e] = col == 0 ? cx<double>{0.0, 0.0} : scale(a[e], sc);
-    store(3, a);
+        for (int e = 0; e < E; ++e) {
+            const int ku = t + e * TH;
+            const double d = 2.0 * ca * sinpi(2.0 * ku / L);
+            const cx<double> qe = scale(q[e], sc);
+            const cx<double> ee = {(a[e].x - sk * b[e].y) * sc, (a[e].y + sk * b[e].x) * sc};
+            a[e] = cx<double>{ee.x - d * qe.y, ee.y + d * qe.x};   // E + i d Q
+            q[e] = qe;
+        }
+        store(slot_e, a);
+        store(slot_q, q);
+    };
+    if (part == 2)
+        channel(0, 1, 2, 2, 3);       // bin M radial spectra into column 0, slots 2, 3
+    else
+        channel(0, 1, 2, 0, 1);
+    if (part == 0) channel(3, 4, 5, 2, 3);
 }
 
 __global__ void k_to_f32(const cx<double> *__restrict__ in, cx<float> *__restrict__ out, long n) {
@@ -473,8 +483,9 @@ int fold_launch(const cx<double> *rowspec, const Plan &p, cx<double> *spec,
         if (lds > 64 * 1024)
             PF_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(k_fold<L, E>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-        hipLaunchKernelGGL((k_fold<L, E>), dim3(p.H), dim3(L / E), lds, st, rowspec, p.H, p.n_r,
-                           p.n_phi, std::log(p.beta), p.dphi, spec, p.ldspec, twL);
+        hipLaunchKernelGGL((k_fold<L, E>), dim3(p.M + 1), dim3(L / E), lds, st, rowspec, p.M,
+                           p.n_r, p.n_phi, std::log(p.beta), p.dphi, p.ca, spec, p.ldspec,
+                           twL);
         PF_HIP(hipGetLastError());
         return PF_OK;
     }
@@ -564,7 +575,7 @@ int build_tables_and_spectra(Plan &p, hipStream_t st) {
     if (rc) return rc;
     rc = upload_twiddles(p.L, true, &twL64.p);
     if (rc) return rc;
-    PF_HIP(hipMalloc(&rowspec.p, (size_t)6 * p.L * p.H * sizeof(cx<double>)));
+    PF_HIP(hipMalloc(&rowspec.p, (size_t)6 * p.L * p.M * sizeof(cx<double>)));
     {
         Shape s = default_schedule(p.n_phi, p.L, true).rows;
         rc = launch_rows_r2c<double>(p, (const double *)tab.p, nullptr, 1, 6 * p.L,
@@ -572,7 +583,7 @@ int build_tables_and_spectra(Plan &p, hipStream_t st) {
                                      (const cx<double> *)twN64.p, s, st);
         if (rc) return rc;
     }
-    const size_t nspec = (size_t)4 * p.H * p.ldspec;
+    const size_t nspec = (size_t)4 * p.M * p.ldspec;
     PF_HIP(hipMalloc(&spec64.p, nspec * sizeof(cx<double>)));
     rc = fold_dispatch((const cx<double> *)rowspec.p, p, (cx<double> *)spec64.p,
                        (const cx<double> *)twL64.p, st);
