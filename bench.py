@@ -11,11 +11,16 @@ roofline of the dominant kernel (the fused column pass) and the FP64 CPU
 oracle timed on the host's cores.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
-Prints one JSON line on stdout.
+                       [--no-batched] [--forward-only] [--copy-reference]
+--forward-only runs only the FP32 forward (headline, pass times, roofline),
+for profiler runs; --copy-reference adds five 64 MiB device-to-device copies
+at the end, the known-size reference that calibrates the FETCH_SIZE and
+WRITE_SIZE counters.  Prints one JSON line on stdout.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -28,6 +33,46 @@ if ROOT not in sys.path:
 METRIC = "cells/s for F_r+F_phi at 1024x2048 (FP32 vs FP64, same GPU); backward cells/s"
 N_R, N_PHI, R_MIN, R_MAX = 1024, 2048, 0.01, 100.0
 HBM_PEAK_GBS = 8000.0
+
+
+# Counter summary of the dominant kernel (FETCH_SIZE / WRITE_SIZE per
+# dispatch with their copy-kernel calibration) and the sources it depends on.
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_cols_fwd_f32_1024x2048_traffic.txt")
+KERNEL_SOURCES = ("paper_1509_01450_amd/csrc/fft_core.hpp",
+                  "paper_1509_01450_amd/csrc/pass_bodies.hpp",
+                  "paper_1509_01450_amd/csrc/pf_passes.hip")
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(cols_shape):
+    """HBM bytes per launch of the dominant kernel from the committed counter
+    summary, or None when the kernel sources or its launch shape differ from
+    those the counters were taken with."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            lines = fh.read().splitlines()
+    except OSError:
+        return None
+    kv = {}
+    for line in lines:
+        if ":" in line and not line.startswith(("#", " ", "|")):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    try:
+        if kv["source_hash"] != kernel_source_hash():
+            return None
+        if [int(x) for x in kv["cols_E_G"].split(",")] != list(cols_shape):
+            return None
+        return float(kv["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def log(*a):
@@ -126,6 +171,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--forward-only", action="store_true")
+    ap.add_argument("--copy-reference", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the single-disk and batched paths run on "
@@ -166,6 +213,33 @@ def main():
     L = p32_L = 2 * N_R
     bA, bB, bC = path_bytes(N_R, N_PHI, p32_L, 4)
     achieved = bB / (passes32[1] * 1e-3) / 1e9
+
+    out["value"] = cells / (ms32 * 1e-3)
+    out["ms_per_step"] = ms32
+    out["config"] = {"workload": "single disk log-polar %dx%d, r in [%g, %g], exponential disk "
+                                 "+ 20%% m=2 log spiral, forward F_r+F_phi" % (N_R, N_PHI, R_MIN, R_MAX),
+                     "n_r": N_R, "n_phi": N_PHI, "L_u": L, "n_tpz": 19, "precision":
+                     "FP32 FFT + spectral multiply, FP64-built kernel spectra"}
+    out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                       "frac": achieved / HBM_PEAK_GBS,
+                       "traffic": measured_traffic(p32.schedule()[2:4])}
+    out["detail"] = {
+        "dominant_kernel": "k_cols_fwd (u-FFT + spectral MAC with spectral radial slope + "
+                           "two inverse u-FFTs)",
+        "dominant_kernel_source_hash": kernel_source_hash(),
+        "step_timing": "K back-to-back pf_forces calls between events on the launch stream",
+        "graph_ms_per_step_fp32": ms32_graph,
+        "graph_cells_per_s_fp32": cells / (ms32_graph * 1e-3),
+        "schedule_fp32": sched(p32),
+        "pass_ms_fp32": passes32, "pass_bytes_fp32": [bA, bB, bC],
+        "pass_GBs_fp32": [b / (t * 1e-3) / 1e9 for b, t in zip((bA, bB, bC), passes32)],
+        "path_bytes_fp32": bA + bB + bC,
+        "path_GBs_fp32": (bA + bB + bC) / (ms32 * 1e-3) / 1e9,
+        "table_build_s": {"fp32": build32},
+    }
+    if args.forward_only:
+        finish(torch, out, args)
+        return 0
 
     # ---- FP64 forward -----------------------------------------------------
     t0 = time.perf_counter()
@@ -212,26 +286,8 @@ def main():
                    "cells": bcells, "ms_per_call": msb, "cells_per_s": bcells / (msb * 1e-3),
                    "table_build_s": build_b}
 
-    out["value"] = cells / (ms32 * 1e-3)
-    out["ms_per_step"] = ms32
-    out["config"] = {"workload": "single disk log-polar %dx%d, r in [%g, %g], exponential disk "
-                                 "+ 20%% m=2 log spiral, forward F_r+F_phi" % (N_R, N_PHI, R_MIN, R_MAX),
-                     "n_r": N_R, "n_phi": N_PHI, "L_u": L, "n_tpz": 19, "precision":
-                     "FP32 FFT + spectral multiply, FP64-built kernel spectra"}
-    out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                       "frac": achieved / HBM_PEAK_GBS, "traffic": None}
-    out["detail"] = {
-        "dominant_kernel": "k_cols_fwd (u-FFT + spectral MAC with spectral radial slope + "
-                           "two inverse u-FFTs)",
-        "step_timing": "K back-to-back pf_forces calls between events on the launch stream",
-        "graph_ms_per_step_fp32": ms32_graph,
-        "graph_cells_per_s_fp32": cells / (ms32_graph * 1e-3),
-        "schedule_fp32": sched(p32),
+    out["detail"].update({
         "schedule_fp64": sched(p64),
-        "pass_ms_fp32": passes32, "pass_bytes_fp32": [bA, bB, bC],
-        "pass_GBs_fp32": [b / (t * 1e-3) / 1e9 for b, t in zip((bA, bB, bC), passes32)],
-        "path_bytes_fp32": bA + bB + bC,
-        "path_GBs_fp32": (bA + bB + bC) / (ms32 * 1e-3) / 1e9,
         "fp64": {"ms_per_call": ms64, "cells_per_s": cells / (ms64 * 1e-3),
                  "pass_ms": passes64,
                  "pass_GBs": [b / (t * 1e-3) / 1e9 for b, t in zip((cA, cB, cC), passes64)],
@@ -239,14 +295,25 @@ def main():
         "backward": {"fp32_ms": msb32, "fp32_cells_per_s": cells / (msb32 * 1e-3),
                      "fp64_ms": msb64, "fp64_cells_per_s": cells / (msb64 * 1e-3),
                      "fp32_pass_ms": passesb32},
-        "table_build_s": {"fp32": build32, "fp64": build64},
         "batched": batched,
-    }
+    })
+    out["detail"]["table_build_s"]["fp64"] = build64
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline()
-    print(json.dumps(out), flush=True)
+    finish(torch, out, args)
     return 0
+
+
+def finish(torch, out, args):
+    if args.copy_reference:
+        log("copy reference: 5 x 64 MiB device-to-device")
+        x = torch.ones(16 * 1024 * 1024, device="cuda:0")
+        y = torch.empty_like(x)
+        for _ in range(5):
+            y.copy_(x)
+        torch.cuda.synchronize()
+    print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":
