@@ -116,11 +116,15 @@ int pf_forces_backward(pf_plan plan, const void *g_fr, const void *g_fphi,
                        void *g_sigma, void *stream);
 
 /* Forward map for n independent disks, each with its own built plan (all of
- * one precision, sizes may differ), in one persistent kernel launch that is
- * captured once per batch signature in a HIP graph and replayed.  Arrays
- * sigma[k], f_r[k], f_phi[k] follow plan[k]'s layout.  Plans of a batch
- * share internal state: do not run two batches with common plans at once.
- * 1 <= n <= 4096.  Asynchronous.                                           */
+ * one precision, sizes may differ), as three launches on `stream` that each
+ * cover every disk (pass A, pass B, pass C).  Arrays sigma[k], f_r[k],
+ * f_phi[k] follow plan[k]'s layout.  Sizes: 128 <= n_phi <= 4096 and
+ * 33 <= n_r <= 2048 (FP32) or 1024 (FP64); other plans give
+ * PF_EUNSUPPORTED.  A plan may appear once per batch (PF_EINVAL otherwise).
+ * Plans of a batch share internal state: do not run two batches with common
+ * plans at once.  The first call for a set of plans, and a call whose field
+ * pointers differ from the previous call's, waits for a small table upload;
+ * otherwise asynchronous.  1 <= n <= 4096.                                  */
 int pf_forces_batched(int n, const pf_plan *plans, const void *const *sigma,
                       void *const *f_r, void *const *f_phi, void *stream);
 

@@ -276,7 +276,7 @@ class Plan:
 
 
 def forces_batched(plans, sigmas, outs=None):
-    """Forward map of many disks (one persistent launch from a cached graph)."""
+    """Forward map of many disks (three launches covering every disk)."""
     import torch
     if outs is None:
         outs = [(torch.empty_like(s), torch.empty_like(s)) for s in sigmas]

@@ -1,21 +1,17 @@
-// pf_batched.hip -- the many-disk forward map as one persistent launch, and
+// pf_batched.hip -- the many-disk forward map as three grouped launches, and
 // the launch-shape autotuner.
 //
-// Batched path.  Every disk contributes work items (disk, pass, unit): pass A
-// units (G rows of the phi transform), pass B units (G columns of the fused
-// column pass), pass C units (G rows of the inverse phi transform).  The
-// items of all disks are laid out in one list in dependency order -- every
-// disk's A items, then every disk's B items, then every disk's C items -- and
-// a persistent kernel's workgroups take them in that order from a global
-// ticket counter.  A B item of disk d waits until all A items of d are done,
-// a C item until all B items of d are done (per-disk counters, released with
-// an agent-scope fence after the item's stores).  Because tickets are taken
-// in dependency order, every item waited on was taken earlier by a workgroup
-// that is already running and that itself only waits on earlier items, so
-// the wait always ends; it is also bounded by a spin limit as a safeguard.
-// The reset of the counters and the persistent kernel are captured once per
-// batch signature in a HIP graph and replayed; the per-disk field pointers
-// live in a device descriptor table that is refreshed when they change.
+// Batched path.  The disks of a batch (sizes may differ, one precision) run
+// as three launches, one per pass, each covering every disk: a workgroup
+// handles one unit of one disk -- G rows of the phi transform (pass A or C)
+// or G columns of the column pass (pass B) -- found through a block -> disk
+// table, and selects the body of the disk's transform length with a switch.
+// The launch boundaries order the passes, and every launch fills the device
+// with the units of all disks at the occupancy of the single-disk kernels.
+// Workgroups have 256 threads; rows take 8 points per thread, columns 16
+// (FP32) or 8 (FP64), so G = 256 / (length / points).  The descriptor and
+// block tables are built once per batch signature and refreshed when the
+// field pointers change.
 //
 // Autotuner.  For each transform size and precision, candidate launch
 // shapes (points per thread E -- the radix of the Stockham stages -- and
@@ -39,249 +35,185 @@
 namespace pf {
 
 // ===========================================================================
-// Persistent batched kernel (FP32)
+// Grouped batched kernels
 // ===========================================================================
-constexpr int kBatchThreads = 256;
-constexpr int kBatchE = 8;  // points per thread in every transform of a batch
+constexpr int kGroupThreads = 256;
+constexpr int kRowE = 8;
+template <typename T>
+constexpr int col_e() { return sizeof(T) == 8 ? 8 : 16; }
 
-struct DiskDesc {
-    int n_r, n_phi, H, L, ldspec;
-    int M;        // n_phi / 2
-    int GA, GB;   // rows per A/C unit, columns per B unit
-    int nA, nB;   // number of A and B units (dependency targets)
-    float ca, c0, cn;
-    const float *sigma;
-    float *fr, *fp;
-    cx<float> *S, *Zr, *Zp;
-    const cx<float> *spec, *twN, *twL;
+template <typename T>
+struct GDisk {
+    int n_r, M, L, H, ldspec;
+    int base[3];   // first workgroup of the disk in each pass's launch
+    T ca, c0, cn;
+    const T *sigma;
+    T *fr, *fp;
+    cx<T> *S, *Zr, *Zp;
+    const cx<T> *spec, *twN, *twL;
 };
 
-struct Item {
-    int disk, pass, unit;
-};
-
-struct BatchCtl {
-    int ticket;
-    int timeouts;
-};
-
-// Wait until *ctr >= target.  The loop is uniform over the workgroup: every
-// lane reads the counter with a relaxed agent-scope load (coherent across
-// XCDs, no cache maintenance per poll) and the condition is taken from the
-// first lane, so all waves leave together and see the same barriers.  Once
-// the count is reached every wave performs one agent-scope acquire so the
-// unit's loads see the producers' stores.  (Polling an acquire load would
-// invalidate the XCD's L2 on every iteration.)
-__device__ __forceinline__ void wait_count(int *ctr, int target, long spin_limit, BatchCtl *ctl) {
-    long n = 0;
-    bool timed_out = false;
-    while (__builtin_amdgcn_readfirstlane(
-               __hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) < target) {
-        __builtin_amdgcn_s_sleep(8);
-        if (++n > spin_limit) {
-            timed_out = true;
-            break;
-        }
-    }
-    if (timed_out) atomicAdd(&ctl->timeouts, threadIdx.x == 0 ? 1 : 0);
-    __syncthreads();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-}
-
-// One size path per function (not inlined into the dispatch loop), so each
-// transform size keeps the register allocation it needs alone.
-template <int M>
-__device__ __attribute__((noinline)) void run_rows(const Item &w, const DiskDesc &d, cx<float> *buf) {
-    constexpr int TH = M / kBatchE;
-    constexpr int G = kBatchThreads / TH;
-    if (w.pass == 0)
-        body_rows_r2c<float, M, kBatchE>(w.unit, G, buf, d.sigma, nullptr, d.n_r, d.n_r, d.S,
-                                         nullptr, d.twN);
+template <typename T, int M>
+__device__ __forceinline__ void group_rows(int pass, int unit, const GDisk<T> &d, cx<T> *buf) {
+    constexpr int G = kGroupThreads / (M / kRowE);
+    if (pass == 0)
+        body_rows_r2c<T, M, kRowE>(unit, G, buf, d.sigma, nullptr, d.n_r, d.n_r, d.S, nullptr,
+                                   d.twN);
     else
-        body_rows_c2r<float, M, kBatchE>(w.unit, G, buf, d.Zr, d.Zp, d.n_r, 2 * d.n_r, d.fr, d.fp,
-                                         d.twN);
+        body_rows_c2r<T, M, kRowE>(unit, G, buf, d.Zr, d.Zp, d.n_r, 2 * d.n_r, d.fr, d.fp,
+                                   d.twN);
 }
 
-template <int L>
-__device__ __attribute__((noinline)) void run_cols(const Item &w, const DiskDesc &d, cx<float> *buf) {
-    constexpr int TH = L / kBatchE;
-    constexpr int G = kBatchThreads / TH;
-    body_cols_fwd<float, L, kBatchE>(w.unit, G, buf, d.S, d.Zr, d.Zp, d.spec, d.H, d.n_r,
-                                     d.ldspec, d.ca, d.c0, d.cn, d.twL);
-}
-
-__global__ __launch_bounds__(kBatchThreads) void k_batched(const DiskDesc *__restrict__ disks,
-                                                           const Item *__restrict__ items,
-                                                           int n_items, BatchCtl *ctl,
-                                                           int *doneA, int *doneB,
-                                                           long spin_limit) {
-    __shared__ cx<float> buf[padded_len(kBatchThreads * kBatchE)];
-    __shared__ int s_it;
-    for (;;) {
-        // The dispatch loop is kept free of per-lane branches so that every
-        // wave runs the same sequence of barriers: all lanes take part in
-        // the atomics (only lane 0 of the workgroup adds a nonzero amount)
-        // and the ticket is broadcast as a scalar (readfirstlane).
-        const int tk = atomicAdd(&ctl->ticket, threadIdx.x == 0 ? 1 : 0);
-        if (threadIdx.x == 0) s_it = tk;
-        __syncthreads();
-        const int it = __builtin_amdgcn_readfirstlane(s_it);
-        __syncthreads();  // s_it read by all; LDS of the previous unit released
-        if (it >= n_items) break;
-        const Item w = items[it];
-        const DiskDesc &d = disks[w.disk];
-        if (w.pass == 1) wait_count(&doneA[w.disk], d.nA, spin_limit, ctl);
-        if (w.pass == 2) wait_count(&doneB[w.disk], d.nB, spin_limit, ctl);
-        if (w.pass == 1) {
-            switch (d.L) {
-                case 128: run_cols<128>(w, d, buf); break;
-                case 256: run_cols<256>(w, d, buf); break;
-                case 512: run_cols<512>(w, d, buf); break;
-                case 1024: run_cols<1024>(w, d, buf); break;
-                case 2048: run_cols<2048>(w, d, buf); break;
-            }
-        } else {
-            switch (d.M) {
-                case 64: run_rows<64>(w, d, buf); break;
-                case 128: run_rows<128>(w, d, buf); break;
-                case 256: run_rows<256>(w, d, buf); break;
-                case 512: run_rows<512>(w, d, buf); break;
-                case 1024: run_rows<1024>(w, d, buf); break;
-                case 2048: run_rows<2048>(w, d, buf); break;
-            }
-        }
-        if (w.pass < 2) {
-            // every wave completes and releases its own stores at agent scope
-            // (consumers may run on another XCD), then one lane publishes
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-            __syncthreads();
-            atomicAdd(w.pass == 0 ? &doneA[w.disk] : &doneB[w.disk], threadIdx.x == 0 ? 1 : 0);
-        }
+// Pass A (pass = 0) or C (pass = 2) of every disk: block -> (disk, unit).
+template <typename T>
+__global__ __launch_bounds__(kGroupThreads) void k_group_rows(const GDisk<T> *__restrict__ disks,
+                                                              const int *__restrict__ bdisk,
+                                                              int pass) {
+    __shared__ cx<T> buf[kGroupThreads * kRowE];
+    const GDisk<T> &d = disks[bdisk[blockIdx.x]];
+    const int unit = blockIdx.x - d.base[pass];
+    switch (d.M) {
+        case 64: group_rows<T, 64>(pass, unit, d, buf); break;
+        case 128: group_rows<T, 128>(pass, unit, d, buf); break;
+        case 256: group_rows<T, 256>(pass, unit, d, buf); break;
+        case 512: group_rows<T, 512>(pass, unit, d, buf); break;
+        case 1024: group_rows<T, 1024>(pass, unit, d, buf); break;
+        case 2048: group_rows<T, 2048>(pass, unit, d, buf); break;
     }
 }
 
-__global__ void k_batch_reset(BatchCtl *ctl, int *done, int n) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i == 0) {
-        ctl->ticket = 0;
-        ctl->timeouts = 0;
+template <typename T, int L>
+__device__ __forceinline__ void group_cols(int unit, const GDisk<T> &d, cx<T> *buf) {
+    constexpr int E = col_e<T>();
+    if constexpr (L / E <= kGroupThreads) {
+        constexpr int G = kGroupThreads / (L / E);
+        body_cols_fwd<T, L, E>(unit, G, buf, d.S, d.Zr, d.Zp, d.spec, d.H, d.n_r, d.ldspec, d.ca,
+                               d.c0, d.cn, d.twL);
     }
-    if (i < n) done[i] = 0;
+}
+
+// Pass B of every disk.  Two waves per SIMD: the register budget of the
+// largest column body (the switch holds every size) must not exceed 256.
+template <typename T>
+__global__ __launch_bounds__(kGroupThreads) __attribute__((amdgpu_waves_per_eu(2)))
+void k_group_cols(const GDisk<T> *__restrict__ disks, const int *__restrict__ bdisk) {
+    __shared__ cx<T> buf[kGroupThreads * col_e<T>()];
+    const GDisk<T> &d = disks[bdisk[blockIdx.x]];
+    const int unit = blockIdx.x - d.base[1];
+    switch (d.L) {
+        case 128: group_cols<T, 128>(unit, d, buf); break;
+        case 256: group_cols<T, 256>(unit, d, buf); break;
+        case 512: group_cols<T, 512>(unit, d, buf); break;
+        case 1024: group_cols<T, 1024>(unit, d, buf); break;
+        case 2048: group_cols<T, 2048>(unit, d, buf); break;
+        case 4096: group_cols<T, 4096>(unit, d, buf); break;
+    }
 }
 
 namespace {
 
+// sizes the grouped kernels instantiate (and whose workgroups fit 256 threads)
 bool batch_size_ok(const Plan &p) {
-    return p.opts.dtype == PF_F32 && p.M >= 64 && p.M <= 2048 && p.L >= 128 && p.L <= 2048;
+    const int ec = p.opts.dtype == PF_F64 ? col_e<double>() : col_e<float>();
+    return p.M >= 64 && p.M <= 2048 && p.L >= 128 && p.L <= 4096 &&
+           p.L / ec <= kGroupThreads;
 }
 
 struct BatchEntry {
     std::vector<int64_t> uids;
-    int n = 0, n_items = 0, grid = 0;
-    DiskDesc *d_desc = nullptr;
-    Item *d_items = nullptr;
-    BatchCtl *d_ctl = nullptr;
-    int *d_done = nullptr;
-    std::vector<DiskDesc> h_desc;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
-    int device = -1;
+    int n = 0, device = -1;
+    bool f64 = false;
+    int nblk[3] = {0, 0, 0};
+    std::vector<unsigned char> h_desc;   // GDisk<T>[n]
+    void *d_desc = nullptr;
+    int *d_map = nullptr;                // block -> disk for pass A, B, C in turn
 
     void release() {
-        if (exec) (void)hipGraphExecDestroy(exec);
-        if (graph) (void)hipGraphDestroy(graph);
         if (d_desc) (void)hipFree(d_desc);
-        if (d_items) (void)hipFree(d_items);
-        if (d_ctl) (void)hipFree(d_ctl);
-        if (d_done) (void)hipFree(d_done);
-        exec = nullptr;
-        graph = nullptr;
+        if (d_map) (void)hipFree(d_map);
         d_desc = nullptr;
-        d_items = nullptr;
-        d_ctl = nullptr;
-        d_done = nullptr;
+        d_map = nullptr;
     }
 };
 
 std::mutex g_batch_mu;
 std::map<std::vector<int64_t>, BatchEntry> g_batches;
 
-long spin_limit_env() {
-    const char *s = getenv("PF_BATCH_SPIN_LIMIT");
-    if (s && *s) return atol(s);
-    return 1L << 21;  // about a second of polling: a safeguard, never reached
-}
-
-int make_entry(BatchEntry &e, const std::vector<const Plan *> &plans) {
+template <typename T>
+int make_entry_t(BatchEntry &e, const std::vector<const Plan *> &plans) {
     const int n = (int)plans.size();
-    e.n = n;
-    e.device = plans[0]->device;
-    e.h_desc.resize(n);
-    std::vector<Item> items;
-    std::vector<Item> a, b, c;
+    e.h_desc.assign(sizeof(GDisk<T>) * n, 0);
+    GDisk<T> *desc = reinterpret_cast<GDisk<T> *>(e.h_desc.data());
+    std::vector<int> map[3];
+    constexpr int EC = col_e<T>();
     for (int k = 0; k < n; ++k) {
         const Plan &p = *plans[k];
-        DiskDesc &d = e.h_desc[k];
-        memset(&d, 0, sizeof(d));
+        GDisk<T> &d = desc[k];
         d.n_r = p.n_r;
-        d.n_phi = p.n_phi;
-        d.H = p.H;
-        d.L = p.L;
-        d.ldspec = p.ldspec;
         d.M = p.M;
-        d.GA = kBatchThreads / (p.M / kBatchE);
-        d.GB = kBatchThreads / (p.L / kBatchE);
-        d.nA = (p.n_r + d.GA - 1) / d.GA;
-        d.nB = (p.H + d.GB - 1) / d.GB;
-        d.ca = (float)p.ca;
-        d.c0 = (float)p.c0;
-        d.cn = (float)p.cn;
-        cx<float> *ws = (cx<float> *)p.ws;
+        d.L = p.L;
+        d.H = p.H;
+        d.ldspec = p.ldspec;
+        d.ca = (T)p.ca;
+        d.c0 = (T)p.c0;
+        d.cn = (T)p.cn;
+        cx<T> *ws = (cx<T> *)p.ws;
         d.S = ws;
         d.Zr = ws + (size_t)p.n_r * p.H;
         d.Zp = d.Zr + (size_t)p.n_r * p.H;
-        d.spec = (const cx<float> *)p.spec;
-        d.twN = (const cx<float> *)p.twN;
-        d.twL = (const cx<float> *)p.twL;
-        const int nC = (2 * p.n_r + d.GA - 1) / d.GA;
-        for (int u = 0; u < d.nA; ++u) a.push_back({k, 0, u});
-        for (int u = 0; u < d.nB; ++u) b.push_back({k, 1, u});
-        for (int u = 0; u < nC; ++u) c.push_back({k, 2, u});
+        d.spec = (const cx<T> *)p.spec;
+        d.twN = (const cx<T> *)p.twN;
+        d.twL = (const cx<T> *)p.twL;
+        const int GA = kGroupThreads / (p.M / kRowE);
+        const int GB = kGroupThreads / (p.L / EC);
+        const int units[3] = {(p.n_r + GA - 1) / GA, (p.H + GB - 1) / GB,
+                              (2 * p.n_r + GA - 1) / GA};
+        for (int q = 0; q < 3; ++q) {
+            d.base[q] = (int)map[q].size();
+            map[q].insert(map[q].end(), units[q], k);
+        }
     }
-    items.insert(items.end(), a.begin(), a.end());
-    items.insert(items.end(), b.begin(), b.end());
-    items.insert(items.end(), c.begin(), c.end());
-    e.n_items = (int)items.size();
-    PF_HIP(hipMalloc(&e.d_desc, sizeof(DiskDesc) * n));
-    PF_HIP(hipMalloc(&e.d_items, sizeof(Item) * items.size()));
-    PF_HIP(hipMalloc(&e.d_ctl, sizeof(BatchCtl)));
-    PF_HIP(hipMalloc(&e.d_done, sizeof(int) * 2 * n));
-    PF_HIP(hipMemcpy(e.d_items, items.data(), sizeof(Item) * items.size(), hipMemcpyHostToDevice));
-    // persistent grid: as many workgroups as stay resident
-    int dev = 0, cus = 0, per_cu = 0;
-    PF_HIP(hipGetDevice(&dev));
-    PF_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    PF_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batched, kBatchThreads, 0));
-    if (per_cu < 1) per_cu = 1;
-    e.grid = std::min(e.n_items, cus * per_cu);
-    // capture reset + persistent kernel
-    hipStream_t cs;
-    PF_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
-    hipError_t err = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
-    if (err == hipSuccess) {
-        hipLaunchKernelGGL(k_batch_reset, dim3((2 * n + 255) / 256), dim3(256), 0, cs, e.d_ctl,
-                           e.d_done, 2 * n);
-        hipLaunchKernelGGL(k_batched, dim3(e.grid), dim3(kBatchThreads), 0, cs, e.d_desc,
-                           e.d_items, e.n_items, e.d_ctl, e.d_done, e.d_done + n,
-                           spin_limit_env());
-        err = hipStreamEndCapture(cs, &e.graph);
+    size_t total = 0;
+    for (int q = 0; q < 3; ++q) {
+        e.nblk[q] = (int)map[q].size();
+        total += map[q].size();
     }
-    if (err == hipSuccess) err = hipGraphInstantiate(&e.exec, e.graph, nullptr, nullptr, 0);
-    (void)hipStreamDestroy(cs);
-    if (err != hipSuccess) {
-        set_error("batch graph capture: %s", hipGetErrorString(err));
-        return PF_EHIP;
+    std::vector<int> all;
+    all.reserve(total);
+    for (int q = 0; q < 3; ++q) all.insert(all.end(), map[q].begin(), map[q].end());
+    PF_HIP(hipMalloc(&e.d_desc, e.h_desc.size()));
+    PF_HIP(hipMalloc(&e.d_map, sizeof(int) * total));
+    PF_HIP(hipMemcpy(e.d_map, all.data(), sizeof(int) * total, hipMemcpyHostToDevice));
+    return PF_OK;
+}
+
+template <typename T>
+bool update_pointers(BatchEntry &e, const void *const *sigma, void *const *f_r,
+                     void *const *f_phi) {
+    GDisk<T> *desc = reinterpret_cast<GDisk<T> *>(e.h_desc.data());
+    bool changed = false;
+    for (int k = 0; k < e.n; ++k) {
+        GDisk<T> &d = desc[k];
+        if (d.sigma != sigma[k] || d.fr != f_r[k] || d.fp != f_phi[k]) {
+            d.sigma = (const T *)sigma[k];
+            d.fr = (T *)f_r[k];
+            d.fp = (T *)f_phi[k];
+            changed = true;
+        }
     }
+    return changed;
+}
+
+template <typename T>
+int launch_group(const BatchEntry &e, hipStream_t st) {
+    const GDisk<T> *desc = (const GDisk<T> *)e.d_desc;
+    const int *mA = e.d_map, *mB = mA + e.nblk[0], *mC = mB + e.nblk[1];
+    hipLaunchKernelGGL(k_group_rows<T>, dim3(e.nblk[0]), dim3(kGroupThreads), 0, st, desc, mA, 0);
+    PF_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_group_cols<T>, dim3(e.nblk[1]), dim3(kGroupThreads), 0, st, desc, mB);
+    PF_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_group_rows<T>, dim3(e.nblk[2]), dim3(kGroupThreads), 0, st, desc, mC, 2);
+    PF_HIP(hipGetLastError());
     return PF_OK;
 }
 
@@ -290,12 +222,13 @@ int make_entry(BatchEntry &e, const std::vector<const Plan *> &plans) {
 int batched_forces(const std::vector<const Plan *> &plans, const void *const *sigma,
                    void *const *f_r, void *const *f_phi, hipStream_t st) {
     const int n = (int)plans.size();
+    const bool f64 = plans[0]->opts.dtype == PF_F64;
     std::vector<int64_t> key(n);
     for (int k = 0; k < n; ++k) {
         if (!batch_size_ok(*plans[k])) {
-            set_error("batched path needs FP32 plans with 128 <= n_phi <= 4096 and "
-                      "33 <= n_r <= 1024 (disk %d: %d x %d)",
-                      k, plans[k]->n_r, plans[k]->n_phi);
+            set_error("batched path needs 128 <= n_phi <= 4096 and 33 <= n_r <= %d "
+                      "(disk %d: %d x %d)",
+                      f64 ? 1024 : 2048, k, plans[k]->n_r, plans[k]->n_phi);
             return PF_EUNSUPPORTED;
         }
         key[k] = plans[k]->uid;
@@ -313,7 +246,10 @@ int batched_forces(const std::vector<const Plan *> &plans, const void *const *si
     if (it == g_batches.end()) {
         BatchEntry e;
         e.uids = key;
-        int rc = make_entry(e, plans);
+        e.n = n;
+        e.f64 = f64;
+        e.device = plans[0]->device;
+        int rc = f64 ? make_entry_t<double>(e, plans) : make_entry_t<float>(e, plans);
         if (rc) {
             e.release();
             return rc;
@@ -321,25 +257,16 @@ int batched_forces(const std::vector<const Plan *> &plans, const void *const *si
         it = g_batches.emplace(key, e).first;
     }
     BatchEntry &e = it->second;
-    bool changed = false;
-    for (int k = 0; k < n; ++k) {
-        DiskDesc &d = e.h_desc[k];
-        if (d.sigma != sigma[k] || d.fr != f_r[k] || d.fp != f_phi[k]) {
-            d.sigma = (const float *)sigma[k];
-            d.fr = (float *)f_r[k];
-            d.fp = (float *)f_phi[k];
-            changed = true;
-        }
-    }
+    const bool changed = f64 ? update_pointers<double>(e, sigma, f_r, f_phi)
+                             : update_pointers<float>(e, sigma, f_r, f_phi);
     if (changed) {
-        // the descriptor table is read by the graph at replay time; the host
-        // copy must outlive the transfer, so wait for it
-        PF_HIP(hipMemcpyAsync(e.d_desc, e.h_desc.data(), sizeof(DiskDesc) * n,
-                              hipMemcpyHostToDevice, st));
+        // the launches read the descriptor table; the host copy must outlive
+        // the transfer, so wait for it
+        PF_HIP(hipMemcpyAsync(e.d_desc, e.h_desc.data(), e.h_desc.size(), hipMemcpyHostToDevice,
+                              st));
         PF_HIP(hipStreamSynchronize(st));
     }
-    PF_HIP(hipGraphLaunch(e.exec, st));
-    return PF_OK;
+    return f64 ? launch_group<double>(e, st) : launch_group<float>(e, st);
 }
 
 void batched_forget(int64_t uid) {

@@ -6,8 +6,8 @@
 
 namespace pf {
 
-// Forward map for several plans in one persistent launch replayed from a
-// cached HIP graph.
+// Forward map for several plans of one precision as three grouped launches
+// (pass A, B, C of every disk).
 int batched_forces(const std::vector<const Plan *> &plans, const void *const *sigma,
                    void *const *f_r, void *const *f_phi, hipStream_t st);
 // Drop cached batch state that refers to plan `uid`.

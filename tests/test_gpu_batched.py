@@ -1,5 +1,5 @@
-"""GPU batched path (one persistent launch from a cached HIP graph) against
-the single-disk path and the FP64 oracle."""
+"""GPU batched path (three grouped launches covering every disk) against the
+single-disk path and the FP64 oracle."""
 import sys
 
 import numpy as np
@@ -26,14 +26,14 @@ def _gpu():
     pf.load()
 
 
-def _disks(sizes, r_min=0.01, r_max=100.0):
+def _disks(sizes, r_min=0.01, r_max=100.0, dtype="f32"):
     plans, sig = [], []
     for d, (nr, nphi) in enumerate(sizes):
-        p = pf.Plan(nr, nphi, r_min, r_max, dtype="f32")
+        p = pf.Plan(nr, nphi, r_min, r_max, dtype=dtype)
         rc, _, _ = p.geometry()
         ph = (np.arange(nphi) + 0.5) * (2 * np.pi / nphi)
         plans.append(p)
-        sig.append(torch.tensor(workloads.multiarm_disk(rc, ph, d), dtype=torch.float32,
+        sig.append(torch.tensor(workloads.multiarm_disk(rc, ph, d), dtype=p.torch_dtype,
                                 device="cuda"))
     return plans, sig
 
@@ -62,7 +62,10 @@ def test_two_small_disks():
 
 
 def test_uneven_batch_matches_single_disk_and_oracle():
-    sizes = [(64, 128), (100, 256), (37, 512), (256, 128), (128, 1024), (200, 4096), (1024, 256)]
+    # includes the extremes of the batched size range: n_phi = 128 and 4096,
+    # n_r = 37 (L = 128) and 1500 (L = 4096)
+    sizes = [(64, 128), (100, 256), (37, 512), (256, 128), (128, 1024), (200, 4096), (1024, 256),
+             (1500, 128)]
     plans, sig = _disks(sizes)
     _say("plans built; batched call")
     outs = pf.forces_batched(plans, sig)
@@ -82,6 +85,25 @@ def test_uneven_batch_matches_single_disk_and_oracle():
         ep = np.linalg.norm(fp - fp_o) / np.linalg.norm(fp_o)
         _say("disk %d %s vs oracle rel-L2 F_r %.3e F_phi %.3e" % (k, sizes[k], er, ep))
         assert er <= 1e-5 and ep <= 1e-5
+
+
+def test_fp64_batch_matches_single_disk_and_oracle():
+    sizes = [(64, 128), (37, 512), (300, 256), (1024, 128)]
+    plans, sig = _disks(sizes, dtype="f64")
+    outs = pf.forces_batched(plans, sig)
+    torch.cuda.synchronize()
+    worst = _check_against_single(plans, sig, outs)
+    _say("FP64 batch vs single-disk worst rel-L2 %.3e" % worst)
+    assert worst <= 1e-13
+    k = 1
+    nr, nphi = sizes[k]
+    g = oracle.Grid(nr, nphi, 0.01, 100.0)
+    T = oracle.tables(g, 19)
+    fr_o, fp_o = oracle.forward(g, T, sig[k].cpu().numpy())
+    er = np.linalg.norm(outs[k][0].cpu().numpy() - fr_o) / np.linalg.norm(fr_o)
+    ep = np.linalg.norm(outs[k][1].cpu().numpy() - fp_o) / np.linalg.norm(fp_o)
+    _say("FP64 disk %d %s vs oracle rel-L2 F_r %.3e F_phi %.3e" % (k, sizes[k], er, ep))
+    assert er <= 1e-11 and ep <= 1e-11
 
 
 def test_replays_with_new_buffers():
@@ -138,4 +160,8 @@ def test_batch_argument_errors():
     p3 = pf.Plan(8, 64, 0.1, 10.0, dtype="f32")  # below the batched size range
     with pytest.raises(pf.PFError) as ei:
         pf.forces_batched([p3], [torch.zeros(8, 64, device="cuda")])
+    assert ei.value.code == pf.PF_EUNSUPPORTED
+    p4 = pf.Plan(1500, 128, 0.1, 10.0, dtype="f64")  # L = 4096: beyond the FP64 batch range
+    with pytest.raises(pf.PFError) as ei:
+        pf.forces_batched([p4], [torch.zeros(1500, 128, dtype=torch.float64, device="cuda")])
     assert ei.value.code == pf.PF_EUNSUPPORTED
