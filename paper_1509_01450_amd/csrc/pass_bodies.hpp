@@ -174,8 +174,14 @@ __device__ __forceinline__ cx<T> spec_at(const cx<T> *__restrict__ col, int ku, 
 //   row n      an  = ca c[n-1]
 //   row L - 1  am1 = -ca c0
 // (c0, ca, cn: the first, interior and last row coefficients).  Its
-// transform at k, with u = W^k and v = W^(n k), W = exp(-2 pi i / L), is
-//   a0 + am1 conj(u) + v (an + an1 conj(u)).
+// transform at k, W = exp(-2 pi i / L), is
+//   a0 + am1 W^-k + an W^(n k) + an1 W^((n-1) k).
+// A thread holds k = t + e TH, e < E, with W^(j k) = W^(j t) W^(j e TH) and
+// W^(j e TH) = r((j e) mod E), r(q) = exp(-2 pi i q / E) an E-th root of
+// unity, the same for the whole workgroup.  So per thread
+//   b1 = an W^(n t),  b2 = am1 W^-t,  b3 = an1 W^((n-1) t)
+// and per point
+//   a0 + b1 r(n e) + b2 conj(r(e)) + b3 r((n-1) e).
 // ---------------------------------------------------------------------------
 template <typename T>
 struct SlopeFix {
@@ -193,17 +199,43 @@ __device__ __forceinline__ SlopeFix<T> slope_fix(cx<T> x0, cx<T> x1, cx<T> xm2, 
     return s;
 }
 
+// real or imaginary parts of the coefficients (one bin of packed column 0)
 template <typename T>
-__device__ __forceinline__ cx<T> slope_fix_at(const SlopeFix<T> &s, cx<T> u, cx<T> v) {
-    const cx<T> uc = conj(u);
-    return s.a0 + cmul(s.am1, uc) + cmul(v, s.an + cmul(s.an1, uc));
+__device__ __forceinline__ SlopeFix<T> slope_fix_part(const SlopeFix<T> &s, bool imag) {
+    auto pick = [imag](cx<T> a) { return cx<T>{imag ? a.y : a.x, T(0)}; };
+    return {pick(s.a0), pick(s.am1), pick(s.an), pick(s.an1)};
 }
 
-// the same with real coefficients (one bin of the packed column 0)
 template <typename T>
-__device__ __forceinline__ cx<T> slope_fix_at_real(T a0, T am1, T an, T an1, cx<T> u, cx<T> v) {
-    const cx<T> in = {an + an1 * u.x, -an1 * u.y};
-    return cx<T>{a0 + am1 * u.x, -am1 * u.y} + cmul(v, in);
+struct SlopePhasors {
+    cx<T> a0, b1, b2, b3;
+};
+
+// wt = W^t, wnt = W^(n t), both from the L-point table
+template <typename T>
+__device__ __forceinline__ SlopePhasors<T> slope_phasors(const SlopeFix<T> &s, cx<T> wt,
+                                                         cx<T> wnt) {
+    const cx<T> wtc = conj(wt);
+    return {s.a0, cmul(s.an, wnt), cmul(s.am1, wtc), cmul(s.an1, cmul(wnt, wtc))};
+}
+
+// E-th roots of unity the workgroup needs for point e: r(e), r(n e),
+// r((n-1) e), read from the L-point table (r(q) = W^(q L / E)) at addresses
+// that are the same for every lane
+template <typename T, int L, int E>
+struct Roots {
+    cx<T> r1, rn, rm;
+    __device__ __forceinline__ Roots(const cx<T> *__restrict__ twL, int n, int e) {
+        constexpr int TH = L / E;
+        r1 = twL[(e & (E - 1)) * TH];
+        rn = twL[((n * e) & (E - 1)) * TH];
+        rm = twL[(((n - 1) * e) & (E - 1)) * TH];
+    }
+};
+
+template <typename T, int L, int E>
+__device__ __forceinline__ cx<T> slope_fix_at(const SlopePhasors<T> &p, const Roots<T, L, E> &r) {
+    return p.a0 + cmul(p.b1, r.rn) + cmulc(p.b2, r.r1) + cmul(p.b3, r.rm);
 }
 
 // Transforms of the two real sequences packed as p = c_0 + i c_M, from p and
@@ -255,9 +287,10 @@ __device__ __forceinline__ void body_cols_fwd(int unit, int G, cx<T> *__restrict
         const int i = t + e * TH;
         v[e] = S[(size_t)(i < n_r ? i : n_r - 1) * H + cl];
     }
-    // the four rows entering the slope correction
+    // the four rows entering the slope correction, and the thread's phasors
     const cx<T> x0 = S[cl], x1 = S[(size_t)H + cl];
     const cx<T> xm2 = S[(size_t)(n_r - 2) * H + cl], xm1 = S[(size_t)(n_r - 1) * H + cl];
+    const cx<T> wt = twL[t], wnt = twL[(int)(((unsigned)n_r * (unsigned)t) & (unsigned)(L - 1))];
     Twiddles<L, E, T> tw;
     tw.load(t, twL, 1);
 #pragma unroll
@@ -277,13 +310,19 @@ __device__ __forceinline__ void body_cols_fwd(int unit, int G, cx<T> *__restrict
     const cx<T> *ep = spec + (size_t)(2 * H + cl) * ldspec;
     const cx<T> *qp = spec + (size_t)(3 * H + cl) * ldspec;
     const SlopeFix<T> a = slope_fix(x0, x1, xm2, xm1, ca, c0, cn);
+    const SlopePhasors<T> ph = slope_phasors(a, wt, wnt);
+    SlopePhasors<T> ph0 = ph, phM = ph;
+    if (is0) {   // bins 0 and M of the packed column: real coefficients each
+        ph0 = slope_phasors(slope_fix_part(a, false), wt, wnt);
+        phM = slope_phasors(slope_fix_part(a, true), wt, wnt);
+    }
     constexpr int CH = mac_batch<T, E>();
     cx<T> yr[E], yp[E];
 #pragma unroll
     for (int cb = 0; cb < E; cb += CH) {
-        // spectra and correction twiddles of the batch issued together;
-        // column 0's slots 2, 3 hold bin M's radial (even) spectra
-        cx<T> sa[CH], sb[CH], sc[CH], sd[CH], uu[CH], vv[CH];
+        // spectra of the batch issued together; column 0's slots 2, 3 hold
+        // bin M's radial (even) spectra
+        cx<T> sa[CH], sb[CH], sc[CH], sd[CH];
 #pragma unroll
         for (int j = 0; j < CH; ++j) {
             const int ku = t + (cb + j) * TH;
@@ -291,23 +330,21 @@ __device__ __forceinline__ void body_cols_fwd(int unit, int G, cx<T> *__restrict
             sb[j] = spec_at<T, L>(qr, ku, false);
             sc[j] = spec_at<T, L>(ep, ku, !is0);
             sd[j] = spec_at<T, L>(qp, ku, !is0);
-            uu[j] = twL[ku];
-            vv[j] = twL[(int)(((unsigned)n_r * (unsigned)ku) & (unsigned)(L - 1))];
         }
 #pragma unroll
         for (int j = 0; j < CH; ++j) {
             const int e = cb + j;
+            const Roots<T, L, E> r(twL, n_r, e);
             if (is0) {
                 const cx<T> m = lds.ld((L - (t + e * TH)) & (L - 1));
                 const cx<T> A = unpack_even(v[e], m), B = unpack_odd(v[e], m);
-                const cx<T> f0 = slope_fix_at_real(a.a0.x, a.am1.x, a.an.x, a.an1.x, uu[j], vv[j]);
-                const cx<T> fM = slope_fix_at_real(a.a0.y, a.am1.y, a.an.y, a.an1.y, uu[j], vv[j]);
+                const cx<T> f0 = slope_fix_at(ph0, r), fM = slope_fix_at(phM, r);
                 const cx<T> y0 = cmul(sa[j], A) + cmul(sb[j], f0);
                 const cx<T> yM = cmul(sc[j], B) + cmul(sd[j], fM);
                 yr[e] = cx<T>{y0.x - yM.y, y0.y + yM.x};   // y0 + i yM
                 yp[e] = cx<T>{T(0), T(0)};
             } else {
-                const cx<T> f = slope_fix_at(a, uu[j], vv[j]);
+                const cx<T> f = slope_fix_at(ph, r);
                 yr[e] = cmul(sa[j], v[e]) + cmul(sb[j], f);
                 yp[e] = cmul(sc[j], v[e]) + cmul(sd[j], f);
             }
@@ -421,13 +458,16 @@ __device__ __forceinline__ void body_cols_adj(int unit, int G, cx<T> *__restrict
     const cx<T> *qr = spec + (size_t)(1 * H + cl) * ldspec;
     const cx<T> *ep = spec + (size_t)(2 * H + cl) * ldspec;
     const cx<T> *qp = spec + (size_t)(3 * H + cl) * ldspec;
-    // w[0] = sum R, w[1] = sum R u, w[2] = sum R conj(v), w[3] = sum R conj(v) u:
-    // the unnormalised inverse transform of R at rows 0, L-1, n, n-1
+    // The unnormalised inverse transform of R at rows 0, L-1, n, n-1:
+    //   w[0] = sum R, w[1] = sum R W^k, w[2] = sum R W^(-n k),
+    //   w[3] = sum R W^(-(n-1) k),
+    // summed per thread against the roots (W^(j k) = W^(j t) r(j e)) and
+    // turned into the thread's share with its phasors afterwards.
     cx<T> w[4] = {{T(0), T(0)}, {T(0), T(0)}, {T(0), T(0)}, {T(0), T(0)}};
     constexpr int CH = mac_batch<T, E>();
 #pragma unroll
     for (int cb = 0; cb < E; cb += CH) {
-        cx<T> sa[CH], sb[CH], sc[CH], sd[CH], uu[CH], vv[CH];
+        cx<T> sa[CH], sb[CH], sc[CH], sd[CH];
 #pragma unroll
         for (int j = 0; j < CH; ++j) {
             const int ku = t + (cb + j) * TH;
@@ -435,8 +475,6 @@ __device__ __forceinline__ void body_cols_adj(int unit, int G, cx<T> *__restrict
             sb[j] = spec_at<T, L>(qr, ku, false);
             sc[j] = spec_at<T, L>(ep, ku, !is0);
             sd[j] = spec_at<T, L>(qp, ku, !is0);
-            uu[j] = twL[ku];
-            vv[j] = twL[(int)(((unsigned)n_r * (unsigned)ku) & (unsigned)(L - 1))];
         }
 #pragma unroll
         for (int j = 0; j < CH; ++j) {
@@ -456,14 +494,22 @@ __device__ __forceinline__ void body_cols_adj(int unit, int G, cx<T> *__restrict
                 r = cmulc(va[e], sb[j]) + cmulc(vb[e], sd[j]);   // conj(Q_r) V_r + conj(Q_p) V_p
             }
             va[e] = x;
-            const cx<T> rv = cmulc(r, vv[j]);
+            const Roots<T, L, E> ro(twL, n_r, e);
             w[0] = w[0] + r;
-            w[1] = w[1] + cmul(r, uu[j]);
-            w[2] = w[2] + rv;
-            w[3] = w[3] + cmul(rv, uu[j]);
+            w[1] = w[1] + cmul(r, ro.r1);
+            w[2] = w[2] + cmulc(r, ro.rn);
+            w[3] = w[3] + cmulc(r, ro.rm);
         }
     }
     if (packed) __syncthreads();
+    {
+        const cx<T> wt = twL[t];
+        const cx<T> wnt = twL[(int)(((unsigned)n_r * (unsigned)t) & (unsigned)(L - 1))];
+        const cx<T> wmt = cmulc(wnt, wt);   // W^((n-1) t)
+        w[1] = cmul(w[1], wt);
+        w[2] = cmulc(w[2], wnt);
+        w[3] = cmulc(w[3], wmt);
+    }
     column_sums<T, 4>(w, G, buf);
     fft_inv<L, E, T>(va, t, lds, tw);
     if (valid) {
