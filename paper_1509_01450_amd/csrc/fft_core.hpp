@@ -21,6 +21,13 @@ struct alignas(2 * sizeof(T)) cx {
     T x, y;
 };
 
+// the values of two channels at one point, one aligned 16-byte (FP32) or
+// 32-byte (FP64) access
+template <typename T>
+struct alignas(4 * sizeof(T)) cx2 {
+    cx<T> a, b;
+};
+
 template <typename T>
 __device__ __forceinline__ cx<T> mk(T a, T b) { return cx<T>{a, b}; }
 template <typename T>
@@ -238,13 +245,14 @@ __device__ __forceinline__ void tw_expand(const cx<T> *p, cx<T> *o) {
 }
 
 // ---------------------------------------------------------------------------
-// Stockham stages.  Template parameters: N (length), E (points per thread),
-// NS (span of the stage), OFF (offset of the stage's twiddles).
-// All threads of the workgroup must call this together (it contains
-// __syncthreads()).
+// Stockham stages of NV independent transforms held together, each in its
+// own LDS region, sharing the stage barriers.  Template parameters: N
+// (length), E (points per thread), NS (span of the stage), OFF (offset of the
+// stage's twiddles), NV (number of transforms).  All threads of the
+// workgroup must call this together (it contains __syncthreads()).
 // ---------------------------------------------------------------------------
-template <int N, int E, int NS, int OFF, typename T>
-__device__ __forceinline__ void fft_stages(cx<T> (&v)[E], int t, const Lds<T> &lds,
+template <int N, int E, int NS, int OFF, int NV, typename T>
+__device__ __forceinline__ void fft_stages(cx<T> (&v)[NV][E], int t, const Lds<T> (&lds)[NV],
                                            const Twiddles<N, E, T> &tw) {
     constexpr int TH = N / E;                 // threads per transform
     constexpr int REM = N / NS;
@@ -256,51 +264,85 @@ __device__ __forceinline__ void fft_stages(cx<T> (&v)[E], int t, const Lds<T> &l
     for (int q = 0; q < NB; ++q) {
         const int b = t + q * TH;
         const int k = b & (NS - 1);
-        cx<T> u[R];
+        cx<T> wr[R];
+        if constexpr (NS > 1) tw_expand<R, T>(&tw.w[OFF + q * ilog2c(R)], wr);
 #pragma unroll
-        for (int r = 0; r < R; ++r) u[r] = v[q + r * NB];
-        if constexpr (NS > 1) {
-            cx<T> wr[R];
-            tw_expand<R, T>(&tw.w[OFF + q * ilog2c(R)], wr);
+        for (int a = 0; a < NV; ++a) {
+            cx<T> u[R];
 #pragma unroll
-            for (int r = 1; r < R; ++r) u[r] = cmul(u[r], wr[r]);
-        }
-        dft<R, T>(u);
-        if constexpr (LAST) {
+            for (int r = 0; r < R; ++r) u[r] = v[a][q + r * NB];
+            if constexpr (NS > 1) {
 #pragma unroll
-            for (int r = 0; r < R; ++r) v[q + r * NB] = u[r];
-        } else {
-            const int base = (b - k) * R + k;
+                for (int r = 1; r < R; ++r) u[r] = cmul(u[r], wr[r]);
+            }
+            dft<R, T>(u);
+            if constexpr (LAST) {
 #pragma unroll
-            for (int r = 0; r < R; ++r) lds.st(base + r * NS, u[r]);
+                for (int r = 0; r < R; ++r) v[a][q + r * NB] = u[r];
+            } else {
+                const int base = (b - k) * R + k;
+#pragma unroll
+                for (int r = 0; r < R; ++r) lds[a].st(base + r * NS, u[r]);
+            }
         }
     }
     if constexpr (!LAST) {
         __syncthreads();
 #pragma unroll
-        for (int e = 0; e < E; ++e) v[e] = lds.ld(t + e * TH);
+        for (int a = 0; a < NV; ++a)
+#pragma unroll
+            for (int e = 0; e < E; ++e) v[a][e] = lds[a].ld(t + e * TH);
         __syncthreads();
-        fft_stages<N, E, NS * R, OFF + (NS > 1 ? NB * ilog2c(R) : 0), T>(v, t, lds, tw);
+        fft_stages<N, E, NS * R, OFF + (NS > 1 ? NB * ilog2c(R) : 0), NV, T>(v, t, lds, tw);
     }
 }
 
-// Forward transform (sign -1) in strided order.
+// Forward transforms (sign -1) of NV arrays in strided order.
+template <int N, int E, int NV, typename T>
+__device__ __forceinline__ void fft_fwd(cx<T> (&v)[NV][E], int t, const Lds<T> (&lds)[NV],
+                                        const Twiddles<N, E, T> &tw) {
+    static_assert((N & (N - 1)) == 0 && N >= E && E >= 2, "sizes");
+    fft_stages<N, E, 1, 0, NV, T>(v, t, lds, tw);
+}
+
+// Inverse transforms (sign +1, unnormalised) as conj(F(conj(x))).
+template <int N, int E, int NV, typename T>
+__device__ __forceinline__ void fft_inv(cx<T> (&v)[NV][E], int t, const Lds<T> (&lds)[NV],
+                                        const Twiddles<N, E, T> &tw) {
+#pragma unroll
+    for (int a = 0; a < NV; ++a)
+#pragma unroll
+        for (int e = 0; e < E; ++e) v[a][e].y = -v[a][e].y;
+    fft_stages<N, E, 1, 0, NV, T>(v, t, lds, tw);
+#pragma unroll
+    for (int a = 0; a < NV; ++a)
+#pragma unroll
+        for (int e = 0; e < E; ++e) v[a][e].y = -v[a][e].y;
+}
+
+// Single-array forms (the copies are register renames once inlined).
 template <int N, int E, typename T>
 __device__ __forceinline__ void fft_fwd(cx<T> (&v)[E], int t, const Lds<T> &lds,
                                         const Twiddles<N, E, T> &tw) {
-    static_assert((N & (N - 1)) == 0 && N >= E && E >= 2, "sizes");
-    fft_stages<N, E, 1, 0, T>(v, t, lds, tw);
+    cx<T> vv[1][E];
+    const Lds<T> l[1] = {lds};
+#pragma unroll
+    for (int e = 0; e < E; ++e) vv[0][e] = v[e];
+    fft_fwd<N, E, 1, T>(vv, t, l, tw);
+#pragma unroll
+    for (int e = 0; e < E; ++e) v[e] = vv[0][e];
 }
 
-// Inverse transform (sign +1, unnormalised) as conj(F(conj(x))).
 template <int N, int E, typename T>
 __device__ __forceinline__ void fft_inv(cx<T> (&v)[E], int t, const Lds<T> &lds,
                                         const Twiddles<N, E, T> &tw) {
+    cx<T> vv[1][E];
+    const Lds<T> l[1] = {lds};
 #pragma unroll
-    for (int e = 0; e < E; ++e) v[e].y = -v[e].y;
-    fft_stages<N, E, 1, 0, T>(v, t, lds, tw);
+    for (int e = 0; e < E; ++e) vv[0][e] = v[e];
+    fft_inv<N, E, 1, T>(vv, t, l, tw);
 #pragma unroll
-    for (int e = 0; e < E; ++e) v[e].y = -v[e].y;
+    for (int e = 0; e < E; ++e) v[e] = vv[0][e];
 }
 
 }  // namespace pf

@@ -33,136 +33,176 @@
 // K^{phi,*} are odd in phi - phi'), so column 0 carries the radial spectra
 // of both bins and its F_phi output is zero.
 //
-// Layouts: S, Zr, Zp, Vr, Vp, D are row-major [n_r][M] complex, M = n_phi/2;
-// spectra are [4][M][L/2+1] complex (slots E'_r, Q_r, E'_p, Q_p; for
-// column 0: E'_r, Q_r of bin 0, E'_r, Q_r of bin M), column-contiguous,
-// holding k_u in [0, L/2]; the rest follows from the kernels' symmetry in
-// phi.
+// Layouts: S and D are row-major [n_r][M] complex, M = n_phi/2; the two
+// force channels travel together as row-major [n_r][M] pairs (Zr, Zp) and
+// (Vr, Vp), so one point of both is one 16-byte (FP32) access.  Spectra are
+// [2][M][L/2+1] pairs, (E'_r, Q_r) then (E'_p, Q_p) -- for column 0 the
+// radial pairs of bin 0 and of bin M -- column-contiguous, holding k_u in
+// [0, L/2]; the rest follows from the kernels' symmetry in phi.
 #pragma once
 #include "fft_core.hpp"
 
 namespace pf {
 
 // ---------------------------------------------------------------------------
-// Pass A: real-to-complex transforms of rows of length N = 2M via one
-// M-point complex transform of z[n] = x[2n] + i x[2n+1]; output in the
-// packed half spectrum (bin 0 = (X_0, X_M)).
-// Workgroup: G rows x (M/E) threads; LDS buf: G*padded_len(M) complex.
+// Row transforms along phi.  A real row of N = 2M points goes through one
+// M-point complex transform of z[n] = x[2n] + i x[2n+1]; its spectrum is
+// the packed half spectrum (bin 0 = (X_0, X_M)).  C = 1 or 2 channels: with
+// C = 2 a thread holds the same points of two fields' rows (the two force
+// channels), whose half spectra are stored as pairs.
+// Workgroup: G rows x (M/E) threads; LDS buf: C*G*M complex.
 // ---------------------------------------------------------------------------
-template <typename T, int M, int E>
+template <typename T, int M, int E, int C>
+__device__ __forceinline__ void row_lds(cx<T> *buf, int gi, int G, Lds<T> (&lds)[C]) {
+#pragma unroll
+    for (int c = 0; c < C; ++c) lds[c] = Lds<T>{buf + (size_t)c * G * M, gi * M, 1};
+}
+
+// Pass A: rows of in0 (and in1 for C = 2) -> packed half spectra
+// (out: [n_rows][M] complex for C = 1, [n_rows][M] pairs for C = 2).
+template <typename T, int M, int E, int C>
 __device__ __forceinline__ void body_rows_r2c(int unit, int G, cx<T> *__restrict__ buf,
-                                           const T *__restrict__ in0,
-                                                  const T *__restrict__ in1, int n_rows,
-                                                  int total_rows, cx<T> *__restrict__ out0,
-                                                  cx<T> *__restrict__ out1,
-                                                  const cx<T> *__restrict__ twN) {
+                                              const T *__restrict__ in0,
+                                              const T *__restrict__ in1, int n_rows,
+                                              cx<T> *__restrict__ out,
+                                              const cx<T> *__restrict__ twN) {
     constexpr int TH = M / E;
     constexpr int N = 2 * M;
-    constexpr int H = M;
     const int gi = threadIdx.x / TH, t = threadIdx.x % TH;
     const int row = unit * G + gi;
-    const bool active = row < total_rows;
-    const int arr = active ? row / n_rows : 0;
-    const int i = active ? row % n_rows : 0;   // inactive lanes read row 0
-    const T *x = (arr == 0 ? in0 : in1) + (size_t)i * N;
-    cx<T> *out = (arr == 0 ? out0 : out1) + (size_t)i * H;
-    Lds<T> lds{buf, gi * padded_len(M), 1};
+    const bool active = row < n_rows;
+    const int i = active ? row : 0;   // inactive lanes read row 0
+    Lds<T> lds[C];
+    row_lds<T, M, E, C>(buf, gi, G, lds);
 
     // unconditional loads (in bounds for every lane) so they issue together
-    cx<T> v[E];
-    const cx<T> *xz = reinterpret_cast<const cx<T> *>(x);
+    cx<T> v[C][E];
 #pragma unroll
-    for (int e = 0; e < E; ++e) v[e] = xz[t + e * TH];
+    for (int c = 0; c < C; ++c) {
+        const cx<T> *xz = reinterpret_cast<const cx<T> *>((c == 0 ? in0 : in1) + (size_t)i * N);
+#pragma unroll
+        for (int e = 0; e < E; ++e) v[c][e] = xz[t + e * TH];
+    }
     Twiddles<M, E, T> tw;
     tw.load(t, twN, 2);
 #pragma unroll
-    for (int e = 0; e < E; ++e)
-        if (!active) v[e] = cx<T>{T(0), T(0)};
-    fft_fwd<M, E, T>(v, t, lds, tw);
+    for (int c = 0; c < C; ++c)
 #pragma unroll
-    for (int e = 0; e < E; ++e) lds.st(t + e * TH, v[e]);
+        for (int e = 0; e < E; ++e)
+            if (!active) v[c][e] = cx<T>{T(0), T(0)};
+    fft_fwd<M, E, C, T>(v, t, lds, tw);
+#pragma unroll
+    for (int c = 0; c < C; ++c)
+#pragma unroll
+        for (int e = 0; e < E; ++e) lds[c].st(t + e * TH, v[c][e]);
     __syncthreads();
-    if (active) {
+    cx<T> o[C][E];
+#pragma unroll
+    for (int c = 0; c < C; ++c)
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             const int k = t + e * TH;
-            cx<T> zk = lds.ld(k), zm = lds.ld((M - k) & (M - 1));
-            cx<T> ev = {T(0.5) * (zk.x + zm.x), T(0.5) * (zk.y - zm.y)};
+            const cx<T> zk = lds[c].ld(k), zm = lds[c].ld((M - k) & (M - 1));
+            const cx<T> ev = {T(0.5) * (zk.x + zm.x), T(0.5) * (zk.y - zm.y)};
             // (zk - conj zm) / (2i)
-            cx<T> od = {T(0.5) * (zk.y + zm.y), -T(0.5) * (zk.x - zm.x)};
-            cx<T> o = ev + cmul(twN[k], od);
-            if (k == 0) o = cx<T>{zk.x + zk.y, zk.x - zk.y};   // (X_0, X_M), both real
-            out[k] = o;
+            const cx<T> od = {T(0.5) * (zk.y + zm.y), -T(0.5) * (zk.x - zm.x)};
+            cx<T> x = ev + cmul(twN[k], od);
+            if (k == 0) x = cx<T>{zk.x + zk.y, zk.x - zk.y};   // (X_0, X_M), both real
+            o[c][e] = x;
+        }
+    if (active) {
+        if constexpr (C == 1) {
+            cx<T> *orow = out + (size_t)i * M;
+#pragma unroll
+            for (int e = 0; e < E; ++e) orow[t + e * TH] = o[0][e];
+        } else {
+            cx2<T> *orow = reinterpret_cast<cx2<T> *>(out) + (size_t)i * M;
+#pragma unroll
+            for (int e = 0; e < E; ++e) orow[t + e * TH] = cx2<T>{o[0][e], o[1][e]};
         }
     }
 }
 
-// ---------------------------------------------------------------------------
-// Pass C: complex-to-real transforms of packed half rows (M values, bin 0 =
-// (X_0, X_M)) to real rows of length N = 2M (unnormalised inverse).
-// ---------------------------------------------------------------------------
-template <typename T, int M, int E>
+// Pass C: packed half rows (in: [n_rows][M] complex for C = 1, pairs for
+// C = 2) -> real rows of out0 (and out1), unnormalised inverse.
+template <typename T, int M, int E, int C>
 __device__ __forceinline__ void body_rows_c2r(int unit, int G, cx<T> *__restrict__ buf,
-                                           const cx<T> *__restrict__ in0,
-                                                  const cx<T> *__restrict__ in1, int n_rows,
-                                                  int total_rows, T *__restrict__ out0,
-                                                  T *__restrict__ out1,
-                                                  const cx<T> *__restrict__ twN) {
+                                              const cx<T> *__restrict__ in, int n_rows,
+                                              T *__restrict__ out0, T *__restrict__ out1,
+                                              const cx<T> *__restrict__ twN) {
     constexpr int TH = M / E;
     constexpr int N = 2 * M;
-    constexpr int H = M;
     const int gi = threadIdx.x / TH, t = threadIdx.x % TH;
     const int row = unit * G + gi;
-    const bool active = row < total_rows;
-    const int arr = active ? row / n_rows : 0;
-    const int i = active ? row % n_rows : 0;   // inactive lanes read row 0
-    const cx<T> *X = (arr == 0 ? in0 : in1) + (size_t)i * H;
-    T *y = (arr == 0 ? out0 : out1) + (size_t)i * N;
-    Lds<T> lds{buf, gi * padded_len(M), 1};
+    const bool active = row < n_rows;
+    const int i = active ? row : 0;   // inactive lanes read row 0
+    Lds<T> lds[C];
+    row_lds<T, M, E, C>(buf, gi, G, lds);
 
     // unconditional loads (in bounds for every lane) so they issue together
-    cx<T> xk[E], xm[E], wk[E];
+    cx<T> xk[C][E], xm[C][E], wk[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         const int k = t + e * TH;
-        xk[e] = X[k];
-        xm[e] = X[(M - k) & (M - 1)];
-        wk[e] = twN[k];                          // exp(-2 pi i k / N)
-    }
-    if (t == 0) {   // unpack bin 0 = (X_0, X_M)
-        const cx<T> p = xk[0];
-        xk[0] = cx<T>{p.x, T(0)};
-        xm[0] = cx<T>{p.y, T(0)};
+        const int km = (M - k) & (M - 1);
+        if constexpr (C == 1) {
+            const cx<T> *X = in + (size_t)i * M;
+            xk[0][e] = X[k];
+            xm[0][e] = X[km];
+        } else {
+            const cx2<T> *X = reinterpret_cast<const cx2<T> *>(in) + (size_t)i * M;
+            const cx2<T> a = X[k], b = X[km];
+            xk[0][e] = a.a;
+            xk[C - 1][e] = a.b;
+            xm[0][e] = b.a;
+            xm[C - 1][e] = b.b;
+        }
+        wk[e] = twN[k];   // exp(-2 pi i k / N)
     }
     Twiddles<M, E, T> tw;
     tw.load(t, twN, 2);
-    cx<T> v[E];
+    if (t == 0) {   // unpack bin 0 = (X_0, X_M)
 #pragma unroll
-    for (int e = 0; e < E; ++e) {
-        cx<T> s = {xk[e].x + xm[e].x, xk[e].y - xm[e].y};   // X[k] + conj X[M-k]
-        cx<T> d = {xk[e].x - xm[e].x, xk[e].y + xm[e].y};   // X[k] - conj X[M-k]
-        cx<T> dw = cmulc(d, wk[e]);                           // d * exp(+2 pi i k / N)
-        v[e] = active ? cx<T>{s.x - dw.y, s.y + dw.x} : cx<T>{T(0), T(0)};   // s + i dw
+        for (int c = 0; c < C; ++c) {
+            const cx<T> p = xk[c][0];
+            xk[c][0] = cx<T>{p.x, T(0)};
+            xm[c][0] = cx<T>{p.y, T(0)};
+        }
     }
-    fft_inv<M, E, T>(v, t, lds, tw);
-    if (active) {
-        cx<T> *yz = reinterpret_cast<cx<T> *>(y);
+    cx<T> v[C][E];
 #pragma unroll
-        for (int e = 0; e < E; ++e) yz[t + e * TH] = v[e];
+    for (int c = 0; c < C; ++c)
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const cx<T> s = {xk[c][e].x + xm[c][e].x, xk[c][e].y - xm[c][e].y};   // X[k] + conj X[M-k]
+            const cx<T> d = {xk[c][e].x - xm[c][e].x, xk[c][e].y + xm[c][e].y};   // X[k] - conj X[M-k]
+            const cx<T> dw = cmulc(d, wk[e]);                                         // d exp(+2 pi i k / N)
+            v[c][e] = active ? cx<T>{s.x - dw.y, s.y + dw.x} : cx<T>{T(0), T(0)};   // s + i dw
+        }
+    fft_inv<M, E, C, T>(v, t, lds, tw);
+    if (active) {
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            cx<T> *yz = reinterpret_cast<cx<T> *>((c == 0 ? out0 : out1) + (size_t)i * N);
+#pragma unroll
+            for (int e = 0; e < E; ++e) yz[t + e * TH] = v[c][e];
+        }
     }
 }
 
 // ---------------------------------------------------------------------------
 // Spectrum access with the phi-parity symmetry of the kernels:
 // E_r, Q_r even in n -> value at -k_u is conj; E_p, Q_p odd -> -conj.
+// One pair (E', Q) of a column per load.
 // ---------------------------------------------------------------------------
 template <typename T, int L>
-__device__ __forceinline__ cx<T> spec_at(const cx<T> *__restrict__ col, int ku, bool odd) {
+__device__ __forceinline__ cx2<T> spec_at(const cx2<T> *__restrict__ col, int ku, bool odd) {
     constexpr int HL = L / 2;
     const bool lo = ku <= HL;
-    const cx<T> s = col[lo ? ku : L - ku];   // one load, no branch
+    const cx2<T> s = col[lo ? ku : L - ku];   // one load, no branch
     if (lo) return s;
-    return odd ? cx<T>{-s.x, s.y} : cx<T>{s.x, -s.y};
+    if (odd) return cx2<T>{{-s.a.x, s.a.y}, {-s.b.x, s.b.y}};
+    return cx2<T>{{s.a.x, -s.a.y}, {s.b.x, -s.b.y}};
 }
 
 // ---------------------------------------------------------------------------
@@ -251,7 +291,7 @@ __device__ __forceinline__ cx<T> unpack_odd(cx<T> p, cx<T> m) {
 }
 
 // Points per batch of spectrum loads in the multiply-accumulate of pass B,
-// sized so that a batch's loads (six complex values per point) fit in the
+// sized so that a batch's loads (four complex values per point) fit in the
 // registers beside the transform data: 64 / E in FP32 (E <= 8: all E),
 // 2 in FP64.
 template <typename T, int E>
@@ -260,13 +300,14 @@ __host__ __device__ constexpr int mac_batch() { return sizeof(T) == 8 ? 2 : (E <
 // ---------------------------------------------------------------------------
 // Pass B, forward.  Workgroup: G columns x (L/E) threads, lane -> (t, column)
 // with the G columns interleaved (consecutive lanes read consecutive
-// columns of a row).  LDS buf: G*padded_len(L) complex.
+// columns of a row).  LDS buf: G*L complex.
+// S: [n_r][H] complex; Z: [n_r][H] pairs (Zr, Zp); spec: [2][H][ldspec] pairs.
 // ---------------------------------------------------------------------------
 template <typename T, int L, int E>
 __device__ __forceinline__ void body_cols_fwd(int unit, int G, cx<T> *__restrict__ buf,
                                               const cx<T> *__restrict__ S,
-                                              cx<T> *__restrict__ Zr, cx<T> *__restrict__ Zp,
-                                              const cx<T> *__restrict__ spec, int H, int n_r,
+                                              cx2<T> *__restrict__ Z,
+                                              const cx2<T> *__restrict__ spec, int H, int n_r,
                                               int ldspec, T ca, T c0, T cn,
                                               const cx<T> *__restrict__ twL) {
     constexpr int TH = L / E;
@@ -276,7 +317,7 @@ __device__ __forceinline__ void body_cols_fwd(int unit, int G, cx<T> *__restrict
     const int cl = valid ? col : 0;
     const bool packed = unit == 0;          // workgroup-uniform: the group holding column 0
     const bool is0 = packed && gi == 0;
-    Lds<T> lds{buf, gi, G};
+    const Lds<T> lds{buf, gi, G};
 
     // The column.  Only the first E/2 strided points of a thread can be data
     // rows (L >= 2 n_r); clamped, always valid addresses so the loads issue
@@ -305,10 +346,8 @@ __device__ __forceinline__ void body_cols_fwd(int unit, int G, cx<T> *__restrict
         __syncthreads();
     }
 
-    const cx<T> *er = spec + (size_t)(0 * H + cl) * ldspec;
-    const cx<T> *qr = spec + (size_t)(1 * H + cl) * ldspec;
-    const cx<T> *ep = spec + (size_t)(2 * H + cl) * ldspec;
-    const cx<T> *qp = spec + (size_t)(3 * H + cl) * ldspec;
+    const cx2<T> *sr = spec + (size_t)cl * ldspec;               // (E'_r, Q_r)
+    const cx2<T> *sp = spec + (size_t)(H + cl) * ldspec;         // (E'_p, Q_p)
     const SlopeFix<T> a = slope_fix(x0, x1, xm2, xm1, ca, c0, cn);
     const SlopePhasors<T> ph = slope_phasors(a, wt, wnt);
     SlopePhasors<T> ph0 = ph, phM = ph;
@@ -317,19 +356,17 @@ __device__ __forceinline__ void body_cols_fwd(int unit, int G, cx<T> *__restrict
         phM = slope_phasors(slope_fix_part(a, true), wt, wnt);
     }
     constexpr int CH = mac_batch<T, E>();
-    cx<T> yr[E], yp[E];
+    cx<T> y[2][E];   // y[0] -> Zr, y[1] -> Zp
 #pragma unroll
     for (int cb = 0; cb < E; cb += CH) {
-        // spectra of the batch issued together; column 0's slots 2, 3 hold
+        // spectra of the batch issued together; column 0's second pair holds
         // bin M's radial (even) spectra
-        cx<T> sa[CH], sb[CH], sc[CH], sd[CH];
+        cx2<T> pr[CH], pp[CH];
 #pragma unroll
         for (int j = 0; j < CH; ++j) {
             const int ku = t + (cb + j) * TH;
-            sa[j] = spec_at<T, L>(er, ku, false);
-            sb[j] = spec_at<T, L>(qr, ku, false);
-            sc[j] = spec_at<T, L>(ep, ku, !is0);
-            sd[j] = spec_at<T, L>(qp, ku, !is0);
+            pr[j] = spec_at<T, L>(sr, ku, false);
+            pp[j] = spec_at<T, L>(sp, ku, !is0);
         }
 #pragma unroll
         for (int j = 0; j < CH; ++j) {
@@ -339,28 +376,25 @@ __device__ __forceinline__ void body_cols_fwd(int unit, int G, cx<T> *__restrict
                 const cx<T> m = lds.ld((L - (t + e * TH)) & (L - 1));
                 const cx<T> A = unpack_even(v[e], m), B = unpack_odd(v[e], m);
                 const cx<T> f0 = slope_fix_at(ph0, r), fM = slope_fix_at(phM, r);
-                const cx<T> y0 = cmul(sa[j], A) + cmul(sb[j], f0);
-                const cx<T> yM = cmul(sc[j], B) + cmul(sd[j], fM);
-                yr[e] = cx<T>{y0.x - yM.y, y0.y + yM.x};   // y0 + i yM
-                yp[e] = cx<T>{T(0), T(0)};
+                const cx<T> y0 = cmul(pr[j].a, A) + cmul(pr[j].b, f0);
+                const cx<T> yM = cmul(pp[j].a, B) + cmul(pp[j].b, fM);
+                y[0][e] = cx<T>{y0.x - yM.y, y0.y + yM.x};   // y0 + i yM
+                y[1][e] = cx<T>{T(0), T(0)};
             } else {
                 const cx<T> f = slope_fix_at(ph, r);
-                yr[e] = cmul(sa[j], v[e]) + cmul(sb[j], f);
-                yp[e] = cmul(sc[j], v[e]) + cmul(sd[j], f);
+                y[0][e] = cmul(pr[j].a, v[e]) + cmul(pr[j].b, f);
+                y[1][e] = cmul(pp[j].a, v[e]) + cmul(pp[j].b, f);
             }
         }
     }
     if (packed) __syncthreads();
-    fft_inv<L, E, T>(yr, t, lds, tw);
-    fft_inv<L, E, T>(yp, t, lds, tw);
+    fft_inv<L, E, T>(y[0], t, lds, tw);
+    fft_inv<L, E, T>(y[1], t, lds, tw);
     if (valid) {
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             const int i = t + e * TH;
-            if (i < n_r) {
-                Zr[(size_t)i * H + col] = yr[e];
-                Zp[(size_t)i * H + col] = yp[e];
-            }
+            if (i < n_r) Z[(size_t)i * H + col] = cx2<T>{y[0][e], y[1][e]};
         }
     }
 }
@@ -408,13 +442,13 @@ __device__ __forceinline__ void column_sums(cx<T> (&x)[Q], int G, cx<T> *__restr
 // the transposed slope: the transposed central difference is in E'; the
 // four-row correction needs the inverse transform of R = conj(Q_r) V_r +
 // conj(Q_p) V_p at rows 0, n-1, n and L-1 only, four sums over k.
+// V: [n_r][H] pairs (Vr, Vp); D: [n_r][H] complex.  LDS buf: G*L complex.
 // ---------------------------------------------------------------------------
 template <typename T, int L, int E>
 __device__ __forceinline__ void body_cols_adj(int unit, int G, cx<T> *__restrict__ buf,
-                                              const cx<T> *__restrict__ Vr,
-                                              const cx<T> *__restrict__ Vp,
+                                              const cx2<T> *__restrict__ V,
                                               cx<T> *__restrict__ D,
-                                              const cx<T> *__restrict__ spec, int H, int n_r,
+                                              const cx2<T> *__restrict__ spec, int H, int n_r,
                                               int ldspec, T ca, T c0, T cn,
                                               const cx<T> *__restrict__ twL) {
     constexpr int TH = L / E;
@@ -424,17 +458,17 @@ __device__ __forceinline__ void body_cols_adj(int unit, int G, cx<T> *__restrict
     const int cl = valid ? col : 0;
     const bool packed = unit == 0;
     const bool is0 = packed && gi == 0;
-    Lds<T> lds{buf, gi, G};
+    const Lds<T> lds{buf, gi, G};
 
     // clamped, always valid addresses so the loads issue back to back; only
     // the first E/2 points of a thread can be data rows (L >= 2 n_r)
-    cx<T> va[E], vb[E];
+    cx<T> va[2][E];   // va[0]: V_r, va[1]: V_p
 #pragma unroll
     for (int e = 0; e < E / 2; ++e) {
         const int i = t + e * TH;
-        const size_t o = (size_t)(i < n_r ? i : n_r - 1) * H + cl;
-        va[e] = Vr[o];
-        vb[e] = Vp[o];
+        const cx2<T> q = V[(size_t)(i < n_r ? i : n_r - 1) * H + cl];
+        va[0][e] = q.a;
+        va[1][e] = q.b;
     }
     Twiddles<L, E, T> tw;
     tw.load(t, twL, 1);
@@ -442,22 +476,20 @@ __device__ __forceinline__ void body_cols_adj(int unit, int G, cx<T> *__restrict
     for (int e = 0; e < E; ++e) {
         const int i = t + e * TH;
         if (e >= E / 2 || !valid || i >= n_r) {
-            va[e] = cx<T>{T(0), T(0)};
-            vb[e] = cx<T>{T(0), T(0)};
+            va[0][e] = cx<T>{T(0), T(0)};
+            va[1][e] = cx<T>{T(0), T(0)};
         }
     }
-    fft_fwd<L, E, T>(va, t, lds, tw);
-    fft_fwd<L, E, T>(vb, t, lds, tw);
+    fft_fwd<L, E, T>(va[0], t, lds, tw);
+    fft_fwd<L, E, T>(va[1], t, lds, tw);
     if (packed) {   // column 0 reads the conjugate mirror points from LDS
 #pragma unroll
-        for (int e = 0; e < E; ++e) lds.st(t + e * TH, va[e]);
+        for (int e = 0; e < E; ++e) lds.st(t + e * TH, va[0][e]);
         __syncthreads();
     }
 
-    const cx<T> *er = spec + (size_t)(0 * H + cl) * ldspec;
-    const cx<T> *qr = spec + (size_t)(1 * H + cl) * ldspec;
-    const cx<T> *ep = spec + (size_t)(2 * H + cl) * ldspec;
-    const cx<T> *qp = spec + (size_t)(3 * H + cl) * ldspec;
+    const cx2<T> *sr = spec + (size_t)cl * ldspec;
+    const cx2<T> *sp = spec + (size_t)(H + cl) * ldspec;
     // The unnormalised inverse transform of R at rows 0, L-1, n, n-1:
     //   w[0] = sum R, w[1] = sum R W^k, w[2] = sum R W^(-n k),
     //   w[3] = sum R W^(-(n-1) k),
@@ -467,33 +499,32 @@ __device__ __forceinline__ void body_cols_adj(int unit, int G, cx<T> *__restrict
     constexpr int CH = mac_batch<T, E>();
 #pragma unroll
     for (int cb = 0; cb < E; cb += CH) {
-        cx<T> sa[CH], sb[CH], sc[CH], sd[CH];
+        cx2<T> pr[CH], pp[CH];
 #pragma unroll
         for (int j = 0; j < CH; ++j) {
             const int ku = t + (cb + j) * TH;
-            sa[j] = spec_at<T, L>(er, ku, false);
-            sb[j] = spec_at<T, L>(qr, ku, false);
-            sc[j] = spec_at<T, L>(ep, ku, !is0);
-            sd[j] = spec_at<T, L>(qp, ku, !is0);
+            pr[j] = spec_at<T, L>(sr, ku, false);
+            pp[j] = spec_at<T, L>(sp, ku, !is0);
         }
 #pragma unroll
         for (int j = 0; j < CH; ++j) {
             const int e = cb + j;
-            cx<T> x, r;
+            cx<T> xe, r;
             if (is0) {
                 // bins 0 and M of the packed column; V_p's bins 0 and M do
                 // not enter (the azimuthal spectra vanish there)
                 const cx<T> m = lds.ld((L - (t + e * TH)) & (L - 1));
-                const cx<T> A = unpack_even(va[e], m), B = unpack_odd(va[e], m);
-                const cx<T> x0 = cmulc(A, sa[j]), xM = cmulc(B, sc[j]);
-                const cx<T> r0 = cmulc(A, sb[j]), rM = cmulc(B, sd[j]);
-                x = cx<T>{x0.x - xM.y, x0.y + xM.x};
+                const cx<T> A = unpack_even(va[0][e], m), B = unpack_odd(va[0][e], m);
+                const cx<T> x0 = cmulc(A, pr[j].a), xM = cmulc(B, pp[j].a);
+                const cx<T> r0 = cmulc(A, pr[j].b), rM = cmulc(B, pp[j].b);
+                xe = cx<T>{x0.x - xM.y, x0.y + xM.x};
                 r = cx<T>{r0.x - rM.y, r0.y + rM.x};
             } else {
-                x = cmulc(va[e], sa[j]) + cmulc(vb[e], sc[j]);   // conj(E'_r) V_r + conj(E'_p) V_p
-                r = cmulc(va[e], sb[j]) + cmulc(vb[e], sd[j]);   // conj(Q_r) V_r + conj(Q_p) V_p
+                // conj(E'_r) V_r + conj(E'_p) V_p and conj(Q_r) V_r + conj(Q_p) V_p
+                xe = cmulc(va[0][e], pr[j].a) + cmulc(va[1][e], pp[j].a);
+                r = cmulc(va[0][e], pr[j].b) + cmulc(va[1][e], pp[j].b);
             }
-            va[e] = x;
+            va[0][e] = xe;   // V_r's point is not needed again
             const Roots<T, L, E> ro(twL, n_r, e);
             w[0] = w[0] + r;
             w[1] = w[1] + cmul(r, ro.r1);
@@ -511,14 +542,14 @@ __device__ __forceinline__ void body_cols_adj(int unit, int G, cx<T> *__restrict
         w[3] = cmulc(w[3], wmt);
     }
     column_sums<T, 4>(w, G, buf);
-    fft_inv<L, E, T>(va, t, lds, tw);
+    fft_inv<L, E, T>(va[0], t, lds, tw);
     if (valid) {
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             const int i = t + e * TH;
             if (i < n_r) {
                 // transposed four-row correction
-                cx<T> acc = va[e];
+                cx<T> acc = va[0][e];
                 if (i == 0) acc = acc - scale(w[0], c0) - scale(w[1], ca);
                 if (i == 1) acc = acc + scale(w[0], c0 - ca);
                 if (i == n_r - 2) acc = acc + scale(w[3], ca - cn);

@@ -145,72 +145,59 @@ template <typename T>
 int forces_t(const Plan &p, const T *sigma, T *fr, T *fp, hipStream_t st) {
     using C = pf::cx<T>;
     C *S = (C *)p.ws;
-    C *Zr = S + (size_t)p.n_r * p.H;
-    C *Zp = Zr + (size_t)p.n_r * p.H;
-    int rc = pf::launch_rows_r2c<T>(p, sigma, nullptr, 1, p.n_r, S, nullptr, (const C *)p.twN,
-                                    p.sched.rows, st);
+    C *Z = S + (size_t)p.n_r * p.H;   // (Zr, Zp) pairs
+    int rc = pf::launch_rows_r2c<T>(p, sigma, nullptr, p.n_r, S, (const C *)p.twN, p.sched.rows,
+                                    st);
     if (rc) return rc;
-    rc = pf::launch_cols_fwd<T>(p, S, Zr, Zp, (const C *)p.spec, (const C *)p.twL, p.sched.cols,
-                                st);
+    rc = pf::launch_cols_fwd<T>(p, S, Z, (const C *)p.spec, (const C *)p.twL, p.sched.cols, st);
     if (rc) return rc;
-    return pf::launch_rows_c2r<T>(p, Zr, Zp, 2, p.n_r, fr, fp, (const C *)p.twN, p.sched.rows,
-                                  st);
+    return pf::launch_rows_c2r<T>(p, Z, p.n_r, fr, fp, (const C *)p.twN, p.sched.rows, st);
 }
 
 template <typename T>
 int backward_t(const Plan &p, const T *gr, const T *gp, T *gs, hipStream_t st) {
     using C = pf::cx<T>;
-    C *Vr = (C *)p.ws;
-    C *Vp = Vr + (size_t)p.n_r * p.H;
-    C *D = Vp + (size_t)p.n_r * p.H;
-    int rc = pf::launch_rows_r2c<T>(p, gr, gp, 2, p.n_r, Vr, Vp, (const C *)p.twN, p.sched.rows,
-                                    st);
+    C *V = (C *)p.ws;                        // (Vr, Vp) pairs
+    C *D = V + 2 * (size_t)p.n_r * p.H;
+    int rc = pf::launch_rows_r2c<T>(p, gr, gp, p.n_r, V, (const C *)p.twN, p.sched.rows, st);
     if (rc) return rc;
-    rc = pf::launch_cols_adj<T>(p, Vr, Vp, D, (const C *)p.spec, (const C *)p.twL, p.sched.cols_adj,
+    rc = pf::launch_cols_adj<T>(p, V, D, (const C *)p.spec, (const C *)p.twL, p.sched.cols_adj,
                                 st);
     if (rc) return rc;
-    return pf::launch_rows_c2r<T>(p, D, nullptr, 1, p.n_r, gs, nullptr, (const C *)p.twN,
-                                  p.sched.rows, st);
+    return pf::launch_rows_c2r<T>(p, D, p.n_r, gs, nullptr, (const C *)p.twN, p.sched.rows, st);
 }
 
-// The passes of forces_t / backward_t with an event before, between and
-// after them.
 template <typename T>
 int timed_t(const Plan &p, bool bwd, const void *in0, const void *in1, void *out0, void *out1,
             int reps, hipStream_t st, hipEvent_t *ev) {
     using C = pf::cx<T>;
-    C *A = (C *)p.ws;
-    C *B = A + (size_t)p.n_r * p.H;
-    C *Cc = B + (size_t)p.n_r * p.H;
+    C *W0 = (C *)p.ws;
+    C *W1 = W0 + (size_t)p.n_r * p.H;       // forward: S = W0, Z = W1
+    C *W2 = W0 + 2 * (size_t)p.n_r * p.H;   // transpose: V = W0, D = W2
     int rc = PF_OK;
     PF_HIP(hipEventRecord(ev[0], st));
-    for (int k = 0; k < reps && !rc; ++k) {
-        if (!bwd)
-            rc = pf::launch_rows_r2c<T>(p, (const T *)in0, nullptr, 1, p.n_r, A, nullptr,
-                                        (const C *)p.twN, p.sched.rows, st);
-        else
-            rc = pf::launch_rows_r2c<T>(p, (const T *)in0, (const T *)in1, 2, p.n_r, A, B,
-                                        (const C *)p.twN, p.sched.rows, st);
-    }
+    for (int k = 0; k < reps && !rc; ++k)
+        rc = pf::launch_rows_r2c<T>(p, (const T *)in0, bwd ? (const T *)in1 : nullptr, p.n_r, W0,
+                                    (const C *)p.twN, p.sched.rows, st);
     if (rc) return rc;
     PF_HIP(hipEventRecord(ev[1], st));
     for (int k = 0; k < reps && !rc; ++k) {
         if (!bwd)
-            rc = pf::launch_cols_fwd<T>(p, A, B, Cc, (const C *)p.spec, (const C *)p.twL,
+            rc = pf::launch_cols_fwd<T>(p, W0, W1, (const C *)p.spec, (const C *)p.twL,
                                         p.sched.cols, st);
         else
-            rc = pf::launch_cols_adj<T>(p, A, B, Cc, (const C *)p.spec, (const C *)p.twL,
+            rc = pf::launch_cols_adj<T>(p, W0, W2, (const C *)p.spec, (const C *)p.twL,
                                         p.sched.cols_adj, st);
     }
     if (rc) return rc;
     PF_HIP(hipEventRecord(ev[2], st));
     for (int k = 0; k < reps && !rc; ++k) {
         if (!bwd)
-            rc = pf::launch_rows_c2r<T>(p, B, Cc, 2, p.n_r, (T *)out0, (T *)out1,
-                                        (const C *)p.twN, p.sched.rows, st);
+            rc = pf::launch_rows_c2r<T>(p, W1, p.n_r, (T *)out0, (T *)out1, (const C *)p.twN,
+                                        p.sched.rows, st);
         else
-            rc = pf::launch_rows_c2r<T>(p, Cc, nullptr, 1, p.n_r, (T *)out0, nullptr,
-                                        (const C *)p.twN, p.sched.rows, st);
+            rc = pf::launch_rows_c2r<T>(p, W2, p.n_r, (T *)out0, nullptr, (const C *)p.twN,
+                                        p.sched.rows, st);
     }
     if (rc) return rc;
     PF_HIP(hipEventRecord(ev[3], st));

@@ -49,19 +49,20 @@ struct GDisk {
     T ca, c0, cn;
     const T *sigma;
     T *fr, *fp;
-    cx<T> *S, *Zr, *Zp;
-    const cx<T> *spec, *twN, *twL;
+    cx<T> *S;
+    cx2<T> *Z;     // (Zr, Zp) pairs
+    const cx2<T> *spec;
+    const cx<T> *twN, *twL;
 };
 
 template <typename T, int M>
 __device__ __forceinline__ void group_rows(int pass, int unit, const GDisk<T> &d, cx<T> *buf) {
     constexpr int G = kGroupThreads / (M / kRowE);
     if (pass == 0)
-        body_rows_r2c<T, M, kRowE>(unit, G, buf, d.sigma, nullptr, d.n_r, d.n_r, d.S, nullptr,
-                                   d.twN);
+        body_rows_r2c<T, M, kRowE, 1>(unit, G, buf, d.sigma, nullptr, d.n_r, d.S, d.twN);
     else
-        body_rows_c2r<T, M, kRowE>(unit, G, buf, d.Zr, d.Zp, d.n_r, 2 * d.n_r, d.fr, d.fp,
-                                   d.twN);
+        body_rows_c2r<T, M, kRowE, 2>(unit, G, buf, reinterpret_cast<const cx<T> *>(d.Z), d.n_r,
+                                      d.fr, d.fp, d.twN);
 }
 
 // Pass A (pass = 0) or C (pass = 2) of every disk: block -> (disk, unit).
@@ -69,7 +70,7 @@ template <typename T>
 __global__ __launch_bounds__(kGroupThreads) void k_group_rows(const GDisk<T> *__restrict__ disks,
                                                               const int *__restrict__ bdisk,
                                                               int pass) {
-    __shared__ cx<T> buf[kGroupThreads * kRowE];
+    __shared__ cx<T> buf[2 * kGroupThreads * kRowE];
     const GDisk<T> &d = disks[bdisk[blockIdx.x]];
     const int unit = blockIdx.x - d.base[pass];
     switch (d.M) {
@@ -87,8 +88,8 @@ __device__ __forceinline__ void group_cols(int unit, const GDisk<T> &d, cx<T> *b
     constexpr int E = col_e<T>();
     if constexpr (L / E <= kGroupThreads) {
         constexpr int G = kGroupThreads / (L / E);
-        body_cols_fwd<T, L, E>(unit, G, buf, d.S, d.Zr, d.Zp, d.spec, d.H, d.n_r, d.ldspec, d.ca,
-                               d.c0, d.cn, d.twL);
+        body_cols_fwd<T, L, E>(unit, G, buf, d.S, d.Z, d.spec, d.H, d.n_r, d.ldspec, d.ca, d.c0,
+                               d.cn, d.twL);
     }
 }
 
@@ -159,15 +160,14 @@ int make_entry_t(BatchEntry &e, const std::vector<const Plan *> &plans) {
         d.cn = (T)p.cn;
         cx<T> *ws = (cx<T> *)p.ws;
         d.S = ws;
-        d.Zr = ws + (size_t)p.n_r * p.H;
-        d.Zp = d.Zr + (size_t)p.n_r * p.H;
-        d.spec = (const cx<T> *)p.spec;
+        d.Z = reinterpret_cast<cx2<T> *>(ws + (size_t)p.n_r * p.H);
+        d.spec = (const cx2<T> *)p.spec;
         d.twN = (const cx<T> *)p.twN;
         d.twL = (const cx<T> *)p.twL;
         const int GA = kGroupThreads / (p.M / kRowE);
         const int GB = kGroupThreads / (p.L / EC);
         const int units[3] = {(p.n_r + GA - 1) / GA, (p.H + GB - 1) / GB,
-                              (2 * p.n_r + GA - 1) / GA};
+                              (p.n_r + GA - 1) / GA};
         for (int q = 0; q < 3; ++q) {
             d.base[q] = (int)map[q].size();
             map[q].insert(map[q].end(), units[q], k);
@@ -401,13 +401,14 @@ void tune_t(Plan &p, hipStream_t st) {
     T *x = nullptr;
     if (hipMalloc(&x, sizeof(T) * 3 * (size_t)p.n_r * p.n_phi) != hipSuccess) return;
     (void)hipMemsetAsync(x, 0, sizeof(T) * 3 * (size_t)p.n_r * p.n_phi, st);
-    C *S = (C *)p.ws;
-    C *Zr = S + (size_t)p.n_r * p.H, *Zp = Zr + (size_t)p.n_r * p.H;
+    C *S = (C *)p.ws;                        // forward: S, then (Zr, Zp) pairs
+    C *Z = S + (size_t)p.n_r * p.H;
+    C *D = S + 2 * (size_t)p.n_r * p.H;      // transpose: (Vr, Vp) pairs at S, then D
     (void)hipMemsetAsync(p.ws, 0, sizeof(C) * 3 * (size_t)p.n_r * p.H, st);
     hipEvent_t e0, e1;
     (void)hipEventCreate(&e0);
     (void)hipEventCreate(&e1);
-    // rows: forward R2C of n_r rows + inverse C2R of 2 n_r rows
+    // rows: forward R2C of n_r rows + two-channel inverse C2R of n_r rows
     Shape best_r = p.sched.rows, best_c = p.sched.cols, best_a = p.sched.cols_adj;
     float tbest = 1e30f;
     for (int E : {4, 8, 16})
@@ -417,10 +418,10 @@ void tune_t(Plan &p, hipStream_t st) {
             if (!valid_shape_rows(p.M, s, f64)) continue;
             float t = time_ms(
                 [&]() {
-                    int rc = launch_rows_r2c<T>(p, x, nullptr, 1, p.n_r, S, nullptr,
-                                                (const C *)p.twN, s, st);
+                    int rc = launch_rows_r2c<T>(p, x, nullptr, p.n_r, S, (const C *)p.twN, s,
+                                                st);
                     if (!rc)
-                        rc = launch_rows_c2r<T>(p, Zr, Zp, 2, p.n_r, x + (size_t)p.n_r * p.n_phi,
+                        rc = launch_rows_c2r<T>(p, Z, p.n_r, x + (size_t)p.n_r * p.n_phi,
                                                 x + 2 * (size_t)p.n_r * p.n_phi,
                                                 (const C *)p.twN, s, st);
                     return rc;
@@ -439,8 +440,8 @@ void tune_t(Plan &p, hipStream_t st) {
             if (!valid_shape_cols(p.L, s, f64)) continue;
             float t = time_ms(
                 [&]() {
-                    return launch_cols_fwd<T>(p, S, Zr, Zp, (const C *)p.spec, (const C *)p.twL,
-                                              s, st);
+                    return launch_cols_fwd<T>(p, S, Z, (const C *)p.spec, (const C *)p.twL, s,
+                                              st);
                 },
                 st, e0, e1);
             if (t > 0 && t < tbest) {
@@ -456,8 +457,8 @@ void tune_t(Plan &p, hipStream_t st) {
             if (!valid_shape_cols(p.L, s, f64)) continue;
             float t = time_ms(
                 [&]() {
-                    return launch_cols_adj<T>(p, S, Zr, Zp, (const C *)p.spec, (const C *)p.twL,
-                                              s, st);
+                    return launch_cols_adj<T>(p, S, D, (const C *)p.spec, (const C *)p.twL, s,
+                                              st);
                 },
                 st, e0, e1);
             if (t > 0 && t < tbest) {

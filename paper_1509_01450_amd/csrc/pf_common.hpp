@@ -53,10 +53,12 @@ struct Plan {
     int device = -1;
     double selfk[3] = {0, 0, 0};
 
-    void *spec = nullptr;     // [4][H][ldspec] complex, plan precision
+    void *spec = nullptr;     // [2][H][ldspec] pairs (E', Q), plan precision
     void *twN = nullptr;      // n_phi-point twiddles, plan precision
     void *twL = nullptr;      // L-point twiddles, plan precision
     void *ws = nullptr;       // workspace: 3 * n_r * H complex, plan precision
+                              // (forward: S, then (Zr, Zp) pairs; transpose:
+                              // (Vr, Vp) pairs, then D)
     double *tables = nullptr; // [6][L][n_phi] FP64 (only with keep_tables)
     Schedule sched;
     int64_t uid = 0;          // identity for batch-graph caching
@@ -65,22 +67,25 @@ struct Plan {
 };
 
 // ---- kernels (pf_passes.hip) -----------------------------------------------
-// Row transforms along phi of n_arr arrays of n_rows rows each.
+// Row transforms along phi of n_rows rows.  r2c: rows of in0 -> packed half
+// spectra out ([n_rows][M] complex); with in1, rows of in0 and in1 -> pairs
+// ([n_rows][M] pairs).  c2r: the inverse, from complex rows to out0, or from
+// pairs to out0 and out1 when out1 is given.
 template <typename T>
-int launch_rows_r2c(const Plan &p, const T *in0, const T *in1, int n_arr, int n_rows,
-                    cx<T> *out0, cx<T> *out1, const cx<T> *twN, Shape s, hipStream_t st);
+int launch_rows_r2c(const Plan &p, const T *in0, const T *in1, int n_rows, cx<T> *out,
+                    const cx<T> *twN, Shape s, hipStream_t st);
 template <typename T>
-int launch_rows_c2r(const Plan &p, const cx<T> *in0, const cx<T> *in1, int n_arr,
-                    int n_rows, T *out0, T *out1, const cx<T> *twN, Shape s, hipStream_t st);
+int launch_rows_c2r(const Plan &p, const cx<T> *in, int n_rows, T *out0, T *out1,
+                    const cx<T> *twN, Shape s, hipStream_t st);
 // Column pass of the forward map (u-FFT, spectral multiply-accumulate with
-// the spectral radial slope, inverse u-FFTs, crop).
+// the spectral radial slope, inverse u-FFTs, crop): S -> pairs Z.
 template <typename T>
-int launch_cols_fwd(const Plan &p, const cx<T> *S, cx<T> *Zr, cx<T> *Zp, const cx<T> *spec,
+int launch_cols_fwd(const Plan &p, const cx<T> *S, cx<T> *Z, const cx<T> *spec,
                     const cx<T> *twL, Shape s, hipStream_t st);
-// Column pass of the transpose.
+// Column pass of the transpose: pairs V -> D.
 template <typename T>
-int launch_cols_adj(const Plan &p, const cx<T> *Vr, const cx<T> *Vp, cx<T> *D,
-                    const cx<T> *spec, const cx<T> *twL, Shape s, hipStream_t st);
+int launch_cols_adj(const Plan &p, const cx<T> *V, cx<T> *D, const cx<T> *spec,
+                    const cx<T> *twL, Shape s, hipStream_t st);
 
 // ---- kernels (pf_tables.hip) ------------------------------------------------
 int build_tables_and_spectra(Plan &p, hipStream_t st);

@@ -13,73 +13,72 @@ namespace pf {
 // columns share cache lines of the row-major intermediates.
 __device__ __forceinline__ int xcd_group(int b, int per_xcd) { return (b & 7) * per_xcd + (b >> 3); }
 
-template <typename T, int M, int E>
+template <typename T, int M, int E, int C>
 __global__ __launch_bounds__(512) void k_rows_r2c(const T *__restrict__ in0,
                                                   const T *__restrict__ in1, int n_rows,
-                                                  int total_rows, cx<T> *__restrict__ out0,
-                                                  cx<T> *__restrict__ out1,
+                                                  cx<T> *__restrict__ out,
                                                   const cx<T> *__restrict__ twN) {
     extern __shared__ unsigned char smem_raw[];
-    body_rows_r2c<T, M, E>(blockIdx.x, blockDim.x / (M / E), reinterpret_cast<cx<T> *>(smem_raw),
-                           in0, in1, n_rows, total_rows, out0, out1, twN);
+    body_rows_r2c<T, M, E, C>(blockIdx.x, blockDim.x / (M / E),
+                              reinterpret_cast<cx<T> *>(smem_raw), in0, in1, n_rows, out, twN);
 }
 
-template <typename T, int M, int E>
-__global__ __launch_bounds__(512) void k_rows_c2r(const cx<T> *__restrict__ in0,
-                                                  const cx<T> *__restrict__ in1, int n_rows,
-                                                  int total_rows, T *__restrict__ out0,
-                                                  T *__restrict__ out1,
+template <typename T, int M, int E, int C>
+__global__ __launch_bounds__(512) void k_rows_c2r(const cx<T> *__restrict__ in, int n_rows,
+                                                  T *__restrict__ out0, T *__restrict__ out1,
                                                   const cx<T> *__restrict__ twN) {
     extern __shared__ unsigned char smem_raw[];
-    body_rows_c2r<T, M, E>(blockIdx.x, blockDim.x / (M / E), reinterpret_cast<cx<T> *>(smem_raw),
-                           in0, in1, n_rows, total_rows, out0, out1, twN);
+    body_rows_c2r<T, M, E, C>(blockIdx.x, blockDim.x / (M / E),
+                              reinterpret_cast<cx<T> *>(smem_raw), in, n_rows, out0, out1, twN);
 }
 
 template <typename T, int L, int E>
 __global__ __launch_bounds__(512) void k_cols_fwd(const cx<T> *__restrict__ S,
-                                                  cx<T> *__restrict__ Zr, cx<T> *__restrict__ Zp,
-                                                  const cx<T> *__restrict__ spec, int H, int n_r,
+                                                  cx2<T> *__restrict__ Z,
+                                                  const cx2<T> *__restrict__ spec, int H, int n_r,
                                                   int ldspec, T ca, T c0, T cn,
                                                   const cx<T> *__restrict__ twL, int per_xcd,
                                                   int n_groups) {
     extern __shared__ unsigned char smem_raw[];
     const int grp = xcd_group(blockIdx.x, per_xcd);
     if (grp >= n_groups) return;  // whole workgroup leaves together
-    body_cols_fwd<T, L, E>(grp, blockDim.x / (L / E), reinterpret_cast<cx<T> *>(smem_raw), S, Zr,
-                           Zp, spec, H, n_r, ldspec, ca, c0, cn, twL);
+    body_cols_fwd<T, L, E>(grp, blockDim.x / (L / E), reinterpret_cast<cx<T> *>(smem_raw), S, Z,
+                           spec, H, n_r, ldspec, ca, c0, cn, twL);
 }
 
 template <typename T, int L, int E>
-__global__ __launch_bounds__(512) void k_cols_adj(const cx<T> *__restrict__ Vr,
-                                                  const cx<T> *__restrict__ Vp,
+__global__ __launch_bounds__(512) void k_cols_adj(const cx2<T> *__restrict__ V,
                                                   cx<T> *__restrict__ D,
-                                                  const cx<T> *__restrict__ spec, int H, int n_r,
+                                                  const cx2<T> *__restrict__ spec, int H, int n_r,
                                                   int ldspec, T ca, T c0, T cn,
                                                   const cx<T> *__restrict__ twL, int per_xcd,
                                                   int n_groups) {
     extern __shared__ unsigned char smem_raw[];
     const int grp = xcd_group(blockIdx.x, per_xcd);
     if (grp >= n_groups) return;
-    body_cols_adj<T, L, E>(grp, blockDim.x / (L / E), reinterpret_cast<cx<T> *>(smem_raw), Vr, Vp,
-                           D, spec, H, n_r, ldspec, ca, c0, cn, twL);
+    body_cols_adj<T, L, E>(grp, blockDim.x / (L / E), reinterpret_cast<cx<T> *>(smem_raw), V, D,
+                           spec, H, n_r, ldspec, ca, c0, cn, twL);
 }
 
 // ---------------------------------------------------------------------------
 // Runtime dispatch onto the template instantiations.
 // ---------------------------------------------------------------------------
+// Row shapes are checked for the two-channel passes (the larger LDS need):
+// 2 G M complex within the default 64 KB.
 bool valid_shape_rows(int M, Shape s, bool f64) {
     if (!(s.E == 4 || s.E == 8 || s.E == 16) || s.E > M) return false;
     const int th = M / s.E;
     if (s.G < 1 || th * s.G > 512) return false;
-    const size_t lds = (size_t)s.G * padded_len(M) * (f64 ? 16 : 8);
+    const size_t lds = (size_t)2 * s.G * M * (f64 ? 16 : 8);
     return lds <= 64 * 1024;
 }
 
+// Column pass: G L complex of LDS.
 bool valid_shape_cols(int L, Shape s, bool f64) {
     if (!(s.E == 8 || s.E == 16) || s.E > L) return false;
     const int th = L / s.E;
     if (s.G < 1 || th * s.G > 512) return false;
-    const size_t lds = (size_t)s.G * padded_len(L) * (f64 ? 16 : 8);
+    const size_t lds = (size_t)s.G * L * (f64 ? 16 : 8);
     return lds <= 144 * 1024;
 }
 
@@ -112,32 +111,30 @@ int allow_lds(K kern, size_t lds) {
 
 template <typename T>
 struct Disp {
-    template <int N, int E>
-    static int r2c(const T *in0, const T *in1, int n_arr, int n_rows, cx<T> *o0, cx<T> *o1,
-                   const cx<T> *tw, int G, hipStream_t st) {
+    template <int N, int E, int C>
+    static int r2c(const T *in0, const T *in1, int n_rows, cx<T> *out, const cx<T> *tw, int G,
+                   hipStream_t st) {
         if constexpr (E <= N) {
             constexpr int TH = N / E;
-            const int total = n_arr * n_rows;
-            const int blocks = (total + G - 1) / G;
-            const size_t lds = (size_t)G * padded_len(N) * sizeof(cx<T>);
-            hipLaunchKernelGGL((k_rows_r2c<T, N, E>), dim3(blocks), dim3(G * TH), lds, st, in0,
-                               in1, n_rows, total, o0, o1, tw);
+            const int blocks = (n_rows + G - 1) / G;
+            const size_t lds = (size_t)C * G * N * sizeof(cx<T>);
+            hipLaunchKernelGGL((k_rows_r2c<T, N, E, C>), dim3(blocks), dim3(G * TH), lds, st, in0,
+                               in1, n_rows, out, tw);
             PF_HIP(hipGetLastError());
             return PF_OK;
         }
         set_error("row transform of %d points cannot take %d points per thread", N, E);
         return PF_EUNSUPPORTED;
     }
-    template <int N, int E>
-    static int c2r(const cx<T> *in0, const cx<T> *in1, int n_arr, int n_rows, T *o0, T *o1,
-                   const cx<T> *tw, int G, hipStream_t st) {
+    template <int N, int E, int C>
+    static int c2r(const cx<T> *in, int n_rows, T *o0, T *o1, const cx<T> *tw, int G,
+                   hipStream_t st) {
         if constexpr (E <= N) {
             constexpr int TH = N / E;
-            const int total = n_arr * n_rows;
-            const int blocks = (total + G - 1) / G;
-            const size_t lds = (size_t)G * padded_len(N) * sizeof(cx<T>);
-            hipLaunchKernelGGL((k_rows_c2r<T, N, E>), dim3(blocks), dim3(G * TH), lds, st, in0,
-                               in1, n_rows, total, o0, o1, tw);
+            const int blocks = (n_rows + G - 1) / G;
+            const size_t lds = (size_t)C * G * N * sizeof(cx<T>);
+            hipLaunchKernelGGL((k_rows_c2r<T, N, E, C>), dim3(blocks), dim3(G * TH), lds, st, in,
+                               n_rows, o0, o1, tw);
             PF_HIP(hipGetLastError());
             return PF_OK;
         }
@@ -145,27 +142,28 @@ struct Disp {
         return PF_EUNSUPPORTED;
     }
     template <int N, int E, bool ADJ>
-    static int cols(const Plan &p, const cx<T> *a, const cx<T> *b, cx<T> *o0, cx<T> *o1,
-                    const cx<T> *spec, const cx<T> *tw, int G, hipStream_t st) {
+    static int cols(const Plan &p, const cx<T> *a, cx<T> *o, const cx<T> *spec, const cx<T> *tw,
+                    int G, hipStream_t st) {
         if constexpr (E <= N) {
             constexpr int TH = N / E;
             const int n_groups = (p.H + G - 1) / G;
             const int per_xcd = (n_groups + 7) / 8;
             const int blocks = per_xcd * 8;
-            const size_t lds = (size_t)G * padded_len(N) * sizeof(cx<T>);
+            const size_t lds = (size_t)G * N * sizeof(cx<T>);
             const T ca = T(p.ca), c0 = T(p.c0), cn = T(p.cn);
+            const cx2<T> *sp = reinterpret_cast<const cx2<T> *>(spec);
             if (ADJ) {
                 int rc = allow_lds(k_cols_adj<T, N, E>, lds);
                 if (rc) return rc;
                 hipLaunchKernelGGL((k_cols_adj<T, N, E>), dim3(blocks), dim3(G * TH), lds, st,
-                                   a, b, o0, spec, p.H, p.n_r, p.ldspec, ca, c0, cn, tw,
-                                   per_xcd, n_groups);
+                                   reinterpret_cast<const cx2<T> *>(a), o, sp, p.H, p.n_r,
+                                   p.ldspec, ca, c0, cn, tw, per_xcd, n_groups);
             } else {
                 int rc = allow_lds(k_cols_fwd<T, N, E>, lds);
                 if (rc) return rc;
-                hipLaunchKernelGGL((k_cols_fwd<T, N, E>), dim3(blocks), dim3(G * TH), lds, st,
-                                   a, o0, o1, spec, p.H, p.n_r, p.ldspec, ca, c0, cn, tw,
-                                   per_xcd, n_groups);
+                hipLaunchKernelGGL((k_cols_fwd<T, N, E>), dim3(blocks), dim3(G * TH), lds, st, a,
+                                   reinterpret_cast<cx2<T> *>(o), sp, p.H, p.n_r, p.ldspec, ca,
+                                   c0, cn, tw, per_xcd, n_groups);
             }
             PF_HIP(hipGetLastError());
             return PF_OK;
@@ -174,43 +172,59 @@ struct Disp {
         return PF_EUNSUPPORTED;
     }
     template <int N>
-    static int r2c_e(int E, const T *in0, const T *in1, int n_arr, int n_rows, cx<T> *o0,
-                     cx<T> *o1, const cx<T> *tw, int G, hipStream_t st) {
-        switch (E) {
-            case 4: return r2c<N, 4>(in0, in1, n_arr, n_rows, o0, o1, tw, G, st);
-            case 8: return r2c<N, 8>(in0, in1, n_arr, n_rows, o0, o1, tw, G, st);
-            case 16: return r2c<N, 16>(in0, in1, n_arr, n_rows, o0, o1, tw, G, st);
+    static int r2c_e(int E, const T *in0, const T *in1, int n_rows, cx<T> *out, const cx<T> *tw,
+                     int G, hipStream_t st) {
+        if (in1) {
+            switch (E) {
+                case 4: return r2c<N, 4, 2>(in0, in1, n_rows, out, tw, G, st);
+                case 8: return r2c<N, 8, 2>(in0, in1, n_rows, out, tw, G, st);
+                case 16: return r2c<N, 16, 2>(in0, in1, n_rows, out, tw, G, st);
+            }
+        } else {
+            switch (E) {
+                case 4: return r2c<N, 4, 1>(in0, in1, n_rows, out, tw, G, st);
+                case 8: return r2c<N, 8, 1>(in0, in1, n_rows, out, tw, G, st);
+                case 16: return r2c<N, 16, 1>(in0, in1, n_rows, out, tw, G, st);
+            }
         }
         set_error("bad points per thread %d", E);
         return PF_EUNSUPPORTED;
     }
     template <int N>
-    static int c2r_e(int E, const cx<T> *in0, const cx<T> *in1, int n_arr, int n_rows, T *o0,
-                     T *o1, const cx<T> *tw, int G, hipStream_t st) {
-        switch (E) {
-            case 4: return c2r<N, 4>(in0, in1, n_arr, n_rows, o0, o1, tw, G, st);
-            case 8: return c2r<N, 8>(in0, in1, n_arr, n_rows, o0, o1, tw, G, st);
-            case 16: return c2r<N, 16>(in0, in1, n_arr, n_rows, o0, o1, tw, G, st);
+    static int c2r_e(int E, const cx<T> *in, int n_rows, T *o0, T *o1, const cx<T> *tw, int G,
+                     hipStream_t st) {
+        if (o1) {
+            switch (E) {
+                case 4: return c2r<N, 4, 2>(in, n_rows, o0, o1, tw, G, st);
+                case 8: return c2r<N, 8, 2>(in, n_rows, o0, o1, tw, G, st);
+                case 16: return c2r<N, 16, 2>(in, n_rows, o0, o1, tw, G, st);
+            }
+        } else {
+            switch (E) {
+                case 4: return c2r<N, 4, 1>(in, n_rows, o0, o1, tw, G, st);
+                case 8: return c2r<N, 8, 1>(in, n_rows, o0, o1, tw, G, st);
+                case 16: return c2r<N, 16, 1>(in, n_rows, o0, o1, tw, G, st);
+            }
         }
         set_error("bad points per thread %d", E);
         return PF_EUNSUPPORTED;
     }
     template <int N>
-    static int fwd_e(int E, const Plan &p, const cx<T> *a, cx<T> *o0, cx<T> *o1,
-                     const cx<T> *spec, const cx<T> *tw, int G, hipStream_t st) {
+    static int fwd_e(int E, const Plan &p, const cx<T> *a, cx<T> *o, const cx<T> *spec,
+                     const cx<T> *tw, int G, hipStream_t st) {
         switch (E) {
-            case 8: return cols<N, 8, false>(p, a, nullptr, o0, o1, spec, tw, G, st);
-            case 16: return cols<N, 16, false>(p, a, nullptr, o0, o1, spec, tw, G, st);
+            case 8: return cols<N, 8, false>(p, a, o, spec, tw, G, st);
+            case 16: return cols<N, 16, false>(p, a, o, spec, tw, G, st);
         }
         set_error("bad points per thread %d", E);
         return PF_EUNSUPPORTED;
     }
     template <int N>
-    static int adj_e(int E, const Plan &p, const cx<T> *a, const cx<T> *b, cx<T> *o0,
-                     const cx<T> *spec, const cx<T> *tw, int G, hipStream_t st) {
+    static int adj_e(int E, const Plan &p, const cx<T> *a, cx<T> *o, const cx<T> *spec,
+                     const cx<T> *tw, int G, hipStream_t st) {
         switch (E) {
-            case 8: return cols<N, 8, true>(p, a, b, o0, nullptr, spec, tw, G, st);
-            case 16: return cols<N, 16, true>(p, a, b, o0, nullptr, spec, tw, G, st);
+            case 8: return cols<N, 8, true>(p, a, o, spec, tw, G, st);
+            case 16: return cols<N, 16, true>(p, a, o, spec, tw, G, st);
         }
         set_error("bad points per thread %d", E);
         return PF_EUNSUPPORTED;
@@ -220,67 +234,55 @@ struct Disp {
 }  // namespace
 
 template <typename T>
-int launch_rows_r2c(const Plan &p, const T *in0, const T *in1, int n_arr, int n_rows,
-                    cx<T> *out0, cx<T> *out1, const cx<T> *twN, Shape s, hipStream_t st) {
+int launch_rows_r2c(const Plan &p, const T *in0, const T *in1, int n_rows, cx<T> *out,
+                    const cx<T> *twN, Shape s, hipStream_t st) {
     if (!valid_shape_rows(p.M, s, sizeof(T) == 8)) {
         set_error("invalid row shape E=%d G=%d for M=%d", s.E, s.G, p.M);
         return PF_EINVAL;
     }
-    PF_SWITCH_POW2(p.M, Disp<T>::template r2c_e, s.E, in0, in1, n_arr, n_rows, out0, out1, twN,
-                   s.G, st);
+    PF_SWITCH_POW2(p.M, Disp<T>::template r2c_e, s.E, in0, in1, n_rows, out, twN, s.G, st);
 }
 
 template <typename T>
-int launch_rows_c2r(const Plan &p, const cx<T> *in0, const cx<T> *in1, int n_arr, int n_rows,
-                    T *out0, T *out1, const cx<T> *twN, Shape s, hipStream_t st) {
+int launch_rows_c2r(const Plan &p, const cx<T> *in, int n_rows, T *out0, T *out1,
+                    const cx<T> *twN, Shape s, hipStream_t st) {
     if (!valid_shape_rows(p.M, s, sizeof(T) == 8)) {
         set_error("invalid row shape E=%d G=%d for M=%d", s.E, s.G, p.M);
         return PF_EINVAL;
     }
-    PF_SWITCH_POW2(p.M, Disp<T>::template c2r_e, s.E, in0, in1, n_arr, n_rows, out0, out1, twN,
-                   s.G, st);
+    PF_SWITCH_POW2(p.M, Disp<T>::template c2r_e, s.E, in, n_rows, out0, out1, twN, s.G, st);
 }
 
 template <typename T>
-int launch_cols_fwd(const Plan &p, const cx<T> *S, cx<T> *Zr, cx<T> *Zp, const cx<T> *spec,
+int launch_cols_fwd(const Plan &p, const cx<T> *S, cx<T> *Z, const cx<T> *spec,
                     const cx<T> *twL, Shape s, hipStream_t st) {
     if (!valid_shape_cols(p.L, s, sizeof(T) == 8)) {
         set_error("invalid column shape E=%d G=%d for L=%d", s.E, s.G, p.L);
         return PF_EINVAL;
     }
-    PF_SWITCH_POW2(p.L, Disp<T>::template fwd_e, s.E, p, S, Zr, Zp, spec, twL, s.G, st);
+    PF_SWITCH_POW2(p.L, Disp<T>::template fwd_e, s.E, p, S, Z, spec, twL, s.G, st);
 }
 
 template <typename T>
-int launch_cols_adj(const Plan &p, const cx<T> *Vr, const cx<T> *Vp, cx<T> *D,
-                    const cx<T> *spec, const cx<T> *twL, Shape s, hipStream_t st) {
+int launch_cols_adj(const Plan &p, const cx<T> *V, cx<T> *D, const cx<T> *spec,
+                    const cx<T> *twL, Shape s, hipStream_t st) {
     if (!valid_shape_cols(p.L, s, sizeof(T) == 8)) {
         set_error("invalid column shape E=%d G=%d for L=%d", s.E, s.G, p.L);
         return PF_EINVAL;
     }
-    PF_SWITCH_POW2(p.L, Disp<T>::template adj_e, s.E, p, Vr, Vp, D, spec, twL, s.G, st);
+    PF_SWITCH_POW2(p.L, Disp<T>::template adj_e, s.E, p, V, D, spec, twL, s.G, st);
 }
 
-template int launch_rows_r2c<float>(const Plan &, const float *, const float *, int, int,
-                                    cx<float> *, cx<float> *, const cx<float> *, Shape, hipStream_t);
-template int launch_rows_r2c<double>(const Plan &, const double *, const double *, int, int,
-                                     cx<double> *, cx<double> *, const cx<double> *, Shape,
-                                     hipStream_t);
-template int launch_rows_c2r<float>(const Plan &, const cx<float> *, const cx<float> *, int, int,
-                                    float *, float *, const cx<float> *, Shape, hipStream_t);
-template int launch_rows_c2r<double>(const Plan &, const cx<double> *, const cx<double> *, int,
-                                     int, double *, double *, const cx<double> *, Shape,
-                                     hipStream_t);
-template int launch_cols_fwd<float>(const Plan &, const cx<float> *, cx<float> *, cx<float> *,
-                                    const cx<float> *, const cx<float> *, Shape, hipStream_t);
-template int launch_cols_fwd<double>(const Plan &, const cx<double> *, cx<double> *,
-                                     cx<double> *, const cx<double> *, const cx<double> *, Shape,
-                                     hipStream_t);
-template int launch_cols_adj<float>(const Plan &, const cx<float> *, const cx<float> *,
-                                    cx<float> *, const cx<float> *, const cx<float> *, Shape,
-                                    hipStream_t);
-template int launch_cols_adj<double>(const Plan &, const cx<double> *, const cx<double> *,
-                                     cx<double> *, const cx<double> *, const cx<double> *, Shape,
-                                     hipStream_t);
+#define PF_INSTANTIATE(T)                                                                      \
+    template int launch_rows_r2c<T>(const Plan &, const T *, const T *, int, cx<T> *,          \
+                                    const cx<T> *, Shape, hipStream_t);                         \
+    template int launch_rows_c2r<T>(const Plan &, const cx<T> *, int, T *, T *, const cx<T> *,  \
+                                    Shape, hipStream_t);                                        \
+    template int launch_cols_fwd<T>(const Plan &, const cx<T> *, cx<T> *, const cx<T> *,        \
+                                    const cx<T> *, Shape, hipStream_t);                         \
+    template int launch_cols_adj<T>(const Plan &, const cx<T> *, cx<T> *, const cx<T> *,        \
+                                    const cx<T> *, Shape, hipStream_t);
+PF_INSTANTIATE(float)
+PF_INSTANTIATE(double)
 
 }  // namespace pf

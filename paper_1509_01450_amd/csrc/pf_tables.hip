@@ -390,7 +390,7 @@ __global__ __launch_bounds__(256) void k_cover_final(const double *__restrict__ 
 // ---------------------------------------------------------------------------
 // Column transforms of the row-transformed tables and the fold into the four
 // spectra.  rowspec: [6][L][M] complex FP64 in the packed half spectrum
-// (column 0 = (bin 0, bin M)).  spec: [4][M][ldspec].
+// (column 0 = (bin 0, bin M)).  spec: [2][M][ldspec] pairs (E', Q).
 // One block per azimuthal bin kb in [0, M] (bins 0 and M read the real and
 // imaginary parts of packed column 0), L/E threads.  With s = 1/(L n_phi),
 // sk = sin(2 pi kb / n_phi) / dphi (the azimuthal central difference) and
@@ -398,14 +398,15 @@ __global__ __launch_bounds__(256) void k_cover_final(const double *__restrict__ 
 //   Q_r  = s FFT(beta^m T_rr)         E_r = s (FFT(T_r0) + i sk FFT(T_rphi))
 //   Q_p  = s FFT(beta^m T_phir)       E_p = s (FFT(T_phi0) + i sk FFT(T_phiphi))
 //   E'   = E + D Q
-// Bins 1..M-1 store (E'_r, Q_r, E'_p, Q_p) in their column; bin 0 stores
-// (E'_r, Q_r) in slots 0, 1 of column 0 and bin M in slots 2, 3 (the
-// azimuthal spectra vanish at both: the kernels K^{phi,*} are odd in phi).
+// Bins 1..M-1 store the pairs (E'_r, Q_r) and (E'_p, Q_p) in their column;
+// column 0 holds the radial pair of bin 0 first and that of bin M second
+// (the azimuthal spectra vanish at both: the kernels K^{phi,*} are odd in
+// phi).
 // ---------------------------------------------------------------------------
 template <int L, int E>
 __global__ __launch_bounds__(512) void k_fold(const cx<double> *__restrict__ rowspec, int M,
                                               int n_r, int n_phi, double lnb, double dphi,
-                                              double ca, cx<double> *__restrict__ spec,
+                                              double ca, cx2<double> *__restrict__ spec,
                                               int ldspec, const cx<double> *__restrict__ twL) {
     constexpr int TH = L / E;
     extern __shared__ unsigned char smem_raw[];
@@ -434,16 +435,16 @@ __global__ __launch_bounds__(512) void k_fold(const cx<double> *__restrict__ row
         }
         fft_fwd<L, E, double>(v, t, lds, tw);
     };
-    auto store = [&](int slot, const cx<double>(&v)[E]) {
-        cx<double> *dst = spec + ((size_t)slot * M + src) * ldspec;
+    auto store = [&](int pair, const cx<double>(&ev)[E], const cx<double>(&qv)[E]) {
+        cx2<double> *dst = spec + ((size_t)pair * M + src) * ldspec;
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             const int ku = t + e * TH;
-            if (ku <= L / 2) dst[ku] = v[e];
+            if (ku <= L / 2) dst[ku] = cx2<double>{ev[e], qv[e]};
         }
     };
     // (E', Q) of one channel from the tables (t0, tr, tphi)
-    auto channel = [&](int t0, int tr, int tphi, int slot_e, int slot_q) {
+    auto channel = [&](int t0, int tr, int tphi, int pair) {
         cx<double> q[E], a[E], b[E];
         load(tr, true, q);
         load(t0, false, a);
@@ -457,14 +458,13 @@ __global__ __launch_bounds__(512) void k_fold(const cx<double> *__restrict__ row
             a[e] = cx<double>{ee.x - d * qe.y, ee.y + d * qe.x};   // E + i d Q
             q[e] = qe;
         }
-        store(slot_e, a);
-        store(slot_q, q);
+        store(pair, a, q);
     };
     if (part == 2)
-        channel(0, 1, 2, 2, 3);       // bin M radial spectra into column 0, slots 2, 3
+        channel(0, 1, 2, 1);       // bin M's radial pair into column 0's second pair
     else
-        channel(0, 1, 2, 0, 1);
-    if (part == 0) channel(3, 4, 5, 2, 3);
+        channel(0, 1, 2, 0);
+    if (part == 0) channel(3, 4, 5, 1);
 }
 
 __global__ void k_to_f32(const cx<double> *__restrict__ in, cx<float> *__restrict__ out, long n) {
@@ -476,7 +476,7 @@ __global__ void k_to_f32(const cx<double> *__restrict__ in, cx<float> *__restric
 namespace {
 
 template <int L, int E>
-int fold_launch(const cx<double> *rowspec, const Plan &p, cx<double> *spec,
+int fold_launch(const cx<double> *rowspec, const Plan &p, cx2<double> *spec,
                 const cx<double> *twL, hipStream_t st) {
     if constexpr (E <= L) {
         const size_t lds = (size_t)padded_len(L) * sizeof(cx<double>);
@@ -493,7 +493,7 @@ int fold_launch(const cx<double> *rowspec, const Plan &p, cx<double> *spec,
     return PF_EUNSUPPORTED;
 }
 
-int fold_dispatch(const cx<double> *rowspec, const Plan &p, cx<double> *spec,
+int fold_dispatch(const cx<double> *rowspec, const Plan &p, cx2<double> *spec,
                   const cx<double> *twL, hipStream_t st) {
     switch (p.L) {
         case 8: return fold_launch<8, 8>(rowspec, p, spec, twL, st);
@@ -578,14 +578,14 @@ int build_tables_and_spectra(Plan &p, hipStream_t st) {
     PF_HIP(hipMalloc(&rowspec.p, (size_t)6 * p.L * p.M * sizeof(cx<double>)));
     {
         Shape s = default_schedule(p.n_phi, p.L, true).rows;
-        rc = launch_rows_r2c<double>(p, (const double *)tab.p, nullptr, 1, 6 * p.L,
-                                     (cx<double> *)rowspec.p, nullptr,
-                                     (const cx<double> *)twN64.p, s, st);
+        rc = launch_rows_r2c<double>(p, (const double *)tab.p, nullptr, 6 * p.L,
+                                     (cx<double> *)rowspec.p, (const cx<double> *)twN64.p, s,
+                                     st);
         if (rc) return rc;
     }
     const size_t nspec = (size_t)4 * p.M * p.ldspec;
     PF_HIP(hipMalloc(&spec64.p, nspec * sizeof(cx<double>)));
-    rc = fold_dispatch((const cx<double> *)rowspec.p, p, (cx<double> *)spec64.p,
+    rc = fold_dispatch((const cx<double> *)rowspec.p, p, (cx2<double> *)spec64.p,
                        (const cx<double> *)twL64.p, st);
     if (rc) return rc;
 
