@@ -50,12 +50,13 @@ def _load():
     lib.or_geometry.argtypes = [i, i, d, d, P, P, P, P]
     lib.or_gauss_legendre.argtypes = [i, P, P]
     lib.or_selfcell_cover.argtypes = [d, d, i, P, P]
-    lib.or_table_entry.argtypes = [i, i, d, d, i, i, i, P, P]
-    lib.or_tables.argtypes = [i, i, d, d, i, P, P]
+    lib.or_selfcell_pv.argtypes = [d, d, P]
+    lib.or_table_entry.argtypes = [i, i, d, d, i, i, i, i, P, P]
+    lib.or_tables.argtypes = [i, i, d, d, i, i, P, P]
     lib.or_channels.argtypes = [i, i, P, d, P, P, P]
     lib.or_forward.argtypes = [i, i, d, d, P, P, P, i64, P, P]
     lib.or_adjoint.argtypes = [i, i, d, d, P, P, P, P, i64, P]
-    for f in ("or_geometry", "or_gauss_legendre", "or_selfcell_cover",
+    for f in ("or_geometry", "or_gauss_legendre", "or_selfcell_cover", "or_selfcell_pv",
               "or_table_entry", "or_tables", "or_channels", "or_forward",
               "or_adjoint", "or_num_threads"):
         getattr(lib, f).restype = i
@@ -129,30 +130,56 @@ def selfcell_cover(beta: float, dphi: float, per: int = 10):
     return float(out[0]), float(out[1]), float(out[2]), int(n[0])
 
 
-def table_entry(grid: Grid, m: int, n_rep: int, n_tpz: int = 19, self_k=None):
+def selfcell_pv(beta: float, dphi: float):
+    """Self-cell kernels as the exact integrals (principal value for
+    K^{r,0}) in local polar coordinates about the cell centre.
+
+    Returns (K^{r,0}_{00}, K^{r,r}_{00}, K^{phi,phi}_{00})."""
+    out = np.empty(3)
+    if _load().or_selfcell_pv(float(beta), float(dphi), _p(out)):
+        raise ValueError("bad self-cell arguments")
+    return float(out[0]), float(out[1]), float(out[2])
+
+
+_TABLE_MODES = {"sim": 0, "exact": 1}
+
+
+def table_entry(grid: Grid, m: int, n_rep: int, n_tpz: int = 19, self_k=None,
+                table_mode: str = "sim"):
     """All six kernels for offset (m, n_rep) (Eq. 30-32, 41-43, A22-A24).
 
-    ``self_k`` supplies the three self-cell constants used at (0, 0)."""
+    table_mode "sim": n_tpz trapezoids in the azimuth (Eq. 41-43); "exact":
+    the same azimuthal integrals converged.  ``self_k`` supplies the three
+    self-cell constants used at (0, 0)."""
     sk = _f64(self_k if self_k is not None else np.zeros(3))
     t = np.empty(6)
     if _load().or_table_entry(grid.n_r, grid.n_phi, grid.r_min, grid.r_max,
-                              int(n_tpz), int(m), int(n_rep), _p(sk), _p(t)):
+                              int(n_tpz), _TABLE_MODES[table_mode], int(m), int(n_rep),
+                              _p(sk), _p(t)):
         raise ValueError("bad arguments")
     return t
 
 
-def tables(grid: Grid, n_tpz: int = 19, cover_per: int = 10, self_k=None):
+def tables(grid: Grid, n_tpz: int = 19, cover_per: int = 10, self_k=None,
+           table_mode: str = "sim", self_mode: str = "cartesian"):
     """Six kernel tables, shape (6, 2 N_r - 1, N_phi); row m + N_r - 1,
     column n = (j - j') mod N_phi; order r0, rr, rphi, phi0, phir, phiphi.
 
-    The self cell comes from :func:`selfcell_cover` unless ``self_k`` is
-    given."""
+    table_mode "sim" (the paper's trapezoids, Eq. 41-43) or "exact"
+    (converged azimuthal integrals).  The self cell comes from
+    :func:`selfcell_cover` (self_mode "cartesian", Sec. 4) or
+    :func:`selfcell_pv` (self_mode "exact") unless ``self_k`` is given."""
     if self_k is None:
-        self_k = selfcell_cover(grid.beta, grid.dphi, cover_per)[:3]
+        if self_mode == "exact":
+            self_k = selfcell_pv(grid.beta, grid.dphi)
+        elif self_mode == "cartesian":
+            self_k = selfcell_cover(grid.beta, grid.dphi, cover_per)[:3]
+        else:
+            raise ValueError("self_mode must be 'cartesian' or 'exact'")
     sk = _f64(self_k)
     T = np.empty((6, 2 * grid.n_r - 1, grid.n_phi))
     if _load().or_tables(grid.n_r, grid.n_phi, grid.r_min, grid.r_max,
-                         int(n_tpz), _p(sk), _p(T)):
+                         int(n_tpz), _TABLE_MODES[table_mode], _p(sk), _p(T)):
         raise ValueError("bad arguments")
     return T
 

@@ -17,7 +17,10 @@
  *     azimuth applied to the exact radial integral (Eq. 41-43), exact double
  *     antiderivatives for K^{phi,0} and K^{phi,r} (A30-A31), and the self cell
  *     from a Cartesian cover evaluated with the Cartesian second-order method
- *     (Eq. 44-46, Eq. 9-15, A8-A13);
+ *     (Eq. 44-46, Eq. 9-15, A8-A13); and, as the converged reference of
+ *     the same definitions, the azimuthal integrals by adaptive quadrature
+ *     (table mode 1) and the self cell as the exact (principal-value)
+ *     integrals in local polar coordinates;
  *   - the cell density and slopes (Eq. 25, central differences);
  *   - the forces as the plain double sums of Eq. 27-29 and A19-A21,
  *     O((N_r N_phi)^2), at any chosen set of destination cells;
@@ -141,6 +144,73 @@ static inline void acc_add(acc_t *a, double x)
     a->s = t;
 }
 static inline double acc_get(const acc_t *a) { return a->s + a->c; }
+
+/* ------------------------------------------------------------------------ */
+/* Adaptive quadrature of K smooth functions at once: 16-point Gauss-Legendre */
+/* on [a, b] against 16-point Gauss-Legendre on its two halves; an interval  */
+/* is accepted when every component agrees to tol[k] (absolute), otherwise  */
+/* both halves are refined.  tol[k] = rel * int |f_k| over the whole range   */
+/* (a scale that does not vanish when int f_k does by symmetry).  At most    */
+/* AD_BUDGET subdivisions per call: where rounding in the integrand (the    */
+/* cancellation in the closed antiderivatives) keeps the two estimates from  */
+/* agreeing to tol, refinement stops there.  The accepted value is the       */
+/* two-half sum.                                                             */
+/* ------------------------------------------------------------------------ */
+#define AD_KMAX 4
+#define AD_BUDGET 2000
+typedef void (*ad_fn)(double x, void *ctx, double *out);
+
+static void gl16_on(ad_fn f, void *ctx, int K, double a, double b, double *out, double *aout)
+{
+    const double *x = gl_x[16], *w = gl_w[16];
+    const double mid = 0.5 * (a + b), half = 0.5 * (b - a);
+    double v[AD_KMAX];
+    for (int k = 0; k < K; ++k) {
+        out[k] = 0.0;
+        if (aout) aout[k] = 0.0;
+    }
+    for (int i = 0; i < 16; ++i) {
+        f(mid + half * x[i], ctx, v);
+        for (int k = 0; k < K; ++k) {
+            out[k] += w[i] * v[k];
+            if (aout) aout[k] += w[i] * fabs(v[k]);
+        }
+    }
+    for (int k = 0; k < K; ++k) {
+        out[k] *= half;
+        if (aout) aout[k] *= fabs(half);
+    }
+}
+
+static void adapt_rec(ad_fn f, void *ctx, int K, double a, double b, const double *whole,
+                      const double *tol, int depth, int *budget, double *out)
+{
+    const double m = 0.5 * (a + b);
+    double l[AD_KMAX], r[AD_KMAX];
+    gl16_on(f, ctx, K, a, m, l, NULL);
+    gl16_on(f, ctx, K, m, b, r, NULL);
+    int ok = 1;
+    for (int k = 0; k < K; ++k)
+        if (fabs(l[k] + r[k] - whole[k]) > tol[k]) ok = 0;
+    if (ok || depth >= 40 || *budget <= 0) {
+        for (int k = 0; k < K; ++k) out[k] = l[k] + r[k];
+        return;
+    }
+    --*budget;
+    double lo[AD_KMAX], hi[AD_KMAX];
+    adapt_rec(f, ctx, K, a, m, l, tol, depth + 1, budget, lo);
+    adapt_rec(f, ctx, K, m, b, r, tol, depth + 1, budget, hi);
+    for (int k = 0; k < K; ++k) out[k] = lo[k] + hi[k];
+}
+
+static void adapt_gl(ad_fn f, void *ctx, int K, double a, double b, double rel, double *out)
+{
+    double whole[AD_KMAX], mag[AD_KMAX], tol[AD_KMAX];
+    gl16_on(f, ctx, K, a, b, whole, mag);
+    for (int k = 0; k < K; ++k) tol[k] = rel * mag[k] + 1e-300;
+    int budget = AD_BUDGET;
+    adapt_rec(f, ctx, K, a, b, whole, tol, 0, &budget, out);
+}
 
 /* ------------------------------------------------------------------------ */
 /* Grid (Sec. 3.2.1, generalised to N_r x N_phi).                             */
@@ -437,11 +507,118 @@ int or_selfcell_cover(double beta, double dphi, int per, double *out,
 }
 
 /* ------------------------------------------------------------------------ */
+/* Self cell as the exact integrals (principal value for K^{r,0}), in local    */
+/* polar coordinates (rho, t) about the cell centre x = (1, 0), xbar - x =   */
+/* rho (cos t, sin t), rho up to the fan's boundary rho_max(t):              */
+/*   K^{r,0}_{00}     = int cos t ln rho_max(t) dt                           */
+/*   K^{r,r}_{00}     = int cos t int_0^rho_max (|xbar| - 1) / rho drho dt    */
+/*   K^{phi,phi}_{00} = int sin t int_0^rho_max xi(xbar) / rho drho dt,       */
+/* xi(xbar) the azimuth of xbar.  (From Eq. 30-32 with eta deta dxi = dA,     */
+/* (1 - eta cos xi) = -rho cos t, eta sin xi = rho sin t, F = rho; the        */
+/* log(0) part of K^{r,0} cancels over the full circle.)  The t-integrals     */
+/* are split at the four corner directions, where rho_max has kinks.         */
+/* ------------------------------------------------------------------------ */
+typedef struct { double r_in, r_out, a; } fan_t;
+
+static double fan_rho_max(const fan_t *f, double t)
+{
+    const double c = cos(t), s = sin(t);
+    double best = -c + sqrt(c * c + f->r_out * f->r_out - 1.0);
+    const double disc = c * c - (1.0 - f->r_in * f->r_in);
+    if (disc >= 0.0) {
+        const double q = sqrt(disc);
+        if (-c - q > 0.0 && -c - q < best) best = -c - q;
+        if (-c + q > 0.0 && -c + q < best) best = -c + q;
+    }
+    for (int sg = -1; sg <= 1; sg += 2) {
+        const double sa = sg * f->a;
+        const double den = s * cos(sa) - c * sin(sa);
+        if (den != 0.0) {
+            const double rr = sin(sa) / den;
+            if (rr > 0.0 && rr < best) best = rr;
+        }
+    }
+    return best;
+}
+
+static void pv_integrand(double t, void *vctx, double *out)
+{
+    const fan_t *f = (const fan_t *)vctx;
+    const double c = cos(t), s = sin(t), rm = fan_rho_max(f, t);
+    const int n = 24;
+    double a = 0.0, b = 0.0;
+    for (int k = 0; k < n; ++k) {
+        const double rho = 0.5 * rm * (1.0 + gl_x[n][k]);
+        const double X = 1.0 + rho * c, Y = rho * s;
+        const double R = hypot(X, Y);
+        /* (|xbar| - 1)/rho = (2c + rho)/(|xbar| + 1), no cancellation */
+        a += gl_w[n][k] * (2.0 * c + rho) / (R + 1.0);
+        b += gl_w[n][k] * atan2(Y, X) / rho;
+    }
+    out[0] = c * log(rm);
+    out[1] = c * 0.5 * rm * a;
+    out[2] = s * 0.5 * rm * b;
+}
+
+int or_selfcell_pv(double beta, double dphi, double *out)
+{
+    if (!(beta > 1.0) || !(dphi > 0.0) || dphi >= OR_PI || !out) return -1;
+    gl_init();
+    fan_t f;
+    f.r_in = 2.0 / (1.0 + beta);
+    f.r_out = 2.0 * beta / (1.0 + beta);
+    f.a = 0.5 * dphi;
+    double brk[6];
+    int nb = 0;
+    brk[nb++] = 0.0;
+    for (int i = 0; i < 2; ++i)
+        for (int sg = -1; sg <= 1; sg += 2) {
+            const double R = i ? f.r_out : f.r_in, sa = sg * f.a;
+            double t = atan2(R * sin(sa), R * cos(sa) - 1.0);
+            if (t < 0.0) t += 2.0 * OR_PI;
+            brk[nb++] = t;
+        }
+    brk[nb++] = 2.0 * OR_PI;
+    /* sort the break points */
+    for (int i = 1; i < nb; ++i)
+        for (int j = i; j > 0 && brk[j] < brk[j - 1]; --j) {
+            double x = brk[j]; brk[j] = brk[j - 1]; brk[j - 1] = x;
+        }
+    double acc[3] = {0, 0, 0};
+    for (int i = 0; i + 1 < nb; ++i) {
+        if (brk[i + 1] - brk[i] <= 0.0) continue;
+        double v[3];
+        adapt_gl(pv_integrand, &f, 3, brk[i], brk[i + 1], 1e-15, v);
+        for (int k = 0; k < 3; ++k) acc[k] += v[k];
+    }
+    for (int k = 0; k < 3; ++k) out[k] = acc[k];
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
 /* One table entry (all six kernels) for offset (m, n_rep).                   */
 /* Output order: r0, rr, rphi, phi0, phir, phiphi.                            */
 /* self = K^{r,0}_{00}, K^{r,r}_{00}, K^{phi,phi}_{00} (used at m = n = 0).   */
 /* ------------------------------------------------------------------------ */
-static void table_entry(double beta, double dphi, int n_tpz, int m, int nrep,
+/* integrand of the four azimuthal integrals at xi (EXACT mode) */
+typedef struct { double eta_l, eta_u, rho, xic; int m; } xi_ctx;
+
+static void xi_integrand(double xi, void *vctx, double *out)
+{
+    const xi_ctx *c = (const xi_ctx *)vctx;
+    int closed = (c->m == 0) && (fabs(xi) < 0.5 * OR_PI);
+    double Ir, Ir2, Iph;
+    radial_integrals(c->eta_l, c->eta_u, xi, closed, &Ir, &Ir2, &Iph);
+    double wl = xi - c->xic;
+    out[0] = Ir;
+    out[1] = Ir2 - c->rho * Ir;
+    out[2] = wl * Ir;
+    out[3] = wl * Iph;
+}
+
+/* table_mode 0: SIM, n_tpz trapezoids in xi (Eq. 41-43); 1: the same
+ * azimuthal integrals converged (adaptive Gauss-Legendre, split at xi = 0). */
+static void table_entry(double beta, double dphi, int n_tpz, int table_mode, int m, int nrep,
                         const double self[3], double T[6])
 {
     if (m == 0 && nrep == 0) {
@@ -457,21 +634,37 @@ static void table_entry(double beta, double dphi, int n_tpz, int m, int nrep,
     const double eta_l = 2.0 * rho / (1.0 + beta);
     const double eta_u = beta * eta_l;
     const double xic = -nrep * dphi;
-    const double dth = dphi / n_tpz;
-
-    /* Eq. 41-43 with the weight (xi - xi_c) inside the trapezoid */
     double r0 = 0, rr = 0, rph = 0, pp = 0;
-    for (int k = 0; k <= n_tpz; ++k) {
-        double xi = xic - 0.5 * dphi + k * dth;
-        double wk = (k == 0 || k == n_tpz) ? 0.5 * dth : dth;
-        int closed = (m == 0) && (fabs(xi) < 0.5 * OR_PI);
-        double Ir, Ir2, Iph;
-        radial_integrals(eta_l, eta_u, xi, closed, &Ir, &Ir2, &Iph);
-        double wl = xi - xic;
-        r0 += wk * Ir;
-        rr += wk * (Ir2 - rho * Ir);
-        rph += wk * wl * Ir;
-        pp += wk * wl * Iph;
+    if (table_mode == 1) {
+        xi_ctx c = {eta_l, eta_u, rho, xic, m};
+        double lo = xic - 0.5 * dphi, hi = xic + 0.5 * dphi, v[4];
+        if (lo < 0.0 && hi > 0.0) {   /* peak (or singular point) at xi = 0 */
+            double v2[4];
+            adapt_gl(xi_integrand, &c, 4, lo, 0.0, 4e-15, v);
+            adapt_gl(xi_integrand, &c, 4, 0.0, hi, 4e-15, v2);
+            for (int k = 0; k < 4; ++k) v[k] += v2[k];
+        } else {
+            adapt_gl(xi_integrand, &c, 4, lo, hi, 4e-15, v);
+        }
+        r0 = v[0];
+        rr = v[1];
+        rph = v[2];
+        pp = v[3];
+    } else {
+        /* Eq. 41-43 with the weight (xi - xi_c) inside the trapezoid */
+        const double dth = dphi / n_tpz;
+        for (int k = 0; k <= n_tpz; ++k) {
+            double xi = xic - 0.5 * dphi + k * dth;
+            double wk = (k == 0 || k == n_tpz) ? 0.5 * dth : dth;
+            int closed = (m == 0) && (fabs(xi) < 0.5 * OR_PI);
+            double Ir, Ir2, Iph;
+            radial_integrals(eta_l, eta_u, xi, closed, &Ir, &Ir2, &Iph);
+            double wl = xi - xic;
+            r0 += wk * Ir;
+            rr += wk * (Ir2 - rho * Ir);
+            rph += wk * wl * Ir;
+            pp += wk * wl * Iph;
+        }
     }
     T[0] = -r0;
     T[1] = -rr;
@@ -507,13 +700,13 @@ static void table_entry(double beta, double dphi, int n_tpz, int m, int nrep,
 }
 
 int or_table_entry(int n_r, int n_phi, double r_min, double r_max, int n_tpz,
-                   int m, int nrep, const double *self, double *T)
+                   int table_mode, int m, int nrep, const double *self, double *T)
 {
     double beta, dphi;
     if (or_geometry(n_r, n_phi, r_min, r_max, NULL, NULL, &beta, &dphi)) return -1;
-    if (n_tpz < 1) return -1;
+    if ((table_mode == 0 && n_tpz < 1) || table_mode < 0 || table_mode > 1) return -1;
     gl_init();
-    table_entry(beta, dphi, n_tpz, m, nrep, self, T);
+    table_entry(beta, dphi, n_tpz, table_mode, m, nrep, self, T);
     return 0;
 }
 
@@ -522,11 +715,12 @@ int or_table_entry(int n_r, int n_phi, double r_min, double r_max, int n_tpz,
  * the parity of each integrand in xi (even: r0, rr, phiphi; odd: rphi,
  * phi0, phir), which holds for every cell of the periodic grid. */
 int or_tables(int n_r, int n_phi, double r_min, double r_max, int n_tpz,
-              const double *self, double *T)
+              int table_mode, const double *self, double *T)
 {
     double beta, dphi;
     if (or_geometry(n_r, n_phi, r_min, r_max, NULL, NULL, &beta, &dphi)) return -1;
-    if (n_tpz < 1 || (n_phi % 2) != 0) return -1;
+    if ((table_mode == 0 && n_tpz < 1) || table_mode < 0 || table_mode > 1 || (n_phi % 2) != 0)
+        return -1;
     gl_init();
     const long rows = 2L * n_r - 1;
     const long plane = rows * (long)n_phi;
@@ -538,7 +732,7 @@ int or_tables(int n_r, int n_phi, double r_min, double r_max, int n_tpz,
         for (int nrep = 0; nrep <= n_phi / 2; ++nrep) {
             int m = (int)(row - (n_r - 1));
             double t[6];
-            table_entry(beta, dphi, n_tpz, m, nrep, self, t);
+            table_entry(beta, dphi, n_tpz, table_mode, m, nrep, self, t);
             long cpos = nrep, cneg = (n_phi - nrep) % n_phi;
             for (int k = 0; k < 6; ++k) {
                 T[k * plane + row * n_phi + cpos] = t[k];

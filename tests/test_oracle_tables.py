@@ -119,6 +119,57 @@ def test_trapezoid_error_law():
         assert 3.8 < e19 / e39 < 4.6, (m, n, e19, e39)
 
 
+def _exact_reference_entry(g, m, n):
+    """The six kernels of Eq. 30-32 (A22-A24) as nested adaptive quadrature
+    over the whole source cell: the converged definition the exact table
+    mode computes (no trapezoid).  The xi range is split at 0 when the cell
+    contains it, the eta range at the singular ring eta = 1."""
+    b, dp = g.beta, g.dphi
+    rho = b ** (-m)
+    el = 2 * rho / (1 + b)
+    eu = b * el
+    xc = -n * dp
+    pts = [1.0] if el < 1 < eu else None
+    fr = lambda e, xi: e * (1 - e * np.cos(xi)) / _F(e, xi) ** 3
+    fp = lambda e, xi: e * e * np.sin(xi) / _F(e, xi) ** 3
+    integrands = [lambda e, xi: -fr(e, xi),
+                  lambda e, xi: -fr(e, xi) * (e - rho),
+                  lambda e, xi: -fr(e, xi) * (xi - xc),
+                  lambda e, xi: fp(e, xi),
+                  lambda e, xi: fp(e, xi) * (e - rho),
+                  lambda e, xi: fp(e, xi) * (xi - xc)]
+    lo, hi = xc - dp / 2, xc + dp / 2
+    cuts = [lo, 0.0, hi] if lo < 0 < hi else [lo, hi]
+    out = []
+    for f in integrands:
+        inner = lambda xi: integrate.quad(lambda e: f(e, xi), el, eu, epsabs=0, epsrel=2e-14,
+                                          limit=200, points=pts)[0]
+        out.append(sum(integrate.quad(inner, a, c, epsabs=1e-16, epsrel=1e-13, limit=200)[0]
+                       for a, c in zip(cuts[:-1], cuts[1:])))
+    return np.array(out)
+
+
+@pytest.mark.parametrize("m,n", [(0, 1), (1, 0), (-1, 0), (1, 1), (-2, 3), (5, 7), (0, 16)])
+def test_exact_entries_match_2d_quadrature(m, n):
+    t = oracle.table_entry(G32, m, n, table_mode="exact")
+    e = _exact_reference_entry(G32, m, n)
+    np.testing.assert_allclose(t, e, rtol=0, atol=2e-13)
+
+
+def test_trapezoid_tables_converge_to_exact_tables():
+    # the SIM tables approach the exact tables as N_tpz^-2 (Eq. 41-43)
+    sk = oracle.selfcell_pv(G32.beta, G32.dphi)
+    te = oracle.tables(G32, self_k=sk, table_mode="exact")
+    err = {}
+    for nt in (19, 39):
+        ts = oracle.tables(G32, nt, self_k=sk)
+        err[nt] = np.array([np.abs(ts[k] - te[k]).max() / np.abs(te[k]).max() for k in range(6)])
+    ratio = err[19][[0, 1, 2, 5]] / err[39][[0, 1, 2, 5]]
+    np.testing.assert_allclose(ratio, (39 / 19) ** 2, rtol=0.05)
+    # K^{phi,0} and K^{phi,r} are exact in both modes (A30-A31)
+    assert err[19][3] == 0.0 and err[19][4] == 0.0
+
+
 def test_parities_and_self_zeros():
     sk = (-0.01, 0.2, 0.3)
     par = np.array([1, 1, -1, -1, -1, 1])
@@ -150,10 +201,11 @@ def test_azimuthal_kernels_sum_to_zero_over_a_ring():
 
 
 def _self_cell_pv(beta, dphi):
-    """Self-cell K^{r,0}_{00} and K^{r,r}_{00} in local polar coordinates
-    (rho, t) about the fan centre (1, 0):
-      K^{r,0} = int cos t ln rho_max(t) dt           (principal value)
-      K^{r,r} = int cos t int_0^{rho_max} (|x| - 1)/rho drho dt."""
+    """Self-cell K^{r,0}_{00}, K^{r,r}_{00} and K^{phi,phi}_{00} in local
+    polar coordinates (rho, t) about the fan centre (1, 0):
+      K^{r,0}     = int cos t ln rho_max(t) dt           (principal value)
+      K^{r,r}     = int cos t int_0^{rho_max} (|x| - 1)/rho drho dt
+      K^{phi,phi} = int sin t int_0^{rho_max} phi(x)/rho drho dt."""
     r_in, r_out = 2 / (1 + beta), 2 * beta / (1 + beta)
     a = dphi / 2
 
@@ -179,32 +231,48 @@ def _self_cell_pv(beta, dphi):
         for sa in (a, -a):
             corners.append(math.atan2(R * math.sin(sa), R * math.cos(sa) - 1) % (2 * math.pi))
     brk = sorted(set([0.0] + corners + [2 * math.pi]))
-    k0 = k1 = 0.0
+    k0 = k1 = k2 = 0.0
     for lo, hi in zip(brk[:-1], brk[1:]):
-        k0 += integrate.quad(lambda t: math.cos(t) * math.log(rho_max(t)), lo, hi,
-                             epsabs=1e-15, epsrel=1e-13)[0]
+        tol = dict(epsabs=1e-16, epsrel=1e-14, limit=200)
+        k0 += integrate.quad(lambda t: math.cos(t) * math.log(rho_max(t)), lo, hi, **tol)[0]
 
         def inner(t):
             c, s = math.cos(t), math.sin(t)
             f = lambda p: (math.hypot(1 + p * c, p * s) - 1) / p
-            return c * integrate.quad(f, 0, rho_max(t), epsabs=1e-15, epsrel=1e-13)[0]
-        k1 += integrate.quad(inner, lo, hi, epsabs=1e-15, epsrel=1e-12)[0]
-    return k0, k1
+            return c * integrate.quad(f, 0, rho_max(t), **tol)[0]
+        k1 += integrate.quad(inner, lo, hi, **tol)[0]
+
+        def inner_phi(t):
+            c, s = math.cos(t), math.sin(t)
+            f = lambda p: math.atan2(p * s, 1 + p * c) / p
+            return s * integrate.quad(f, 0, rho_max(t), **tol)[0]
+        k2 += integrate.quad(inner_phi, lo, hi, **tol)[0]
+    return k0, k1, k2
+
+
+@pytest.mark.parametrize("shape", [(64, 64, 0.01, 1.0), (37, 128, 0.1, 10.0), (16, 8, 0.5, 2.0)])
+def test_oracle_principal_value_matches_local_polar_quadrature(shape):
+    g = oracle.Grid(*shape)
+    ref = _self_cell_pv(g.beta, g.dphi)
+    got = oracle.selfcell_pv(g.beta, g.dphi)
+    np.testing.assert_allclose(got, ref, rtol=1e-11, atol=1e-15)
 
 
 def test_self_cell_cover_converges_to_principal_value():
     g = oracle.Grid(64, 64, 0.01, 1.0)
-    pv0, pv1 = _self_cell_pv(g.beta, g.dphi)
-    errs0, errs1 = [], []
+    pv0, pv1, pv2 = _self_cell_pv(g.beta, g.dphi)
+    errs0, errs1, errs2 = [], [], []
     for per in (10, 20, 40):
-        c0, c1, _, _ = oracle.selfcell_cover(g.beta, g.dphi, per)
+        c0, c1, c2, _ = oracle.selfcell_cover(g.beta, g.dphi, per)
         errs0.append(abs(c0 - pv0) / abs(pv0))
         errs1.append(abs(c1 - pv1) / abs(pv1))
+        errs2.append(abs(c2 - pv2) / abs(pv2))
     # paper's rule (10 per Delta x, Delta y) is within a few percent, and the
     # cover error shrinks under refinement
-    assert errs0[0] < 0.05 and errs1[0] < 1e-3
+    assert errs0[0] < 0.05 and errs1[0] < 1e-3 and errs2[0] < 1e-4
     assert errs0[2] < errs0[1] < errs0[0]
     assert errs1[2] < errs1[0]
+    assert errs2[2] < errs2[0]
 
 
 def test_self_cell_cover_counts_match_paper_rule():
