@@ -65,6 +65,19 @@ enum pf_status {
 
 enum pf_dtype { PF_F32 = 0, PF_F64 = 1 };
 
+/* How the azimuthal integrals of the kernel tables are taken. */
+enum pf_table_mode {
+    PF_TABLE_SIM = 0,     /* n_tpz trapezoids per source cell (Sec. 4, Eq. 41-43) */
+    PF_TABLE_EXACT = 1    /* the same integrals converged to rounding          */
+};
+
+/* How the singular self-cell constants K_{00} are obtained. */
+enum pf_self_mode {
+    PF_SELF_CARTESIAN = 0,  /* Cartesian cover of the cell (Sec. 4, Eq. 44-46) */
+    PF_SELF_EXACT = 1       /* the exact integrals (principal value for       */
+                            /* K^{r,0}) in local polar coordinates            */
+};
+
 /* Kernel-table construction options (Sec. 4).
  *   dtype        PF_F32: FFT and spectral multiply in FP32 with FP32
  *                accumulation (tables and spectra are built in FP64 and
@@ -76,15 +89,23 @@ enum pf_dtype { PF_F32 = 0, PF_F64 = 1 };
  *                the singular self cell (Eq. 44-45); the paper uses 10.
  *                Range 1..64.
  *   keep_tables  nonzero: keep the six FP64 kernel tables on the device so
- *                that pf_plan_tables() can return them (diagnostics).      */
+ *                that pf_plan_tables() can return them (diagnostics).
+ *   table_mode   PF_TABLE_SIM (the paper's method; n_tpz applies) or
+ *                PF_TABLE_EXACT (n_tpz ignored).  K^{phi,0}, K^{phi,r} are
+ *                exact in both modes (A30-A31).
+ *   self_mode    PF_SELF_CARTESIAN (the paper's cover; cover_per applies) or
+ *                PF_SELF_EXACT (cover_per ignored).                        */
 typedef struct {
     int dtype;
     int n_tpz;
     int cover_per;
     int keep_tables;
+    int table_mode;
+    int self_mode;
 } pf_build_opts;
 
-/* Defaults: PF_F32, n_tpz = 19, cover_per = 10, keep_tables = 0. */
+/* Defaults: PF_F32, n_tpz = 19, cover_per = 10, keep_tables = 0,
+ * PF_TABLE_SIM, PF_SELF_CARTESIAN (the paper's method). */
 void pf_build_opts_default(pf_build_opts *opts);
 
 /* Create a plan for an n_r x n_phi grid on [r_min, r_max] (Sec. 3.2.1).

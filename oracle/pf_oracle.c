@@ -516,7 +516,10 @@ int or_selfcell_cover(double beta, double dphi, int per, double *out,
 /* xi(xbar) the azimuth of xbar.  (From Eq. 30-32 with eta deta dxi = dA,     */
 /* (1 - eta cos xi) = -rho cos t, eta sin xi = rho sin t, F = rho; the        */
 /* log(0) part of K^{r,0} cancels over the full circle.)  The t-integrals     */
-/* are split at the four corner directions, where rho_max has kinks.         */
+/* are split at the four corner directions, where rho_max has kinks, and at */
+/* the two directions tangent to the inner circle, where the ray stops      */
+/* meeting the inner arc (rho_max jumps there when the tangent point lies on */
+/* the cell's inner arc).                                                    */
 /* ------------------------------------------------------------------------ */
 typedef struct { double r_in, r_out, a; } fan_t;
 
@@ -568,7 +571,7 @@ int or_selfcell_pv(double beta, double dphi, double *out)
     f.r_in = 2.0 / (1.0 + beta);
     f.r_out = 2.0 * beta / (1.0 + beta);
     f.a = 0.5 * dphi;
-    double brk[6];
+    double brk[8];
     int nb = 0;
     brk[nb++] = 0.0;
     for (int i = 0; i < 2; ++i)
@@ -578,6 +581,12 @@ int or_selfcell_pv(double beta, double dphi, double *out)
             if (t < 0.0) t += 2.0 * OR_PI;
             brk[nb++] = t;
         }
+    for (int sg = -1; sg <= 1; sg += 2) {
+        /* tangent point T of the inner circle seen from (1, 0): T_x = r_in^2 */
+        double t = atan2(sg * f.r_in * sqrt(1.0 - f.r_in * f.r_in), f.r_in * f.r_in - 1.0);
+        if (t < 0.0) t += 2.0 * OR_PI;
+        brk[nb++] = t;
+    }
     brk[nb++] = 2.0 * OR_PI;
     /* sort the break points */
     for (int i = 1; i < nb; ++i)

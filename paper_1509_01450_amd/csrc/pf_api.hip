@@ -217,6 +217,8 @@ void pf_build_opts_default(pf_build_opts *o) {
     o->dtype = PF_F32;
     o->n_tpz = 19;
     o->cover_per = 10;
+    o->table_mode = PF_TABLE_SIM;
+    o->self_mode = PF_SELF_CARTESIAN;
     o->keep_tables = 0;
 }
 
@@ -360,11 +362,19 @@ int pf_kernels_build(pf_plan h, const pf_build_opts *opts, void *stream) {
         pf::set_error("dtype must be PF_F32 or PF_F64");
         return PF_EINVAL;
     }
-    if (o.n_tpz < 1 || o.n_tpz > 1024) {
+    if (o.table_mode != PF_TABLE_SIM && o.table_mode != PF_TABLE_EXACT) {
+        pf::set_error("table_mode must be PF_TABLE_SIM or PF_TABLE_EXACT");
+        return PF_EINVAL;
+    }
+    if (o.self_mode != PF_SELF_CARTESIAN && o.self_mode != PF_SELF_EXACT) {
+        pf::set_error("self_mode must be PF_SELF_CARTESIAN or PF_SELF_EXACT");
+        return PF_EINVAL;
+    }
+    if (o.table_mode == PF_TABLE_SIM && (o.n_tpz < 1 || o.n_tpz > 1024)) {
         pf::set_error("n_tpz = %d outside [1, 1024]", o.n_tpz);
         return PF_EINVAL;
     }
-    if (o.cover_per < 1 || o.cover_per > 64) {
+    if (o.self_mode == PF_SELF_CARTESIAN && (o.cover_per < 1 || o.cover_per > 64)) {
         pf::set_error("cover_per = %d outside [1, 64]", o.cover_per);
         return PF_EINVAL;
     }

@@ -15,7 +15,9 @@
 //   K^{phi,phi}=int int eta^2 sin xi (xi - xi_c) / F^3.
 // SIM (Sec. 4): K^{r,0}, K^{r,r}, K^{r,phi}, K^{phi,phi} take the composite
 // trapezoid rule with n_tpz panels in xi (Eq. 41-43) of the exact eta
-// integral; K^{phi,0} and K^{phi,r} are exact (A30-A31).  Here every exact
+// integral; K^{phi,0} and K^{phi,r} are exact (A30-A31).  The exact table
+// mode takes those four xi integrals converged as well (graded Gauss-
+// Legendre panels towards the singularities in xi).  Here every exact
 // one-dimensional integral is evaluated by 16-point Gauss-Legendre on panels
 // graded geometrically towards the nearest complex singularity of the
 // integrand (eta = exp(+-i xi)), which keeps each panel's Bernstein-ellipse
@@ -32,21 +34,27 @@
 // (Eq. 9-15, closed forms A8-A13) gives the force at (1, 0) of the test
 // densities 1, rbar - 1 and phibar, with the densities' slopes taken at each
 // Cartesian centre; these are K^{r,0}_{00}, K^{r,r}_{00} and
-// K^{phi,phi}_{00}.  The other three self kernels vanish by symmetry.
+// K^{phi,phi}_{00}.  The other three self kernels vanish by symmetry.  The
+// exact self mode takes the same three constants as the exact integrals over
+// the fan (principal value for K^{r,0}, k_selfpv).
 //
 // Spectra.  With T_rr and T_phir multiplied by beta^m (the r_i / r_i'
 // factor of Eq. 28), all six tables are 2-D transformed (rows along phi,
 // then columns along u, padded to L), the azimuthal slope kernels folded in
-// with the periodic central difference, and normalised by 1/(L n_phi):
-//   E_r = F(T_r0) + i sin(2 pi k / n_phi) / dphi * F(T_rphi)
-//   Q_r = F(beta^m T_rr)
-//   E_p = F(T_p0) + i sin(2 pi k / n_phi) / dphi * F(T_pphi)
-//   Q_p = F(beta^m T_pr)
-// stored for k_u in [0, L/2] only.  The k = 0 column of E_p and Q_p is set
-// to exactly zero (odd kernels: an axisymmetric density has no azimuthal
-// force).
+// with the periodic central difference, the radial slope's circular central
+// difference D(k) = 2i ca sin(2 pi k / L) folded in, and normalised by
+// 1/(L n_phi):
+//   E'_r = F(T_r0) + i sin(2 pi k / n_phi) / dphi * F(T_rphi) + D Q_r
+//   Q_r  = F(beta^m T_rr)
+//   E'_p = F(T_p0) + i sin(2 pi k / n_phi) / dphi * F(T_pphi) + D Q_p
+//   Q_p  = F(beta^m T_pr)
+// stored for k_u in [0, L/2] only, as pairs (E', Q) (k_fold).  E_p and Q_p
+// vanish at the azimuthal bins 0 and n_phi/2 (odd kernels) and are not
+// stored there.
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <vector>
 
 #include "pf_common.hpp"
 
@@ -117,6 +125,7 @@ __device__ void graded_gl16(double a, double b, double pr, double pim, Fn &f) {
 struct TabGeo {
     double beta, dphi, lnb;
     int n_r, n_phi, L, n_tpz;
+    int exact;   // 1: azimuthal integrals converged instead of n_tpz trapezoids
 };
 
 // All six kernels of offset (m, n_rep) into t[6]:
@@ -135,12 +144,10 @@ __device__ void table_entry(const TabGeo &g, int m, int nrep, const double *self
     const double el = 2.0 * rho / (1.0 + g.beta);
     const double eu = g.beta * el;
     const double xic = -nrep * g.dphi;
-    const double dth = g.dphi / g.n_tpz;
 
+    // one azimuth xi with quadrature weight wk: the exact radial integrals
     double r0 = 0, rr = 0, rph = 0, pp = 0;
-    for (int k = 0; k <= g.n_tpz; ++k) {
-        const double xi = xic - 0.5 * g.dphi + k * dth;
-        const double wk = (k == 0 || k == g.n_tpz) ? 0.5 * dth : dth;
+    auto point = [&](double xi, double wk) {
         double s, c;
         sincos(xi, &s, &c);
         const double sh = sin(0.5 * xi);
@@ -159,6 +166,20 @@ __device__ void table_entry(const TabGeo &g, int m, int nrep, const double *self
         rr += wk * (Ir2 - rho * Ir);
         rph += wl * Ir;
         pp += wl * Iph;
+    };
+    if (g.exact) {
+        // Converged azimuthal integrals: 16-point Gauss-Legendre panels graded
+        // towards the integrand's nearest singularities, where F = 0 for some
+        // eta of the cell: xi = +-2i asinh(|eta - 1| / (2 sqrt(eta))), closest
+        // for the eta of [el, eu] nearest to 1.
+        const double es = fmin(fmax(1.0, el), eu);
+        const double dxi = 2.0 * asinh(fabs(es - 1.0) / (2.0 * sqrt(es)));
+        graded_gl16(xic - 0.5 * g.dphi, xic + 0.5 * g.dphi, 0.0, dxi, point);
+    } else {
+        // Eq. 41-43: n_tpz trapezoids, the weight (xi - xi_c) inside
+        const double dth = g.dphi / g.n_tpz;
+        for (int k = 0; k <= g.n_tpz; ++k)
+            point(xic - 0.5 * g.dphi + k * dth, (k == 0 || k == g.n_tpz) ? 0.5 * dth : dth);
     }
     t[0] = -r0;
     t[1] = -rr;
@@ -388,6 +409,113 @@ __global__ __launch_bounds__(256) void k_cover_final(const double *__restrict__ 
 }
 
 // ---------------------------------------------------------------------------
+// Self cell as the exact integrals.  In local polar coordinates (rho, t)
+// about the cell centre x = (1, 0), xbar = x + rho (cos t, sin t), rho up to
+// the fan's boundary rho_max(t) (from Eq. 30-32 with eta deta dxi = dA):
+//   K^{r,0}_{00}     = int cos t ln rho_max(t) dt       (principal value)
+//   K^{r,r}_{00}     = int cos t int_0^rho_max (|xbar| - 1)/rho drho dt
+//   K^{phi,phi}_{00} = int sin t int_0^rho_max phi(xbar)/rho drho dt.
+// The t-range is cut at the four corner directions (rho_max has kinks
+// there) and at the two directions tangent to the inner circle (where the
+// ray stops meeting the inner arc, rho_max jumps when the tangent point lies
+// on the cell's inner arc, and has a square-root branch point otherwise),
+// and each arc takes 16-point
+// Gauss-Legendre panels graded geometrically towards both of its ends
+// (widths halving kPvLevels times from the middle), which converges
+// exponentially whatever the singularity beyond an end.  The inner
+// integrals take 16-point Gauss-Legendre on [0, rho_max] (analytic
+// integrands whose singularities lie at |rho| = 1, far beyond rho_max).
+// One workgroup.
+// ---------------------------------------------------------------------------
+struct FanGeo {
+    double rin, rout, a;
+    double brk[8];   // sorted break points of [0, 2 pi]
+    int nb;
+};
+
+__device__ double fan_rho_max(const FanGeo &f, double t) {
+    double s, c;
+    sincos(t, &s, &c);
+    double best = -c + sqrt(c * c + f.rout * f.rout - 1.0);
+    const double disc = c * c - (1.0 - f.rin * f.rin);
+    if (disc >= 0.0) {
+        const double q = sqrt(disc);
+        if (-c - q > 0.0 && -c - q < best) best = -c - q;
+        if (-c + q > 0.0 && -c + q < best) best = -c + q;
+    }
+    for (int sg = -1; sg <= 1; sg += 2) {
+        double ss, cs;
+        sincos(sg * f.a, &ss, &cs);
+        const double den = s * cs - c * ss;
+        if (den != 0.0) {
+            const double rr = ss / den;
+            if (rr > 0.0 && rr < best) best = rr;
+        }
+    }
+    return best;
+}
+
+constexpr int kPvLevels = 30;                  // panels per half arc
+constexpr int kPvPanels = 2 * kPvLevels;       // per arc
+
+// panel j of an arc of length len starting at lo: the half [lo, lo + len/2]
+// is cut at lo + len 2^-(k+1), k = 0..kPvLevels-1 (the last panel reaching
+// the end), the other half mirrored
+__device__ __forceinline__ void pv_panel(double lo, double len, int j, double &a, double &b) {
+    const int k = j < kPvLevels ? j : kPvPanels - 1 - j;   // level from the middle
+    const double outer = ldexp(len, -(k + 1));              // distance of the panel's
+    const double inner = k + 1 < kPvLevels ? ldexp(len, -(k + 2)) : 0.0;   // edges to the end
+    if (j < kPvLevels) {
+        a = lo + inner;
+        b = lo + outer;
+    } else {
+        a = lo + len - outer;
+        b = lo + len - inner;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_selfpv(FanGeo f, double *__restrict__ out) {
+    __shared__ double sh[3][256];
+    const int total = (f.nb - 1) * kPvPanels * 16;
+    double k0 = 0.0, k1 = 0.0, k2 = 0.0;
+    for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
+        const int arc = idx / (kPvPanels * 16), rem = idx % (kPvPanels * 16);
+        const int pnl = rem / 16, q = rem % 16;
+        double pa, pb;
+        pv_panel(f.brk[arc], f.brk[arc + 1] - f.brk[arc], pnl, pa, pb);
+        const double width = pb - pa;
+        const double mid = 0.5 * (pa + pb);
+        const double xq = (q < 8 ? -1.0 : 1.0) * kGL16x[q & 7];
+        const double t = mid + 0.5 * width * xq, wt = 0.5 * width * kGL16w[q & 7];
+        double s, c;
+        sincos(t, &s, &c);
+        const double rm = fan_rho_max(f, t);
+        double a = 0.0, b = 0.0;
+        for (int j = 0; j < 16; ++j) {
+            const double rho = 0.5 * rm * (1.0 + (j < 8 ? -1.0 : 1.0) * kGL16x[j & 7]);
+            const double X = 1.0 + rho * c, Y = rho * s;
+            const double R = sqrt(X * X + Y * Y);
+            a += kGL16w[j & 7] * (2.0 * c + rho) / (R + 1.0);   // (|xbar| - 1) / rho
+            b += kGL16w[j & 7] * atan2(Y, X) / rho;
+        }
+        k0 += wt * c * log(rm);
+        k1 += wt * c * 0.5 * rm * a;
+        k2 += wt * s * 0.5 * rm * b;
+    }
+    sh[0][threadIdx.x] = k0;
+    sh[1][threadIdx.x] = k1;
+    sh[2][threadIdx.x] = k2;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            for (int k = 0; k < 3; ++k) sh[k][threadIdx.x] += sh[k][threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        for (int k = 0; k < 3; ++k) out[k] = sh[k][0];
+}
+
+// ---------------------------------------------------------------------------
 // Column transforms of the row-transformed tables and the fold into the four
 // spectra.  rowspec: [6][L][M] complex FP64 in the packed half spectrum
 // (column 0 = (bin 0, bin M)).  spec: [2][M][ldspec] pairs (E', Q).
@@ -548,21 +676,47 @@ int build_tables_and_spectra(Plan &p, hipStream_t st) {
         cg.ncell = cg.nkx * cg.nky;
         cg.chunk = 16;
     }
-    const long nthreads = (cg.ncell + cg.chunk - 1) / cg.chunk;
-    const int nblk = (int)((nthreads + 255) / 256);
     PF_HIP(hipMalloc(&selfk.p, 3 * sizeof(double)));
-    PF_HIP(hipMalloc(&partial.p, (size_t)nblk * 6 * sizeof(double)));
-    hipLaunchKernelGGL(k_cover, dim3(nblk), dim3(256), 0, st, cg, (double *)partial.p);
-    PF_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_cover_final, dim3(1), dim3(256), 0, st, (const double *)partial.p, nblk,
-                       (double *)selfk.p);
-    PF_HIP(hipGetLastError());
+    if (p.opts.self_mode == PF_SELF_EXACT) {
+        FanGeo fg{};
+        fg.rin = 2.0 / (1.0 + p.beta);
+        fg.rout = 2.0 * p.beta / (1.0 + p.beta);
+        fg.a = 0.5 * p.dphi;
+        std::vector<double> b = {0.0, 2.0 * M_PI};
+        for (double R : {fg.rin, fg.rout})
+            for (double sa : {fg.a, -fg.a}) {   // corners
+                double t = std::atan2(R * std::sin(sa), R * std::cos(sa) - 1.0);
+                if (t < 0.0) t += 2.0 * M_PI;
+                b.push_back(t);
+            }
+        for (double sg : {1.0, -1.0}) {   // tangents to the inner circle
+            const double ty = sg * fg.rin * std::sqrt(1.0 - fg.rin * fg.rin);
+            double t = std::atan2(ty, fg.rin * fg.rin - 1.0);
+            if (t < 0.0) t += 2.0 * M_PI;
+            b.push_back(t);
+        }
+        std::sort(b.begin(), b.end());
+        fg.nb = (int)b.size();
+        for (int k = 0; k < fg.nb; ++k) fg.brk[k] = b[k];
+        hipLaunchKernelGGL(k_selfpv, dim3(1), dim3(256), 0, st, fg, (double *)selfk.p);
+        PF_HIP(hipGetLastError());
+    } else {
+        const long nthreads = (cg.ncell + cg.chunk - 1) / cg.chunk;
+        const int nblk = (int)((nthreads + 255) / 256);
+        PF_HIP(hipMalloc(&partial.p, (size_t)nblk * 6 * sizeof(double)));
+        hipLaunchKernelGGL(k_cover, dim3(nblk), dim3(256), 0, st, cg, (double *)partial.p);
+        PF_HIP(hipGetLastError());
+        hipLaunchKernelGGL(k_cover_final, dim3(1), dim3(256), 0, st, (const double *)partial.p,
+                           nblk, (double *)selfk.p);
+        PF_HIP(hipGetLastError());
+    }
 
     // --- kernel tables -------------------------------------------------------
     PF_HIP(hipMalloc(&tab.p, 6 * plane * sizeof(double)));
     hipLaunchKernelGGL(k_fill, dim3(1024), dim3(256), 0, st, (double *)tab.p, 6 * plane, 0.0);
     PF_HIP(hipGetLastError());
-    TabGeo tg{p.beta, p.dphi, std::log(p.beta), p.n_r, p.n_phi, p.L, p.opts.n_tpz};
+    TabGeo tg{p.beta, p.dphi, std::log(p.beta), p.n_r, p.n_phi, p.L, p.opts.n_tpz,
+              p.opts.table_mode == PF_TABLE_EXACT ? 1 : 0};
     {
         const long n = (long)(2 * p.n_r - 1) * (p.n_phi / 2 + 1);
         hipLaunchKernelGGL(k_tables, dim3((unsigned)((n + 127) / 128)), dim3(128), 0, st, tg,

@@ -80,6 +80,17 @@ def test_unbuilt_plan_and_null_arguments_are_refused():
         o = pf.pf_build_opts_default()
         o.dtype = 7
         assert lib.pf_kernels_build(h, ctypes.byref(o), None) == pf.PF_EINVAL
+        for field in ("table_mode", "self_mode"):
+            o = pf.pf_build_opts_default()
+            setattr(o, field, 2)
+            assert lib.pf_kernels_build(h, ctypes.byref(o), None) == pf.PF_EINVAL
+        # n_tpz and cover_per are checked only where their mode uses them
+        o = pf.pf_build_opts_default()
+        o.n_tpz, o.table_mode = 0, pf.PF_TABLE_SIM
+        assert lib.pf_kernels_build(h, ctypes.byref(o), None) == pf.PF_EINVAL
+        o = pf.pf_build_opts_default()
+        o.cover_per, o.self_mode = 0, pf.PF_SELF_CARTESIAN
+        assert lib.pf_kernels_build(h, ctypes.byref(o), None) == pf.PF_EINVAL
     finally:
         pf.pf_plan_destroy(h)
     pf.pf_plan_destroy(None)
@@ -88,3 +99,5 @@ def test_unbuilt_plan_and_null_arguments_are_refused():
 def test_default_options():
     o = pf.pf_build_opts_default()
     assert (o.dtype, o.n_tpz, o.cover_per, o.keep_tables) == (pf.PF_F32, 19, 10, 0)
+    # the paper's method by default (SIM tables, Cartesian cover of the self cell)
+    assert (o.table_mode, o.self_mode) == (pf.PF_TABLE_SIM, pf.PF_SELF_CARTESIAN)

@@ -72,6 +72,50 @@ def test_tables_match_oracle(shape):
     np.testing.assert_allclose(sk, ok, rtol=1e-12)
 
 
+# (16, 8, 0.5, 2.0): the inner circle's tangent point from the cell centre
+# lies on the cell's inner arc, so rho_max(t) of the self cell jumps
+@pytest.mark.parametrize("shape", [(16, 32, 0.1, 10.0), (37, 64, 0.01, 1.0), (9, 8, 0.5, 2.0),
+                                   (16, 8, 0.5, 2.0)])
+def test_exact_modes_tables_match_oracle(shape):
+    # converged azimuthal integrals and the exact self cell: two independent
+    # quadratures (graded Gauss-Legendre panels against adaptive bisection)
+    # of the same definitions
+    n_r, n_phi, a, b = shape
+    _say("exact-mode tables", shape)
+    plan = pf.Plan(n_r, n_phi, a, b, dtype="f64", keep_tables=True, table_mode="exact",
+                   self_mode="exact")
+    T = plan.tables()
+    g = oracle.Grid(*shape)
+    To = oracle.tables(g, table_mode="exact", self_mode="exact")
+    base = np.abs(To[0]).max()
+    for k in range(6):
+        scale = max(np.abs(To[k]).max(), base)
+        err = np.abs(T[k] - To[k]).max()
+        _say("  table", oracle.TABLE_NAMES[k], "max|diff| / scale = %.3e" % (err / scale))
+        assert err <= 1e-13 * scale, (k, err, scale)
+    # the self constants enter the tables on their O(1) scale; K^{r,0}_{00} is
+    # a small difference of logarithms, so compare on that scale
+    np.testing.assert_allclose(plan.selfcell(), oracle.selfcell_pv(g.beta, g.dphi), rtol=1e-13,
+                               atol=1e-14)
+    # the modes change the tables: SIM with the cover differs at O(1e-4)
+    sim = pf.Plan(n_r, n_phi, a, b, dtype="f64", keep_tables=True).tables()
+    assert np.abs(sim[0] - T[0]).max() > 1e-8 * base
+
+
+@pytest.mark.parametrize("dt,tol", [("f64", 1e-11), ("f32", 1e-5)])
+def test_exact_modes_forward_matches_oracle(dt, tol):
+    shape = (37, 64, 0.01, 1.0)
+    g = oracle.Grid(*shape)
+    To = oracle.tables(g, table_mode="exact", self_mode="exact")
+    sig = workloads.single_disk_blobs(g.r_centres, g.phi_centres)
+    fr_o, fp_o = oracle.forward(g, To, sig)
+    plan = pf.Plan(*shape, dtype=dt, table_mode="exact", self_mode="exact")
+    fr, fp = _run(plan, sig)
+    e1, e2 = _rel_l2(fr, fr_o), _rel_l2(fp, fp_o)
+    _say("exact modes %s rel-L2 F_r %.3e F_phi %.3e" % (dt, e1, e2))
+    assert e1 <= tol and e2 <= tol
+
+
 @pytest.mark.parametrize("shape", [(4, 8, 0.5, 2.0), (5, 16, 0.1, 10.0), (37, 16, 0.1, 10.0),
                                    (64, 8, 0.01, 1.0), (100, 128, 0.01, 100.0),
                                    (33, 256, 0.2, 5.0)])
