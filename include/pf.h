@@ -78,6 +78,16 @@ enum pf_self_mode {
                             /* K^{r,0}) in local polar coordinates            */
 };
 
+/* Which force method the tables encode. */
+enum pf_method {
+    PF_METHOD_SIM = 0,            /* second-order method with SIM kernels (Sec. 3.2, 4) */
+    PF_METHOD_PARTICLE = 1,       /* point masses sigma r dr dphi at the cell centres, */
+                                  /* no self force (Eq. 35-36)                         */
+    PF_METHOD_PARTICLE_PLUS = 2   /* the same plus the self-cell correction            */
+                                  /* sigma K^{r,0}_00 + r delta^r K^{r,r}_00,          */
+                                  /* delta^phi K^{phi,phi}_00 (Eq. 34, 37)             */
+};
+
 /* Kernel-table construction options (Sec. 4).
  *   dtype        PF_F32: FFT and spectral multiply in FP32 with FP32
  *                accumulation (tables and spectra are built in FP64 and
@@ -94,7 +104,11 @@ enum pf_self_mode {
  *                PF_TABLE_EXACT (n_tpz ignored).  K^{phi,0}, K^{phi,r} are
  *                exact in both modes (A30-A31).
  *   self_mode    PF_SELF_CARTESIAN (the paper's cover; cover_per applies) or
- *                PF_SELF_EXACT (cover_per ignored).                        */
+ *                PF_SELF_EXACT (cover_per ignored).
+ *   method       PF_METHOD_SIM, PF_METHOD_PARTICLE or PF_METHOD_PARTICLE_PLUS
+ *                (table_mode and n_tpz apply to SIM only; self_mode to SIM
+ *                and PARTICLE_PLUS).  The forward and transpose calls are
+ *                the same for every method.                              */
 typedef struct {
     int dtype;
     int n_tpz;
@@ -102,10 +116,11 @@ typedef struct {
     int keep_tables;
     int table_mode;
     int self_mode;
+    int method;
 } pf_build_opts;
 
 /* Defaults: PF_F32, n_tpz = 19, cover_per = 10, keep_tables = 0,
- * PF_TABLE_SIM, PF_SELF_CARTESIAN (the paper's method). */
+ * PF_TABLE_SIM, PF_SELF_CARTESIAN, PF_METHOD_SIM (the paper's method). */
 void pf_build_opts_default(pf_build_opts *opts);
 
 /* Create a plan for an n_r x n_phi grid on [r_min, r_max] (Sec. 3.2.1).

@@ -56,9 +56,10 @@ def _load():
     lib.or_channels.argtypes = [i, i, P, d, P, P, P]
     lib.or_forward.argtypes = [i, i, d, d, P, P, P, i64, P, P]
     lib.or_adjoint.argtypes = [i, i, d, d, P, P, P, P, i64, P]
+    lib.or_forward_particle.argtypes = [i, i, d, d, i, P, P, P, i64, P, P]
     for f in ("or_geometry", "or_gauss_legendre", "or_selfcell_cover", "or_selfcell_pv",
               "or_table_entry", "or_tables", "or_channels", "or_forward",
-              "or_adjoint", "or_num_threads"):
+              "or_adjoint", "or_forward_particle", "or_num_threads"):
         getattr(lib, f).restype = i
     _lib = lib
     return lib
@@ -217,6 +218,36 @@ def forward(grid: Grid, T, sigma, dest=None):
                             _p(T), _p(s), _p(d), nd, _p(fr), _p(fp))
     if rc:
         raise RuntimeError("or_forward failed (%d)" % rc)
+    return fr, fp
+
+
+def forward_particle(grid: Grid, sigma, plus: bool = False, self_k=None, dest=None,
+                     self_mode: str = "cartesian", cover_per: int = 10):
+    """F_r, F_phi of the particle method (plus=False, Eq. 35-36 without the
+    correction) or the modified particle method (plus=True, Eq. 34-37): point
+    masses sigma r dr dphi at the cell centres, no self force, plus the
+    self-cell correction with the constants of :func:`selfcell_cover` (or
+    :func:`selfcell_pv` for self_mode "exact") unless ``self_k`` is given.
+    ``dest`` as in :func:`forward`."""
+    s = _f64(sigma)
+    assert s.shape == grid.shape
+    if self_k is None:
+        self_k = (selfcell_pv(grid.beta, grid.dphi) if self_mode == "exact"
+                  else selfcell_cover(grid.beta, grid.dphi, cover_per)[:3])
+    sk = _f64(self_k)
+    if dest is None:
+        fr = np.empty(grid.shape)
+        fp = np.empty(grid.shape)
+        d, nd = None, 0
+    else:
+        d = np.ascontiguousarray(dest, dtype=np.int64)
+        nd = d.size
+        fr = np.empty(nd)
+        fp = np.empty(nd)
+    rc = _load().or_forward_particle(grid.n_r, grid.n_phi, grid.r_min, grid.r_max, int(bool(plus)),
+                                     _p(sk), _p(s), _p(d), nd, _p(fr), _p(fp))
+    if rc:
+        raise RuntimeError("or_forward_particle failed (%d)" % rc)
     return fr, fp
 
 

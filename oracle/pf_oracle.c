@@ -25,7 +25,9 @@
  *   - the forces as the plain double sums of Eq. 27-29 and A19-A21,
  *     O((N_r N_phi)^2), at any chosen set of destination cells;
  *   - the transpose of that linear map, as a plain double sum, at any chosen
- *     set of source cells.
+ *     set of source cells;
+ *   - the particle and modified particle methods (Eq. 34-37, 56-62) as plain
+ *     double sums of point masses in physical coordinates.
  *
  * Index conventions (0-based).  Radial cell i spans
  * [r_min beta^i, r_min beta^(i+1)], centre r_i = r_min beta^i (1+beta)/2 (the
@@ -938,6 +940,75 @@ int or_adjoint(int n_r, int n_phi, double r_min, double r_max, const double *T,
         g[q] = tot;
     }
     free(rc);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Particle and modified particle methods in polar coordinates (Eq. 34-37,   */
+/* 56-62), as plain double sums in physical coordinates.  Each source cell is */
+/* a point mass Mbar = sigma r_i' dr_i' dphi at its centre (with arithmetic  */
+/* centres this is the density times the exact polar cell area), and a cell  */
+/* feels no force from itself.  The force of a point mass M at (r', phi') on  */
+/* (r_i, phi_j) is M (r' cos d - r_i, r' sin d) / D^(3/2) in (r-hat, phi-hat), */
+/* d = phi' - phi_j, D = (r_i - r')^2 + 4 r_i r' sin^2(d/2).                 */
+/* plus = 1 adds the self-cell correction of the modified method:             */
+/*   F^{r,corr}   = sigma K^{r,0}_{00} + r_i delta^r K^{r,r}_{00},           */
+/*   F^{phi,corr} = delta^phi K^{phi,phi}_{00}                               */
+/* (K^{r,phi}_{00}, K^{phi,0}_{00}, K^{phi,r}_{00} vanish by symmetry);      */
+/* self = K^{r,0}_{00}, K^{r,r}_{00}, K^{phi,phi}_{00}.                       */
+/* ------------------------------------------------------------------------ */
+int or_forward_particle(int n_r, int n_phi, double r_min, double r_max, int plus,
+                        const double *self, const double *sigma, const int64_t *dest,
+                        int64_t n_dest, double *f_r, double *f_phi)
+{
+    double beta, dphi;
+    double *rc = (double *)malloc(sizeof(double) * n_r);
+    double *re = (double *)malloc(sizeof(double) * (n_r + 1));
+    if (!rc || !re) { free(rc); free(re); return -2; }
+    if (or_geometry(n_r, n_phi, r_min, r_max, rc, re, &beta, &dphi)) {
+        free(rc); free(re); return -1;
+    }
+    const long N = (long)n_r * n_phi;
+    double *dr = (double *)malloc(sizeof(double) * N);
+    double *dp = (double *)malloc(sizeof(double) * N);
+    double *mass = (double *)malloc(sizeof(double) * N);
+    if (!dr || !dp || !mass) { free(rc); free(re); free(dr); free(dp); free(mass); return -2; }
+    or_channels(n_r, n_phi, rc, dphi, sigma, dr, dp);
+    for (int i = 0; i < n_r; ++i) {
+        const double area = 0.5 * (re[i + 1] * re[i + 1] - re[i] * re[i]) * dphi;
+        for (int j = 0; j < n_phi; ++j) mass[(long)i * n_phi + j] = sigma[(long)i * n_phi + j] * area;
+    }
+    const long nd = dest ? (long)n_dest : N;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 4)
+#endif
+    for (long q = 0; q < nd; ++q) {
+        const long cell = dest ? (long)dest[q] : q;
+        const int i = (int)(cell / n_phi), j = (int)(cell % n_phi);
+        acc_t ar = {0, 0}, ap = {0, 0};
+        for (int i2 = 0; i2 < n_r; ++i2) {
+            const double r2 = rc[i2];
+            for (int j2 = 0; j2 < n_phi; ++j2) {
+                if (i2 == i && j2 == j) continue;
+                const double M = mass[(long)i2 * n_phi + j2];
+                if (M == 0.0) continue;
+                const double d = (j2 - j) * dphi;
+                const double sh = sin(0.5 * d);
+                const double D = (rc[i] - r2) * (rc[i] - r2) + 4.0 * rc[i] * r2 * sh * sh;
+                const double w = M / (D * sqrt(D));
+                acc_add(&ar, w * (r2 * cos(d) - rc[i]));
+                acc_add(&ap, w * r2 * sin(d));
+            }
+        }
+        double fr = acc_get(&ar), fp = acc_get(&ap);
+        if (plus) {
+            fr += sigma[cell] * self[0] + rc[i] * dr[cell] * self[1];
+            fp += dp[cell] * self[2];
+        }
+        f_r[q] = fr;
+        f_phi[q] = fp;
+    }
+    free(rc); free(re); free(dr); free(dp); free(mass);
     return 0;
 }
 

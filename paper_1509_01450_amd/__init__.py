@@ -25,6 +25,9 @@ PF_OK, PF_EINVAL, PF_ESTATE, PF_ENOMEM, PF_EHIP, PF_ENODEV, PF_EUNSUPPORTED = ra
 PF_F32, PF_F64 = 0, 1
 PF_TABLE_SIM, PF_TABLE_EXACT = 0, 1
 PF_SELF_CARTESIAN, PF_SELF_EXACT = 0, 1
+PF_METHOD_SIM, PF_METHOD_PARTICLE, PF_METHOD_PARTICLE_PLUS = 0, 1, 2
+_METHODS = {"sim": PF_METHOD_SIM, "particle": PF_METHOD_PARTICLE,
+            "particle+": PF_METHOD_PARTICLE_PLUS}
 _TABLE_MODES = {"sim": PF_TABLE_SIM, "exact": PF_TABLE_EXACT}
 _SELF_MODES = {"cartesian": PF_SELF_CARTESIAN, "exact": PF_SELF_EXACT}
 _STATUS = {1: "PF_EINVAL", 2: "PF_ESTATE", 3: "PF_ENOMEM", 4: "PF_EHIP", 5: "PF_ENODEV",
@@ -45,7 +48,8 @@ class PFError(RuntimeError):
 class pf_build_opts(ctypes.Structure):
     _fields_ = [("dtype", ctypes.c_int), ("n_tpz", ctypes.c_int),
                 ("cover_per", ctypes.c_int), ("keep_tables", ctypes.c_int),
-                ("table_mode", ctypes.c_int), ("self_mode", ctypes.c_int)]
+                ("table_mode", ctypes.c_int), ("self_mode", ctypes.c_int),
+                ("method", ctypes.c_int)]
 
 
 _lib = None
@@ -194,23 +198,26 @@ class Plan:
     """A built n_r x n_phi log-polar grid on [r_min, r_max] (owns libpf state)."""
 
     def __init__(self, n_r, n_phi, r_min, r_max, dtype="f32", n_tpz=19, cover_per=10,
-                 keep_tables=False, build=True, table_mode="sim", self_mode="cartesian"):
+                 keep_tables=False, build=True, table_mode="sim", self_mode="cartesian",
+                 method="sim"):
         self.n_r, self.n_phi = int(n_r), int(n_phi)
         self.r_min, self.r_max = float(r_min), float(r_max)
         self.handle = pf_plan_create(n_r, n_phi, r_min, r_max)
         self.dtype = None
         if build:
-            self.build(dtype, n_tpz, cover_per, keep_tables, table_mode, self_mode)
+            self.build(dtype, n_tpz, cover_per, keep_tables, table_mode, self_mode, method)
 
     def build(self, dtype="f32", n_tpz=19, cover_per=10, keep_tables=False, table_mode="sim",
-              self_mode="cartesian"):
-        """table_mode "sim" (n_tpz trapezoids, Eq. 41-43) or "exact";
-        self_mode "cartesian" (cover, Eq. 44-46) or "exact"."""
+              self_mode="cartesian", method="sim"):
+        """method "sim" (second order, SIM kernels), "particle" or "particle+"
+        (Eq. 34-37); table_mode "sim" (n_tpz trapezoids, Eq. 41-43) or
+        "exact"; self_mode "cartesian" (cover, Eq. 44-46) or "exact"."""
         o = pf_build_opts_default()
         o.dtype = PF_F64 if dtype in ("f64", "float64", PF_F64) else PF_F32
         o.n_tpz, o.cover_per, o.keep_tables = int(n_tpz), int(cover_per), int(bool(keep_tables))
         o.table_mode = _TABLE_MODES[table_mode]
         o.self_mode = _SELF_MODES[self_mode]
+        o.method = _METHODS[method]
         pf_kernels_build(self.handle, o, _stream())
         self.dtype = "f64" if o.dtype == PF_F64 else "f32"
         return self

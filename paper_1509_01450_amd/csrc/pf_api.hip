@@ -219,6 +219,7 @@ void pf_build_opts_default(pf_build_opts *o) {
     o->cover_per = 10;
     o->table_mode = PF_TABLE_SIM;
     o->self_mode = PF_SELF_CARTESIAN;
+    o->method = PF_METHOD_SIM;
     o->keep_tables = 0;
 }
 
@@ -370,11 +371,19 @@ int pf_kernels_build(pf_plan h, const pf_build_opts *opts, void *stream) {
         pf::set_error("self_mode must be PF_SELF_CARTESIAN or PF_SELF_EXACT");
         return PF_EINVAL;
     }
-    if (o.table_mode == PF_TABLE_SIM && (o.n_tpz < 1 || o.n_tpz > 1024)) {
+    if (o.method != PF_METHOD_SIM && o.method != PF_METHOD_PARTICLE &&
+        o.method != PF_METHOD_PARTICLE_PLUS) {
+        pf::set_error("method must be PF_METHOD_SIM, PF_METHOD_PARTICLE or "
+                      "PF_METHOD_PARTICLE_PLUS");
+        return PF_EINVAL;
+    }
+    if (o.method == PF_METHOD_SIM && o.table_mode == PF_TABLE_SIM &&
+        (o.n_tpz < 1 || o.n_tpz > 1024)) {
         pf::set_error("n_tpz = %d outside [1, 1024]", o.n_tpz);
         return PF_EINVAL;
     }
-    if (o.self_mode == PF_SELF_CARTESIAN && (o.cover_per < 1 || o.cover_per > 64)) {
+    if (o.method != PF_METHOD_PARTICLE && o.self_mode == PF_SELF_CARTESIAN &&
+        (o.cover_per < 1 || o.cover_per > 64)) {
         pf::set_error("cover_per = %d outside [1, 64]", o.cover_per);
         return PF_EINVAL;
     }

@@ -125,8 +125,40 @@ __device__ void graded_gl16(double a, double b, double pr, double pim, Fn &f) {
 struct TabGeo {
     double beta, dphi, lnb;
     int n_r, n_phi, L, n_tpz;
-    int exact;   // 1: azimuthal integrals converged instead of n_tpz trapezoids
+    int exact;    // 1: azimuthal integrals converged instead of n_tpz trapezoids
+    int method;   // PF_METHOD_*
 };
+
+// Particle methods (Eq. 35-37, 56-62).  A source cell is the point mass
+// Mbar = sigma r_i' dr_i' dphi at its centre; with r_i' = rho r_i,
+// rho = beta^-m, dr / r = 2 (beta - 1)/(beta + 1) for arithmetic centres and
+// xi_c = -n dphi its force on the destination centre, per unit sigma, is
+//   F_r   = rho^2 c_A dphi (rho cos xi_c - 1) / F^3,
+//   F_phi = rho^3 c_A dphi sin xi_c / F^3,  F^2 = (1 - rho)^2 + 4 rho sin^2(xi_c/2),
+// independent of r_i (Eq. 33).  No self force; the modified method puts the
+// self-cell correction in the (0, 0) entries of K^{r,0}, K^{r,r}, K^{phi,phi}.
+__device__ void particle_entry(const TabGeo &g, int m, int nrep, const double *selfk,
+                               double *t) {
+    for (int k = 0; k < 6; ++k) t[k] = 0.0;
+    if (m == 0 && nrep == 0) {
+        if (g.method == PF_METHOD_PARTICLE_PLUS) {
+            t[0] = selfk[0];
+            t[1] = selfk[1];
+            t[5] = selfk[2];
+        }
+        return;
+    }
+    const double rho = exp(-m * g.lnb);
+    const double xic = -nrep * g.dphi;
+    const double cA = 2.0 * (g.beta - 1.0) / (g.beta + 1.0);
+    const double sh = sin(0.5 * xic);
+    const double D = (1.0 - rho) * (1.0 - rho) + 4.0 * rho * sh * sh;
+    const double w = rho * rho * cA * g.dphi / (D * sqrt(D));
+    double s, c;
+    sincos(xic, &s, &c);
+    t[0] = w * (rho * c - 1.0);
+    t[3] = w * rho * s;
+}
 
 // All six kernels of offset (m, n_rep) into t[6]:
 // r0, rr, rphi, phi0, phir, phiphi (unscaled by beta^m).
@@ -224,7 +256,10 @@ __global__ void k_tables(TabGeo g, const double *__restrict__ selfk, double *__r
     const int ir = (int)(idx / nh), nrep = (int)(idx % nh);
     const int m = ir - (g.n_r - 1);
     double t[6];
-    table_entry(g, m, nrep, selfk, t);
+    if (g.method == PF_METHOD_SIM)
+        table_entry(g, m, nrep, selfk, t);
+    else
+        particle_entry(g, m, nrep, selfk, t);
     const int row = (m % g.L + g.L) % g.L;
     const long plane = (long)g.L * g.n_phi;
     const int cp = nrep, cn = (g.n_phi - nrep) % g.n_phi;
@@ -716,7 +751,7 @@ int build_tables_and_spectra(Plan &p, hipStream_t st) {
     hipLaunchKernelGGL(k_fill, dim3(1024), dim3(256), 0, st, (double *)tab.p, 6 * plane, 0.0);
     PF_HIP(hipGetLastError());
     TabGeo tg{p.beta, p.dphi, std::log(p.beta), p.n_r, p.n_phi, p.L, p.opts.n_tpz,
-              p.opts.table_mode == PF_TABLE_EXACT ? 1 : 0};
+              p.opts.table_mode == PF_TABLE_EXACT ? 1 : 0, p.opts.method};
     {
         const long n = (long)(2 * p.n_r - 1) * (p.n_phi / 2 + 1);
         hipLaunchKernelGGL(k_tables, dim3((unsigned)((n + 127) / 128)), dim3(128), 0, st, tg,

@@ -42,15 +42,17 @@ FIT_FROM = 2   # asymptotic fit over TABLE1_N[2:] = 256, 512, 1024
 NORMS = ["L1_r", "L2_r", "Linf_r", "L1_phi", "L2_phi", "Linf_phi"]
 
 
-def _table1(disk):
+def _table1(disk, method="SIM"):
+    """Orders of Table 1 for one disk and method column."""
+    col = {"particle": 0, "SIM": 1, "particle+": 2}[method]
     path = os.path.join(os.path.dirname(__file__), "golden", "table1_sim_orders.txt")
     vals = {}
     with open(path) as fh:
         for line in fh:
             if line.strip() and not line.startswith("#"):
-                d, norm, order = line.split()
+                d, norm, *orders = line.split()
                 if d == disk:
-                    vals[norm] = float(order)
+                    vals[norm] = float(orders[col])
     return np.array([vals[n] for n in NORMS])
 
 
@@ -182,3 +184,27 @@ def test_table1_orders_sigma_d2_fp64():
     _say("sigma_D2 orders fitted 64-1024 %s, 256-1024 %s (Table 1: %s)"
          % (np.array2string(full, precision=2), np.array2string(fit, precision=2), ref))
     assert np.all(np.abs(fit - ref) < 0.2), (fit, ref)
+
+
+@pytest.mark.parametrize("method", ["particle", "particle+"])
+def test_table1_orders_particle_methods_fp64(method):
+    # Table 1's particle and particle+ columns: first order (the correction
+    # lowers the error but not the order)
+    for disk, n in (("D2", 2), ("D5", 5)):
+        e = []
+        for N in TABLE1_N:
+            g, sig, ar, ap = _case(N, N, n)
+            plan = pf.Plan(N, N, 0.01, 1.0, dtype="f64", method=method)
+            try:
+                s = torch.tensor(sig, dtype=torch.float64, device="cuda")
+                fr, fp = plan.forces(s)
+                torch.cuda.synchronize()
+                e.append(_norms(fr.cpu().numpy(), fp.cpu().numpy(), ar, ap))
+            finally:
+                plan.close()
+        e = np.array(e)
+        full, fit, ref = _fitted_orders(e), _fitted_orders(e, FIT_FROM), _table1(disk, method)
+        _say("%s %s orders fitted 64-1024 %s, 256-1024 %s (Table 1: %s)"
+             % (method, disk, np.array2string(full, precision=2),
+                np.array2string(fit, precision=2), ref))
+        assert np.all(np.abs(full - ref) < 0.15), (method, disk, full, ref)

@@ -116,6 +116,37 @@ def test_exact_modes_forward_matches_oracle(dt, tol):
     assert e1 <= tol and e2 <= tol
 
 
+@pytest.mark.parametrize("method", ["particle", "particle+"])
+@pytest.mark.parametrize("dt,tol", [("f64", 1e-11), ("f32", 1e-5)])
+def test_particle_methods_match_oracle(method, dt, tol):
+    # the particle methods through the same passes, against the oracle's
+    # point-mass double sums in physical coordinates (Eq. 34-37)
+    shape = (37, 64, 0.01, 1.0)
+    g = oracle.Grid(*shape)
+    sig = workloads.single_disk_blobs(g.r_centres, g.phi_centres, 0.01, 1.0)
+    fr_o, fp_o = oracle.forward_particle(g, sig, plus=(method == "particle+"))
+    plan = pf.Plan(*shape, dtype=dt, method=method)
+    fr, fp = _run(plan, sig)
+    e1, e2 = _rel_l2(fr, fr_o), _rel_l2(fp, fp_o)
+    _say("%s %s rel-L2 F_r %.3e F_phi %.3e" % (method, dt, e1, e2))
+    assert e1 <= tol and e2 <= tol
+
+
+def test_particle_plus_full_size_sampled():
+    n_r, n_phi, a, b = C2
+    g = oracle.Grid(n_r, n_phi, a, b)
+    phi = g.phi_centres
+    sig = workloads.spiral_disk(g.r_centres, phi)
+    idx = np.random.default_rng(11).choice(n_r * n_phi, 256, replace=False)
+    fr_o, fp_o = oracle.forward_particle(g, sig, plus=True, dest=idx)
+    plan = pf.Plan(n_r, n_phi, a, b, dtype="f32", method="particle+")
+    fr, fp = _run(plan, sig)
+    e1 = _rel_l2(fr.ravel()[idx], fr_o)
+    e2 = _rel_l2(fp.ravel()[idx], fp_o)
+    _say("particle+ C2 f32 sampled rel-L2 F_r %.3e F_phi %.3e" % (e1, e2))
+    assert e1 <= 1e-5 and e2 <= 1e-5
+
+
 @pytest.mark.parametrize("shape", [(4, 8, 0.5, 2.0), (5, 16, 0.1, 10.0), (37, 16, 0.1, 10.0),
                                    (64, 8, 0.01, 1.0), (100, 128, 0.01, 100.0),
                                    (33, 256, 0.2, 5.0)])
