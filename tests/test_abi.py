@@ -80,9 +80,9 @@ def test_unbuilt_plan_and_null_arguments_are_refused():
         o = pf.pf_build_opts_default()
         o.dtype = 7
         assert lib.pf_kernels_build(h, ctypes.byref(o), None) == pf.PF_EINVAL
-        for field in ("table_mode", "self_mode"):
+        for field, bad in (("table_mode", 2), ("self_mode", 2), ("method", 3), ("method", -1)):
             o = pf.pf_build_opts_default()
-            setattr(o, field, 2)
+            setattr(o, field, bad)
             assert lib.pf_kernels_build(h, ctypes.byref(o), None) == pf.PF_EINVAL
         # n_tpz and cover_per are checked only where their mode uses them
         o = pf.pf_build_opts_default()
@@ -101,3 +101,5 @@ def test_default_options():
     assert (o.dtype, o.n_tpz, o.cover_per, o.keep_tables) == (pf.PF_F32, 19, 10, 0)
     # the paper's method by default (SIM tables, Cartesian cover of the self cell)
     assert (o.table_mode, o.self_mode) == (pf.PF_TABLE_SIM, pf.PF_SELF_CARTESIAN)
+    assert o.method == pf.PF_METHOD_SIM
+    assert (pf.PF_METHOD_PARTICLE, pf.PF_METHOD_PARTICLE_PLUS) == (1, 2)
