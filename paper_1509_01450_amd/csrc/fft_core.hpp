@@ -147,23 +147,36 @@ __device__ __forceinline__ void dft<16, double>(cx<double> *u) { dft16_impl(u); 
 
 // ---------------------------------------------------------------------------
 // LDS accessors.  Element i of the FFT group lives at
-// base + swz(i) * stride with swz(i) = i ^ ((i >> 4) & 15): the XOR of the
-// low four index bits with the next four spreads the stride-R stores of the
-// early Stockham stages over the banks (modelled at most 1.33-way for 64
-// banks of 4 bytes and conflict-free for 32, for 8- and 16-byte elements,
-// E = 8 and 16, one transform per region or G interleaved columns).  It is
-// a permutation of every aligned block of 256 indices, so an N-point
-// transform needs exactly N slots.
+// base + pad(i) * stride with pad(i) = i + (i >> 4): one unused slot after
+// every 16 elements.  The stride-R stores of the early Stockham stages then
+// fall on distinct banks (modelled at most 1.33-way for 64 banks of 4 bytes
+// and conflict-free for 32, for 8- and 16-byte elements, E = 8 and 16, one
+// transform per region or G interleaved columns), and the map splits over
+// the sums the stages form: for a power of two P, 0 <= a < P and c a
+// multiple of P, pad(a + c) = pad(a) + pad(c) whenever the span of a lies in
+// one aligned block of 16 or P is a multiple of 16 -- which holds for the
+// exchange reads (t + e TH, t < TH) and for the butterfly writes
+// (base + r NS, base = NS R m + k, k < NS).  The per-thread part is formed
+// once and every access is that register plus a constant offset.  An
+// N-point transform needs padded_len(N) slots.
 // ---------------------------------------------------------------------------
-__host__ __device__ constexpr int padded_len(int n) { return n; }
+__host__ __device__ constexpr int lds_pad(int i) { return i + (i >> 4); }
+__host__ __device__ constexpr int padded_len(int n) { return n + n / 16; }
 
 template <typename T>
 struct Lds {
     cx<T> *p;
     int base, stride;
-    __device__ __forceinline__ int at(int i) const { return base + (i ^ ((i >> 4) & 15)) * stride; }
+    __device__ __forceinline__ int at(int i) const { return base + lds_pad(i) * stride; }
     __device__ __forceinline__ cx<T> ld(int i) const { return p[at(i)]; }
     __device__ __forceinline__ void st(int i, cx<T> v) const { p[at(i)] = v; }
+    // element a + c given pa = lds_pad(a) and the split condition above
+    __device__ __forceinline__ cx<T> ld_split(int pa, int c) const {
+        return p[base + (pa + lds_pad(c)) * stride];
+    }
+    __device__ __forceinline__ void st_split(int pa, int c, cx<T> v) const {
+        p[base + (pa + lds_pad(c)) * stride] = v;
+    }
 };
 
 // ---------------------------------------------------------------------------
@@ -280,18 +293,19 @@ __device__ __forceinline__ void fft_stages(cx<T> (&v)[NV][E], int t, const Lds<T
 #pragma unroll
                 for (int r = 0; r < R; ++r) v[a][q + r * NB] = u[r];
             } else {
-                const int base = (b - k) * R + k;
+                const int pb = lds_pad((b - k) * R + k);
 #pragma unroll
-                for (int r = 0; r < R; ++r) lds[a].st(base + r * NS, u[r]);
+                for (int r = 0; r < R; ++r) lds[a].st_split(pb, r * NS, u[r]);
             }
         }
     }
     if constexpr (!LAST) {
         __syncthreads();
+        const int pt = lds_pad(t);
 #pragma unroll
         for (int a = 0; a < NV; ++a)
 #pragma unroll
-            for (int e = 0; e < E; ++e) v[a][e] = lds[a].ld(t + e * TH);
+            for (int e = 0; e < E; ++e) v[a][e] = lds[a].ld_split(pt, e * TH);
         __syncthreads();
         fft_stages<N, E, NS * R, OFF + (NS > 1 ? NB * ilog2c(R) : 0), NV, T>(v, t, lds, tw);
     }
@@ -305,19 +319,24 @@ __device__ __forceinline__ void fft_fwd(cx<T> (&v)[NV][E], int t, const Lds<T> (
     fft_stages<N, E, 1, 0, NV, T>(v, t, lds, tw);
 }
 
-// Inverse transforms (sign +1, unnormalised) as conj(F(conj(x))).
+// Inverse transforms (sign +1, unnormalised) as swap(F(swap(x))), where
+// swap exchanges real and imaginary parts (swap(z) = i conj(z), so
+// swap(F(swap(x))) = conj(F(conj(x)))): a register renaming, no arithmetic.
+template <typename T>
+__device__ __forceinline__ cx<T> swap_ri(cx<T> a) { return {a.y, a.x}; }
+
 template <int N, int E, int NV, typename T>
 __device__ __forceinline__ void fft_inv(cx<T> (&v)[NV][E], int t, const Lds<T> (&lds)[NV],
                                         const Twiddles<N, E, T> &tw) {
 #pragma unroll
     for (int a = 0; a < NV; ++a)
 #pragma unroll
-        for (int e = 0; e < E; ++e) v[a][e].y = -v[a][e].y;
+        for (int e = 0; e < E; ++e) v[a][e] = swap_ri(v[a][e]);
     fft_stages<N, E, 1, 0, NV, T>(v, t, lds, tw);
 #pragma unroll
     for (int a = 0; a < NV; ++a)
 #pragma unroll
-        for (int e = 0; e < E; ++e) v[a][e].y = -v[a][e].y;
+        for (int e = 0; e < E; ++e) v[a][e] = swap_ri(v[a][e]);
 }
 
 // Single-array forms (the copies are register renames once inlined).

@@ -50,12 +50,13 @@ namespace pf {
 // the packed half spectrum (bin 0 = (X_0, X_M)).  C = 1 or 2 channels: with
 // C = 2 a thread holds the same points of two fields' rows (the two force
 // channels), whose half spectra are stored as pairs.
-// Workgroup: G rows x (M/E) threads; LDS buf: C*G*M complex.
+// Workgroup: G rows x (M/E) threads; LDS buf: C*G*padded_len(M) complex.
 // ---------------------------------------------------------------------------
 template <typename T, int M, int E, int C>
 __device__ __forceinline__ void row_lds(cx<T> *buf, int gi, int G, Lds<T> (&lds)[C]) {
 #pragma unroll
-    for (int c = 0; c < C; ++c) lds[c] = Lds<T>{buf + (size_t)c * G * M, gi * M, 1};
+    for (int c = 0; c < C; ++c)
+        lds[c] = Lds<T>{buf + (size_t)c * G * padded_len(M), gi * padded_len(M), 1};
 }
 
 // Pass A: rows of in0 (and in1 for C = 2) -> packed half spectra
@@ -94,7 +95,7 @@ __device__ __forceinline__ void body_rows_r2c(int unit, int G, cx<T> *__restrict
 #pragma unroll
     for (int c = 0; c < C; ++c)
 #pragma unroll
-        for (int e = 0; e < E; ++e) lds[c].st(t + e * TH, v[c][e]);
+        for (int e = 0; e < E; ++e) lds[c].st_split(lds_pad(t), e * TH, v[c][e]);
     __syncthreads();
     cx<T> o[C][E];
 #pragma unroll
@@ -191,18 +192,34 @@ __device__ __forceinline__ void body_rows_c2r(int unit, int G, cx<T> *__restrict
 }
 
 // ---------------------------------------------------------------------------
-// Spectrum access with the phi-parity symmetry of the kernels:
-// E_r, Q_r even in n -> value at -k_u is conj; E_p, Q_p odd -> -conj.
-// One pair (E', Q) of a column per load.
+// Spectrum access.  Spectra are stored for k_u in [0, L/2]; the kernels'
+// symmetry in phi gives the rest: E_r, Q_r are even in n (the value at -k_u
+// is the conjugate), E_p, Q_p odd (minus the conjugate).  Point e of thread
+// t is k_u = t + e TH: for e < E/2 it is stored as is; for e > E/2 it is
+// the mirror of L - k_u; for e = E/2 it is k_u = L/2 + t, stored at L/2 for
+// t = 0 and the mirror of L/2 - t otherwise.  With e fixed by the unrolled
+// loops the index is t plus a constant and the mirror's conjugation folds
+// into the product (no branch, no sign flips).
 // ---------------------------------------------------------------------------
-template <typename T, int L>
-__device__ __forceinline__ cx2<T> spec_at(const cx2<T> *__restrict__ col, int ku, bool odd) {
-    constexpr int HL = L / 2;
-    const bool lo = ku <= HL;
-    const cx2<T> s = col[lo ? ku : L - ku];   // one load, no branch
-    if (lo) return s;
-    if (odd) return cx2<T>{{-s.a.x, s.a.y}, {-s.b.x, s.b.y}};
-    return cx2<T>{{s.a.x, -s.a.y}, {s.b.x, -s.b.y}};
+template <int L, int E>
+__device__ __forceinline__ int spec_index(int t, int e) {
+    constexpr int TH = L / E;
+    return e < E / 2 ? t + e * TH : L - t - e * TH;
+}
+
+// x S (CJ false) or x conj(S) (CJ true) for the spectrum value S of point
+// e whose stored value is s (spec_index); ODD: a kernel odd in phi, whose
+// mirror is -conj rather than conj.  t0: the thread is t = 0.
+template <typename T, int E, bool ODD, bool CJ>
+__device__ __forceinline__ cx<T> spec_mul(cx<T> s, cx<T> x, int e, bool t0) {
+    if (e == E / 2) {
+        const cx<T> m = ODD ? cx<T>{-s.x, s.y} : cx<T>{s.x, -s.y};
+        const cx<T> se = t0 ? s : m;
+        return CJ ? cmulc(x, se) : cmul(x, se);
+    }
+    if (e < E / 2) return CJ ? cmulc(x, s) : cmul(x, s);
+    const cx<T> p = CJ ? cmul(x, s) : cmulc(x, s);
+    return ODD ? cx<T>{-p.x, -p.y} : p;
 }
 
 // ---------------------------------------------------------------------------
@@ -300,7 +317,7 @@ __host__ __device__ constexpr int mac_batch() { return sizeof(T) == 8 ? 2 : (E <
 // ---------------------------------------------------------------------------
 // Pass B, forward.  Workgroup: G columns x (L/E) threads, lane -> (t, column)
 // with the G columns interleaved (consecutive lanes read consecutive
-// columns of a row).  LDS buf: G*L complex.
+// columns of a row).  LDS buf: G*padded_len(L) complex.
 // S: [n_r][H] complex; Z: [n_r][H] pairs (Zr, Zp); spec: [2][H][ldspec] pairs.
 // ---------------------------------------------------------------------------
 template <typename T, int L, int E>
@@ -342,7 +359,7 @@ __device__ __forceinline__ void body_cols_fwd(int unit, int G, cx<T> *__restrict
     fft_fwd<L, E, T>(v, t, lds, tw);
     if (packed) {   // column 0 reads the conjugate mirror points from LDS
 #pragma unroll
-        for (int e = 0; e < E; ++e) lds.st(t + e * TH, v[e]);
+        for (int e = 0; e < E; ++e) lds.st_split(lds_pad(t), e * TH, v[e]);
         __syncthreads();
     }
 
@@ -356,6 +373,7 @@ __device__ __forceinline__ void body_cols_fwd(int unit, int G, cx<T> *__restrict
         phM = slope_phasors(slope_fix_part(a, true), wt, wnt);
     }
     constexpr int CH = mac_batch<T, E>();
+    const bool t0 = t == 0;
     cx<T> y[2][E];   // y[0] -> Zr, y[1] -> Zp
 #pragma unroll
     for (int cb = 0; cb < E; cb += CH) {
@@ -364,9 +382,9 @@ __device__ __forceinline__ void body_cols_fwd(int unit, int G, cx<T> *__restrict
         cx2<T> pr[CH], pp[CH];
 #pragma unroll
         for (int j = 0; j < CH; ++j) {
-            const int ku = t + (cb + j) * TH;
-            pr[j] = spec_at<T, L>(sr, ku, false);
-            pp[j] = spec_at<T, L>(sp, ku, !is0);
+            const int ix = spec_index<L, E>(t, cb + j);
+            pr[j] = sr[ix];
+            pp[j] = sp[ix];
         }
 #pragma unroll
         for (int j = 0; j < CH; ++j) {
@@ -376,14 +394,18 @@ __device__ __forceinline__ void body_cols_fwd(int unit, int G, cx<T> *__restrict
                 const cx<T> m = lds.ld((L - (t + e * TH)) & (L - 1));
                 const cx<T> A = unpack_even(v[e], m), B = unpack_odd(v[e], m);
                 const cx<T> f0 = slope_fix_at(ph0, r), fM = slope_fix_at(phM, r);
-                const cx<T> y0 = cmul(pr[j].a, A) + cmul(pr[j].b, f0);
-                const cx<T> yM = cmul(pp[j].a, B) + cmul(pp[j].b, fM);
+                const cx<T> y0 = spec_mul<T, E, false, false>(pr[j].a, A, e, t0) +
+                                 spec_mul<T, E, false, false>(pr[j].b, f0, e, t0);
+                const cx<T> yM = spec_mul<T, E, false, false>(pp[j].a, B, e, t0) +
+                                 spec_mul<T, E, false, false>(pp[j].b, fM, e, t0);
                 y[0][e] = cx<T>{y0.x - yM.y, y0.y + yM.x};   // y0 + i yM
                 y[1][e] = cx<T>{T(0), T(0)};
             } else {
                 const cx<T> f = slope_fix_at(ph, r);
-                y[0][e] = cmul(pr[j].a, v[e]) + cmul(pr[j].b, f);
-                y[1][e] = cmul(pp[j].a, v[e]) + cmul(pp[j].b, f);
+                y[0][e] = spec_mul<T, E, false, false>(pr[j].a, v[e], e, t0) +
+                          spec_mul<T, E, false, false>(pr[j].b, f, e, t0);
+                y[1][e] = spec_mul<T, E, true, false>(pp[j].a, v[e], e, t0) +
+                          spec_mul<T, E, true, false>(pp[j].b, f, e, t0);
             }
         }
     }
@@ -442,7 +464,8 @@ __device__ __forceinline__ void column_sums(cx<T> (&x)[Q], int G, cx<T> *__restr
 // the transposed slope: the transposed central difference is in E'; the
 // four-row correction needs the inverse transform of R = conj(Q_r) V_r +
 // conj(Q_p) V_p at rows 0, n-1, n and L-1 only, four sums over k.
-// V: [n_r][H] pairs (Vr, Vp); D: [n_r][H] complex.  LDS buf: G*L complex.
+// V: [n_r][H] pairs (Vr, Vp); D: [n_r][H] complex.  LDS buf: G*padded_len(L)
+// complex.
 // ---------------------------------------------------------------------------
 template <typename T, int L, int E>
 __device__ __forceinline__ void body_cols_adj(int unit, int G, cx<T> *__restrict__ buf,
@@ -484,7 +507,7 @@ __device__ __forceinline__ void body_cols_adj(int unit, int G, cx<T> *__restrict
     fft_fwd<L, E, T>(va[1], t, lds, tw);
     if (packed) {   // column 0 reads the conjugate mirror points from LDS
 #pragma unroll
-        for (int e = 0; e < E; ++e) lds.st(t + e * TH, va[0][e]);
+        for (int e = 0; e < E; ++e) lds.st_split(lds_pad(t), e * TH, va[0][e]);
         __syncthreads();
     }
 
@@ -497,14 +520,15 @@ __device__ __forceinline__ void body_cols_adj(int unit, int G, cx<T> *__restrict
     // turned into the thread's share with its phasors afterwards.
     cx<T> w[4] = {{T(0), T(0)}, {T(0), T(0)}, {T(0), T(0)}, {T(0), T(0)}};
     constexpr int CH = mac_batch<T, E>();
+    const bool t0 = t == 0;
 #pragma unroll
     for (int cb = 0; cb < E; cb += CH) {
         cx2<T> pr[CH], pp[CH];
 #pragma unroll
         for (int j = 0; j < CH; ++j) {
-            const int ku = t + (cb + j) * TH;
-            pr[j] = spec_at<T, L>(sr, ku, false);
-            pp[j] = spec_at<T, L>(sp, ku, !is0);
+            const int ix = spec_index<L, E>(t, cb + j);
+            pr[j] = sr[ix];
+            pp[j] = sp[ix];
         }
 #pragma unroll
         for (int j = 0; j < CH; ++j) {
@@ -515,14 +539,18 @@ __device__ __forceinline__ void body_cols_adj(int unit, int G, cx<T> *__restrict
                 // not enter (the azimuthal spectra vanish there)
                 const cx<T> m = lds.ld((L - (t + e * TH)) & (L - 1));
                 const cx<T> A = unpack_even(va[0][e], m), B = unpack_odd(va[0][e], m);
-                const cx<T> x0 = cmulc(A, pr[j].a), xM = cmulc(B, pp[j].a);
-                const cx<T> r0 = cmulc(A, pr[j].b), rM = cmulc(B, pp[j].b);
+                const cx<T> x0 = spec_mul<T, E, false, true>(pr[j].a, A, e, t0);
+                const cx<T> xM = spec_mul<T, E, false, true>(pp[j].a, B, e, t0);
+                const cx<T> r0 = spec_mul<T, E, false, true>(pr[j].b, A, e, t0);
+                const cx<T> rM = spec_mul<T, E, false, true>(pp[j].b, B, e, t0);
                 xe = cx<T>{x0.x - xM.y, x0.y + xM.x};
                 r = cx<T>{r0.x - rM.y, r0.y + rM.x};
             } else {
                 // conj(E'_r) V_r + conj(E'_p) V_p and conj(Q_r) V_r + conj(Q_p) V_p
-                xe = cmulc(va[0][e], pr[j].a) + cmulc(va[1][e], pp[j].a);
-                r = cmulc(va[0][e], pr[j].b) + cmulc(va[1][e], pp[j].b);
+                xe = spec_mul<T, E, false, true>(pr[j].a, va[0][e], e, t0) +
+                     spec_mul<T, E, true, true>(pp[j].a, va[1][e], e, t0);
+                r = spec_mul<T, E, false, true>(pr[j].b, va[0][e], e, t0) +
+                    spec_mul<T, E, true, true>(pp[j].b, va[1][e], e, t0);
             }
             va[0][e] = xe;   // V_r's point is not needed again
             const Roots<T, L, E> ro(twL, n_r, e);

@@ -70,7 +70,7 @@ template <typename T>
 __global__ __launch_bounds__(kGroupThreads) void k_group_rows(const GDisk<T> *__restrict__ disks,
                                                               const int *__restrict__ bdisk,
                                                               int pass) {
-    __shared__ cx<T> buf[2 * kGroupThreads * kRowE];
+    __shared__ cx<T> buf[2 * padded_len(kGroupThreads * kRowE)];
     const GDisk<T> &d = disks[bdisk[blockIdx.x]];
     const int unit = blockIdx.x - d.base[pass];
     switch (d.M) {
@@ -98,7 +98,7 @@ __device__ __forceinline__ void group_cols(int unit, const GDisk<T> &d, cx<T> *b
 template <typename T>
 __global__ __launch_bounds__(kGroupThreads) __attribute__((amdgpu_waves_per_eu(2)))
 void k_group_cols(const GDisk<T> *__restrict__ disks, const int *__restrict__ bdisk) {
-    __shared__ cx<T> buf[kGroupThreads * col_e<T>()];
+    __shared__ cx<T> buf[padded_len(kGroupThreads * col_e<T>())];
     const GDisk<T> &d = disks[bdisk[blockIdx.x]];
     const int unit = blockIdx.x - d.base[1];
     switch (d.L) {

@@ -64,21 +64,21 @@ __global__ __launch_bounds__(512) void k_cols_adj(const cx2<T> *__restrict__ V,
 // Runtime dispatch onto the template instantiations.
 // ---------------------------------------------------------------------------
 // Row shapes are checked for the two-channel passes (the larger LDS need):
-// 2 G M complex within the default 64 KB.
+// 2 G padded_len(M) complex within 144 KB.
 bool valid_shape_rows(int M, Shape s, bool f64) {
     if (!(s.E == 4 || s.E == 8 || s.E == 16) || s.E > M) return false;
     const int th = M / s.E;
     if (s.G < 1 || th * s.G > 512) return false;
-    const size_t lds = (size_t)2 * s.G * M * (f64 ? 16 : 8);
-    return lds <= 64 * 1024;
+    const size_t lds = (size_t)2 * s.G * padded_len(M) * (f64 ? 16 : 8);
+    return lds <= 144 * 1024;
 }
 
-// Column pass: G L complex of LDS.
+// Column pass: G padded_len(L) complex of LDS.
 bool valid_shape_cols(int L, Shape s, bool f64) {
     if (!(s.E == 8 || s.E == 16) || s.E > L) return false;
     const int th = L / s.E;
     if (s.G < 1 || th * s.G > 512) return false;
-    const size_t lds = (size_t)s.G * L * (f64 ? 16 : 8);
+    const size_t lds = (size_t)s.G * padded_len(L) * (f64 ? 16 : 8);
     return lds <= 144 * 1024;
 }
 
@@ -117,7 +117,9 @@ struct Disp {
         if constexpr (E <= N) {
             constexpr int TH = N / E;
             const int blocks = (n_rows + G - 1) / G;
-            const size_t lds = (size_t)C * G * N * sizeof(cx<T>);
+            const size_t lds = (size_t)C * G * padded_len(N) * sizeof(cx<T>);
+            int rc = allow_lds(k_rows_r2c<T, N, E, C>, lds);
+            if (rc) return rc;
             hipLaunchKernelGGL((k_rows_r2c<T, N, E, C>), dim3(blocks), dim3(G * TH), lds, st, in0,
                                in1, n_rows, out, tw);
             PF_HIP(hipGetLastError());
@@ -132,7 +134,9 @@ struct Disp {
         if constexpr (E <= N) {
             constexpr int TH = N / E;
             const int blocks = (n_rows + G - 1) / G;
-            const size_t lds = (size_t)C * G * N * sizeof(cx<T>);
+            const size_t lds = (size_t)C * G * padded_len(N) * sizeof(cx<T>);
+            int rc = allow_lds(k_rows_c2r<T, N, E, C>, lds);
+            if (rc) return rc;
             hipLaunchKernelGGL((k_rows_c2r<T, N, E, C>), dim3(blocks), dim3(G * TH), lds, st, in,
                                n_rows, o0, o1, tw);
             PF_HIP(hipGetLastError());
@@ -149,7 +153,7 @@ struct Disp {
             const int n_groups = (p.H + G - 1) / G;
             const int per_xcd = (n_groups + 7) / 8;
             const int blocks = per_xcd * 8;
-            const size_t lds = (size_t)G * N * sizeof(cx<T>);
+            const size_t lds = (size_t)G * padded_len(N) * sizeof(cx<T>);
             const T ca = T(p.ca), c0 = T(p.c0), cn = T(p.cn);
             const cx2<T> *sp = reinterpret_cast<const cx2<T> *>(spec);
             if (ADJ) {
