@@ -145,6 +145,89 @@ __device__ __forceinline__ void dft<16, float>(cx<float> *u) { dft16_impl(u); }
 template <>
 __device__ __forceinline__ void dft<16, double>(cx<double> *u) { dft16_impl(u); }
 
+// Radix R DFT whose inputs u[R/2 .. R-1] are zero (the first stage of a
+// transform of a zero-padded sequence): the first layer of radix-4
+// butterflies sees two nonzero inputs each.
+template <typename T>
+__device__ __forceinline__ void dft4_zh(cx<T> &a0, cx<T> &a1, cx<T> &a2, cx<T> &a3) {
+    const cx<T> d1 = mul_mi(a1);
+    a2 = a0 - a1;
+    a3 = a0 - d1;
+    const cx<T> s = a0 + a1;
+    a1 = a0 + d1;
+    a0 = s;
+}
+
+template <int R, typename T>
+__device__ __forceinline__ void dft_zh(cx<T> *u) {
+    if constexpr (R == 4) {
+        dft4_zh(u[0], u[1], u[2], u[3]);
+    } else if constexpr (R == 8) {
+        const T h = T(0.70710678118654752440084436210484903928);
+        cx<T> e0 = u[0], e1 = u[2], e2, e3;
+        cx<T> o0 = u[1], o1 = u[3], o2, o3;
+        dft4_zh(e0, e1, e2, e3);
+        dft4_zh(o0, o1, o2, o3);
+        cx<T> w1 = {(o1.x + o1.y) * h, (o1.y - o1.x) * h};
+        cx<T> w2 = mul_mi(o2);
+        cx<T> w3 = {(o3.y - o3.x) * h, -(o3.x + o3.y) * h};
+        u[0] = e0 + o0;
+        u[4] = e0 - o0;
+        u[1] = e1 + w1;
+        u[5] = e1 - w1;
+        u[2] = e2 + w2;
+        u[6] = e2 - w2;
+        u[3] = e3 + w3;
+        u[7] = e3 - w3;
+    } else {
+        static_assert(R == 16, "radix");
+        const T c1 = T(0.92387953251128675612818318939678828682);
+        const T s1 = T(0.38268343236508977172845998403039886676);
+        const T h = T(0.70710678118654752440084436210484903928);
+        cx<T> a[4][4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            a[j][0] = u[j];
+            a[j][1] = u[j + 4];
+            dft4_zh(a[j][0], a[j][1], a[j][2], a[j][3]);
+        }
+        const cx<T> w[10] = {{T(1), T(0)}, {c1, -s1}, {h, -h}, {s1, -c1}, {T(0), T(-1)},
+                             {-s1, -c1}, {-h, -h}, {-c1, -s1}, {T(-1), T(0)}, {-c1, s1}};
+#pragma unroll
+        for (int j = 1; j < 4; ++j)
+#pragma unroll
+            for (int k = 1; k < 4; ++k) a[j][k] = cmul(a[j][k], w[j * k]);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            dft4(a[0][k], a[1][k], a[2][k], a[3][k]);
+            u[k] = a[0][k];
+            u[k + 4] = a[1][k];
+            u[k + 8] = a[2][k];
+            u[k + 12] = a[3][k];
+        }
+    }
+}
+
+// x w^k with w = exp(-2 pi i / E), E in {4, 8, 16}, for a k fixed at compile
+// time once loops are unrolled: quarter turns are swaps and sign changes,
+// the others one complex product by constants.
+template <int E, typename T>
+__device__ __forceinline__ cx<T> mul_root(cx<T> x, int k) {
+    static_assert(E == 4 || E == 8 || E == 16, "roots of unity of order 4, 8 or 16");
+    const int q = (((k % E) + E) % E) * (16 / E);   // sixteenths of a turn
+    if (q == 0) return x;
+    if (q == 4) return {x.y, -x.x};
+    if (q == 8) return {-x.x, -x.y};
+    if (q == 12) return {-x.y, x.x};
+    const T c1 = T(0.92387953251128675612818318939678828682);
+    const T s1 = T(0.38268343236508977172845998403039886676);
+    const T h = T(0.70710678118654752440084436210484903928);
+    // cos and sin of 2 pi q / 16
+    const T cs[16] = {T(1), c1, h, s1, T(0), -s1, -h, -c1, T(-1), -c1, -h, -s1, T(0), s1, h, c1};
+    const T c = cs[q], sn = cs[(q + 12) & 15];
+    return {x.x * c + x.y * sn, x.y * c - x.x * sn};
+}
+
 // ---------------------------------------------------------------------------
 // LDS accessors.  Element i of the FFT group lives at
 // base + pad(i) * stride with pad(i) = i + (i >> 4): one unused slot after
@@ -264,7 +347,7 @@ __device__ __forceinline__ void tw_expand(const cx<T> *p, cx<T> *o) {
 // stage's twiddles), NV (number of transforms).  All threads of the
 // workgroup must call this together (it contains __syncthreads()).
 // ---------------------------------------------------------------------------
-template <int N, int E, int NS, int OFF, int NV, typename T>
+template <int N, int E, int NS, int OFF, int NV, typename T, bool ZH = false>
 __device__ __forceinline__ void fft_stages(cx<T> (&v)[NV][E], int t, const Lds<T> (&lds)[NV],
                                            const Twiddles<N, E, T> &tw) {
     constexpr int TH = N / E;                 // threads per transform
@@ -288,7 +371,10 @@ __device__ __forceinline__ void fft_stages(cx<T> (&v)[NV][E], int t, const Lds<T
 #pragma unroll
                 for (int r = 1; r < R; ++r) u[r] = cmul(u[r], wr[r]);
             }
-            dft<R, T>(u);
+            if constexpr (ZH && NS == 1 && NB == 1)
+                dft_zh<R, T>(u);
+            else
+                dft<R, T>(u);
             if constexpr (LAST) {
 #pragma unroll
                 for (int r = 0; r < R; ++r) v[a][q + r * NB] = u[r];
@@ -311,12 +397,14 @@ __device__ __forceinline__ void fft_stages(cx<T> (&v)[NV][E], int t, const Lds<T
     }
 }
 
-// Forward transforms (sign -1) of NV arrays in strided order.
-template <int N, int E, int NV, typename T>
+// Forward transforms (sign -1) of NV arrays in strided order.  ZH: the
+// points of the upper half (v[e], e >= E/2) are zero and are not read.
+template <int N, int E, int NV, typename T, bool ZH = false>
 __device__ __forceinline__ void fft_fwd(cx<T> (&v)[NV][E], int t, const Lds<T> (&lds)[NV],
                                         const Twiddles<N, E, T> &tw) {
     static_assert((N & (N - 1)) == 0 && N >= E && E >= 2, "sizes");
-    fft_stages<N, E, 1, 0, NV, T>(v, t, lds, tw);
+    static_assert(!ZH || E >= 4, "zero upper half needs E >= 4");
+    fft_stages<N, E, 1, 0, NV, T, ZH>(v, t, lds, tw);
 }
 
 // Inverse transforms (sign +1, unnormalised) as swap(F(swap(x))), where
@@ -340,14 +428,14 @@ __device__ __forceinline__ void fft_inv(cx<T> (&v)[NV][E], int t, const Lds<T> (
 }
 
 // Single-array forms (the copies are register renames once inlined).
-template <int N, int E, typename T>
+template <int N, int E, typename T, bool ZH = false>
 __device__ __forceinline__ void fft_fwd(cx<T> (&v)[E], int t, const Lds<T> &lds,
                                         const Twiddles<N, E, T> &tw) {
     cx<T> vv[1][E];
     const Lds<T> l[1] = {lds};
 #pragma unroll
     for (int e = 0; e < E; ++e) vv[0][e] = v[e];
-    fft_fwd<N, E, 1, T>(vv, t, l, tw);
+    fft_fwd<N, E, 1, T, ZH>(vv, t, l, tw);
 #pragma unroll
     for (int e = 0; e < E; ++e) v[e] = vv[0][e];
 }

@@ -234,11 +234,12 @@ __device__ __forceinline__ cx<T> spec_mul(cx<T> s, cx<T> x, int e, bool t0) {
 // transform at k, W = exp(-2 pi i / L), is
 //   a0 + am1 W^-k + an W^(n k) + an1 W^((n-1) k).
 // A thread holds k = t + e TH, e < E, with W^(j k) = W^(j t) W^(j e TH) and
-// W^(j e TH) = r((j e) mod E), r(q) = exp(-2 pi i q / E) an E-th root of
-// unity, the same for the whole workgroup.  So per thread
+// W^(j e TH) = w^(j e), w = exp(-2 pi i / E) an E-th root of unity.  So per
+// thread
 //   b1 = an W^(n t),  b2 = am1 W^-t,  b3 = an1 W^((n-1) t)
-// and per point
-//   a0 + b1 r(n e) + b2 conj(r(e)) + b3 r((n-1) e).
+// and per point, with w^(n e) the same for the whole workgroup (read from
+// the table) and w^-e a constant of the unrolled code,
+//   a0 + b2 w^-e + w^(n e) (b1 + b3 w^-e).
 // ---------------------------------------------------------------------------
 template <typename T>
 struct SlopeFix {
@@ -276,23 +277,16 @@ __device__ __forceinline__ SlopePhasors<T> slope_phasors(const SlopeFix<T> &s, c
     return {s.a0, cmul(s.an, wnt), cmul(s.am1, wtc), cmul(s.an1, cmul(wnt, wtc))};
 }
 
-// E-th roots of unity the workgroup needs for point e: r(e), r(n e),
-// r((n-1) e), read from the L-point table (r(q) = W^(q L / E)) at addresses
-// that are the same for every lane
+// w^(n e) for point e, read from the L-point table (w^q = W^(q L / E)) at an
+// address that is the same for every lane
 template <typename T, int L, int E>
-struct Roots {
-    cx<T> r1, rn, rm;
-    __device__ __forceinline__ Roots(const cx<T> *__restrict__ twL, int n, int e) {
-        constexpr int TH = L / E;
-        r1 = twL[(e & (E - 1)) * TH];
-        rn = twL[((n * e) & (E - 1)) * TH];
-        rm = twL[(((n - 1) * e) & (E - 1)) * TH];
-    }
-};
+__device__ __forceinline__ cx<T> root_ne(const cx<T> *__restrict__ twL, int n, int e) {
+    return twL[((n * e) & (E - 1)) * (L / E)];
+}
 
-template <typename T, int L, int E>
-__device__ __forceinline__ cx<T> slope_fix_at(const SlopePhasors<T> &p, const Roots<T, L, E> &r) {
-    return p.a0 + cmul(p.b1, r.rn) + cmulc(p.b2, r.r1) + cmul(p.b3, r.rm);
+template <typename T, int E>
+__device__ __forceinline__ cx<T> slope_fix_at(const SlopePhasors<T> &p, cx<T> rne, int e) {
+    return p.a0 + mul_root<E>(p.b2, -e) + cmul(rne, p.b1 + mul_root<E>(p.b3, -e));
 }
 
 // Transforms of the two real sequences packed as p = c_0 + i c_M, from p and
@@ -356,7 +350,7 @@ __device__ __forceinline__ void body_cols_fwd(int unit, int G, cx<T> *__restrict
         const int i = t + e * TH;
         if (e >= E / 2 || !valid || i >= n_r) v[e] = cx<T>{T(0), T(0)};
     }
-    fft_fwd<L, E, T>(v, t, lds, tw);
+    fft_fwd<L, E, T, true>(v, t, lds, tw);
     if (packed) {   // column 0 reads the conjugate mirror points from LDS
 #pragma unroll
         for (int e = 0; e < E; ++e) lds.st_split(lds_pad(t), e * TH, v[e]);
@@ -389,11 +383,12 @@ __device__ __forceinline__ void body_cols_fwd(int unit, int G, cx<T> *__restrict
 #pragma unroll
         for (int j = 0; j < CH; ++j) {
             const int e = cb + j;
-            const Roots<T, L, E> r(twL, n_r, e);
+            const cx<T> rne = root_ne<T, L, E>(twL, n_r, e);
             if (is0) {
                 const cx<T> m = lds.ld((L - (t + e * TH)) & (L - 1));
                 const cx<T> A = unpack_even(v[e], m), B = unpack_odd(v[e], m);
-                const cx<T> f0 = slope_fix_at(ph0, r), fM = slope_fix_at(phM, r);
+                const cx<T> f0 = slope_fix_at<T, E>(ph0, rne, e);
+                const cx<T> fM = slope_fix_at<T, E>(phM, rne, e);
                 const cx<T> y0 = spec_mul<T, E, false, false>(pr[j].a, A, e, t0) +
                                  spec_mul<T, E, false, false>(pr[j].b, f0, e, t0);
                 const cx<T> yM = spec_mul<T, E, false, false>(pp[j].a, B, e, t0) +
@@ -401,7 +396,7 @@ __device__ __forceinline__ void body_cols_fwd(int unit, int G, cx<T> *__restrict
                 y[0][e] = cx<T>{y0.x - yM.y, y0.y + yM.x};   // y0 + i yM
                 y[1][e] = cx<T>{T(0), T(0)};
             } else {
-                const cx<T> f = slope_fix_at(ph, r);
+                const cx<T> f = slope_fix_at<T, E>(ph, rne, e);
                 y[0][e] = spec_mul<T, E, false, false>(pr[j].a, v[e], e, t0) +
                           spec_mul<T, E, false, false>(pr[j].b, f, e, t0);
                 y[1][e] = spec_mul<T, E, true, false>(pp[j].a, v[e], e, t0) +
@@ -413,8 +408,10 @@ __device__ __forceinline__ void body_cols_fwd(int unit, int G, cx<T> *__restrict
     fft_inv<L, E, T>(y[0], t, lds, tw);
     fft_inv<L, E, T>(y[1], t, lds, tw);
     if (valid) {
+        // only the first E/2 points of a thread can be rows (L >= 2 n_r): the
+        // rest of the last stage is never formed
 #pragma unroll
-        for (int e = 0; e < E; ++e) {
+        for (int e = 0; e < E / 2; ++e) {
             const int i = t + e * TH;
             if (i < n_r) Z[(size_t)i * H + col] = cx2<T>{y[0][e], y[1][e]};
         }
@@ -503,8 +500,8 @@ __device__ __forceinline__ void body_cols_adj(int unit, int G, cx<T> *__restrict
             va[1][e] = cx<T>{T(0), T(0)};
         }
     }
-    fft_fwd<L, E, T>(va[0], t, lds, tw);
-    fft_fwd<L, E, T>(va[1], t, lds, tw);
+    fft_fwd<L, E, T, true>(va[0], t, lds, tw);
+    fft_fwd<L, E, T, true>(va[1], t, lds, tw);
     if (packed) {   // column 0 reads the conjugate mirror points from LDS
 #pragma unroll
         for (int e = 0; e < E; ++e) lds.st_split(lds_pad(t), e * TH, va[0][e]);
@@ -553,11 +550,12 @@ __device__ __forceinline__ void body_cols_adj(int unit, int G, cx<T> *__restrict
                     spec_mul<T, E, true, true>(pp[j].b, va[1][e], e, t0);
             }
             va[0][e] = xe;   // V_r's point is not needed again
-            const Roots<T, L, E> ro(twL, n_r, e);
+            // r W^(j k) over the thread's points: w^e, w^-(n e), w^-((n-1) e)
+            const cx<T> q = cmulc(r, root_ne<T, L, E>(twL, n_r, e));
             w[0] = w[0] + r;
-            w[1] = w[1] + cmul(r, ro.r1);
-            w[2] = w[2] + cmulc(r, ro.rn);
-            w[3] = w[3] + cmulc(r, ro.rm);
+            w[1] = w[1] + mul_root<E>(r, e);
+            w[2] = w[2] + q;
+            w[3] = w[3] + mul_root<E>(q, e);
         }
     }
     if (packed) __syncthreads();
@@ -573,7 +571,7 @@ __device__ __forceinline__ void body_cols_adj(int unit, int G, cx<T> *__restrict
     fft_inv<L, E, T>(va[0], t, lds, tw);
     if (valid) {
 #pragma unroll
-        for (int e = 0; e < E; ++e) {
+        for (int e = 0; e < E / 2; ++e) {   // rows lie in the first half (L >= 2 n_r)
             const int i = t + e * TH;
             if (i < n_r) {
                 // transposed four-row correction
