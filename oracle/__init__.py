@@ -57,9 +57,13 @@ def _load():
     lib.or_forward.argtypes = [i, i, d, d, P, P, P, i64, P, P]
     lib.or_adjoint.argtypes = [i, i, d, d, P, P, P, P, i64, P]
     lib.or_forward_particle.argtypes = [i, i, d, d, i, P, P, P, i64, P, P]
+    lib.or_cart_tables.argtypes = [i, i, d, d, i, P]
+    lib.or_cart_slopes.argtypes = [i, i, d, d, P, P, P]
+    lib.or_cart_forward.argtypes = [i, i, d, d, P, P, P, i64, P, P]
     for f in ("or_geometry", "or_gauss_legendre", "or_selfcell_cover", "or_selfcell_pv",
               "or_table_entry", "or_tables", "or_channels", "or_forward",
-              "or_adjoint", "or_forward_particle", "or_num_threads"):
+              "or_adjoint", "or_forward_particle", "or_cart_tables", "or_cart_slopes",
+              "or_cart_forward", "or_num_threads"):
         getattr(lib, f).restype = i
     _lib = lib
     return lib
@@ -275,3 +279,80 @@ def error_norms(num, ana):
     e = np.abs(np.asarray(num, dtype=np.float64) - np.asarray(ana, dtype=np.float64))
     n = e.size
     return float(e.sum() / n), float(np.sqrt((e * e).sum() / n)), float(e.max())
+
+
+# ---------------------------------------------------------------------------
+# Cartesian coordinates (Sec. 3.1, Eq. 6-21, A1-A16)
+# ---------------------------------------------------------------------------
+CART_TABLE_NAMES = ("x0", "xx", "xy", "y0", "yy", "yx")
+CART_METHODS = {"second": 0, "particle": 1, "particle+": 2}
+
+
+class CartGrid:
+    """Uniform N_x x N_y grid of cells Delta x by Delta y (Sec. 3.1.1); cell
+    (i, j) has centre (x0 + (i + 1/2) Delta x, y0 + (j + 1/2) Delta y)."""
+
+    def __init__(self, n_x: int, n_y: int, dx: float, dy: float, x0: float = 0.0,
+                 y0: float = 0.0):
+        self.n_x, self.n_y = int(n_x), int(n_y)
+        self.dx, self.dy = float(dx), float(dy)
+        self.x0, self.y0 = float(x0), float(y0)
+
+    @classmethod
+    def square(cls, n: int, half_width: float):
+        """The paper's domain [-M, M]^2 with N_d = n cells per side."""
+        h = 2.0 * half_width / n
+        return cls(n, n, h, h, -half_width, -half_width)
+
+    @property
+    def shape(self):
+        return (self.n_x, self.n_y)
+
+    def centres(self):
+        x = self.x0 + (np.arange(self.n_x) + 0.5) * self.dx
+        y = self.y0 + (np.arange(self.n_y) + 0.5) * self.dy
+        return np.meshgrid(x, y, indexing="ij")
+
+
+def cart_tables(grid: CartGrid, method: str = "second"):
+    """The six Cartesian kernel tables [6][2N_x - 1][2N_y - 1], offsets
+    m = i - i', n = j - j' at [k][m + N_x - 1][n + N_y - 1]; kernels in the
+    order of ``CART_TABLE_NAMES`` (Eq. 13-15, A5-A13; particle kernels of
+    Eq. 20 and A15 with masses sigma Dx Dy, plus the self terms of Eq. 21 and
+    A16 for "particle+")."""
+    T = np.empty((6, 2 * grid.n_x - 1, 2 * grid.n_y - 1))
+    if _load().or_cart_tables(grid.n_x, grid.n_y, grid.dx, grid.dy, CART_METHODS[method], _p(T)):
+        raise ValueError("bad Cartesian grid")
+    return T
+
+
+def cart_slopes(grid: CartGrid, sigma):
+    """delta^x, delta^y: central differences, one-sided at the edges."""
+    s = _f64(sigma)
+    gx = np.empty_like(s)
+    gy = np.empty_like(s)
+    if _load().or_cart_slopes(grid.n_x, grid.n_y, grid.dx, grid.dy, _p(s), _p(gx), _p(gy)):
+        raise ValueError("bad Cartesian grid")
+    return gx, gy
+
+
+def cart_forward(grid: CartGrid, T, sigma, dest=None):
+    """F^x, F^y by the plain double sums of Eq. 9-12 and A1-A4 with tables
+    ``T`` from :func:`cart_tables`; ``dest``: optional flat indices
+    i * N_y + j."""
+    s = _f64(sigma)
+    T = _f64(T)
+    assert s.shape == grid.shape and T.shape == (6, 2 * grid.n_x - 1, 2 * grid.n_y - 1)
+    if dest is None:
+        fx = np.empty(grid.shape)
+        fy = np.empty(grid.shape)
+        d, nd = None, 0
+    else:
+        d = np.ascontiguousarray(dest, dtype=np.int64)
+        nd = d.size
+        fx = np.empty(nd)
+        fy = np.empty(nd)
+    if _load().or_cart_forward(grid.n_x, grid.n_y, grid.dx, grid.dy, _p(T), _p(s), _p(d), nd,
+                               _p(fx), _p(fy)):
+        raise RuntimeError("or_cart_forward failed")
+    return fx, fy

@@ -27,7 +27,10 @@
  *   - the transpose of that linear map, as a plain double sum, at any chosen
  *     set of source cells;
  *   - the particle and modified particle methods (Eq. 34-37, 56-62) as plain
- *     double sums of point masses in physical coordinates.
+ *     double sums of point masses in physical coordinates;
+ *   - on a uniform Cartesian grid: the six closed-form cell kernels (A8-A13),
+ *     the second-order method (Eq. 9-15, A1-A7) and the particle and
+ *     modified particle methods (Eq. 18-21, A14-A16) as plain double sums.
  *
  * Index conventions (0-based).  Radial cell i spans
  * [r_min beta^i, r_min beta^(i+1)], centre r_i = r_min beta^i (1+beta)/2 (the
@@ -49,6 +52,9 @@
  *   - the trapezoid rule acts on the whole azimuthal integrand including the
  *     local weight (xi - xi_c), so every table depends on (m, n) only;
  *   - H^phi_2 uses cos(xi) (the printed cos(phi) is a typo);
+ *   - Cartesian grid: cell slopes by central differences, one-sided at the
+ *     domain edges (the paper leaves them open); particle masses
+ *     sigma Delta x Delta y;
  *   - Cartesian cover of the self cell: cell sizes Delta x / per and
  *     Delta y / per (per = 10 by default), grid aligned so the fan centre is a
  *     cell centre, a cell kept iff its centre lies in the closed fan, and the
@@ -1009,6 +1015,160 @@ int or_forward_particle(int n_r, int n_phi, double r_min, double r_max, int plus
         f_phi[q] = fp;
     }
     free(rc); free(re); free(dr); free(dp); free(mass);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Cartesian coordinates (Sec. 3.1, Eq. 6-21, A1-A16).  An N_x x N_y grid of */
+/* cells Delta x by Delta y; cell (i, j), 0-based, i along x and j along y.  */
+/* Arrays are row-major [N_x][N_y].  Tables are indexed by the offsets        */
+/* m = i - i', n = j - j' (destination minus source), stored at             */
+/* [k][m + N_x - 1][n + N_y - 1], kernels in the order                       */
+/*   K^{x,0}, K^{x,x}, K^{x,y}, K^{y,0}, K^{y,y}, K^{y,x}                   */
+/* (Eq. 13-15 and A5-A7).  The source centre relative to the destination is */
+/* (X, Y) = (-m Delta x, -n Delta y).                                        */
+/*                                                                          */
+/* Second-order tables: the closed forms A8-A13 (cart_closed above) for     */
+/* cells within three cell sizes of the destination; beyond that the same   */
+/* integrals by a tensor Gauss-Legendre rule, whose order per direction is  */
+/* chosen so that (h / 2d)^(2n) < 1e-17 (the closed double differences lose */
+/* digits to cancellation far away).                                        */
+/* ------------------------------------------------------------------------ */
+static void cart_gl(double X, double Y, double dx, double dy, int nx, int ny, double K[6])
+{
+    const double *xg = gl_x[nx], *wx = gl_w[nx], *yg = gl_x[ny], *wy = gl_w[ny];
+    acc_t a[6];
+    for (int k = 0; k < 6; ++k) a[k].s = a[k].c = 0;
+    for (int p = 0; p < nx; ++p) {
+        const double u = 0.5 * dx * xg[p];            /* xbar - x_i' */
+        const double x = X + u;                        /* xbar - x_i  */
+        for (int q = 0; q < ny; ++q) {
+            const double v = 0.5 * dy * yg[q];        /* ybar - y_j' */
+            const double y = Y + v;                    /* ybar - y_j  */
+            const double r2 = x * x + y * y;
+            const double w = 0.25 * dx * dy * wx[p] * wy[q] / (r2 * sqrt(r2));
+            acc_add(&a[0], w * x);
+            acc_add(&a[1], w * x * u);
+            acc_add(&a[2], w * x * v);
+            acc_add(&a[3], w * y);
+            acc_add(&a[4], w * y * v);
+            acc_add(&a[5], w * y * u);
+        }
+    }
+    for (int k = 0; k < 6; ++k) K[k] = acc_get(&a[k]);
+}
+
+static int gl_order_for(double q)
+{
+    static const int ns[7] = {2, 3, 4, 6, 8, 12, 16};
+    for (int k = 0; k < 7; ++k)
+        if (pow(q, 2 * ns[k]) < 1e-17) return ns[k];
+    return 16;
+}
+
+/* method: 0 second order (Eq. 10-15), 1 particle (Eq. 20 kernel, no
+ * correction), 2 modified particle (Eq. 20 plus the self-cell correction
+ * of Eq. 21, i.e. K^{x,x}_{00} and K^{y,y}_{00} in the (0, 0) entries; the
+ * other self terms vanish by symmetry).  Particle masses sigma Dx Dy. */
+int or_cart_tables(int n_x, int n_y, double dx, double dy, int method, double *T)
+{
+    if (n_x < 2 || n_y < 2 || !(dx > 0) || !(dy > 0) || method < 0 || method > 2) return -1;
+    gl_init();
+    const long rows = 2L * n_x - 1, cols = 2L * n_y - 1, plane = rows * cols;
+    const double hmax = dx > dy ? dx : dy;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 4)
+#endif
+    for (long row = 0; row < rows; ++row) {
+        const int m = (int)row - (n_x - 1);
+        for (long col = 0; col < cols; ++col) {
+            const int n = (int)col - (n_y - 1);
+            const double X = -m * dx, Y = -n * dy;
+            const double d = sqrt(X * X + Y * Y);
+            double K[6] = {0, 0, 0, 0, 0, 0};
+            if (method == 0) {
+                if (d < 3.0 * hmax)
+                    cart_closed(X - 0.5 * dx, X + 0.5 * dx, Y - 0.5 * dy, Y + 0.5 * dy, X, Y, K);
+                else
+                    cart_gl(X, Y, dx, dy, gl_order_for(0.5 * dx / d), gl_order_for(0.5 * dy / d), K);
+            } else if (m != 0 || n != 0) {
+                const double w = dx * dy / (d * d * d);
+                K[0] = w * X;
+                K[3] = w * Y;
+            } else if (method == 2) {
+                double S[6];
+                cart_closed(-0.5 * dx, 0.5 * dx, -0.5 * dy, 0.5 * dy, 0.0, 0.0, S);
+                K[1] = S[1];
+                K[4] = S[4];
+            }
+            for (int k = 0; k < 6; ++k) T[k * plane + row * cols + col] = K[k];
+        }
+    }
+    return 0;
+}
+
+/* Cell slopes: central differences, one-sided two-point differences on the
+ * first and last cells of each direction. */
+static void cart_slopes(int n_x, int n_y, double dx, double dy, const double *s, double *gx,
+                        double *gy)
+{
+    for (int i = 0; i < n_x; ++i)
+        for (int j = 0; j < n_y; ++j) {
+            const long c = (long)i * n_y + j;
+            if (i == 0) gx[c] = (s[c + n_y] - s[c]) / dx;
+            else if (i == n_x - 1) gx[c] = (s[c] - s[c - n_y]) / dx;
+            else gx[c] = (s[c + n_y] - s[c - n_y]) / (2.0 * dx);
+            if (j == 0) gy[c] = (s[c + 1] - s[c]) / dy;
+            else if (j == n_y - 1) gy[c] = (s[c] - s[c - 1]) / dy;
+            else gy[c] = (s[c + 1] - s[c - 1]) / (2.0 * dy);
+        }
+}
+
+int or_cart_slopes(int n_x, int n_y, double dx, double dy, const double *sigma, double *gx,
+                   double *gy)
+{
+    if (n_x < 2 || n_y < 2) return -1;
+    cart_slopes(n_x, n_y, dx, dy, sigma, gx, gy);
+    return 0;
+}
+
+/* F^x, F^y as the plain double sums of Eq. 9-12 and A1-A4 at the chosen
+ * destinations (flat i * N_y + j), or at every cell. */
+int or_cart_forward(int n_x, int n_y, double dx, double dy, const double *T, const double *sigma,
+                    const int64_t *dest, int64_t n_dest, double *f_x, double *f_y)
+{
+    if (n_x < 2 || n_y < 2) return -1;
+    const long N = (long)n_x * n_y;
+    const long cols = 2L * n_y - 1, plane = (2L * n_x - 1) * cols;
+    double *gx = (double *)malloc(sizeof(double) * N), *gy = (double *)malloc(sizeof(double) * N);
+    if (!gx || !gy) { free(gx); free(gy); return -2; }
+    cart_slopes(n_x, n_y, dx, dy, sigma, gx, gy);
+    const long nd = dest ? (long)n_dest : N;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 4)
+#endif
+    for (long q = 0; q < nd; ++q) {
+        const long cell = dest ? (long)dest[q] : q;
+        const int i = (int)(cell / n_y), j = (int)(cell % n_y);
+        acc_t ax = {0, 0}, ay = {0, 0};
+        for (int ip = 0; ip < n_x; ++ip) {
+            const long row = (long)(i - ip) + (n_x - 1);
+            const long base = row * cols + (j + n_y - 1);   /* column of jp = 0 */
+            double sx = 0, sy = 0;
+            for (int jp = 0; jp < n_y; ++jp) {
+                const long t = base - jp;
+                const long c = (long)ip * n_y + jp;
+                sx += sigma[c] * T[t] + gx[c] * T[plane + t] + gy[c] * T[2 * plane + t];
+                sy += sigma[c] * T[3 * plane + t] + gy[c] * T[4 * plane + t] +
+                      gx[c] * T[5 * plane + t];
+            }
+            acc_add(&ax, sx);
+            acc_add(&ay, sy);
+        }
+        f_x[q] = acc_get(&ax);
+        f_y[q] = acc_get(&ay);
+    }
+    free(gx); free(gy);
     return 0;
 }
 
