@@ -202,6 +202,53 @@ int pf_plan_tables(pf_plan plan, double *dst);
 /* Release the plan and everything it owns.  NULL is ignored.              */
 void pf_plan_destroy(pf_plan plan);
 
+/* ---- Cartesian grid (Sec. 3.1) ------------------------------------------
+ * The paper's uniform-grid methods, on the same three-pass FFT structure:
+ * the second-order method (Eq. 9-15, A1-A13: three convolutions of the cell
+ * density and its two slopes with the closed-form cell kernels A8-A13) and
+ * the particle and modified particle methods (Eq. 18-21, A14-A16: point
+ * masses sigma Dx Dy at the cell centres with no self force, the modified
+ * method adding delta^x K^{x,x}_{00} to F^x and delta^y K^{y,y}_{00} to
+ * F^y).  Grid: N_x x N_y cells of Dx by Dy; cell (i, j) at offset
+ * i * N_y + j of every field, i along x.  Slopes are central differences,
+ * one-sided on the first and last cell of each direction.  The convolution
+ * is zero-padded in both directions (no mass outside the grid, no
+ * artificial boundary).  F^x, F^y are the forces at the cell centres
+ * (G = 1).  Field pointers are device pointers of the plan's precision;
+ * errors, streams and ownership as for the log-polar plan.               */
+typedef struct pf_cart_s *pf_cart;
+
+enum pf_cart_method {
+    PF_CART_SECOND = 0,          /* second-order method (Eq. 9-15)        */
+    PF_CART_PARTICLE = 1,        /* particle method without softening     */
+                                 /* and without the correction (Eq. 20)   */
+    PF_CART_PARTICLE_PLUS = 2    /* modified particle method (Eq. 18-21)  */
+};
+
+/* Create a Cartesian plan; host only.  4 <= N_x, N_y <= 2048; Dx, Dy > 0
+ * and finite.  NULL on failure (pf_last_error()).                        */
+pf_cart pf_cart_create(int n_x, int n_y, double dx, double dy);
+
+/* Build the kernel tables and their spectra on the current device (FP64,
+ * rounded once for PF_F32), synchronised before returning.  dtype: PF_F32
+ * or PF_F64; method: a pf_cart_method.  May be called again.              */
+int pf_cart_build(pf_cart plan, int dtype, int method, void *stream);
+
+/* sigma [N_x][N_y] -> f_x, f_y [N_x][N_y].  Asynchronous.                 */
+int pf_cart_forces(pf_cart plan, const void *sigma, void *f_x, void *f_y, void *stream);
+
+/* Diagnostic form of pf_cart_forces: each of the three passes launched
+ * `reps` times back to back (1 <= reps <= 10000) between events; writes the
+ * mean duration of one launch in ms to pass_ms[3].  Synchronous.          */
+int pf_cart_forces_timed(pf_cart plan, const void *sigma, void *f_x, void *f_y, int reps,
+                         void *stream, float *pass_ms);
+
+/* out[0..3] = N_x, N_y, L_x, L_y (the padded transform lengths).          */
+int pf_cart_geometry(pf_cart plan, int out[4]);
+
+/* Release the plan.  NULL is ignored.                                    */
+void pf_cart_destroy(pf_cart plan);
+
 /* Per-thread description of the last failure ("" if none).                */
 const char *pf_last_error(void);
 

@@ -33,10 +33,15 @@ _SELF_MODES = {"cartesian": PF_SELF_CARTESIAN, "exact": PF_SELF_EXACT}
 _STATUS = {1: "PF_EINVAL", 2: "PF_ESTATE", 3: "PF_ENOMEM", 4: "PF_EHIP", 5: "PF_ENODEV",
            6: "PF_EUNSUPPORTED"}
 
+PF_CART_SECOND, PF_CART_PARTICLE, PF_CART_PARTICLE_PLUS = 0, 1, 2
+_CART_METHODS = {"second": PF_CART_SECOND, "particle": PF_CART_PARTICLE,
+                 "particle+": PF_CART_PARTICLE_PLUS}
+
 EXPORTS = ("pf_build_opts_default", "pf_plan_create", "pf_kernels_build", "pf_forces",
            "pf_forces_backward", "pf_forces_batched", "pf_forces_timed", "pf_plan_geometry",
            "pf_plan_schedule", "pf_plan_selfcell", "pf_plan_tables", "pf_plan_destroy",
-           "pf_last_error", "pf_version")
+           "pf_last_error", "pf_version", "pf_cart_create", "pf_cart_build", "pf_cart_forces",
+           "pf_cart_forces_timed", "pf_cart_geometry", "pf_cart_destroy")
 
 
 class PFError(RuntimeError):
@@ -90,6 +95,16 @@ def load():
         getattr(lib, f).restype = I
     lib.pf_plan_destroy.argtypes = [P]
     lib.pf_plan_destroy.restype = None
+    lib.pf_cart_create.argtypes = [I, I, D, D]
+    lib.pf_cart_create.restype = P
+    lib.pf_cart_build.argtypes = [P, I, I, P]
+    lib.pf_cart_forces.argtypes = [P, P, P, P, P]
+    lib.pf_cart_forces_timed.argtypes = [P, P, P, P, I, P, P]
+    lib.pf_cart_geometry.argtypes = [P, P]
+    for f in ("pf_cart_build", "pf_cart_forces", "pf_cart_forces_timed", "pf_cart_geometry"):
+        getattr(lib, f).restype = I
+    lib.pf_cart_destroy.argtypes = [P]
+    lib.pf_cart_destroy.restype = None
     lib.pf_last_error.argtypes = []
     lib.pf_last_error.restype = ctypes.c_char_p
     lib.pf_version.argtypes = []
@@ -184,6 +199,39 @@ def pf_plan_tables(plan: int, n_r: int, n_phi: int):
 
 def pf_plan_destroy(plan: int) -> None:
     load().pf_plan_destroy(plan)
+
+
+def pf_cart_create(n_x: int, n_y: int, dx: float, dy: float) -> int:
+    h = load().pf_cart_create(int(n_x), int(n_y), float(dx), float(dy))
+    if not h:
+        raise PFError(PF_EINVAL, pf_last_error())
+    return h
+
+
+def pf_cart_build(plan: int, dtype: int, method: int, stream: int = 0) -> None:
+    _check(load().pf_cart_build(plan, int(dtype), int(method), stream or None))
+
+
+def pf_cart_forces(plan: int, sigma: int, f_x: int, f_y: int, stream: int = 0) -> None:
+    _check(load().pf_cart_forces(plan, sigma, f_x, f_y, stream or None))
+
+
+def pf_cart_forces_timed(plan: int, sigma: int, f_x: int, f_y: int, reps: int = 1,
+                         stream: int = 0):
+    ms = (ctypes.c_float * 3)()
+    _check(load().pf_cart_forces_timed(plan, sigma, f_x, f_y, int(reps), stream or None, ms))
+    return [float(v) for v in ms]
+
+
+def pf_cart_geometry(plan: int):
+    """(N_x, N_y, L_x, L_y)."""
+    out = np.zeros(4, dtype=np.int32)
+    _check(load().pf_cart_geometry(plan, out.ctypes.data))
+    return tuple(int(v) for v in out)
+
+
+def pf_cart_destroy(plan: int) -> None:
+    load().pf_cart_destroy(plan)
 
 
 # --------------------------------------------------------------------------
@@ -336,3 +384,68 @@ def forces(sigma, plan: Plan):
     if _FN is None:
         _FN = _make_function()
     return _FN.apply(sigma, plan)
+
+
+class CartPlan:
+    """A built N_x x N_y uniform Cartesian grid of cells dx by dy (Sec. 3.1):
+    method "second" (Eq. 9-15), "particle" (Eq. 20) or "particle+"
+    (Eq. 18-21)."""
+
+    def __init__(self, n_x, n_y, dx, dy, dtype="f32", method="second", build=True):
+        self.n_x, self.n_y = int(n_x), int(n_y)
+        self.dx, self.dy = float(dx), float(dy)
+        self.handle = pf_cart_create(n_x, n_y, dx, dy)
+        self.dtype = None
+        if build:
+            self.build(dtype, method)
+
+    def build(self, dtype="f32", method="second"):
+        d = PF_F64 if dtype in ("f64", "float64", PF_F64) else PF_F32
+        pf_cart_build(self.handle, d, _CART_METHODS[method], _stream())
+        self.dtype = "f64" if d == PF_F64 else "f32"
+        return self
+
+    @property
+    def torch_dtype(self):
+        import torch
+        return torch.float64 if self.dtype == "f64" else torch.float32
+
+    @property
+    def shape(self):
+        return (self.n_x, self.n_y)
+
+    def geometry(self):
+        return pf_cart_geometry(self.handle)
+
+    def _check_field(self, t, name):
+        import torch
+        if not isinstance(t, torch.Tensor) or not t.is_cuda:
+            raise TypeError("%s must be a CUDA tensor" % name)
+        if t.dtype != self.torch_dtype or tuple(t.shape) != self.shape or not t.is_contiguous():
+            raise TypeError("%s must be a contiguous %s tensor of shape %s"
+                            % (name, self.torch_dtype, self.shape))
+
+    def forces(self, sigma, out=None):
+        import torch
+        self._check_field(sigma, "sigma")
+        fx, fy = out if out is not None else (torch.empty_like(sigma), torch.empty_like(sigma))
+        pf_cart_forces(self.handle, sigma.data_ptr(), fx.data_ptr(), fy.data_ptr(), _stream())
+        return fx, fy
+
+    def timed(self, sigma, reps=1):
+        import torch
+        self._check_field(sigma, "sigma")
+        fx, fy = torch.empty_like(sigma), torch.empty_like(sigma)
+        return pf_cart_forces_timed(self.handle, sigma.data_ptr(), fx.data_ptr(), fy.data_ptr(),
+                                    reps, _stream())
+
+    def close(self):
+        if getattr(self, "handle", None):
+            pf_cart_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -18,7 +18,7 @@ OUT = os.path.join(HERE, "libpf.so")
 BUILD = os.path.join(HERE, "_build")
 ARCH = os.environ.get("PF_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["pf_api.hip", "pf_passes.hip", "pf_tables.hip", "pf_batched.hip"]
+SOURCES = ["pf_api.hip", "pf_passes.hip", "pf_tables.hip", "pf_batched.hip", "pf_cart.hip"]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH,

@@ -103,3 +103,29 @@ def test_default_options():
     assert (o.table_mode, o.self_mode) == (pf.PF_TABLE_SIM, pf.PF_SELF_CARTESIAN)
     assert o.method == pf.PF_METHOD_SIM
     assert (pf.PF_METHOD_PARTICLE, pf.PF_METHOD_PARTICLE_PLUS) == (1, 2)
+
+
+def test_cartesian_plan_host_checks():
+    lib = pf.load()
+    for args in [(3, 8, 0.1, 0.1), (8, 2049, 0.1, 0.1), (8, 8, 0.0, 0.1), (8, 8, 0.1, float("inf"))]:
+        with pytest.raises(pf.PFError):
+            pf.pf_cart_create(*args)
+        assert pf.pf_last_error()
+    h = pf.pf_cart_create(100, 37, 0.1, 0.2)
+    try:
+        # padded transform lengths: powers of two of at least twice the grid
+        assert pf.pf_cart_geometry(h) == (100, 37, 256, 128)
+        ms3 = (ctypes.c_float * 3)()
+        assert lib.pf_cart_forces(h, 8, 8, 8, None) == pf.PF_ESTATE
+        assert lib.pf_cart_forces_timed(h, 8, 8, 8, 1, None, ms3) == pf.PF_ESTATE
+        assert lib.pf_cart_forces(h, None, 8, 8, None) == pf.PF_EINVAL
+        assert lib.pf_cart_forces(None, 8, 8, 8, None) == pf.PF_EINVAL
+        assert lib.pf_cart_forces_timed(h, 8, 8, 8, 0, None, ms3) == pf.PF_EINVAL
+        assert lib.pf_cart_geometry(h, None) == pf.PF_EINVAL
+        # bad options are refused before the device is touched
+        assert lib.pf_cart_build(h, 7, pf.PF_CART_SECOND, None) == pf.PF_EINVAL
+        assert lib.pf_cart_build(h, pf.PF_F32, 3, None) == pf.PF_EINVAL
+        assert lib.pf_cart_build(None, pf.PF_F32, 0, None) == pf.PF_EINVAL
+    finally:
+        pf.pf_cart_destroy(h)
+    pf.pf_cart_destroy(None)
