@@ -6,9 +6,10 @@ Headline: cells/s of the forward map (F_r + F_phi) on the single-disk
 m = 2 logarithmic spiral), FP32 FFT/multiply with FP64-built kernel spectra.
 One step = one pf_forces call on that grid with the density already resident
 in HBM.  Also reported: the FP64 path, the transpose (backward) in both
-precisions, the 64-disk batched launch, the one-time table build, the
-roofline of the dominant kernel (the fused column pass) and the FP64 CPU
-oracle timed on the host's cores.
+precisions, the 64-disk batched launch, the Cartesian second-order method on
+a 1024 x 1024 grid, the one-time table builds, the roofline of the dominant
+kernel (the fused column pass) and the FP64 CPU oracle timed on the host's
+cores.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
                        [--no-batched] [--forward-only] [--copy-reference]
@@ -89,6 +90,19 @@ def path_bytes(n_r, n_phi, L, w):
     a = n_r * n_phi * w + n_r * H * 2 * w
     b = n_r * H * 2 * w + 4 * (L // 2 + 1) * H * 2 * w + 2 * n_r * H * 2 * w
     c = 2 * n_r * H * 2 * w + 2 * n_r * n_phi * w
+    return a, b, c
+
+
+def cart_path_bytes(n_x, n_y, Lx, Ly, w):
+    """Algorithmic HBM bytes of one Cartesian forward call, H = L_y/2:
+    pass A reads sigma (N_x N_y w) and writes the (S, Dy) pairs
+    (N_x H 4w); pass B reads them, the six half spectra
+    (2 H (L_x/2+1) (4w + 2w)) and writes the (Zx, Zy) pairs (N_x H 4w);
+    pass C reads the pairs and writes F^x, F^y (2 N_x N_y w)."""
+    H = Ly // 2
+    a = n_x * n_y * w + n_x * H * 4 * w
+    b = n_x * H * 4 * w + 2 * H * (Lx // 2 + 1) * 6 * w + n_x * H * 4 * w
+    c = n_x * H * 4 * w + 2 * n_x * n_y * w
     return a, b, c
 
 
@@ -286,7 +300,35 @@ def main():
                    "cells": bcells, "ms_per_call": msb, "cells_per_s": bcells / (msb * 1e-3),
                    "table_build_s": build_b}
 
+    # ---- Cartesian grid (second-order method, sigma_D2 disk) -----------------
+    log("cartesian 1024 x 1024")
+    cart = {}
+    NC = 1024
+    xc = (np.arange(NC) + 0.5) / NC - 0.5
+    Xc, Yc = np.meshgrid(xc, xc, indexing="ij")
+    sig_c = np.clip(1.0 - (Xc ** 2 + Yc ** 2) / 0.25 ** 2, 0.0, None) ** 1.5
+    for dt in ("f32", "f64"):
+        t0 = time.perf_counter()
+        pc = pf.CartPlan(NC, NC, 1.0 / NC, 1.0 / NC, dtype=dt, method="second")
+        torch.cuda.synchronize()
+        bc = time.perf_counter() - t0
+        sc = torch.tensor(sig_c, dtype=pc.torch_dtype, device=dev)
+        oc = (torch.empty_like(sc), torch.empty_like(sc))
+        msc = time_calls(torch, lambda: pc.forces(sc, oc), max(K // 2, 10), W)
+        pmc = pc.timed(sc, reps=100)
+        _, _, Lx, Ly = pc.geometry()
+        bts = cart_path_bytes(NC, NC, Lx, Ly, 4 if dt == "f32" else 8)
+        cart[dt] = {"ms_per_call": msc, "cells_per_s": NC * NC / (msc * 1e-3), "pass_ms": pmc,
+                    "pass_bytes": list(bts),
+                    "pass_GBs": [b / (t * 1e-3) / 1e9 for b, t in zip(bts, pmc)],
+                    "pass_B_frac_of_hbm_peak": bts[1] / (pmc[1] * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                    "table_build_s": bc}
+        pc.close()
+    cart["workload"] = ("Cartesian 1024 x 1024 cells on [-0.5, 0.5]^2, sigma_D2 disk "
+                        "(alpha = 0.25), second-order method")
+
     out["detail"].update({
+        "cartesian": cart,
         "schedule_fp64": sched(p64),
         "fp64": {"ms_per_call": ms64, "cells_per_s": cells / (ms64 * 1e-3),
                  "pass_ms": passes64,

@@ -440,7 +440,7 @@ __device__ __forceinline__ void body_cart_cols(int unit, int G, cx<T> *__restric
         phM = slope_phasors(slope_fix_part(a, true), wt, wnt);
     }
     // spectrum loads per batch: six complex values per point
-    constexpr int CH = sizeof(T) == 8 ? 2 : 4;
+    constexpr int CH = sizeof(T) == 8 ? 1 : 4;
     const bool t0 = t == 0;
 #pragma unroll
     for (int cb = 0; cb < E; cb += CH) {
@@ -616,9 +616,15 @@ Shape cart_rows_shape(int M) {
     return s;
 }
 
+// The column body holds two transforms and six spectra per point: E = 8
+// points per thread in FP32 and 4 in FP64 keep it within the register file
+// (it spills at 16 and 8 respectively); FP64 at L = 4096 takes E = 8 to stay
+// within 512 threads per column.
+__host__ __device__ constexpr int cart_cols_e(int L, bool f64) { return f64 && L < 4096 ? 4 : 8; }
+
 Shape cart_cols_shape(int L, bool f64) {
     Shape s;
-    s.E = (!f64 && L >= 1024) ? 16 : 8;
+    s.E = cart_cols_e(L, f64);
     const int th = L / s.E;
     s.G = th >= 256 ? 1 : 256 / th;
     return s;
@@ -675,7 +681,7 @@ int launch_cart_rows(const CartPlan &c, bool pass_c, const void *in, void *o0, v
 
 template <typename T, int L>
 int cols_l(const CartPlan &c, const void *SD, void *Z, hipStream_t st) {
-    constexpr int E = (sizeof(T) == 4 && L >= 1024) ? 16 : 8;
+    constexpr int E = cart_cols_e(L, sizeof(T) == 8);
     const Shape s = cart_cols_shape(L, sizeof(T) == 8);
     const int n_groups = (c.H + s.G - 1) / s.G;
     const int per_xcd = (n_groups + 7) / 8;
