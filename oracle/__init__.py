@@ -57,12 +57,17 @@ def _load():
     lib.or_forward.argtypes = [i, i, d, d, P, P, P, i64, P, P]
     lib.or_adjoint.argtypes = [i, i, d, d, P, P, P, P, i64, P]
     lib.or_forward_particle.argtypes = [i, i, d, d, i, P, P, P, i64, P, P]
+    lib.or_patch_tables.argtypes = [i, i, i, i, d, d, i, i, P, P]
+    lib.or_wedge_tables.argtypes = [i, i, d, d, i, i, P]
+    lib.or_patch_forward.argtypes = [i, i, i, i, d, d, P, P, P, P, P, i64, P, P]
+    lib.or_patch_particle.argtypes = [i, i, i, i, d, d, i, P, P, P, P, i64, P, P]
     lib.or_cart_tables.argtypes = [i, i, d, d, i, P]
     lib.or_cart_slopes.argtypes = [i, i, d, d, P, P, P]
     lib.or_cart_forward.argtypes = [i, i, d, d, P, P, P, i64, P, P]
     for f in ("or_geometry", "or_gauss_legendre", "or_selfcell_cover", "or_selfcell_pv",
               "or_table_entry", "or_tables", "or_channels", "or_forward",
-              "or_adjoint", "or_forward_particle", "or_cart_tables", "or_cart_slopes",
+              "or_adjoint", "or_forward_particle", "or_patch_tables", "or_wedge_tables",
+              "or_patch_forward", "or_patch_particle", "or_cart_tables", "or_cart_slopes",
               "or_cart_forward", "or_num_threads"):
         getattr(lib, f).restype = i
     _lib = lib
@@ -279,6 +284,84 @@ def error_norms(num, ana):
     e = np.abs(np.asarray(num, dtype=np.float64) - np.asarray(ana, dtype=np.float64))
     n = e.size
     return float(e.sum() / n), float(np.sqrt((e * e).sum() / n)), float(e.max())
+
+
+# ---------------------------------------------------------------------------
+# Two patches of one log-polar grid and the origin wedges (Sec. 3.2.1)
+# ---------------------------------------------------------------------------
+def patch_tables(grid: Grid, n_src: int, s0: int, n_tpz: int = 19, self_k=None,
+                 table_mode: str = "sim", self_mode: str = "cartesian", cover_per: int = 10):
+    """Tables of the source patch (rows s0 .. s0 + n_src - 1 of the grid of
+    the destination patch ``grid``) acting on the destination:
+    [6][n_src + n_dst - 1][N_phi], row m' + n_src - 1 for m' = i - i'."""
+    if self_k is None:
+        self_k = (selfcell_pv(grid.beta, grid.dphi) if self_mode == "exact"
+                  else selfcell_cover(grid.beta, grid.dphi, cover_per)[:3])
+    sk = _f64(self_k)
+    T = np.empty((6, n_src + grid.n_r - 1, grid.n_phi))
+    mode = {"sim": 0, "exact": 1}[table_mode]
+    if _load().or_patch_tables(int(n_src), int(s0), grid.n_r, grid.n_phi, grid.r_min,
+                               grid.r_max, int(n_tpz), mode, _p(sk), _p(T)):
+        raise ValueError("bad patch arguments")
+    return T
+
+
+def wedge_tables(grid: Grid, s0: int, method: str = "sim"):
+    """Origin-wedge kernels [6][N_dst][N_phi] for wedges of radius
+    r_min beta^s0 (method "sim": the integrals; "particle": point masses)."""
+    T = np.empty((6, grid.n_r, grid.n_phi))
+    m = 0 if method == "sim" else 1
+    if _load().or_wedge_tables(grid.n_r, grid.n_phi, grid.r_min, grid.r_max, int(s0), m, _p(T)):
+        raise ValueError("bad wedge arguments")
+    return T
+
+
+def _dest(grid, dest):
+    if dest is None:
+        return None, 0, np.empty(grid.shape), np.empty(grid.shape)
+    d = np.ascontiguousarray(dest, dtype=np.int64)
+    return d, d.size, np.empty(d.size), np.empty(d.size)
+
+
+def patch_forward(grid: Grid, n_src: int, s0: int, T, sigma_src, Tw=None, sigma_w=None,
+                  dest=None):
+    """F_r, F_phi on the destination patch from the source patch (and the
+    origin wedges when Tw and sigma_w are given), plain double sums."""
+    s = _f64(sigma_src)
+    assert s.shape == (n_src, grid.n_phi)
+    T = _f64(T)
+    Tw = _f64(Tw) if Tw is not None else None
+    sw = _f64(sigma_w) if sigma_w is not None else None
+    d, nd, fr, fp = _dest(grid, dest)
+    if _load().or_patch_forward(int(n_src), int(s0), grid.n_r, grid.n_phi, grid.r_min,
+                                grid.r_max, _p(T), _p(s), _p(Tw), _p(sw), _p(d), nd, _p(fr),
+                                _p(fp)):
+        raise RuntimeError("or_patch_forward failed")
+    return fr, fp
+
+
+def patch_particle(grid: Grid, n_src: int, s0: int, sigma_src, sigma_w=None, plus=False,
+                   self_k=None, dest=None):
+    """Particle (plus=False) or modified particle method between patches,
+    point masses in physical coordinates, wedges as point masses."""
+    s = _f64(sigma_src)
+    if self_k is None:
+        self_k = selfcell_cover(grid.beta, grid.dphi, 10)[:3]
+    sk = _f64(self_k)
+    sw = _f64(sigma_w) if sigma_w is not None else None
+    d, nd, fr, fp = _dest(grid, dest)
+    if _load().or_patch_particle(int(n_src), int(s0), grid.n_r, grid.n_phi, grid.r_min,
+                                 grid.r_max, int(bool(plus)), _p(sk), _p(s), _p(sw), _p(d), nd,
+                                 _p(fr), _p(fp)):
+        raise RuntimeError("or_patch_particle failed")
+    return fr, fp
+
+
+def patch_centres(grid: Grid, n_src: int, s0: int):
+    """Centres of the source rows and the wedge centre r_w / 2."""
+    k = s0 + np.arange(n_src)
+    rc = grid.r_min * grid.beta ** k * 0.5 * (1.0 + grid.beta)
+    return rc, 0.5 * grid.r_min * grid.beta ** s0
 
 
 # ---------------------------------------------------------------------------

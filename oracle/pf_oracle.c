@@ -28,6 +28,10 @@
  *     set of source cells;
  *   - the particle and modified particle methods (Eq. 34-37, 56-62) as plain
  *     double sums of point masses in physical coordinates;
+ *   - two patches of one log-polar grid (destination and source rows at any
+ *     integer offset) and the origin wedges below the source patch, by the
+ *     same direct sums (Sec. 3.2.1, Eq. 27-29), for the second-order and the
+ *     particle methods;
  *   - on a uniform Cartesian grid: the six closed-form cell kernels (A8-A13),
  *     the second-order method (Eq. 9-15, A1-A7) and the particle and
  *     modified particle methods (Eq. 18-21, A14-A16) as plain double sums.
@@ -164,7 +168,7 @@ static inline double acc_get(const acc_t *a) { return a->s + a->c; }
 /* agreeing to tol, refinement stops there.  The accepted value is the       */
 /* two-half sum.                                                             */
 /* ------------------------------------------------------------------------ */
-#define AD_KMAX 4
+#define AD_KMAX 6
 #define AD_BUDGET 2000
 typedef void (*ad_fn)(double x, void *ctx, double *out);
 
@@ -1016,6 +1020,305 @@ int or_forward_particle(int n_r, int n_phi, double r_min, double r_max, int plus
     }
     free(rc); free(re); free(dr); free(dp); free(mass);
     return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Two patches of one log-polar grid (Sec. 3.2.1, Eq. 27-29 with the         */
+/* interaction and origin terms).  Rows of the common grid are indexed by    */
+/* any integer k: row k spans [r_min beta^k, r_min beta^(k+1)], centre       */
+/* r_min beta^k (1 + beta)/2, with beta and dphi from the destination patch  */
+/* (N_dst rows from r_min to r_max).  The source patch holds rows            */
+/* s0 ... s0 + N_src - 1.  Destination row i and source row i' are at the    */
+/* offset m = i - (s0 + i'); tables are stored by m' = i - i' in              */
+/* [-(N_src-1), N_dst-1], row m' + N_src - 1, each entry the kernel of        */
+/* offset m = m' - s0.  Source slopes are taken inside the source patch      */
+/* (one-sided on its first and last rows).                                    */
+/*                                                                          */
+/* Origin wedges (the cells R^hat_j = [0, r_w] x [phi_j' +- dphi/2] below    */
+/* the source patch, r_w = r_min beta^s0; the paper uses barred kernels for  */
+/* them without defining them).  Reading: the same integrands as Eq. 30-32   */
+/* and A22-A24 over the wedge, the wedge's radial centre taken as r_w / 2    */
+/* (the arithmetic centre, as for every other cell), its density value at    */
+/* that centre, its azimuthal slope by periodic central differences and its  */
+/* radial slope by the one-sided difference towards the first source row.   */
+/* In units of r_i (eta = rbar / r_i, xi = phibar - phi_j, xi_c = -n dphi):  */
+/*   Tw_r0 = -int eta (1 - eta cos xi) / F^3,                               */
+/*   Tw_rr = -int eta (1 - eta cos xi) (eta - eta_c) / F^3,                 */
+/*   Tw_rphi = -int eta (1 - eta cos xi) (xi - xi_c) / F^3,                 */
+/*   Tw_phi0 = int eta^2 sin xi / F^3, and likewise Tw_phir, Tw_phiphi,      */
+/* over eta in [0, r_w / r_i], eta_c = r_w / (2 r_i), xi in [xi_c +- dphi/2]; */
+/* F^r += sigma Tw_r0 + r_i delta^r Tw_rr + delta^phi Tw_rphi, and the same  */
+/* for F^phi.  The integrand is smooth (the wedge lies inside r_min), so a    */
+/* 24-point Gauss-Legendre rule in xi and adaptive Gauss-Legendre in eta are */
+/* used.  For the particle methods a wedge is the point mass                 */
+/* sigma r_w^2 dphi / 2 (its exact area) at (r_w / 2, phi_j').               */
+/* ------------------------------------------------------------------------ */
+int or_patch_tables(int n_src, int s0, int n_dst, int n_phi, double r_min, double r_max,
+                    int n_tpz, int table_mode, const double *self, double *T)
+{
+    double beta, dphi;
+    if (or_geometry(n_dst, n_phi, r_min, r_max, NULL, NULL, &beta, &dphi)) return -1;
+    if (n_src < 2 || (table_mode == 0 && n_tpz < 1) || table_mode < 0 || table_mode > 1 ||
+        (n_phi % 2) != 0)
+        return -1;
+    gl_init();
+    const long rows = (long)n_src + n_dst - 1;
+    const long plane = rows * (long)n_phi;
+    static const double par[6] = {1, 1, -1, -1, -1, 1};
+#ifdef _OPENMP
+#pragma omp parallel for collapse(2) schedule(dynamic, 16)
+#endif
+    for (long row = 0; row < rows; ++row)
+        for (int nrep = 0; nrep <= n_phi / 2; ++nrep) {
+            const int m = (int)(row - (n_src - 1)) - s0;
+            double t[6];
+            table_entry(beta, dphi, n_tpz, table_mode, m, nrep, self, t);
+            long cpos = nrep, cneg = (n_phi - nrep) % n_phi;
+            for (int k = 0; k < 6; ++k) {
+                T[k * plane + row * n_phi + cpos] = t[k];
+                if (cneg != cpos) T[k * plane + row * n_phi + cneg] = par[k] * t[k];
+            }
+        }
+    return 0;
+}
+
+typedef struct { double xic, dphi, eta_c; } wedge_ctx;
+
+static void wedge_integrand(double eta, void *vctx, double *out)
+{
+    const wedge_ctx *c = (const wedge_ctx *)vctx;
+    const int n = 24;
+    double a[6] = {0, 0, 0, 0, 0, 0};
+    for (int k = 0; k < n; ++k) {
+        const double xi = c->xic + 0.5 * c->dphi * gl_x[n][k];
+        const double w = 0.5 * c->dphi * gl_w[n][k];
+        const double F = Fpol(eta, sin(0.5 * xi));
+        const double iF3 = 1.0 / (F * F * F);
+        const double fr = eta * (1.0 - eta * cos(xi)) * iF3;
+        const double fp = eta * eta * sin(xi) * iF3;
+        const double dx = xi - c->xic;
+        a[0] += w * fr;
+        a[1] += w * fr * (eta - c->eta_c);
+        a[2] += w * fr * dx;
+        a[3] += w * fp;
+        a[4] += w * fp * (eta - c->eta_c);
+        a[5] += w * fp * dx;
+    }
+    for (int k = 0; k < 6; ++k) out[k] = a[k];
+}
+
+/* Wedge tables [6][N_dst][N_phi] (order r0, rr, rphi, phi0, phir, phiphi);
+ * column n = (j - j') mod N_phi.  method 0: the integrals above; 1: point
+ * masses. */
+int or_wedge_tables(int n_dst, int n_phi, double r_min, double r_max, int s0, int method,
+                    double *T)
+{
+    double beta, dphi;
+    double *rc = (double *)malloc(sizeof(double) * n_dst);
+    if (!rc) return -2;
+    if (or_geometry(n_dst, n_phi, r_min, r_max, rc, NULL, &beta, &dphi) || s0 > 0 ||
+        method < 0 || method > 1) {
+        free(rc);
+        return -1;
+    }
+    gl_init();
+    const double r_w = r_min * pow(beta, s0);
+    const long plane = (long)n_dst * n_phi;
+#ifdef _OPENMP
+#pragma omp parallel for collapse(2) schedule(dynamic, 4)
+#endif
+    for (int i = 0; i < n_dst; ++i)
+        for (int n = 0; n < n_phi; ++n) {
+            const int nrep = n <= n_phi / 2 ? n : n - n_phi;
+            const double xic = -nrep * dphi;
+            const double eta_w = r_w / rc[i];
+            double t[6];
+            if (method == 0) {
+                wedge_ctx c = {xic, dphi, 0.5 * eta_w};
+                adapt_gl(wedge_integrand, &c, 6, 0.0, eta_w, 1e-14, t);
+                t[0] = -t[0];
+                t[1] = -t[1];
+                t[2] = -t[2];
+            } else {
+                const double ec = 0.5 * eta_w, A = 0.5 * eta_w * eta_w * dphi;
+                const double F = Fpol(ec, sin(0.5 * xic));
+                const double iF3 = 1.0 / (F * F * F);
+                t[0] = A * (ec * cos(xic) - 1.0) * iF3;
+                t[3] = A * ec * sin(xic) * iF3;
+                t[1] = t[2] = t[4] = t[5] = 0.0;
+            }
+            for (int k = 0; k < 6; ++k) T[k * plane + (long)i * n_phi + n] = t[k];
+        }
+    free(rc);
+    return 0;
+}
+
+/* Forces on the destination patch from the source patch (tables T of
+ * or_patch_tables) and, when Tw and sigma_w are given, from the origin
+ * wedges (tables Tw of or_wedge_tables, wedge densities sigma_w[N_phi]). */
+int or_patch_forward(int n_src, int s0, int n_dst, int n_phi, double r_min, double r_max,
+                     const double *T, const double *sigma_src, const double *Tw,
+                     const double *sigma_w, const int64_t *dest, int64_t n_dest, double *f_r,
+                     double *f_phi)
+{
+    double beta, dphi;
+    double *rd = (double *)malloc(sizeof(double) * n_dst);
+    double *rs = (double *)malloc(sizeof(double) * n_src);
+    const long Ns = (long)n_src * n_phi;
+    double *dr = (double *)malloc(sizeof(double) * Ns);
+    double *dp = (double *)malloc(sizeof(double) * Ns);
+    double *wr = (double *)malloc(sizeof(double) * n_phi);
+    double *wp = (double *)malloc(sizeof(double) * n_phi);
+    int rcode = 0;
+    if (!rd || !rs || !dr || !dp || !wr || !wp) { rcode = -2; goto done; }
+    if (or_geometry(n_dst, n_phi, r_min, r_max, rd, NULL, &beta, &dphi) || n_src < 2) {
+        rcode = -1;
+        goto done;
+    }
+    for (int k = 0; k < n_src; ++k) rs[k] = r_min * pow(beta, s0 + k) * 0.5 * (1.0 + beta);
+    or_channels(n_src, n_phi, rs, dphi, sigma_src, dr, dp);
+    if (Tw && sigma_w) {
+        const double r_w = r_min * pow(beta, s0), rh = 0.5 * r_w;
+        for (int j = 0; j < n_phi; ++j) {
+            wp[j] = (sigma_w[(j + 1) % n_phi] - sigma_w[(j + n_phi - 1) % n_phi]) / (2.0 * dphi);
+            wr[j] = (sigma_src[j] - sigma_w[j]) / (rs[0] - rh);
+        }
+    }
+    {
+        const long rows = (long)n_src + n_dst - 1;
+        const long plane = rows * (long)n_phi, wplane = (long)n_dst * n_phi;
+        const long nd = dest ? (long)n_dest : (long)n_dst * n_phi;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 4)
+#endif
+        for (long q = 0; q < nd; ++q) {
+            const long cell = dest ? (long)dest[q] : q;
+            const int i = (int)(cell / n_phi), j = (int)(cell % n_phi);
+            acc_t a0 = {0, 0}, ar = {0, 0}, ap = {0, 0}, b0 = {0, 0}, br = {0, 0}, bp = {0, 0};
+            for (int ip = 0; ip < n_src; ++ip) {
+                const long row = (long)(i - ip) + (n_src - 1);
+                const double *sg = sigma_src + (long)ip * n_phi, *gr = dr + (long)ip * n_phi,
+                             *gp = dp + (long)ip * n_phi;
+                double x0 = 0, xr = 0, xp = 0, y0 = 0, yr = 0, yp = 0;
+                for (int jp = 0; jp < n_phi; ++jp) {
+                    int n = j - jp;
+                    if (n < 0) n += n_phi;
+                    const long t = row * n_phi + n;
+                    x0 += sg[jp] * T[t];
+                    xr += gr[jp] * T[plane + t];
+                    xp += gp[jp] * T[2 * plane + t];
+                    y0 += sg[jp] * T[3 * plane + t];
+                    yr += gr[jp] * T[4 * plane + t];
+                    yp += gp[jp] * T[5 * plane + t];
+                }
+                acc_add(&a0, x0); acc_add(&ar, xr); acc_add(&ap, xp);
+                acc_add(&b0, y0); acc_add(&br, yr); acc_add(&bp, yp);
+            }
+            if (Tw && sigma_w) {
+                double x0 = 0, xr = 0, xp = 0, y0 = 0, yr = 0, yp = 0;
+                for (int jp = 0; jp < n_phi; ++jp) {
+                    int n = j - jp;
+                    if (n < 0) n += n_phi;
+                    const long t = (long)i * n_phi + n;
+                    x0 += sigma_w[jp] * Tw[t];
+                    xr += wr[jp] * Tw[wplane + t];
+                    xp += wp[jp] * Tw[2 * wplane + t];
+                    y0 += sigma_w[jp] * Tw[3 * wplane + t];
+                    yr += wr[jp] * Tw[4 * wplane + t];
+                    yp += wp[jp] * Tw[5 * wplane + t];
+                }
+                acc_add(&a0, x0); acc_add(&ar, xr); acc_add(&ap, xp);
+                acc_add(&b0, y0); acc_add(&br, yr); acc_add(&bp, yp);
+            }
+            f_r[q] = acc_get(&a0) + rd[i] * acc_get(&ar) + acc_get(&ap);
+            f_phi[q] = acc_get(&b0) + rd[i] * acc_get(&br) + acc_get(&bp);
+        }
+    }
+done:
+    free(rd); free(rs); free(dr); free(dp); free(wr); free(wp);
+    return rcode;
+}
+
+/* Particle and modified particle methods between patches, in physical
+ * coordinates: source cells are point masses sigma r dr dphi at their
+ * centres, wedges (if sigma_w) point masses sigma r_w^2 dphi / 2 at
+ * (r_w / 2, phi_j'); a destination cell that coincides with a source cell
+ * feels no force from it, and plus = 1 adds there the self-cell correction
+ * of Eq. 34-37 with the source patch's slopes. */
+int or_patch_particle(int n_src, int s0, int n_dst, int n_phi, double r_min, double r_max,
+                      int plus, const double *self, const double *sigma_src,
+                      const double *sigma_w, const int64_t *dest, int64_t n_dest, double *f_r,
+                      double *f_phi)
+{
+    double beta, dphi;
+    double *rd = (double *)malloc(sizeof(double) * n_dst);
+    double *rs = (double *)malloc(sizeof(double) * n_src);
+    const long Ns = (long)n_src * n_phi;
+    double *dr = (double *)malloc(sizeof(double) * Ns);
+    double *dp = (double *)malloc(sizeof(double) * Ns);
+    int rcode = 0;
+    if (!rd || !rs || !dr || !dp) { rcode = -2; goto done; }
+    if (or_geometry(n_dst, n_phi, r_min, r_max, rd, NULL, &beta, &dphi) || n_src < 2) {
+        rcode = -1;
+        goto done;
+    }
+    for (int k = 0; k < n_src; ++k) rs[k] = r_min * pow(beta, s0 + k) * 0.5 * (1.0 + beta);
+    or_channels(n_src, n_phi, rs, dphi, sigma_src, dr, dp);
+    {
+        const double r_w = r_min * pow(beta, s0);
+        const long nd = dest ? (long)n_dest : (long)n_dst * n_phi;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 4)
+#endif
+        for (long q = 0; q < nd; ++q) {
+            const long cell = dest ? (long)dest[q] : q;
+            const int i = (int)(cell / n_phi), j = (int)(cell % n_phi);
+            const double ri = rd[i];
+            acc_t ar = {0, 0}, ap = {0, 0};
+            for (int ip = 0; ip < n_src; ++ip) {
+                const int k = s0 + ip;
+                const double r2 = rs[ip];
+                const double area = 0.5 * (pow(beta, 2.0 * (k + 1)) - pow(beta, 2.0 * k)) *
+                                    r_min * r_min * dphi;
+                for (int jp = 0; jp < n_phi; ++jp) {
+                    if (k == i && jp == j) continue;
+                    const double M = sigma_src[(long)ip * n_phi + jp] * area;
+                    if (M == 0.0) continue;
+                    const double d = (jp - j) * dphi;
+                    const double sh = sin(0.5 * d);
+                    const double D = (ri - r2) * (ri - r2) + 4.0 * ri * r2 * sh * sh;
+                    const double w = M / (D * sqrt(D));
+                    acc_add(&ar, w * (r2 * cos(d) - ri));
+                    acc_add(&ap, w * r2 * sin(d));
+                }
+            }
+            if (sigma_w) {
+                const double r2 = 0.5 * r_w, area = 0.5 * r_w * r_w * dphi;
+                for (int jp = 0; jp < n_phi; ++jp) {
+                    const double M = sigma_w[jp] * area;
+                    if (M == 0.0) continue;
+                    const double d = (jp - j) * dphi;
+                    const double sh = sin(0.5 * d);
+                    const double D = (ri - r2) * (ri - r2) + 4.0 * ri * r2 * sh * sh;
+                    const double w = M / (D * sqrt(D));
+                    acc_add(&ar, w * (r2 * cos(d) - ri));
+                    acc_add(&ap, w * r2 * sin(d));
+                }
+            }
+            double fr = acc_get(&ar), fp = acc_get(&ap);
+            const int ip = i - s0;
+            if (plus && ip >= 0 && ip < n_src) {
+                const long c = (long)ip * n_phi + j;
+                fr += sigma_src[c] * self[0] + ri * dr[c] * self[1];
+                fp += dp[c] * self[2];
+            }
+            f_r[q] = fr;
+            f_phi[q] = fp;
+        }
+    }
+done:
+    free(rd); free(rs); free(dr); free(dp);
+    return rcode;
 }
 
 /* ------------------------------------------------------------------------ */

@@ -1,0 +1,113 @@
+"""Pins of the oracle's patch interaction and origin wedges (Sec. 3.2.1,
+Eq. 27-29): a source patch at any row offset acting on a destination patch
+equals the single-grid double sums on the union grid when the source's edge
+rows hold no mass (the only place where slopes taken inside the patch and on
+the union differ), for gaps, adjacency and overlap; the particle methods the
+same way; the wedge kernels against independent 2-D quadrature and, summed,
+the force of a uniform disk."""
+import numpy as np
+import pytest
+from scipy import integrate
+
+import oracle
+import workloads
+
+
+def _union(g, n_src, s0):
+    lo = min(s0, 0)
+    hi = max(s0 + n_src, g.n_r)
+    u = oracle.Grid(hi - lo, g.n_phi, g.r_min * g.beta ** lo, g.r_min * g.beta ** hi)
+    return u, lo
+
+
+def _source(n_src, n_phi, seed):
+    s = workloads.random_field((n_src, n_phi), seed) + 0.5
+    s[:2] = 0.0
+    s[-2:] = 0.0
+    return s
+
+
+@pytest.mark.parametrize("s0", [-9, -6, -3, 2])
+def test_patch_sums_equal_union_grid(s0):
+    g = oracle.Grid(7, 16, 0.3, 2.0)
+    n_src = 6
+    sig = _source(n_src, g.n_phi, 21 + s0)
+    u, lo = _union(g, n_src, s0)
+    sk = oracle.selfcell_cover(g.beta, g.dphi, 10)[:3]
+    su = np.zeros(u.shape)
+    su[s0 - lo:s0 - lo + n_src] = sig
+    Tu = oracle.tables(u, 19, self_k=sk)
+    fr_u, fp_u = oracle.forward(u, Tu, su)
+    T = oracle.patch_tables(g, n_src, s0, 19, self_k=sk)
+    fr, fp = oracle.patch_forward(g, n_src, s0, T, sig)
+    d = slice(-lo, -lo + g.n_r)
+    scale = np.abs(fr_u[d]).max()
+    np.testing.assert_allclose(fr, fr_u[d], rtol=0, atol=1e-12 * scale)
+    np.testing.assert_allclose(fp, fp_u[d], rtol=0, atol=1e-12 * scale)
+    # particle and modified particle methods
+    for plus in (False, True):
+        pr_u, pp_u = oracle.forward_particle(u, su, plus=plus, self_k=sk)
+        pr, pp = oracle.patch_particle(g, n_src, s0, sig, plus=plus, self_k=sk)
+        np.testing.assert_allclose(pr, pr_u[d], rtol=0, atol=1e-12 * scale)
+        np.testing.assert_allclose(pp, pp_u[d], rtol=0, atol=1e-12 * scale)
+
+
+def test_sampled_destinations():
+    g = oracle.Grid(6, 12, 0.5, 3.0)
+    sig = _source(5, 12, 4)
+    T = oracle.patch_tables(g, 5, -5, 3)
+    full = oracle.patch_forward(g, 5, -5, T, sig)
+    idx = np.array([0, 7, 30, 71])
+    part = oracle.patch_forward(g, 5, -5, T, sig, dest=idx)
+    np.testing.assert_array_equal(part[0], full[0].ravel()[idx])
+    np.testing.assert_array_equal(part[1], full[1].ravel()[idx])
+
+
+def _wedge_quad(g, s0, i, n, k):
+    """Wedge kernel k at destination row i, offset n, by 2-D quadrature of
+    its defining integrand in (eta, xi)."""
+    r_w = g.r_min * g.beta ** s0
+    ew = r_w / g.r_centres[i]
+    ec = 0.5 * ew
+    nrep = n if n <= g.n_phi // 2 else n - g.n_phi
+    xc = -nrep * g.dphi
+
+    def f(eta, xi):
+        F3 = (eta * eta - 2 * eta * np.cos(xi) + 1.0) ** 1.5
+        fr = eta * (1 - eta * np.cos(xi)) / F3
+        fp = eta * eta * np.sin(xi) / F3
+        return [-fr, -fr * (eta - ec), -fr * (xi - xc), fp, fp * (eta - ec), fp * (xi - xc)][k]
+
+    return integrate.dblquad(f, xc - g.dphi / 2, xc + g.dphi / 2, 0.0, ew,
+                             epsabs=1e-17, epsrel=1e-12)[0]
+
+
+def test_wedge_kernels_match_quadrature():
+    g = oracle.Grid(5, 8, 0.05, 1.0)
+    for s0 in (-3, -1):
+        Tw = oracle.wedge_tables(g, s0)
+        for i, n in [(0, 0), (0, 1), (2, 3), (4, 7)]:
+            for k in range(6):
+                ref = _wedge_quad(g, s0, i, n, k)
+                scale = abs(Tw[0, i, 0])
+                assert abs(Tw[k, i, n] - ref) < 1e-11 * scale, (s0, i, n, k, Tw[k, i, n], ref)
+
+
+def test_uniform_wedges_are_a_uniform_disk():
+    # unit density in every wedge: the force of a uniform disk of radius r_w
+    g = oracle.Grid(6, 16, 0.02, 1.0)
+    s0 = -4
+    r_w = g.r_min * g.beta ** s0
+    Tw = oracle.wedge_tables(g, s0)
+    for i in (0, 3, 5):
+        ri = g.r_centres[i]
+        ref = -integrate.dblquad(
+            lambda rb, th: rb * (ri - rb * np.cos(th)) / (rb * rb + ri * ri - 2 * rb * ri * np.cos(th)) ** 1.5,
+            0, 2 * np.pi, 0, r_w, epsabs=1e-18, epsrel=1e-12)[0]
+        assert abs(Tw[0, i].sum() - ref) < 1e-11 * abs(ref)
+        # azimuthal force of an axisymmetric ring of wedges vanishes
+        assert abs(Tw[3, i].sum()) < 1e-14 * abs(ref)
+    # point-mass wedges: the same mass at r_w / 2, within O((r_w / r)^2)
+    Tp = oracle.wedge_tables(g, s0, "particle")
+    for i in (0, 5):
+        assert abs(Tp[0, i].sum() / Tw[0, i].sum() - 1) < 2 * (r_w / g.r_centres[i]) ** 2
