@@ -130,6 +130,33 @@ void pf_build_opts_default(pf_build_opts *opts);
  * failures are reported the same way.                                      */
 pf_plan pf_plan_create(int n_r, int n_phi, double r_min, double r_max);
 
+/* A plan for the force of one patch of a log-polar grid on another
+ * (Sec. 3.2.1, Eq. 27-29: the interaction terms, and the origin terms).
+ * The destination patch is the grid of pf_plan_create(n_dst, n_phi, r_min,
+ * r_max); its beta and dphi define a common grid whose row k (any integer)
+ * spans [r_min beta^k, r_min beta^(k+1)].  The source patch holds the rows
+ * src_row0 ... src_row0 + n_src - 1 of that grid (below, above, or
+ * overlapping the destination; where a source cell coincides with a
+ * destination cell the singular self cell enters as in the single grid).
+ * Source slopes are taken inside the source patch (one-sided on its first
+ * and last rows).  wedges != 0 adds the origin wedges
+ * [0, r_min beta^src_row0] x [phi_j +- dphi/2] as a further source (needs
+ * src_row0 <= 0); the paper does not define their kernels: they are the
+ * integrands of Eq. 30-32 and A22-A24 over the wedge with its centre at half
+ * its radius (SIM and exact table modes), or a point mass sigma r_w^2
+ * dphi / 2 there (particle methods), with the wedge's azimuthal slope by
+ * periodic central differences and its radial slope by the one-sided
+ * difference towards the first source row.  The transforms are zero-padded
+ * to L >= 2 max(n_src, n_dst) along u; the kernels keep their parity in phi
+ * (no azimuthal offset between the patches).  Build with pf_kernels_build;
+ * pf_forces takes sigma [n_src][n_phi] and writes f_r, f_phi
+ * [n_dst][n_phi] (no wedges), pf_forces_patches also the wedge densities.
+ * The transpose, the batched path and the autotuner are for single-grid
+ * plans (PF_EUNSUPPORTED).  Sizes: 4 <= n_src <= 4096,
+ * |src_row0| <= 65536, n_dst and n_phi as for pf_plan_create.             */
+pf_plan pf_plan_create_patches(int n_src, int src_row0, int n_dst, int n_phi, double r_min,
+                               double r_max, int wedges);
+
 /* Build the kernel tables and their spectra on the current device
  * (Eq. 30-33, 41-46, A22-A35): one-time work, FP64 throughout, enqueued on
  * `stream` and synchronised before returning.  opts == NULL means defaults.
@@ -143,6 +170,14 @@ int pf_kernels_build(pf_plan plan, const pf_build_opts *opts, void *stream);
  * cells only: no mass inside r_min or outside r_max.  Asynchronous.        */
 int pf_forces(pf_plan plan, const void *sigma, void *f_r, void *f_phi,
               void *stream);
+
+/* Forward map of a patch plan: sigma_src [n_src][n_phi] (cell-centre
+ * densities of the source patch) and, for plans with origin wedges,
+ * sigma_wedge [n_phi] (the wedge densities at half the wedge radius; NULL
+ * otherwise) -> f_r, f_phi [n_dst][n_phi] on the destination patch.
+ * Asynchronous.                                                            */
+int pf_forces_patches(pf_plan plan, const void *sigma_src, const void *sigma_wedge, void *f_r,
+                      void *f_phi, void *stream);
 
 /* Transpose of the forward map: g_sigma = A^T [g_fr; g_fphi], i.e. the
  * gradient of any scalar loss L(F_r, F_phi) with respect to sigma, given
@@ -196,7 +231,9 @@ int pf_plan_schedule(pf_plan plan, int out[6]);
  * keep_tables).  Layout: [6][2 n_r - 1][n_phi], kernels in the order
  * K^{r,0}, K^{r,r}, K^{r,phi}, K^{phi,0}, K^{phi,r}, K^{phi,phi}; row
  * m + n_r - 1 holds radial offset m = i - i' (destination minus source),
- * column n = (j - j') mod n_phi.  Synchronous.                             */
+ * column n = (j - j') mod n_phi.  Patch plans: [6][n_src + n_dst - 1][n_phi],
+ * row m' + n_src - 1 for the row offset m' = i - i' (the kernel of the grid
+ * offset m' - src_row0).  Synchronous.                                      */
 int pf_plan_tables(pf_plan plan, double *dst);
 
 /* Release the plan and everything it owns.  NULL is ignored.              */

@@ -40,7 +40,8 @@ _CART_METHODS = {"second": PF_CART_SECOND, "particle": PF_CART_PARTICLE,
 EXPORTS = ("pf_build_opts_default", "pf_plan_create", "pf_kernels_build", "pf_forces",
            "pf_forces_backward", "pf_forces_batched", "pf_forces_timed", "pf_plan_geometry",
            "pf_plan_schedule", "pf_plan_selfcell", "pf_plan_tables", "pf_plan_destroy",
-           "pf_last_error", "pf_version", "pf_cart_create", "pf_cart_build", "pf_cart_forces",
+           "pf_last_error", "pf_version", "pf_plan_create_patches", "pf_forces_patches",
+           "pf_cart_create", "pf_cart_build", "pf_cart_forces",
            "pf_cart_forces_timed", "pf_cart_geometry", "pf_cart_destroy")
 
 
@@ -95,6 +96,10 @@ def load():
         getattr(lib, f).restype = I
     lib.pf_plan_destroy.argtypes = [P]
     lib.pf_plan_destroy.restype = None
+    lib.pf_plan_create_patches.argtypes = [I, I, I, I, D, D, I]
+    lib.pf_plan_create_patches.restype = P
+    lib.pf_forces_patches.argtypes = [P, P, P, P, P, P]
+    lib.pf_forces_patches.restype = I
     lib.pf_cart_create.argtypes = [I, I, D, D]
     lib.pf_cart_create.restype = P
     lib.pf_cart_build.argtypes = [P, I, I, P]
@@ -199,6 +204,21 @@ def pf_plan_tables(plan: int, n_r: int, n_phi: int):
 
 def pf_plan_destroy(plan: int) -> None:
     load().pf_plan_destroy(plan)
+
+
+def pf_plan_create_patches(n_src: int, src_row0: int, n_dst: int, n_phi: int, r_min: float,
+                           r_max: float, wedges: bool = False) -> int:
+    h = load().pf_plan_create_patches(int(n_src), int(src_row0), int(n_dst), int(n_phi),
+                                      float(r_min), float(r_max), int(bool(wedges)))
+    if not h:
+        raise PFError(PF_EINVAL, pf_last_error())
+    return h
+
+
+def pf_forces_patches(plan: int, sigma_src: int, sigma_wedge: int, f_r: int, f_phi: int,
+                      stream: int = 0) -> None:
+    _check(load().pf_forces_patches(plan, sigma_src, sigma_wedge or None, f_r, f_phi,
+                                    stream or None))
 
 
 def pf_cart_create(n_x: int, n_y: int, dx: float, dy: float) -> int:
@@ -449,3 +469,52 @@ class CartPlan:
             self.close()
         except Exception:
             pass
+
+
+class PatchPlan(Plan):
+    """The force of a source patch (rows src_row0 .. src_row0 + n_src - 1 of
+    the log-polar grid of the destination patch [r_min, r_max], n_dst rows)
+    on the destination patch, optionally with the origin wedges below the
+    source (Sec. 3.2.1, Eq. 27-29)."""
+
+    def __init__(self, n_src, src_row0, n_dst, n_phi, r_min, r_max, wedges=False, dtype="f32",
+                 n_tpz=19, cover_per=10, build=True, table_mode="sim", self_mode="cartesian",
+                 method="sim", keep_tables=False):
+        self.n_r, self.n_phi = int(n_dst), int(n_phi)
+        self.n_src, self.src_row0 = int(n_src), int(src_row0)
+        self.r_min, self.r_max = float(r_min), float(r_max)
+        self.wedges = bool(wedges)
+        self.handle = pf_plan_create_patches(n_src, src_row0, n_dst, n_phi, r_min, r_max, wedges)
+        self.dtype = None
+        if build:
+            self.build(dtype, n_tpz, cover_per, keep_tables, table_mode, self_mode, method)
+
+    @property
+    def src_shape(self):
+        return (self.n_src, self.n_phi)
+
+    def tables(self):
+        out = np.empty((6, self.n_src + self.n_r - 1, self.n_phi))
+        _check(load().pf_plan_tables(self.handle, out.ctypes.data))
+        return out
+
+    def forces(self, sigma_src, sigma_wedge=None, out=None):
+        import torch
+        if (not isinstance(sigma_src, torch.Tensor) or not sigma_src.is_cuda
+                or sigma_src.dtype != self.torch_dtype or tuple(sigma_src.shape) != self.src_shape
+                or not sigma_src.is_contiguous()):
+            raise TypeError("sigma_src must be a contiguous %s CUDA tensor of shape %s"
+                            % (self.torch_dtype, self.src_shape))
+        if sigma_wedge is not None and (tuple(sigma_wedge.shape) != (self.n_phi,)
+                                        or sigma_wedge.dtype != self.torch_dtype
+                                        or not sigma_wedge.is_cuda):
+            raise TypeError("sigma_wedge must be a %s CUDA tensor of shape (%d,)"
+                            % (self.torch_dtype, self.n_phi))
+        if out is None:
+            out = (torch.empty(self.shape, dtype=self.torch_dtype, device=sigma_src.device),
+                   torch.empty(self.shape, dtype=self.torch_dtype, device=sigma_src.device))
+        fr, fp = out
+        pf_forces_patches(self.handle, sigma_src.data_ptr(),
+                          sigma_wedge.data_ptr() if sigma_wedge is not None else 0,
+                          fr.data_ptr(), fp.data_ptr(), _stream())
+        return fr, fp

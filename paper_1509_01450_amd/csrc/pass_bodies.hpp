@@ -312,14 +312,15 @@ __host__ __device__ constexpr int mac_batch() { return sizeof(T) == 8 ? 2 : (E <
 // Pass B, forward.  Workgroup: G columns x (L/E) threads, lane -> (t, column)
 // with the G columns interleaved (consecutive lanes read consecutive
 // columns of a row).  LDS buf: G*padded_len(L) complex.
-// S: [n_r][H] complex; Z: [n_r][H] pairs (Zr, Zp); spec: [2][H][ldspec] pairs.
+// S: [n_r][H] complex (the source rows); Z: [n_out][H] pairs (Zr, Zp), the
+// destination rows; spec: [2][H][ldspec] pairs.
 // ---------------------------------------------------------------------------
 template <typename T, int L, int E>
 __device__ __forceinline__ void body_cols_fwd(int unit, int G, cx<T> *__restrict__ buf,
                                               const cx<T> *__restrict__ S,
                                               cx2<T> *__restrict__ Z,
                                               const cx2<T> *__restrict__ spec, int H, int n_r,
-                                              int ldspec, T ca, T c0, T cn,
+                                              int n_out, int ldspec, T ca, T c0, T cn,
                                               const cx<T> *__restrict__ twL) {
     constexpr int TH = L / E;
     const int gi = threadIdx.x % G, t = threadIdx.x / G;
@@ -408,12 +409,12 @@ __device__ __forceinline__ void body_cols_fwd(int unit, int G, cx<T> *__restrict
     fft_inv<L, E, T>(y[0], t, lds, tw);
     fft_inv<L, E, T>(y[1], t, lds, tw);
     if (valid) {
-        // only the first E/2 points of a thread can be rows (L >= 2 n_r): the
+        // only the first E/2 points of a thread can be rows (L >= 2 n_out): the
         // rest of the last stage is never formed
 #pragma unroll
         for (int e = 0; e < E / 2; ++e) {
             const int i = t + e * TH;
-            if (i < n_r) Z[(size_t)i * H + col] = cx2<T>{y[0][e], y[1][e]};
+            if (i < n_out) Z[(size_t)i * H + col] = cx2<T>{y[0][e], y[1][e]};
         }
     }
 }

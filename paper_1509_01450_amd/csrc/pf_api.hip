@@ -1,6 +1,7 @@
 // pf_api.hip -- host side of the C ABI declared in include/pf.h: argument
 // validation, plan geometry (Sec. 3.2.1), build orchestration and the launch
 // sequences of the forward map and its transpose.
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -98,7 +99,9 @@ static void free_plan_device(Plan *p) {
     if (p->twL) (void)hipFree(p->twL);
     if (p->ws) (void)hipFree(p->ws);
     if (p->tables) (void)hipFree(p->tables);
-    p->spec = p->twN = p->twL = p->ws = nullptr;
+    if (p->wspec) (void)hipFree(p->wspec);
+    if (p->wws) (void)hipFree(p->wws);
+    p->spec = p->twN = p->twL = p->ws = p->wspec = p->wws = nullptr;
     p->tables = nullptr;
     p->built = false;
 }
@@ -141,16 +144,22 @@ int check_call(pf_plan h, const void *a, const void *b, const void *c) {
     return PF_OK;
 }
 
+// Forward map: pass A on the n_in source rows, pass B, the origin wedges'
+// terms (plans with wedges), pass C on the n_r destination rows.
 template <typename T>
-int forces_t(const Plan &p, const T *sigma, T *fr, T *fp, hipStream_t st) {
+int forces_t(const Plan &p, const T *sigma, const T *sigma_w, T *fr, T *fp, hipStream_t st) {
     using C = pf::cx<T>;
     C *S = (C *)p.ws;
-    C *Z = S + (size_t)p.n_r * p.H;   // (Zr, Zp) pairs
-    int rc = pf::launch_rows_r2c<T>(p, sigma, nullptr, p.n_r, S, (const C *)p.twN, p.sched.rows,
+    C *Z = S + (size_t)p.n_in * p.H;   // (Zr, Zp) pairs
+    int rc = pf::launch_rows_r2c<T>(p, sigma, nullptr, p.n_in, S, (const C *)p.twN, p.sched.rows,
                                     st);
     if (rc) return rc;
     rc = pf::launch_cols_fwd<T>(p, S, Z, (const C *)p.spec, (const C *)p.twL, p.sched.cols, st);
     if (rc) return rc;
+    if (p.wedges) {
+        rc = pf::launch_wedge_terms<T>(p, sigma, sigma_w, Z, st);
+        if (rc) return rc;
+    }
     return pf::launch_rows_c2r<T>(p, Z, p.n_r, fr, fp, (const C *)p.twN, p.sched.rows, st);
 }
 
@@ -172,13 +181,13 @@ int timed_t(const Plan &p, bool bwd, const void *in0, const void *in1, void *out
             int reps, hipStream_t st, hipEvent_t *ev) {
     using C = pf::cx<T>;
     C *W0 = (C *)p.ws;
-    C *W1 = W0 + (size_t)p.n_r * p.H;       // forward: S = W0, Z = W1
+    C *W1 = W0 + (size_t)p.n_in * p.H;      // forward: S = W0, Z = W1
     C *W2 = W0 + 2 * (size_t)p.n_r * p.H;   // transpose: V = W0, D = W2
     int rc = PF_OK;
     PF_HIP(hipEventRecord(ev[0], st));
     for (int k = 0; k < reps && !rc; ++k)
-        rc = pf::launch_rows_r2c<T>(p, (const T *)in0, bwd ? (const T *)in1 : nullptr, p.n_r, W0,
-                                    (const C *)p.twN, p.sched.rows, st);
+        rc = pf::launch_rows_r2c<T>(p, (const T *)in0, bwd ? (const T *)in1 : nullptr, p.n_in,
+                                    W0, (const C *)p.twN, p.sched.rows, st);
     if (rc) return rc;
     PF_HIP(hipEventRecord(ev[1], st));
     for (int k = 0; k < reps && !rc; ++k) {
@@ -244,6 +253,8 @@ pf_plan pf_plan_create(int n_r, int n_phi, double r_min, double r_max) {
     }
     Plan &p = h->p;
     p.n_r = n_r;
+    p.n_in = n_r;
+    p.s0 = 0;
     p.n_phi = n_phi;
     p.M = n_phi / 2;
     p.H = n_phi / 2;   // packed half spectrum: bins 0 and n_phi/2 share column 0
@@ -262,6 +273,36 @@ pf_plan pf_plan_create(int n_r, int n_phi, double r_min, double r_max) {
     p.cn = 1.0 / (1.0 - 1.0 / p.beta);
     pf_build_opts_default(&p.opts);
     p.uid = pf::next_uid();
+    return h;
+}
+
+pf_plan pf_plan_create_patches(int n_src, int src_row0, int n_dst, int n_phi, double r_min,
+                               double r_max, int wedges) {
+    pf::clear_error();
+    if (n_src < 4 || n_src > 4096) {
+        pf::set_error("n_src = %d outside [4, 4096]", n_src);
+        return nullptr;
+    }
+    if (src_row0 < -65536 || src_row0 > 65536) {
+        pf::set_error("src_row0 = %d outside [-65536, 65536]", src_row0);
+        return nullptr;
+    }
+    if (wedges && src_row0 > 0) {
+        pf::set_error("origin wedges need the source patch to start at or below r_min "
+                      "(src_row0 <= 0, got %d)", src_row0);
+        return nullptr;
+    }
+    pf_plan h = pf_plan_create(n_dst, n_phi, r_min, r_max);
+    if (!h) return nullptr;
+    Plan &p = h->p;
+    p.n_in = n_src;
+    p.s0 = src_row0;
+    p.patch = true;
+    p.wedges = wedges != 0;
+    int L = 8;
+    while (L < 2 * n_src || L < 2 * n_dst) L *= 2;
+    p.L = L;
+    p.ldspec = L / 2 + 1;
     return h;
 }
 
@@ -336,10 +377,10 @@ int pf_plan_tables(pf_plan h, double *dst) {
         pf::set_error("plan not built with keep_tables");
         return PF_ESTATE;
     }
-    const int rows = 2 * p.n_r - 1;
+    const int rows = p.n_in + p.n_r - 1;
     for (int k = 0; k < 6; ++k)
         for (int ir = 0; ir < rows; ++ir) {
-            const int m = ir - (p.n_r - 1);
+            const int m = ir - (p.n_in - 1);
             const int row = (m % p.L + p.L) % p.L;
             PF_HIP(hipMemcpy(dst + ((size_t)k * rows + ir) * p.n_phi,
                              p.tables + ((size_t)k * p.L + row) * p.n_phi,
@@ -405,17 +446,21 @@ int pf_kernels_build(pf_plan h, const pf_build_opts *opts, void *stream) {
     rc = pf::upload_twiddles(p.n_phi, f64, &p.twN);
     if (!rc) rc = pf::upload_twiddles(p.L, f64, &p.twL);
     if (!rc) {
-        hipError_t e = hipMalloc(&p.ws, (size_t)3 * p.n_r * p.H * (f64 ? 16 : 8));
+        // forward: S (n_in rows) and the (Zr, Zp) pairs (n_r rows); transpose:
+        // the (Vr, Vp) pairs and D (n_r rows each)
+        const size_t rows = std::max((size_t)p.n_in + 2 * (size_t)p.n_r, (size_t)3 * p.n_r);
+        hipError_t e = hipMalloc(&p.ws, rows * p.H * (f64 ? 16 : 8));
         if (e != hipSuccess) {
             pf::set_error("workspace allocation failed: %s", hipGetErrorString(e));
             rc = PF_ENOMEM;
         }
     }
+    if (!rc && p.wedges) rc = pf::build_wedge_spectra(p, st);
     if (rc) {
         pf::free_plan_device(&p);
         return rc;
     }
-    pf::autotune_plan(p, st);
+    if (!p.patch) pf::autotune_plan(p, st);
     p.built = true;
     return PF_OK;
 }
@@ -425,10 +470,34 @@ int pf_forces(pf_plan h, const void *sigma, void *f_r, void *f_phi, void *stream
     int rc = check_call(h, sigma, f_r, f_phi);
     if (rc) return rc;
     const Plan &p = h->p;
+    if (p.wedges) {
+        pf::set_error("the plan has origin wedges: call pf_forces_patches");
+        return PF_EINVAL;
+    }
     hipStream_t st = (hipStream_t)stream;
     if (p.opts.dtype == PF_F64)
-        return forces_t<double>(p, (const double *)sigma, (double *)f_r, (double *)f_phi, st);
-    return forces_t<float>(p, (const float *)sigma, (float *)f_r, (float *)f_phi, st);
+        return forces_t<double>(p, (const double *)sigma, nullptr, (double *)f_r,
+                                (double *)f_phi, st);
+    return forces_t<float>(p, (const float *)sigma, nullptr, (float *)f_r, (float *)f_phi, st);
+}
+
+int pf_forces_patches(pf_plan h, const void *sigma_src, const void *sigma_wedge, void *f_r,
+                      void *f_phi, void *stream) {
+    pf::clear_error();
+    int rc = check_call(h, sigma_src, f_r, f_phi);
+    if (rc) return rc;
+    const Plan &p = h->p;
+    if (p.wedges != (sigma_wedge != nullptr)) {
+        pf::set_error(p.wedges ? "the plan has origin wedges: sigma_wedge is required"
+                               : "the plan has no origin wedges: sigma_wedge must be NULL");
+        return PF_EINVAL;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    if (p.opts.dtype == PF_F64)
+        return forces_t<double>(p, (const double *)sigma_src, (const double *)sigma_wedge,
+                                (double *)f_r, (double *)f_phi, st);
+    return forces_t<float>(p, (const float *)sigma_src, (const float *)sigma_wedge, (float *)f_r,
+                           (float *)f_phi, st);
 }
 
 int pf_forces_backward(pf_plan h, const void *g_fr, const void *g_fphi, void *g_sigma,
@@ -437,6 +506,10 @@ int pf_forces_backward(pf_plan h, const void *g_fr, const void *g_fphi, void *g_
     int rc = check_call(h, g_fr, g_fphi, g_sigma);
     if (rc) return rc;
     const Plan &p = h->p;
+    if (p.patch) {
+        pf::set_error("the transpose is built for single-grid plans only");
+        return PF_EUNSUPPORTED;
+    }
     hipStream_t st = (hipStream_t)stream;
     if (p.opts.dtype == PF_F64)
         return backward_t<double>(p, (const double *)g_fr, (const double *)g_fphi,
@@ -458,6 +531,10 @@ int pf_forces_timed(pf_plan h, int backward, const void *in0, const void *in1, v
         return PF_EINVAL;
     }
     const Plan &p = h->p;
+    if (p.patch && (backward || p.wedges)) {
+        pf::set_error("timing of patch plans: forward without wedges only");
+        return PF_EUNSUPPORTED;
+    }
     hipStream_t st = (hipStream_t)stream;
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     for (int k = 0; k < 4; ++k) {
@@ -498,6 +575,10 @@ int pf_forces_batched(int n, const pf_plan *plans, const void *const *sigma, voi
         int rc = check_call(plans[k], sigma[k], f_r[k], f_phi[k]);
         if (rc) return rc;
         ps[k] = &plans[k]->p;
+        if (ps[k]->patch) {
+            pf::set_error("batched plans must be single-grid plans (plan %d is a patch plan)", k);
+            return PF_EUNSUPPORTED;
+        }
         if (ps[k]->opts.dtype != ps[0]->opts.dtype) {
             pf::set_error("batched plans must share one precision");
             return PF_EINVAL;

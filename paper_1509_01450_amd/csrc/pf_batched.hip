@@ -88,8 +88,8 @@ __device__ __forceinline__ void group_cols(int unit, const GDisk<T> &d, cx<T> *b
     constexpr int E = col_e<T>();
     if constexpr (L / E <= kGroupThreads) {
         constexpr int G = kGroupThreads / (L / E);
-        body_cols_fwd<T, L, E>(unit, G, buf, d.S, d.Z, d.spec, d.H, d.n_r, d.ldspec, d.ca, d.c0,
-                               d.cn, d.twL);
+        body_cols_fwd<T, L, E>(unit, G, buf, d.S, d.Z, d.spec, d.H, d.n_r, d.n_r, d.ldspec, d.ca,
+                               d.c0, d.cn, d.twL);
     }
 }
 

@@ -44,6 +44,11 @@ struct Plan {
     // 0 holds the real bins 0 and M); L = transform length along u; ldspec =
     // L / 2 + 1 stored k_u per spectrum column
     int n_r = 0, n_phi = 0, M = 0, H = 0, L = 0, ldspec = 0;
+    // source rows s0 .. s0 + n_in - 1 of the grid (n_in = n_r, s0 = 0 for
+    // one grid); n_r is the number of destination rows
+    int n_in = 0, s0 = 0;
+    bool patch = false;    // made by pf_plan_create_patches
+    bool wedges = false;   // origin wedges [0, r_min beta^s0] below the source
     double r_min = 0, r_max = 0, beta = 0, dphi = 0;
     // radial slope coefficients of g = r delta^r (interior, first, last row)
     double ca = 0, c0 = 0, cn = 0;
@@ -60,6 +65,8 @@ struct Plan {
                               // (forward: S, then (Zr, Zp) pairs; transpose:
                               // (Vr, Vp) pairs, then D)
     double *tables = nullptr; // [6][L][n_phi] FP64 (only with keep_tables)
+    void *wspec = nullptr;    // wedge spectra [2][n_r][H] pairs, plan precision
+    void *wws = nullptr;      // wedge workspace: slope row, then its spectra
     Schedule sched;
     int64_t uid = 0;          // identity for batch-graph caching
 
@@ -78,7 +85,8 @@ template <typename T>
 int launch_rows_c2r(const Plan &p, const cx<T> *in, int n_rows, T *out0, T *out1,
                     const cx<T> *twN, Shape s, hipStream_t st);
 // Column pass of the forward map (u-FFT, spectral multiply-accumulate with
-// the spectral radial slope, inverse u-FFTs, crop): S -> pairs Z.
+// the spectral radial slope, inverse u-FFTs, crop): S ([n_in][H]) -> pairs
+// Z ([n_r][H]).
 template <typename T>
 int launch_cols_fwd(const Plan &p, const cx<T> *S, cx<T> *Z, const cx<T> *spec,
                     const cx<T> *twL, Shape s, hipStream_t st);
@@ -89,6 +97,13 @@ int launch_cols_adj(const Plan &p, const cx<T> *V, cx<T> *D, const cx<T> *spec,
 
 // ---- kernels (pf_tables.hip) ------------------------------------------------
 int build_tables_and_spectra(Plan &p, hipStream_t st);
+// Origin-wedge spectra (plans with wedges) and the per-call wedge terms:
+// Z += the wedges' contribution, from the wedge densities sigma_w[n_phi] and
+// the first source row.
+int build_wedge_spectra(Plan &p, hipStream_t st);
+template <typename T>
+int launch_wedge_terms(const Plan &p, const T *sigma_src, const T *sigma_w, cx<T> *Z,
+                       hipStream_t st);
 
 // ---- host helpers -------------------------------------------------------------
 // exp(-2 pi i j / n) for j in [0, n), computed in long double

@@ -36,14 +36,14 @@ template <typename T, int L, int E>
 __global__ __launch_bounds__(512) void k_cols_fwd(const cx<T> *__restrict__ S,
                                                   cx2<T> *__restrict__ Z,
                                                   const cx2<T> *__restrict__ spec, int H, int n_r,
-                                                  int ldspec, T ca, T c0, T cn,
+                                                  int n_out, int ldspec, T ca, T c0, T cn,
                                                   const cx<T> *__restrict__ twL, int per_xcd,
                                                   int n_groups) {
     extern __shared__ unsigned char smem_raw[];
     const int grp = xcd_group(blockIdx.x, per_xcd);
     if (grp >= n_groups) return;  // whole workgroup leaves together
     body_cols_fwd<T, L, E>(grp, blockDim.x / (L / E), reinterpret_cast<cx<T> *>(smem_raw), S, Z,
-                           spec, H, n_r, ldspec, ca, c0, cn, twL);
+                           spec, H, n_r, n_out, ldspec, ca, c0, cn, twL);
 }
 
 template <typename T, int L, int E>
@@ -166,8 +166,8 @@ struct Disp {
                 int rc = allow_lds(k_cols_fwd<T, N, E>, lds);
                 if (rc) return rc;
                 hipLaunchKernelGGL((k_cols_fwd<T, N, E>), dim3(blocks), dim3(G * TH), lds, st, a,
-                                   reinterpret_cast<cx2<T> *>(o), sp, p.H, p.n_r, p.ldspec, ca,
-                                   c0, cn, tw, per_xcd, n_groups);
+                                   reinterpret_cast<cx2<T> *>(o), sp, p.H, p.n_in, p.n_r,
+                                   p.ldspec, ca, c0, cn, tw, per_xcd, n_groups);
             }
             PF_HIP(hipGetLastError());
             return PF_OK;

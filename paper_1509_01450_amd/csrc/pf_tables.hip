@@ -127,6 +127,7 @@ struct TabGeo {
     int n_r, n_phi, L, n_tpz;
     int exact;    // 1: azimuthal integrals converged instead of n_tpz trapezoids
     int method;   // PF_METHOD_*
+    int n_in, s0; // source rows s0 .. s0 + n_in - 1 (n_r destination rows)
 };
 
 // Particle methods (Eq. 35-37, 56-62).  A source cell is the point mass
@@ -246,21 +247,25 @@ __device__ void table_entry(const TabGeo &g, int m, int nrep, const double *self
     t[4] = a1;
 }
 
-// tables: [6][L][n_phi] FP64, row (m mod L).  One thread per (m, n_rep),
-// n_rep in [0, n_phi/2]; entries at -n_rep follow from the parity in xi.
+// tables: [6][L][n_phi] FP64, row (m' mod L) for the row offset
+// m' = i - i' in [-(n_in - 1), n_r - 1] between destination row i and source
+// row i' (the kernel of the grid offset m = m' - s0).  One thread per
+// (m', n_rep), n_rep in [0, n_phi/2]; entries at -n_rep follow from the
+// parity in xi.
 __global__ void k_tables(TabGeo g, const double *__restrict__ selfk, double *__restrict__ tab) {
     const int nh = g.n_phi / 2 + 1;
-    const int rows = 2 * g.n_r - 1;
+    const int rows = g.n_in + g.n_r - 1;
     const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= (long)rows * nh) return;
     const int ir = (int)(idx / nh), nrep = (int)(idx % nh);
-    const int m = ir - (g.n_r - 1);
+    const int mp = ir - (g.n_in - 1);
+    const int m = mp - g.s0;
     double t[6];
     if (g.method == PF_METHOD_SIM)
         table_entry(g, m, nrep, selfk, t);
     else
         particle_entry(g, m, nrep, selfk, t);
-    const int row = (m % g.L + g.L) % g.L;
+    const int row = (mp % g.L + g.L) % g.L;
     const long plane = (long)g.L * g.n_phi;
     const int cp = nrep, cn = (g.n_phi - nrep) % g.n_phi;
     const double par[6] = {1, 1, -1, -1, -1, 1};
@@ -568,9 +573,10 @@ __global__ __launch_bounds__(256) void k_selfpv(FanGeo f, double *__restrict__ o
 // ---------------------------------------------------------------------------
 template <int L, int E>
 __global__ __launch_bounds__(512) void k_fold(const cx<double> *__restrict__ rowspec, int M,
-                                              int n_r, int n_phi, double lnb, double dphi,
-                                              double ca, cx2<double> *__restrict__ spec,
-                                              int ldspec, const cx<double> *__restrict__ twL) {
+                                              int n_r, int s0, int n_phi, double lnb,
+                                              double dphi, double ca,
+                                              cx2<double> *__restrict__ spec, int ldspec,
+                                              const cx<double> *__restrict__ twL) {
     constexpr int TH = L / E;
     extern __shared__ unsigned char smem_raw[];
     cx<double> *buf = reinterpret_cast<cx<double> *>(smem_raw);
@@ -590,9 +596,9 @@ __global__ __launch_bounds__(512) void k_fold(const cx<double> *__restrict__ row
             cx<double> x = rowspec[((size_t)tab * L + row) * M + src];
             if (part == 1) x = cx<double>{x.x, 0.0};
             if (part == 2) x = cx<double>{x.y, 0.0};
-            if (bscale) {
-                const int m = row < n_r ? row : row - L;
-                x = scale(x, exp(m * lnb));
+            if (bscale) {   // r_i / r_i' = beta^m, m = m' - s0 the grid offset
+                const int mp = row < n_r ? row : row - L;
+                x = scale(x, exp((mp - s0) * lnb));
             }
             v[e] = x;
         }
@@ -647,8 +653,8 @@ int fold_launch(const cx<double> *rowspec, const Plan &p, cx2<double> *spec,
             PF_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(k_fold<L, E>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
         hipLaunchKernelGGL((k_fold<L, E>), dim3(p.M + 1), dim3(L / E), lds, st, rowspec, p.M,
-                           p.n_r, p.n_phi, std::log(p.beta), p.dphi, p.ca, spec, p.ldspec,
-                           twL);
+                           p.n_r, p.s0, p.n_phi, std::log(p.beta), p.dphi, p.ca, spec,
+                           p.ldspec, twL);
         PF_HIP(hipGetLastError());
         return PF_OK;
     }
@@ -751,9 +757,9 @@ int build_tables_and_spectra(Plan &p, hipStream_t st) {
     hipLaunchKernelGGL(k_fill, dim3(1024), dim3(256), 0, st, (double *)tab.p, 6 * plane, 0.0);
     PF_HIP(hipGetLastError());
     TabGeo tg{p.beta, p.dphi, std::log(p.beta), p.n_r, p.n_phi, p.L, p.opts.n_tpz,
-              p.opts.table_mode == PF_TABLE_EXACT ? 1 : 0, p.opts.method};
+              p.opts.table_mode == PF_TABLE_EXACT ? 1 : 0, p.opts.method, p.n_in, p.s0};
     {
-        const long n = (long)(2 * p.n_r - 1) * (p.n_phi / 2 + 1);
+        const long n = (long)(p.n_in + p.n_r - 1) * (p.n_phi / 2 + 1);
         hipLaunchKernelGGL(k_tables, dim3((unsigned)((n + 127) / 128)), dim3(128), 0, st, tg,
                            (const double *)selfk.p, (double *)tab.p);
         PF_HIP(hipGetLastError());
@@ -814,5 +820,216 @@ int build_tables_and_spectra(Plan &p, hipStream_t st) {
     }
     return PF_OK;
 }
+
+// ---------------------------------------------------------------------------
+// Origin wedges: the cells [0, r_w] x [phi_j' +- dphi/2], r_w = r_min beta^s0,
+// below the source rows (Sec. 3.2.1; the paper uses barred kernels for them
+// without defining them).  Reading: the integrands of Eq. 30-32 and A22-A24
+// over the wedge, with the wedge's radial centre at r_w / 2 (the arithmetic
+// centre, as for every other cell); in units of r_i (eta = rbar / r_i,
+// eta_w = r_w / r_i, eta_c = eta_w / 2, xi_c = -n dphi)
+//   T_r0 = -int eta (1 - eta cos xi) / F^3,      T_phi0 = int eta^2 sin xi / F^3,
+//   T_rr = -int eta (1 - eta cos xi) (eta - eta_c) / F^3, T_phir likewise,
+//   T_rphi = -int eta (1 - eta cos xi) (xi - xi_c) / F^3, T_phiphi likewise,
+// over eta in [0, eta_w], xi in [xi_c +- dphi/2]; the particle methods take
+// the wedge as the point mass sigma r_w^2 dphi / 2 at (r_w / 2, phi_j').
+// Radial integrals by 16-point Gauss-Legendre graded towards the complex
+// zeros of F for each azimuth, the azimuthal integral graded towards
+// xi = +-i 2 asinh((1 - eta_w) / (2 sqrt(eta_w))), where F vanishes at the
+// wedge's outer edge.  The wedges act on row i through a periodic
+// convolution in phi only; F^r += sigma T_r0 + r_i delta^r T_rr +
+// delta^phi T_rphi (and likewise F^phi), with the wedge's azimuthal slope by
+// periodic central differences and its radial slope by the one-sided
+// difference towards the first source row.
+// ---------------------------------------------------------------------------
+struct WedgeGeo {
+    double beta, dphi, r_min;
+    int n_r, n_phi, s0, method;
+};
+
+// tab: [6][n_r][n_phi], column n = (j - j') mod n_phi
+__global__ void k_wedge_tables(WedgeGeo g, double *__restrict__ tab) {
+    const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (long)g.n_r * g.n_phi) return;
+    const int i = (int)(idx / g.n_phi), n = (int)(idx % g.n_phi);
+    const int nrep = n <= g.n_phi / 2 ? n : n - g.n_phi;
+    const double xic = -nrep * g.dphi;
+    const double ri = g.r_min * pow(g.beta, (double)i) * 0.5 * (1.0 + g.beta);
+    const double ew = g.r_min * pow(g.beta, (double)g.s0) / ri;
+    const double ec = 0.5 * ew;
+    double t[6] = {0, 0, 0, 0, 0, 0};
+    if (g.method == PF_METHOD_SIM) {
+        double a[6] = {0, 0, 0, 0, 0, 0};
+        auto point = [&](double xi, double wk) {
+            double sx, cxi;
+            sincos(xi, &sx, &cxi);
+            const double sh = sin(0.5 * xi);
+            double ir = 0, ir2 = 0, ip = 0, ip2 = 0;
+            auto f = [&](double eta, double w) {
+                const double F = Fpol(eta, sh);
+                const double iF3 = 1.0 / (F * F * F);
+                const double fr = eta * (1.0 - eta * cxi) * iF3;
+                const double fp = eta * eta * sx * iF3;
+                ir += w * fr;
+                ir2 += w * fr * (eta - ec);
+                ip += w * fp;
+                ip2 += w * fp * (eta - ec);
+            };
+            graded_gl16(0.0, ew, cxi, fabs(sx), f);
+            const double wl = wk * (xi - xic);
+            a[0] += wk * ir;
+            a[1] += wk * ir2;
+            a[2] += wl * ir;
+            a[3] += wk * ip;
+            a[4] += wk * ip2;
+            a[5] += wl * ip;
+        };
+        const double dxi = 2.0 * asinh((1.0 - ew) / (2.0 * sqrt(ew)));
+        graded_gl16(xic - 0.5 * g.dphi, xic + 0.5 * g.dphi, 0.0, dxi, point);
+        t[0] = -a[0];
+        t[1] = -a[1];
+        t[2] = -a[2];
+        t[3] = a[3];
+        t[4] = a[4];
+        t[5] = a[5];
+    } else {
+        const double A = 0.5 * ew * ew * g.dphi;
+        const double F = Fpol(ec, sin(0.5 * xic));
+        const double iF3 = 1.0 / (F * F * F);
+        double sx, cxi;
+        sincos(xic, &sx, &cxi);
+        t[0] = A * (ec * cxi - 1.0) * iF3;
+        t[3] = A * ec * sx * iF3;
+    }
+    const size_t plane = (size_t)g.n_r * g.n_phi;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) tab[k * plane + (size_t)i * g.n_phi + n] = t[k];
+}
+
+// Wedge spectra per destination row: wspec[c][i][k], pairs (E, Q) with
+//   E = s (T_0 + i sk T_phi),  Q = s r_i T_r,   s = 1 / n_phi,
+// sk = sin(2 pi k / n_phi) / dphi; c = 0 the radial force, c = 1 the
+// azimuthal one; column 0 holds the radial pair of bin 0 (c = 0) and of
+// bin n_phi/2 (c = 1), the azimuthal spectra vanishing at both.
+__global__ void k_wedge_fold(const cx<double> *__restrict__ rowspec, WedgeGeo g, int H,
+                             cx2<double> *__restrict__ wspec) {
+    const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (long)g.n_r * (H + 1)) return;
+    const int i = (int)(idx / (H + 1)), kb = (int)(idx % (H + 1));
+    const int src = kb == H ? 0 : kb;
+    const int part = kb == 0 ? 1 : (kb == H ? 2 : 0);
+    auto get = [&](int tab) {
+        cx<double> x = rowspec[((size_t)tab * g.n_r + i) * H + src];
+        if (part == 1) x = cx<double>{x.x, 0.0};
+        if (part == 2) x = cx<double>{x.y, 0.0};
+        return x;
+    };
+    const double sw = 1.0 / g.n_phi;
+    const double sk = sinpi(2.0 * kb / g.n_phi) / g.dphi;
+    const double ri = g.r_min * pow(g.beta, (double)i) * 0.5 * (1.0 + g.beta);
+    auto pair = [&](int t0, int tr, int tp) {
+        const cx<double> a = get(t0), b = get(tp), q = get(tr);
+        return cx2<double>{{(a.x - sk * b.y) * sw, (a.y + sk * b.x) * sw}, scale(q, sw * ri)};
+    };
+    if (part == 0) {
+        wspec[(size_t)i * H + kb] = pair(0, 1, 2);
+        wspec[((size_t)g.n_r + i) * H + kb] = pair(3, 4, 5);
+    } else {
+        wspec[((size_t)(part == 1 ? 0 : g.n_r) + i) * H] = pair(0, 1, 2);
+    }
+}
+
+// delta^r of the wedges: towards the centre of the first source row
+template <typename T>
+__global__ void k_wedge_slope(const T *__restrict__ sigma_src, const T *__restrict__ sigma_w,
+                              int n_phi, T inv_dr, T *__restrict__ out) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < n_phi) out[j] = (sigma_src[j] - sigma_w[j]) * inv_dr;
+}
+
+// Z[i][k] += wedge terms, from the row spectra w[k] = (sigma_w^, delta^r^)
+template <typename T>
+__global__ void k_wedge_add(cx2<T> *__restrict__ Z, const cx2<T> *__restrict__ wspec,
+                            const cx2<T> *__restrict__ w, int n_r, int H) {
+    const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (long)n_r * H) return;
+    const int k = (int)(idx % H);
+    const cx2<T> a = wspec[idx], b = wspec[(size_t)n_r * H + idx], x = w[k];
+    cx2<T> z = Z[idx];
+    if (k == 0) {   // bins 0 and n_phi/2: real parts, radial force only
+        z.a.x += a.a.x * x.a.x + a.b.x * x.b.x;
+        z.a.y += b.a.x * x.a.y + b.b.x * x.b.y;
+    } else {
+        z.a = z.a + cmul(a.a, x.a) + cmul(a.b, x.b);
+        z.b = z.b + cmul(b.a, x.a) + cmul(b.b, x.b);
+    }
+    Z[idx] = z;
+}
+
+int build_wedge_spectra(Plan &p, hipStream_t st) {
+    const bool f64 = p.opts.dtype == PF_F64;
+    DevBuf tab, rowspec, w64, twN64;
+    const size_t plane = (size_t)p.n_r * p.n_phi;
+    WedgeGeo g{p.beta, p.dphi, p.r_min, p.n_r, p.n_phi, p.s0,
+               p.opts.method == PF_METHOD_SIM ? PF_METHOD_SIM : PF_METHOD_PARTICLE};
+    PF_HIP(hipMalloc(&tab.p, 6 * plane * sizeof(double)));
+    hipLaunchKernelGGL(k_wedge_tables, dim3((unsigned)((plane + 127) / 128)), dim3(128), 0, st, g,
+                       (double *)tab.p);
+    PF_HIP(hipGetLastError());
+    int rc = upload_twiddles(p.n_phi, true, &twN64.p);
+    if (rc) return rc;
+    PF_HIP(hipMalloc(&rowspec.p, 6 * (size_t)p.n_r * p.H * sizeof(cx<double>)));
+    rc = launch_rows_r2c<double>(p, (const double *)tab.p, nullptr, 6 * p.n_r,
+                                 (cx<double> *)rowspec.p, (const cx<double> *)twN64.p,
+                                 default_schedule(p.n_phi, p.L, true).rows, st);
+    if (rc) return rc;
+    const size_t nw = (size_t)2 * p.n_r * p.H;   // pairs
+    PF_HIP(hipMalloc(&w64.p, nw * sizeof(cx2<double>)));
+    {
+        const long n = (long)p.n_r * (p.H + 1);
+        hipLaunchKernelGGL(k_wedge_fold, dim3((unsigned)((n + 127) / 128)), dim3(128), 0, st,
+                           (const cx<double> *)rowspec.p, g, p.H, (cx2<double> *)w64.p);
+        PF_HIP(hipGetLastError());
+    }
+    if (f64) {
+        p.wspec = w64.p;
+        w64.p = nullptr;
+    } else {
+        PF_HIP(hipMalloc(&p.wspec, nw * sizeof(cx2<float>)));
+        hipLaunchKernelGGL(k_to_f32, dim3(1024), dim3(256), 0, st, (const cx<double> *)w64.p,
+                           (cx<float> *)p.wspec, (long)(2 * nw));
+        PF_HIP(hipGetLastError());
+    }
+    // workspace: the slope row (n_phi values), then the row's spectra (H pairs)
+    PF_HIP(hipMalloc(&p.wws, (size_t)p.n_phi * (f64 ? 8 : 4) + (size_t)p.H * (f64 ? 32 : 16)));
+    PF_HIP(hipStreamSynchronize(st));
+    return PF_OK;
+}
+
+template <typename T>
+int launch_wedge_terms(const Plan &p, const T *sigma_src, const T *sigma_w, cx<T> *Z,
+                       hipStream_t st) {
+    T *slope = (T *)p.wws;
+    cx<T> *wrow = (cx<T> *)((char *)p.wws + (size_t)p.n_phi * sizeof(T));
+    const double rc0 = p.r_min * std::pow(p.beta, p.s0) * 0.5 * (1.0 + p.beta);
+    const double rh = 0.5 * p.r_min * std::pow(p.beta, p.s0);
+    hipLaunchKernelGGL(k_wedge_slope<T>, dim3((p.n_phi + 255) / 256), dim3(256), 0, st,
+                       sigma_src, sigma_w, p.n_phi, T(1.0 / (rc0 - rh)), slope);
+    PF_HIP(hipGetLastError());
+    int rc = launch_rows_r2c<T>(p, sigma_w, slope, 1, wrow, (const cx<T> *)p.twN, p.sched.rows,
+                                st);
+    if (rc) return rc;
+    const long n = (long)p.n_r * p.H;
+    hipLaunchKernelGGL(k_wedge_add<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st,
+                       reinterpret_cast<cx2<T> *>(Z), (const cx2<T> *)p.wspec,
+                       reinterpret_cast<const cx2<T> *>(wrow), p.n_r, p.H);
+    PF_HIP(hipGetLastError());
+    return PF_OK;
+}
+
+template int launch_wedge_terms<float>(const Plan &, const float *, const float *, cx<float> *,
+                                       hipStream_t);
+template int launch_wedge_terms<double>(const Plan &, const double *, const double *,
+                                        cx<double> *, hipStream_t);
 
 }  // namespace pf

@@ -129,3 +129,21 @@ def test_cartesian_plan_host_checks():
     finally:
         pf.pf_cart_destroy(h)
     pf.pf_cart_destroy(None)
+
+
+def test_patch_plan_host_checks():
+    lib = pf.load()
+    for args in [(3, -3, 16, 32, 0.1, 1.0, 0), (8, 2, 16, 32, 0.1, 1.0, 1),
+                 (8, -70000, 16, 32, 0.1, 1.0, 0), (8, -8, 16, 33, 0.1, 1.0, 0)]:
+        with pytest.raises(pf.PFError):
+            pf.pf_plan_create_patches(*args)
+        assert pf.pf_last_error()
+    h = pf.pf_plan_create_patches(10, -10, 16, 32, 0.1, 1.0, 1)
+    try:
+        rc, re_, dphi = pf.pf_plan_geometry(h, 16)
+        assert abs(re_[0] - 0.1) < 1e-15 and abs(re_[-1] - 1.0) < 1e-12
+        assert lib.pf_forces(h, 8, 8, 8, None) == pf.PF_ESTATE
+        assert lib.pf_forces_patches(h, 8, 8, 8, 8, None) == pf.PF_ESTATE
+        assert lib.pf_forces_patches(h, None, 8, 8, 8, None) == pf.PF_EINVAL
+    finally:
+        pf.pf_plan_destroy(h)

@@ -1,0 +1,142 @@
+"""GPU parity of patch plans (Sec. 3.2.1, Eq. 27-29: a source patch of a
+log-polar grid acting on a destination patch, with the origin wedges) with
+the oracle's direct sums, element by element, and the paper's polar case 1
+(Fig. 4): a sigma_D2 disk (alpha = 0.006) at the origin, inside the source
+annulus [M_in, 0.01] and the wedges [0, M_in], acting on the mass-free
+destination [0.01, 1].
+
+Parity bars: relative L2 <= 1e-11 (FP64) and 1e-5 (FP32) on both force
+components, for source patches below (adjacent and with a gap), above and
+overlapping the destination, ragged sizes, all methods, with and without
+wedges."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from oracle import analytic
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+import paper_1509_01450_amd as pf  # noqa: E402
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    pf.load()
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def _gpu_patch(n_src, s0, g, sig, sig_w, dtype, method, n_tpz=19):
+    plan = pf.PatchPlan(n_src, s0, g.n_r, g.n_phi, g.r_min, g.r_max, wedges=sig_w is not None,
+                        dtype=dtype, method=method, n_tpz=n_tpz)
+    try:
+        s = torch.tensor(sig, dtype=plan.torch_dtype, device="cuda")
+        w = torch.tensor(sig_w, dtype=plan.torch_dtype, device="cuda") if sig_w is not None else None
+        fr, fp = plan.forces(s, w)
+        torch.cuda.synchronize()
+        return fr.double().cpu().numpy(), fp.double().cpu().numpy()
+    finally:
+        plan.close()
+
+
+def _oracle_patch(n_src, s0, g, sig, sig_w, method, n_tpz=19):
+    if method == "sim":
+        T = oracle.patch_tables(g, n_src, s0, n_tpz)
+        Tw = oracle.wedge_tables(g, s0) if sig_w is not None else None
+        return oracle.patch_forward(g, n_src, s0, T, sig, Tw, sig_w)
+    return oracle.patch_particle(g, n_src, s0, sig, sig_w, plus=(method == "particle+"))
+
+
+CASES = [
+    # (n_src, s0, n_dst, n_phi, wedges)
+    (10, -10, 24, 32, True),     # adjacent below, with wedges
+    (12, -17, 20, 64, False),    # below with a gap
+    (12, -3, 20, 32, False),     # overlapping: singular self cells
+    (9, 26, 24, 16, False),      # above the destination
+    (33, -33, 40, 128, True),    # several tiles, ragged
+]
+
+
+@pytest.mark.parametrize("method", ["sim", "particle", "particle+"])
+@pytest.mark.parametrize("case", CASES)
+def test_patch_parity(case, method):
+    n_src, s0, n_dst, n_phi, wedges = case
+    g = oracle.Grid(n_dst, n_phi, 0.05, 2.0)
+    sig = workloads.random_field((n_src, n_phi), 31 + n_src) + 0.3
+    sig_w = (workloads.random_field((n_phi,), 5 + n_phi) + 0.5) if wedges else None
+    _say("patch parity %s %s" % (case, method))
+    o_r, o_p = _oracle_patch(n_src, s0, g, sig, sig_w, method)
+    for dt, tol in (("f64", 1e-11), ("f32", 1e-5)):
+        fr, fp = _gpu_patch(n_src, s0, g, sig, sig_w, dt, method)
+        a, b = _rel(fr, o_r), _rel(fp, o_p)
+        _say("  %s rel-L2 F_r %.2e F_phi %.2e" % (dt, a, b))
+        assert a < tol and b < tol, (case, method, dt, a, b)
+
+
+def test_patch_with_one_trapezoid_and_wedges():
+    g = oracle.Grid(16, 16, 1e-2, 1.0)
+    sig = workloads.random_field((18, 16), 3) + 0.5
+    sig_w = workloads.random_field((16,), 4) + 0.5
+    o_r, o_p = _oracle_patch(18, -18, g, sig, sig_w, "sim", n_tpz=1)
+    fr, fp = _gpu_patch(18, -18, g, sig, sig_w, "f64", "sim", n_tpz=1)
+    assert _rel(fr, o_r) < 1e-11 and _rel(fp, o_p) < 1e-11
+
+
+def _fig4(label):
+    path = os.path.join(os.path.dirname(__file__), "golden", "fig4_case1_orders.txt")
+    for line in open(path):
+        if line.strip() and not line.startswith("#"):
+            k, norm, o = line.split()
+            if (k + " " + norm) == label:
+                return float(o)
+    raise KeyError(label)
+
+
+def _case1(N, method, dtype="f64"):
+    """Polar case 1: destination [0.01, 1], N x N; source annulus with M_in
+    about 1e-4 (8 / N), the nearest whole number of rows below 0.01; the
+    sigma_D2 disk (alpha = 0.006) sampled at the source centres and at the
+    wedge centres."""
+    g = oracle.Grid(N, N, 1e-2, 1.0)
+    n_s = int(round(np.log(1e-2 / (1e-4 * 8.0 / N)) / np.log(g.beta)))
+    rc_s, rh = oracle.patch_centres(g, n_s, -n_s)
+    sig = np.repeat(analytic.sigma_dn(rc_s, 2, 0.006)[:, None], N, axis=1)
+    sig_w = np.full(N, float(analytic.sigma_dn(np.array([rh]), 2, 0.006)[0]))
+    kw = {"particle": dict(method="particle"), "yen12": dict(method="sim", n_tpz=1)}[method]
+    plan = pf.PatchPlan(n_s, -n_s, N, N, 1e-2, 1.0, wedges=True, dtype=dtype, **kw)
+    try:
+        fr, _ = plan.forces(torch.tensor(sig, dtype=plan.torch_dtype, device="cuda"),
+                            torch.tensor(sig_w, dtype=plan.torch_dtype, device="cuda"))
+        torch.cuda.synchronize()
+        fr = fr.double().cpu().numpy()
+    finally:
+        plan.close()
+    ana = np.repeat(analytic.force_dn(g.r_centres, 2, 0.006)[:, None], N, axis=1)
+    return np.array(oracle.error_norms(fr, ana))
+
+
+def test_fig4_case1_orders():
+    Ns = [32, 64, 128, 256, 512]
+    x = np.log(np.array(Ns[1:], dtype=float))
+    for method, name in (("particle", "particle"), ("yen12", "yen12")):
+        e = np.array([_case1(N, method) for N in Ns])
+        fit = [-np.polyfit(x, np.log(e[1:, q]), 1)[0] for q in (0, 2)]
+        _say("case 1 %s L1 %s Linf %s  orders (last four) L1 %.2f Linf %.2f (Fig. 4: %.1f, %.1f)"
+             % (name, np.array2string(e[:, 0], precision=3), np.array2string(e[:, 2], precision=3),
+                fit[0], fit[1], _fig4(name + " L1"), _fig4(name + " Linf")))
+        assert abs(fit[0] - _fig4(name + " L1")) < 0.3 and abs(fit[1] - _fig4(name + " Linf")) < 0.3
