@@ -6,8 +6,10 @@ Headline: cells/s of the forward map (F_r + F_phi) on the single-disk
 m = 2 logarithmic spiral), FP32 FFT/multiply with FP64-built kernel spectra.
 One step = one pf_forces call on that grid with the density already resident
 in HBM.  Also reported: the FP64 path, the transpose (backward) in both
-precisions, the 64-disk batched launch, the Cartesian second-order method on
-a 1024 x 1024 grid, the one-time table builds, the roofline of the dominant
+precisions, the 64-disk batched launch, the paper's polar case 1 as a patch
+plan (source annulus and origin wedges on a 1024 x 1024 destination), the
+Cartesian second-order method on a 1024 x 1024 grid, the one-time table
+builds, the roofline of the dominant
 kernel (the fused column pass) and the FP64 CPU oracle timed on the host's
 cores.
 
@@ -327,7 +329,35 @@ def main():
     cart["workload"] = ("Cartesian 1024 x 1024 cells on [-0.5, 0.5]^2, sigma_D2 disk "
                         "(alpha = 0.25), second-order method")
 
+    # ---- patches: the paper's polar case 1 at N_d = 1024 ---------------------
+    log("patches: polar case 1, 1024 x 1024 destination")
+    ND = 1024
+    beta_d = 100.0 ** (1.0 / ND)
+    n_s = int(round(np.log(1e-2 / (1e-4 * 8.0 / ND)) / np.log(beta_d)))
+    k = -n_s + np.arange(n_s)
+    rc_s = 1e-2 * beta_d ** k * 0.5 * (1.0 + beta_d)
+    rh = 0.5 * 1e-2 * beta_d ** (-n_s)
+    sd2 = lambda r: np.clip(1.0 - (r / 0.006) ** 2, 0.0, None) ** 1.5
+    patches = {"workload": "polar case 1: sigma_D2 (alpha = 0.006) in a %d-row source "
+                           "annulus and the origin wedges, acting on the mass-free "
+                           "1024 x 1024 destination [0.01, 1]" % n_s}
+    for dt in ("f32", "f64"):
+        t0 = time.perf_counter()
+        pp = pf.PatchPlan(n_s, -n_s, ND, ND, 1e-2, 1.0, wedges=True, dtype=dt, method="sim")
+        torch.cuda.synchronize()
+        bp = time.perf_counter() - t0
+        ss = torch.tensor(np.repeat(sd2(rc_s)[:, None], ND, axis=1), dtype=pp.torch_dtype,
+                          device=dev)
+        sw = torch.full((ND,), float(sd2(np.array([rh]))[0]), dtype=pp.torch_dtype, device=dev)
+        op = (torch.empty((ND, ND), dtype=pp.torch_dtype, device=dev),
+              torch.empty((ND, ND), dtype=pp.torch_dtype, device=dev))
+        msp = time_calls(torch, lambda: pp.forces(ss, sw, op), max(K // 2, 10), W)
+        patches[dt] = {"ms_per_call": msp, "destination_cells_per_s": ND * ND / (msp * 1e-3),
+                       "table_build_s": bp}
+        pp.close()
+
     out["detail"].update({
+        "patches": patches,
         "cartesian": cart,
         "schedule_fp64": sched(p64),
         "fp64": {"ms_per_call": ms64, "cells_per_s": cells / (ms64 * 1e-3),
