@@ -222,10 +222,12 @@ int pf_plan_selfcell(pf_plan plan, double out[3]);
 
 /* Launch shapes chosen for the plan by the last build (autotuned unless
  * PF_AUTOTUNE=0): out[0], out[1] = points per thread and rows per workgroup
- * of the row transforms; out[2], out[3] = points per thread and columns per
- * workgroup of the forward column pass; out[4], out[5] the same for the
+ * of the one-channel row transforms (forward pass A, transpose pass C);
+ * out[2], out[3] the same for the two-channel row transforms (forward pass
+ * C, transpose pass A); out[4], out[5] = points per thread and columns per
+ * workgroup of the forward column pass; out[6], out[7] the same for the
  * transpose column pass.  Not in the paper: a diagnostic.                  */
-int pf_plan_schedule(pf_plan plan, int out[6]);
+int pf_plan_schedule(pf_plan plan, int out[8]);
 
 /* Copy the six FP64 kernel tables to host memory `dst` (plan built with
  * keep_tables).  Layout: [6][2 n_r - 1][n_phi], kernels in the order

@@ -189,9 +189,9 @@ def pf_plan_selfcell(plan: int):
 
 
 def pf_plan_schedule(plan: int):
-    """(row E, row G, column E, column G, transpose column E, transpose
-    column G) launch shapes of a built plan."""
-    out = np.zeros(6, dtype=np.int32)
+    """(one-channel row E, G, two-channel row E, G, column E, G, transpose
+    column E, G) launch shapes of a built plan."""
+    out = np.zeros(8, dtype=np.int32)
     _check(load().pf_plan_schedule(plan, out.ctypes.data))
     return tuple(int(v) for v in out)
 

@@ -73,6 +73,7 @@ Schedule default_schedule(int n_phi, int L, bool f64) {
         s.rows.G = th >= 256 ? 1 : 256 / th;
         while (s.rows.G > 1 && !valid_shape_rows(M, s.rows, f64)) s.rows.G /= 2;
     }
+    s.rows2 = s.rows;
     // column pass: 16 points per thread in FP32 from L = 2048 on (fewer LDS
     // exchanges, two columns per workgroup), 8 otherwise; the transpose pass
     // holds two input channels and takes 8
@@ -160,7 +161,7 @@ int forces_t(const Plan &p, const T *sigma, const T *sigma_w, T *fr, T *fp, hipS
         rc = pf::launch_wedge_terms<T>(p, sigma, sigma_w, Z, st);
         if (rc) return rc;
     }
-    return pf::launch_rows_c2r<T>(p, Z, p.n_r, fr, fp, (const C *)p.twN, p.sched.rows, st);
+    return pf::launch_rows_c2r<T>(p, Z, p.n_r, fr, fp, (const C *)p.twN, p.sched.rows2, st);
 }
 
 template <typename T>
@@ -168,7 +169,7 @@ int backward_t(const Plan &p, const T *gr, const T *gp, T *gs, hipStream_t st) {
     using C = pf::cx<T>;
     C *V = (C *)p.ws;                        // (Vr, Vp) pairs
     C *D = V + 2 * (size_t)p.n_r * p.H;
-    int rc = pf::launch_rows_r2c<T>(p, gr, gp, p.n_r, V, (const C *)p.twN, p.sched.rows, st);
+    int rc = pf::launch_rows_r2c<T>(p, gr, gp, p.n_r, V, (const C *)p.twN, p.sched.rows2, st);
     if (rc) return rc;
     rc = pf::launch_cols_adj<T>(p, V, D, (const C *)p.spec, (const C *)p.twL, p.sched.cols_adj,
                                 st);
@@ -187,7 +188,7 @@ int timed_t(const Plan &p, bool bwd, const void *in0, const void *in1, void *out
     PF_HIP(hipEventRecord(ev[0], st));
     for (int k = 0; k < reps && !rc; ++k)
         rc = pf::launch_rows_r2c<T>(p, (const T *)in0, bwd ? (const T *)in1 : nullptr, p.n_in,
-                                    W0, (const C *)p.twN, p.sched.rows, st);
+                                    W0, (const C *)p.twN, bwd ? p.sched.rows2 : p.sched.rows, st);
     if (rc) return rc;
     PF_HIP(hipEventRecord(ev[1], st));
     for (int k = 0; k < reps && !rc; ++k) {
@@ -203,7 +204,7 @@ int timed_t(const Plan &p, bool bwd, const void *in0, const void *in1, void *out
     for (int k = 0; k < reps && !rc; ++k) {
         if (!bwd)
             rc = pf::launch_rows_c2r<T>(p, W1, p.n_r, (T *)out0, (T *)out1, (const C *)p.twN,
-                                        p.sched.rows, st);
+                                        p.sched.rows2, st);
         else
             rc = pf::launch_rows_c2r<T>(p, W2, p.n_r, (T *)out0, nullptr, (const C *)p.twN,
                                         p.sched.rows, st);
@@ -346,7 +347,7 @@ int pf_plan_selfcell(pf_plan h, double out[3]) {
     return PF_OK;
 }
 
-int pf_plan_schedule(pf_plan h, int out[6]) {
+int pf_plan_schedule(pf_plan h, int out[8]) {
     pf::clear_error();
     if (!h || !out) {
         pf::set_error("null argument");
@@ -359,10 +360,12 @@ int pf_plan_schedule(pf_plan h, int out[6]) {
     const pf::Schedule &s = h->p.sched;
     out[0] = s.rows.E;
     out[1] = s.rows.G;
-    out[2] = s.cols.E;
-    out[3] = s.cols.G;
-    out[4] = s.cols_adj.E;
-    out[5] = s.cols_adj.G;
+    out[2] = s.rows2.E;
+    out[3] = s.rows2.G;
+    out[4] = s.cols.E;
+    out[5] = s.cols.G;
+    out[6] = s.cols_adj.E;
+    out[7] = s.cols_adj.G;
     return PF_OK;
 }
 

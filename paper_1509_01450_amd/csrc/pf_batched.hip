@@ -379,8 +379,10 @@ void tune_t(Plan &p, hipStream_t st) {
     using C = cx<T>;
     const bool f64 = sizeof(T) == 8;
     const std::string pre = arch_name() + (f64 ? "|f64|" : "|f32|");
-    const std::string krow = pre + "rows|M=" + std::to_string(p.M) + "|rows=" +
-                             std::to_string(2 * p.n_r);
+    const std::string krow = pre + "rows1|M=" + std::to_string(p.M) + "|rows=" +
+                             std::to_string(p.n_r);
+    const std::string krow2 = pre + "rows2|M=" + std::to_string(p.M) + "|rows=" +
+                              std::to_string(p.n_r);
     const std::string kcol = pre + "cols|L=" + std::to_string(p.L) + "|H=" + std::to_string(p.H) +
                              "|n_r=" + std::to_string(p.n_r);
     const std::string kadj = pre + "adj|L=" + std::to_string(p.L) + "|H=" + std::to_string(p.H) +
@@ -388,11 +390,13 @@ void tune_t(Plan &p, hipStream_t st) {
     {
         std::lock_guard<std::mutex> g(g_tune_mu);
         load_cache();
-        auto a = g_tune.find(krow), b = g_tune.find(kcol), c = g_tune.find(kadj);
-        if (a != g_tune.end() && b != g_tune.end() && c != g_tune.end() &&
-            valid_shape_rows(p.M, a->second, f64) && valid_shape_cols(p.L, b->second, f64) &&
-            valid_shape_cols(p.L, c->second, f64)) {
+        auto a = g_tune.find(krow), a2 = g_tune.find(krow2), b = g_tune.find(kcol),
+             c = g_tune.find(kadj);
+        if (a != g_tune.end() && a2 != g_tune.end() && b != g_tune.end() && c != g_tune.end() &&
+            valid_shape_rows(p.M, a->second, f64) && valid_shape_rows(p.M, a2->second, f64) &&
+            valid_shape_cols(p.L, b->second, f64) && valid_shape_cols(p.L, c->second, f64)) {
             p.sched.rows = a->second;
+            p.sched.rows2 = a2->second;
             p.sched.cols = b->second;
             p.sched.cols_adj = c->second;
             return;
@@ -408,9 +412,12 @@ void tune_t(Plan &p, hipStream_t st) {
     hipEvent_t e0, e1;
     (void)hipEventCreate(&e0);
     (void)hipEventCreate(&e1);
-    // rows: forward R2C of n_r rows + two-channel inverse C2R of n_r rows
-    Shape best_r = p.sched.rows, best_c = p.sched.cols, best_a = p.sched.cols_adj;
-    float tbest = 1e30f;
+    // rows: the one-channel forward R2C and the two-channel inverse C2R of
+    // n_r rows, each on its own (they stand for the one- and two-channel row
+    // transforms of both directions)
+    Shape best_r = p.sched.rows, best_r2 = p.sched.rows2, best_c = p.sched.cols,
+          best_a = p.sched.cols_adj;
+    float tbest = 1e30f, tbest2 = 1e30f;
     for (int E : {4, 8, 16})
         for (int thr : {64, 128, 256, 512}) {
             if (E > p.M || (p.M / E) > thr) continue;
@@ -418,18 +425,23 @@ void tune_t(Plan &p, hipStream_t st) {
             if (!valid_shape_rows(p.M, s, f64)) continue;
             float t = time_ms(
                 [&]() {
-                    int rc = launch_rows_r2c<T>(p, x, nullptr, p.n_r, S, (const C *)p.twN, s,
-                                                st);
-                    if (!rc)
-                        rc = launch_rows_c2r<T>(p, Z, p.n_r, x + (size_t)p.n_r * p.n_phi,
-                                                x + 2 * (size_t)p.n_r * p.n_phi,
-                                                (const C *)p.twN, s, st);
-                    return rc;
+                    return launch_rows_r2c<T>(p, x, nullptr, p.n_r, S, (const C *)p.twN, s, st);
                 },
                 st, e0, e1);
             if (t > 0 && t < tbest) {
                 tbest = t;
                 best_r = s;
+            }
+            t = time_ms(
+                [&]() {
+                    return launch_rows_c2r<T>(p, Z, p.n_r, x + (size_t)p.n_r * p.n_phi,
+                                              x + 2 * (size_t)p.n_r * p.n_phi, (const C *)p.twN,
+                                              s, st);
+                },
+                st, e0, e1);
+            if (t > 0 && t < tbest2) {
+                tbest2 = t;
+                best_r2 = s;
             }
         }
     tbest = 1e30f;
@@ -472,10 +484,12 @@ void tune_t(Plan &p, hipStream_t st) {
     (void)hipFree(x);
     clear_error();
     p.sched.rows = best_r;
+    p.sched.rows2 = best_r2;
     p.sched.cols = best_c;
     p.sched.cols_adj = best_a;
     std::lock_guard<std::mutex> g(g_tune_mu);
     g_tune[krow] = best_r;
+    g_tune[krow2] = best_r2;
     g_tune[kcol] = best_c;
     g_tune[kadj] = best_a;
     save_cache();

@@ -34,7 +34,10 @@ struct Shape {
 
 // Schedule of a plan: launch shapes of the three passes for its sizes.
 struct Schedule {
-    Shape rows;       // row transforms along phi (length n_phi, half-length M)
+    Shape rows;       // one-channel row transforms along phi (forward pass A,
+                      // transpose pass C; half-length M)
+    Shape rows2;      // two-channel row transforms (forward pass C, transpose
+                      // pass A)
     Shape cols;       // forward column pass along u (length L)
     Shape cols_adj;   // transpose column pass along u
 };

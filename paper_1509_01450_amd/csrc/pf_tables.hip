@@ -1016,7 +1016,7 @@ int launch_wedge_terms(const Plan &p, const T *sigma_src, const T *sigma_w, cx<T
     hipLaunchKernelGGL(k_wedge_slope<T>, dim3((p.n_phi + 255) / 256), dim3(256), 0, st,
                        sigma_src, sigma_w, p.n_phi, T(1.0 / (rc0 - rh)), slope);
     PF_HIP(hipGetLastError());
-    int rc = launch_rows_r2c<T>(p, sigma_w, slope, 1, wrow, (const cx<T> *)p.twN, p.sched.rows,
+    int rc = launch_rows_r2c<T>(p, sigma_w, slope, 1, wrow, (const cx<T> *)p.twN, p.sched.rows2,
                                 st);
     if (rc) return rc;
     const long n = (long)p.n_r * p.H;

@@ -64,8 +64,8 @@ def test_unbuilt_plan_and_null_arguments_are_refused():
         assert lib.pf_forces(h, 8, 8, 8, None) == pf.PF_ESTATE
         assert lib.pf_forces_backward(h, 8, 8, 8, None) == pf.PF_ESTATE
         assert lib.pf_plan_selfcell(h, None) == pf.PF_EINVAL
-        out6 = (ctypes.c_int * 6)()
-        assert lib.pf_plan_schedule(h, out6) == pf.PF_ESTATE
+        out8 = (ctypes.c_int * 8)()
+        assert lib.pf_plan_schedule(h, out8) == pf.PF_ESTATE
         assert lib.pf_plan_schedule(h, None) == pf.PF_EINVAL
         ms3 = (ctypes.c_float * 3)()
         assert lib.pf_forces_timed(h, 0, 8, None, 8, 8, 1, None, ms3) == pf.PF_ESTATE
