@@ -303,10 +303,13 @@ __device__ __forceinline__ cx<T> unpack_odd(cx<T> p, cx<T> m) {
 
 // Points per batch of spectrum loads in the multiply-accumulate of pass B,
 // sized so that a batch's loads (four complex values per point) fit in the
-// registers beside the transform data: 64 / E in FP32 (E <= 8: all E),
-// 2 in FP64.
-template <typename T, int E>
-__host__ __device__ constexpr int mac_batch() { return sizeof(T) == 8 ? 2 : (E < 8 ? E : 64 / E); }
+// registers beside the transform data: 64 / E in FP32 (E <= 8: all E) for
+// the forward pass, half that for the transpose pass (which holds two input
+// channels and spills otherwise at E = 16), 2 in FP64.
+template <typename T, int E, bool ADJ = false>
+__host__ __device__ constexpr int mac_batch() {
+    return sizeof(T) == 8 ? 2 : (E < 8 ? E : (ADJ ? 32 : 64) / E);
+}
 
 // ---------------------------------------------------------------------------
 // Pass B, forward.  Workgroup: G columns x (L/E) threads, lane -> (t, column)
@@ -517,7 +520,7 @@ __device__ __forceinline__ void body_cols_adj(int unit, int G, cx<T> *__restrict
     // summed per thread against the roots (W^(j k) = W^(j t) r(j e)) and
     // turned into the thread's share with its phasors afterwards.
     cx<T> w[4] = {{T(0), T(0)}, {T(0), T(0)}, {T(0), T(0)}, {T(0), T(0)}};
-    constexpr int CH = mac_batch<T, E>();
+    constexpr int CH = mac_batch<T, E, true>();
     const bool t0 = t == 0;
 #pragma unroll
     for (int cb = 0; cb < E; cb += CH) {
