@@ -308,7 +308,7 @@ __device__ __forceinline__ cx<T> unpack_odd(cx<T> p, cx<T> m) {
 // channels and spills otherwise at E = 16), 2 in FP64.
 template <typename T, int E, bool ADJ = false>
 __host__ __device__ constexpr int mac_batch() {
-    return sizeof(T) == 8 ? 2 : (E < 8 ? E : (ADJ ? 32 : 64) / E);
+    return sizeof(T) == 8 ? 1 : (E < 8 ? E : (ADJ ? 32 : 64) / E);
 }
 
 // ---------------------------------------------------------------------------
