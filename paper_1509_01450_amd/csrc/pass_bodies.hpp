@@ -318,7 +318,12 @@ __host__ __device__ constexpr int mac_batch() {
 // S: [n_r][H] complex (the source rows); Z: [n_out][H] pairs (Zr, Zp), the
 // destination rows; spec: [2][H][ldspec] pairs.
 // ---------------------------------------------------------------------------
-template <typename T, int L, int E>
+// Entries of the radial spectrum pair per column in the LDS prefetch region
+// (L/2 + 1 rounded up to whole 64-lane chunks).
+template <int L>
+__host__ __device__ constexpr int spec_prefetch_len() { return ((L / 2 + 1) + 63) / 64 * 64; }
+
+template <typename T, int L, int E, bool PF = false>
 __device__ __forceinline__ void body_cols_fwd(int unit, int G, cx<T> *__restrict__ buf,
                                               const cx<T> *__restrict__ S,
                                               cx2<T> *__restrict__ Z,
@@ -333,6 +338,30 @@ __device__ __forceinline__ void body_cols_fwd(int unit, int G, cx<T> *__restrict
     const bool packed = unit == 0;          // workgroup-uniform: the group holding column 0
     const bool is0 = packed && gi == 0;
     const Lds<T> lds{buf, gi, G};
+
+    // PF (FP32): the radial spectrum pairs (E'_r, Q_r) of the workgroup's
+    // columns go straight from global memory into LDS (16 bytes per lane,
+    // 1 KB per wave instruction, no registers held) while the column is
+    // gathered and transformed; the multiply-accumulate reads them from
+    // there.  Region after the transform's: G x spec_prefetch_len<L>() pairs.
+    constexpr int LP = spec_prefetch_len<L>();
+    cx2<T> *const spl = reinterpret_cast<cx2<T> *>(buf + (size_t)G * padded_len(L));
+    if constexpr (PF) {
+        static_assert(sizeof(cx2<T>) == 16, "16-byte pairs (FP32)");
+        const int lane = (int)(threadIdx.x & 63), wv = (int)(threadIdx.x >> 6);
+        const int nw = (int)(blockDim.x >> 6);
+        constexpr int NCH = LP / 64;
+        for (int c = wv; c < G * NCH; c += nw) {   // wave-uniform loop
+            const int g2 = c / NCH, q = c % NCH;
+            const int cg = unit * G + g2;
+            const int ccl = cg < H ? cg : 0;
+            const int ku = min(q * 64 + lane, L / 2);   // always a valid entry
+            __builtin_amdgcn_global_load_lds(
+                (const void *)(spec + (size_t)ccl * ldspec + ku),
+                (__attribute__((address_space(3))) void *)(spl + (size_t)g2 * LP + q * 64), 16, 0,
+                0);
+        }
+    }
 
     // The column.  Only the first E/2 strided points of a thread can be data
     // rows (L >= 2 n_r); clamped, always valid addresses so the loads issue
@@ -363,6 +392,13 @@ __device__ __forceinline__ void body_cols_fwd(int unit, int G, cx<T> *__restrict
 
     const cx2<T> *sr = spec + (size_t)cl * ldspec;               // (E'_r, Q_r)
     const cx2<T> *sp = spec + (size_t)(H + cl) * ldspec;         // (E'_p, Q_p)
+    const cx2<T> *srl = spl + (size_t)gi * LP;                    // (E'_r, Q_r) in LDS
+    if constexpr (PF) {
+        // the prefetch has landed for this wave; the barrier makes every
+        // wave's chunks visible
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+    }
     const SlopeFix<T> a = slope_fix(x0, x1, xm2, xm1, ca, c0, cn);
     const SlopePhasors<T> ph = slope_phasors(a, wt, wnt);
     SlopePhasors<T> ph0 = ph, phM = ph;
@@ -381,7 +417,7 @@ __device__ __forceinline__ void body_cols_fwd(int unit, int G, cx<T> *__restrict
 #pragma unroll
         for (int j = 0; j < CH; ++j) {
             const int ix = spec_index<L, E>(t, cb + j);
-            pr[j] = sr[ix];
+            pr[j] = PF ? srl[ix] : sr[ix];
             pp[j] = sp[ix];
         }
 #pragma unroll

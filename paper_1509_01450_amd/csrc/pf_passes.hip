@@ -42,8 +42,9 @@ __global__ __launch_bounds__(512) void k_cols_fwd(const cx<T> *__restrict__ S,
     extern __shared__ unsigned char smem_raw[];
     const int grp = xcd_group(blockIdx.x, per_xcd);
     if (grp >= n_groups) return;  // whole workgroup leaves together
-    body_cols_fwd<T, L, E>(grp, blockDim.x / (L / E), reinterpret_cast<cx<T> *>(smem_raw), S, Z,
-                           spec, H, n_r, n_out, ldspec, ca, c0, cn, twL);
+    body_cols_fwd<T, L, E, sizeof(T) == 4>(grp, blockDim.x / (L / E),
+                                           reinterpret_cast<cx<T> *>(smem_raw), S, Z, spec, H,
+                                           n_r, n_out, ldspec, ca, c0, cn, twL);
 }
 
 template <typename T, int L, int E>
@@ -73,13 +74,20 @@ bool valid_shape_rows(int M, Shape s, bool f64) {
     return lds <= 144 * 1024;
 }
 
-// Column pass: G padded_len(L) complex of LDS.
+// Column pass LDS: G padded_len(L) complex for the transforms, and in FP32
+// the forward pass's prefetched radial spectra, G ((L/2 + 1) rounded up to
+// 64) pairs.
+size_t cols_lds_bytes(int L, int G, bool f64, bool fwd) {
+    const size_t fft = (size_t)G * padded_len(L) * (f64 ? 16 : 8);
+    const size_t pf = (fwd && !f64) ? (size_t)G * (((L / 2 + 1) + 63) / 64 * 64) * 16 : 0;
+    return fft + pf;
+}
+
 bool valid_shape_cols(int L, Shape s, bool f64) {
     if (!(s.E == 8 || s.E == 16) || s.E > L) return false;
     const int th = L / s.E;
     if (s.G < 1 || th * s.G > 512) return false;
-    const size_t lds = (size_t)s.G * padded_len(L) * (f64 ? 16 : 8);
-    return lds <= 144 * 1024;
+    return cols_lds_bytes(L, s.G, f64, true) <= 144 * 1024;
 }
 
 #define PF_SWITCH_POW2(v, F, ...)                          \
@@ -153,7 +161,7 @@ struct Disp {
             const int n_groups = (p.H + G - 1) / G;
             const int per_xcd = (n_groups + 7) / 8;
             const int blocks = per_xcd * 8;
-            const size_t lds = (size_t)G * padded_len(N) * sizeof(cx<T>);
+            const size_t lds = cols_lds_bytes(N, G, sizeof(T) == 8, !ADJ);
             const T ca = T(p.ca), c0 = T(p.c0), cn = T(p.cn);
             const cx2<T> *sp = reinterpret_cast<const cx2<T> *>(spec);
             if (ADJ) {
