@@ -323,6 +323,31 @@ __host__ __device__ constexpr int mac_batch() {
 template <int L>
 __host__ __device__ constexpr int spec_prefetch_len() { return ((L / 2 + 1) + 63) / 64 * 64; }
 
+// The radial spectrum pairs (E'_r, Q_r) of the workgroup's G columns from
+// global memory straight into LDS (16 bytes per lane, 1 KB per wave
+// instruction, no registers held), into spl[G][spec_prefetch_len<L>()];
+// the caller waits (vector memory count 0, then a barrier) before reading.
+// FP32 only (16-byte pairs).
+template <typename T, int L>
+__device__ __forceinline__ void prefetch_radial_spectra(int unit, int G, int H, int ldspec,
+                                                        const cx2<T> *__restrict__ spec,
+                                                        cx2<T> *spl) {
+    static_assert(sizeof(cx2<T>) == 16, "16-byte pairs (FP32)");
+    constexpr int LP = spec_prefetch_len<L>();
+    constexpr int NCH = LP / 64;
+    const int lane = (int)(threadIdx.x & 63), wv = (int)(threadIdx.x >> 6);
+    const int nw = (int)(blockDim.x >> 6);
+    for (int c = wv; c < G * NCH; c += nw) {   // wave-uniform loop
+        const int g2 = c / NCH, q = c % NCH;
+        const int cg = unit * G + g2;
+        const int ccl = cg < H ? cg : 0;
+        const int ku = min(q * 64 + lane, L / 2);   // always a valid entry
+        __builtin_amdgcn_global_load_lds(
+            (const void *)(spec + (size_t)ccl * ldspec + ku),
+            (__attribute__((address_space(3))) void *)(spl + (size_t)g2 * LP + q * 64), 16, 0, 0);
+    }
+}
+
 template <typename T, int L, int E, bool PF = false>
 __device__ __forceinline__ void body_cols_fwd(int unit, int G, cx<T> *__restrict__ buf,
                                               const cx<T> *__restrict__ S,
@@ -339,29 +364,11 @@ __device__ __forceinline__ void body_cols_fwd(int unit, int G, cx<T> *__restrict
     const bool is0 = packed && gi == 0;
     const Lds<T> lds{buf, gi, G};
 
-    // PF (FP32): the radial spectrum pairs (E'_r, Q_r) of the workgroup's
-    // columns go straight from global memory into LDS (16 bytes per lane,
-    // 1 KB per wave instruction, no registers held) while the column is
-    // gathered and transformed; the multiply-accumulate reads them from
-    // there.  Region after the transform's: G x spec_prefetch_len<L>() pairs.
+    // PF (FP32): the radial spectrum pairs of the workgroup's columns go
+    // straight into LDS while the column is gathered and transformed
     constexpr int LP = spec_prefetch_len<L>();
     cx2<T> *const spl = reinterpret_cast<cx2<T> *>(buf + (size_t)G * padded_len(L));
-    if constexpr (PF) {
-        static_assert(sizeof(cx2<T>) == 16, "16-byte pairs (FP32)");
-        const int lane = (int)(threadIdx.x & 63), wv = (int)(threadIdx.x >> 6);
-        const int nw = (int)(blockDim.x >> 6);
-        constexpr int NCH = LP / 64;
-        for (int c = wv; c < G * NCH; c += nw) {   // wave-uniform loop
-            const int g2 = c / NCH, q = c % NCH;
-            const int cg = unit * G + g2;
-            const int ccl = cg < H ? cg : 0;
-            const int ku = min(q * 64 + lane, L / 2);   // always a valid entry
-            __builtin_amdgcn_global_load_lds(
-                (const void *)(spec + (size_t)ccl * ldspec + ku),
-                (__attribute__((address_space(3))) void *)(spl + (size_t)g2 * LP + q * 64), 16, 0,
-                0);
-        }
-    }
+    if constexpr (PF) prefetch_radial_spectra<T, L>(unit, G, H, ldspec, spec, spl);
 
     // The column.  Only the first E/2 strided points of a thread can be data
     // rows (L >= 2 n_r); clamped, always valid addresses so the loads issue

@@ -74,9 +74,9 @@ bool valid_shape_rows(int M, Shape s, bool f64) {
     return lds <= 144 * 1024;
 }
 
-// Column pass LDS: G padded_len(L) complex for the transforms, and in FP32
-// the forward pass's prefetched radial spectra, G ((L/2 + 1) rounded up to
-// 64) pairs.
+// Column pass LDS: G padded_len(L) complex for the transforms, and in the
+// FP32 forward pass the prefetched radial spectra, G ((L/2 + 1) rounded up
+// to 64) pairs.
 size_t cols_lds_bytes(int L, int G, bool f64, bool fwd) {
     const size_t fft = (size_t)G * padded_len(L) * (f64 ? 16 : 8);
     const size_t pf = (fwd && !f64) ? (size_t)G * (((L / 2 + 1) + 63) / 64 * 64) * 16 : 0;
