@@ -4,8 +4,9 @@ sums, element by element, and Fig. 3's orders on the analytic sigma_D2 disk.
 
 * full-grid parity on ragged and non-power-of-two grids spanning several
   tiles, all three methods, FP64 (relative L2 <= 1e-11) and FP32 (<= 1e-5);
-* sampled parity at 512 x 512 and 1024 x 1024 (every boundary row and
-  column plus random cells), FP64 and FP32;
+* sampled parity at 512 x 512, 1024 x 1024 and the largest grid,
+  2048 x 2048 (every boundary row and column plus random cells), FP64 and
+  FP32;
 * the sigma_D2 disk (alpha = 0.25, centred in [-M, M]^2 with M = 0.5) for
   N = 64 ... 1024: fitted orders of the L1 error of F_r over the last four
   grids within 0.15 of Fig. 3 (2.0, 1.1, 1.0), and the ordering of the
@@ -77,7 +78,7 @@ def test_full_grid_parity(shape, method):
         assert rx < tol and ry < tol, (shape, method, dt, rx, ry)
 
 
-@pytest.mark.parametrize("N", [512, 1024])
+@pytest.mark.parametrize("N", [512, 1024, 2048])
 def test_sampled_parity_large(N):
     g = oracle.CartGrid.square(N, 0.5)
     sig = _density(g, 5)
