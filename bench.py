@@ -298,9 +298,11 @@ def main():
         build_b = time.perf_counter() - t0
         outs = [(torch.empty_like(s), torch.empty_like(s)) for s in sig_b]
         msb = time_calls(torch, lambda: pf.forces_batched(plans, sig_b, outs), max(K // 4, 10), 5)
+        msg = time_graph(torch, lambda: pf.forces_batched(plans, sig_b, outs), max(K // 4, 10), 5)
         bcells = sum(nr * nphi for nr, nphi in sizes)
         batched = {"workload": "64 disks, N_r in {256..1024}, N_phi in {256..2048}, FP32",
                    "cells": bcells, "ms_per_call": msb, "cells_per_s": bcells / (msb * 1e-3),
+                   "graph_ms_per_call": msg, "graph_cells_per_s": bcells / (msg * 1e-3),
                    "table_build_s": build_b}
 
     # ---- Cartesian grid (second-order method, sigma_D2 disk) -----------------

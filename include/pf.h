@@ -195,7 +195,10 @@ int pf_forces_backward(pf_plan plan, const void *g_fr, const void *g_fphi,
  * Plans of a batch share internal state: do not run two batches with common
  * plans at once.  The first call for a set of plans, and a call whose field
  * pointers differ from the previous call's, waits for a small table upload;
- * otherwise asynchronous.  1 <= n <= 4096.                                  */
+ * otherwise the call only enqueues the three launches (asynchronous, and it
+ * may be captured into a HIP graph).  The launches read the batch's pointer
+ * table at run time: a graph replay writes to the fields of the most recent
+ * call for that set of plans.  1 <= n <= 4096.                              */
 int pf_forces_batched(int n, const pf_plan *plans, const void *const *sigma,
                       void *const *f_r, void *const *f_phi, void *stream);
 
