@@ -40,7 +40,7 @@ HBM_PEAK_GBS = 8000.0
 
 # Counter summary of the dominant kernel (FETCH_SIZE / WRITE_SIZE per
 # dispatch with their copy-kernel calibration) and the sources it depends on.
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_cols_fwd_f32_1024x2048_traffic.txt")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_cols_fwd_pf_f32_1024x2048_traffic.txt")
 KERNEL_SOURCES = ("paper_1509_01450_amd/csrc/fft_core.hpp",
                   "paper_1509_01450_amd/csrc/pass_bodies.hpp",
                   "paper_1509_01450_amd/csrc/pf_passes.hip")
@@ -241,8 +241,8 @@ def main():
                        "frac": achieved / HBM_PEAK_GBS,
                        "traffic": measured_traffic(p32.schedule()[4:6])}
     out["detail"] = {
-        "dominant_kernel": "k_cols_fwd (u-FFT + spectral MAC with spectral radial slope + "
-                           "two inverse u-FFTs)",
+        "dominant_kernel": "k_cols_fwd_pf (u-FFT + spectral MAC with spectral radial slope + "
+                           "two inverse u-FFTs; radial spectra prefetched to LDS)",
         "dominant_kernel_source_hash": kernel_source_hash(),
         "step_timing": "K back-to-back pf_forces calls between events on the launch stream",
         "graph_ms_per_step_fp32": ms32_graph,

@@ -262,6 +262,16 @@ struct Lds {
     }
 };
 
+// Workgroup barrier for the LDS exchanges: this wave's LDS operations are
+// complete (LDS count 0), then the hardware barrier; the memory clobber
+// keeps the compiler from moving memory accesses across it.  Unlike
+// __syncthreads() it does not wait for the wave's outstanding global memory
+// operations, so loads issued before a transform -- including loads into
+// another LDS array -- stay in flight across its exchanges.
+__device__ __forceinline__ void lds_barrier() {
+    asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
 // ---------------------------------------------------------------------------
 // Twiddles.  A thread's twiddles depend only on its index t and the stage,
 // so they are loaded once from the table into registers (Twiddles::load)
@@ -345,7 +355,7 @@ __device__ __forceinline__ void tw_expand(const cx<T> *p, cx<T> *o) {
 // own LDS region, sharing the stage barriers.  Template parameters: N
 // (length), E (points per thread), NS (span of the stage), OFF (offset of the
 // stage's twiddles), NV (number of transforms).  All threads of the
-// workgroup must call this together (it contains __syncthreads()).
+// workgroup must call this together (it contains workgroup barriers).
 // ---------------------------------------------------------------------------
 template <int N, int E, int NS, int OFF, int NV, typename T, bool ZH = false>
 __device__ __forceinline__ void fft_stages(cx<T> (&v)[NV][E], int t, const Lds<T> (&lds)[NV],
@@ -386,13 +396,13 @@ __device__ __forceinline__ void fft_stages(cx<T> (&v)[NV][E], int t, const Lds<T
         }
     }
     if constexpr (!LAST) {
-        __syncthreads();
+        lds_barrier();
         const int pt = lds_pad(t);
 #pragma unroll
         for (int a = 0; a < NV; ++a)
 #pragma unroll
             for (int e = 0; e < E; ++e) v[a][e] = lds[a].ld_split(pt, e * TH);
-        __syncthreads();
+        lds_barrier();
         fft_stages<N, E, NS * R, OFF + (NS > 1 ? NB * ilog2c(R) : 0), NV, T>(v, t, lds, tw);
     }
 }

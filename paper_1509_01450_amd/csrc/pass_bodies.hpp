@@ -318,43 +318,68 @@ __host__ __device__ constexpr int mac_batch() {
 // S: [n_r][H] complex (the source rows); Z: [n_out][H] pairs (Zr, Zp), the
 // destination rows; spec: [2][H][ldspec] pairs.
 // ---------------------------------------------------------------------------
-// Entries of the radial spectrum pair per column in the LDS prefetch region
-// (L/2 + 1 rounded up to whole 64-lane chunks).
-template <int L>
-__host__ __device__ constexpr int spec_prefetch_len() { return ((L / 2 + 1) + 63) / 64 * 64; }
+// Entries of the radial spectrum pair per column in the LDS prefetch region:
+// L/2 + 1 rounded up to whole 64-lane chunks and, when a column has at
+// least 64 threads (L / E >= 64), to a multiple of L / E, so that every
+// wave issues the same number of chunk loads, known at compile time.
+template <int L, int E>
+__host__ __device__ constexpr int spec_prefetch_len() {
+    constexpr int Q = (L / E) > 64 ? (L / E) : 64;
+    return ((L / 2 + 1) + Q - 1) / Q * Q;
+}
 
 // The radial spectrum pairs (E'_r, Q_r) of the workgroup's G columns from
-// global memory straight into LDS (16 bytes per lane, 1 KB per wave
-// instruction, no registers held), into spl[G][spec_prefetch_len<L>()];
-// the caller waits (vector memory count 0, then a barrier) before reading.
-// FP32 only (16-byte pairs).
-template <typename T, int L>
+// global memory straight into LDS, spl[G][spec_prefetch_len<L, E>()]: buffer
+// loads with the LDS-direct flag, 16 bytes per lane, 1 KB per wave
+// instruction, no registers held.  The caller waits (all counters 0, then a
+// barrier) before reading.  With L / E >= 64 the G columns take
+// G L / (64 E) waves and each wave issues LP E / L chunk loads, a count
+// fixed at compile time: the compiler can then wait for loads issued before
+// these without waiting for these, and when spl is an LDS array of its own
+// the transform's LDS accesses do not wait for them either.  Offsets are
+// 32-bit: the radial half of the spectra must be below 2 GB (checked by the
+// host).  FP32 only (16-byte pairs).
+template <typename T, int L, int E>
 __device__ __forceinline__ void prefetch_radial_spectra(int unit, int G, int H, int ldspec,
                                                         const cx2<T> *__restrict__ spec,
                                                         cx2<T> *spl) {
     static_assert(sizeof(cx2<T>) == 16, "16-byte pairs (FP32)");
-    constexpr int LP = spec_prefetch_len<L>();
+    constexpr int LP = spec_prefetch_len<L, E>();
     constexpr int NCH = LP / 64;
     const int lane = (int)(threadIdx.x & 63), wv = (int)(threadIdx.x >> 6);
     const int nw = (int)(blockDim.x >> 6);
-    for (int c = wv; c < G * NCH; c += nw) {   // wave-uniform loop
+    // raw buffer over the radial half (stride 0, byte offsets); the last
+    // word is the data-format field every gfx9 raw buffer access uses
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<cx2<T> *>(spec), (short)0, H * ldspec * 16, 0x00020000);
+    auto chunk = [&](int c) {
         const int g2 = c / NCH, q = c % NCH;
         const int cg = unit * G + g2;
         const int ccl = cg < H ? cg : 0;
         const int ku = min(q * 64 + lane, L / 2);   // always a valid entry
-        __builtin_amdgcn_global_load_lds(
-            (const void *)(spec + (size_t)ccl * ldspec + ku),
-            (__attribute__((address_space(3))) void *)(spl + (size_t)g2 * LP + q * 64), 16, 0, 0);
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(
+            rs, (__attribute__((address_space(3))) void *)(spl + (size_t)g2 * LP + q * 64), 16,
+            (ccl * ldspec + ku) * 16, 0, 0, 0);
+    };
+    if constexpr (L / E >= 64) {
+        // nw = G L / (64 E) waves, G NCH chunks: LP E / L chunks per wave
+#pragma unroll
+        for (int k = 0; k < LP / (L / E); ++k) chunk(wv + k * nw);
+    } else {
+        for (int c = wv; c < G * NCH; c += nw) chunk(c);   // wave-uniform loop
     }
 }
 
+// PF (FP32): the radial spectrum pairs go to LDS at spl (G
+// spec_prefetch_len<L, E>() pairs) while the column is transformed.
 template <typename T, int L, int E, bool PF = false>
 __device__ __forceinline__ void body_cols_fwd(int unit, int G, cx<T> *__restrict__ buf,
                                               const cx<T> *__restrict__ S,
                                               cx2<T> *__restrict__ Z,
                                               const cx2<T> *__restrict__ spec, int H, int n_r,
                                               int n_out, int ldspec, T ca, T c0, T cn,
-                                              const cx<T> *__restrict__ twL) {
+                                              const cx<T> *__restrict__ twL,
+                                              cx2<T> *spl = nullptr) {
     constexpr int TH = L / E;
     const int gi = threadIdx.x % G, t = threadIdx.x / G;
     const int col = unit * G + gi;
@@ -364,11 +389,7 @@ __device__ __forceinline__ void body_cols_fwd(int unit, int G, cx<T> *__restrict
     const bool is0 = packed && gi == 0;
     const Lds<T> lds{buf, gi, G};
 
-    // PF (FP32): the radial spectrum pairs of the workgroup's columns go
-    // straight into LDS while the column is gathered and transformed
-    constexpr int LP = spec_prefetch_len<L>();
-    cx2<T> *const spl = reinterpret_cast<cx2<T> *>(buf + (size_t)G * padded_len(L));
-    if constexpr (PF) prefetch_radial_spectra<T, L>(unit, G, H, ldspec, spec, spl);
+    constexpr int LP = spec_prefetch_len<L, E>();
 
     // The column.  Only the first E/2 strided points of a thread can be data
     // rows (L >= 2 n_r); clamped, always valid addresses so the loads issue
@@ -385,6 +406,8 @@ __device__ __forceinline__ void body_cols_fwd(int unit, int G, cx<T> *__restrict
     const cx<T> wt = twL[t], wnt = twL[(int)(((unsigned)n_r * (unsigned)t) & (unsigned)(L - 1))];
     Twiddles<L, E, T> tw;
     tw.load(t, twL, 1);
+    // issued after the column's loads, which the transform waits for
+    if constexpr (PF) prefetch_radial_spectra<T, L, E>(unit, G, H, ldspec, spec, spl);
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         const int i = t + e * TH;
@@ -394,12 +417,12 @@ __device__ __forceinline__ void body_cols_fwd(int unit, int G, cx<T> *__restrict
     if (packed) {   // column 0 reads the conjugate mirror points from LDS
 #pragma unroll
         for (int e = 0; e < E; ++e) lds.st_split(lds_pad(t), e * TH, v[e]);
-        __syncthreads();
+        lds_barrier();
     }
 
     const cx2<T> *sr = spec + (size_t)cl * ldspec;               // (E'_r, Q_r)
     const cx2<T> *sp = spec + (size_t)(H + cl) * ldspec;         // (E'_p, Q_p)
-    const cx2<T> *srl = spl + (size_t)gi * LP;                    // (E'_r, Q_r) in LDS
+    const cx2<T> *srl = PF ? spl + (size_t)gi * LP : nullptr;     // (E'_r, Q_r) in LDS
     if constexpr (PF) {
         // the prefetch has landed for this wave; the barrier makes every
         // wave's chunks visible
@@ -451,7 +474,7 @@ __device__ __forceinline__ void body_cols_fwd(int unit, int G, cx<T> *__restrict
             }
         }
     }
-    if (packed) __syncthreads();
+    if (packed) lds_barrier();
     fft_inv<L, E, T>(y[0], t, lds, tw);
     fft_inv<L, E, T>(y[1], t, lds, tw);
     if (valid) {

@@ -42,9 +42,33 @@ __global__ __launch_bounds__(512) void k_cols_fwd(const cx<T> *__restrict__ S,
     extern __shared__ unsigned char smem_raw[];
     const int grp = xcd_group(blockIdx.x, per_xcd);
     if (grp >= n_groups) return;  // whole workgroup leaves together
-    body_cols_fwd<T, L, E, sizeof(T) == 4>(grp, blockDim.x / (L / E),
-                                           reinterpret_cast<cx<T> *>(smem_raw), S, Z, spec, H,
-                                           n_r, n_out, ldspec, ca, c0, cn, twL);
+    const int G = blockDim.x / (L / E);
+    cx<T> *const buf = reinterpret_cast<cx<T> *>(smem_raw);
+    body_cols_fwd<T, L, E, sizeof(T) == 4>(grp, G, buf, S, Z, spec, H, n_r, n_out, ldspec, ca,
+                                           c0, cn, twL,
+                                           reinterpret_cast<cx2<T> *>(buf + (size_t)G * padded_len(L)));
+}
+
+// FP32 forward column pass with G fixed at compile time: the transform
+// buffer and the radial spectrum prefetch region are two static LDS arrays,
+// so the prefetch stays in flight while the column is transformed (the
+// compiler sees that the transform's LDS accesses cannot touch the
+// prefetch region; with one dynamic LDS array it waits for the prefetch
+// before the first exchange).
+template <int L, int E, int G>
+__global__ __launch_bounds__(512) void k_cols_fwd_pf(const cx<float> *__restrict__ S,
+                                                     cx2<float> *__restrict__ Z,
+                                                     const cx2<float> *__restrict__ spec, int H,
+                                                     int n_r, int n_out, int ldspec, float ca,
+                                                     float c0, float cn,
+                                                     const cx<float> *__restrict__ twL,
+                                                     int per_xcd, int n_groups) {
+    __shared__ cx<float> fbuf[G * padded_len(L)];
+    __shared__ cx2<float> spl[G * spec_prefetch_len<L, E>()];
+    const int grp = xcd_group(blockIdx.x, per_xcd);
+    if (grp >= n_groups) return;  // whole workgroup leaves together
+    body_cols_fwd<float, L, E, true>(grp, G, fbuf, S, Z, spec, H, n_r, n_out, ldspec, ca, c0, cn,
+                                     twL, spl);
 }
 
 template <typename T, int L, int E>
@@ -75,11 +99,12 @@ bool valid_shape_rows(int M, Shape s, bool f64) {
 }
 
 // Column pass LDS: G padded_len(L) complex for the transforms, and in the
-// FP32 forward pass the prefetched radial spectra, G ((L/2 + 1) rounded up
-// to 64) pairs.
-size_t cols_lds_bytes(int L, int G, bool f64, bool fwd) {
+// FP32 forward pass the prefetched radial spectra, G spec_prefetch_len<L, E>
+// pairs (L/2 + 1 rounded up to a multiple of max(64, L/E)).
+size_t cols_lds_bytes(int L, int E, int G, bool f64, bool fwd) {
     const size_t fft = (size_t)G * padded_len(L) * (f64 ? 16 : 8);
-    const size_t pf = (fwd && !f64) ? (size_t)G * (((L / 2 + 1) + 63) / 64 * 64) * 16 : 0;
+    const int q = L / E > 64 ? L / E : 64;
+    const size_t pf = (fwd && !f64) ? (size_t)G * (((L / 2 + 1) + q - 1) / q * q) * 16 : 0;
     return fft + pf;
 }
 
@@ -87,7 +112,7 @@ bool valid_shape_cols(int L, Shape s, bool f64) {
     if (!(s.E == 8 || s.E == 16) || s.E > L) return false;
     const int th = L / s.E;
     if (s.G < 1 || th * s.G > 512) return false;
-    return cols_lds_bytes(L, s.G, f64, true) <= 144 * 1024;
+    return cols_lds_bytes(L, s.E, s.G, f64, true) <= 144 * 1024;
 }
 
 #define PF_SWITCH_POW2(v, F, ...)                          \
@@ -115,6 +140,28 @@ int allow_lds(K kern, size_t lds) {
         PF_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     return PF_OK;
+}
+
+// The static-LDS forward column kernel for a compile-time G, when its LDS
+// (transform buffer and prefetch region) fits the 144 KB the shape check
+// allows; false (nothing launched) otherwise.
+template <int N, int E, int G>
+constexpr bool cols_pf_fits() {
+    return G * (N / E) <= 512 && (size_t)G * padded_len(N) * 8 +
+                                         (size_t)G * spec_prefetch_len<N, E>() * 16 <=
+                                     (size_t)144 * 1024;
+}
+
+template <int N, int E, int G>
+bool launch_cols_pf(dim3 grid, hipStream_t st, const cx<float> *S, cx2<float> *Z,
+                    const cx2<float> *spec, const Plan &p, float ca, float c0, float cn,
+                    const cx<float> *tw, int per_xcd, int n_groups) {
+    if constexpr (cols_pf_fits<N, E, G>()) {
+        hipLaunchKernelGGL((k_cols_fwd_pf<N, E, G>), grid, dim3(G * (N / E)), 0, st, S, Z, spec,
+                           p.H, p.n_in, p.n_r, p.ldspec, ca, c0, cn, tw, per_xcd, n_groups);
+        return true;
+    }
+    return false;
 }
 
 template <typename T>
@@ -161,7 +208,7 @@ struct Disp {
             const int n_groups = (p.H + G - 1) / G;
             const int per_xcd = (n_groups + 7) / 8;
             const int blocks = per_xcd * 8;
-            const size_t lds = cols_lds_bytes(N, G, sizeof(T) == 8, !ADJ);
+            const size_t lds = cols_lds_bytes(N, E, G, sizeof(T) == 8, !ADJ);
             const T ca = T(p.ca), c0 = T(p.c0), cn = T(p.cn);
             const cx2<T> *sp = reinterpret_cast<const cx2<T> *>(spec);
             if (ADJ) {
@@ -171,6 +218,27 @@ struct Disp {
                                    reinterpret_cast<const cx2<T> *>(a), o, sp, p.H, p.n_r,
                                    p.ldspec, ca, c0, cn, tw, per_xcd, n_groups);
             } else {
+                if constexpr (sizeof(T) == 4 && TH >= 64) {
+                    // the prefetch's 32-bit offsets cover the radial half
+                    if ((size_t)p.H * p.ldspec * 16 >= ((size_t)1 << 31)) {
+                        set_error("spectra too large for the column pass prefetch");
+                        return PF_EUNSUPPORTED;
+                    }
+                    const dim3 grid(blocks);
+                    cx2<T> *z = reinterpret_cast<cx2<T> *>(o);
+                    const bool done =
+                        G == 1   ? launch_cols_pf<N, E, 1>(grid, st, a, z, sp, p, ca, c0, cn, tw,
+                                                           per_xcd, n_groups)
+                        : G == 2 ? launch_cols_pf<N, E, 2>(grid, st, a, z, sp, p, ca, c0, cn, tw,
+                                                           per_xcd, n_groups)
+                        : G == 4 ? launch_cols_pf<N, E, 4>(grid, st, a, z, sp, p, ca, c0, cn, tw,
+                                                           per_xcd, n_groups)
+                                 : false;
+                    if (done) {
+                        PF_HIP(hipGetLastError());
+                        return PF_OK;
+                    }
+                }
                 int rc = allow_lds(k_cols_fwd<T, N, E>, lds);
                 if (rc) return rc;
                 hipLaunchKernelGGL((k_cols_fwd<T, N, E>), dim3(blocks), dim3(G * TH), lds, st, a,
