@@ -304,8 +304,9 @@ __device__ __forceinline__ cx<T> unpack_odd(cx<T> p, cx<T> m) {
 // Points per batch of spectrum loads in the multiply-accumulate of pass B,
 // sized so that a batch's loads (four complex values per point) fit in the
 // registers beside the transform data: 64 / E in FP32 (E <= 8: all E) for
-// the forward pass, half that for the transpose pass (which holds two input
-// channels and spills otherwise at E = 16), 2 in FP64.
+// the forward pass, half that for the transpose pass when it loads all
+// four values from global memory (it holds two input channels and spills
+// otherwise at E = 16), one in FP64.
 template <typename T, int E, bool ADJ = false>
 __host__ __device__ constexpr int mac_batch() {
     return sizeof(T) == 8 ? 1 : (E < 8 ? E : (ADJ ? 32 : 64) / E);
@@ -329,48 +330,53 @@ __host__ __device__ constexpr int spec_prefetch_len() {
 }
 
 // The radial spectrum pairs (E'_r, Q_r) of the workgroup's G columns from
-// global memory straight into LDS, spl[G][spec_prefetch_len<L, E>()]: buffer
-// loads with the LDS-direct flag, 16 bytes per lane, 1 KB per wave
+// global memory straight into LDS, spl[G][spec_prefetch_len<L, E>()] (a
+// byte copy of the leading pairs of each column): buffer loads with the
+// LDS-direct flag, 16 bytes per lane (half a pair in FP64), 1 KB per wave
 // instruction, no registers held.  The caller waits (all counters 0, then a
 // barrier) before reading.  With L / E >= 64 the G columns take
-// G L / (64 E) waves and each wave issues LP E / L chunk loads, a count
-// fixed at compile time: the compiler can then wait for loads issued before
-// these without waiting for these, and when spl is an LDS array of its own
-// the transform's LDS accesses do not wait for them either.  Offsets are
-// 32-bit: the radial half of the spectra must be below 2 GB (checked by the
-// host).  FP32 only (16-byte pairs).
+// G L / (64 E) waves and each wave issues LP U E / L chunk loads (U = 16-byte
+// units per pair), a count fixed at compile time: the compiler can then wait
+// for loads issued before these without waiting for these, and when spl is
+// an LDS array of its own the transforms' LDS accesses do not wait for them
+// either.  Offsets are 32-bit: the radial half of the spectra must be below
+// 2 GB (checked by the host).
 template <typename T, int L, int E>
 __device__ __forceinline__ void prefetch_radial_spectra(int unit, int G, int H, int ldspec,
                                                         const cx2<T> *__restrict__ spec,
                                                         cx2<T> *spl) {
-    static_assert(sizeof(cx2<T>) == 16, "16-byte pairs (FP32)");
+    constexpr int U = (int)sizeof(cx2<T>) / 16;     // 16-byte units per pair
+    static_assert(U == 1 || U == 2, "16- or 32-byte pairs");
     constexpr int LP = spec_prefetch_len<L, E>();
-    constexpr int NCH = LP / 64;
+    constexpr int NCH = LP * U / 64;                // 64-lane chunks per column
+    constexpr int LAST = (L / 2 + 1) * U - 1;       // last unit of a column's data
     const int lane = (int)(threadIdx.x & 63), wv = (int)(threadIdx.x >> 6);
     const int nw = (int)(blockDim.x >> 6);
     // raw buffer over the radial half (stride 0, byte offsets); the last
     // word is the data-format field every gfx9 raw buffer access uses
     const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
-        const_cast<cx2<T> *>(spec), (short)0, H * ldspec * 16, 0x00020000);
+        const_cast<cx2<T> *>(spec), (short)0, H * ldspec * 16 * U, 0x00020000);
+    unsigned char *const dst = reinterpret_cast<unsigned char *>(spl);
     auto chunk = [&](int c) {
         const int g2 = c / NCH, q = c % NCH;
         const int cg = unit * G + g2;
         const int ccl = cg < H ? cg : 0;
-        const int ku = min(q * 64 + lane, L / 2);   // always a valid entry
+        const int u = min(q * 64 + lane, LAST);     // always a valid unit
         __builtin_amdgcn_raw_ptr_buffer_load_lds(
-            rs, (__attribute__((address_space(3))) void *)(spl + (size_t)g2 * LP + q * 64), 16,
-            (ccl * ldspec + ku) * 16, 0, 0, 0);
+            rs,
+            (__attribute__((address_space(3))) void *)(dst + ((size_t)g2 * LP * U + q * 64) * 16),
+            16, (ccl * ldspec * U + u) * 16, 0, 0, 0);
     };
     if constexpr (L / E >= 64) {
-        // nw = G L / (64 E) waves, G NCH chunks: LP E / L chunks per wave
+        // nw = G L / (64 E) waves, G NCH chunks: LP U E / L chunks per wave
 #pragma unroll
-        for (int k = 0; k < LP / (L / E); ++k) chunk(wv + k * nw);
+        for (int k = 0; k < LP * U / (L / E); ++k) chunk(wv + k * nw);
     } else {
         for (int c = wv; c < G * NCH; c += nw) chunk(c);   // wave-uniform loop
     }
 }
 
-// PF (FP32): the radial spectrum pairs go to LDS at spl (G
+// PF: the radial spectrum pairs go to LDS at spl (G
 // spec_prefetch_len<L, E>() pairs) while the column is transformed.
 template <typename T, int L, int E, bool PF = false>
 __device__ __forceinline__ void body_cols_fwd(int unit, int G, cx<T> *__restrict__ buf,
@@ -534,13 +540,17 @@ __device__ __forceinline__ void column_sums(cx<T> (&x)[Q], int G, cx<T> *__restr
 // V: [n_r][H] pairs (Vr, Vp); D: [n_r][H] complex.  LDS buf: G*padded_len(L)
 // complex.
 // ---------------------------------------------------------------------------
-template <typename T, int L, int E>
+// PF: the radial spectrum pairs go to LDS at spl (G
+// spec_prefetch_len<L, E>() pairs) while the two input channels are
+// transformed.
+template <typename T, int L, int E, bool PF = false>
 __device__ __forceinline__ void body_cols_adj(int unit, int G, cx<T> *__restrict__ buf,
                                               const cx2<T> *__restrict__ V,
                                               cx<T> *__restrict__ D,
                                               const cx2<T> *__restrict__ spec, int H, int n_r,
                                               int ldspec, T ca, T c0, T cn,
-                                              const cx<T> *__restrict__ twL) {
+                                              const cx<T> *__restrict__ twL,
+                                              cx2<T> *spl = nullptr) {
     constexpr int TH = L / E;
     const int gi = threadIdx.x % G, t = threadIdx.x / G;
     const int col = unit * G + gi;
@@ -562,6 +572,8 @@ __device__ __forceinline__ void body_cols_adj(int unit, int G, cx<T> *__restrict
     }
     Twiddles<L, E, T> tw;
     tw.load(t, twL, 1);
+    // issued after the column's loads, which the transforms wait for
+    if constexpr (PF) prefetch_radial_spectra<T, L, E>(unit, G, H, ldspec, spec, spl);
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         const int i = t + e * TH;
@@ -575,18 +587,27 @@ __device__ __forceinline__ void body_cols_adj(int unit, int G, cx<T> *__restrict
     if (packed) {   // column 0 reads the conjugate mirror points from LDS
 #pragma unroll
         for (int e = 0; e < E; ++e) lds.st_split(lds_pad(t), e * TH, va[0][e]);
-        __syncthreads();
+        lds_barrier();
     }
 
     const cx2<T> *sr = spec + (size_t)cl * ldspec;
     const cx2<T> *sp = spec + (size_t)(H + cl) * ldspec;
+    const cx2<T> *srl = PF ? spl + (size_t)gi * spec_prefetch_len<L, E>() : nullptr;
+    if constexpr (PF) {
+        // the prefetch has landed for this wave; the barrier makes every
+        // wave's chunks visible
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+    }
     // The unnormalised inverse transform of R at rows 0, L-1, n, n-1:
     //   w[0] = sum R, w[1] = sum R W^k, w[2] = sum R W^(-n k),
     //   w[3] = sum R W^(-(n-1) k),
     // summed per thread against the roots (W^(j k) = W^(j t) r(j e)) and
     // turned into the thread's share with its phasors afterwards.
     cx<T> w[4] = {{T(0), T(0)}, {T(0), T(0)}, {T(0), T(0)}, {T(0), T(0)}};
-    constexpr int CH = mac_batch<T, E, true>();
+    // with the radial pairs in LDS only the azimuthal ones take registers:
+    // the forward pass's batch
+    constexpr int CH = mac_batch<T, E, !PF>();
     const bool t0 = t == 0;
 #pragma unroll
     for (int cb = 0; cb < E; cb += CH) {
@@ -594,7 +615,7 @@ __device__ __forceinline__ void body_cols_adj(int unit, int G, cx<T> *__restrict
 #pragma unroll
         for (int j = 0; j < CH; ++j) {
             const int ix = spec_index<L, E>(t, cb + j);
-            pr[j] = sr[ix];
+            pr[j] = PF ? srl[ix] : sr[ix];
             pp[j] = sp[ix];
         }
 #pragma unroll
@@ -628,7 +649,7 @@ __device__ __forceinline__ void body_cols_adj(int unit, int G, cx<T> *__restrict
             w[3] = w[3] + mul_root<E>(q, e);
         }
     }
-    if (packed) __syncthreads();
+    if (packed) lds_barrier();
     {
         const cx<T> wt = twL[t];
         const cx<T> wnt = twL[(int)(((unsigned)n_r * (unsigned)t) & (unsigned)(L - 1))];

@@ -49,26 +49,25 @@ __global__ __launch_bounds__(512) void k_cols_fwd(const cx<T> *__restrict__ S,
                                            reinterpret_cast<cx2<T> *>(buf + (size_t)G * padded_len(L)));
 }
 
-// FP32 forward column pass with G fixed at compile time: the transform
-// buffer and the radial spectrum prefetch region are two static LDS arrays,
+// Forward column pass with G fixed at compile time: the transform buffer
+// and the radial spectrum prefetch region are two static LDS arrays,
 // so the prefetch stays in flight while the column is transformed (the
 // compiler sees that the transform's LDS accesses cannot touch the
 // prefetch region; with one dynamic LDS array it waits for the prefetch
 // before the first exchange).
-template <int L, int E, int G>
-__global__ __launch_bounds__(512) void k_cols_fwd_pf(const cx<float> *__restrict__ S,
-                                                     cx2<float> *__restrict__ Z,
-                                                     const cx2<float> *__restrict__ spec, int H,
-                                                     int n_r, int n_out, int ldspec, float ca,
-                                                     float c0, float cn,
-                                                     const cx<float> *__restrict__ twL,
+template <typename T, int L, int E, int G>
+__global__ __launch_bounds__(512) void k_cols_fwd_pf(const cx<T> *__restrict__ S,
+                                                     cx2<T> *__restrict__ Z,
+                                                     const cx2<T> *__restrict__ spec, int H,
+                                                     int n_r, int n_out, int ldspec, T ca, T c0,
+                                                     T cn, const cx<T> *__restrict__ twL,
                                                      int per_xcd, int n_groups) {
-    __shared__ cx<float> fbuf[G * padded_len(L)];
-    __shared__ cx2<float> spl[G * spec_prefetch_len<L, E>()];
+    __shared__ cx<T> fbuf[G * padded_len(L)];
+    __shared__ cx2<T> spl[G * spec_prefetch_len<L, E>()];
     const int grp = xcd_group(blockIdx.x, per_xcd);
     if (grp >= n_groups) return;  // whole workgroup leaves together
-    body_cols_fwd<float, L, E, true>(grp, G, fbuf, S, Z, spec, H, n_r, n_out, ldspec, ca, c0, cn,
-                                     twL, spl);
+    body_cols_fwd<T, L, E, true>(grp, G, fbuf, S, Z, spec, H, n_r, n_out, ldspec, ca, c0, cn,
+                                 twL, spl);
 }
 
 template <typename T, int L, int E>
@@ -85,6 +84,22 @@ __global__ __launch_bounds__(512) void k_cols_adj(const cx2<T> *__restrict__ V,
                            spec, H, n_r, ldspec, ca, c0, cn, twL);
 }
 
+// Transpose column pass with G fixed at compile time and the radial
+// spectrum prefetch in a static LDS array of its own (as k_cols_fwd_pf).
+template <typename T, int L, int E, int G>
+__global__ __launch_bounds__(512) void k_cols_adj_pf(const cx2<T> *__restrict__ V,
+                                                     cx<T> *__restrict__ D,
+                                                     const cx2<T> *__restrict__ spec, int H,
+                                                     int n_r, int ldspec, T ca, T c0, T cn,
+                                                     const cx<T> *__restrict__ twL, int per_xcd,
+                                                     int n_groups) {
+    __shared__ cx<T> fbuf[G * padded_len(L)];
+    __shared__ cx2<T> spl[G * spec_prefetch_len<L, E>()];
+    const int grp = xcd_group(blockIdx.x, per_xcd);
+    if (grp >= n_groups) return;  // whole workgroup leaves together
+    body_cols_adj<T, L, E, true>(grp, G, fbuf, V, D, spec, H, n_r, ldspec, ca, c0, cn, twL, spl);
+}
+
 // ---------------------------------------------------------------------------
 // Runtime dispatch onto the template instantiations.
 // ---------------------------------------------------------------------------
@@ -98,13 +113,13 @@ bool valid_shape_rows(int M, Shape s, bool f64) {
     return lds <= 144 * 1024;
 }
 
-// Column pass LDS: G padded_len(L) complex for the transforms, and in the
-// FP32 forward pass the prefetched radial spectra, G spec_prefetch_len<L, E>
-// pairs (L/2 + 1 rounded up to a multiple of max(64, L/E)).
-size_t cols_lds_bytes(int L, int E, int G, bool f64, bool fwd) {
+// Column pass LDS: G padded_len(L) complex for the transforms and, when
+// the radial spectra are prefetched, G spec_prefetch_len<L, E> pairs
+// (L/2 + 1 rounded up to a multiple of max(64, L/E)).
+size_t cols_lds_bytes(int L, int E, int G, bool f64, bool prefetch) {
     const size_t fft = (size_t)G * padded_len(L) * (f64 ? 16 : 8);
     const int q = L / E > 64 ? L / E : 64;
-    const size_t pf = (fwd && !f64) ? (size_t)G * (((L / 2 + 1) + q - 1) / q * q) * 16 : 0;
+    const size_t pf = prefetch ? (size_t)G * (((L / 2 + 1) + q - 1) / q * q) * (f64 ? 32 : 16) : 0;
     return fft + pf;
 }
 
@@ -112,7 +127,10 @@ bool valid_shape_cols(int L, Shape s, bool f64) {
     if (!(s.E == 8 || s.E == 16) || s.E > L) return false;
     const int th = L / s.E;
     if (s.G < 1 || th * s.G > 512) return false;
-    return cols_lds_bytes(L, s.E, s.G, f64, true) <= 144 * 1024;
+    // FP32 shapes keep room for the prefetch (every FP32 forward kernel
+    // takes it); FP64 falls back to the kernel without it when the static
+    // prefetch kernel does not fit
+    return cols_lds_bytes(L, s.E, s.G, f64, !f64) <= 144 * 1024;
 }
 
 #define PF_SWITCH_POW2(v, F, ...)                          \
@@ -145,20 +163,32 @@ int allow_lds(K kern, size_t lds) {
 // The static-LDS forward column kernel for a compile-time G, when its LDS
 // (transform buffer and prefetch region) fits the 144 KB the shape check
 // allows; false (nothing launched) otherwise.
-template <int N, int E, int G>
+template <typename T, int N, int E, int G>
 constexpr bool cols_pf_fits() {
-    return G * (N / E) <= 512 && (size_t)G * padded_len(N) * 8 +
-                                         (size_t)G * spec_prefetch_len<N, E>() * 16 <=
+    return G * (N / E) <= 512 && (size_t)G * padded_len(N) * sizeof(cx<T>) +
+                                         (size_t)G * spec_prefetch_len<N, E>() * sizeof(cx2<T>) <=
                                      (size_t)144 * 1024;
 }
 
-template <int N, int E, int G>
-bool launch_cols_pf(dim3 grid, hipStream_t st, const cx<float> *S, cx2<float> *Z,
-                    const cx2<float> *spec, const Plan &p, float ca, float c0, float cn,
-                    const cx<float> *tw, int per_xcd, int n_groups) {
-    if constexpr (cols_pf_fits<N, E, G>()) {
-        hipLaunchKernelGGL((k_cols_fwd_pf<N, E, G>), grid, dim3(G * (N / E)), 0, st, S, Z, spec,
-                           p.H, p.n_in, p.n_r, p.ldspec, ca, c0, cn, tw, per_xcd, n_groups);
+template <typename T, int N, int E, int G>
+bool launch_cols_pf(dim3 grid, hipStream_t st, const cx<T> *S, cx2<T> *Z, const cx2<T> *spec,
+                    const Plan &p, T ca, T c0, T cn, const cx<T> *tw, int per_xcd,
+                    int n_groups) {
+    if constexpr (cols_pf_fits<T, N, E, G>()) {
+        hipLaunchKernelGGL((k_cols_fwd_pf<T, N, E, G>), grid, dim3(G * (N / E)), 0, st, S, Z,
+                           spec, p.H, p.n_in, p.n_r, p.ldspec, ca, c0, cn, tw, per_xcd, n_groups);
+        return true;
+    }
+    return false;
+}
+
+template <typename T, int N, int E, int G>
+bool launch_cols_adj_pf(dim3 grid, hipStream_t st, const cx2<T> *V, cx<T> *D,
+                        const cx2<T> *spec, const Plan &p, T ca, T c0, T cn, const cx<T> *tw,
+                        int per_xcd, int n_groups) {
+    if constexpr (cols_pf_fits<T, N, E, G>()) {
+        hipLaunchKernelGGL((k_cols_adj_pf<T, N, E, G>), grid, dim3(G * (N / E)), 0, st, V, D,
+                           spec, p.H, p.n_r, p.ldspec, ca, c0, cn, tw, per_xcd, n_groups);
         return true;
     }
     return false;
@@ -208,31 +238,52 @@ struct Disp {
             const int n_groups = (p.H + G - 1) / G;
             const int per_xcd = (n_groups + 7) / 8;
             const int blocks = per_xcd * 8;
-            const size_t lds = cols_lds_bytes(N, E, G, sizeof(T) == 8, !ADJ);
+            // dynamic-LDS kernels: only the FP32 forward one prefetches
+            const size_t lds = cols_lds_bytes(N, E, G, sizeof(T) == 8, !ADJ && sizeof(T) == 4);
             const T ca = T(p.ca), c0 = T(p.c0), cn = T(p.cn);
             const cx2<T> *sp = reinterpret_cast<const cx2<T> *>(spec);
             if (ADJ) {
+                if constexpr (TH >= 64) {
+                    if ((size_t)p.H * p.ldspec * sizeof(cx2<T>) >= ((size_t)1 << 31)) {
+                        set_error("spectra too large for the column pass prefetch");
+                        return PF_EUNSUPPORTED;
+                    }
+                    const dim3 grid(blocks);
+                    const cx2<T> *v = reinterpret_cast<const cx2<T> *>(a);
+                    const bool done =
+                        G == 1   ? launch_cols_adj_pf<T, N, E, 1>(grid, st, v, o, sp, p, ca, c0,
+                                                                  cn, tw, per_xcd, n_groups)
+                        : G == 2 ? launch_cols_adj_pf<T, N, E, 2>(grid, st, v, o, sp, p, ca, c0,
+                                                                  cn, tw, per_xcd, n_groups)
+                        : G == 4 ? launch_cols_adj_pf<T, N, E, 4>(grid, st, v, o, sp, p, ca, c0,
+                                                                  cn, tw, per_xcd, n_groups)
+                                 : false;
+                    if (done) {
+                        PF_HIP(hipGetLastError());
+                        return PF_OK;
+                    }
+                }
                 int rc = allow_lds(k_cols_adj<T, N, E>, lds);
                 if (rc) return rc;
                 hipLaunchKernelGGL((k_cols_adj<T, N, E>), dim3(blocks), dim3(G * TH), lds, st,
                                    reinterpret_cast<const cx2<T> *>(a), o, sp, p.H, p.n_r,
                                    p.ldspec, ca, c0, cn, tw, per_xcd, n_groups);
             } else {
-                if constexpr (sizeof(T) == 4 && TH >= 64) {
+                if constexpr (TH >= 64) {
                     // the prefetch's 32-bit offsets cover the radial half
-                    if ((size_t)p.H * p.ldspec * 16 >= ((size_t)1 << 31)) {
+                    if ((size_t)p.H * p.ldspec * sizeof(cx2<T>) >= ((size_t)1 << 31)) {
                         set_error("spectra too large for the column pass prefetch");
                         return PF_EUNSUPPORTED;
                     }
                     const dim3 grid(blocks);
                     cx2<T> *z = reinterpret_cast<cx2<T> *>(o);
                     const bool done =
-                        G == 1   ? launch_cols_pf<N, E, 1>(grid, st, a, z, sp, p, ca, c0, cn, tw,
-                                                           per_xcd, n_groups)
-                        : G == 2 ? launch_cols_pf<N, E, 2>(grid, st, a, z, sp, p, ca, c0, cn, tw,
-                                                           per_xcd, n_groups)
-                        : G == 4 ? launch_cols_pf<N, E, 4>(grid, st, a, z, sp, p, ca, c0, cn, tw,
-                                                           per_xcd, n_groups)
+                        G == 1   ? launch_cols_pf<T, N, E, 1>(grid, st, a, z, sp, p, ca, c0, cn,
+                                                              tw, per_xcd, n_groups)
+                        : G == 2 ? launch_cols_pf<T, N, E, 2>(grid, st, a, z, sp, p, ca, c0, cn,
+                                                              tw, per_xcd, n_groups)
+                        : G == 4 ? launch_cols_pf<T, N, E, 4>(grid, st, a, z, sp, p, ca, c0, cn,
+                                                              tw, per_xcd, n_groups)
                                  : false;
                     if (done) {
                         PF_HIP(hipGetLastError());
