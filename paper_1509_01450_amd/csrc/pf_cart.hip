@@ -378,14 +378,17 @@ __device__ __forceinline__ void body_cart_c2r(int unit, int G, cx<T> *__restrict
 // Pass B: G columns (interleaved lane by lane) x (L/E) threads; LDS two
 // regions of G padded_len(L) complex.
 // ---------------------------------------------------------------------------
-template <typename T, int L, int E>
+// PF: the pairs (E'_x, Q_x) go to LDS at spl (G spec_prefetch_len<L, E>()
+// pairs, an LDS array of its own) while the two columns are transformed.
+template <typename T, int L, int E, bool PF = false>
 __device__ __forceinline__ void body_cart_cols(int unit, int G, cx<T> *__restrict__ buf,
                                                const cx2<T> *__restrict__ SD,
                                                cx2<T> *__restrict__ Z,
                                                const cx2<T> *__restrict__ spec,
                                                const cx<T> *__restrict__ rsp, int H, int n_x,
                                                int ldspec, T ca, T c0, T cn,
-                                               const cx<T> *__restrict__ twL) {
+                                               const cx<T> *__restrict__ twL,
+                                               cx2<T> *spl = nullptr) {
     constexpr int TH = L / E;
     const int gi = threadIdx.x % G, t = threadIdx.x / G;
     const int col = unit * G + gi;
@@ -409,6 +412,8 @@ __device__ __forceinline__ void body_cart_cols(int unit, int G, cx<T> *__restric
     const cx<T> wt = twL[t], wnt = twL[(int)(((unsigned)n_x * (unsigned)t) & (unsigned)(L - 1))];
     Twiddles<L, E, T> tw;
     tw.load(t, twL, 1);
+    // issued after the column's loads, which the transforms wait for
+    if constexpr (PF) prefetch_radial_spectra<T, L, E>(unit, G, H, ldspec, spec, spl);
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         const int i = t + e * TH;
@@ -425,6 +430,13 @@ __device__ __forceinline__ void body_cart_cols(int unit, int G, cx<T> *__restric
             lS.st_split(lds_pad(t), e * TH, v[0][e]);
             lD.st_split(lds_pad(t), e * TH, v[1][e]);
         }
+        lds_barrier();
+    }
+    const cx2<T> *s0l = PF ? spl + (size_t)gi * spec_prefetch_len<L, E>() : nullptr;
+    if constexpr (PF) {
+        // the prefetch has landed for this wave; the barrier makes every
+        // wave's chunks visible
+        __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
     }
 
@@ -449,7 +461,7 @@ __device__ __forceinline__ void body_cart_cols(int unit, int G, cx<T> *__restric
 #pragma unroll
         for (int j = 0; j < CH; ++j) {
             const int ix = spec_index<L, E>(t, cb + j);
-            pa[j] = s0[ix];
+            pa[j] = PF ? s0l[ix] : s0[ix];
             pb[j] = s1[ix];
             ra[j] = r0[ix];
             rb[j] = r1[ix];
@@ -487,7 +499,7 @@ __device__ __forceinline__ void body_cart_cols(int unit, int G, cx<T> *__restric
             v[1][e] = y1;
         }
     }
-    if (packed) __syncthreads();
+    if (packed) lds_barrier();
     fft_inv<L, E, T>(v[0], t, lS, tw);
     fft_inv<L, E, T>(v[1], t, lD, tw);
     if (valid) {
@@ -535,6 +547,38 @@ __global__ __launch_bounds__(512) void k_cart_cols(const cx2<T> *__restrict__ SD
     if (grp >= n_groups) return;   // whole workgroup leaves together
     body_cart_cols<T, L, E>(grp, blockDim.x / (L / E), reinterpret_cast<cx<T> *>(smem_raw), SD,
                             Z, spec, rsp, H, n_x, ldspec, ca, c0, cn, twL);
+}
+
+// Column workgroup size of the Cartesian pass: one column of L / E threads,
+// or 256 / (L / E) columns when a column has fewer than 256 threads.
+__host__ __device__ constexpr int cart_cols_g(int L, int E) {
+    return L / E >= 256 ? 1 : 256 / (L / E);
+}
+
+// The static LDS of the prefetching column kernel (two transform buffers
+// and the prefetch region); it is used when that fits two workgroups per CU.
+template <typename T, int L, int E>
+constexpr size_t cart_cols_pf_lds() {
+    constexpr int G = cart_cols_g(L, E);
+    return (size_t)2 * G * padded_len(L) * sizeof(cx<T>) +
+           (size_t)G * spec_prefetch_len<L, E>() * sizeof(cx2<T>);
+}
+
+template <typename T, int L, int E>
+__global__ __launch_bounds__(512) void k_cart_cols_pf(const cx2<T> *__restrict__ SD,
+                                                      cx2<T> *__restrict__ Z,
+                                                      const cx2<T> *__restrict__ spec,
+                                                      const cx<T> *__restrict__ rsp, int H,
+                                                      int n_x, int ldspec, T ca, T c0, T cn,
+                                                      const cx<T> *__restrict__ twL, int per_xcd,
+                                                      int n_groups) {
+    constexpr int G = cart_cols_g(L, E);
+    __shared__ cx<T> fbuf[2 * G * padded_len(L)];
+    __shared__ cx2<T> spl[G * spec_prefetch_len<L, E>()];
+    const int grp = cart_xcd_group(blockIdx.x, per_xcd);
+    if (grp >= n_groups) return;   // whole workgroup leaves together
+    body_cart_cols<T, L, E, true>(grp, G, fbuf, SD, Z, spec, rsp, H, n_x, ldspec, ca, c0, cn, twL,
+                                  spl);
 }
 
 }  // namespace
@@ -625,8 +669,7 @@ __host__ __device__ constexpr int cart_cols_e(int L, bool f64) { return f64 && L
 Shape cart_cols_shape(int L, bool f64) {
     Shape s;
     s.E = cart_cols_e(L, f64);
-    const int th = L / s.E;
-    s.G = th >= 256 ? 1 : 256 / th;
+    s.G = cart_cols_g(L, s.E);
     return s;
 }
 
@@ -685,6 +728,19 @@ int cols_l(const CartPlan &c, const void *SD, void *Z, hipStream_t st) {
     const Shape s = cart_cols_shape(L, sizeof(T) == 8);
     const int n_groups = (c.H + s.G - 1) / s.G;
     const int per_xcd = (n_groups + 7) / 8;
+    if constexpr (sizeof(T) == 4 && L / E >= 64 && cart_cols_pf_lds<T, L, E>() <= 80 * 1024) {
+        // FP32 with the (E'_x, Q_x) prefetch (32-bit offsets over that half)
+        if ((size_t)c.H * c.ldspec * sizeof(cx2<T>) >= ((size_t)1 << 31)) {
+            set_error("Cartesian spectra too large for the column pass prefetch");
+            return PF_EUNSUPPORTED;
+        }
+        hipLaunchKernelGGL((k_cart_cols_pf<T, L, E>), dim3(per_xcd * 8), dim3(s.G * (L / E)), 0,
+                           st, (const cx2<T> *)SD, (cx2<T> *)Z, (const cx2<T> *)c.spec,
+                           (const cx<T> *)c.rsp, c.H, c.n_x, c.ldspec, T(0.5 / c.dx),
+                           T(1.0 / c.dx), T(1.0 / c.dx), (const cx<T> *)c.twL, per_xcd, n_groups);
+        PF_HIP(hipGetLastError());
+        return PF_OK;
+    }
     const size_t lds = (size_t)2 * s.G * padded_len(L) * sizeof(cx<T>);
     int rc = allow_lds_cart(k_cart_cols<T, L, E>, lds);
     if (rc) return rc;
