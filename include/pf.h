@@ -232,6 +232,16 @@ int pf_plan_selfcell(pf_plan plan, double out[3]);
  * transpose column pass.  Not in the paper: a diagnostic.                  */
 int pf_plan_schedule(pf_plan plan, int out[8]);
 
+/* Set the launch shapes of a built plan, in[8] in the layout of
+ * pf_plan_schedule, in place of the autotuned or default ones (for
+ * reproducible shapes without tuning, or to run a given kernel variant).
+ * Each shape must fit its transform: points per thread 4, 8 or 16 for the
+ * rows and 8 or 16 for the columns, at most the transform length, at most
+ * 512 threads per workgroup, and the workgroup's LDS within 144 KB;
+ * otherwise PF_EINVAL and the plan keeps its shapes.  PF_ESTATE if the plan
+ * is not built.  Not in the paper: a tuning control.                      */
+int pf_plan_set_schedule(pf_plan plan, const int in[8]);
+
 /* Copy the six FP64 kernel tables to host memory `dst` (plan built with
  * keep_tables).  Layout: [6][2 n_r - 1][n_phi], kernels in the order
  * K^{r,0}, K^{r,r}, K^{r,phi}, K^{phi,0}, K^{phi,r}, K^{phi,phi}; row

@@ -39,7 +39,8 @@ _CART_METHODS = {"second": PF_CART_SECOND, "particle": PF_CART_PARTICLE,
 
 EXPORTS = ("pf_build_opts_default", "pf_plan_create", "pf_kernels_build", "pf_forces",
            "pf_forces_backward", "pf_forces_batched", "pf_forces_timed", "pf_plan_geometry",
-           "pf_plan_schedule", "pf_plan_selfcell", "pf_plan_tables", "pf_plan_destroy",
+           "pf_plan_schedule", "pf_plan_set_schedule", "pf_plan_selfcell", "pf_plan_tables",
+           "pf_plan_destroy",
            "pf_last_error", "pf_version", "pf_plan_create_patches", "pf_forces_patches",
            "pf_cart_create", "pf_cart_build", "pf_cart_forces",
            "pf_cart_forces_timed", "pf_cart_geometry", "pf_cart_destroy")
@@ -89,10 +90,12 @@ def load():
     lib.pf_plan_geometry.argtypes = [P, P, P, P]
     lib.pf_plan_selfcell.argtypes = [P, P]
     lib.pf_plan_schedule.argtypes = [P, P]
+    lib.pf_plan_set_schedule.argtypes = [P, P]
     lib.pf_plan_tables.argtypes = [P, P]
     for f in ("pf_kernels_build", "pf_forces", "pf_forces_backward", "pf_forces_batched",
               "pf_forces_timed",
-              "pf_plan_geometry", "pf_plan_selfcell", "pf_plan_schedule", "pf_plan_tables"):
+              "pf_plan_geometry", "pf_plan_selfcell", "pf_plan_schedule", "pf_plan_set_schedule",
+              "pf_plan_tables"):
         getattr(lib, f).restype = I
     lib.pf_plan_destroy.argtypes = [P]
     lib.pf_plan_destroy.restype = None
@@ -194,6 +197,12 @@ def pf_plan_schedule(plan: int):
     out = np.zeros(8, dtype=np.int32)
     _check(load().pf_plan_schedule(plan, out.ctypes.data))
     return tuple(int(v) for v in out)
+
+
+def pf_plan_set_schedule(plan: int, shapes) -> None:
+    """Set the eight launch-shape numbers (layout of pf_plan_schedule)."""
+    a = np.ascontiguousarray(np.asarray(shapes, dtype=np.int32).reshape(8))
+    _check(load().pf_plan_set_schedule(plan, a.ctypes.data))
 
 
 def pf_plan_tables(plan: int, n_r: int, n_phi: int):
@@ -310,6 +319,9 @@ class Plan:
 
     def schedule(self):
         return pf_plan_schedule(self.handle)
+
+    def set_schedule(self, shapes):
+        pf_plan_set_schedule(self.handle, shapes)
 
     def _check_field(self, t, name):
         import torch

@@ -369,6 +369,36 @@ int pf_plan_schedule(pf_plan h, int out[8]) {
     return PF_OK;
 }
 
+int pf_plan_set_schedule(pf_plan h, const int in[8]) {
+    pf::clear_error();
+    if (!h || !in) {
+        pf::set_error("null argument");
+        return PF_EINVAL;
+    }
+    if (!h->p.built) {
+        pf::set_error("plan not built");
+        return PF_ESTATE;
+    }
+    pf::Plan &p = h->p;
+    const bool f64 = p.opts.dtype == PF_F64;
+    const pf::Shape r1{in[0], in[1]}, r2{in[2], in[3]}, c{in[4], in[5]}, a{in[6], in[7]};
+    if (!pf::valid_shape_rows(p.M, r1, f64) || !pf::valid_shape_rows(p.M, r2, f64)) {
+        pf::set_error("row shapes (%d, %d), (%d, %d) do not fit %d-point row transforms", r1.E,
+                      r1.G, r2.E, r2.G, p.M);
+        return PF_EINVAL;
+    }
+    if (!pf::valid_shape_cols(p.L, c, f64) || !pf::valid_shape_cols(p.L, a, f64)) {
+        pf::set_error("column shapes (%d, %d), (%d, %d) do not fit %d-point column transforms",
+                      c.E, c.G, a.E, a.G, p.L);
+        return PF_EINVAL;
+    }
+    p.sched.rows = r1;
+    p.sched.rows2 = r2;
+    p.sched.cols = c;
+    p.sched.cols_adj = a;
+    return PF_OK;
+}
+
 int pf_plan_tables(pf_plan h, double *dst) {
     pf::clear_error();
     if (!h || !dst) {

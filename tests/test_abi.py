@@ -67,6 +67,9 @@ def test_unbuilt_plan_and_null_arguments_are_refused():
         out8 = (ctypes.c_int * 8)()
         assert lib.pf_plan_schedule(h, out8) == pf.PF_ESTATE
         assert lib.pf_plan_schedule(h, None) == pf.PF_EINVAL
+        assert lib.pf_plan_set_schedule(h, out8) == pf.PF_ESTATE
+        assert lib.pf_plan_set_schedule(h, None) == pf.PF_EINVAL
+        assert lib.pf_plan_set_schedule(None, out8) == pf.PF_EINVAL
         ms3 = (ctypes.c_float * 3)()
         assert lib.pf_forces_timed(h, 0, 8, None, 8, 8, 1, None, ms3) == pf.PF_ESTATE
         # null pointers
