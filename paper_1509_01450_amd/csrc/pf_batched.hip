@@ -83,13 +83,35 @@ __global__ __launch_bounds__(kGroupThreads) void k_group_rows(const GDisk<T> *__
     }
 }
 
+// Column sizes of the grouped pass B whose columns have at least 64 threads
+// prefetch their radial spectrum pairs into an LDS array of their own while
+// the column is transformed (as the single-plan kernels); this is the
+// largest G spec_prefetch_len<L, E>() over those sizes.
+template <typename T>
+constexpr int group_prefetch_len() {
+    constexpr int E = col_e<T>();
+    int n = 64;
+    for (int L = 128; L <= 4096; L *= 2) {
+        const int th = L / E;
+        if (th >= 64 && th <= kGroupThreads) {
+            const int lp = ((L / 2 + 1) + th - 1) / th * th;
+            const int g = kGroupThreads / th;
+            n = g * lp > n ? g * lp : n;
+        }
+    }
+    return n;
+}
+
 template <typename T, int L>
-__device__ __forceinline__ void group_cols(int unit, const GDisk<T> &d, cx<T> *buf) {
+__device__ __forceinline__ void group_cols(int unit, const GDisk<T> &d, cx<T> *buf,
+                                           cx2<T> *spl) {
     constexpr int E = col_e<T>();
     if constexpr (L / E <= kGroupThreads) {
         constexpr int G = kGroupThreads / (L / E);
-        body_cols_fwd<T, L, E>(unit, G, buf, d.S, d.Z, d.spec, d.H, d.n_r, d.n_r, d.ldspec, d.ca,
-                               d.c0, d.cn, d.twL);
+        constexpr bool PF = L / E >= 64;
+        static_assert(!PF || G * spec_prefetch_len<L, E>() <= group_prefetch_len<T>(), "LDS");
+        body_cols_fwd<T, L, E, PF>(unit, G, buf, d.S, d.Z, d.spec, d.H, d.n_r, d.n_r, d.ldspec,
+                                   d.ca, d.c0, d.cn, d.twL, spl);
     }
 }
 
@@ -99,15 +121,16 @@ template <typename T>
 __global__ __launch_bounds__(kGroupThreads) __attribute__((amdgpu_waves_per_eu(2)))
 void k_group_cols(const GDisk<T> *__restrict__ disks, const int *__restrict__ bdisk) {
     __shared__ cx<T> buf[padded_len(kGroupThreads * col_e<T>())];
+    __shared__ cx2<T> spl[group_prefetch_len<T>()];
     const GDisk<T> &d = disks[bdisk[blockIdx.x]];
     const int unit = blockIdx.x - d.base[1];
     switch (d.L) {
-        case 128: group_cols<T, 128>(unit, d, buf); break;
-        case 256: group_cols<T, 256>(unit, d, buf); break;
-        case 512: group_cols<T, 512>(unit, d, buf); break;
-        case 1024: group_cols<T, 1024>(unit, d, buf); break;
-        case 2048: group_cols<T, 2048>(unit, d, buf); break;
-        case 4096: group_cols<T, 4096>(unit, d, buf); break;
+        case 128: group_cols<T, 128>(unit, d, buf, spl); break;
+        case 256: group_cols<T, 256>(unit, d, buf, spl); break;
+        case 512: group_cols<T, 512>(unit, d, buf, spl); break;
+        case 1024: group_cols<T, 1024>(unit, d, buf, spl); break;
+        case 2048: group_cols<T, 2048>(unit, d, buf, spl); break;
+        case 4096: group_cols<T, 4096>(unit, d, buf, spl); break;
     }
 }
 
