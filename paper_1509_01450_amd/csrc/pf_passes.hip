@@ -32,6 +32,11 @@ __global__ __launch_bounds__(512) void k_rows_c2r(const cx<T> *__restrict__ in, 
                               reinterpret_cast<cx<T> *>(smem_raw), in, n_rows, out0, out1, twN);
 }
 
+// Forward column pass for any G, with one dynamic LDS array: used where the
+// static-LDS kernel below has no instance (columns of fewer than 64
+// threads, more than four columns per workgroup, or static LDS beyond
+// 144 KB).  In FP32 it prefetches the radial pairs into the same array, so
+// the compiler waits for them before the first exchange.
 template <typename T, int L, int E>
 __global__ __launch_bounds__(512) void k_cols_fwd(const cx<T> *__restrict__ S,
                                                   cx2<T> *__restrict__ Z,
