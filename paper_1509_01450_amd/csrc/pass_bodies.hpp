@@ -306,10 +306,11 @@ __device__ __forceinline__ cx<T> unpack_odd(cx<T> p, cx<T> m) {
 // registers beside the transform data: 64 / E in FP32 (E <= 8: all E) for
 // the forward pass, half that for the transpose pass when it loads all
 // four values from global memory (it holds two input channels and spills
-// otherwise at E = 16), one in FP64.
-template <typename T, int E, bool ADJ = false>
+// otherwise at E = 16); in FP64 one point, two when the radial pairs come
+// from LDS (PF).
+template <typename T, int E, bool ADJ = false, bool PF = false>
 __host__ __device__ constexpr int mac_batch() {
-    return sizeof(T) == 8 ? 1 : (E < 8 ? E : (ADJ ? 32 : 64) / E);
+    return sizeof(T) == 8 ? (PF ? 2 : 1) : (E < 8 ? E : (ADJ && !PF ? 32 : 64) / E);
 }
 
 // ---------------------------------------------------------------------------
@@ -442,7 +443,7 @@ __device__ __forceinline__ void body_cols_fwd(int unit, int G, cx<T> *__restrict
         ph0 = slope_phasors(slope_fix_part(a, false), wt, wnt);
         phM = slope_phasors(slope_fix_part(a, true), wt, wnt);
     }
-    constexpr int CH = mac_batch<T, E>();
+    constexpr int CH = mac_batch<T, E, false, PF>();
     const bool t0 = t == 0;
     cx<T> y[2][E];   // y[0] -> Zr, y[1] -> Zp
 #pragma unroll
@@ -607,7 +608,7 @@ __device__ __forceinline__ void body_cols_adj(int unit, int G, cx<T> *__restrict
     cx<T> w[4] = {{T(0), T(0)}, {T(0), T(0)}, {T(0), T(0)}, {T(0), T(0)}};
     // with the radial pairs in LDS only the azimuthal ones take registers:
     // the forward pass's batch
-    constexpr int CH = mac_batch<T, E, !PF>();
+    constexpr int CH = mac_batch<T, E, true, PF>();
     const bool t0 = t == 0;
 #pragma unroll
     for (int cb = 0; cb < E; cb += CH) {
