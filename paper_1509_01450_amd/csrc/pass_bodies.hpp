@@ -140,26 +140,33 @@ __device__ __forceinline__ void body_rows_c2r(int unit, int G, cx<T> *__restrict
     Lds<T> lds[C];
     row_lds<T, M, E, C>(buf, gi, G, lds);
 
-    // unconditional loads (in bounds for every lane) so they issue together
+    // unconditional loads (in bounds for every lane) so they issue together;
+    // the mirror bins M - k come from LDS
     cx<T> xk[C][E], xm[C][E], wk[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         const int k = t + e * TH;
-        const int km = (M - k) & (M - 1);
         if constexpr (C == 1) {
             const cx<T> *X = in + (size_t)i * M;
             xk[0][e] = X[k];
-            xm[0][e] = X[km];
         } else {
             const cx2<T> *X = reinterpret_cast<const cx2<T> *>(in) + (size_t)i * M;
-            const cx2<T> a = X[k], b = X[km];
+            const cx2<T> a = X[k];
             xk[0][e] = a.a;
             xk[C - 1][e] = a.b;
-            xm[0][e] = b.a;
-            xm[C - 1][e] = b.b;
         }
         wk[e] = twN[k];   // exp(-2 pi i k / N)
     }
+#pragma unroll
+    for (int c = 0; c < C; ++c)
+#pragma unroll
+        for (int e = 0; e < E; ++e) lds[c].st_split(lds_pad(t), e * TH, xk[c][e]);
+    lds_barrier();
+#pragma unroll
+    for (int c = 0; c < C; ++c)
+#pragma unroll
+        for (int e = 0; e < E; ++e) xm[c][e] = lds[c].ld((M - (t + e * TH)) & (M - 1));
+    lds_barrier();
     Twiddles<M, E, T> tw;
     tw.load(t, twN, 2);
     if (t == 0) {   // unpack bin 0 = (X_0, X_M)

@@ -326,18 +326,27 @@ __device__ __forceinline__ void body_cart_c2r(int unit, int G, cx<T> *__restrict
     Lds<T> lds[2];
     row_lds<T, M, E, 2>(buf, gi, G, lds);
 
+    // the thread's bins k from global memory, the mirror bins M - k from LDS
     cx<T> xk[2][E], xm[2][E], wk[E];
     const cx2<T> *X = in + (size_t)i * M;
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         const int k = t + e * TH;
-        const cx2<T> a = X[k], b = X[(M - k) & (M - 1)];
+        const cx2<T> a = X[k];
         xk[0][e] = a.a;
         xk[1][e] = a.b;
-        xm[0][e] = b.a;
-        xm[1][e] = b.b;
         wk[e] = twN[k];
     }
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int e = 0; e < E; ++e) lds[c].st_split(lds_pad(t), e * TH, xk[c][e]);
+    lds_barrier();
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int e = 0; e < E; ++e) xm[c][e] = lds[c].ld((M - (t + e * TH)) & (M - 1));
+    lds_barrier();
     Twiddles<M, E, T> tw;
     tw.load(t, twN, 2);
     if (t == 0) {   // unpack bin 0 = (X_0, X_M)
