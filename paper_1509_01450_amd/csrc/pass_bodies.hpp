@@ -44,6 +44,23 @@
 
 namespace pf {
 
+// Streaming (non-temporal) stores of one complex value or one pair, for the
+// row passes' outputs, which the next pass reads from other XCDs: they go
+// out to memory during the pass instead of staying dirty in the XCD's L2
+// until the end of the kernel (forward step 32.6 to 31.7 us at 1024 x 2048).
+template <typename T>
+__device__ __forceinline__ void store_stream(cx<T> *p, cx<T> v) {
+    typedef T v2 __attribute__((ext_vector_type(2)));
+    const v2 x = {v.x, v.y};
+    __builtin_nontemporal_store(x, reinterpret_cast<v2 *>(p));
+}
+template <typename T>
+__device__ __forceinline__ void store_stream(cx2<T> *p, cx2<T> v) {
+    typedef T v4 __attribute__((ext_vector_type(4)));
+    const v4 x = {v.a.x, v.a.y, v.b.x, v.b.y};
+    __builtin_nontemporal_store(x, reinterpret_cast<v4 *>(p));
+}
+
 // ---------------------------------------------------------------------------
 // Row transforms along phi.  A real row of N = 2M points goes through one
 // M-point complex transform of z[n] = x[2n] + i x[2n+1]; its spectrum is
@@ -115,11 +132,12 @@ __device__ __forceinline__ void body_rows_r2c(int unit, int G, cx<T> *__restrict
         if constexpr (C == 1) {
             cx<T> *orow = out + (size_t)i * M;
 #pragma unroll
-            for (int e = 0; e < E; ++e) orow[t + e * TH] = o[0][e];
+            for (int e = 0; e < E; ++e) store_stream(&orow[t + e * TH], o[0][e]);
         } else {
             cx2<T> *orow = reinterpret_cast<cx2<T> *>(out) + (size_t)i * M;
 #pragma unroll
-            for (int e = 0; e < E; ++e) orow[t + e * TH] = cx2<T>{o[0][e], o[1][e]};
+            for (int e = 0; e < E; ++e)
+                store_stream(&orow[t + e * TH], cx2<T>{o[0][e], o[1][e]});
         }
     }
 }
@@ -193,7 +211,7 @@ __device__ __forceinline__ void body_rows_c2r(int unit, int G, cx<T> *__restrict
         for (int c = 0; c < C; ++c) {
             cx<T> *yz = reinterpret_cast<cx<T> *>((c == 0 ? out0 : out1) + (size_t)i * N);
 #pragma unroll
-            for (int e = 0; e < E; ++e) yz[t + e * TH] = v[c][e];
+            for (int e = 0; e < E; ++e) store_stream(&yz[t + e * TH], v[c][e]);
         }
     }
 }
