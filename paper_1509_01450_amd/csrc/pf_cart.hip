@@ -308,7 +308,7 @@ __device__ __forceinline__ void body_cart_rows(int unit, int G, cx<T> *__restric
     if (active) {
         cx2<T> *orow = out + (size_t)i * M;
 #pragma unroll
-        for (int e = 0; e < E; ++e) orow[t + e * TH] = cx2<T>{o[0][e], o[1][e]};
+        for (int e = 0; e < E; ++e) store_stream(&orow[t + e * TH], cx2<T>{o[0][e], o[1][e]});
     }
 }
 
@@ -376,8 +376,9 @@ __device__ __forceinline__ void body_cart_c2r(int unit, int G, cx<T> *__restrict
 #pragma unroll
             for (int e = 0; e < E / 2; ++e) {
                 const int j = 2 * (t + e * TH);
-                if (j < n_y) o[j] = v[c][e].x;
-                if (j + 1 < n_y) o[j + 1] = v[c][e].y;
+                // streaming stores, as in the polar row passes
+                if (j < n_y) __builtin_nontemporal_store(v[c][e].x, &o[j]);
+                if (j + 1 < n_y) __builtin_nontemporal_store(v[c][e].y, &o[j + 1]);
             }
         }
     }
