@@ -14,9 +14,10 @@ kernel (the fused column pass) and the FP64 CPU oracle timed on the host's
 cores.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
-                       [--no-batched] [--forward-only] [--copy-reference]
+                       [--no-batched] [--forward-only [--transpose]] [--copy-reference]
 --forward-only runs only the FP32 forward (headline, pass times, roofline),
-for profiler runs; --copy-reference adds five 64 MiB device-to-device copies
+for profiler runs, and with --transpose the FP32 transpose of the same plan
+as well; --copy-reference adds five 64 MiB device-to-device copies
 at the end, the known-size reference that calibrates the FETCH_SIZE and
 WRITE_SIZE counters.  Prints one JSON line on stdout.
 """
@@ -189,6 +190,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--forward-only", action="store_true")
+    ap.add_argument("--transpose", action="store_true")
     ap.add_argument("--copy-reference", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -255,6 +257,14 @@ def main():
         "table_build_s": {"fp32": build32},
     }
     if args.forward_only:
+        if args.transpose:
+            log("fp32 transpose")
+            gr32, gp32 = torch.randn_like(s32), torch.randn_like(s32)
+            gs32 = torch.empty_like(s32)
+            msb32 = time_calls(torch, lambda: p32.backward(gr32, gp32, gs32), K, W)
+            passesb32 = pass_times(p32, gr32, gp32, backward=True)
+            out["detail"]["backward"] = {"fp32_ms": msb32, "fp32_cells_per_s": cells / (msb32 * 1e-3),
+                                         "fp32_pass_ms": passesb32}
         finish(torch, out, args)
         return 0
 
