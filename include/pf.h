@@ -160,6 +160,11 @@ pf_plan pf_plan_create_patches(int n_src, int src_row0, int n_dst, int n_phi, do
 /* Build the kernel tables and their spectra on the current device
  * (Eq. 30-33, 41-46, A22-A35): one-time work, FP64 throughout, enqueued on
  * `stream` and synchronised before returning.  opts == NULL means defaults.
+ * Single-grid plans then get launch shapes tuned on the device (unless
+ * PF_AUTOTUNE=0; cached in PF_AUTOTUNE_CACHE, default
+ * ~/.cache/pf/autotune.json).  A failed HIP call, in the build or in the
+ * tuning, returns PF_EHIP (PF_ENOMEM for the workspace) with the message in
+ * pf_last_error and leaves the plan unbuilt; PF_ENODEV without a device.
  * May be called again to rebuild with other options.                       */
 int pf_kernels_build(pf_plan plan, const pf_build_opts *opts, void *stream);
 
@@ -237,9 +242,12 @@ int pf_plan_schedule(pf_plan plan, int out[8]);
  * reproducible shapes without tuning, or to run a given kernel variant).
  * Each shape must fit its transform: points per thread 4, 8 or 16 for the
  * rows and 8 or 16 for the columns, at most the transform length, at most
- * 512 threads per workgroup, and the workgroup's LDS within 144 KB;
- * otherwise PF_EINVAL and the plan keeps its shapes.  PF_ESTATE if the plan
- * is not built.  Not in the paper: a tuning control.                      */
+ * 512 threads per workgroup, and the workgroup's LDS within 144 KB; a
+ * column shape also needs a power-of-two number of columns per workgroup
+ * and a workgroup of whole 64-lane waves.  Otherwise PF_EINVAL (checked
+ * first, against the plan's current precision, built or not) and the plan
+ * keeps its shapes.  PF_ESTATE if the shapes fit but the plan is not built.
+ * Not in the paper: a tuning control.                                      */
 int pf_plan_set_schedule(pf_plan plan, const int in[8]);
 
 /* Copy the six FP64 kernel tables to host memory `dst` (plan built with

@@ -334,7 +334,12 @@ class Plan:
     def forces(self, sigma, out=None):
         import torch
         self._check_field(sigma, "sigma")
-        fr, fp = out if out is not None else (torch.empty_like(sigma), torch.empty_like(sigma))
+        if out is None:
+            fr, fp = torch.empty_like(sigma), torch.empty_like(sigma)
+        else:
+            fr, fp = out
+            self._check_field(fr, "out[0]")
+            self._check_field(fp, "out[1]")
         pf_forces(self.handle, sigma.data_ptr(), fr.data_ptr(), fp.data_ptr(), _stream())
         return fr, fp
 
@@ -343,6 +348,8 @@ class Plan:
         self._check_field(g_fr, "g_fr")
         self._check_field(g_fphi, "g_fphi")
         gs = out if out is not None else torch.empty_like(g_fr)
+        if out is not None:
+            self._check_field(gs, "out")
         pf_forces_backward(self.handle, g_fr.data_ptr(), g_fphi.data_ptr(), gs.data_ptr(),
                            _stream())
         return gs
@@ -352,7 +359,9 @@ class Plan:
         (a = sigma) or its transpose (a, b = g_fr, g_fphi), each pass
         launched `reps` times back to back."""
         import torch
+        self._check_field(a, "a")
         if backward:
+            self._check_field(b, "b")
             out = torch.empty_like(a)
             return pf_forces_timed(self.handle, True, a.data_ptr(), b.data_ptr(),
                                    out.data_ptr(), 0, reps, _stream())
@@ -375,10 +384,16 @@ class Plan:
 def forces_batched(plans, sigmas, outs=None):
     """Forward map of many disks (three launches covering every disk)."""
     import torch
-    if outs is None:
-        outs = [(torch.empty_like(s), torch.empty_like(s)) for s in sigmas]
+    if len(plans) != len(sigmas) or (outs is not None and len(outs) != len(plans)):
+        raise TypeError("one sigma (and one output pair) per plan")
     for p, s in zip(plans, sigmas):
         p._check_field(s, "sigma")
+    if outs is None:
+        outs = [(torch.empty_like(s), torch.empty_like(s)) for s in sigmas]
+    else:
+        for p, o in zip(plans, outs):
+            p._check_field(o[0], "outs[k][0]")
+            p._check_field(o[1], "outs[k][1]")
     pf_forces_batched([p.handle for p in plans], [s.data_ptr() for s in sigmas],
                       [o[0].data_ptr() for o in outs], [o[1].data_ptr() for o in outs],
                       _stream())
@@ -460,7 +475,12 @@ class CartPlan:
     def forces(self, sigma, out=None):
         import torch
         self._check_field(sigma, "sigma")
-        fx, fy = out if out is not None else (torch.empty_like(sigma), torch.empty_like(sigma))
+        if out is None:
+            fx, fy = torch.empty_like(sigma), torch.empty_like(sigma)
+        else:
+            fx, fy = out
+            self._check_field(fx, "out[0]")
+            self._check_field(fy, "out[1]")
         pf_cart_forces(self.handle, sigma.data_ptr(), fx.data_ptr(), fy.data_ptr(), _stream())
         return fx, fy
 
@@ -517,15 +537,19 @@ class PatchPlan(Plan):
                 or not sigma_src.is_contiguous()):
             raise TypeError("sigma_src must be a contiguous %s CUDA tensor of shape %s"
                             % (self.torch_dtype, self.src_shape))
-        if sigma_wedge is not None and (tuple(sigma_wedge.shape) != (self.n_phi,)
+        if sigma_wedge is not None and (not isinstance(sigma_wedge, torch.Tensor)
+                                        or tuple(sigma_wedge.shape) != (self.n_phi,)
                                         or sigma_wedge.dtype != self.torch_dtype
-                                        or not sigma_wedge.is_cuda):
-            raise TypeError("sigma_wedge must be a %s CUDA tensor of shape (%d,)"
+                                        or not sigma_wedge.is_cuda
+                                        or not sigma_wedge.is_contiguous()):
+            raise TypeError("sigma_wedge must be a contiguous %s CUDA tensor of shape (%d,)"
                             % (self.torch_dtype, self.n_phi))
         if out is None:
             out = (torch.empty(self.shape, dtype=self.torch_dtype, device=sigma_src.device),
                    torch.empty(self.shape, dtype=self.torch_dtype, device=sigma_src.device))
         fr, fp = out
+        self._check_field(fr, "out[0]")   # destination grid: n_dst x n_phi
+        self._check_field(fp, "out[1]")
         pf_forces_patches(self.handle, sigma_src.data_ptr(),
                           sigma_wedge.data_ptr() if sigma_wedge is not None else 0,
                           fr.data_ptr(), fp.data_ptr(), _stream())

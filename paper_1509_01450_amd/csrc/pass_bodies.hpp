@@ -377,7 +377,9 @@ __device__ __forceinline__ void prefetch_radial_spectra(int unit, int G, int H, 
     constexpr int NCH = LP * U / 64;                // 64-lane chunks per column
     constexpr int LAST = (L / 2 + 1) * U - 1;       // last unit of a column's data
     const int lane = (int)(threadIdx.x & 63), wv = (int)(threadIdx.x >> 6);
-    const int nw = (int)(blockDim.x >> 6);
+    // whole waves (the shape check requires it); at least one, so the
+    // wave-uniform loop below always advances
+    const int nw = max(1, (int)(blockDim.x >> 6));
     // raw buffer over the radial half (stride 0, byte offsets); the last
     // word is the data-format field every gfx9 raw buffer access uses
     const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(

@@ -375,11 +375,9 @@ int pf_plan_set_schedule(pf_plan h, const int in[8]) {
         pf::set_error("null argument");
         return PF_EINVAL;
     }
-    if (!h->p.built) {
-        pf::set_error("plan not built");
-        return PF_ESTATE;
-    }
     pf::Plan &p = h->p;
+    // the shapes are checked first (against the plan's current precision),
+    // so a bad shape is refused whether or not the plan is built
     const bool f64 = p.opts.dtype == PF_F64;
     const pf::Shape r1{in[0], in[1]}, r2{in[2], in[3]}, c{in[4], in[5]}, a{in[6], in[7]};
     if (!pf::valid_shape_rows(p.M, r1, f64) || !pf::valid_shape_rows(p.M, r2, f64)) {
@@ -391,6 +389,10 @@ int pf_plan_set_schedule(pf_plan h, const int in[8]) {
         pf::set_error("column shapes (%d, %d), (%d, %d) do not fit %d-point column transforms",
                       c.E, c.G, a.E, a.G, p.L);
         return PF_EINVAL;
+    }
+    if (!p.built) {
+        pf::set_error("plan not built");
+        return PF_ESTATE;
     }
     p.sched.rows = r1;
     p.sched.rows2 = r2;
@@ -493,7 +495,11 @@ int pf_kernels_build(pf_plan h, const pf_build_opts *opts, void *stream) {
         pf::free_plan_device(&p);
         return rc;
     }
-    if (!p.patch) pf::autotune_plan(p, st);
+    if (!p.patch) rc = pf::autotune_plan(p, st);
+    if (rc) {
+        pf::free_plan_device(&p);
+        return rc;
+    }
     p.built = true;
     return PF_OK;
 }

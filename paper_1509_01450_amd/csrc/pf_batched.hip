@@ -382,29 +382,47 @@ std::string arch_name() {
     return a.substr(0, a.find(':'));
 }
 
+// Mean duration (ms) of one launch: the best of three runs of 20
+// back-to-back launches after three warm-up launches (candidates a few
+// percent apart are told apart reliably).  A failed launch or event call
+// returns its status; *ms is then untouched.
 template <class F>
-float time_ms(F launch, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
-    for (int i = 0; i < 3; ++i)
-        if (launch()) return -1.f;
-    // the best of three runs of 20 back-to-back launches: candidates a few
-    // percent apart are told apart reliably
+int time_ms(F launch, hipStream_t st, hipEvent_t e0, hipEvent_t e1, float *ms) {
+    for (int i = 0; i < 3; ++i) {
+        const int rc = launch();
+        if (rc) return rc;
+    }
     const int reps = 20;
     float best = -1.f;
     for (int trial = 0; trial < 3; ++trial) {
-        if (hipEventRecord(e0, st) != hipSuccess) return -1.f;
-        for (int i = 0; i < reps; ++i)
-            if (launch()) return -1.f;
-        if (hipEventRecord(e1, st) != hipSuccess) return -1.f;
-        if (hipEventSynchronize(e1) != hipSuccess) return -1.f;
-        float ms = 0;
-        if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) return -1.f;
-        if (best < 0.f || ms < best) best = ms;
+        PF_HIP(hipEventRecord(e0, st));
+        for (int i = 0; i < reps; ++i) {
+            const int rc = launch();
+            if (rc) return rc;
+        }
+        PF_HIP(hipEventRecord(e1, st));
+        PF_HIP(hipEventSynchronize(e1));
+        float t = 0;
+        PF_HIP(hipEventElapsedTime(&t, e0, e1));
+        if (best < 0.f || t < best) best = t;
     }
-    return best / reps;
+    *ms = best / reps;
+    return PF_OK;
 }
 
+// Device resources of one tuning run, released on every return path.
+struct TuneScratch {
+    void *x = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    ~TuneScratch() {
+        if (x) (void)hipFree(x);
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+    }
+};
+
 template <typename T>
-void tune_t(Plan &p, hipStream_t st) {
+int tune_t(Plan &p, hipStream_t st) {
     using C = cx<T>;
     const bool f64 = sizeof(T) == 8;
     const std::string pre = arch_name() + (f64 ? "|f64|" : "|f32|");
@@ -428,19 +446,20 @@ void tune_t(Plan &p, hipStream_t st) {
             p.sched.rows2 = a2->second;
             p.sched.cols = b->second;
             p.sched.cols_adj = c->second;
-            return;
+            return PF_OK;
         }
     }
-    T *x = nullptr;
-    if (hipMalloc(&x, sizeof(T) * 3 * (size_t)p.n_r * p.n_phi) != hipSuccess) return;
-    (void)hipMemsetAsync(x, 0, sizeof(T) * 3 * (size_t)p.n_r * p.n_phi, st);
+    TuneScratch ts;
+    const size_t xbytes = sizeof(T) * 3 * (size_t)p.n_r * p.n_phi;
+    PF_HIP(hipMalloc(&ts.x, xbytes));
+    T *x = (T *)ts.x;
+    PF_HIP(hipMemsetAsync(x, 0, xbytes, st));
     C *S = (C *)p.ws;                        // forward: S, then (Zr, Zp) pairs
     C *Z = S + (size_t)p.n_r * p.H;
     C *D = S + 2 * (size_t)p.n_r * p.H;      // transpose: (Vr, Vp) pairs at S, then D
-    (void)hipMemsetAsync(p.ws, 0, sizeof(C) * 3 * (size_t)p.n_r * p.H, st);
-    hipEvent_t e0, e1;
-    (void)hipEventCreate(&e0);
-    (void)hipEventCreate(&e1);
+    PF_HIP(hipMemsetAsync(p.ws, 0, sizeof(C) * 3 * (size_t)p.n_r * p.H, st));
+    PF_HIP(hipEventCreate(&ts.e0));
+    PF_HIP(hipEventCreate(&ts.e1));
     // rows: the one-channel forward R2C and the two-channel inverse C2R of
     // n_r rows, each on its own (they stand for the one- and two-channel row
     // transforms of both directions)
@@ -451,83 +470,72 @@ void tune_t(Plan &p, hipStream_t st) {
     // lower clocks and lost to later ones they beat in steady state.  Each
     // candidate set is then swept twice, keeping every candidate's best time.
     for (int i = 0; i < 100; ++i) {
-        if (launch_rows_c2r<T>(p, Z, p.n_r, x + (size_t)p.n_r * p.n_phi,
-                               x + 2 * (size_t)p.n_r * p.n_phi, (const C *)p.twN, p.sched.rows2,
-                               st))
-            break;
-        if (launch_cols_fwd<T>(p, S, Z, (const C *)p.spec, (const C *)p.twL, p.sched.cols, st))
-            break;
+        int rc = launch_rows_c2r<T>(p, Z, p.n_r, x + (size_t)p.n_r * p.n_phi,
+                                    x + 2 * (size_t)p.n_r * p.n_phi, (const C *)p.twN,
+                                    p.sched.rows2, st);
+        if (!rc)
+            rc = launch_cols_fwd<T>(p, S, Z, (const C *)p.spec, (const C *)p.twL, p.sched.cols,
+                                    st);
+        if (rc) return rc;
     }
-    (void)hipStreamSynchronize(st);
-    float tbest = 1e30f, tbest2 = 1e30f;
+    PF_HIP(hipStreamSynchronize(st));
+    float tbest = 1e30f, tbest2 = 1e30f, t = 0.f;
+    int rc = PF_OK;
     for (int sweep = 0; sweep < 2; ++sweep)
-    for (int E : {4, 8, 16})
-        for (int thr : {64, 128, 256, 512}) {
-            if (E > p.M || (p.M / E) > thr) continue;
-            Shape s{E, thr / (p.M / E)};
-            if (!valid_shape_rows(p.M, s, f64)) continue;
-            float t = time_ms(
-                [&]() {
-                    return launch_rows_r2c<T>(p, x, nullptr, p.n_r, S, (const C *)p.twN, s, st);
-                },
-                st, e0, e1);
-            if (t > 0 && t < tbest) {
-                tbest = t;
-                best_r = s;
+        for (int E : {4, 8, 16})
+            for (int thr : {64, 128, 256, 512}) {
+                if (E > p.M || (p.M / E) > thr) continue;
+                Shape s{E, thr / (p.M / E)};
+                if (!valid_shape_rows(p.M, s, f64)) continue;
+                rc = time_ms(
+                    [&]() {
+                        return launch_rows_r2c<T>(p, x, nullptr, p.n_r, S, (const C *)p.twN, s,
+                                                  st);
+                    },
+                    st, ts.e0, ts.e1, &t);
+                if (rc) return rc;
+                if (t < tbest) {
+                    tbest = t;
+                    best_r = s;
+                }
+                rc = time_ms(
+                    [&]() {
+                        return launch_rows_c2r<T>(p, Z, p.n_r, x + (size_t)p.n_r * p.n_phi,
+                                                  x + 2 * (size_t)p.n_r * p.n_phi,
+                                                  (const C *)p.twN, s, st);
+                    },
+                    st, ts.e0, ts.e1, &t);
+                if (rc) return rc;
+                if (t < tbest2) {
+                    tbest2 = t;
+                    best_r2 = s;
+                }
             }
-            t = time_ms(
-                [&]() {
-                    return launch_rows_c2r<T>(p, Z, p.n_r, x + (size_t)p.n_r * p.n_phi,
-                                              x + 2 * (size_t)p.n_r * p.n_phi, (const C *)p.twN,
-                                              s, st);
-                },
-                st, e0, e1);
-            if (t > 0 && t < tbest2) {
-                tbest2 = t;
-                best_r2 = s;
-            }
-        }
-    tbest = 1e30f;
-    for (int sweep = 0; sweep < 2; ++sweep)
-    for (int E : {8, 16})
-        for (int thr : {64, 128, 256, 512}) {
-            if (E > p.L || (p.L / E) > thr) continue;
-            Shape s{E, thr / (p.L / E)};
-            if (!valid_shape_cols(p.L, s, f64)) continue;
-            float t = time_ms(
-                [&]() {
-                    return launch_cols_fwd<T>(p, S, Z, (const C *)p.spec, (const C *)p.twL, s,
-                                              st);
-                },
-                st, e0, e1);
-            if (t > 0 && t < tbest) {
-                tbest = t;
-                best_c = s;
-            }
-        }
-    tbest = 1e30f;
-    for (int sweep = 0; sweep < 2; ++sweep)
-    for (int E : {8, 16})
-        for (int thr : {64, 128, 256, 512}) {
-            if (E > p.L || (p.L / E) > thr) continue;
-            Shape s{E, thr / (p.L / E)};
-            if (!valid_shape_cols(p.L, s, f64)) continue;
-            float t = time_ms(
-                [&]() {
-                    return launch_cols_adj<T>(p, S, D, (const C *)p.spec, (const C *)p.twL, s,
-                                              st);
-                },
-                st, e0, e1);
-            if (t > 0 && t < tbest) {
-                tbest = t;
-                best_a = s;
-            }
-        }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    (void)hipStreamSynchronize(st);
-    (void)hipFree(x);
-    clear_error();
+    for (int adj = 0; adj < 2; ++adj) {
+        tbest = 1e30f;
+        Shape &best = adj ? best_a : best_c;
+        for (int sweep = 0; sweep < 2; ++sweep)
+            for (int E : {8, 16})
+                for (int thr : {64, 128, 256, 512}) {
+                    if (E > p.L || (p.L / E) > thr) continue;
+                    Shape s{E, thr / (p.L / E)};
+                    if (!valid_shape_cols(p.L, s, f64)) continue;
+                    rc = time_ms(
+                        [&]() {
+                            return adj ? launch_cols_adj<T>(p, S, D, (const C *)p.spec,
+                                                            (const C *)p.twL, s, st)
+                                       : launch_cols_fwd<T>(p, S, Z, (const C *)p.spec,
+                                                            (const C *)p.twL, s, st);
+                        },
+                        st, ts.e0, ts.e1, &t);
+                    if (rc) return rc;
+                    if (t < tbest) {
+                        tbest = t;
+                        best = s;
+                    }
+                }
+    }
+    PF_HIP(hipStreamSynchronize(st));
     p.sched.rows = best_r;
     p.sched.rows2 = best_r2;
     p.sched.cols = best_c;
@@ -538,17 +546,15 @@ void tune_t(Plan &p, hipStream_t st) {
     g_tune[kcol] = best_c;
     g_tune[kadj] = best_a;
     save_cache();
+    return PF_OK;
 }
 
 }  // namespace
 
-void autotune_plan(Plan &p, hipStream_t st) {
+int autotune_plan(Plan &p, hipStream_t st) {
     const char *e = getenv("PF_AUTOTUNE");
-    if (e && e[0] == '0') return;
-    if (p.opts.dtype == PF_F64)
-        tune_t<double>(p, st);
-    else
-        tune_t<float>(p, st);
+    if (e && e[0] == '0') return PF_OK;
+    return p.opts.dtype == PF_F64 ? tune_t<double>(p, st) : tune_t<float>(p, st);
 }
 
 }  // namespace pf

@@ -13,6 +13,8 @@ int batched_forces(const std::vector<const Plan *> &plans, const void *const *si
 // Drop cached batch state that refers to plan `uid`.
 void batched_forget(int64_t uid);
 // Choose launch shapes for the plan's sizes (timed on the device, cached).
-void autotune_plan(Plan &p, hipStream_t st);
+// A failed HIP call or launch returns its status (message in pf_last_error)
+// and leaves the plan's shapes as they were.
+int autotune_plan(Plan &p, hipStream_t st);
 
 }  // namespace pf

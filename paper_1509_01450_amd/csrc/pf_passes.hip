@@ -132,6 +132,10 @@ bool valid_shape_cols(int L, Shape s, bool f64) {
     if (!(s.E == 8 || s.E == 16) || s.E > L) return false;
     const int th = L / s.E;
     if (s.G < 1 || th * s.G > 512) return false;
+    // G a power of two: the column sums of the transpose combine the lanes
+    // of a column by exchanges at lane distances G, 2G, ... (interleaved
+    // columns); whole waves: the prefetch and the column sums count waves
+    if ((s.G & (s.G - 1)) != 0 || (th * s.G) % 64 != 0) return false;
     // FP32 shapes keep room for the prefetch (every FP32 forward kernel
     // takes it); FP64 falls back to the kernel without it when the static
     // prefetch kernel does not fit

@@ -67,7 +67,13 @@ def test_unbuilt_plan_and_null_arguments_are_refused():
         out8 = (ctypes.c_int * 8)()
         assert lib.pf_plan_schedule(h, out8) == pf.PF_ESTATE
         assert lib.pf_plan_schedule(h, None) == pf.PF_EINVAL
-        assert lib.pf_plan_set_schedule(h, out8) == pf.PF_ESTATE
+        # shapes are checked before the plan's state: zeros do not fit, a
+        # fitting shape on an unbuilt plan is a state error
+        assert lib.pf_plan_set_schedule(h, out8) == pf.PF_EINVAL
+        ok8 = (ctypes.c_int * 8)(8, 2, 8, 2, 8, 1, 8, 1)    # L = 32: 4 threads per column
+        assert lib.pf_plan_set_schedule(h, ok8) == pf.PF_EINVAL   # not a whole wave
+        ok8 = (ctypes.c_int * 8)(8, 2, 8, 2, 8, 16, 8, 16)  # 64 threads
+        assert lib.pf_plan_set_schedule(h, ok8) == pf.PF_ESTATE
         assert lib.pf_plan_set_schedule(h, None) == pf.PF_EINVAL
         assert lib.pf_plan_set_schedule(None, out8) == pf.PF_EINVAL
         ms3 = (ctypes.c_float * 3)()
@@ -97,6 +103,37 @@ def test_unbuilt_plan_and_null_arguments_are_refused():
     finally:
         pf.pf_plan_destroy(h)
     pf.pf_plan_destroy(None)
+
+
+def _gpu_present():
+    import torch
+    return torch.cuda.device_count() > 0
+
+
+@pytest.mark.skipif(_gpu_present(), reason="checks the library's answer when no GPU is present")
+def test_no_device_is_reported():
+    """Without a GPU the build calls return PF_ENODEV with a message, and the
+    per-call entry points, which need a built plan, return PF_ESTATE."""
+    lib = pf.load()
+    h = pf.pf_plan_create(16, 32, 0.1, 10.0)
+    try:
+        o = pf.pf_build_opts_default()
+        assert lib.pf_kernels_build(h, ctypes.byref(o), None) == pf.PF_ENODEV
+        assert "no GPU" in pf.pf_last_error()
+        assert lib.pf_forces(h, 8, 8, 8, None) == pf.PF_ESTATE
+        assert lib.pf_forces_backward(h, 8, 8, 8, None) == pf.PF_ESTATE
+        arr = (ctypes.c_void_p * 1)(8)
+        hs = (ctypes.c_void_p * 1)(h)
+        assert lib.pf_forces_batched(1, hs, arr, arr, arr, None) == pf.PF_ESTATE
+    finally:
+        pf.pf_plan_destroy(h)
+    c = pf.pf_cart_create(8, 8, 0.1, 0.1)
+    try:
+        assert lib.pf_cart_build(c, pf.PF_F32, pf.PF_CART_SECOND, None) == pf.PF_ENODEV
+        assert "no GPU" in pf.pf_last_error()
+        assert lib.pf_cart_forces(c, 8, 8, 8, None) == pf.PF_ESTATE
+    finally:
+        pf.pf_cart_destroy(c)
 
 
 def test_default_options():

@@ -129,10 +129,37 @@ def test_bad_shapes_are_refused_and_keep_the_schedule():
         for bad in (base[:4] + [32, 1, 8, 1],          # points per thread not 8 or 16
                     base[:4] + [8, 64, 8, 1],          # more than 512 threads
                     [3, 1] + base[2:],                 # row points per thread
-                    base[:4] + [16, 0, 16, 1]):        # no columns per workgroup
+                    base[:4] + [16, 0, 16, 1],         # no columns per workgroup
+                    base[:4] + [8, 3, 8, 3],           # columns per workgroup not a power of two
+                    base[:4] + [16, 1, 16, 1]):        # L = 128, 8 threads: not a whole wave
             with pytest.raises(pf.PFError) as exc:
                 plan.set_schedule(bad)
             assert exc.value.code == pf.PF_EINVAL
             assert list(plan.schedule()) == base
+    finally:
+        plan.close()
+
+
+def test_out_tensors_are_checked_before_any_launch():
+    plan = pf.Plan(32, 64, 0.1, 10.0, dtype="f32")
+    try:
+        s = torch.zeros(32, 64, device="cuda")
+        good = torch.empty_like(s)
+        bad = [torch.empty(32, 32, device="cuda"),                        # too small
+               torch.empty(32, 64, dtype=torch.float64, device="cuda"),   # wrong dtype
+               torch.empty(64, 32, device="cuda").t(),                     # not contiguous
+               torch.empty(32, 64)]                                        # host memory
+        for b in bad:
+            with pytest.raises(TypeError):
+                plan.forces(s, out=(good, b))
+            with pytest.raises(TypeError):
+                plan.forces(s, out=(b, good))
+            with pytest.raises(TypeError):
+                plan.backward(s, s, out=b)
+            with pytest.raises(TypeError):
+                pf.forces_batched([plan], [s], outs=[(good, b)])
+        fr, fp = plan.forces(s, out=(good, torch.empty_like(s)))
+        torch.cuda.synchronize()
+        assert fr.data_ptr() == good.data_ptr()
     finally:
         plan.close()

@@ -6,6 +6,7 @@ error law of Eq. 41-43, the parities the paper states for the self cell, the
 invariance of Eq. 33, and a principal-value integral of the self cell.
 """
 import math
+import os
 
 import numpy as np
 import pytest
@@ -280,3 +281,33 @@ def test_self_cell_cover_counts_match_paper_rule():
     g = oracle.Grid(64, 64, 0.01, 1.0)
     n = oracle.selfcell_cover(g.beta, g.dphi, 10)[3]
     assert 0.3 * 50 * 64 * 64 < n < 50 * 64 * 64
+
+
+def _selfcell_golden():
+    path = os.path.join(os.path.dirname(__file__), "golden", "selfcell_constants.txt")
+    rows = []
+    with open(path) as fh:
+        for line in fh:
+            if line.strip() and not line.startswith("#"):
+                rows.append([float(v) for v in line.split()])
+    return rows
+
+
+@pytest.mark.parametrize("row", _selfcell_golden(), ids=lambda r: "N%d" % r[0])
+def test_self_cell_constants_against_independent_values(row):
+    """The principal values to 1e-14 and the paper's cover (Sec. 4) to the
+    digits of an independent implementation (tests/golden/selfcell_constants.txt):
+    a misaligned cover grid or an open-fan inclusion test moves the cover's
+    constants in the fourth digit and fails here."""
+    N, pv0, pv1, cv0, cv1 = row
+    N = int(N)
+    g = oracle.Grid(N, N, 0.01, 1.0)
+    k0, k1, _ = oracle.selfcell_pv(g.beta, g.dphi)
+    # 1e-14 absolute: 12 significant digits at N = 64, 11 at N = 256 (the
+    # constants shrink as the cell; the integrands' terms are of order one)
+    assert abs(k0 - pv0) <= 1e-14
+    assert abs(k1 - pv1) <= 1e-14
+    c0, c1, _, _ = oracle.selfcell_cover(g.beta, g.dphi, 10)
+    # the golden digits: half a unit in the last place shown
+    assert abs(c0 - cv0) <= 5e-7
+    assert abs(c1 - cv1) <= 5e-7
