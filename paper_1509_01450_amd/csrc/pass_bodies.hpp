@@ -326,16 +326,14 @@ __device__ __forceinline__ cx<T> unpack_odd(cx<T> p, cx<T> m) {
     return {T(0.5) * (p.y + m.y), T(0.5) * (m.x - p.x)};
 }
 
-// Points per batch of spectrum loads in the multiply-accumulate of pass B,
-// sized so that a batch's loads (four complex values per point) fit in the
-// registers beside the transform data: 64 / E in FP32 (E <= 8: all E) for
-// the forward pass, half that for the transpose pass when it loads all
-// four values from global memory (it holds two input channels and spills
-// otherwise at E = 16); in FP64 one point, two when the radial pairs come
-// from LDS (PF).
-template <typename T, int E, bool ADJ = false, bool PF = false>
+// Points per batch of spectrum loads when a column pass reads its spectra
+// straight from global memory (kernels without the LDS prefetch): one pair
+// per point and multiply-accumulate sweep, so that a batch's loads fit in
+// the registers beside the transform data: 64 / E in FP32 (E <= 8: all E),
+// two in FP64.
+template <typename T, int E>
 __host__ __device__ constexpr int mac_batch() {
-    return sizeof(T) == 8 ? (PF ? 2 : 1) : (E < 8 ? E : (ADJ && !PF ? 32 : 64) / E);
+    return sizeof(T) == 8 ? 2 : (E < 8 ? E : 64 / E);
 }
 
 // ---------------------------------------------------------------------------
@@ -345,7 +343,7 @@ __host__ __device__ constexpr int mac_batch() {
 // S: [n_r][H] complex (the source rows); Z: [n_out][H] pairs (Zr, Zp), the
 // destination rows; spec: [2][H][ldspec] pairs.
 // ---------------------------------------------------------------------------
-// Entries of the radial spectrum pair per column in the LDS prefetch region:
+// Entries of one spectrum half per column in the LDS prefetch region:
 // L/2 + 1 rounded up to whole 64-lane chunks and, when a column has at
 // least 64 threads (L / E >= 64), to a multiple of L / E, so that every
 // wave issues the same number of chunk loads, known at compile time.
@@ -355,45 +353,50 @@ __host__ __device__ constexpr int spec_prefetch_len() {
     return ((L / 2 + 1) + Q - 1) / Q * Q;
 }
 
-// The radial spectrum pairs (E'_r, Q_r) of the workgroup's G columns from
-// global memory straight into LDS, spl[G][spec_prefetch_len<L, E>()] (a
-// byte copy of the leading pairs of each column): buffer loads with the
-// LDS-direct flag, 16 bytes per lane (half a pair in FP64), 1 KB per wave
-// instruction, no registers held.  The caller waits (all counters 0, then a
-// barrier) before reading.  With L / E >= 64 the G columns take
+// The spectrum pairs of one half (radial (E'_r, Q_r) at half = spec, or
+// azimuthal (E'_p, Q_p) at half = spec + H ldspec) of the workgroup's G
+// columns from global memory straight into LDS, spl[G][spec_prefetch_len<L,
+// E>()] (a byte copy of the leading pairs of each column): buffer loads with
+// the LDS-direct flag, 16 bytes per lane (half a pair in FP64), 1 KB per
+// wave instruction, no registers held.  The caller waits (all counters 0,
+// then a barrier) before reading.  With L / E >= 64 the G columns take
 // G L / (64 E) waves and each wave issues LP U E / L chunk loads (U = 16-byte
 // units per pair), a count fixed at compile time: the compiler can then wait
 // for loads issued before these without waiting for these, and when spl is
 // an LDS array of its own the transforms' LDS accesses do not wait for them
-// either.  Offsets are 32-bit: the radial half of the spectra must be below
-// 2 GB (checked by the host).
+// either.  A chunk's address is the lane's 16-byte slot (one register for
+// every chunk) plus a wave-uniform offset in a scalar register; the last
+// chunk of a column may run past the column's L/2 + 1 pairs, into the next
+// column or, for the last column, into the spectra's tail pad
+// (kSpecTailPad), and those LDS slots are never read.  Offsets are 32-bit:
+// one half of the spectra must be below 2 GB (checked by the host).
 template <typename T, int L, int E>
-__device__ __forceinline__ void prefetch_radial_spectra(int unit, int G, int H, int ldspec,
-                                                        const cx2<T> *__restrict__ spec,
-                                                        cx2<T> *spl) {
+__device__ __forceinline__ void prefetch_spectra(int unit, int G, int H, int ldspec,
+                                                 const cx2<T> *__restrict__ half, cx2<T> *spl) {
     constexpr int U = (int)sizeof(cx2<T>) / 16;     // 16-byte units per pair
     static_assert(U == 1 || U == 2, "16- or 32-byte pairs");
     constexpr int LP = spec_prefetch_len<L, E>();
     constexpr int NCH = LP * U / 64;                // 64-lane chunks per column
-    constexpr int LAST = (L / 2 + 1) * U - 1;       // last unit of a column's data
-    const int lane = (int)(threadIdx.x & 63), wv = (int)(threadIdx.x >> 6);
+    const int lane = (int)(threadIdx.x & 63);
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     // whole waves (the shape check requires it); at least one, so the
     // wave-uniform loop below always advances
     const int nw = max(1, (int)(blockDim.x >> 6));
-    // raw buffer over the radial half (stride 0, byte offsets); the last
-    // word is the data-format field every gfx9 raw buffer access uses
+    // raw buffer over the half and the data beyond it up to the tail pad
+    // (stride 0, byte offsets); the last word is the data-format field every
+    // gfx9 raw buffer access uses
     const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
-        const_cast<cx2<T> *>(spec), (short)0, H * ldspec * 16 * U, 0x00020000);
+        const_cast<cx2<T> *>(half), (short)0, 2 * H * ldspec * 16 * U, 0x00020000);
     unsigned char *const dst = reinterpret_cast<unsigned char *>(spl);
-    auto chunk = [&](int c) {
+    const int voff = lane * 16;
+    auto chunk = [&](int c) {                       // c is wave-uniform
         const int g2 = c / NCH, q = c % NCH;
         const int cg = unit * G + g2;
         const int ccl = cg < H ? cg : 0;
-        const int u = min(q * 64 + lane, LAST);     // always a valid unit
         __builtin_amdgcn_raw_ptr_buffer_load_lds(
             rs,
             (__attribute__((address_space(3))) void *)(dst + ((size_t)g2 * LP * U + q * 64) * 16),
-            16, (ccl * ldspec * U + u) * 16, 0, 0, 0);
+            16, voff, (ccl * ldspec * U + q * 64) * 16, 0, 0);
     };
     if constexpr (L / E >= 64) {
         // nw = G L / (64 E) waves, G NCH chunks: LP U E / L chunks per wave
@@ -404,8 +407,87 @@ __device__ __forceinline__ void prefetch_radial_spectra(int unit, int G, int H, 
     }
 }
 
-// PF: the radial spectrum pairs go to LDS at spl (G
-// spec_prefetch_len<L, E>() pairs) while the column is transformed.
+// Waits for this wave's prefetch, then for every wave's (the chunks of a
+// column come from several waves).
+__device__ __forceinline__ void prefetch_wait() {
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+}
+
+// One multiply-accumulate sweep of the column pass over the thread's E
+// points with the spectrum pairs (A, B) of one half:
+//   y[e] = A(k) x[e] + B(k) f[e]   (CJ false), or
+//   y[e] = conj A(k) x[e],  z[e] = conj B(k) x[e]   (CJ true, the transpose),
+// ODD for the azimuthal half (odd in phi).  The pairs come from the LDS
+// prefetch region sl (PF) or from global memory sg in batches.
+//
+// The forward sweep takes the slope correction at the points either from f
+// (KEEP: formed once, kept in registers for both sweeps) or forms it from
+// the phasors ph (FP64, where 16 more registers per point would spill).
+template <typename T, int L, int E, bool ODD, bool PF, bool KEEP>
+__device__ __forceinline__ void mac_fwd(cx<T> (&y)[E], const cx<T> (&x)[E], const cx<T> (&f)[E],
+                                        const SlopePhasors<T> &ph, const cx<T> *__restrict__ twL,
+                                        int n_r, const cx2<T> *sl, const cx2<T> *__restrict__ sg,
+                                        int t) {
+    const bool t0 = t == 0;
+    constexpr int CH = PF ? E : mac_batch<T, E>();
+#pragma unroll
+    for (int cb = 0; cb < E; cb += CH) {
+        cx2<T> s[CH];
+#pragma unroll
+        for (int j = 0; j < CH; ++j) {
+            const int ix = spec_index<L, E>(t, cb + j);
+            s[j] = PF ? sl[ix] : sg[ix];
+        }
+#pragma unroll
+        for (int j = 0; j < CH; ++j) {
+            const int e = cb + j;
+            const cx<T> fe = KEEP ? f[e] : slope_fix_at<T, E>(ph, root_ne<T, L, E>(twL, n_r, e), e);
+            y[e] = spec_mul<T, E, ODD, false>(s[j].a, x[e], e, t0) +
+                   spec_mul<T, E, ODD, false>(s[j].b, fe, e, t0);
+        }
+    }
+}
+
+template <typename T, int L, int E, bool ODD, bool PF, bool ACC>
+__device__ __forceinline__ void mac_adj(cx<T> (&y)[E], cx<T> (&z)[E], const cx<T> (&x)[E],
+                                        const cx2<T> *sl, const cx2<T> *__restrict__ sg, int t,
+                                        bool skip = false) {
+    const bool t0 = t == 0;
+    constexpr int CH = PF ? E : mac_batch<T, E>();
+#pragma unroll
+    for (int cb = 0; cb < E; cb += CH) {
+        cx2<T> s[CH];
+#pragma unroll
+        for (int j = 0; j < CH; ++j) {
+            const int ix = spec_index<L, E>(t, cb + j);
+            s[j] = PF ? sl[ix] : sg[ix];
+        }
+#pragma unroll
+        for (int j = 0; j < CH; ++j) {
+            const int e = cb + j;
+            const cx<T> a = spec_mul<T, E, ODD, true>(s[j].a, x[e], e, t0);
+            const cx<T> b = spec_mul<T, E, ODD, true>(s[j].b, x[e], e, t0);
+            if constexpr (ACC) {
+                y[e] = skip ? y[e] : y[e] + a;
+                z[e] = skip ? z[e] : z[e] + b;
+            } else {
+                y[e] = a;
+                z[e] = b;
+            }
+        }
+    }
+}
+
+// The column pass runs the two force channels one after the other: the
+// radial channel's multiply-accumulate with the radial pairs, then, while
+// its inverse transform runs, the azimuthal pairs arrive (in the LDS region
+// the radial pairs held), then the azimuthal channel.  So the spectrum
+// loads of the second half overlap a transform instead of waiting in the
+// multiply-accumulate, and no point's work depends on a per-lane branch
+// outside the one workgroup that holds the packed column 0.
+// PF: the spectrum pairs go to LDS at spl (G spec_prefetch_len<L, E>()
+// pairs), one half at a time.
 template <typename T, int L, int E, bool PF = false>
 __device__ __forceinline__ void body_cols_fwd(int unit, int G, cx<T> *__restrict__ buf,
                                               const cx<T> *__restrict__ S,
@@ -422,8 +504,9 @@ __device__ __forceinline__ void body_cols_fwd(int unit, int G, cx<T> *__restrict
     const bool packed = unit == 0;          // workgroup-uniform: the group holding column 0
     const bool is0 = packed && gi == 0;
     const Lds<T> lds{buf, gi, G};
-
     constexpr int LP = spec_prefetch_len<L, E>();
+    const cx2<T> *const srad = spec;                        // (E'_r, Q_r) per column
+    const cx2<T> *const sazi = spec + (size_t)H * ldspec;   // (E'_p, Q_p) per column
 
     // The column.  Only the first E/2 strided points of a thread can be data
     // rows (L >= 2 n_r); clamped, always valid addresses so the loads issue
@@ -441,83 +524,90 @@ __device__ __forceinline__ void body_cols_fwd(int unit, int G, cx<T> *__restrict
     Twiddles<L, E, T> tw;
     tw.load(t, twL, 1);
     // issued after the column's loads, which the transform waits for
-    if constexpr (PF) prefetch_radial_spectra<T, L, E>(unit, G, H, ldspec, spec, spl);
+    if constexpr (PF) prefetch_spectra<T, L, E>(unit, G, H, ldspec, srad, spl);
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         const int i = t + e * TH;
         if (e >= E / 2 || !valid || i >= n_r) v[e] = cx<T>{T(0), T(0)};
     }
     fft_fwd<L, E, T, true>(v, t, lds, tw);
-    if (packed) {   // column 0 reads the conjugate mirror points from LDS
+
+    // transform of the four-row slope correction at the thread's points
+    // (kept for both sweeps in FP32)
+    constexpr bool KEEP = sizeof(T) == 4;
+    const SlopePhasors<T> ph = slope_phasors(slope_fix(x0, x1, xm2, xm1, ca, c0, cn), wt, wnt);
+    cx<T> f[E];
+    if constexpr (KEEP) {
+#pragma unroll
+        for (int e = 0; e < E; ++e) f[e] = slope_fix_at<T, E>(ph, root_ne<T, L, E>(twL, n_r, e), e);
+    }
+    const cx2<T> *sl = PF ? spl + (size_t)gi * LP : nullptr;
+    const cx2<T> *const gr = srad + (size_t)cl * ldspec;
+    const cx2<T> *const gp = sazi + (size_t)cl * ldspec;
+
+    // radial channel: y0 = E'_r X + Q_r B
+    if constexpr (PF) prefetch_wait();
+    cx<T> y0[E];
+    mac_fwd<T, L, E, false, PF, KEEP>(y0, v, f, ph, twL, n_r, sl, gr, t);
+    if (packed) {
+        // column 0 holds bins 0 and M packed as c_0 + i c_M: its radial
+        // channel is y_0 + i y_M, from the bin-0 radial pairs (at the radial
+        // place) and the bin-M radial pairs (at the azimuthal place, read
+        // from global memory) applied to the two unpacked transforms, which
+        // need the conjugate mirror points (through LDS)
 #pragma unroll
         for (int e = 0; e < E; ++e) lds.st_split(lds_pad(t), e * TH, v[e]);
         lds_barrier();
-    }
-
-    const cx2<T> *sr = spec + (size_t)cl * ldspec;               // (E'_r, Q_r)
-    const cx2<T> *sp = spec + (size_t)(H + cl) * ldspec;         // (E'_p, Q_p)
-    const cx2<T> *srl = PF ? spl + (size_t)gi * LP : nullptr;     // (E'_r, Q_r) in LDS
-    if constexpr (PF) {
-        // the prefetch has landed for this wave; the barrier makes every
-        // wave's chunks visible
-        __builtin_amdgcn_s_waitcnt(0);
-        __syncthreads();
-    }
-    const SlopeFix<T> a = slope_fix(x0, x1, xm2, xm1, ca, c0, cn);
-    const SlopePhasors<T> ph = slope_phasors(a, wt, wnt);
-    SlopePhasors<T> ph0 = ph, phM = ph;
-    if (is0) {   // bins 0 and M of the packed column: real coefficients each
-        ph0 = slope_phasors(slope_fix_part(a, false), wt, wnt);
-        phM = slope_phasors(slope_fix_part(a, true), wt, wnt);
-    }
-    constexpr int CH = mac_batch<T, E, false, PF>();
-    const bool t0 = t == 0;
-    cx<T> y[2][E];   // y[0] -> Zr, y[1] -> Zp
+        if (is0) {
+            // the four boundary rows again (read here rather than kept live
+            // through the transform for this one column)
+            const SlopeFix<T> a = slope_fix(S[0], S[(size_t)H], S[(size_t)(n_r - 2) * H],
+                                            S[(size_t)(n_r - 1) * H], ca, c0, cn);
+            const SlopePhasors<T> ph0 = slope_phasors(slope_fix_part(a, false), wt, wnt);
+            const SlopePhasors<T> phM = slope_phasors(slope_fix_part(a, true), wt, wnt);
+            const bool t0 = t == 0;
 #pragma unroll
-    for (int cb = 0; cb < E; cb += CH) {
-        // spectra of the batch issued together; column 0's second pair holds
-        // bin M's radial (even) spectra
-        cx2<T> pr[CH], pp[CH];
-#pragma unroll
-        for (int j = 0; j < CH; ++j) {
-            const int ix = spec_index<L, E>(t, cb + j);
-            pr[j] = PF ? srl[ix] : sr[ix];
-            pp[j] = sp[ix];
-        }
-#pragma unroll
-        for (int j = 0; j < CH; ++j) {
-            const int e = cb + j;
-            const cx<T> rne = root_ne<T, L, E>(twL, n_r, e);
-            if (is0) {
+            for (int e = 0; e < E; ++e) {
+                const int ix = spec_index<L, E>(t, e);
+                const cx2<T> pr = PF ? sl[ix] : gr[ix];
+                const cx2<T> pm = gp[ix];
+                const cx<T> rne = root_ne<T, L, E>(twL, n_r, e);
                 const cx<T> m = lds.ld((L - (t + e * TH)) & (L - 1));
                 const cx<T> A = unpack_even(v[e], m), B = unpack_odd(v[e], m);
                 const cx<T> f0 = slope_fix_at<T, E>(ph0, rne, e);
                 const cx<T> fM = slope_fix_at<T, E>(phM, rne, e);
-                const cx<T> y0 = spec_mul<T, E, false, false>(pr[j].a, A, e, t0) +
-                                 spec_mul<T, E, false, false>(pr[j].b, f0, e, t0);
-                const cx<T> yM = spec_mul<T, E, false, false>(pp[j].a, B, e, t0) +
-                                 spec_mul<T, E, false, false>(pp[j].b, fM, e, t0);
-                y[0][e] = cx<T>{y0.x - yM.y, y0.y + yM.x};   // y0 + i yM
-                y[1][e] = cx<T>{T(0), T(0)};
-            } else {
-                const cx<T> f = slope_fix_at<T, E>(ph, rne, e);
-                y[0][e] = spec_mul<T, E, false, false>(pr[j].a, v[e], e, t0) +
-                          spec_mul<T, E, false, false>(pr[j].b, f, e, t0);
-                y[1][e] = spec_mul<T, E, true, false>(pp[j].a, v[e], e, t0) +
-                          spec_mul<T, E, true, false>(pp[j].b, f, e, t0);
+                const cx<T> ya = spec_mul<T, E, false, false>(pr.a, A, e, t0) +
+                                 spec_mul<T, E, false, false>(pr.b, f0, e, t0);
+                const cx<T> yb = spec_mul<T, E, false, false>(pm.a, B, e, t0) +
+                                 spec_mul<T, E, false, false>(pm.b, fM, e, t0);
+                y0[e] = cx<T>{ya.x - yb.y, ya.y + yb.x};   // ya + i yb
             }
         }
+        lds_barrier();   // mirror reads done before the transforms reuse buf
     }
-    if (packed) lds_barrier();
-    fft_inv<L, E, T>(y[0], t, lds, tw);
-    fft_inv<L, E, T>(y[1], t, lds, tw);
+    if constexpr (PF) {
+        // every wave has read its radial pairs: the azimuthal pairs go to the
+        // same LDS region during the radial channel's inverse transform
+        lds_barrier();
+        prefetch_spectra<T, L, E>(unit, G, H, ldspec, sazi, spl);
+    }
+    fft_inv<L, E, T>(y0, t, lds, tw);
+
+    // azimuthal channel: y1 = E'_p X + Q_p B (zero for column 0: the
+    // azimuthal spectra vanish at bins 0 and M)
+    if constexpr (PF) prefetch_wait();
+    cx<T> y1[E];
+    mac_fwd<T, L, E, true, PF, KEEP>(y1, v, f, ph, twL, n_r, sl, gp, t);
+#pragma unroll
+    for (int e = 0; e < E; ++e) y1[e] = is0 ? cx<T>{T(0), T(0)} : y1[e];
+    fft_inv<L, E, T>(y1, t, lds, tw);
     if (valid) {
         // only the first E/2 points of a thread can be rows (L >= 2 n_out): the
         // rest of the last stage is never formed
 #pragma unroll
         for (int e = 0; e < E / 2; ++e) {
             const int i = t + e * TH;
-            if (i < n_out) Z[(size_t)i * H + col] = cx2<T>{y[0][e], y[1][e]};
+            if (i < n_out) Z[(size_t)i * H + col] = cx2<T>{y0[e], y1[e]};
         }
     }
 }
@@ -566,11 +656,12 @@ __device__ __forceinline__ void column_sums(cx<T> (&x)[Q], int G, cx<T> *__restr
 // four-row correction needs the inverse transform of R = conj(Q_r) V_r +
 // conj(Q_p) V_p at rows 0, n-1, n and L-1 only, four sums over k.
 // V: [n_r][H] pairs (Vr, Vp); D: [n_r][H] complex.  LDS buf: G*padded_len(L)
-// complex.
-// ---------------------------------------------------------------------------
-// PF: the radial spectrum pairs go to LDS at spl (G
-// spec_prefetch_len<L, E>() pairs) while the two input channels are
+// complex.  As the forward pass, one spectrum half at a time: the radial
+// pairs meet V_r's transform, and the azimuthal pairs arrive while V_p is
 // transformed.
+// PF: the spectrum pairs go to LDS at spl (G spec_prefetch_len<L, E>()
+// pairs), one half at a time.
+// ---------------------------------------------------------------------------
 template <typename T, int L, int E, bool PF = false>
 __device__ __forceinline__ void body_cols_adj(int unit, int G, cx<T> *__restrict__ buf,
                                               const cx2<T> *__restrict__ V,
@@ -587,6 +678,9 @@ __device__ __forceinline__ void body_cols_adj(int unit, int G, cx<T> *__restrict
     const bool packed = unit == 0;
     const bool is0 = packed && gi == 0;
     const Lds<T> lds{buf, gi, G};
+    constexpr int LP = spec_prefetch_len<L, E>();
+    const cx2<T> *const srad = spec;
+    const cx2<T> *const sazi = spec + (size_t)H * ldspec;
 
     // clamped, always valid addresses so the loads issue back to back; only
     // the first E/2 points of a thread can be data rows (L >= 2 n_r)
@@ -601,7 +695,7 @@ __device__ __forceinline__ void body_cols_adj(int unit, int G, cx<T> *__restrict
     Twiddles<L, E, T> tw;
     tw.load(t, twL, 1);
     // issued after the column's loads, which the transforms wait for
-    if constexpr (PF) prefetch_radial_spectra<T, L, E>(unit, G, H, ldspec, spec, spl);
+    if constexpr (PF) prefetch_spectra<T, L, E>(unit, G, H, ldspec, srad, spl);
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         const int i = t + e * TH;
@@ -611,73 +705,67 @@ __device__ __forceinline__ void body_cols_adj(int unit, int G, cx<T> *__restrict
         }
     }
     fft_fwd<L, E, T, true>(va[0], t, lds, tw);
-    fft_fwd<L, E, T, true>(va[1], t, lds, tw);
-    if (packed) {   // column 0 reads the conjugate mirror points from LDS
+
+    const cx2<T> *sl = PF ? spl + (size_t)gi * LP : nullptr;
+    const cx2<T> *const gr = srad + (size_t)cl * ldspec;
+    const cx2<T> *const gp = sazi + (size_t)cl * ldspec;
+    // radial half: xe = conj(E'_r) V_r, r = conj(Q_r) V_r
+    if constexpr (PF) prefetch_wait();
+    cx<T> xe[E], r[E];
+    mac_adj<T, L, E, false, PF, false>(xe, r, va[0], sl, gr, t);
+    if (packed) {
+        // bins 0 and M of the packed column 0, from the unpacked transforms
+        // of V_r (conjugate mirror points through LDS) and the bin-0 and
+        // bin-M radial pairs; V_p's bins 0 and M do not enter (the azimuthal
+        // spectra vanish there)
 #pragma unroll
         for (int e = 0; e < E; ++e) lds.st_split(lds_pad(t), e * TH, va[0][e]);
         lds_barrier();
+        if (is0) {
+            const bool t0 = t == 0;
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                const int ix = spec_index<L, E>(t, e);
+                const cx2<T> pr = PF ? sl[ix] : gr[ix];
+                const cx2<T> pm = gp[ix];
+                const cx<T> m = lds.ld((L - (t + e * TH)) & (L - 1));
+                const cx<T> A = unpack_even(va[0][e], m), B = unpack_odd(va[0][e], m);
+                const cx<T> x0 = spec_mul<T, E, false, true>(pr.a, A, e, t0);
+                const cx<T> xM = spec_mul<T, E, false, true>(pm.a, B, e, t0);
+                const cx<T> r0 = spec_mul<T, E, false, true>(pr.b, A, e, t0);
+                const cx<T> rM = spec_mul<T, E, false, true>(pm.b, B, e, t0);
+                xe[e] = cx<T>{x0.x - xM.y, x0.y + xM.x};
+                r[e] = cx<T>{r0.x - rM.y, r0.y + rM.x};
+            }
+        }
+        lds_barrier();   // mirror reads done before the transform reuses buf
     }
-
-    const cx2<T> *sr = spec + (size_t)cl * ldspec;
-    const cx2<T> *sp = spec + (size_t)(H + cl) * ldspec;
-    const cx2<T> *srl = PF ? spl + (size_t)gi * spec_prefetch_len<L, E>() : nullptr;
     if constexpr (PF) {
-        // the prefetch has landed for this wave; the barrier makes every
-        // wave's chunks visible
-        __builtin_amdgcn_s_waitcnt(0);
-        __syncthreads();
+        // every wave has read its radial pairs: the azimuthal pairs go to the
+        // same LDS region while V_p is transformed
+        lds_barrier();
+        prefetch_spectra<T, L, E>(unit, G, H, ldspec, sazi, spl);
     }
+    fft_fwd<L, E, T, true>(va[1], t, lds, tw);
+    // azimuthal half: xe += conj(E'_p) V_p, r += conj(Q_p) V_p
+    if constexpr (PF) prefetch_wait();
+    mac_adj<T, L, E, true, PF, true>(xe, r, va[1], sl, gp, t, is0);
+
     // The unnormalised inverse transform of R at rows 0, L-1, n, n-1:
     //   w[0] = sum R, w[1] = sum R W^k, w[2] = sum R W^(-n k),
     //   w[3] = sum R W^(-(n-1) k),
     // summed per thread against the roots (W^(j k) = W^(j t) r(j e)) and
     // turned into the thread's share with its phasors afterwards.
     cx<T> w[4] = {{T(0), T(0)}, {T(0), T(0)}, {T(0), T(0)}, {T(0), T(0)}};
-    // with the radial pairs in LDS only the azimuthal ones take registers:
-    // the forward pass's batch
-    constexpr int CH = mac_batch<T, E, true, PF>();
-    const bool t0 = t == 0;
 #pragma unroll
-    for (int cb = 0; cb < E; cb += CH) {
-        cx2<T> pr[CH], pp[CH];
-#pragma unroll
-        for (int j = 0; j < CH; ++j) {
-            const int ix = spec_index<L, E>(t, cb + j);
-            pr[j] = PF ? srl[ix] : sr[ix];
-            pp[j] = sp[ix];
-        }
-#pragma unroll
-        for (int j = 0; j < CH; ++j) {
-            const int e = cb + j;
-            cx<T> xe, r;
-            if (is0) {
-                // bins 0 and M of the packed column; V_p's bins 0 and M do
-                // not enter (the azimuthal spectra vanish there)
-                const cx<T> m = lds.ld((L - (t + e * TH)) & (L - 1));
-                const cx<T> A = unpack_even(va[0][e], m), B = unpack_odd(va[0][e], m);
-                const cx<T> x0 = spec_mul<T, E, false, true>(pr[j].a, A, e, t0);
-                const cx<T> xM = spec_mul<T, E, false, true>(pp[j].a, B, e, t0);
-                const cx<T> r0 = spec_mul<T, E, false, true>(pr[j].b, A, e, t0);
-                const cx<T> rM = spec_mul<T, E, false, true>(pp[j].b, B, e, t0);
-                xe = cx<T>{x0.x - xM.y, x0.y + xM.x};
-                r = cx<T>{r0.x - rM.y, r0.y + rM.x};
-            } else {
-                // conj(E'_r) V_r + conj(E'_p) V_p and conj(Q_r) V_r + conj(Q_p) V_p
-                xe = spec_mul<T, E, false, true>(pr[j].a, va[0][e], e, t0) +
-                     spec_mul<T, E, true, true>(pp[j].a, va[1][e], e, t0);
-                r = spec_mul<T, E, false, true>(pr[j].b, va[0][e], e, t0) +
-                    spec_mul<T, E, true, true>(pp[j].b, va[1][e], e, t0);
-            }
-            va[0][e] = xe;   // V_r's point is not needed again
-            // r W^(j k) over the thread's points: w^e, w^-(n e), w^-((n-1) e)
-            const cx<T> q = cmulc(r, root_ne<T, L, E>(twL, n_r, e));
-            w[0] = w[0] + r;
-            w[1] = w[1] + mul_root<E>(r, e);
-            w[2] = w[2] + q;
-            w[3] = w[3] + mul_root<E>(q, e);
-        }
+    for (int e = 0; e < E; ++e) {
+        // r W^(j k) over the thread's points: w^e, w^-(n e), w^-((n-1) e)
+        const cx<T> q = cmulc(r[e], root_ne<T, L, E>(twL, n_r, e));
+        w[0] = w[0] + r[e];
+        w[1] = w[1] + mul_root<E>(r[e], e);
+        w[2] = w[2] + q;
+        w[3] = w[3] + mul_root<E>(q, e);
     }
-    if (packed) lds_barrier();
     {
         const cx<T> wt = twL[t];
         const cx<T> wnt = twL[(int)(((unsigned)n_r * (unsigned)t) & (unsigned)(L - 1))];
@@ -687,14 +775,14 @@ __device__ __forceinline__ void body_cols_adj(int unit, int G, cx<T> *__restrict
         w[3] = cmulc(w[3], wmt);
     }
     column_sums<T, 4>(w, G, buf);
-    fft_inv<L, E, T>(va[0], t, lds, tw);
+    fft_inv<L, E, T>(xe, t, lds, tw);
     if (valid) {
 #pragma unroll
         for (int e = 0; e < E / 2; ++e) {   // rows lie in the first half (L >= 2 n_r)
             const int i = t + e * TH;
             if (i < n_r) {
                 // transposed four-row correction
-                cx<T> acc = va[0][e];
+                cx<T> acc = xe[e];
                 if (i == 0) acc = acc - scale(w[0], c0) - scale(w[1], ca);
                 if (i == 1) acc = acc + scale(w[0], c0 - ca);
                 if (i == n_r - 2) acc = acc + scale(w[3], ca - cn);

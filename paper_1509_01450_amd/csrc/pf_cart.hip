@@ -423,7 +423,7 @@ __device__ __forceinline__ void body_cart_cols(int unit, int G, cx<T> *__restric
     Twiddles<L, E, T> tw;
     tw.load(t, twL, 1);
     // issued after the column's loads, which the transforms wait for
-    if constexpr (PF) prefetch_radial_spectra<T, L, E>(unit, G, H, ldspec, spec, spl);
+    if constexpr (PF) prefetch_spectra<T, L, E>(unit, G, H, ldspec, spec, spl);
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         const int i = t + e * TH;
@@ -839,7 +839,7 @@ int cart_build(CartPlan &c, int dtype, int method, hipStream_t st) {
     const size_t plane = (size_t)c.Lx * c.Ly;
     if (hipMalloc(&tab.p, 6 * plane * sizeof(double)) != hipSuccess ||
         hipMalloc(&rowspec.p, 6 * (size_t)c.Lx * c.H * sizeof(cx<double>)) != hipSuccess ||
-        hipMalloc(&spec64.p, ns * sizeof(cx2<double>)) != hipSuccess ||
+        hipMalloc(&spec64.p, ns * sizeof(cx2<double>) + kSpecTailPad) != hipSuccess ||
         hipMalloc(&rsp64.p, ns * sizeof(cx<double>)) != hipSuccess) {
         set_error("Cartesian table allocation failed");
         return PF_ENOMEM;
@@ -876,7 +876,7 @@ int cart_build(CartPlan &c, int dtype, int method, hipStream_t st) {
         c.twL = twL64.p;
         twN64.p = twL64.p = nullptr;
     } else {
-        PF_HIP(hipMalloc(&c.spec, ns * sizeof(cx2<float>)));
+        PF_HIP(hipMalloc(&c.spec, ns * sizeof(cx2<float>) + kSpecTailPad));
         PF_HIP(hipMalloc(&c.rsp, ns * sizeof(cx<float>)));
         hipLaunchKernelGGL(k_cart_to_f32, dim3(1024), dim3(256), 0, st,
                            (const double *)spec64.p, (float *)c.spec, (long)(ns * 4));

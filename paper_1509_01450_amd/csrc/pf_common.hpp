@@ -25,6 +25,12 @@ void clear_error();
         }                                                                         \
     } while (0)
 
+// Bytes allocated after the kernel spectra: the column passes copy each
+// column's spectrum pairs into LDS in whole chunks of 64 lanes, which can
+// reach up to L/E pairs past the column's last one; for the last column of
+// the array those bytes are this tail, never used.
+constexpr size_t kSpecTailPad = 64 * 1024;
+
 // Launch shape of one transform pass: E points per thread and G transforms
 // (rows or columns) per workgroup.
 struct Shape {

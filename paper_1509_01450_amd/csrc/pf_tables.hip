@@ -779,7 +779,7 @@ int build_tables_and_spectra(Plan &p, hipStream_t st) {
         if (rc) return rc;
     }
     const size_t nspec = (size_t)4 * p.M * p.ldspec;
-    PF_HIP(hipMalloc(&spec64.p, nspec * sizeof(cx<double>)));
+    PF_HIP(hipMalloc(&spec64.p, nspec * sizeof(cx<double>) + kSpecTailPad));
     rc = fold_dispatch((const cx<double> *)rowspec.p, p, (cx2<double> *)spec64.p,
                        (const cx<double> *)twL64.p, st);
     if (rc) return rc;
@@ -789,7 +789,7 @@ int build_tables_and_spectra(Plan &p, hipStream_t st) {
         spec_final = spec64.p;
         spec64.p = nullptr;
     } else {
-        PF_HIP(hipMalloc(&spec_final, nspec * sizeof(cx<float>)));
+        PF_HIP(hipMalloc(&spec_final, nspec * sizeof(cx<float>) + kSpecTailPad));
         hipLaunchKernelGGL(k_to_f32, dim3(1024), dim3(256), 0, st, (const cx<double> *)spec64.p,
                            (cx<float> *)spec_final, (long)nspec);
         hipError_t e = hipGetLastError();
