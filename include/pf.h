@@ -192,18 +192,22 @@ int pf_forces_backward(pf_plan plan, const void *g_fr, const void *g_fphi,
                        void *g_sigma, void *stream);
 
 /* Forward map for n independent disks, each with its own built plan (all of
- * one precision, sizes may differ), as three launches on `stream` that each
- * cover every disk (pass A, pass B, pass C).  Arrays sigma[k], f_r[k],
+ * one precision, sizes may differ), on `stream`: the disks are grouped per
+ * pass into classes of equal transform length and tuned launch shape (each
+ * plan's pf_plan_schedule), and each class is one launch covering every
+ * disk in it -- pass A of all disks, then pass B, then pass C.  The results
+ * equal pf_forces on each plan bit for bit.  Arrays sigma[k], f_r[k],
  * f_phi[k] follow plan[k]'s layout.  Sizes: 128 <= n_phi <= 4096 and
- * 33 <= n_r <= 2048 (FP32) or 1024 (FP64); other plans give
- * PF_EUNSUPPORTED.  A plan may appear once per batch (PF_EINVAL otherwise).
- * Plans of a batch share internal state: do not run two batches with common
- * plans at once.  The first call for a set of plans, and a call whose field
- * pointers differ from the previous call's, waits for a small table upload;
- * otherwise the call only enqueues the three launches (asynchronous, and it
- * may be captured into a HIP graph).  The launches read the batch's pointer
- * table at run time: a graph replay writes to the fields of the most recent
- * call for that set of plans.  1 <= n <= 4096.                              */
+ * 33 <= n_r <= 2048; other plans give PF_EUNSUPPORTED.  A plan may appear
+ * once per batch (PF_EINVAL otherwise).  Plans of a batch share internal
+ * state: do not run two batches with common plans at once.  The first call
+ * for a set of plans allocates the batch's device tables (released with the
+ * plans); a call whose field pointers differ from the previous call's
+ * enqueues their upload (kernel arguments, nothing waits); otherwise the call
+ * only enqueues the class launches (asynchronous, and it may be captured
+ * into a HIP graph).  The launches read the batch's pointer table at run
+ * time: a graph replay writes to the fields of the most recent call for
+ * that set of plans.  1 <= n <= 4096.                                       */
 int pf_forces_batched(int n, const pf_plan *plans, const void *const *sigma,
                       void *const *f_r, void *const *f_phi, void *stream);
 

@@ -382,7 +382,7 @@ class Plan:
 
 
 def forces_batched(plans, sigmas, outs=None):
-    """Forward map of many disks (three launches covering every disk)."""
+    """Forward map of many disks (grouped launches covering every disk)."""
     import torch
     if len(plans) != len(sigmas) or (outs is not None and len(outs) != len(plans)):
         raise TypeError("one sigma (and one output pair) per plan")

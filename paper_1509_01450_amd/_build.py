@@ -2,7 +2,11 @@
 
 Every translation unit under csrc/ is compiled in parallel, then linked into
 ``paper_1509_01450_amd/libpf.so``.  Packed FP32 instructions are disabled
-for all device code (-Xclang -target-feature -Xclang -packed-fp32-ops).
+for all device code (-Xclang -target-feature -Xclang -packed-fp32-ops), and
+floating-point contraction is limited to single expressions
+(-ffp-contract=on): every rounding step follows from the source, so kernels
+that share a pass body give identical results (the batched and single-disk
+paths), and the hot loops write their fused multiply-adds out.
 """
 from __future__ import annotations
 
@@ -18,10 +22,11 @@ OUT = os.path.join(HERE, "libpf.so")
 BUILD = os.path.join(HERE, "_build")
 ARCH = os.environ.get("PF_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["pf_api.hip", "pf_passes.hip", "pf_tables.hip", "pf_batched.hip", "pf_cart.hip"]
+SOURCES = ["pf_api.hip", "pf_passes.hip", "pf_tables.hip", "pf_batched.hip", "pf_tune.hip",
+           "pf_cart.hip"]
 
 HIPCC_FLAGS = [
-    "-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH,
+    "-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH, "-ffp-contract=on",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
     "-Wno-unused-result",

@@ -45,6 +45,26 @@ __device__ __forceinline__ cx<T> cmulc(cx<T> a, cx<T> b) {
 }
 template <typename T>
 __device__ __forceinline__ cx<T> conj(cx<T> a) { return {a.x, -a.y}; }
+
+// Fused multiply-adds written out.  The library is compiled with contraction
+// limited to single expressions (-ffp-contract=on), so every rounding step
+// is fixed by the source and not by how a kernel happens to be inlined or
+// scheduled: the batched kernels, which run the same pass bodies, then give
+// the single-disk results bit for bit.  Where a product and a sum are to
+// fuse across expressions they go through these.
+__device__ __forceinline__ float fmadd(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmadd(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+// acc + a b
+template <typename T>
+__device__ __forceinline__ cx<T> cmac(cx<T> acc, cx<T> a, cx<T> b) {
+    return {fmadd(a.x, b.x, fmadd(-a.y, b.y, acc.x)), fmadd(a.x, b.y, fmadd(a.y, b.x, acc.y))};
+}
+// acc + a conj(b)
+template <typename T>
+__device__ __forceinline__ cx<T> cmacc(cx<T> acc, cx<T> a, cx<T> b) {
+    return {fmadd(a.x, b.x, fmadd(a.y, b.y, acc.x)), fmadd(a.y, b.x, fmadd(-a.x, b.y, acc.y))};
+}
 template <typename T>
 __device__ __forceinline__ cx<T> scale(cx<T> a, T s) { return {a.x * s, a.y * s}; }
 // multiply by -i
@@ -226,6 +246,23 @@ __device__ __forceinline__ cx<T> mul_root(cx<T> x, int k) {
     const T cs[16] = {T(1), c1, h, s1, T(0), -s1, -h, -c1, T(-1), -c1, -h, -s1, T(0), s1, h, c1};
     const T c = cs[q], sn = cs[(q + 12) & 15];
     return {x.x * c + x.y * sn, x.y * c - x.x * sn};
+}
+
+// acc + x w^k (as mul_root, the product fused into the sum)
+template <int E, typename T>
+__device__ __forceinline__ cx<T> mul_root_add(cx<T> acc, cx<T> x, int k) {
+    static_assert(E == 4 || E == 8 || E == 16, "roots of unity of order 4, 8 or 16");
+    const int q = (((k % E) + E) % E) * (16 / E);   // sixteenths of a turn
+    if (q == 0) return acc + x;
+    if (q == 4) return {acc.x + x.y, acc.y - x.x};
+    if (q == 8) return {acc.x - x.x, acc.y - x.y};
+    if (q == 12) return {acc.x - x.y, acc.y + x.x};
+    const T c1 = T(0.92387953251128675612818318939678828682);
+    const T s1 = T(0.38268343236508977172845998403039886676);
+    const T h = T(0.70710678118654752440084436210484903928);
+    const T cs[16] = {T(1), c1, h, s1, T(0), -s1, -h, -c1, T(-1), -c1, -h, -s1, T(0), s1, h, c1};
+    const T c = cs[q], sn = cs[(q + 12) & 15];
+    return {fmadd(x.x, c, fmadd(x.y, sn, acc.x)), fmadd(x.y, c, fmadd(-x.x, sn, acc.y))};
 }
 
 // ---------------------------------------------------------------------------

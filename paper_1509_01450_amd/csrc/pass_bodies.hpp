@@ -124,7 +124,7 @@ __device__ __forceinline__ void body_rows_r2c(int unit, int G, cx<T> *__restrict
             const cx<T> ev = {T(0.5) * (zk.x + zm.x), T(0.5) * (zk.y - zm.y)};
             // (zk - conj zm) / (2i)
             const cx<T> od = {T(0.5) * (zk.y + zm.y), -T(0.5) * (zk.x - zm.x)};
-            cx<T> x = ev + cmul(twN[k], od);
+            cx<T> x = cmac(ev, twN[k], od);
             if (k == 0) x = cx<T>{zk.x + zk.y, zk.x - zk.y};   // (X_0, X_M), both real
             o[c][e] = x;
         }
@@ -202,8 +202,9 @@ __device__ __forceinline__ void body_rows_c2r(int unit, int G, cx<T> *__restrict
         for (int e = 0; e < E; ++e) {
             const cx<T> s = {xk[c][e].x + xm[c][e].x, xk[c][e].y - xm[c][e].y};   // X[k] + conj X[M-k]
             const cx<T> d = {xk[c][e].x - xm[c][e].x, xk[c][e].y + xm[c][e].y};   // X[k] - conj X[M-k]
-            const cx<T> dw = cmulc(d, wk[e]);                                         // d exp(+2 pi i k / N)
-            v[c][e] = active ? cx<T>{s.x - dw.y, s.y + dw.x} : cx<T>{T(0), T(0)};   // s + i dw
+            // s + i d exp(+2 pi i k / N): i conj(w) = (w.y, w.x) for w = wk
+            const cx<T> iw = {wk[e].y, wk[e].x};
+            v[c][e] = active ? cmac(s, d, iw) : cx<T>{T(0), T(0)};
         }
     fft_inv<M, E, C, T>(v, t, lds, tw);
     if (active) {
@@ -234,17 +235,27 @@ __device__ __forceinline__ int spec_index(int t, int e) {
 
 // x S (CJ false) or x conj(S) (CJ true) for the spectrum value S of point
 // e whose stored value is s (spec_index); ODD: a kernel odd in phi, whose
-// mirror is -conj rather than conj.  t0: the thread is t = 0.
+// mirror is -conj rather than conj.  t0: the thread is t = 0.  spec_mac adds
+// the product to acc (fused).  The mirror's conjugation and sign fold into
+// the operands: S = w with w = s, or the mirror of s.
+template <typename T, int E, bool ODD>
+__device__ __forceinline__ cx<T> spec_value(cx<T> s, int e, bool t0) {
+    const cx<T> m = ODD ? cx<T>{-s.x, s.y} : cx<T>{s.x, -s.y};
+    if (e == E / 2) return t0 ? s : m;
+    return e < E / 2 ? s : m;
+}
+
 template <typename T, int E, bool ODD, bool CJ>
 __device__ __forceinline__ cx<T> spec_mul(cx<T> s, cx<T> x, int e, bool t0) {
-    if (e == E / 2) {
-        const cx<T> m = ODD ? cx<T>{-s.x, s.y} : cx<T>{s.x, -s.y};
-        const cx<T> se = t0 ? s : m;
-        return CJ ? cmulc(x, se) : cmul(x, se);
-    }
-    if (e < E / 2) return CJ ? cmulc(x, s) : cmul(x, s);
-    const cx<T> p = CJ ? cmul(x, s) : cmulc(x, s);
-    return ODD ? cx<T>{-p.x, -p.y} : p;
+    const cx<T> w = spec_value<T, E, ODD>(s, e, t0);
+    return CJ ? cx<T>{fmadd(x.x, w.x, x.y * w.y), fmadd(x.y, w.x, -(x.x * w.y))}
+              : cx<T>{fmadd(x.x, w.x, -(x.y * w.y)), fmadd(x.x, w.y, x.y * w.x)};
+}
+
+template <typename T, int E, bool ODD, bool CJ>
+__device__ __forceinline__ cx<T> spec_mac(cx<T> acc, cx<T> s, cx<T> x, int e, bool t0) {
+    const cx<T> w = spec_value<T, E, ODD>(s, e, t0);
+    return CJ ? cmacc(acc, x, w) : cmac(acc, x, w);
 }
 
 // ---------------------------------------------------------------------------
@@ -311,7 +322,7 @@ __device__ __forceinline__ cx<T> root_ne(const cx<T> *__restrict__ twL, int n, i
 
 template <typename T, int E>
 __device__ __forceinline__ cx<T> slope_fix_at(const SlopePhasors<T> &p, cx<T> rne, int e) {
-    return p.a0 + mul_root<E>(p.b2, -e) + cmul(rne, p.b1 + mul_root<E>(p.b3, -e));
+    return cmac(mul_root_add<E>(p.a0, p.b2, -e), rne, mul_root_add<E>(p.b1, p.b3, -e));
 }
 
 // Transforms of the two real sequences packed as p = c_0 + i c_M, from p and
@@ -443,8 +454,8 @@ __device__ __forceinline__ void mac_fwd(cx<T> (&y)[E], const cx<T> (&x)[E], cons
         for (int j = 0; j < CH; ++j) {
             const int e = cb + j;
             const cx<T> fe = KEEP ? f[e] : slope_fix_at<T, E>(ph, root_ne<T, L, E>(twL, n_r, e), e);
-            y[e] = spec_mul<T, E, ODD, false>(s[j].a, x[e], e, t0) +
-                   spec_mul<T, E, ODD, false>(s[j].b, fe, e, t0);
+            y[e] = spec_mac<T, E, ODD, false>(spec_mul<T, E, ODD, false>(s[j].a, x[e], e, t0),
+                                              s[j].b, fe, e, t0);
         }
     }
 }
@@ -466,17 +477,30 @@ __device__ __forceinline__ void mac_adj(cx<T> (&y)[E], cx<T> (&z)[E], const cx<T
 #pragma unroll
         for (int j = 0; j < CH; ++j) {
             const int e = cb + j;
-            const cx<T> a = spec_mul<T, E, ODD, true>(s[j].a, x[e], e, t0);
-            const cx<T> b = spec_mul<T, E, ODD, true>(s[j].b, x[e], e, t0);
             if constexpr (ACC) {
-                y[e] = skip ? y[e] : y[e] + a;
-                z[e] = skip ? z[e] : z[e] + b;
+                const cx<T> a = spec_mac<T, E, ODD, true>(y[e], s[j].a, x[e], e, t0);
+                const cx<T> b = spec_mac<T, E, ODD, true>(z[e], s[j].b, x[e], e, t0);
+                y[e] = skip ? y[e] : a;
+                z[e] = skip ? z[e] : b;
             } else {
-                y[e] = a;
-                z[e] = b;
+                y[e] = spec_mul<T, E, ODD, true>(s[j].a, x[e], e, t0);
+                z[e] = spec_mul<T, E, ODD, true>(s[j].b, x[e], e, t0);
             }
         }
     }
+}
+
+// The transpose's four sums of R against the roots at one point k of the
+// thread: w[0] += r, w[1] += r W^k, w[2] += r W^(-n k), w[3] += r W^(-(n-1) k),
+// with the thread's share of each root (W^(j t)) applied afterwards, so per
+// point r w^e, r w^-(n e) and r w^-((n-1) e) (rne = w^(n e)).
+template <typename T, int E>
+__device__ __forceinline__ void accum_w(cx<T> (&w)[4], cx<T> r, cx<T> rne, int e) {
+    const cx<T> q = cmulc(r, rne);
+    w[0] = w[0] + r;
+    w[1] = mul_root_add<E>(w[1], r, e);
+    w[2] = w[2] + q;
+    w[3] = mul_root_add<E>(w[3], q, e);
 }
 
 // The column pass runs the two force channels one after the other: the
@@ -576,10 +600,10 @@ __device__ __forceinline__ void body_cols_fwd(int unit, int G, cx<T> *__restrict
                 const cx<T> A = unpack_even(v[e], m), B = unpack_odd(v[e], m);
                 const cx<T> f0 = slope_fix_at<T, E>(ph0, rne, e);
                 const cx<T> fM = slope_fix_at<T, E>(phM, rne, e);
-                const cx<T> ya = spec_mul<T, E, false, false>(pr.a, A, e, t0) +
-                                 spec_mul<T, E, false, false>(pr.b, f0, e, t0);
-                const cx<T> yb = spec_mul<T, E, false, false>(pm.a, B, e, t0) +
-                                 spec_mul<T, E, false, false>(pm.b, fM, e, t0);
+                const cx<T> ya = spec_mac<T, E, false, false>(
+                    spec_mul<T, E, false, false>(pr.a, A, e, t0), pr.b, f0, e, t0);
+                const cx<T> yb = spec_mac<T, E, false, false>(
+                    spec_mul<T, E, false, false>(pm.a, B, e, t0), pm.b, fM, e, t0);
                 y0[e] = cx<T>{ya.x - yb.y, ya.y + yb.x};   // ya + i yb
             }
         }
@@ -704,67 +728,117 @@ __device__ __forceinline__ void body_cols_adj(int unit, int G, cx<T> *__restrict
             va[1][e] = cx<T>{T(0), T(0)};
         }
     }
-    fft_fwd<L, E, T, true>(va[0], t, lds, tw);
-
+    // FP32 (SPLIT): V_r is transformed, meets the radial pairs, then V_p is
+    // transformed while the azimuthal pairs arrive in LDS.  FP64: both
+    // channels are transformed while the radial pairs arrive, then one
+    // sweep takes the radial pairs from LDS and the azimuthal ones from
+    // global memory, R entering the four sums point by point and the
+    // transposed correlation replacing V_r in place (in FP64 the split order
+    // keeps too many values live across a transform and spills).
+    constexpr bool SPLIT = sizeof(T) == 4;
     const cx2<T> *sl = PF ? spl + (size_t)gi * LP : nullptr;
     const cx2<T> *const gr = srad + (size_t)cl * ldspec;
     const cx2<T> *const gp = sazi + (size_t)cl * ldspec;
-    // radial half: xe = conj(E'_r) V_r, r = conj(Q_r) V_r
-    if constexpr (PF) prefetch_wait();
-    cx<T> xe[E], r[E];
-    mac_adj<T, L, E, false, PF, false>(xe, r, va[0], sl, gr, t);
-    if (packed) {
-        // bins 0 and M of the packed column 0, from the unpacked transforms
-        // of V_r (conjugate mirror points through LDS) and the bin-0 and
-        // bin-M radial pairs; V_p's bins 0 and M do not enter (the azimuthal
-        // spectra vanish there)
-#pragma unroll
-        for (int e = 0; e < E; ++e) lds.st_split(lds_pad(t), e * TH, va[0][e]);
-        lds_barrier();
-        if (is0) {
-            const bool t0 = t == 0;
-#pragma unroll
-            for (int e = 0; e < E; ++e) {
-                const int ix = spec_index<L, E>(t, e);
-                const cx2<T> pr = PF ? sl[ix] : gr[ix];
-                const cx2<T> pm = gp[ix];
-                const cx<T> m = lds.ld((L - (t + e * TH)) & (L - 1));
-                const cx<T> A = unpack_even(va[0][e], m), B = unpack_odd(va[0][e], m);
-                const cx<T> x0 = spec_mul<T, E, false, true>(pr.a, A, e, t0);
-                const cx<T> xM = spec_mul<T, E, false, true>(pm.a, B, e, t0);
-                const cx<T> r0 = spec_mul<T, E, false, true>(pr.b, A, e, t0);
-                const cx<T> rM = spec_mul<T, E, false, true>(pm.b, B, e, t0);
-                xe[e] = cx<T>{x0.x - xM.y, x0.y + xM.x};
-                r[e] = cx<T>{r0.x - rM.y, r0.y + rM.x};
-            }
-        }
-        lds_barrier();   // mirror reads done before the transform reuses buf
-    }
-    if constexpr (PF) {
-        // every wave has read its radial pairs: the azimuthal pairs go to the
-        // same LDS region while V_p is transformed
-        lds_barrier();
-        prefetch_spectra<T, L, E>(unit, G, H, ldspec, sazi, spl);
-    }
-    fft_fwd<L, E, T, true>(va[1], t, lds, tw);
-    // azimuthal half: xe += conj(E'_p) V_p, r += conj(Q_p) V_p
-    if constexpr (PF) prefetch_wait();
-    mac_adj<T, L, E, true, PF, true>(xe, r, va[1], sl, gp, t, is0);
-
     // The unnormalised inverse transform of R at rows 0, L-1, n, n-1:
     //   w[0] = sum R, w[1] = sum R W^k, w[2] = sum R W^(-n k),
     //   w[3] = sum R W^(-(n-1) k),
     // summed per thread against the roots (W^(j k) = W^(j t) r(j e)) and
     // turned into the thread's share with its phasors afterwards.
     cx<T> w[4] = {{T(0), T(0)}, {T(0), T(0)}, {T(0), T(0)}, {T(0), T(0)}};
+    cx<T> xe[E];
+    fft_fwd<L, E, T, true>(va[0], t, lds, tw);
+    if constexpr (SPLIT) {
+        // radial half: xe = conj(E'_r) V_r, r = conj(Q_r) V_r
+        if constexpr (PF) prefetch_wait();
+        cx<T> r[E];
+        mac_adj<T, L, E, false, PF, false>(xe, r, va[0], sl, gr, t);
+        if (packed) {
+            // bins 0 and M of the packed column 0, from the unpacked
+            // transforms of V_r (conjugate mirror points through LDS) and
+            // the bin-0 and bin-M radial pairs; V_p's bins 0 and M do not
+            // enter (the azimuthal spectra vanish there)
 #pragma unroll
-    for (int e = 0; e < E; ++e) {
-        // r W^(j k) over the thread's points: w^e, w^-(n e), w^-((n-1) e)
-        const cx<T> q = cmulc(r[e], root_ne<T, L, E>(twL, n_r, e));
-        w[0] = w[0] + r[e];
-        w[1] = w[1] + mul_root<E>(r[e], e);
-        w[2] = w[2] + q;
-        w[3] = w[3] + mul_root<E>(q, e);
+            for (int e = 0; e < E; ++e) lds.st_split(lds_pad(t), e * TH, va[0][e]);
+            lds_barrier();
+            if (is0) {
+                const bool t0 = t == 0;
+#pragma unroll
+                for (int e = 0; e < E; ++e) {
+                    const int ix = spec_index<L, E>(t, e);
+                    const cx2<T> pr = PF ? sl[ix] : gr[ix];
+                    const cx2<T> pm = gp[ix];
+                    const cx<T> m = lds.ld((L - (t + e * TH)) & (L - 1));
+                    const cx<T> A = unpack_even(va[0][e], m), B = unpack_odd(va[0][e], m);
+                    const cx<T> x0 = spec_mul<T, E, false, true>(pr.a, A, e, t0);
+                    const cx<T> xM = spec_mul<T, E, false, true>(pm.a, B, e, t0);
+                    const cx<T> r0 = spec_mul<T, E, false, true>(pr.b, A, e, t0);
+                    const cx<T> rM = spec_mul<T, E, false, true>(pm.b, B, e, t0);
+                    xe[e] = cx<T>{x0.x - xM.y, x0.y + xM.x};
+                    r[e] = cx<T>{r0.x - rM.y, r0.y + rM.x};
+                }
+            }
+            lds_barrier();   // mirror reads done before the transform reuses buf
+        }
+        if constexpr (PF) {
+            // every wave has read its radial pairs: the azimuthal pairs go to
+            // the same LDS region while V_p is transformed
+            lds_barrier();
+            prefetch_spectra<T, L, E>(unit, G, H, ldspec, sazi, spl);
+        }
+        fft_fwd<L, E, T, true>(va[1], t, lds, tw);
+        // azimuthal half: xe += conj(E'_p) V_p, r += conj(Q_p) V_p
+        if constexpr (PF) prefetch_wait();
+        mac_adj<T, L, E, true, PF, true>(xe, r, va[1], sl, gp, t, is0);
+#pragma unroll
+        for (int e = 0; e < E; ++e) accum_w<T, E>(w, r[e], root_ne<T, L, E>(twL, n_r, e), e);
+    } else {
+        fft_fwd<L, E, T, true>(va[1], t, lds, tw);
+        if (packed) {   // column 0 reads the conjugate mirror points from LDS
+#pragma unroll
+            for (int e = 0; e < E; ++e) lds.st_split(lds_pad(t), e * TH, va[0][e]);
+            lds_barrier();
+        }
+        if constexpr (PF) prefetch_wait();
+        constexpr int CH = mac_batch<T, E>();
+        const bool t0 = t == 0;
+#pragma unroll
+        for (int cb = 0; cb < E; cb += CH) {
+            cx2<T> pr[CH], pp[CH];
+#pragma unroll
+            for (int j = 0; j < CH; ++j) {
+                const int ix = spec_index<L, E>(t, cb + j);
+                pr[j] = PF ? sl[ix] : gr[ix];
+                pp[j] = gp[ix];
+            }
+#pragma unroll
+            for (int j = 0; j < CH; ++j) {
+                const int e = cb + j;
+                cx<T> x, r;
+                if (is0) {
+                    // bins 0 and M of the packed column (bin M's radial pairs
+                    // at the azimuthal place); V_p's bins 0 and M do not enter
+                    const cx<T> m = lds.ld((L - (t + e * TH)) & (L - 1));
+                    const cx<T> A = unpack_even(va[0][e], m), B = unpack_odd(va[0][e], m);
+                    const cx<T> x0 = spec_mul<T, E, false, true>(pr[j].a, A, e, t0);
+                    const cx<T> xM = spec_mul<T, E, false, true>(pp[j].a, B, e, t0);
+                    const cx<T> r0 = spec_mul<T, E, false, true>(pr[j].b, A, e, t0);
+                    const cx<T> rM = spec_mul<T, E, false, true>(pp[j].b, B, e, t0);
+                    x = cx<T>{x0.x - xM.y, x0.y + xM.x};
+                    r = cx<T>{r0.x - rM.y, r0.y + rM.x};
+                } else {
+                    // conj(E'_r) V_r + conj(E'_p) V_p, conj(Q_r) V_r + conj(Q_p) V_p
+                    x = spec_mac<T, E, true, true>(
+                        spec_mul<T, E, false, true>(pr[j].a, va[0][e], e, t0), pp[j].a,
+                        va[1][e], e, t0);
+                    r = spec_mac<T, E, true, true>(
+                        spec_mul<T, E, false, true>(pr[j].b, va[0][e], e, t0), pp[j].b,
+                        va[1][e], e, t0);
+                }
+                xe[e] = x;
+                accum_w<T, E>(w, r, root_ne<T, L, E>(twL, n_r, e), e);
+            }
+        }
+        if (packed) lds_barrier();   // mirror reads done before buf is reused
     }
     {
         const cx<T> wt = twL[t];

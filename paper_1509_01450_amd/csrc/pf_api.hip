@@ -394,6 +394,7 @@ int pf_plan_set_schedule(pf_plan h, const int in[8]) {
         pf::set_error("plan not built");
         return PF_ESTATE;
     }
+    pf::batched_forget(p.uid);   // batches group disks by their launch shapes
     p.sched.rows = r1;
     p.sched.rows2 = r2;
     p.sched.cols = c;
@@ -602,14 +603,18 @@ int pf_forces_timed(pf_plan h, int backward, const void *in0, const void *in1, v
     return rc;
 }
 
-int pf_forces_batched(int n, const pf_plan *plans, const void *const *sigma, void *const *f_r,
-                      void *const *f_phi, void *stream) {
-    pf::clear_error();
+}  // extern "C"
+
+namespace {
+
+// Arguments of a batched call: every plan built, single-grid, one precision,
+// one device; ps[k] = the plans.
+int check_batch(int n, const pf_plan *plans, const void *const *sigma, void *const *f_r,
+                void *const *f_phi, const Plan **ps) {
     if (n < 1 || n > 4096 || !plans || !sigma || !f_r || !f_phi) {
         pf::set_error("bad batch arguments (n = %d)", n);
         return PF_EINVAL;
     }
-    std::vector<const Plan *> ps(n);
     for (int k = 0; k < n; ++k) {
         int rc = check_call(plans[k], sigma[k], f_r[k], f_phi[k]);
         if (rc) return rc;
@@ -627,7 +632,21 @@ int pf_forces_batched(int n, const pf_plan *plans, const void *const *sigma, voi
             return PF_EINVAL;
         }
     }
+    return PF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pf_forces_batched(int n, const pf_plan *plans, const void *const *sigma, void *const *f_r,
+                      void *const *f_phi, void *stream) {
+    pf::clear_error();
+    std::vector<const Plan *> ps(n > 0 && n <= 4096 ? n : 0);
+    int rc = check_batch(n, plans, sigma, f_r, f_phi, ps.data());
+    if (rc) return rc;
     return pf::batched_forces(ps, sigma, f_r, f_phi, (hipStream_t)stream);
 }
+
 
 }  // extern "C"

@@ -1,33 +1,30 @@
-// pf_batched.hip -- the many-disk forward map as three grouped launches, and
-// the launch-shape autotuner.
+// pf_batched.hip -- the many-disk forward map: grouped launches over all disks
+// of a batch, each disk at the launch shapes tuned for its sizes.
 //
-// Batched path.  The disks of a batch (sizes may differ, one precision) run
-// as three launches, one per pass, each covering every disk: a workgroup
-// handles one unit of one disk -- G rows of the phi transform (pass A or C)
-// or G columns of the column pass (pass B) -- found through a block -> disk
-// table, and selects the body of the disk's transform length with a switch.
-// The launch boundaries order the passes, and every launch fills the device
-// with the units of all disks at the occupancy of the single-disk kernels.
-// Workgroups have 256 threads; rows take 8 points per thread, columns 16
-// (FP32) or 8 (FP64), so G = 256 / (length / points).  The descriptor and
-// block tables are built once per batch signature and refreshed when the
-// field pointers change.
+// The disks of a batch (sizes may differ, one precision) are grouped per
+// pass into classes of equal transform length and launch shape: for pass A
+// the one-channel row shape of the disk's schedule, for pass C the
+// two-channel one, for pass B the column shape.  Each class is one launch
+// whose workgroups cover every unit (G rows or G columns) of every disk of
+// the class; a workgroup finds its disk by a binary search over the class's
+// entry table (disk, first block), then runs the pass body of the
+// single-disk kernels at that shape.  Pass A of every class, then pass B,
+// then pass C: the launch boundaries order the passes.  For the 64-disk
+// workload (N_r in {256 ... 1024}, N_phi in {256 ... 2048}) that is up to
+// four row classes and three column classes per pass instead of one kernel
+// holding every size at one register budget.
 //
-// Autotuner.  For each transform size and precision, candidate launch
-// shapes (points per thread E -- the radix of the Stockham stages -- and
-// transforms per workgroup G) are timed on the device with HIP events; the
-// fastest is kept in memory and in a JSON file (PF_AUTOTUNE_CACHE, default
-// ~/.cache/pf/autotune.json).  PF_AUTOTUNE=0 disables tuning.
-#include <sys/stat.h>
-#include <unistd.h>
-
+// The tables (one descriptor per disk and the three entry tables) go to the
+// device through small upload kernels that take the bytes as kernel
+// arguments: no host buffer has to outlive the call and nothing waits.
+// pf_forces_batched keeps them in device memory it allocates once per set of
+// plans (refreshed when the field pointers change).
 #include <algorithm>
 #include <cstdio>
-#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
-#include <string>
+#include <vector>
 
 #include "pass_bodies.hpp"
 #include "pf_batched.hpp"
@@ -35,17 +32,11 @@
 namespace pf {
 
 // ===========================================================================
-// Grouped batched kernels
+// Device side
 // ===========================================================================
-constexpr int kGroupThreads = 256;
-constexpr int kRowE = 8;
-template <typename T>
-constexpr int col_e() { return sizeof(T) == 8 ? 8 : 16; }
-
 template <typename T>
 struct GDisk {
     int n_r, M, L, H, ldspec;
-    int base[3];   // first workgroup of the disk in each pass's launch
     T ca, c0, cn;
     const T *sigma;
     T *fr, *fp;
@@ -55,124 +46,188 @@ struct GDisk {
     const cx<T> *twN, *twL;
 };
 
-template <typename T, int M>
-__device__ __forceinline__ void group_rows(int pass, int unit, const GDisk<T> &d, cx<T> *buf) {
-    constexpr int G = kGroupThreads / (M / kRowE);
-    if (pass == 0)
-        body_rows_r2c<T, M, kRowE, 1>(unit, G, buf, d.sigma, nullptr, d.n_r, d.S, d.twN);
+// One disk in one class launch: its descriptor and its first workgroup.
+struct GEntry {
+    int disk;
+    int first;
+};
+
+// The entry of the calling workgroup: the last one whose first block is at
+// or below blockIdx.x (entries sorted by first block, n >= 1).  Wave-uniform.
+__device__ __forceinline__ GEntry find_entry(const GEntry *__restrict__ ent, int n) {
+    const int b = blockIdx.x;
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (ent[mid].first <= b)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return ent[lo];
+}
+
+// Pass A (C = 1) or pass C (C = 2) of the disks of one class: G rows per
+// workgroup (G = blockDim.x / (M / E)), LDS C G padded_len(M) complex.
+template <typename T, int M, int E, int C>
+__global__ __launch_bounds__(512) void k_grp_rows(const GDisk<T> *__restrict__ desc,
+                                                  const GEntry *__restrict__ ent, int n_ent) {
+    extern __shared__ unsigned char smem_raw[];
+    const GEntry en = find_entry(ent, n_ent);
+    const GDisk<T> &d = desc[en.disk];
+    const int unit = blockIdx.x - en.first;
+    const int G = blockDim.x / (M / E);
+    cx<T> *const buf = reinterpret_cast<cx<T> *>(smem_raw);
+    if constexpr (C == 1)
+        body_rows_r2c<T, M, E, 1>(unit, G, buf, d.sigma, nullptr, d.n_r, d.S, d.twN);
     else
-        body_rows_c2r<T, M, kRowE, 2>(unit, G, buf, reinterpret_cast<const cx<T> *>(d.Z), d.n_r,
-                                      d.fr, d.fp, d.twN);
+        body_rows_c2r<T, M, E, 2>(unit, G, buf, reinterpret_cast<const cx<T> *>(d.Z), d.n_r,
+                                  d.fr, d.fp, d.twN);
 }
 
-// Pass A (pass = 0) or C (pass = 2) of every disk: block -> (disk, unit).
-template <typename T>
-__global__ __launch_bounds__(kGroupThreads) void k_group_rows(const GDisk<T> *__restrict__ disks,
-                                                              const int *__restrict__ bdisk,
-                                                              int pass) {
-    __shared__ cx<T> buf[2 * padded_len(kGroupThreads * kRowE)];
-    const GDisk<T> &d = disks[bdisk[blockIdx.x]];
-    const int unit = blockIdx.x - d.base[pass];
-    switch (d.M) {
-        case 64: group_rows<T, 64>(pass, unit, d, buf); break;
-        case 128: group_rows<T, 128>(pass, unit, d, buf); break;
-        case 256: group_rows<T, 256>(pass, unit, d, buf); break;
-        case 512: group_rows<T, 512>(pass, unit, d, buf); break;
-        case 1024: group_rows<T, 1024>(pass, unit, d, buf); break;
-        case 2048: group_rows<T, 2048>(pass, unit, d, buf); break;
-    }
+// Column groups of a disk are remapped as in the single-disk kernels: a
+// disk's blocks start at a multiple of 8 and run round-robin over the 8
+// XCDs, and each XCD gets a contiguous range of column groups.
+__device__ __forceinline__ int grp_xcd(int b, int n_groups) {
+    const int per_xcd = (n_groups + 7) / 8;
+    return (b & 7) * per_xcd + (b >> 3);
 }
 
-// Column sizes of the grouped pass B whose columns have at least 64 threads
-// prefetch their radial spectrum pairs into an LDS array of their own while
-// the column is transformed (as the single-plan kernels); this is the
-// largest G spec_prefetch_len<L, E>() over those sizes.
-template <typename T>
-constexpr int group_prefetch_len() {
-    constexpr int E = col_e<T>();
-    int n = 64;
-    for (int L = 128; L <= 4096; L *= 2) {
-        const int th = L / E;
-        if (th >= 64 && th <= kGroupThreads) {
-            const int lp = ((L / 2 + 1) + th - 1) / th * th;
-            const int g = kGroupThreads / th;
-            n = g * lp > n ? g * lp : n;
-        }
-    }
-    return n;
+// Pass B of the disks of one class, G fixed at compile time: the transform
+// buffer and the spectrum prefetch region are static LDS arrays (as the
+// single-disk k_cols_fwd_pf).
+template <typename T, int L, int E, int G>
+__global__ __launch_bounds__(512) void k_grp_cols_pf(const GDisk<T> *__restrict__ desc,
+                                                     const GEntry *__restrict__ ent, int n_ent) {
+    __shared__ cx<T> fbuf[G * padded_len(L)];
+    __shared__ cx2<T> spl[G * spec_prefetch_len<L, E>()];
+    const GEntry en = find_entry(ent, n_ent);
+    const GDisk<T> &d = desc[en.disk];
+    const int n_groups = (d.H + G - 1) / G;
+    const int grp = grp_xcd(blockIdx.x - en.first, n_groups);
+    if (grp >= n_groups) return;   // whole workgroup leaves together
+    body_cols_fwd<T, L, E, true>(grp, G, fbuf, d.S, d.Z, d.spec, d.H, d.n_r, d.n_r, d.ldspec,
+                                 d.ca, d.c0, d.cn, d.twL, spl);
 }
 
-template <typename T, int L>
-__device__ __forceinline__ void group_cols(int unit, const GDisk<T> &d, cx<T> *buf,
-                                           cx2<T> *spl) {
-    constexpr int E = col_e<T>();
-    if constexpr (L / E <= kGroupThreads) {
-        constexpr int G = kGroupThreads / (L / E);
-        constexpr bool PF = L / E >= 64;
-        static_assert(!PF || G * spec_prefetch_len<L, E>() <= group_prefetch_len<T>(), "LDS");
-        body_cols_fwd<T, L, E, PF>(unit, G, buf, d.S, d.Z, d.spec, d.H, d.n_r, d.n_r, d.ldspec,
-                                   d.ca, d.c0, d.cn, d.twL, spl);
-    }
+// Pass B for shapes without a static instance: one dynamic LDS array (FP32
+// prefetches into its tail, as k_cols_fwd).
+template <typename T, int L, int E>
+__global__ __launch_bounds__(512) void k_grp_cols(const GDisk<T> *__restrict__ desc,
+                                                  const GEntry *__restrict__ ent, int n_ent) {
+    extern __shared__ unsigned char smem_raw[];
+    const GEntry en = find_entry(ent, n_ent);
+    const GDisk<T> &d = desc[en.disk];
+    const int G = blockDim.x / (L / E);
+    const int n_groups = (d.H + G - 1) / G;
+    const int grp = grp_xcd(blockIdx.x - en.first, n_groups);
+    if (grp >= n_groups) return;
+    cx<T> *const buf = reinterpret_cast<cx<T> *>(smem_raw);
+    body_cols_fwd<T, L, E, sizeof(T) == 4>(
+        grp, G, buf, d.S, d.Z, d.spec, d.H, d.n_r, d.n_r, d.ldspec, d.ca, d.c0, d.cn, d.twL,
+        reinterpret_cast<cx2<T> *>(buf + (size_t)G * padded_len(L)));
 }
 
-// Pass B of every disk.  Two waves per SIMD: the register budget of the
-// largest column body (the switch holds every size) must not exceed 256.
-template <typename T>
-__global__ __launch_bounds__(kGroupThreads) __attribute__((amdgpu_waves_per_eu(2)))
-void k_group_cols(const GDisk<T> *__restrict__ disks, const int *__restrict__ bdisk) {
-    __shared__ cx<T> buf[padded_len(kGroupThreads * col_e<T>())];
-    __shared__ cx2<T> spl[group_prefetch_len<T>()];
-    const GDisk<T> &d = disks[bdisk[blockIdx.x]];
-    const int unit = blockIdx.x - d.base[1];
-    switch (d.L) {
-        case 128: group_cols<T, 128>(unit, d, buf, spl); break;
-        case 256: group_cols<T, 256>(unit, d, buf, spl); break;
-        case 512: group_cols<T, 512>(unit, d, buf, spl); break;
-        case 1024: group_cols<T, 1024>(unit, d, buf, spl); break;
-        case 2048: group_cols<T, 2048>(unit, d, buf, spl); break;
-        case 4096: group_cols<T, 4096>(unit, d, buf, spl); break;
-    }
+// Table upload: the bytes travel as the kernel's argument.
+struct UpChunk {
+    static constexpr int kWords = 766;   // 3 KB of payload per launch
+    unsigned int off, words;             // destination offset and length, in words
+    unsigned int w[kWords];
+};
+
+__global__ __launch_bounds__(256) void k_upload(UpChunk c, unsigned int *__restrict__ dst) {
+    for (unsigned int i = threadIdx.x; i < c.words; i += blockDim.x) dst[c.off + i] = c.w[i];
 }
 
 namespace {
 
-// sizes the grouped kernels instantiate (and whose workgroups fit 256 threads)
+// ===========================================================================
+// Host side
+// ===========================================================================
+// Sizes the grouped kernels instantiate.
 bool batch_size_ok(const Plan &p) {
-    const int ec = p.opts.dtype == PF_F64 ? col_e<double>() : col_e<float>();
-    return p.M >= 64 && p.M <= 2048 && p.L >= 128 && p.L <= 4096 &&
-           p.L / ec <= kGroupThreads;
+    return p.M >= 64 && p.M <= 2048 && p.L >= 128 && p.L <= 4096;
 }
 
-struct BatchEntry {
-    std::vector<int64_t> uids;
-    int n = 0, device = -1;
-    bool f64 = false;
-    int nblk[3] = {0, 0, 0};
-    std::vector<unsigned char> h_desc;   // GDisk<T>[n]
-    void *d_desc = nullptr;
-    int *d_map = nullptr;                // block -> disk for pass A, B, C in turn
-
-    void release() {
-        if (d_desc) (void)hipFree(d_desc);
-        if (d_map) (void)hipFree(d_map);
-        d_desc = nullptr;
-        d_map = nullptr;
-    }
+// One class launch: a kernel shape and the range [e0, e1) of its pass's
+// entry table.
+struct GClass {
+    int pass;       // 0: pass A, 1: pass B, 2: pass C
+    int n;          // transform length: M for rows, L for columns
+    Shape s;
+    int e0, e1;     // entries
+    int blocks;     // total workgroups
 };
 
-std::mutex g_batch_mu;
-std::map<std::vector<int64_t>, BatchEntry> g_batches;
+// blocks of one disk in one pass at shape s
+int disk_blocks(const Plan &p, int pass, Shape s) {
+    if (pass == 1) {
+        const int n_groups = (p.H + s.G - 1) / s.G;
+        return (n_groups + 7) / 8 * 8;   // whole rounds of the 8 XCDs
+    }
+    return (p.n_r + s.G - 1) / s.G;
+}
+
+Shape pass_shape(const Plan &p, int pass) {
+    return pass == 0 ? p.sched.rows : pass == 1 ? p.sched.cols : p.sched.rows2;
+}
+
+// The tables of one batch from the plans' tuned schedules: for each pass q,
+// the entries ent[q n ... q n + n - 1] ordered by class (transform length,
+// then shape), and the classes, cls[0 ... *n_cls - 1].  order[n] is working
+// space.  Allocates nothing (an insertion sort: batches are small).
+void make_layout(const Plan *const *plans, int n, GEntry *ent, GClass *cls, int *n_cls,
+                 int *order) {
+    int nc = 0;
+    for (int q = 0; q < 3; ++q) {
+        auto key = [&](int k) {
+            const Shape s = pass_shape(*plans[k], q);
+            const int len = q == 1 ? plans[k]->L : plans[k]->M;
+            return std::make_tuple(len, s.E, s.G, k);
+        };
+        for (int k = 0; k < n; ++k) {
+            int j = k;
+            while (j > 0 && key(k) < key(order[j - 1])) {
+                order[j] = order[j - 1];
+                --j;
+            }
+            order[j] = k;
+        }
+        auto same = [&](int a, int b) {
+            return std::get<0>(key(a)) == std::get<0>(key(b)) &&
+                   std::get<1>(key(a)) == std::get<1>(key(b)) &&
+                   std::get<2>(key(a)) == std::get<2>(key(b));
+        };
+        int i = 0;
+        while (i < n) {
+            int j = i;
+            GClass c;
+            c.pass = q;
+            c.n = q == 1 ? plans[order[i]]->L : plans[order[i]]->M;
+            c.s = pass_shape(*plans[order[i]], q);
+            c.e0 = q * n + i;
+            int blocks = 0;
+            while (j < n && same(order[j], order[i])) {
+                ent[q * n + j] = GEntry{order[j], blocks};
+                blocks += disk_blocks(*plans[order[j]], q, c.s);
+                ++j;
+            }
+            c.e1 = q * n + j;
+            c.blocks = blocks;
+            cls[nc++] = c;
+            i = j;
+        }
+    }
+    *n_cls = nc;
+}
 
 template <typename T>
-int make_entry_t(BatchEntry &e, const std::vector<const Plan *> &plans) {
-    const int n = (int)plans.size();
-    e.h_desc.assign(sizeof(GDisk<T>) * n, 0);
-    GDisk<T> *desc = reinterpret_cast<GDisk<T> *>(e.h_desc.data());
-    std::vector<int> map[3];
-    constexpr int EC = col_e<T>();
+void make_desc(const Plan *const *plans, int n, const void *const *sigma, void *const *f_r,
+               void *const *f_phi, GDisk<T> *desc) {
     for (int k = 0; k < n; ++k) {
         const Plan &p = *plans[k];
         GDisk<T> &d = desc[k];
+        memset(&d, 0, sizeof(d));
         d.n_r = p.n_r;
         d.M = p.M;
         d.L = p.L;
@@ -187,56 +242,193 @@ int make_entry_t(BatchEntry &e, const std::vector<const Plan *> &plans) {
         d.spec = (const cx2<T> *)p.spec;
         d.twN = (const cx<T> *)p.twN;
         d.twL = (const cx<T> *)p.twL;
-        const int GA = kGroupThreads / (p.M / kRowE);
-        const int GB = kGroupThreads / (p.L / EC);
-        const int units[3] = {(p.n_r + GA - 1) / GA, (p.H + GB - 1) / GB,
-                              (p.n_r + GA - 1) / GA};
-        for (int q = 0; q < 3; ++q) {
-            d.base[q] = (int)map[q].size();
-            map[q].insert(map[q].end(), units[q], k);
-        }
+        d.sigma = (const T *)sigma[k];
+        d.fr = (T *)f_r[k];
+        d.fp = (T *)f_phi[k];
     }
-    size_t total = 0;
-    for (int q = 0; q < 3; ++q) {
-        e.nblk[q] = (int)map[q].size();
-        total += map[q].size();
+}
+
+// bytes (a multiple of 4) to device memory at dst, through upload launches
+int upload(const void *src, size_t bytes, void *dst, hipStream_t st) {
+    const unsigned int *w = (const unsigned int *)src;
+    const size_t words = bytes / 4;
+    UpChunk c;
+    for (size_t off = 0; off < words; off += UpChunk::kWords) {
+        c.off = (unsigned int)off;
+        c.words = (unsigned int)std::min<size_t>(UpChunk::kWords, words - off);
+        memcpy(c.w, w + off, (size_t)c.words * 4);
+        hipLaunchKernelGGL(k_upload, dim3(1), dim3(256), 0, st, c, (unsigned int *)dst);
+        PF_HIP(hipGetLastError());
     }
-    std::vector<int> all;
-    all.reserve(total);
-    for (int q = 0; q < 3; ++q) all.insert(all.end(), map[q].begin(), map[q].end());
-    PF_HIP(hipMalloc(&e.d_desc, e.h_desc.size()));
-    PF_HIP(hipMalloc(&e.d_map, sizeof(int) * total));
-    PF_HIP(hipMemcpy(e.d_map, all.data(), sizeof(int) * total, hipMemcpyHostToDevice));
+    return PF_OK;
+}
+
+template <typename K>
+int allow_lds(K kern, size_t lds) {
+    if (lds > 64 * 1024)
+        PF_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     return PF_OK;
 }
 
 template <typename T>
-bool update_pointers(BatchEntry &e, const void *const *sigma, void *const *f_r,
-                     void *const *f_phi) {
-    GDisk<T> *desc = reinterpret_cast<GDisk<T> *>(e.h_desc.data());
-    bool changed = false;
-    for (int k = 0; k < e.n; ++k) {
-        GDisk<T> &d = desc[k];
-        if (d.sigma != sigma[k] || d.fr != f_r[k] || d.fp != f_phi[k]) {
-            d.sigma = (const T *)sigma[k];
-            d.fr = (T *)f_r[k];
-            d.fp = (T *)f_phi[k];
-            changed = true;
+struct GLaunch {
+    const GDisk<T> *desc;
+    const GEntry *ent;   // the class's entries
+    int n_ent, blocks;
+    hipStream_t st;
+
+    template <int M, int E, int C>
+    int rows(int G) {
+        if constexpr (E <= M) {
+            const size_t lds = (size_t)C * G * padded_len(M) * sizeof(cx<T>);
+            int rc = allow_lds(k_grp_rows<T, M, E, C>, lds);
+            if (rc) return rc;
+            hipLaunchKernelGGL((k_grp_rows<T, M, E, C>), dim3(blocks), dim3(G * (M / E)), lds, st,
+                               desc, ent, n_ent);
+            PF_HIP(hipGetLastError());
+            return PF_OK;
         }
+        set_error("row transform of %d points cannot take %d points per thread", M, E);
+        return PF_EUNSUPPORTED;
     }
-    return changed;
+    template <int M, int C>
+    int rows_e(Shape s) {
+        switch (s.E) {
+            case 4: return rows<M, 4, C>(s.G);
+            case 8: return rows<M, 8, C>(s.G);
+            case 16: return rows<M, 16, C>(s.G);
+        }
+        set_error("bad points per thread %d", s.E);
+        return PF_EUNSUPPORTED;
+    }
+    template <int M>
+    int rows1(Shape s) { return rows_e<M, 1>(s); }
+    template <int M>
+    int rows2(Shape s) { return rows_e<M, 2>(s); }
+    template <int L, int E, int G>
+    bool cols_pf() {
+        constexpr int TH = L / E;
+        if constexpr (TH >= 64 && G * TH <= 512 &&
+                      (size_t)G * padded_len(L) * sizeof(cx<T>) +
+                              (size_t)G * spec_prefetch_len<L, E>() * sizeof(cx2<T>) <=
+                          (size_t)144 * 1024) {
+            hipLaunchKernelGGL((k_grp_cols_pf<T, L, E, G>), dim3(blocks), dim3(G * TH), 0, st,
+                               desc, ent, n_ent);
+            return true;
+        }
+        return false;
+    }
+    template <int L, int E>
+    int cols(int G) {
+        if constexpr (E <= L) {
+            const bool done = G == 1   ? cols_pf<L, E, 1>()
+                              : G == 2 ? cols_pf<L, E, 2>()
+                              : G == 4 ? cols_pf<L, E, 4>()
+                                       : false;
+            if (!done) {
+                const size_t lds = cols_lds_bytes(L, E, G, sizeof(T) == 8, sizeof(T) == 4);
+                int rc = allow_lds(k_grp_cols<T, L, E>, lds);
+                if (rc) return rc;
+                hipLaunchKernelGGL((k_grp_cols<T, L, E>), dim3(blocks), dim3(G * (L / E)), lds,
+                                   st, desc, ent, n_ent);
+            }
+            PF_HIP(hipGetLastError());
+            return PF_OK;
+        }
+        set_error("column transform of %d points cannot take %d points per thread", L, E);
+        return PF_EUNSUPPORTED;
+    }
+    template <int L>
+    int cols_e(Shape s) {
+        switch (s.E) {
+            case 8: return cols<L, 8>(s.G);
+            case 16: return cols<L, 16>(s.G);
+        }
+        set_error("bad points per thread %d", s.E);
+        return PF_EUNSUPPORTED;
+    }
+};
+
+#define PF_SWITCH_ROWS(v, F, ...)                                                        \
+    switch (v) {                                                                         \
+        case 64: return F<64>(__VA_ARGS__);                                              \
+        case 128: return F<128>(__VA_ARGS__);                                            \
+        case 256: return F<256>(__VA_ARGS__);                                            \
+        case 512: return F<512>(__VA_ARGS__);                                            \
+        case 1024: return F<1024>(__VA_ARGS__);                                          \
+        case 2048: return F<2048>(__VA_ARGS__);                                          \
+        default: set_error("unsupported batched row length %d", v); return PF_EUNSUPPORTED; \
+    }
+#define PF_SWITCH_COLS(v, F, ...)                                                        \
+    switch (v) {                                                                         \
+        case 128: return F<128>(__VA_ARGS__);                                            \
+        case 256: return F<256>(__VA_ARGS__);                                            \
+        case 512: return F<512>(__VA_ARGS__);                                            \
+        case 1024: return F<1024>(__VA_ARGS__);                                          \
+        case 2048: return F<2048>(__VA_ARGS__);                                          \
+        case 4096: return F<4096>(__VA_ARGS__);                                          \
+        default: set_error("unsupported batched column length %d", v); return PF_EUNSUPPORTED; \
+    }
+
+template <typename T>
+int launch_class(const GClass &c, const void *desc, const GEntry *ent, hipStream_t st) {
+    GLaunch<T> g{(const GDisk<T> *)desc, ent + c.e0, c.e1 - c.e0, c.blocks, st};
+    if (c.pass == 1) {
+        PF_SWITCH_COLS(c.n, g.template cols_e, c.s);
+    }
+    if (c.pass == 0) {
+        PF_SWITCH_ROWS(c.n, g.template rows1, c.s);
+    }
+    PF_SWITCH_ROWS(c.n, g.template rows2, c.s);
+}
+
+// ---- pf_forces_batched: tables in device memory allocated per set of plans
+struct BatchEntry {
+    int n = 0, n_cls = 0;
+    bool f64 = false;
+    std::vector<GEntry> ent;             // 3 n
+    std::vector<GClass> cls;             // up to 3 n
+    std::vector<unsigned char> h_desc;   // GDisk<T>[n], as last uploaded
+    void *d_tab = nullptr;               // descriptors, then the entries
+    size_t desc_bytes = 0;
+
+    void release() {
+        if (d_tab) (void)hipFree(d_tab);
+        d_tab = nullptr;
+    }
+};
+
+std::mutex g_batch_mu;
+std::map<std::vector<int64_t>, BatchEntry> g_batches;
+
+size_t desc_size(bool f64, int n) {
+    return (f64 ? sizeof(GDisk<double>) : sizeof(GDisk<float>)) * (size_t)n;
+}
+
+int check_plans(const Plan *const *plans, int n) {
+    for (int k = 0; k < n; ++k) {
+        if (!batch_size_ok(*plans[k])) {
+            set_error("batched path needs 128 <= n_phi <= 4096 and 33 <= n_r <= 2048 "
+                      "(disk %d: %d x %d)", k, plans[k]->n_r, plans[k]->n_phi);
+            return PF_EUNSUPPORTED;
+        }
+        for (int j = 0; j < k; ++j)
+            if (plans[j] == plans[k]) {
+                set_error("a plan appears twice in one batch (plans own their workspace)");
+                return PF_EINVAL;
+            }
+    }
+    return PF_OK;
 }
 
 template <typename T>
-int launch_group(const BatchEntry &e, hipStream_t st) {
-    const GDisk<T> *desc = (const GDisk<T> *)e.d_desc;
-    const int *mA = e.d_map, *mB = mA + e.nblk[0], *mC = mB + e.nblk[1];
-    hipLaunchKernelGGL(k_group_rows<T>, dim3(e.nblk[0]), dim3(kGroupThreads), 0, st, desc, mA, 0);
-    PF_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_group_cols<T>, dim3(e.nblk[1]), dim3(kGroupThreads), 0, st, desc, mB);
-    PF_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_group_rows<T>, dim3(e.nblk[2]), dim3(kGroupThreads), 0, st, desc, mC, 2);
-    PF_HIP(hipGetLastError());
+int launch_classes(const GClass *cls, int n_cls, const void *desc, const GEntry *ent,
+                   hipStream_t st) {
+    for (int c = 0; c < n_cls; ++c) {
+        const int rc = launch_class<T>(cls[c], desc, ent, st);
+        if (rc) return rc;
+    }
     return PF_OK;
 }
 
@@ -246,50 +438,48 @@ int batched_forces(const std::vector<const Plan *> &plans, const void *const *si
                    void *const *f_r, void *const *f_phi, hipStream_t st) {
     const int n = (int)plans.size();
     const bool f64 = plans[0]->opts.dtype == PF_F64;
+    int rc = check_plans(plans.data(), n);
+    if (rc) return rc;
     std::vector<int64_t> key(n);
-    for (int k = 0; k < n; ++k) {
-        if (!batch_size_ok(*plans[k])) {
-            set_error("batched path needs 128 <= n_phi <= 4096 and 33 <= n_r <= %d "
-                      "(disk %d: %d x %d)",
-                      f64 ? 1024 : 2048, k, plans[k]->n_r, plans[k]->n_phi);
-            return PF_EUNSUPPORTED;
-        }
-        key[k] = plans[k]->uid;
-    }
-    {
-        std::vector<int64_t> s = key;
-        std::sort(s.begin(), s.end());
-        if (std::adjacent_find(s.begin(), s.end()) != s.end()) {
-            set_error("a plan appears twice in one batch (plans own their workspace)");
-            return PF_EINVAL;
-        }
-    }
+    for (int k = 0; k < n; ++k) key[k] = plans[k]->uid;
     std::lock_guard<std::mutex> g(g_batch_mu);
     auto it = g_batches.find(key);
     if (it == g_batches.end()) {
         BatchEntry e;
-        e.uids = key;
         e.n = n;
         e.f64 = f64;
-        e.device = plans[0]->device;
-        int rc = f64 ? make_entry_t<double>(e, plans) : make_entry_t<float>(e, plans);
+        e.ent.resize(3 * (size_t)n);
+        e.cls.resize(3 * (size_t)n);
+        std::vector<int> order(n);
+        make_layout(plans.data(), n, e.ent.data(), e.cls.data(), &e.n_cls, order.data());
+        e.desc_bytes = desc_size(f64, n);
+        hipError_t he = hipMalloc(&e.d_tab, e.desc_bytes + e.ent.size() * sizeof(GEntry));
+        if (he != hipSuccess) {
+            set_error("batch table allocation failed: %s", hipGetErrorString(he));
+            return PF_ENOMEM;
+        }
+        rc = upload(e.ent.data(), e.ent.size() * sizeof(GEntry),
+                    (unsigned char *)e.d_tab + e.desc_bytes, st);
         if (rc) {
             e.release();
             return rc;
         }
-        it = g_batches.emplace(key, e).first;
+        it = g_batches.emplace(key, std::move(e)).first;
     }
     BatchEntry &e = it->second;
-    const bool changed = f64 ? update_pointers<double>(e, sigma, f_r, f_phi)
-                             : update_pointers<float>(e, sigma, f_r, f_phi);
-    if (changed) {
-        // the launches read the descriptor table; the host copy must outlive
-        // the transfer, so wait for it
-        PF_HIP(hipMemcpyAsync(e.d_desc, e.h_desc.data(), e.h_desc.size(), hipMemcpyHostToDevice,
-                              st));
-        PF_HIP(hipStreamSynchronize(st));
+    std::vector<unsigned char> desc(e.desc_bytes);
+    if (f64)
+        make_desc<double>(plans.data(), n, sigma, f_r, f_phi, (GDisk<double> *)desc.data());
+    else
+        make_desc<float>(plans.data(), n, sigma, f_r, f_phi, (GDisk<float> *)desc.data());
+    if (desc != e.h_desc) {
+        rc = upload(desc.data(), desc.size(), e.d_tab, st);
+        if (rc) return rc;
+        e.h_desc.swap(desc);
     }
-    return f64 ? launch_group<double>(e, st) : launch_group<float>(e, st);
+    const GEntry *ent = (const GEntry *)((unsigned char *)e.d_tab + e.desc_bytes);
+    return f64 ? launch_classes<double>(e.cls.data(), e.n_cls, e.d_tab, ent, st)
+               : launch_classes<float>(e.cls.data(), e.n_cls, e.d_tab, ent, st);
 }
 
 void batched_forget(int64_t uid) {
@@ -302,259 +492,6 @@ void batched_forget(int64_t uid) {
             ++it;
         }
     }
-}
-
-// ===========================================================================
-// Autotuner
-// ===========================================================================
-namespace {
-
-std::mutex g_tune_mu;
-std::map<std::string, Shape> g_tune;
-bool g_tune_loaded = false;
-
-std::string cache_path() {
-    const char *p = getenv("PF_AUTOTUNE_CACHE");
-    if (p && *p) return p;
-    const char *h = getenv("HOME");
-    if (!h || !*h) return "";
-    return std::string(h) + "/.cache/pf/autotune.json";
-}
-
-// file format: one JSON object {"key": [E, G], ...}
-void load_cache() {
-    if (g_tune_loaded) return;
-    g_tune_loaded = true;
-    const std::string path = cache_path();
-    if (path.empty()) return;
-    FILE *f = fopen(path.c_str(), "r");
-    if (!f) return;
-    std::string s;
-    char buf[4096];
-    size_t n;
-    while ((n = fread(buf, 1, sizeof(buf), f)) > 0) s.append(buf, n);
-    fclose(f);
-    size_t pos = 0;
-    while (true) {
-        size_t q0 = s.find('"', pos);
-        if (q0 == std::string::npos) break;
-        size_t q1 = s.find('"', q0 + 1);
-        if (q1 == std::string::npos) break;
-        const std::string key = s.substr(q0 + 1, q1 - q0 - 1);
-        size_t b0 = s.find('[', q1);
-        size_t b1 = s.find(']', b0 == std::string::npos ? q1 : b0);
-        if (b0 == std::string::npos || b1 == std::string::npos) break;
-        Shape sh;
-        if (sscanf(s.c_str() + b0 + 1, "%d , %d", &sh.E, &sh.G) == 2) g_tune[key] = sh;
-        pos = b1 + 1;
-    }
-}
-
-void save_cache() {
-    const std::string path = cache_path();
-    if (path.empty()) return;
-    const size_t slash = path.rfind('/');
-    if (slash != std::string::npos) {
-        std::string dir = path.substr(0, slash);
-        // create the directory chain if needed (best effort)
-        for (size_t i = 1; i <= dir.size(); ++i)
-            if (i == dir.size() || dir[i] == '/') mkdir(dir.substr(0, i).c_str(), 0755);
-    }
-    const std::string tmp = path + ".tmp" + std::to_string((long)getpid());
-    FILE *f = fopen(tmp.c_str(), "w");
-    if (!f) return;
-    fprintf(f, "{\n");
-    size_t k = 0;
-    for (auto &kv : g_tune)
-        fprintf(f, "  \"%s\": [%d, %d]%s\n", kv.first.c_str(), kv.second.E, kv.second.G,
-                ++k < g_tune.size() ? "," : "");
-    fprintf(f, "}\n");
-    fclose(f);
-    rename(tmp.c_str(), path.c_str());
-}
-
-std::string arch_name() {
-    int dev = 0;
-    hipDeviceProp_t prop;
-    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
-        return "unknown";
-    std::string a = prop.gcnArchName;
-    return a.substr(0, a.find(':'));
-}
-
-// Mean duration (ms) of one launch: the best of three runs of 20
-// back-to-back launches after three warm-up launches (candidates a few
-// percent apart are told apart reliably).  A failed launch or event call
-// returns its status; *ms is then untouched.
-template <class F>
-int time_ms(F launch, hipStream_t st, hipEvent_t e0, hipEvent_t e1, float *ms) {
-    for (int i = 0; i < 3; ++i) {
-        const int rc = launch();
-        if (rc) return rc;
-    }
-    const int reps = 20;
-    float best = -1.f;
-    for (int trial = 0; trial < 3; ++trial) {
-        PF_HIP(hipEventRecord(e0, st));
-        for (int i = 0; i < reps; ++i) {
-            const int rc = launch();
-            if (rc) return rc;
-        }
-        PF_HIP(hipEventRecord(e1, st));
-        PF_HIP(hipEventSynchronize(e1));
-        float t = 0;
-        PF_HIP(hipEventElapsedTime(&t, e0, e1));
-        if (best < 0.f || t < best) best = t;
-    }
-    *ms = best / reps;
-    return PF_OK;
-}
-
-// Device resources of one tuning run, released on every return path.
-struct TuneScratch {
-    void *x = nullptr;
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    ~TuneScratch() {
-        if (x) (void)hipFree(x);
-        if (e0) (void)hipEventDestroy(e0);
-        if (e1) (void)hipEventDestroy(e1);
-    }
-};
-
-template <typename T>
-int tune_t(Plan &p, hipStream_t st) {
-    using C = cx<T>;
-    const bool f64 = sizeof(T) == 8;
-    const std::string pre = arch_name() + (f64 ? "|f64|" : "|f32|");
-    const std::string krow = pre + "rows1|M=" + std::to_string(p.M) + "|rows=" +
-                             std::to_string(p.n_r);
-    const std::string krow2 = pre + "rows2|M=" + std::to_string(p.M) + "|rows=" +
-                              std::to_string(p.n_r);
-    const std::string kcol = pre + "cols|L=" + std::to_string(p.L) + "|H=" + std::to_string(p.H) +
-                             "|n_r=" + std::to_string(p.n_r);
-    const std::string kadj = pre + "adj|L=" + std::to_string(p.L) + "|H=" + std::to_string(p.H) +
-                             "|n_r=" + std::to_string(p.n_r);
-    {
-        std::lock_guard<std::mutex> g(g_tune_mu);
-        load_cache();
-        auto a = g_tune.find(krow), a2 = g_tune.find(krow2), b = g_tune.find(kcol),
-             c = g_tune.find(kadj);
-        if (a != g_tune.end() && a2 != g_tune.end() && b != g_tune.end() && c != g_tune.end() &&
-            valid_shape_rows(p.M, a->second, f64) && valid_shape_rows(p.M, a2->second, f64) &&
-            valid_shape_cols(p.L, b->second, f64) && valid_shape_cols(p.L, c->second, f64)) {
-            p.sched.rows = a->second;
-            p.sched.rows2 = a2->second;
-            p.sched.cols = b->second;
-            p.sched.cols_adj = c->second;
-            return PF_OK;
-        }
-    }
-    TuneScratch ts;
-    const size_t xbytes = sizeof(T) * 3 * (size_t)p.n_r * p.n_phi;
-    PF_HIP(hipMalloc(&ts.x, xbytes));
-    T *x = (T *)ts.x;
-    PF_HIP(hipMemsetAsync(x, 0, xbytes, st));
-    C *S = (C *)p.ws;                        // forward: S, then (Zr, Zp) pairs
-    C *Z = S + (size_t)p.n_r * p.H;
-    C *D = S + 2 * (size_t)p.n_r * p.H;      // transpose: (Vr, Vp) pairs at S, then D
-    PF_HIP(hipMemsetAsync(p.ws, 0, sizeof(C) * 3 * (size_t)p.n_r * p.H, st));
-    PF_HIP(hipEventCreate(&ts.e0));
-    PF_HIP(hipEventCreate(&ts.e1));
-    // rows: the one-channel forward R2C and the two-channel inverse C2R of
-    // n_r rows, each on its own (they stand for the one- and two-channel row
-    // transforms of both directions)
-    Shape best_r = p.sched.rows, best_r2 = p.sched.rows2, best_c = p.sched.cols,
-          best_a = p.sched.cols_adj;
-    // Bring the GPU to its working clocks first (a few ms of the default
-    // shapes): timed right after the plan build, the first candidates ran at
-    // lower clocks and lost to later ones they beat in steady state.  Each
-    // candidate set is then swept twice, keeping every candidate's best time.
-    for (int i = 0; i < 100; ++i) {
-        int rc = launch_rows_c2r<T>(p, Z, p.n_r, x + (size_t)p.n_r * p.n_phi,
-                                    x + 2 * (size_t)p.n_r * p.n_phi, (const C *)p.twN,
-                                    p.sched.rows2, st);
-        if (!rc)
-            rc = launch_cols_fwd<T>(p, S, Z, (const C *)p.spec, (const C *)p.twL, p.sched.cols,
-                                    st);
-        if (rc) return rc;
-    }
-    PF_HIP(hipStreamSynchronize(st));
-    float tbest = 1e30f, tbest2 = 1e30f, t = 0.f;
-    int rc = PF_OK;
-    for (int sweep = 0; sweep < 2; ++sweep)
-        for (int E : {4, 8, 16})
-            for (int thr : {64, 128, 256, 512}) {
-                if (E > p.M || (p.M / E) > thr) continue;
-                Shape s{E, thr / (p.M / E)};
-                if (!valid_shape_rows(p.M, s, f64)) continue;
-                rc = time_ms(
-                    [&]() {
-                        return launch_rows_r2c<T>(p, x, nullptr, p.n_r, S, (const C *)p.twN, s,
-                                                  st);
-                    },
-                    st, ts.e0, ts.e1, &t);
-                if (rc) return rc;
-                if (t < tbest) {
-                    tbest = t;
-                    best_r = s;
-                }
-                rc = time_ms(
-                    [&]() {
-                        return launch_rows_c2r<T>(p, Z, p.n_r, x + (size_t)p.n_r * p.n_phi,
-                                                  x + 2 * (size_t)p.n_r * p.n_phi,
-                                                  (const C *)p.twN, s, st);
-                    },
-                    st, ts.e0, ts.e1, &t);
-                if (rc) return rc;
-                if (t < tbest2) {
-                    tbest2 = t;
-                    best_r2 = s;
-                }
-            }
-    for (int adj = 0; adj < 2; ++adj) {
-        tbest = 1e30f;
-        Shape &best = adj ? best_a : best_c;
-        for (int sweep = 0; sweep < 2; ++sweep)
-            for (int E : {8, 16})
-                for (int thr : {64, 128, 256, 512}) {
-                    if (E > p.L || (p.L / E) > thr) continue;
-                    Shape s{E, thr / (p.L / E)};
-                    if (!valid_shape_cols(p.L, s, f64)) continue;
-                    rc = time_ms(
-                        [&]() {
-                            return adj ? launch_cols_adj<T>(p, S, D, (const C *)p.spec,
-                                                            (const C *)p.twL, s, st)
-                                       : launch_cols_fwd<T>(p, S, Z, (const C *)p.spec,
-                                                            (const C *)p.twL, s, st);
-                        },
-                        st, ts.e0, ts.e1, &t);
-                    if (rc) return rc;
-                    if (t < tbest) {
-                        tbest = t;
-                        best = s;
-                    }
-                }
-    }
-    PF_HIP(hipStreamSynchronize(st));
-    p.sched.rows = best_r;
-    p.sched.rows2 = best_r2;
-    p.sched.cols = best_c;
-    p.sched.cols_adj = best_a;
-    std::lock_guard<std::mutex> g(g_tune_mu);
-    g_tune[krow] = best_r;
-    g_tune[krow2] = best_r2;
-    g_tune[kcol] = best_c;
-    g_tune[kadj] = best_a;
-    save_cache();
-    return PF_OK;
-}
-
-}  // namespace
-
-int autotune_plan(Plan &p, hipStream_t st) {
-    const char *e = getenv("PF_AUTOTUNE");
-    if (e && e[0] == '0') return PF_OK;
-    return p.opts.dtype == PF_F64 ? tune_t<double>(p, st) : tune_t<float>(p, st);
 }
 
 }  // namespace pf

@@ -6,8 +6,9 @@
 
 namespace pf {
 
-// Forward map for several plans of one precision as three grouped launches
-// (pass A, B, C of every disk).
+// Forward map for several plans of one precision as grouped launches (pass
+// A, B, C of every disk, one launch per class of transform length and
+// launch shape).
 int batched_forces(const std::vector<const Plan *> &plans, const void *const *sigma,
                    void *const *f_r, void *const *f_phi, hipStream_t st);
 // Drop cached batch state that refers to plan `uid`.

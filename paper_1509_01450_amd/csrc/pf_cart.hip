@@ -488,22 +488,24 @@ __device__ __forceinline__ void body_cart_cols(int unit, int G, cx<T> *__restric
                 const cx<T> AD = unpack_even(v[1][e], mD), BD = unpack_odd(v[1][e], mD);
                 const cx<T> f0 = slope_fix_at<T, E>(ph0, rne, e);
                 const cx<T> fM = slope_fix_at<T, E>(phM, rne, e);
-                const cx<T> zx0 = spec_mul<T, E, false, false>(pa[j].a, AS, e, t0) +
-                                  spec_mul<T, E, false, false>(pa[j].b, f0, e, t0);
-                const cx<T> zxM = spec_mul<T, E, false, false>(pb[j].a, BS, e, t0) +
-                                  spec_mul<T, E, false, false>(pb[j].b, fM, e, t0);
+                const cx<T> zx0 = spec_mac<T, E, false, false>(
+                    spec_mul<T, E, false, false>(pa[j].a, AS, e, t0), pa[j].b, f0, e, t0);
+                const cx<T> zxM = spec_mac<T, E, false, false>(
+                    spec_mul<T, E, false, false>(pb[j].a, BS, e, t0), pb[j].b, fM, e, t0);
                 const cx<T> zy0 = spec_mul<T, E, false, false>(rb[j], AD, e, t0);
                 const cx<T> zyM = spec_mul<T, E, false, false>(ra[j], BD, e, t0);
                 y0 = cx<T>{zx0.x - zxM.y, zx0.y + zxM.x};   // bin 0 + i bin M
                 y1 = cx<T>{zy0.x - zyM.y, zy0.y + zyM.x};
             } else {
                 const cx<T> f = slope_fix_at<T, E>(ph, rne, e);
-                y0 = spec_mul<T, E, false, false>(pa[j].a, v[0][e], e, t0) +
-                     spec_mul<T, E, false, false>(pa[j].b, f, e, t0) +
-                     spec_mul<T, E, true, false>(ra[j], v[1][e], e, t0);
-                y1 = spec_mul<T, E, true, false>(pb[j].a, v[0][e], e, t0) +
-                     spec_mul<T, E, true, false>(pb[j].b, f, e, t0) +
-                     spec_mul<T, E, false, false>(rb[j], v[1][e], e, t0);
+                y0 = spec_mac<T, E, true, false>(
+                    spec_mac<T, E, false, false>(
+                        spec_mul<T, E, false, false>(pa[j].a, v[0][e], e, t0), pa[j].b, f, e, t0),
+                    ra[j], v[1][e], e, t0);
+                y1 = spec_mac<T, E, false, false>(
+                    spec_mac<T, E, true, false>(
+                        spec_mul<T, E, true, false>(pb[j].a, v[0][e], e, t0), pb[j].b, f, e, t0),
+                    rb[j], v[1][e], e, t0);
             }
             v[0][e] = y0;
             v[1][e] = y1;

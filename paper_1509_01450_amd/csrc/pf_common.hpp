@@ -121,6 +121,9 @@ int upload_twiddles(int n, bool f64, void **dst);
 Schedule default_schedule(int n_phi, int L, bool f64);
 bool valid_shape_rows(int M, Shape s, bool f64);
 bool valid_shape_cols(int L, Shape s, bool f64);
+// LDS bytes of a column-pass workgroup: the transform buffers and, with the
+// prefetch, the spectrum region
+size_t cols_lds_bytes(int L, int E, int G, bool f64, bool prefetch);
 
 inline int ilog2(int v) {
     int k = 0;

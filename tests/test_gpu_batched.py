@@ -1,5 +1,6 @@
-"""GPU batched path (three grouped launches covering every disk) against the
-single-disk path and the FP64 oracle."""
+"""GPU batched path (grouped launches per class of transform length and
+tuned launch shape, covering every disk) against the single-disk path -- bit
+for bit: the same pass bodies at the same shapes -- and the FP64 oracle."""
 import sys
 
 import numpy as np
@@ -43,11 +44,14 @@ def _rel(a, b):
 
 
 def _check_against_single(plans, sig, outs, tol=1e-6):
+    """Worst relative-L2 difference from the single-disk path; each disk must
+    also equal it bit for bit."""
     worst = 0.0
-    for p, s, (fr, fp) in zip(plans, sig, outs):
+    for k, (p, s, (fr, fp)) in enumerate(zip(plans, sig, outs)):
         r, q = p.forces(s)
+        torch.cuda.synchronize()
         worst = max(worst, _rel(fr, r), _rel(fp, q))
-    torch.cuda.synchronize()
+        assert torch.equal(fr, r) and torch.equal(fp, q), (k, p.shape, _rel(fr, r), _rel(fp, q))
     return worst
 
 
@@ -88,7 +92,8 @@ def test_uneven_batch_matches_single_disk_and_oracle():
 
 
 def test_fp64_batch_matches_single_disk_and_oracle():
-    sizes = [(64, 128), (37, 512), (300, 256), (1024, 128)]
+    # up to n_r = 1500 (L = 4096)
+    sizes = [(64, 128), (37, 512), (300, 256), (1024, 128), (1500, 256)]
     plans, sig = _disks(sizes, dtype="f64")
     outs = pf.forces_batched(plans, sig)
     torch.cuda.synchronize()
@@ -198,7 +203,25 @@ def test_batch_argument_errors():
     with pytest.raises(pf.PFError) as ei:
         pf.forces_batched([p3], [torch.zeros(8, 64, device="cuda")])
     assert ei.value.code == pf.PF_EUNSUPPORTED
-    p4 = pf.Plan(1500, 128, 0.1, 10.0, dtype="f64")  # L = 4096: beyond the FP64 batch range
+    p4 = pf.Plan(2100, 128, 0.1, 10.0, dtype="f32")  # L = 8192: beyond the batch range
     with pytest.raises(pf.PFError) as ei:
-        pf.forces_batched([p4], [torch.zeros(1500, 128, dtype=torch.float64, device="cuda")])
+        pf.forces_batched([p4], [torch.zeros(2100, 128, device="cuda")])
     assert ei.value.code == pf.PF_EUNSUPPORTED
+
+
+def test_disks_of_one_size_with_different_shapes():
+    """Two disks of one size, one at the tuned shapes and one at other valid
+    shapes: they fall into different classes, and each still equals its
+    single-disk result bit for bit."""
+    plans, sig = _disks([(256, 512), (256, 512), (100, 256)])
+    base = list(plans[0].schedule())
+    # rows: other points per thread; columns (L = 512): 64-thread workgroups
+    # of the other radix
+    cols = [8, 1] if base[4] == 16 else [16, 2]
+    other = [16 if base[0] != 16 else 8, 1, 4, 4] + cols + [base[6], base[7]]
+    plans[1].set_schedule(other)
+    assert list(plans[1].schedule()) == other
+    outs = pf.forces_batched(plans, sig)
+    torch.cuda.synchronize()
+    worst = _check_against_single(plans, sig, outs)
+    _say("mixed-shape batch vs single-disk worst rel-L2 %.3e" % worst)

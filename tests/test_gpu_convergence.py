@@ -208,3 +208,37 @@ def test_table1_orders_particle_methods_fp64(method):
              % (method, disk, np.array2string(full, precision=2),
                 np.array2string(fit, precision=2), ref))
         assert np.all(np.abs(full - ref) < 0.15), (method, disk, full, ref)
+
+
+@pytest.fixture(scope="module")
+def largest_reference():
+    """The oracle on sampled cells of the largest C3 grid, 2048 x 4096
+    (L = 4096): 768 random cells, 256 random cells of the rows the disk
+    covers, and both boundary rows in full."""
+    n_r, n_phi = SIZES[-1]
+    g, sig, _, _ = _case(n_r, n_phi, 5)
+    _say("2048 x 4096: oracle tables")
+    T = oracle.tables(g, 19)
+    rng = workloads.rng(3, 1)
+    rows = np.nonzero(np.abs(sig).max(axis=1) > 0)[0]
+    disk = rows[rng.integers(0, rows.size, 256)] * n_phi + rng.integers(0, n_phi, 256)
+    dest = np.unique(np.concatenate([rng.integers(0, n_r * n_phi, 768), disk,
+                                     np.arange(n_phi), (n_r - 1) * n_phi + np.arange(n_phi)]))
+    _say("2048 x 4096: oracle sums at %d cells" % dest.size)
+    ofr, ofp = oracle.forward(g, T, sig, dest)
+    del T
+    return sig, dest, ofr, ofp
+
+
+@pytest.mark.parametrize("dt,tol", [("f64", 1e-11), ("f32", 1e-5)])
+def test_largest_grid_sampled_oracle_parity(largest_reference, dt, tol):
+    sig, dest, ofr, ofp = largest_reference
+    n_r, n_phi = SIZES[-1]
+    fr, fp = _gpu_forces(n_r, n_phi, sig, dt)
+    a, b = fr.ravel()[dest], fp.ravel()[dest]
+    r1 = np.linalg.norm(a - ofr) / np.linalg.norm(ofr)
+    r2 = np.linalg.norm(b - ofp) / np.linalg.norm(ofp)
+    m = max(np.abs(a - ofr).max(), np.abs(b - ofp).max())
+    _say("2048 x 4096 %s sampled (%d cells) rel-L2 F_r %.3e F_phi %.3e max-abs %.3e"
+         % (dt, dest.size, r1, r2, m))
+    assert r1 < tol and r2 < tol
