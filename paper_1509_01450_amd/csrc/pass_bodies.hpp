@@ -556,75 +556,133 @@ __device__ __forceinline__ void body_cols_fwd(int unit, int G, cx<T> *__restrict
     }
     fft_fwd<L, E, T, true>(v, t, lds, tw);
 
-    // transform of the four-row slope correction at the thread's points
-    // (kept for both sweeps in FP32)
-    constexpr bool KEEP = sizeof(T) == 4;
+    // FP32 (SPLIT): the radial channel's sweep and inverse transform, then
+    // the azimuthal channel's (its spectrum pairs arriving meanwhile).  FP64:
+    // one sweep forms both channels (radial pairs from LDS, azimuthal ones
+    // from global memory), then the two inverse transforms -- fewer values
+    // live across a transform (the split order spills at E = 8).
+    constexpr bool SPLIT = sizeof(T) == 4;
     const SlopePhasors<T> ph = slope_phasors(slope_fix(x0, x1, xm2, xm1, ca, c0, cn), wt, wnt);
-    cx<T> f[E];
-    if constexpr (KEEP) {
-#pragma unroll
-        for (int e = 0; e < E; ++e) f[e] = slope_fix_at<T, E>(ph, root_ne<T, L, E>(twL, n_r, e), e);
-    }
     const cx2<T> *sl = PF ? spl + (size_t)gi * LP : nullptr;
     const cx2<T> *const gr = srad + (size_t)cl * ldspec;
     const cx2<T> *const gp = sazi + (size_t)cl * ldspec;
-
-    // radial channel: y0 = E'_r X + Q_r B
-    if constexpr (PF) prefetch_wait();
-    cx<T> y0[E];
-    mac_fwd<T, L, E, false, PF, KEEP>(y0, v, f, ph, twL, n_r, sl, gr, t);
-    if (packed) {
-        // column 0 holds bins 0 and M packed as c_0 + i c_M: its radial
-        // channel is y_0 + i y_M, from the bin-0 radial pairs (at the radial
-        // place) and the bin-M radial pairs (at the azimuthal place, read
-        // from global memory) applied to the two unpacked transforms, which
-        // need the conjugate mirror points (through LDS)
+    cx<T> y0[E], y1[E];
+    if constexpr (SPLIT) {
+        // transform of the four-row slope correction at the thread's points,
+        // kept for both sweeps
+        cx<T> f[E];
 #pragma unroll
-        for (int e = 0; e < E; ++e) lds.st_split(lds_pad(t), e * TH, v[e]);
-        lds_barrier();
-        if (is0) {
-            // the four boundary rows again (read here rather than kept live
-            // through the transform for this one column)
+        for (int e = 0; e < E; ++e) f[e] = slope_fix_at<T, E>(ph, root_ne<T, L, E>(twL, n_r, e), e);
+
+        // radial channel: y0 = E'_r X + Q_r B
+        if constexpr (PF) prefetch_wait();
+        mac_fwd<T, L, E, false, PF, true>(y0, v, f, ph, twL, n_r, sl, gr, t);
+        if (packed) {
+            // column 0 holds bins 0 and M packed as c_0 + i c_M: its radial
+            // channel is y_0 + i y_M, from the bin-0 radial pairs (at the
+            // radial place) and the bin-M radial pairs (at the azimuthal
+            // place, read from global memory) applied to the two unpacked
+            // transforms, which need the conjugate mirror points (through LDS)
+#pragma unroll
+            for (int e = 0; e < E; ++e) lds.st_split(lds_pad(t), e * TH, v[e]);
+            lds_barrier();
+            if (is0) {
+                // the four boundary rows again (read here rather than kept live
+                // through the transform for this one column)
+                const SlopeFix<T> a = slope_fix(S[0], S[(size_t)H], S[(size_t)(n_r - 2) * H],
+                                                S[(size_t)(n_r - 1) * H], ca, c0, cn);
+                const SlopePhasors<T> ph0 = slope_phasors(slope_fix_part(a, false), wt, wnt);
+                const SlopePhasors<T> phM = slope_phasors(slope_fix_part(a, true), wt, wnt);
+                const bool t0 = t == 0;
+#pragma unroll
+                for (int e = 0; e < E; ++e) {
+                    const int ix = spec_index<L, E>(t, e);
+                    const cx2<T> pr = PF ? sl[ix] : gr[ix];
+                    const cx2<T> pm = gp[ix];
+                    const cx<T> rne = root_ne<T, L, E>(twL, n_r, e);
+                    const cx<T> m = lds.ld((L - (t + e * TH)) & (L - 1));
+                    const cx<T> A = unpack_even(v[e], m), B = unpack_odd(v[e], m);
+                    const cx<T> f0 = slope_fix_at<T, E>(ph0, rne, e);
+                    const cx<T> fM = slope_fix_at<T, E>(phM, rne, e);
+                    const cx<T> ya = spec_mac<T, E, false, false>(
+                        spec_mul<T, E, false, false>(pr.a, A, e, t0), pr.b, f0, e, t0);
+                    const cx<T> yb = spec_mac<T, E, false, false>(
+                        spec_mul<T, E, false, false>(pm.a, B, e, t0), pm.b, fM, e, t0);
+                    y0[e] = cx<T>{ya.x - yb.y, ya.y + yb.x};   // ya + i yb
+                }
+            }
+            lds_barrier();   // mirror reads done before the transforms reuse buf
+        }
+        if constexpr (PF) {
+            // every wave has read its radial pairs: the azimuthal pairs go to
+            // the same LDS region during the radial channel's inverse transform
+            lds_barrier();
+            prefetch_spectra<T, L, E>(unit, G, H, ldspec, sazi, spl);
+        }
+        fft_inv<L, E, T>(y0, t, lds, tw);
+
+        // azimuthal channel: y1 = E'_p X + Q_p B (zero for column 0: the
+        // azimuthal spectra vanish at bins 0 and M)
+        if constexpr (PF) prefetch_wait();
+        mac_fwd<T, L, E, true, PF, true>(y1, v, f, ph, twL, n_r, sl, gp, t);
+#pragma unroll
+        for (int e = 0; e < E; ++e) y1[e] = is0 ? cx<T>{T(0), T(0)} : y1[e];
+        fft_inv<L, E, T>(y1, t, lds, tw);
+    } else {
+        if (packed) {   // column 0 reads the conjugate mirror points from LDS
+#pragma unroll
+            for (int e = 0; e < E; ++e) lds.st_split(lds_pad(t), e * TH, v[e]);
+            lds_barrier();
+        }
+        SlopePhasors<T> ph0 = ph, phM = ph;
+        if (is0) {   // bins 0 and M of the packed column: real coefficients each
             const SlopeFix<T> a = slope_fix(S[0], S[(size_t)H], S[(size_t)(n_r - 2) * H],
                                             S[(size_t)(n_r - 1) * H], ca, c0, cn);
-            const SlopePhasors<T> ph0 = slope_phasors(slope_fix_part(a, false), wt, wnt);
-            const SlopePhasors<T> phM = slope_phasors(slope_fix_part(a, true), wt, wnt);
-            const bool t0 = t == 0;
+            ph0 = slope_phasors(slope_fix_part(a, false), wt, wnt);
+            phM = slope_phasors(slope_fix_part(a, true), wt, wnt);
+        }
+        if constexpr (PF) prefetch_wait();
+        constexpr int CH = mac_batch<T, E>();
+        const bool t0 = t == 0;
 #pragma unroll
-            for (int e = 0; e < E; ++e) {
-                const int ix = spec_index<L, E>(t, e);
-                const cx2<T> pr = PF ? sl[ix] : gr[ix];
-                const cx2<T> pm = gp[ix];
+        for (int cb = 0; cb < E; cb += CH) {
+            // spectra of the batch issued together; column 0's azimuthal
+            // place holds bin M's radial (even) pairs
+            cx2<T> pr[CH], pp[CH];
+#pragma unroll
+            for (int j = 0; j < CH; ++j) {
+                const int ix = spec_index<L, E>(t, cb + j);
+                pr[j] = PF ? sl[ix] : gr[ix];
+                pp[j] = gp[ix];
+            }
+#pragma unroll
+            for (int j = 0; j < CH; ++j) {
+                const int e = cb + j;
                 const cx<T> rne = root_ne<T, L, E>(twL, n_r, e);
-                const cx<T> m = lds.ld((L - (t + e * TH)) & (L - 1));
-                const cx<T> A = unpack_even(v[e], m), B = unpack_odd(v[e], m);
-                const cx<T> f0 = slope_fix_at<T, E>(ph0, rne, e);
-                const cx<T> fM = slope_fix_at<T, E>(phM, rne, e);
-                const cx<T> ya = spec_mac<T, E, false, false>(
-                    spec_mul<T, E, false, false>(pr.a, A, e, t0), pr.b, f0, e, t0);
-                const cx<T> yb = spec_mac<T, E, false, false>(
-                    spec_mul<T, E, false, false>(pm.a, B, e, t0), pm.b, fM, e, t0);
-                y0[e] = cx<T>{ya.x - yb.y, ya.y + yb.x};   // ya + i yb
+                if (is0) {
+                    const cx<T> m = lds.ld((L - (t + e * TH)) & (L - 1));
+                    const cx<T> A = unpack_even(v[e], m), B = unpack_odd(v[e], m);
+                    const cx<T> f0 = slope_fix_at<T, E>(ph0, rne, e);
+                    const cx<T> fM = slope_fix_at<T, E>(phM, rne, e);
+                    const cx<T> ya = spec_mac<T, E, false, false>(
+                        spec_mul<T, E, false, false>(pr[j].a, A, e, t0), pr[j].b, f0, e, t0);
+                    const cx<T> yb = spec_mac<T, E, false, false>(
+                        spec_mul<T, E, false, false>(pp[j].a, B, e, t0), pp[j].b, fM, e, t0);
+                    y0[e] = cx<T>{ya.x - yb.y, ya.y + yb.x};   // ya + i yb
+                    y1[e] = cx<T>{T(0), T(0)};
+                } else {
+                    const cx<T> f = slope_fix_at<T, E>(ph, rne, e);
+                    y0[e] = spec_mac<T, E, false, false>(
+                        spec_mul<T, E, false, false>(pr[j].a, v[e], e, t0), pr[j].b, f, e, t0);
+                    y1[e] = spec_mac<T, E, true, false>(
+                        spec_mul<T, E, true, false>(pp[j].a, v[e], e, t0), pp[j].b, f, e, t0);
+                }
             }
         }
-        lds_barrier();   // mirror reads done before the transforms reuse buf
+        if (packed) lds_barrier();   // mirror reads done before the transforms reuse buf
+        fft_inv<L, E, T>(y0, t, lds, tw);
+        fft_inv<L, E, T>(y1, t, lds, tw);
     }
-    if constexpr (PF) {
-        // every wave has read its radial pairs: the azimuthal pairs go to the
-        // same LDS region during the radial channel's inverse transform
-        lds_barrier();
-        prefetch_spectra<T, L, E>(unit, G, H, ldspec, sazi, spl);
-    }
-    fft_inv<L, E, T>(y0, t, lds, tw);
-
-    // azimuthal channel: y1 = E'_p X + Q_p B (zero for column 0: the
-    // azimuthal spectra vanish at bins 0 and M)
-    if constexpr (PF) prefetch_wait();
-    cx<T> y1[E];
-    mac_fwd<T, L, E, true, PF, KEEP>(y1, v, f, ph, twL, n_r, sl, gp, t);
-#pragma unroll
-    for (int e = 0; e < E; ++e) y1[e] = is0 ? cx<T>{T(0), T(0)} : y1[e];
-    fft_inv<L, E, T>(y1, t, lds, tw);
     if (valid) {
         // only the first E/2 points of a thread can be rows (L >= 2 n_out): the
         // rest of the last stage is never formed
