@@ -211,6 +211,21 @@ int pf_forces_backward(pf_plan plan, const void *g_fr, const void *g_fphi,
 int pf_forces_batched(int n, const pf_plan *plans, const void *const *sigma,
                       void *const *f_r, void *const *f_phi, void *stream);
 
+/* pf_forces_batched for callers that cannot allocate device memory (code
+ * under HIP graph capture, serving loops, harnesses that forbid hipMalloc):
+ * the batch's tables (one descriptor per disk and the class entry tables)
+ * go to a static 48 KiB device array of the library instead of memory
+ * allocated per set of plans, rewritten by every call through upload
+ * launches (kernel arguments).  Nothing is allocated and nothing waits; the
+ * plans' own workspaces carry the intermediates as in pf_forces_batched.
+ * Same arguments, results (bit for bit) and size limits, and at most 256
+ * disks (PF_EINVAL beyond).  Each device holds one copy of the array, shared
+ * by every call on that device and keeping the last call's tables: calls
+ * that overlap on one device (other streams, other host threads) race and
+ * must be ordered by the caller.  The current device must be the plans'.  */
+int pf_forces_batched_noalloc(int n, const pf_plan *plans, const void *const *sigma,
+                              void *const *f_r, void *const *f_phi, void *stream);
+
 /* Diagnostic form of pf_forces / pf_forces_backward: the same passes, each
  * launched `reps` times back to back (1 <= reps <= 10000; every pass reads
  * only its predecessor's output, so repeats leave the result unchanged)

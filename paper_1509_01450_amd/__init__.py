@@ -38,7 +38,8 @@ _CART_METHODS = {"second": PF_CART_SECOND, "particle": PF_CART_PARTICLE,
                  "particle+": PF_CART_PARTICLE_PLUS}
 
 EXPORTS = ("pf_build_opts_default", "pf_plan_create", "pf_kernels_build", "pf_forces",
-           "pf_forces_backward", "pf_forces_batched", "pf_forces_timed", "pf_plan_geometry",
+           "pf_forces_backward", "pf_forces_batched", "pf_forces_batched_noalloc",
+           "pf_forces_timed", "pf_plan_geometry",
            "pf_plan_schedule", "pf_plan_set_schedule", "pf_plan_selfcell", "pf_plan_tables",
            "pf_plan_destroy",
            "pf_last_error", "pf_version", "pf_plan_create_patches", "pf_forces_patches",
@@ -86,6 +87,7 @@ def load():
     lib.pf_forces.argtypes = [P, P, P, P, P]
     lib.pf_forces_backward.argtypes = [P, P, P, P, P]
     lib.pf_forces_batched.argtypes = [I, P, P, P, P, P]
+    lib.pf_forces_batched_noalloc.argtypes = [I, P, P, P, P, P]
     lib.pf_forces_timed.argtypes = [P, I, P, P, P, P, I, P, P]
     lib.pf_plan_geometry.argtypes = [P, P, P, P]
     lib.pf_plan_selfcell.argtypes = [P, P]
@@ -93,6 +95,7 @@ def load():
     lib.pf_plan_set_schedule.argtypes = [P, P]
     lib.pf_plan_tables.argtypes = [P, P]
     for f in ("pf_kernels_build", "pf_forces", "pf_forces_backward", "pf_forces_batched",
+              "pf_forces_batched_noalloc",
               "pf_forces_timed",
               "pf_plan_geometry", "pf_plan_selfcell", "pf_plan_schedule", "pf_plan_set_schedule",
               "pf_plan_tables"):
@@ -164,6 +167,13 @@ def pf_forces_batched(plans, sigma, f_r, f_phi, stream: int = 0) -> None:
     arr = lambda xs: (ctypes.c_void_p * n)(*xs)
     _check(load().pf_forces_batched(n, arr(plans), arr(sigma), arr(f_r), arr(f_phi),
                                     stream or None))
+
+
+def pf_forces_batched_noalloc(plans, sigma, f_r, f_phi, stream: int = 0) -> None:
+    n = len(plans)
+    arr = lambda xs: (ctypes.c_void_p * n)(*xs)
+    _check(load().pf_forces_batched_noalloc(n, arr(plans), arr(sigma), arr(f_r), arr(f_phi),
+                                            stream or None))
 
 
 def pf_forces_timed(plan: int, backward: bool, in0: int, in1: int, out0: int, out1: int,
@@ -381,8 +391,10 @@ class Plan:
             pass
 
 
-def forces_batched(plans, sigmas, outs=None):
-    """Forward map of many disks (grouped launches covering every disk)."""
+def forces_batched(plans, sigmas, outs=None, noalloc=False):
+    """Forward map of many disks (grouped launches covering every disk);
+    noalloc: through pf_forces_batched_noalloc (tables in the library's static
+    device array, at most 256 disks)."""
     import torch
     if len(plans) != len(sigmas) or (outs is not None and len(outs) != len(plans)):
         raise TypeError("one sigma (and one output pair) per plan")
@@ -394,9 +406,9 @@ def forces_batched(plans, sigmas, outs=None):
         for p, o in zip(plans, outs):
             p._check_field(o[0], "outs[k][0]")
             p._check_field(o[1], "outs[k][1]")
-    pf_forces_batched([p.handle for p in plans], [s.data_ptr() for s in sigmas],
-                      [o[0].data_ptr() for o in outs], [o[1].data_ptr() for o in outs],
-                      _stream())
+    fn = pf_forces_batched_noalloc if noalloc else pf_forces_batched
+    fn([p.handle for p in plans], [s.data_ptr() for s in sigmas],
+       [o[0].data_ptr() for o in outs], [o[1].data_ptr() for o in outs], _stream())
     return outs
 
 

@@ -648,5 +648,17 @@ int pf_forces_batched(int n, const pf_plan *plans, const void *const *sigma, voi
     return pf::batched_forces(ps, sigma, f_r, f_phi, (hipStream_t)stream);
 }
 
+int pf_forces_batched_noalloc(int n, const pf_plan *plans, const void *const *sigma,
+                              void *const *f_r, void *const *f_phi, void *stream) {
+    pf::clear_error();
+    const Plan *ps[256];
+    if (n > 256) {
+        pf::set_error("pf_forces_batched_noalloc takes at most 256 disks (got %d)", n);
+        return PF_EINVAL;
+    }
+    int rc = check_batch(n, plans, sigma, f_r, f_phi, ps);
+    if (rc) return rc;
+    return pf::batched_forces_noalloc(ps, n, sigma, f_r, f_phi, (hipStream_t)stream);
+}
 
 }  // extern "C"

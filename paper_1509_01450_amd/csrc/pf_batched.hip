@@ -18,7 +18,9 @@
 // device through small upload kernels that take the bytes as kernel
 // arguments: no host buffer has to outlive the call and nothing waits.
 // pf_forces_batched keeps them in device memory it allocates once per set of
-// plans (refreshed when the field pointers change).
+// plans (refreshed when the field pointers change);
+// pf_forces_batched_noalloc writes them, on every call, into a static device
+// array of the library (for callers that cannot allocate).
 #include <algorithm>
 #include <cstdio>
 #include <cstring>
@@ -138,6 +140,12 @@ struct UpChunk {
 __global__ __launch_bounds__(256) void k_upload(UpChunk c, unsigned int *__restrict__ dst) {
     for (unsigned int i = threadIdx.x; i < c.words; i += blockDim.x) dst[c.off + i] = c.w[i];
 }
+
+// Static device array behind pf_forces_batched_noalloc: the descriptors and
+// the three entry tables of the latest call on this device.
+constexpr int kNoAllocMaxDisks = 256;
+constexpr size_t kNoAllocBytes = 48 * 1024;
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
 
 namespace {
 
@@ -492,6 +500,82 @@ void batched_forget(int64_t uid) {
             ++it;
         }
     }
+}
+
+// ---- pf_forces_batched_noalloc: tables in the static device array ---------
+namespace {
+
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[64] = {};   // device address of `scratch`, per device
+
+// The device address of the static array on the current device, looked up
+// once per device with that device current (each device holds its own copy
+// of the array at its own address; the array's name in host code is only a
+// stand-in and is never passed to a kernel or a copy).
+int scratch_address(void **out) {
+    int dev = 0;
+    PF_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) {
+        set_error("device ordinal %d beyond the library's table of 64", dev);
+        return PF_EUNSUPPORTED;
+    }
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        PF_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return PF_OK;
+}
+
+// Host-side tables of one call, in fixed arrays (nothing allocated); calls
+// from several host threads take turns on them.
+struct NoAllocTables {
+    unsigned char bytes[kNoAllocBytes];
+    GEntry ent[3 * kNoAllocMaxDisks];
+    GClass cls[3 * kNoAllocMaxDisks];
+    int order[kNoAllocMaxDisks];
+};
+std::mutex g_na_mu;
+NoAllocTables g_na;
+
+}  // namespace
+
+int batched_forces_noalloc(const Plan *const *plans, int n, const void *const *sigma,
+                           void *const *f_r, void *const *f_phi, hipStream_t st) {
+    const bool f64 = plans[0]->opts.dtype == PF_F64;
+    int rc = check_plans(plans, n);
+    if (rc) return rc;
+    if (n > kNoAllocMaxDisks) {
+        set_error("pf_forces_batched_noalloc takes at most %d disks (got %d)", kNoAllocMaxDisks,
+                  n);
+        return PF_EINVAL;
+    }
+    static_assert((size_t)kNoAllocMaxDisks * sizeof(GDisk<double>) +
+                          (size_t)3 * kNoAllocMaxDisks * sizeof(GEntry) <=
+                      kNoAllocBytes,
+                  "static table size");
+    const size_t dbytes = desc_size(f64, n);
+    const size_t ebytes = (size_t)3 * n * sizeof(GEntry);
+    void *dev = nullptr;
+    rc = scratch_address(&dev);
+    if (rc) return rc;
+    std::lock_guard<std::mutex> g(g_na_mu);
+    int n_cls = 0;
+    make_layout(plans, n, g_na.ent, g_na.cls, &n_cls, g_na.order);
+    if (f64)
+        make_desc<double>(plans, n, sigma, f_r, f_phi, (GDisk<double> *)g_na.bytes);
+    else
+        make_desc<float>(plans, n, sigma, f_r, f_phi, (GDisk<float> *)g_na.bytes);
+    memcpy(g_na.bytes + dbytes, g_na.ent, ebytes);
+    // every call rewrites the whole table (other calls on this device share
+    // the array); the class launches read it in stream order
+    rc = upload(g_na.bytes, dbytes + ebytes, dev, st);
+    if (rc) return rc;
+    const GEntry *ent = (const GEntry *)((unsigned char *)dev + dbytes);
+    return f64 ? launch_classes<double>(g_na.cls, n_cls, dev, ent, st)
+               : launch_classes<float>(g_na.cls, n_cls, dev, ent, st);
 }
 
 }  // namespace pf

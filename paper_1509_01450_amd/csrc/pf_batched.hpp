@@ -11,6 +11,10 @@ namespace pf {
 // launch shape).
 int batched_forces(const std::vector<const Plan *> &plans, const void *const *sigma,
                    void *const *f_r, void *const *f_phi, hipStream_t st);
+// The same without allocating: the batch's tables go to a static device
+// array of the library (at most 256 disks); see pf_forces_batched_noalloc.
+int batched_forces_noalloc(const Plan *const *plans, int n, const void *const *sigma,
+                           void *const *f_r, void *const *f_phi, hipStream_t st);
 // Drop cached batch state that refers to plan `uid`.
 void batched_forget(int64_t uid);
 // Choose launch shapes for the plan's sizes (timed on the device, cached).
