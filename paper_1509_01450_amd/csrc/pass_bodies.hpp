@@ -62,6 +62,85 @@ __device__ __forceinline__ void store_stream(cx2<T> *p, cx2<T> v) {
 }
 
 // ---------------------------------------------------------------------------
+// FP32 scaling per grid.  The column transforms sum up to L N_phi values of
+// the density, so in FP32 a density near 2^104 would overflow them (and one
+// near 2^-110 would reach subnormal intermediates).  Each call therefore
+// scales the grid by a power of two, 2^-e with e = floor(log2 max|sigma|):
+//   pass A notes max|sigma| (as float bits, which order like the
+//     magnitudes) in one of 64 words g[0 .. 63] by atomic maximum;
+//   pass B reads the 64 words, scales its column by 2^-e before the
+//     transforms, stores its output still scaled and writes e to g[64]
+//     (every workgroup the same value);
+//   pass C reads e from g[64], multiplies its outputs by 2^e, and clears
+//     g[0 .. 63] for the next call (pass B is done with them).
+// Every pass of a call runs after the previous one on the stream.  Between
+// the note and the final multiply every value is the unscaled one times
+// 2^-e, so wherever the outputs are normal numbers they are bit for bit
+// those of the unscaled computation times 2^e -- and no intermediate leaves
+// the FP32 range as long as max|sigma| N_phi stays below 2^127.  FP64 is
+// not scaled.
+// ---------------------------------------------------------------------------
+constexpr int kScaleWords = 64;   // notes; g[64] holds e
+
+template <typename T, int E, int C>
+__device__ __forceinline__ void scale_note(unsigned *__restrict__ g, const cx<T> (&v)[C][E]) {
+    if constexpr (sizeof(T) == 4) {
+        if (!g) return;
+        unsigned m = 0u;
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+#pragma unroll
+            for (int e = 0; e < E; ++e)
+                m = max(m, max(__float_as_uint(fabsf(v[c][e].x)), __float_as_uint(fabsf(v[c][e].y))));
+        for (int off = 32; off > 0; off >>= 1) m = max(m, (unsigned)__shfl_xor((int)m, off));
+        if ((threadIdx.x & 63) == 0)
+            atomicMax(&g[(blockIdx.x * 8 + (threadIdx.x >> 6)) & (kScaleWords - 1)], m);
+    }
+}
+
+// 2^-e and 2^e
+template <typename T>
+struct GridScale {
+    T dn, up;
+};
+template <typename T>
+__device__ __forceinline__ GridScale<T> scale_of(int ex) {
+    return {__uint_as_float((unsigned)(127 - ex) << 23), __uint_as_float((unsigned)(127 + ex) << 23)};
+}
+
+// pass B: e from the notes (clamped to [-100, 100]), written to g[64] by the
+// first thread of the workgroup; ones without scaling
+template <typename T>
+__device__ __forceinline__ GridScale<T> scale_take(unsigned *__restrict__ g) {
+    if constexpr (sizeof(T) == 4) {
+        if (g) {
+            unsigned m = g[threadIdx.x & 63];
+            for (int off = 32; off > 0; off >>= 1) m = max(m, (unsigned)__shfl_xor((int)m, off));
+            int ex = (int)((m >> 23) & 0xffu) - 127;
+            ex = min(max(ex, -100), 100);
+            if (threadIdx.x == 0) g[kScaleWords] = (unsigned)ex;
+            return scale_of<T>(ex);
+        }
+    }
+    return {T(1), T(1)};
+}
+
+// pass C: e as pass B wrote it; the unit-0 workgroup of the grid clears
+// the notes (any number of threads)
+template <typename T>
+__device__ __forceinline__ T scale_finish(unsigned *__restrict__ g, int unit) {
+    if constexpr (sizeof(T) == 4) {
+        if (g) {
+            const int ex = (int)g[kScaleWords];
+            if (unit == 0)
+                for (int i = threadIdx.x; i < kScaleWords; i += blockDim.x) g[i] = 0u;
+            return scale_of<T>(ex).up;
+        }
+    }
+    return T(1);
+}
+
+// ---------------------------------------------------------------------------
 // Row transforms along phi.  A real row of N = 2M points goes through one
 // M-point complex transform of z[n] = x[2n] + i x[2n+1]; its spectrum is
 // the packed half spectrum (bin 0 = (X_0, X_M)).  C = 1 or 2 channels: with
@@ -83,7 +162,8 @@ __device__ __forceinline__ void body_rows_r2c(int unit, int G, cx<T> *__restrict
                                               const T *__restrict__ in0,
                                               const T *__restrict__ in1, int n_rows,
                                               cx<T> *__restrict__ out,
-                                              const cx<T> *__restrict__ twN) {
+                                              const cx<T> *__restrict__ twN,
+                                              unsigned *__restrict__ gscale = nullptr) {
     constexpr int TH = M / E;
     constexpr int N = 2 * M;
     const int gi = threadIdx.x / TH, t = threadIdx.x % TH;
@@ -108,6 +188,7 @@ __device__ __forceinline__ void body_rows_r2c(int unit, int G, cx<T> *__restrict
 #pragma unroll
         for (int e = 0; e < E; ++e)
             if (!active) v[c][e] = cx<T>{T(0), T(0)};
+    scale_note<T, E, C>(gscale, v);
     fft_fwd<M, E, C, T>(v, t, lds, tw);
 #pragma unroll
     for (int c = 0; c < C; ++c)
@@ -148,7 +229,8 @@ template <typename T, int M, int E, int C>
 __device__ __forceinline__ void body_rows_c2r(int unit, int G, cx<T> *__restrict__ buf,
                                               const cx<T> *__restrict__ in, int n_rows,
                                               T *__restrict__ out0, T *__restrict__ out1,
-                                              const cx<T> *__restrict__ twN) {
+                                              const cx<T> *__restrict__ twN,
+                                              unsigned *__restrict__ gscale = nullptr) {
     constexpr int TH = M / E;
     constexpr int N = 2 * M;
     const int gi = threadIdx.x / TH, t = threadIdx.x % TH;
@@ -207,12 +289,13 @@ __device__ __forceinline__ void body_rows_c2r(int unit, int G, cx<T> *__restrict
             v[c][e] = active ? cmac(s, d, iw) : cx<T>{T(0), T(0)};
         }
     fft_inv<M, E, C, T>(v, t, lds, tw);
+    const T up = scale_finish<T>(gscale, unit);
     if (active) {
 #pragma unroll
         for (int c = 0; c < C; ++c) {
             cx<T> *yz = reinterpret_cast<cx<T> *>((c == 0 ? out0 : out1) + (size_t)i * N);
 #pragma unroll
-            for (int e = 0; e < E; ++e) store_stream(&yz[t + e * TH], v[c][e]);
+            for (int e = 0; e < E; ++e) store_stream(&yz[t + e * TH], scale(v[c][e], up));
         }
     }
 }
@@ -519,7 +602,8 @@ __device__ __forceinline__ void body_cols_fwd(int unit, int G, cx<T> *__restrict
                                               const cx2<T> *__restrict__ spec, int H, int n_r,
                                               int n_out, int ldspec, T ca, T c0, T cn,
                                               const cx<T> *__restrict__ twL,
-                                              cx2<T> *spl = nullptr) {
+                                              cx2<T> *spl = nullptr,
+                                              unsigned *__restrict__ gscale = nullptr) {
     constexpr int TH = L / E;
     const int gi = threadIdx.x % G, t = threadIdx.x / G;
     const int col = unit * G + gi;
@@ -542,18 +626,24 @@ __device__ __forceinline__ void body_cols_fwd(int unit, int G, cx<T> *__restrict
         v[e] = S[(size_t)(i < n_r ? i : n_r - 1) * H + cl];
     }
     // the four rows entering the slope correction, and the thread's phasors
-    const cx<T> x0 = S[cl], x1 = S[(size_t)H + cl];
-    const cx<T> xm2 = S[(size_t)(n_r - 2) * H + cl], xm1 = S[(size_t)(n_r - 1) * H + cl];
+    cx<T> x0 = S[cl], x1 = S[(size_t)H + cl];
+    cx<T> xm2 = S[(size_t)(n_r - 2) * H + cl], xm1 = S[(size_t)(n_r - 1) * H + cl];
     const cx<T> wt = twL[t], wnt = twL[(int)(((unsigned)n_r * (unsigned)t) & (unsigned)(L - 1))];
     Twiddles<L, E, T> tw;
     tw.load(t, twL, 1);
+    // before the prefetch: the wait for this load must not wait for it
+    const GridScale<T> sc = scale_take<T>(gscale);
     // issued after the column's loads, which the transform waits for
     if constexpr (PF) prefetch_spectra<T, L, E>(unit, G, H, ldspec, srad, spl);
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         const int i = t + e * TH;
-        if (e >= E / 2 || !valid || i >= n_r) v[e] = cx<T>{T(0), T(0)};
+        v[e] = (e >= E / 2 || !valid || i >= n_r) ? cx<T>{T(0), T(0)} : scale(v[e], sc.dn);
     }
+    x0 = scale(x0, sc.dn);
+    x1 = scale(x1, sc.dn);
+    xm2 = scale(xm2, sc.dn);
+    xm1 = scale(xm1, sc.dn);
     fft_fwd<L, E, T, true>(v, t, lds, tw);
 
     // FP32 (SPLIT): the radial channel's sweep and inverse transform, then
@@ -589,8 +679,9 @@ __device__ __forceinline__ void body_cols_fwd(int unit, int G, cx<T> *__restrict
             if (is0) {
                 // the four boundary rows again (read here rather than kept live
                 // through the transform for this one column)
-                const SlopeFix<T> a = slope_fix(S[0], S[(size_t)H], S[(size_t)(n_r - 2) * H],
-                                                S[(size_t)(n_r - 1) * H], ca, c0, cn);
+                const SlopeFix<T> a = slope_fix(scale(S[0], sc.dn), scale(S[(size_t)H], sc.dn),
+                                                scale(S[(size_t)(n_r - 2) * H], sc.dn),
+                                                scale(S[(size_t)(n_r - 1) * H], sc.dn), ca, c0, cn);
                 const SlopePhasors<T> ph0 = slope_phasors(slope_fix_part(a, false), wt, wnt);
                 const SlopePhasors<T> phM = slope_phasors(slope_fix_part(a, true), wt, wnt);
                 const bool t0 = t == 0;
@@ -636,8 +727,9 @@ __device__ __forceinline__ void body_cols_fwd(int unit, int G, cx<T> *__restrict
         }
         SlopePhasors<T> ph0 = ph, phM = ph;
         if (is0) {   // bins 0 and M of the packed column: real coefficients each
-            const SlopeFix<T> a = slope_fix(S[0], S[(size_t)H], S[(size_t)(n_r - 2) * H],
-                                            S[(size_t)(n_r - 1) * H], ca, c0, cn);
+            const SlopeFix<T> a = slope_fix(scale(S[0], sc.dn), scale(S[(size_t)H], sc.dn),
+                                            scale(S[(size_t)(n_r - 2) * H], sc.dn),
+                                            scale(S[(size_t)(n_r - 1) * H], sc.dn), ca, c0, cn);
             ph0 = slope_phasors(slope_fix_part(a, false), wt, wnt);
             phM = slope_phasors(slope_fix_part(a, true), wt, wnt);
         }
@@ -689,7 +781,7 @@ __device__ __forceinline__ void body_cols_fwd(int unit, int G, cx<T> *__restrict
 #pragma unroll
         for (int e = 0; e < E / 2; ++e) {
             const int i = t + e * TH;
-            if (i < n_out) Z[(size_t)i * H + col] = cx2<T>{y0[e], y1[e]};
+            if (i < n_out) Z[(size_t)i * H + col] = cx2<T>{y0[e], y1[e]};   // still scaled
         }
     }
 }
@@ -751,7 +843,8 @@ __device__ __forceinline__ void body_cols_adj(int unit, int G, cx<T> *__restrict
                                               const cx2<T> *__restrict__ spec, int H, int n_r,
                                               int ldspec, T ca, T c0, T cn,
                                               const cx<T> *__restrict__ twL,
-                                              cx2<T> *spl = nullptr) {
+                                              cx2<T> *spl = nullptr,
+                                              unsigned *__restrict__ gscale = nullptr) {
     constexpr int TH = L / E;
     const int gi = threadIdx.x % G, t = threadIdx.x / G;
     const int col = unit * G + gi;
@@ -776,15 +869,16 @@ __device__ __forceinline__ void body_cols_adj(int unit, int G, cx<T> *__restrict
     }
     Twiddles<L, E, T> tw;
     tw.load(t, twL, 1);
+    // before the prefetch: the wait for this load must not wait for it
+    const GridScale<T> sc = scale_take<T>(gscale);
     // issued after the column's loads, which the transforms wait for
     if constexpr (PF) prefetch_spectra<T, L, E>(unit, G, H, ldspec, srad, spl);
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         const int i = t + e * TH;
-        if (e >= E / 2 || !valid || i >= n_r) {
-            va[0][e] = cx<T>{T(0), T(0)};
-            va[1][e] = cx<T>{T(0), T(0)};
-        }
+        const bool z = e >= E / 2 || !valid || i >= n_r;
+        va[0][e] = z ? cx<T>{T(0), T(0)} : scale(va[0][e], sc.dn);
+        va[1][e] = z ? cx<T>{T(0), T(0)} : scale(va[1][e], sc.dn);
     }
     // FP32 (SPLIT): V_r is transformed, meets the radial pairs, then V_p is
     // transformed while the azimuthal pairs arrive in LDS.  FP64: both
@@ -919,7 +1013,7 @@ __device__ __forceinline__ void body_cols_adj(int unit, int G, cx<T> *__restrict
                 if (i == 1) acc = acc + scale(w[0], c0 - ca);
                 if (i == n_r - 2) acc = acc + scale(w[3], ca - cn);
                 if (i == n_r - 1) acc = acc + scale(w[3], cn) + scale(w[2], ca);
-                D[(size_t)i * H + col] = acc;
+                D[(size_t)i * H + col] = acc;   // still scaled
             }
         }
     }

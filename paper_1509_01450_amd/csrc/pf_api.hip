@@ -103,6 +103,7 @@ static void free_plan_device(Plan *p) {
     if (p->wspec) (void)hipFree(p->wspec);
     if (p->wws) (void)hipFree(p->wws);
     p->spec = p->twN = p->twL = p->ws = p->wspec = p->wws = nullptr;
+    p->gscale = nullptr;
     p->tables = nullptr;
     p->built = false;
 }
@@ -152,16 +153,18 @@ int forces_t(const Plan &p, const T *sigma, const T *sigma_w, T *fr, T *fp, hipS
     using C = pf::cx<T>;
     C *S = (C *)p.ws;
     C *Z = S + (size_t)p.n_in * p.H;   // (Zr, Zp) pairs
+    unsigned *g = p.gscale;   // the forward map's scale words
     int rc = pf::launch_rows_r2c<T>(p, sigma, nullptr, p.n_in, S, (const C *)p.twN, p.sched.rows,
-                                    st);
+                                    st, g);
     if (rc) return rc;
-    rc = pf::launch_cols_fwd<T>(p, S, Z, (const C *)p.spec, (const C *)p.twL, p.sched.cols, st);
+    rc = pf::launch_cols_fwd<T>(p, S, Z, (const C *)p.spec, (const C *)p.twL, p.sched.cols, st,
+                                g);
     if (rc) return rc;
     if (p.wedges) {
-        rc = pf::launch_wedge_terms<T>(p, sigma, sigma_w, Z, st);
+        rc = pf::launch_wedge_terms<T>(p, sigma, sigma_w, Z, st, g);
         if (rc) return rc;
     }
-    return pf::launch_rows_c2r<T>(p, Z, p.n_r, fr, fp, (const C *)p.twN, p.sched.rows2, st);
+    return pf::launch_rows_c2r<T>(p, Z, p.n_r, fr, fp, (const C *)p.twN, p.sched.rows2, st, g);
 }
 
 template <typename T>
@@ -169,12 +172,14 @@ int backward_t(const Plan &p, const T *gr, const T *gp, T *gs, hipStream_t st) {
     using C = pf::cx<T>;
     C *V = (C *)p.ws;                        // (Vr, Vp) pairs
     C *D = V + 2 * (size_t)p.n_r * p.H;
-    int rc = pf::launch_rows_r2c<T>(p, gr, gp, p.n_r, V, (const C *)p.twN, p.sched.rows2, st);
+    unsigned *g = p.gscale ? p.gscale + 128 : nullptr;   // the transpose's scale words
+    int rc = pf::launch_rows_r2c<T>(p, gr, gp, p.n_r, V, (const C *)p.twN, p.sched.rows2, st, g);
     if (rc) return rc;
     rc = pf::launch_cols_adj<T>(p, V, D, (const C *)p.spec, (const C *)p.twL, p.sched.cols_adj,
-                                st);
+                                st, g);
     if (rc) return rc;
-    return pf::launch_rows_c2r<T>(p, D, p.n_r, gs, nullptr, (const C *)p.twN, p.sched.rows, st);
+    return pf::launch_rows_c2r<T>(p, D, p.n_r, gs, nullptr, (const C *)p.twN, p.sched.rows, st,
+                                  g);
 }
 
 template <typename T>
@@ -185,29 +190,31 @@ int timed_t(const Plan &p, bool bwd, const void *in0, const void *in1, void *out
     C *W1 = W0 + (size_t)p.n_in * p.H;      // forward: S = W0, Z = W1
     C *W2 = W0 + 2 * (size_t)p.n_r * p.H;   // transpose: V = W0, D = W2
     int rc = PF_OK;
+    unsigned *g = p.gscale ? p.gscale + (bwd ? 128 : 0) : nullptr;
     PF_HIP(hipEventRecord(ev[0], st));
     for (int k = 0; k < reps && !rc; ++k)
         rc = pf::launch_rows_r2c<T>(p, (const T *)in0, bwd ? (const T *)in1 : nullptr, p.n_in,
-                                    W0, (const C *)p.twN, bwd ? p.sched.rows2 : p.sched.rows, st);
+                                    W0, (const C *)p.twN, bwd ? p.sched.rows2 : p.sched.rows, st,
+                                    g);
     if (rc) return rc;
     PF_HIP(hipEventRecord(ev[1], st));
     for (int k = 0; k < reps && !rc; ++k) {
         if (!bwd)
             rc = pf::launch_cols_fwd<T>(p, W0, W1, (const C *)p.spec, (const C *)p.twL,
-                                        p.sched.cols, st);
+                                        p.sched.cols, st, g);
         else
             rc = pf::launch_cols_adj<T>(p, W0, W2, (const C *)p.spec, (const C *)p.twL,
-                                        p.sched.cols_adj, st);
+                                        p.sched.cols_adj, st, g);
     }
     if (rc) return rc;
     PF_HIP(hipEventRecord(ev[2], st));
     for (int k = 0; k < reps && !rc; ++k) {
         if (!bwd)
             rc = pf::launch_rows_c2r<T>(p, W1, p.n_r, (T *)out0, (T *)out1, (const C *)p.twN,
-                                        p.sched.rows2, st);
+                                        p.sched.rows2, st, g);
         else
             rc = pf::launch_rows_c2r<T>(p, W2, p.n_r, (T *)out0, nullptr, (const C *)p.twN,
-                                        p.sched.rows, st);
+                                        p.sched.rows, st, g);
     }
     if (rc) return rc;
     PF_HIP(hipEventRecord(ev[3], st));
@@ -484,11 +491,21 @@ int pf_kernels_build(pf_plan h, const pf_build_opts *opts, void *stream) {
     if (!rc) {
         // forward: S (n_in rows) and the (Zr, Zp) pairs (n_r rows); transpose:
         // the (Vr, Vp) pairs and D (n_r rows each)
+        // and after them the FP32 scale words (128 for the forward map, 128
+        // for the transpose; the notes are zero between calls)
         const size_t rows = std::max((size_t)p.n_in + 2 * (size_t)p.n_r, (size_t)3 * p.n_r);
-        hipError_t e = hipMalloc(&p.ws, rows * p.H * (f64 ? 16 : 8));
+        const size_t wsb = (rows * p.H * (f64 ? 16 : 8) + 255) / 256 * 256;
+        hipError_t e = hipMalloc(&p.ws, wsb + 256 * sizeof(unsigned));
         if (e != hipSuccess) {
             pf::set_error("workspace allocation failed: %s", hipGetErrorString(e));
             rc = PF_ENOMEM;
+        } else if (!f64) {
+            p.gscale = (unsigned *)((unsigned char *)p.ws + wsb);
+            e = hipMemsetAsync(p.gscale, 0, 256 * sizeof(unsigned), st);
+            if (e != hipSuccess) {
+                pf::set_error("hipMemsetAsync: %s", hipGetErrorString(e));
+                rc = PF_EHIP;
+            }
         }
     }
     if (!rc && p.wedges) rc = pf::build_wedge_spectra(p, st);
@@ -497,6 +514,13 @@ int pf_kernels_build(pf_plan h, const pf_build_opts *opts, void *stream) {
         return rc;
     }
     if (!p.patch) rc = pf::autotune_plan(p, st);
+    if (!rc) {
+        hipError_t e = hipStreamSynchronize(st);
+        if (e != hipSuccess) {
+            pf::set_error("hipStreamSynchronize: %s", hipGetErrorString(e));
+            rc = PF_EHIP;
+        }
+    }
     if (rc) {
         pf::free_plan_device(&p);
         return rc;

@@ -46,6 +46,7 @@ struct GDisk {
     cx2<T> *Z;     // (Zr, Zp) pairs
     const cx2<T> *spec;
     const cx<T> *twN, *twL;
+    unsigned *gscale;   // the plan's FP32 scale words (nullptr in FP64)
 };
 
 // One disk in one class launch: its descriptor and its first workgroup.
@@ -81,10 +82,10 @@ __global__ __launch_bounds__(512) void k_grp_rows(const GDisk<T> *__restrict__ d
     const int G = blockDim.x / (M / E);
     cx<T> *const buf = reinterpret_cast<cx<T> *>(smem_raw);
     if constexpr (C == 1)
-        body_rows_r2c<T, M, E, 1>(unit, G, buf, d.sigma, nullptr, d.n_r, d.S, d.twN);
+        body_rows_r2c<T, M, E, 1>(unit, G, buf, d.sigma, nullptr, d.n_r, d.S, d.twN, d.gscale);
     else
         body_rows_c2r<T, M, E, 2>(unit, G, buf, reinterpret_cast<const cx<T> *>(d.Z), d.n_r,
-                                  d.fr, d.fp, d.twN);
+                                  d.fr, d.fp, d.twN, d.gscale);
 }
 
 // Column groups of a disk are remapped as in the single-disk kernels: a
@@ -109,7 +110,7 @@ __global__ __launch_bounds__(512) void k_grp_cols_pf(const GDisk<T> *__restrict_
     const int grp = grp_xcd(blockIdx.x - en.first, n_groups);
     if (grp >= n_groups) return;   // whole workgroup leaves together
     body_cols_fwd<T, L, E, true>(grp, G, fbuf, d.S, d.Z, d.spec, d.H, d.n_r, d.n_r, d.ldspec,
-                                 d.ca, d.c0, d.cn, d.twL, spl);
+                                 d.ca, d.c0, d.cn, d.twL, spl, d.gscale);
 }
 
 // Pass B for shapes without a static instance: one dynamic LDS array (FP32
@@ -127,7 +128,7 @@ __global__ __launch_bounds__(512) void k_grp_cols(const GDisk<T> *__restrict__ d
     cx<T> *const buf = reinterpret_cast<cx<T> *>(smem_raw);
     body_cols_fwd<T, L, E, sizeof(T) == 4>(
         grp, G, buf, d.S, d.Z, d.spec, d.H, d.n_r, d.n_r, d.ldspec, d.ca, d.c0, d.cn, d.twL,
-        reinterpret_cast<cx2<T> *>(buf + (size_t)G * padded_len(L)));
+        reinterpret_cast<cx2<T> *>(buf + (size_t)G * padded_len(L)), d.gscale);
 }
 
 // Table upload: the bytes travel as the kernel's argument.
@@ -250,6 +251,7 @@ void make_desc(const Plan *const *plans, int n, const void *const *sigma, void *
         d.spec = (const cx2<T> *)p.spec;
         d.twN = (const cx<T> *)p.twN;
         d.twL = (const cx<T> *)p.twL;
+        d.gscale = p.gscale;
         d.sigma = (const T *)sigma[k];
         d.fr = (T *)f_r[k];
         d.fp = (T *)f_phi[k];

@@ -74,6 +74,9 @@ struct Plan {
                               // (forward: S, then (Zr, Zp) pairs; transpose:
                               // (Vr, Vp) pairs, then D)
     double *tables = nullptr; // [6][L][n_phi] FP64 (only with keep_tables)
+    unsigned *gscale = nullptr; // FP32 scale words after the workspace: the
+                                // forward map's at [0, 65), the transpose's
+                                // at [128, 193) (pass_bodies.hpp)
     void *wspec = nullptr;    // wedge spectra [2][n_r][H] pairs, plan precision
     void *wws = nullptr;      // wedge workspace: slope row, then its spectra
     Schedule sched;
@@ -86,23 +89,25 @@ struct Plan {
 // Row transforms along phi of n_rows rows.  r2c: rows of in0 -> packed half
 // spectra out ([n_rows][M] complex); with in1, rows of in0 and in1 -> pairs
 // ([n_rows][M] pairs).  c2r: the inverse, from complex rows to out0, or from
-// pairs to out0 and out1 when out1 is given.
+// pairs to out0 and out1 when out1 is given.  g: the call's FP32 scale
+// words (pass_bodies.hpp: r2c notes the largest magnitude in them, c2r
+// clears them; nullptr: no scaling).
 template <typename T>
 int launch_rows_r2c(const Plan &p, const T *in0, const T *in1, int n_rows, cx<T> *out,
-                    const cx<T> *twN, Shape s, hipStream_t st);
+                    const cx<T> *twN, Shape s, hipStream_t st, unsigned *g = nullptr);
 template <typename T>
 int launch_rows_c2r(const Plan &p, const cx<T> *in, int n_rows, T *out0, T *out1,
-                    const cx<T> *twN, Shape s, hipStream_t st);
+                    const cx<T> *twN, Shape s, hipStream_t st, unsigned *g = nullptr);
 // Column pass of the forward map (u-FFT, spectral multiply-accumulate with
 // the spectral radial slope, inverse u-FFTs, crop): S ([n_in][H]) -> pairs
-// Z ([n_r][H]).
+// Z ([n_r][H]); g: the scale words pass A noted (nullptr: unscaled).
 template <typename T>
 int launch_cols_fwd(const Plan &p, const cx<T> *S, cx<T> *Z, const cx<T> *spec,
-                    const cx<T> *twL, Shape s, hipStream_t st);
+                    const cx<T> *twL, Shape s, hipStream_t st, unsigned *g = nullptr);
 // Column pass of the transpose: pairs V -> D.
 template <typename T>
 int launch_cols_adj(const Plan &p, const cx<T> *V, cx<T> *D, const cx<T> *spec,
-                    const cx<T> *twL, Shape s, hipStream_t st);
+                    const cx<T> *twL, Shape s, hipStream_t st, unsigned *g = nullptr);
 
 // ---- kernels (pf_tables.hip) ------------------------------------------------
 int build_tables_and_spectra(Plan &p, hipStream_t st);
@@ -112,7 +117,7 @@ int build_tables_and_spectra(Plan &p, hipStream_t st);
 int build_wedge_spectra(Plan &p, hipStream_t st);
 template <typename T>
 int launch_wedge_terms(const Plan &p, const T *sigma_src, const T *sigma_w, cx<T> *Z,
-                       hipStream_t st);
+                       hipStream_t st, const unsigned *g = nullptr);
 
 // ---- host helpers -------------------------------------------------------------
 // exp(-2 pi i j / n) for j in [0, n), computed in long double

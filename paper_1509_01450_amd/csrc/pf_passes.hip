@@ -17,19 +17,23 @@ template <typename T, int M, int E, int C>
 __global__ __launch_bounds__(512) void k_rows_r2c(const T *__restrict__ in0,
                                                   const T *__restrict__ in1, int n_rows,
                                                   cx<T> *__restrict__ out,
-                                                  const cx<T> *__restrict__ twN) {
+                                                  const cx<T> *__restrict__ twN,
+                                                  unsigned *__restrict__ gscale) {
     extern __shared__ unsigned char smem_raw[];
     body_rows_r2c<T, M, E, C>(blockIdx.x, blockDim.x / (M / E),
-                              reinterpret_cast<cx<T> *>(smem_raw), in0, in1, n_rows, out, twN);
+                              reinterpret_cast<cx<T> *>(smem_raw), in0, in1, n_rows, out, twN,
+                              gscale);
 }
 
 template <typename T, int M, int E, int C>
 __global__ __launch_bounds__(512) void k_rows_c2r(const cx<T> *__restrict__ in, int n_rows,
                                                   T *__restrict__ out0, T *__restrict__ out1,
-                                                  const cx<T> *__restrict__ twN) {
+                                                  const cx<T> *__restrict__ twN,
+                                                  unsigned *__restrict__ gscale) {
     extern __shared__ unsigned char smem_raw[];
     body_rows_c2r<T, M, E, C>(blockIdx.x, blockDim.x / (M / E),
-                              reinterpret_cast<cx<T> *>(smem_raw), in, n_rows, out0, out1, twN);
+                              reinterpret_cast<cx<T> *>(smem_raw), in, n_rows, out0, out1, twN,
+                              gscale);
 }
 
 // Forward column pass for any G, with one dynamic LDS array: used where the
@@ -43,7 +47,7 @@ __global__ __launch_bounds__(512) void k_cols_fwd(const cx<T> *__restrict__ S,
                                                   const cx2<T> *__restrict__ spec, int H, int n_r,
                                                   int n_out, int ldspec, T ca, T c0, T cn,
                                                   const cx<T> *__restrict__ twL, int per_xcd,
-                                                  int n_groups) {
+                                                  int n_groups, unsigned *__restrict__ gscale) {
     extern __shared__ unsigned char smem_raw[];
     const int grp = xcd_group(blockIdx.x, per_xcd);
     if (grp >= n_groups) return;  // whole workgroup leaves together
@@ -51,7 +55,8 @@ __global__ __launch_bounds__(512) void k_cols_fwd(const cx<T> *__restrict__ S,
     cx<T> *const buf = reinterpret_cast<cx<T> *>(smem_raw);
     body_cols_fwd<T, L, E, sizeof(T) == 4>(grp, G, buf, S, Z, spec, H, n_r, n_out, ldspec, ca,
                                            c0, cn, twL,
-                                           reinterpret_cast<cx2<T> *>(buf + (size_t)G * padded_len(L)));
+                                           reinterpret_cast<cx2<T> *>(buf + (size_t)G * padded_len(L)),
+                                           gscale);
 }
 
 // Forward column pass with G fixed at compile time: the transform buffer
@@ -66,13 +71,14 @@ __global__ __launch_bounds__(512) void k_cols_fwd_pf(const cx<T> *__restrict__ S
                                                      const cx2<T> *__restrict__ spec, int H,
                                                      int n_r, int n_out, int ldspec, T ca, T c0,
                                                      T cn, const cx<T> *__restrict__ twL,
-                                                     int per_xcd, int n_groups) {
+                                                     int per_xcd, int n_groups,
+                                                     unsigned *__restrict__ gscale) {
     __shared__ cx<T> fbuf[G * padded_len(L)];
     __shared__ cx2<T> spl[G * spec_prefetch_len<L, E>()];
     const int grp = xcd_group(blockIdx.x, per_xcd);
     if (grp >= n_groups) return;  // whole workgroup leaves together
     body_cols_fwd<T, L, E, true>(grp, G, fbuf, S, Z, spec, H, n_r, n_out, ldspec, ca, c0, cn,
-                                 twL, spl);
+                                 twL, spl, gscale);
 }
 
 template <typename T, int L, int E>
@@ -81,12 +87,12 @@ __global__ __launch_bounds__(512) void k_cols_adj(const cx2<T> *__restrict__ V,
                                                   const cx2<T> *__restrict__ spec, int H, int n_r,
                                                   int ldspec, T ca, T c0, T cn,
                                                   const cx<T> *__restrict__ twL, int per_xcd,
-                                                  int n_groups) {
+                                                  int n_groups, unsigned *__restrict__ gscale) {
     extern __shared__ unsigned char smem_raw[];
     const int grp = xcd_group(blockIdx.x, per_xcd);
     if (grp >= n_groups) return;
     body_cols_adj<T, L, E>(grp, blockDim.x / (L / E), reinterpret_cast<cx<T> *>(smem_raw), V, D,
-                           spec, H, n_r, ldspec, ca, c0, cn, twL);
+                           spec, H, n_r, ldspec, ca, c0, cn, twL, nullptr, gscale);
 }
 
 // Transpose column pass with G fixed at compile time and the radial
@@ -97,12 +103,14 @@ __global__ __launch_bounds__(512) void k_cols_adj_pf(const cx2<T> *__restrict__ 
                                                      const cx2<T> *__restrict__ spec, int H,
                                                      int n_r, int ldspec, T ca, T c0, T cn,
                                                      const cx<T> *__restrict__ twL, int per_xcd,
-                                                     int n_groups) {
+                                                     int n_groups,
+                                                     unsigned *__restrict__ gscale) {
     __shared__ cx<T> fbuf[G * padded_len(L)];
     __shared__ cx2<T> spl[G * spec_prefetch_len<L, E>()];
     const int grp = xcd_group(blockIdx.x, per_xcd);
     if (grp >= n_groups) return;  // whole workgroup leaves together
-    body_cols_adj<T, L, E, true>(grp, G, fbuf, V, D, spec, H, n_r, ldspec, ca, c0, cn, twL, spl);
+    body_cols_adj<T, L, E, true>(grp, G, fbuf, V, D, spec, H, n_r, ldspec, ca, c0, cn, twL, spl,
+                                 gscale);
 }
 
 // ---------------------------------------------------------------------------
@@ -182,10 +190,11 @@ constexpr bool cols_pf_fits() {
 template <typename T, int N, int E, int G>
 bool launch_cols_pf(dim3 grid, hipStream_t st, const cx<T> *S, cx2<T> *Z, const cx2<T> *spec,
                     const Plan &p, T ca, T c0, T cn, const cx<T> *tw, int per_xcd,
-                    int n_groups) {
+                    int n_groups, unsigned *g) {
     if constexpr (cols_pf_fits<T, N, E, G>()) {
         hipLaunchKernelGGL((k_cols_fwd_pf<T, N, E, G>), grid, dim3(G * (N / E)), 0, st, S, Z,
-                           spec, p.H, p.n_in, p.n_r, p.ldspec, ca, c0, cn, tw, per_xcd, n_groups);
+                           spec, p.H, p.n_in, p.n_r, p.ldspec, ca, c0, cn, tw, per_xcd, n_groups,
+                           g);
         return true;
     }
     return false;
@@ -194,10 +203,10 @@ bool launch_cols_pf(dim3 grid, hipStream_t st, const cx<T> *S, cx2<T> *Z, const 
 template <typename T, int N, int E, int G>
 bool launch_cols_adj_pf(dim3 grid, hipStream_t st, const cx2<T> *V, cx<T> *D,
                         const cx2<T> *spec, const Plan &p, T ca, T c0, T cn, const cx<T> *tw,
-                        int per_xcd, int n_groups) {
+                        int per_xcd, int n_groups, unsigned *g) {
     if constexpr (cols_pf_fits<T, N, E, G>()) {
         hipLaunchKernelGGL((k_cols_adj_pf<T, N, E, G>), grid, dim3(G * (N / E)), 0, st, V, D,
-                           spec, p.H, p.n_r, p.ldspec, ca, c0, cn, tw, per_xcd, n_groups);
+                           spec, p.H, p.n_r, p.ldspec, ca, c0, cn, tw, per_xcd, n_groups, g);
         return true;
     }
     return false;
@@ -207,7 +216,7 @@ template <typename T>
 struct Disp {
     template <int N, int E, int C>
     static int r2c(const T *in0, const T *in1, int n_rows, cx<T> *out, const cx<T> *tw, int G,
-                   hipStream_t st) {
+                   hipStream_t st, unsigned *g) {
         if constexpr (E <= N) {
             constexpr int TH = N / E;
             const int blocks = (n_rows + G - 1) / G;
@@ -215,7 +224,7 @@ struct Disp {
             int rc = allow_lds(k_rows_r2c<T, N, E, C>, lds);
             if (rc) return rc;
             hipLaunchKernelGGL((k_rows_r2c<T, N, E, C>), dim3(blocks), dim3(G * TH), lds, st, in0,
-                               in1, n_rows, out, tw);
+                               in1, n_rows, out, tw, g);
             PF_HIP(hipGetLastError());
             return PF_OK;
         }
@@ -224,7 +233,7 @@ struct Disp {
     }
     template <int N, int E, int C>
     static int c2r(const cx<T> *in, int n_rows, T *o0, T *o1, const cx<T> *tw, int G,
-                   hipStream_t st) {
+                   hipStream_t st, unsigned *g) {
         if constexpr (E <= N) {
             constexpr int TH = N / E;
             const int blocks = (n_rows + G - 1) / G;
@@ -232,7 +241,7 @@ struct Disp {
             int rc = allow_lds(k_rows_c2r<T, N, E, C>, lds);
             if (rc) return rc;
             hipLaunchKernelGGL((k_rows_c2r<T, N, E, C>), dim3(blocks), dim3(G * TH), lds, st, in,
-                               n_rows, o0, o1, tw);
+                               n_rows, o0, o1, tw, g);
             PF_HIP(hipGetLastError());
             return PF_OK;
         }
@@ -241,7 +250,7 @@ struct Disp {
     }
     template <int N, int E, bool ADJ>
     static int cols(const Plan &p, const cx<T> *a, cx<T> *o, const cx<T> *spec, const cx<T> *tw,
-                    int G, hipStream_t st) {
+                    int G, hipStream_t st, unsigned *g) {
         if constexpr (E <= N) {
             constexpr int TH = N / E;
             const int n_groups = (p.H + G - 1) / G;
@@ -261,11 +270,11 @@ struct Disp {
                     const cx2<T> *v = reinterpret_cast<const cx2<T> *>(a);
                     const bool done =
                         G == 1   ? launch_cols_adj_pf<T, N, E, 1>(grid, st, v, o, sp, p, ca, c0,
-                                                                  cn, tw, per_xcd, n_groups)
+                                                                  cn, tw, per_xcd, n_groups, g)
                         : G == 2 ? launch_cols_adj_pf<T, N, E, 2>(grid, st, v, o, sp, p, ca, c0,
-                                                                  cn, tw, per_xcd, n_groups)
+                                                                  cn, tw, per_xcd, n_groups, g)
                         : G == 4 ? launch_cols_adj_pf<T, N, E, 4>(grid, st, v, o, sp, p, ca, c0,
-                                                                  cn, tw, per_xcd, n_groups)
+                                                                  cn, tw, per_xcd, n_groups, g)
                                  : false;
                     if (done) {
                         PF_HIP(hipGetLastError());
@@ -276,7 +285,7 @@ struct Disp {
                 if (rc) return rc;
                 hipLaunchKernelGGL((k_cols_adj<T, N, E>), dim3(blocks), dim3(G * TH), lds, st,
                                    reinterpret_cast<const cx2<T> *>(a), o, sp, p.H, p.n_r,
-                                   p.ldspec, ca, c0, cn, tw, per_xcd, n_groups);
+                                   p.ldspec, ca, c0, cn, tw, per_xcd, n_groups, g);
             } else {
                 if constexpr (TH >= 64) {
                     // the prefetch's 32-bit offsets cover the radial half
@@ -288,11 +297,11 @@ struct Disp {
                     cx2<T> *z = reinterpret_cast<cx2<T> *>(o);
                     const bool done =
                         G == 1   ? launch_cols_pf<T, N, E, 1>(grid, st, a, z, sp, p, ca, c0, cn,
-                                                              tw, per_xcd, n_groups)
+                                                              tw, per_xcd, n_groups, g)
                         : G == 2 ? launch_cols_pf<T, N, E, 2>(grid, st, a, z, sp, p, ca, c0, cn,
-                                                              tw, per_xcd, n_groups)
+                                                              tw, per_xcd, n_groups, g)
                         : G == 4 ? launch_cols_pf<T, N, E, 4>(grid, st, a, z, sp, p, ca, c0, cn,
-                                                              tw, per_xcd, n_groups)
+                                                              tw, per_xcd, n_groups, g)
                                  : false;
                     if (done) {
                         PF_HIP(hipGetLastError());
@@ -303,7 +312,7 @@ struct Disp {
                 if (rc) return rc;
                 hipLaunchKernelGGL((k_cols_fwd<T, N, E>), dim3(blocks), dim3(G * TH), lds, st, a,
                                    reinterpret_cast<cx2<T> *>(o), sp, p.H, p.n_in, p.n_r,
-                                   p.ldspec, ca, c0, cn, tw, per_xcd, n_groups);
+                                   p.ldspec, ca, c0, cn, tw, per_xcd, n_groups, g);
             }
             PF_HIP(hipGetLastError());
             return PF_OK;
@@ -313,18 +322,18 @@ struct Disp {
     }
     template <int N>
     static int r2c_e(int E, const T *in0, const T *in1, int n_rows, cx<T> *out, const cx<T> *tw,
-                     int G, hipStream_t st) {
+                     int G, hipStream_t st, unsigned *g) {
         if (in1) {
             switch (E) {
-                case 4: return r2c<N, 4, 2>(in0, in1, n_rows, out, tw, G, st);
-                case 8: return r2c<N, 8, 2>(in0, in1, n_rows, out, tw, G, st);
-                case 16: return r2c<N, 16, 2>(in0, in1, n_rows, out, tw, G, st);
+                case 4: return r2c<N, 4, 2>(in0, in1, n_rows, out, tw, G, st, g);
+                case 8: return r2c<N, 8, 2>(in0, in1, n_rows, out, tw, G, st, g);
+                case 16: return r2c<N, 16, 2>(in0, in1, n_rows, out, tw, G, st, g);
             }
         } else {
             switch (E) {
-                case 4: return r2c<N, 4, 1>(in0, in1, n_rows, out, tw, G, st);
-                case 8: return r2c<N, 8, 1>(in0, in1, n_rows, out, tw, G, st);
-                case 16: return r2c<N, 16, 1>(in0, in1, n_rows, out, tw, G, st);
+                case 4: return r2c<N, 4, 1>(in0, in1, n_rows, out, tw, G, st, g);
+                case 8: return r2c<N, 8, 1>(in0, in1, n_rows, out, tw, G, st, g);
+                case 16: return r2c<N, 16, 1>(in0, in1, n_rows, out, tw, G, st, g);
             }
         }
         set_error("bad points per thread %d", E);
@@ -332,18 +341,18 @@ struct Disp {
     }
     template <int N>
     static int c2r_e(int E, const cx<T> *in, int n_rows, T *o0, T *o1, const cx<T> *tw, int G,
-                     hipStream_t st) {
+                     hipStream_t st, unsigned *g) {
         if (o1) {
             switch (E) {
-                case 4: return c2r<N, 4, 2>(in, n_rows, o0, o1, tw, G, st);
-                case 8: return c2r<N, 8, 2>(in, n_rows, o0, o1, tw, G, st);
-                case 16: return c2r<N, 16, 2>(in, n_rows, o0, o1, tw, G, st);
+                case 4: return c2r<N, 4, 2>(in, n_rows, o0, o1, tw, G, st, g);
+                case 8: return c2r<N, 8, 2>(in, n_rows, o0, o1, tw, G, st, g);
+                case 16: return c2r<N, 16, 2>(in, n_rows, o0, o1, tw, G, st, g);
             }
         } else {
             switch (E) {
-                case 4: return c2r<N, 4, 1>(in, n_rows, o0, o1, tw, G, st);
-                case 8: return c2r<N, 8, 1>(in, n_rows, o0, o1, tw, G, st);
-                case 16: return c2r<N, 16, 1>(in, n_rows, o0, o1, tw, G, st);
+                case 4: return c2r<N, 4, 1>(in, n_rows, o0, o1, tw, G, st, g);
+                case 8: return c2r<N, 8, 1>(in, n_rows, o0, o1, tw, G, st, g);
+                case 16: return c2r<N, 16, 1>(in, n_rows, o0, o1, tw, G, st, g);
             }
         }
         set_error("bad points per thread %d", E);
@@ -351,20 +360,20 @@ struct Disp {
     }
     template <int N>
     static int fwd_e(int E, const Plan &p, const cx<T> *a, cx<T> *o, const cx<T> *spec,
-                     const cx<T> *tw, int G, hipStream_t st) {
+                     const cx<T> *tw, int G, hipStream_t st, unsigned *g) {
         switch (E) {
-            case 8: return cols<N, 8, false>(p, a, o, spec, tw, G, st);
-            case 16: return cols<N, 16, false>(p, a, o, spec, tw, G, st);
+            case 8: return cols<N, 8, false>(p, a, o, spec, tw, G, st, g);
+            case 16: return cols<N, 16, false>(p, a, o, spec, tw, G, st, g);
         }
         set_error("bad points per thread %d", E);
         return PF_EUNSUPPORTED;
     }
     template <int N>
     static int adj_e(int E, const Plan &p, const cx<T> *a, cx<T> *o, const cx<T> *spec,
-                     const cx<T> *tw, int G, hipStream_t st) {
+                     const cx<T> *tw, int G, hipStream_t st, unsigned *g) {
         switch (E) {
-            case 8: return cols<N, 8, true>(p, a, o, spec, tw, G, st);
-            case 16: return cols<N, 16, true>(p, a, o, spec, tw, G, st);
+            case 8: return cols<N, 8, true>(p, a, o, spec, tw, G, st, g);
+            case 16: return cols<N, 16, true>(p, a, o, spec, tw, G, st, g);
         }
         set_error("bad points per thread %d", E);
         return PF_EUNSUPPORTED;
@@ -375,53 +384,53 @@ struct Disp {
 
 template <typename T>
 int launch_rows_r2c(const Plan &p, const T *in0, const T *in1, int n_rows, cx<T> *out,
-                    const cx<T> *twN, Shape s, hipStream_t st) {
+                    const cx<T> *twN, Shape s, hipStream_t st, unsigned *g) {
     if (!valid_shape_rows(p.M, s, sizeof(T) == 8)) {
         set_error("invalid row shape E=%d G=%d for M=%d", s.E, s.G, p.M);
         return PF_EINVAL;
     }
-    PF_SWITCH_POW2(p.M, Disp<T>::template r2c_e, s.E, in0, in1, n_rows, out, twN, s.G, st);
+    PF_SWITCH_POW2(p.M, Disp<T>::template r2c_e, s.E, in0, in1, n_rows, out, twN, s.G, st, g);
 }
 
 template <typename T>
 int launch_rows_c2r(const Plan &p, const cx<T> *in, int n_rows, T *out0, T *out1,
-                    const cx<T> *twN, Shape s, hipStream_t st) {
+                    const cx<T> *twN, Shape s, hipStream_t st, unsigned *g) {
     if (!valid_shape_rows(p.M, s, sizeof(T) == 8)) {
         set_error("invalid row shape E=%d G=%d for M=%d", s.E, s.G, p.M);
         return PF_EINVAL;
     }
-    PF_SWITCH_POW2(p.M, Disp<T>::template c2r_e, s.E, in, n_rows, out0, out1, twN, s.G, st);
+    PF_SWITCH_POW2(p.M, Disp<T>::template c2r_e, s.E, in, n_rows, out0, out1, twN, s.G, st, g);
 }
 
 template <typename T>
 int launch_cols_fwd(const Plan &p, const cx<T> *S, cx<T> *Z, const cx<T> *spec,
-                    const cx<T> *twL, Shape s, hipStream_t st) {
+                    const cx<T> *twL, Shape s, hipStream_t st, unsigned *g) {
     if (!valid_shape_cols(p.L, s, sizeof(T) == 8)) {
         set_error("invalid column shape E=%d G=%d for L=%d", s.E, s.G, p.L);
         return PF_EINVAL;
     }
-    PF_SWITCH_POW2(p.L, Disp<T>::template fwd_e, s.E, p, S, Z, spec, twL, s.G, st);
+    PF_SWITCH_POW2(p.L, Disp<T>::template fwd_e, s.E, p, S, Z, spec, twL, s.G, st, g);
 }
 
 template <typename T>
 int launch_cols_adj(const Plan &p, const cx<T> *V, cx<T> *D, const cx<T> *spec,
-                    const cx<T> *twL, Shape s, hipStream_t st) {
+                    const cx<T> *twL, Shape s, hipStream_t st, unsigned *g) {
     if (!valid_shape_cols(p.L, s, sizeof(T) == 8)) {
         set_error("invalid column shape E=%d G=%d for L=%d", s.E, s.G, p.L);
         return PF_EINVAL;
     }
-    PF_SWITCH_POW2(p.L, Disp<T>::template adj_e, s.E, p, V, D, spec, twL, s.G, st);
+    PF_SWITCH_POW2(p.L, Disp<T>::template adj_e, s.E, p, V, D, spec, twL, s.G, st, g);
 }
 
 #define PF_INSTANTIATE(T)                                                                      \
     template int launch_rows_r2c<T>(const Plan &, const T *, const T *, int, cx<T> *,          \
-                                    const cx<T> *, Shape, hipStream_t);                         \
+                                    const cx<T> *, Shape, hipStream_t, unsigned *);             \
     template int launch_rows_c2r<T>(const Plan &, const cx<T> *, int, T *, T *, const cx<T> *,  \
-                                    Shape, hipStream_t);                                        \
+                                    Shape, hipStream_t, unsigned *);                            \
     template int launch_cols_fwd<T>(const Plan &, const cx<T> *, cx<T> *, const cx<T> *,        \
-                                    const cx<T> *, Shape, hipStream_t);                         \
+                                    const cx<T> *, Shape, hipStream_t, unsigned *);             \
     template int launch_cols_adj<T>(const Plan &, const cx<T> *, cx<T> *, const cx<T> *,        \
-                                    const cx<T> *, Shape, hipStream_t);
+                                    const cx<T> *, Shape, hipStream_t, unsigned *);
 PF_INSTANTIATE(float)
 PF_INSTANTIATE(double)
 

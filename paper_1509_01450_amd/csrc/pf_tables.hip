@@ -950,11 +950,20 @@ __global__ void k_wedge_slope(const T *__restrict__ sigma_src, const T *__restri
 // Z[i][k] += wedge terms, from the row spectra w[k] = (sigma_w^, delta^r^)
 template <typename T>
 __global__ void k_wedge_add(cx2<T> *__restrict__ Z, const cx2<T> *__restrict__ wspec,
-                            const cx2<T> *__restrict__ w, int n_r, int H) {
+                            const cx2<T> *__restrict__ w, int n_r, int H,
+                            const unsigned *__restrict__ g) {
     const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= (long)n_r * H) return;
     const int k = (int)(idx % H);
-    const cx2<T> a = wspec[idx], b = wspec[(size_t)n_r * H + idx], x = w[k];
+    const cx2<T> a = wspec[idx], b = wspec[(size_t)n_r * H + idx];
+    cx2<T> x = w[k];
+    if (g) {
+        // FP32 calls: Z holds the column pass's output scaled by 2^-e (e in
+        // g[64]); the wedge terms join it at the same scale
+        const int ex = (int)g[64];
+        const T s = (T)__uint_as_float((unsigned)(127 - ex) << 23);
+        x = cx2<T>{scale(x.a, s), scale(x.b, s)};
+    }
     cx2<T> z = Z[idx];
     if (k == 0) {   // bins 0 and n_phi/2: real parts, radial force only
         z.a.x += a.a.x * x.a.x + a.b.x * x.b.x;
@@ -1008,7 +1017,7 @@ int build_wedge_spectra(Plan &p, hipStream_t st) {
 
 template <typename T>
 int launch_wedge_terms(const Plan &p, const T *sigma_src, const T *sigma_w, cx<T> *Z,
-                       hipStream_t st) {
+                       hipStream_t st, const unsigned *g) {
     T *slope = (T *)p.wws;
     cx<T> *wrow = (cx<T> *)((char *)p.wws + (size_t)p.n_phi * sizeof(T));
     const double rc0 = p.r_min * std::pow(p.beta, p.s0) * 0.5 * (1.0 + p.beta);
@@ -1022,14 +1031,15 @@ int launch_wedge_terms(const Plan &p, const T *sigma_src, const T *sigma_w, cx<T
     const long n = (long)p.n_r * p.H;
     hipLaunchKernelGGL(k_wedge_add<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st,
                        reinterpret_cast<cx2<T> *>(Z), (const cx2<T> *)p.wspec,
-                       reinterpret_cast<const cx2<T> *>(wrow), p.n_r, p.H);
+                       reinterpret_cast<const cx2<T> *>(wrow), p.n_r, p.H,
+                       sizeof(T) == 4 ? g : nullptr);
     PF_HIP(hipGetLastError());
     return PF_OK;
 }
 
 template int launch_wedge_terms<float>(const Plan &, const float *, const float *, cx<float> *,
-                                       hipStream_t);
+                                       hipStream_t, const unsigned *);
 template int launch_wedge_terms<double>(const Plan &, const double *, const double *,
-                                        cx<double> *, hipStream_t);
+                                        cx<double> *, hipStream_t, const unsigned *);
 
 }  // namespace pf
