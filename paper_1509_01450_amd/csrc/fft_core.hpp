@@ -10,9 +10,20 @@
 // with no extra exchange.  Twiddles come from a table w[j] = exp(-2 pi i j/N)
 // built on the host in extended precision, held per thread in registers.
 #pragma once
+#include <type_traits>
 #include <hip/hip_runtime.h>
 
 namespace pf {
+
+// Words of the FP32 per-grid scale (used by the passes, described in
+// pass_bodies.hpp): 64 notes 128 bytes apart, then the word holding the
+// exponent; one set of kScaleSet words for the forward map and one for the
+// transpose.
+constexpr int kScaleWords = 64;
+constexpr int kScaleStride = 32;
+constexpr int kScaleE = kScaleWords * kScaleStride;
+constexpr int kScaleSet = kScaleE + kScaleStride;
+constexpr int kScaleFree = 32;   // |e| up to this: no scaling
 
 // complex value, aligned to its full size so that loads, stores and LDS
 // accesses are single 64-bit (float) or 128-bit (double) operations
@@ -394,9 +405,16 @@ __device__ __forceinline__ void tw_expand(const cx<T> *p, cx<T> *o) {
 // stage's twiddles), NV (number of transforms).  All threads of the
 // workgroup must call this together (it contains workgroup barriers).
 // ---------------------------------------------------------------------------
-template <int N, int E, int NS, int OFF, int NV, typename T, bool ZH = false>
+// F: when not NoScale, an object whose pre() runs after the first stage's
+// butterflies, before that stage's barrier, and whose post() runs after the
+// barrier; the values read back after the exchange are multiplied by what
+// post() returns (a power of two: exact), so a scale found while the first
+// stage runs still applies before the later stages.
+struct NoScale {};
+template <int N, int E, int NS, int OFF, int NV, typename T, bool ZH = false,
+          typename F = NoScale>
 __device__ __forceinline__ void fft_stages(cx<T> (&v)[NV][E], int t, const Lds<T> (&lds)[NV],
-                                           const Twiddles<N, E, T> &tw) {
+                                           const Twiddles<N, E, T> &tw, F f = F{}) {
     constexpr int TH = N / E;                 // threads per transform
     constexpr int REM = N / NS;
     constexpr int R = REM >= E ? E : REM;     // radix of this stage
@@ -433,12 +451,22 @@ __device__ __forceinline__ void fft_stages(cx<T> (&v)[NV][E], int t, const Lds<T
         }
     }
     if constexpr (!LAST) {
+        constexpr bool SC = NS == 1 && !std::is_same<F, NoScale>::value;
+        T sc = T(1);
+        if constexpr (SC) f.pre();
         lds_barrier();
+        if constexpr (SC) sc = f.post();
         const int pt = lds_pad(t);
 #pragma unroll
         for (int a = 0; a < NV; ++a)
 #pragma unroll
             for (int e = 0; e < E; ++e) v[a][e] = lds[a].ld_split(pt, e * TH);
+        if constexpr (SC)
+            if (sc != T(1))   // uniform: a branch, not a select
+#pragma unroll
+                for (int a = 0; a < NV; ++a)
+#pragma unroll
+                    for (int e = 0; e < E; ++e) v[a][e] = scale(v[a][e], sc);
         lds_barrier();
         fft_stages<N, E, NS * R, OFF + (NS > 1 ? NB * ilog2c(R) : 0), NV, T>(v, t, lds, tw);
     }
@@ -452,6 +480,33 @@ __device__ __forceinline__ void fft_fwd(cx<T> (&v)[NV][E], int t, const Lds<T> (
     static_assert((N & (N - 1)) == 0 && N >= E && E >= 2, "sizes");
     static_assert(!ZH || E >= 4, "zero upper half needs E >= 4");
     fft_stages<N, E, 1, 0, NV, T, ZH>(v, t, lds, tw);
+}
+
+// The forward transform of one zero-padded array (upper half zero) times a
+// power of two that f gives (see fft_stages): the values are scaled after
+// the first stage's exchange.
+// The result equals the transform of the scaled input exactly as long as the
+// first stage's values (at most E/2 times the largest input) stay in range.
+template <int N, int E, typename T, typename F>
+__device__ __forceinline__ void fft_fwd_zh_scaled(cx<T> (&v)[E], int t, const Lds<T> &lds,
+                                                  const Twiddles<N, E, T> &tw, F f) {
+    static_assert((N & (N - 1)) == 0 && N >= E && E >= 4, "sizes");
+    cx<T> vv[1][E];
+    const Lds<T> l[1] = {lds};
+#pragma unroll
+    for (int e = 0; e < E; ++e) vv[0][e] = v[e];
+    if constexpr (N == E) {   // one stage: scale the input instead
+        f.pre();
+        __syncthreads();
+        const T sc = f.post();
+#pragma unroll
+        for (int e = 0; e < E; ++e) vv[0][e] = scale(vv[0][e], sc);
+        fft_stages<N, E, 1, 0, 1, T, true>(vv, t, l, tw);
+    } else {
+        fft_stages<N, E, 1, 0, 1, T, true, F>(vv, t, l, tw, f);
+    }
+#pragma unroll
+    for (int e = 0; e < E; ++e) v[e] = vv[0][e];
 }
 
 // Inverse transforms (sign +1, unnormalised) as swap(F(swap(x))), where

@@ -67,34 +67,58 @@ __device__ __forceinline__ void store_stream(cx2<T> *p, cx2<T> v) {
 // near 2^-110 would reach subnormal intermediates).  Each call therefore
 // scales the grid by a power of two, 2^-e with e = floor(log2 max|sigma|):
 //   pass A notes max|sigma| (as float bits, which order like the
-//     magnitudes) in one of 64 words g[0 .. 63] by atomic maximum;
-//   pass B reads the 64 words, scales its column by 2^-e before the
-//     transforms, stores its output still scaled and writes e to g[64]
-//     (every workgroup the same value);
-//   pass C reads e from g[64], multiplies its outputs by 2^e, and clears
-//     g[0 .. 63] for the next call (pass B is done with them).
+//     magnitudes) in one of 64 words by atomic maximum, one atomic per
+//     wave; the words sit 128 bytes apart (word w at g[32 w]), each in a
+//     cache line of its own, so the atomics of the pass spread over 64
+//     lines instead of queueing on one;
+//   pass B reads the 64 words, scales its column by 2^-e (after the first
+//     stage of the column transform, which sums at most 8 values), stores
+//     its output still scaled and writes e to g[32 * 64];
+//   pass C reads e, multiplies its outputs by 2^e, and clears the 64 words
+//     for the next call (pass B is done with them).
 // Every pass of a call runs after the previous one on the stream.  Between
 // the note and the final multiply every value is the unscaled one times
 // 2^-e, so wherever the outputs are normal numbers they are bit for bit
 // those of the unscaled computation times 2^e -- and no intermediate leaves
-// the FP32 range as long as max|sigma| N_phi stays below 2^127.  FP64 is
-// not scaled.
+// the FP32 range as long as max|sigma| N_phi stays below 2^127.  For
+// |e| <= kScaleFree the unscaled sums stay far inside the range (below
+// 2^33 L N_phi <= 2^59 before the product with the kernel spectra), so e is
+// taken as 0 there and the multiplies by 2^-e and 2^e are skipped (a
+// branch on a value uniform over the workgroup).  FP64 is not scaled.
 // ---------------------------------------------------------------------------
-constexpr int kScaleWords = 64;   // notes; g[64] holds e
+// (the layout constants kScale* are in fft_core.hpp)
+
+// The maximum of m over a whole wave (all 64 lanes active), uniform (in a
+// scalar register): row
+// shifts by 1, 2, 4 and 8 lanes (lanes before a row's start read 0, the
+// identity of the unsigned maximum) leave each row's maximum in its lane 15;
+// the row broadcasts of lanes 15 and 31 carry them on to lane 63.
+__device__ __forceinline__ unsigned wave_max_u32(unsigned m) {
+    m = max(m, (unsigned)__builtin_amdgcn_update_dpp(0, (int)m, 0x111, 0xf, 0xf, false));
+    m = max(m, (unsigned)__builtin_amdgcn_update_dpp(0, (int)m, 0x112, 0xf, 0xf, false));
+    m = max(m, (unsigned)__builtin_amdgcn_update_dpp(0, (int)m, 0x114, 0xf, 0xf, false));
+    m = max(m, (unsigned)__builtin_amdgcn_update_dpp(0, (int)m, 0x118, 0xf, 0xf, false));
+    m = max(m, (unsigned)__builtin_amdgcn_update_dpp(0, (int)m, 0x142, 0xa, 0xf, false));
+    m = max(m, (unsigned)__builtin_amdgcn_update_dpp(0, (int)m, 0x143, 0xc, 0xf, false));
+    return (unsigned)__builtin_amdgcn_readlane((int)m, 63);
+}
 
 template <typename T, int E, int C>
 __device__ __forceinline__ void scale_note(unsigned *__restrict__ g, const cx<T> (&v)[C][E]) {
     if constexpr (sizeof(T) == 4) {
-        if (!g) return;
         unsigned m = 0u;
 #pragma unroll
         for (int c = 0; c < C; ++c)
 #pragma unroll
             for (int e = 0; e < E; ++e)
                 m = max(m, max(__float_as_uint(fabsf(v[c][e].x)), __float_as_uint(fabsf(v[c][e].y))));
-        for (int off = 32; off > 0; off >>= 1) m = max(m, (unsigned)__shfl_xor((int)m, off));
-        if ((threadIdx.x & 63) == 0)
-            atomicMax(&g[(blockIdx.x * 8 + (threadIdx.x >> 6)) & (kScaleWords - 1)], m);
+        unsigned *const w = &g[((blockIdx.x * 8 + (threadIdx.x >> 6)) & (kScaleWords - 1)) * kScaleStride];
+        if ((threadIdx.x | 63) < blockDim.x) {   // a whole wave: one atomic
+            m = wave_max_u32(m);
+            if ((threadIdx.x & 63) == 0) atomicMax(w, m);
+        } else {   // the part-filled last wave of a small workgroup: every lane
+            atomicMax(w, m);
+        }
     }
 }
 
@@ -108,34 +132,72 @@ __device__ __forceinline__ GridScale<T> scale_of(int ex) {
     return {__uint_as_float((unsigned)(127 - ex) << 23), __uint_as_float((unsigned)(127 + ex) << 23)};
 }
 
-// pass B: e from the notes (clamped to [-100, 100]), written to g[64] by the
-// first thread of the workgroup; ones without scaling
+// pass B: the first wave loads the 64 notes (lane i reads note i; issued
+// after the column's loads and before the spectrum prefetch) and reduces
+// them while the first stage of the column transform runs; e (clamped to
+// [-100, 100], 0 within [-kScaleFree, kScaleFree]) reaches the other waves
+// through LDS across that stage's barrier, and the unit-0 workgroup writes
+// it to g[kScaleE] for pass C.
+// The column passes apply 2^-e after the first stage of their forward
+// transforms (fft_fwd_zh_scaled).  FP32 passes always get the words; FP64
+// passes are not scaled (ones).
 template <typename T>
-__device__ __forceinline__ GridScale<T> scale_take(unsigned *__restrict__ g) {
-    if constexpr (sizeof(T) == 4) {
-        if (g) {
-            unsigned m = g[threadIdx.x & 63];
-            for (int off = 32; off > 0; off >>= 1) m = max(m, (unsigned)__shfl_xor((int)m, off));
-            int ex = (int)((m >> 23) & 0xffu) - 127;
-            ex = min(max(ex, -100), 100);
-            if (threadIdx.x == 0) g[kScaleWords] = (unsigned)ex;
-            return scale_of<T>(ex);
+__device__ __forceinline__ unsigned scale_load(const unsigned *__restrict__ g) {
+    if constexpr (sizeof(T) == 4)
+        if (threadIdx.x < 64) return g[threadIdx.x * kScaleStride];
+    return 0u;
+}
+__device__ __forceinline__ int &scale_slot() {
+    __shared__ int s_ex;
+    return s_ex;
+}
+// The scale step of the first column transform (the F of fft_stages): pre()
+// in the first wave reduces the notes and publishes e, post() reads it.
+template <typename T>
+struct ScaleFind {
+    unsigned *g;
+    unsigned note;
+    int unit;
+    GridScale<T> *res;
+    __device__ __forceinline__ void pre() const {
+        if constexpr (sizeof(T) == 4) {
+            if (threadIdx.x < 64) {
+                const unsigned m = wave_max_u32(note);
+                int ex = min(max((int)((m >> 23) & 0xffu) - 127, -100), 100);
+                if (ex >= -kScaleFree && ex <= kScaleFree) ex = 0;
+                if (threadIdx.x == 0) {
+                    scale_slot() = ex;
+                    if (unit == 0) g[kScaleE] = (unsigned)ex;
+                }
+            }
         }
     }
-    return {T(1), T(1)};
-}
+    __device__ __forceinline__ T post() const {
+        if constexpr (sizeof(T) == 4) {
+            *res = scale_of<T>(__builtin_amdgcn_readfirstlane(scale_slot()));
+            return res->dn;
+        }
+        *res = GridScale<T>{T(1), T(1)};
+        return T(1);
+    }
+};
+// A scale already known (the second column transform of the adjoint).
+template <typename T>
+struct ScaleKnown {
+    T s;
+    __device__ __forceinline__ void pre() const {}
+    __device__ __forceinline__ T post() const { return s; }
+};
 
 // pass C: e as pass B wrote it; the unit-0 workgroup of the grid clears
 // the notes (any number of threads)
 template <typename T>
 __device__ __forceinline__ T scale_finish(unsigned *__restrict__ g, int unit) {
     if constexpr (sizeof(T) == 4) {
-        if (g) {
-            const int ex = (int)g[kScaleWords];
-            if (unit == 0)
-                for (int i = threadIdx.x; i < kScaleWords; i += blockDim.x) g[i] = 0u;
-            return scale_of<T>(ex).up;
-        }
+        const int ex = (int)g[kScaleE];
+        if (unit == 0)
+            for (int i = threadIdx.x; i < kScaleWords; i += blockDim.x) g[i * kScaleStride] = 0u;
+        return scale_of<T>(ex).up;
     }
     return T(1);
 }
@@ -290,12 +352,17 @@ __device__ __forceinline__ void body_rows_c2r(int unit, int G, cx<T> *__restrict
         }
     fft_inv<M, E, C, T>(v, t, lds, tw);
     const T up = scale_finish<T>(gscale, unit);
+    if (up != T(1))
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+#pragma unroll
+            for (int e = 0; e < E; ++e) v[c][e] = scale(v[c][e], up);
     if (active) {
 #pragma unroll
         for (int c = 0; c < C; ++c) {
             cx<T> *yz = reinterpret_cast<cx<T> *>((c == 0 ? out0 : out1) + (size_t)i * N);
 #pragma unroll
-            for (int e = 0; e < E; ++e) store_stream(&yz[t + e * TH], scale(v[c][e], up));
+            for (int e = 0; e < E; ++e) store_stream(&yz[t + e * TH], v[c][e]);
         }
     }
 }
@@ -586,6 +653,21 @@ __device__ __forceinline__ void accum_w(cx<T> (&w)[4], cx<T> r, cx<T> rne, int e
     w[3] = mul_root_add<E>(w[3], q, e);
 }
 
+// The forward column transform of a zero-padded column, times the grid
+// scale that f gives: in FP32 applied after the first stage, in FP64 not at
+// all (f still runs, and gives one).
+template <int L, int E, typename T, typename F>
+__device__ __forceinline__ void fft_col_fwd(cx<T> (&v)[E], int t, const Lds<T> &lds,
+                                            const Twiddles<L, E, T> &tw, F f) {
+    if constexpr (sizeof(T) == 4) {
+        fft_fwd_zh_scaled<L, E, T>(v, t, lds, tw, f);
+    } else {
+        f.pre();
+        (void)f.post();
+        fft_fwd<L, E, T, true>(v, t, lds, tw);
+    }
+}
+
 // The column pass runs the two force channels one after the other: the
 // radial channel's multiply-accumulate with the radial pairs, then, while
 // its inverse transform runs, the azimuthal pairs arrive (in the LDS region
@@ -616,6 +698,9 @@ __device__ __forceinline__ void body_cols_fwd(int unit, int G, cx<T> *__restrict
     const cx2<T> *const srad = spec;                        // (E'_r, Q_r) per column
     const cx2<T> *const sazi = spec + (size_t)H * ldspec;   // (E'_p, Q_p) per column
 
+    // The scale note first: loads complete in order, so the first wave's
+    // wait for it (after the first transform stage) waits for no later load.
+    const unsigned note = scale_load<T>(gscale);
     // The column.  Only the first E/2 strided points of a thread can be data
     // rows (L >= 2 n_r); clamped, always valid addresses so the loads issue
     // back to back.
@@ -631,20 +716,19 @@ __device__ __forceinline__ void body_cols_fwd(int unit, int G, cx<T> *__restrict
     const cx<T> wt = twL[t], wnt = twL[(int)(((unsigned)n_r * (unsigned)t) & (unsigned)(L - 1))];
     Twiddles<L, E, T> tw;
     tw.load(t, twL, 1);
-    // before the prefetch: the wait for this load must not wait for it
-    const GridScale<T> sc = scale_take<T>(gscale);
     // issued after the column's loads, which the transform waits for
     if constexpr (PF) prefetch_spectra<T, L, E>(unit, G, H, ldspec, srad, spl);
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         const int i = t + e * TH;
-        v[e] = (e >= E / 2 || !valid || i >= n_r) ? cx<T>{T(0), T(0)} : scale(v[e], sc.dn);
+        if (e >= E / 2 || !valid || i >= n_r) v[e] = cx<T>{T(0), T(0)};
     }
+    GridScale<T> sc;
+    fft_col_fwd<L, E, T>(v, t, lds, tw, ScaleFind<T>{gscale, note, unit, &sc});
     x0 = scale(x0, sc.dn);
     x1 = scale(x1, sc.dn);
     xm2 = scale(xm2, sc.dn);
     xm1 = scale(xm1, sc.dn);
-    fft_fwd<L, E, T, true>(v, t, lds, tw);
 
     // FP32 (SPLIT): the radial channel's sweep and inverse transform, then
     // the azimuthal channel's (its spectrum pairs arriving meanwhile).  FP64:
@@ -857,6 +941,9 @@ __device__ __forceinline__ void body_cols_adj(int unit, int G, cx<T> *__restrict
     const cx2<T> *const srad = spec;
     const cx2<T> *const sazi = spec + (size_t)H * ldspec;
 
+    // The scale note first: loads complete in order, so the first wave's
+    // wait for it (after the first transform stage) waits for no later load.
+    const unsigned note = scale_load<T>(gscale);
     // clamped, always valid addresses so the loads issue back to back; only
     // the first E/2 points of a thread can be data rows (L >= 2 n_r)
     cx<T> va[2][E];   // va[0]: V_r, va[1]: V_p
@@ -869,17 +956,17 @@ __device__ __forceinline__ void body_cols_adj(int unit, int G, cx<T> *__restrict
     }
     Twiddles<L, E, T> tw;
     tw.load(t, twL, 1);
-    // before the prefetch: the wait for this load must not wait for it
-    const GridScale<T> sc = scale_take<T>(gscale);
     // issued after the column's loads, which the transforms wait for
     if constexpr (PF) prefetch_spectra<T, L, E>(unit, G, H, ldspec, srad, spl);
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         const int i = t + e * TH;
-        const bool z = e >= E / 2 || !valid || i >= n_r;
-        va[0][e] = z ? cx<T>{T(0), T(0)} : scale(va[0][e], sc.dn);
-        va[1][e] = z ? cx<T>{T(0), T(0)} : scale(va[1][e], sc.dn);
+        if (e >= E / 2 || !valid || i >= n_r) {
+            va[0][e] = cx<T>{T(0), T(0)};
+            va[1][e] = cx<T>{T(0), T(0)};
+        }
     }
+    GridScale<T> sc;
     // FP32 (SPLIT): V_r is transformed, meets the radial pairs, then V_p is
     // transformed while the azimuthal pairs arrive in LDS.  FP64: both
     // channels are transformed while the radial pairs arrive, then one
@@ -898,7 +985,7 @@ __device__ __forceinline__ void body_cols_adj(int unit, int G, cx<T> *__restrict
     // turned into the thread's share with its phasors afterwards.
     cx<T> w[4] = {{T(0), T(0)}, {T(0), T(0)}, {T(0), T(0)}, {T(0), T(0)}};
     cx<T> xe[E];
-    fft_fwd<L, E, T, true>(va[0], t, lds, tw);
+    fft_col_fwd<L, E, T>(va[0], t, lds, tw, ScaleFind<T>{gscale, note, unit, &sc});
     if constexpr (SPLIT) {
         // radial half: xe = conj(E'_r) V_r, r = conj(Q_r) V_r
         if constexpr (PF) prefetch_wait();
@@ -937,14 +1024,14 @@ __device__ __forceinline__ void body_cols_adj(int unit, int G, cx<T> *__restrict
             lds_barrier();
             prefetch_spectra<T, L, E>(unit, G, H, ldspec, sazi, spl);
         }
-        fft_fwd<L, E, T, true>(va[1], t, lds, tw);
+        fft_col_fwd<L, E, T>(va[1], t, lds, tw, ScaleKnown<T>{sc.dn});
         // azimuthal half: xe += conj(E'_p) V_p, r += conj(Q_p) V_p
         if constexpr (PF) prefetch_wait();
         mac_adj<T, L, E, true, PF, true>(xe, r, va[1], sl, gp, t, is0);
 #pragma unroll
         for (int e = 0; e < E; ++e) accum_w<T, E>(w, r[e], root_ne<T, L, E>(twL, n_r, e), e);
     } else {
-        fft_fwd<L, E, T, true>(va[1], t, lds, tw);
+        fft_col_fwd<L, E, T>(va[1], t, lds, tw, ScaleKnown<T>{sc.dn});
         if (packed) {   // column 0 reads the conjugate mirror points from LDS
 #pragma unroll
             for (int e = 0; e < E; ++e) lds.st_split(lds_pad(t), e * TH, va[0][e]);

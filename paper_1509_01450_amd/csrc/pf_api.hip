@@ -172,7 +172,7 @@ int backward_t(const Plan &p, const T *gr, const T *gp, T *gs, hipStream_t st) {
     using C = pf::cx<T>;
     C *V = (C *)p.ws;                        // (Vr, Vp) pairs
     C *D = V + 2 * (size_t)p.n_r * p.H;
-    unsigned *g = p.gscale ? p.gscale + 128 : nullptr;   // the transpose's scale words
+    unsigned *g = p.gscale ? p.gscale + pf::kScaleSet : nullptr;   // the transpose's words
     int rc = pf::launch_rows_r2c<T>(p, gr, gp, p.n_r, V, (const C *)p.twN, p.sched.rows2, st, g);
     if (rc) return rc;
     rc = pf::launch_cols_adj<T>(p, V, D, (const C *)p.spec, (const C *)p.twL, p.sched.cols_adj,
@@ -190,7 +190,7 @@ int timed_t(const Plan &p, bool bwd, const void *in0, const void *in1, void *out
     C *W1 = W0 + (size_t)p.n_in * p.H;      // forward: S = W0, Z = W1
     C *W2 = W0 + 2 * (size_t)p.n_r * p.H;   // transpose: V = W0, D = W2
     int rc = PF_OK;
-    unsigned *g = p.gscale ? p.gscale + (bwd ? 128 : 0) : nullptr;
+    unsigned *g = p.gscale ? p.gscale + (bwd ? pf::kScaleSet : 0) : nullptr;
     PF_HIP(hipEventRecord(ev[0], st));
     for (int k = 0; k < reps && !rc; ++k)
         rc = pf::launch_rows_r2c<T>(p, (const T *)in0, bwd ? (const T *)in1 : nullptr, p.n_in,
@@ -491,17 +491,17 @@ int pf_kernels_build(pf_plan h, const pf_build_opts *opts, void *stream) {
     if (!rc) {
         // forward: S (n_in rows) and the (Zr, Zp) pairs (n_r rows); transpose:
         // the (Vr, Vp) pairs and D (n_r rows each)
-        // and after them the FP32 scale words (128 for the forward map, 128
-        // for the transpose; the notes are zero between calls)
+        // and after them the FP32 scale words (one set for the forward map,
+        // one for the transpose; the notes are zero between calls)
         const size_t rows = std::max((size_t)p.n_in + 2 * (size_t)p.n_r, (size_t)3 * p.n_r);
         const size_t wsb = (rows * p.H * (f64 ? 16 : 8) + 255) / 256 * 256;
-        hipError_t e = hipMalloc(&p.ws, wsb + 256 * sizeof(unsigned));
+        hipError_t e = hipMalloc(&p.ws, wsb + 2 * pf::kScaleSet * sizeof(unsigned));
         if (e != hipSuccess) {
             pf::set_error("workspace allocation failed: %s", hipGetErrorString(e));
             rc = PF_ENOMEM;
         } else if (!f64) {
             p.gscale = (unsigned *)((unsigned char *)p.ws + wsb);
-            e = hipMemsetAsync(p.gscale, 0, 256 * sizeof(unsigned), st);
+            e = hipMemsetAsync(p.gscale, 0, 2 * pf::kScaleSet * sizeof(unsigned), st);
             if (e != hipSuccess) {
                 pf::set_error("hipMemsetAsync: %s", hipGetErrorString(e));
                 rc = PF_EHIP;

@@ -75,8 +75,8 @@ struct Plan {
                               // (Vr, Vp) pairs, then D)
     double *tables = nullptr; // [6][L][n_phi] FP64 (only with keep_tables)
     unsigned *gscale = nullptr; // FP32 scale words after the workspace: the
-                                // forward map's at [0, 65), the transpose's
-                                // at [128, 193) (pass_bodies.hpp)
+                                // forward map's set, then the transpose's
+                                // (kScaleSet words each)
     void *wspec = nullptr;    // wedge spectra [2][n_r][H] pairs, plan precision
     void *wws = nullptr;      // wedge workspace: slope row, then its spectra
     Schedule sched;

@@ -385,6 +385,10 @@ struct Disp {
 template <typename T>
 int launch_rows_r2c(const Plan &p, const T *in0, const T *in1, int n_rows, cx<T> *out,
                     const cx<T> *twN, Shape s, hipStream_t st, unsigned *g) {
+    if (sizeof(T) == 4 && !g) {
+        set_error("FP32 passes need the plan's scale words");
+        return PF_EINVAL;
+    }
     if (!valid_shape_rows(p.M, s, sizeof(T) == 8)) {
         set_error("invalid row shape E=%d G=%d for M=%d", s.E, s.G, p.M);
         return PF_EINVAL;
@@ -395,6 +399,10 @@ int launch_rows_r2c(const Plan &p, const T *in0, const T *in1, int n_rows, cx<T>
 template <typename T>
 int launch_rows_c2r(const Plan &p, const cx<T> *in, int n_rows, T *out0, T *out1,
                     const cx<T> *twN, Shape s, hipStream_t st, unsigned *g) {
+    if (sizeof(T) == 4 && !g) {
+        set_error("FP32 passes need the plan's scale words");
+        return PF_EINVAL;
+    }
     if (!valid_shape_rows(p.M, s, sizeof(T) == 8)) {
         set_error("invalid row shape E=%d G=%d for M=%d", s.E, s.G, p.M);
         return PF_EINVAL;
@@ -405,6 +413,10 @@ int launch_rows_c2r(const Plan &p, const cx<T> *in, int n_rows, T *out0, T *out1
 template <typename T>
 int launch_cols_fwd(const Plan &p, const cx<T> *S, cx<T> *Z, const cx<T> *spec,
                     const cx<T> *twL, Shape s, hipStream_t st, unsigned *g) {
+    if (sizeof(T) == 4 && !g) {
+        set_error("FP32 passes need the plan's scale words");
+        return PF_EINVAL;
+    }
     if (!valid_shape_cols(p.L, s, sizeof(T) == 8)) {
         set_error("invalid column shape E=%d G=%d for L=%d", s.E, s.G, p.L);
         return PF_EINVAL;
@@ -415,6 +427,10 @@ int launch_cols_fwd(const Plan &p, const cx<T> *S, cx<T> *Z, const cx<T> *spec,
 template <typename T>
 int launch_cols_adj(const Plan &p, const cx<T> *V, cx<T> *D, const cx<T> *spec,
                     const cx<T> *twL, Shape s, hipStream_t st, unsigned *g) {
+    if (sizeof(T) == 4 && !g) {
+        set_error("FP32 passes need the plan's scale words");
+        return PF_EINVAL;
+    }
     if (!valid_shape_cols(p.L, s, sizeof(T) == 8)) {
         set_error("invalid column shape E=%d G=%d for L=%d", s.E, s.G, p.L);
         return PF_EINVAL;

@@ -959,8 +959,9 @@ __global__ void k_wedge_add(cx2<T> *__restrict__ Z, const cx2<T> *__restrict__ w
     cx2<T> x = w[k];
     if (g) {
         // FP32 calls: Z holds the column pass's output scaled by 2^-e (e in
-        // g[64]); the wedge terms join it at the same scale
-        const int ex = (int)g[64];
+        // the scale words, after the 64 notes); the wedge terms join it at
+        // the same scale
+        const int ex = (int)g[kScaleE];
         const T s = (T)__uint_as_float((unsigned)(127 - ex) << 23);
         x = cx2<T>{scale(x.a, s), scale(x.b, s)};
     }
@@ -1025,8 +1026,10 @@ int launch_wedge_terms(const Plan &p, const T *sigma_src, const T *sigma_w, cx<T
     hipLaunchKernelGGL(k_wedge_slope<T>, dim3((p.n_phi + 255) / 256), dim3(256), 0, st,
                        sigma_src, sigma_w, p.n_phi, T(1.0 / (rc0 - rh)), slope);
     PF_HIP(hipGetLastError());
+    // (the forward's scale words: the note lands after pass B has read the
+    // notes, and pass C clears it)
     int rc = launch_rows_r2c<T>(p, sigma_w, slope, 1, wrow, (const cx<T> *)p.twN, p.sched.rows2,
-                                st);
+                                st, p.gscale);
     if (rc) return rc;
     const long n = (long)p.n_r * p.H;
     hipLaunchKernelGGL(k_wedge_add<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st,

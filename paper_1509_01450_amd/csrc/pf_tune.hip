@@ -182,10 +182,10 @@ int tune_t(Plan &p, hipStream_t st) {
     for (int i = 0; i < 100; ++i) {
         int rc = launch_rows_c2r<T>(p, Z, p.n_r, x + (size_t)p.n_r * p.n_phi,
                                     x + 2 * (size_t)p.n_r * p.n_phi, (const C *)p.twN,
-                                    p.sched.rows2, st);
+                                    p.sched.rows2, st, p.gscale);
         if (!rc)
             rc = launch_cols_fwd<T>(p, S, Z, (const C *)p.spec, (const C *)p.twL, p.sched.cols,
-                                    st);
+                                    st, p.gscale);
         if (rc) return rc;
     }
     PF_HIP(hipStreamSynchronize(st));
@@ -200,7 +200,7 @@ int tune_t(Plan &p, hipStream_t st) {
                 rc = time_ms(
                     [&]() {
                         return launch_rows_r2c<T>(p, x, nullptr, p.n_r, S, (const C *)p.twN, s,
-                                                  st);
+                                                  st, p.gscale);
                     },
                     st, ts.e0, ts.e1, &t);
                 if (rc) return rc;
@@ -212,7 +212,7 @@ int tune_t(Plan &p, hipStream_t st) {
                     [&]() {
                         return launch_rows_c2r<T>(p, Z, p.n_r, x + (size_t)p.n_r * p.n_phi,
                                                   x + 2 * (size_t)p.n_r * p.n_phi,
-                                                  (const C *)p.twN, s, st);
+                                                  (const C *)p.twN, s, st, p.gscale);
                     },
                     st, ts.e0, ts.e1, &t);
                 if (rc) return rc;
@@ -233,9 +233,9 @@ int tune_t(Plan &p, hipStream_t st) {
                     rc = time_ms(
                         [&]() {
                             return adj ? launch_cols_adj<T>(p, S, D, (const C *)p.spec,
-                                                            (const C *)p.twL, s, st)
+                                                            (const C *)p.twL, s, st, p.gscale)
                                        : launch_cols_fwd<T>(p, S, Z, (const C *)p.spec,
-                                                            (const C *)p.twL, s, st);
+                                                            (const C *)p.twL, s, st, p.gscale);
                         },
                         st, ts.e0, ts.e1, &t);
                     if (rc) return rc;
@@ -245,6 +245,9 @@ int tune_t(Plan &p, hipStream_t st) {
                     }
                 }
     }
+    // the timing runs left notes in the scale words: clear them for the
+    // first call
+    if (p.gscale) PF_HIP(hipMemsetAsync(p.gscale, 0, 2 * kScaleSet * sizeof(unsigned), st));
     PF_HIP(hipStreamSynchronize(st));
     p.sched.rows = best_r;
     p.sched.rows2 = best_r2;

@@ -82,6 +82,17 @@ def test_unbuilt_plan_and_null_arguments_are_refused():
         assert lib.pf_forces(h, None, 8, 8, None) == pf.PF_EINVAL
         assert lib.pf_forces(None, 8, 8, 8, None) == pf.PF_EINVAL
         assert lib.pf_forces_batched(0, None, None, None, None, None) == pf.PF_EINVAL
+        # the no-allocation form: 1 <= n <= 256, checked before the plans
+        arr257 = (ctypes.c_void_p * 257)(*([8] * 257))
+        hs257 = (ctypes.c_void_p * 257)(*([h] * 257))
+        for n in (0, -1, 257):
+            assert lib.pf_forces_batched_noalloc(n, hs257, arr257, arr257, arr257,
+                                                 None) == pf.PF_EINVAL
+        assert "256" in pf.pf_last_error() or "bad batch" in pf.pf_last_error()
+        assert lib.pf_forces_batched_noalloc(1, None, None, None, None, None) == pf.PF_EINVAL
+        # within bounds, an unbuilt plan is a state error
+        assert lib.pf_forces_batched_noalloc(1, hs257, arr257, arr257, arr257,
+                                             None) == pf.PF_ESTATE
         # bad build options are refused before the device is touched
         o = pf.pf_build_opts_default()
         o.n_tpz = 0

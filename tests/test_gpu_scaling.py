@@ -1,6 +1,7 @@
 """FP32 scaling per grid: the FP32 path scales each call's grid by a power of
 two chosen from max|sigma| (pass A notes it, pass B scales its columns by
-2^-e before the transforms and by 2^e after them, pass C clears the note).
+2^-e after the first stage of their transforms, pass C multiplies by 2^e and
+clears the notes); within |e| <= 32 the scale is one.
 
 At 512 x 1024 the column transforms sum L N_phi = 2^20 values, so a density
 of 2^110 would reach 2^130 in them, beyond the FP32 range, without the
@@ -156,3 +157,40 @@ def test_scaled_disk_in_a_batch():
         assert torch.isfinite(fr).all() and torch.equal(fr, r) and torch.equal(fp, q), k
     for p in plans:
         p.close()
+
+
+@pytest.mark.parametrize("cell", [(0, 5), (N_R // 2 + 3, 700), (N_R - 1, N_PHI - 1)])
+def test_single_spike_sets_the_scale(case, cell):
+    """A density of order one with one cell at 2^110: only the note of the
+    wave holding that cell sees 2^110, so the scale is right only if the
+    maximum over every note reaches pass B (else the column transforms
+    overflow).  FP32 forces agree with the FP64 path on the whole grid."""
+    sig = case[0].copy()
+    sig[cell] = 2.0 ** 110
+    p32 = pf.Plan(N_R, N_PHI, R_MIN, R_MAX, dtype="f32")
+    p64 = pf.Plan(N_R, N_PHI, R_MIN, R_MAX, dtype="f64")
+    try:
+        fr, fp = p32.forces(torch.tensor(sig, dtype=torch.float32, device="cuda"))
+        gr, gp = p64.forces(torch.tensor(sig, dtype=torch.float64, device="cuda"))
+        torch.cuda.synchronize()
+        assert torch.isfinite(fr).all() and torch.isfinite(fp).all(), cell
+        e = (_rel(fr.double().cpu().numpy(), gr.cpu().numpy()),
+             _rel(fp.double().cpu().numpy(), gp.cpu().numpy()))
+        _say("spike 2^110 at %s: FP32 vs FP64 rel-L2 F_r %.2e F_phi %.2e" % (cell, e[0], e[1]))
+        assert max(e) < 1e-5
+        # the transpose with one cotangent cell at 2^110
+        a = np.zeros_like(sig)
+        a[cell] = 2.0 ** 110
+        b = case[5].copy()
+        d32 = p32.backward(torch.tensor(a, dtype=torch.float32, device="cuda"),
+                           torch.tensor(b, dtype=torch.float32, device="cuda"))
+        d64 = p64.backward(torch.tensor(a, dtype=torch.float64, device="cuda"),
+                           torch.tensor(b, dtype=torch.float64, device="cuda"))
+        torch.cuda.synchronize()
+        assert torch.isfinite(d32).all(), cell
+        e = _rel(d32.double().cpu().numpy(), d64.cpu().numpy())
+        _say("cotangent spike 2^110 at %s: FP32 vs FP64 rel-L2 %.2e" % (cell, e))
+        assert e < 1e-5
+    finally:
+        p32.close()
+        p64.close()
