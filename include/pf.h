@@ -108,7 +108,17 @@ enum pf_method {
  *   method       PF_METHOD_SIM, PF_METHOD_PARTICLE or PF_METHOD_PARTICLE_PLUS
  *                (table_mode and n_tpz apply to SIM only; self_mode to SIM
  *                and PARTICLE_PLUS).  The forward and transpose calls are
- *                the same for every method.                              */
+ *                the same for every method.
+ *   slope_order  how the slopes delta^r, delta^phi of Eq. 25 (the
+ *                derivatives of sigma at the cell centres) are taken from
+ *                the cell values: 2 = central differences (one-sided on the
+ *                first and last rows); 4 = five-point central differences
+ *                (radially in u = ln r) where all five points exist, the
+ *                order-2 ones on the rows next to the ends.  The paper does
+ *                not fix the difference; Table 1's SIM orders over
+ *                N_d = 64 ... 1024 come out with order 4 (a reading).
+ *                Order 4 takes the general column kernels (slower) and is
+ *                refused for patch plans and batched calls.             */
 typedef struct {
     int dtype;
     int n_tpz;
@@ -117,10 +127,12 @@ typedef struct {
     int table_mode;
     int self_mode;
     int method;
+    int slope_order;
 } pf_build_opts;
 
 /* Defaults: PF_F32, n_tpz = 19, cover_per = 10, keep_tables = 0,
- * PF_TABLE_SIM, PF_SELF_CARTESIAN, PF_METHOD_SIM (the paper's method). */
+ * PF_TABLE_SIM, PF_SELF_CARTESIAN, PF_METHOD_SIM (the paper's method),
+ * slope_order = 2. */
 void pf_build_opts_default(pf_build_opts *opts);
 
 /* Create a plan for an n_r x n_phi grid on [r_min, r_max] (Sec. 3.2.1).

@@ -54,9 +54,13 @@ def _load():
     lib.or_table_entry.argtypes = [i, i, d, d, i, i, i, i, P, P]
     lib.or_tables.argtypes = [i, i, d, d, i, i, P, P]
     lib.or_channels.argtypes = [i, i, P, d, P, P, P]
+    lib.or_channels_o.argtypes = [i, i, P, d, i, P, P, P]
     lib.or_forward.argtypes = [i, i, d, d, P, P, P, i64, P, P]
+    lib.or_forward_o.argtypes = [i, i, d, d, i, P, P, P, i64, P, P]
     lib.or_adjoint.argtypes = [i, i, d, d, P, P, P, P, i64, P]
+    lib.or_adjoint_o.argtypes = [i, i, d, d, i, P, P, P, P, i64, P]
     lib.or_forward_particle.argtypes = [i, i, d, d, i, P, P, P, i64, P, P]
+    lib.or_forward_particle_o.argtypes = [i, i, d, d, i, i, P, P, P, i64, P, P]
     lib.or_patch_tables.argtypes = [i, i, i, i, d, d, i, i, P, P]
     lib.or_wedge_tables.argtypes = [i, i, d, d, i, i, P]
     lib.or_patch_forward.argtypes = [i, i, i, i, d, d, P, P, P, P, P, i64, P, P]
@@ -66,7 +70,8 @@ def _load():
     lib.or_cart_forward.argtypes = [i, i, d, d, P, P, P, i64, P, P]
     for f in ("or_geometry", "or_gauss_legendre", "or_selfcell_cover", "or_selfcell_pv",
               "or_table_entry", "or_tables", "or_channels", "or_forward",
-              "or_adjoint", "or_forward_particle", "or_patch_tables", "or_wedge_tables",
+              "or_adjoint", "or_forward_particle", "or_channels_o", "or_forward_o",
+              "or_adjoint_o", "or_forward_particle_o", "or_patch_tables", "or_wedge_tables",
               "or_patch_forward", "or_patch_particle", "or_cart_tables", "or_cart_slopes",
               "or_cart_forward", "or_num_threads"):
         getattr(lib, f).restype = i
@@ -194,20 +199,25 @@ def tables(grid: Grid, n_tpz: int = 19, cover_per: int = 10, self_k=None,
     return T
 
 
-def channels(grid: Grid, sigma):
-    """Radial and azimuthal slopes of Eq. 25 by central differences
-    (one-sided on the first and last rows)."""
+def channels(grid: Grid, sigma, slope_order: int = 2):
+    """Radial and azimuthal slopes of Eq. 25 (delta^r = d sigma / dr,
+    delta^phi = d sigma / dphi at the cell centres) from the cell values.
+    slope_order 2: central differences, one-sided on the first and last rows.
+    slope_order 4: five-point central differences (in u = ln r radially)
+    where the five points exist, the order-2 ones on the rows next to the
+    ends."""
     s = _f64(sigma)
     dr = np.empty_like(s)
     dp = np.empty_like(s)
-    if _load().or_channels(grid.n_r, grid.n_phi, _p(grid.r_centres),
-                           grid.dphi, _p(s), _p(dr), _p(dp)):
-        raise ValueError("bad grid")
+    if _load().or_channels_o(grid.n_r, grid.n_phi, _p(grid.r_centres),
+                             grid.dphi, int(slope_order), _p(s), _p(dr), _p(dp)):
+        raise ValueError("bad grid or slope order")
     return dr, dp
 
 
-def forward(grid: Grid, T, sigma, dest=None):
-    """F_r, F_phi by the plain double sums of Eq. 27-29 and A19-A21.
+def forward(grid: Grid, T, sigma, dest=None, slope_order: int = 2):
+    """F_r, F_phi by the plain double sums of Eq. 27-29 and A19-A21, with
+    the slopes of :func:`channels` of the given order.
 
     ``dest``: optional flat destination indices i * N_phi + j; returns the
     forces at those cells (1-D) or on the whole grid (2-D)."""
@@ -223,15 +233,15 @@ def forward(grid: Grid, T, sigma, dest=None):
         nd = d.size
         fr = np.empty(nd)
         fp = np.empty(nd)
-    rc = _load().or_forward(grid.n_r, grid.n_phi, grid.r_min, grid.r_max,
-                            _p(T), _p(s), _p(d), nd, _p(fr), _p(fp))
+    rc = _load().or_forward_o(grid.n_r, grid.n_phi, grid.r_min, grid.r_max, int(slope_order),
+                              _p(T), _p(s), _p(d), nd, _p(fr), _p(fp))
     if rc:
         raise RuntimeError("or_forward failed (%d)" % rc)
     return fr, fp
 
 
 def forward_particle(grid: Grid, sigma, plus: bool = False, self_k=None, dest=None,
-                     self_mode: str = "cartesian", cover_per: int = 10):
+                     self_mode: str = "cartesian", cover_per: int = 10, slope_order: int = 2):
     """F_r, F_phi of the particle method (plus=False, Eq. 35-36 without the
     correction) or the modified particle method (plus=True, Eq. 34-37): point
     masses sigma r dr dphi at the cell centres, no self force, plus the
@@ -253,16 +263,18 @@ def forward_particle(grid: Grid, sigma, plus: bool = False, self_k=None, dest=No
         nd = d.size
         fr = np.empty(nd)
         fp = np.empty(nd)
-    rc = _load().or_forward_particle(grid.n_r, grid.n_phi, grid.r_min, grid.r_max, int(bool(plus)),
-                                     _p(sk), _p(s), _p(d), nd, _p(fr), _p(fp))
+    rc = _load().or_forward_particle_o(grid.n_r, grid.n_phi, grid.r_min, grid.r_max,
+                                       int(bool(plus)), int(slope_order), _p(sk), _p(s), _p(d),
+                                       nd, _p(fr), _p(fp))
     if rc:
         raise RuntimeError("or_forward_particle failed (%d)" % rc)
     return fr, fp
 
 
-def adjoint(grid: Grid, T, v_r, v_phi, src=None):
-    """Transpose of :func:`forward` applied to cotangents (v_r, v_phi), as a
-    plain double sum, at flat source indices ``src`` (or every cell)."""
+def adjoint(grid: Grid, T, v_r, v_phi, src=None, slope_order: int = 2):
+    """Transpose of :func:`forward` (same slope order) applied to cotangents
+    (v_r, v_phi), as a plain double sum, at flat source indices ``src`` (or
+    every cell)."""
     vr, vp, T = _f64(v_r), _f64(v_phi), _f64(T)
     assert vr.shape == grid.shape and vp.shape == grid.shape
     if src is None:
@@ -272,8 +284,8 @@ def adjoint(grid: Grid, T, v_r, v_phi, src=None):
         s = np.ascontiguousarray(src, dtype=np.int64)
         ns = s.size
         g = np.empty(ns)
-    rc = _load().or_adjoint(grid.n_r, grid.n_phi, grid.r_min, grid.r_max,
-                            _p(T), _p(vr), _p(vp), _p(s), ns, _p(g))
+    rc = _load().or_adjoint_o(grid.n_r, grid.n_phi, grid.r_min, grid.r_max, int(slope_order),
+                              _p(T), _p(vr), _p(vp), _p(s), ns, _p(g))
     if rc:
         raise RuntimeError("or_adjoint failed (%d)" % rc)
     return g

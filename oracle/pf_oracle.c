@@ -21,7 +21,8 @@
  *     the same definitions, the azimuthal integrals by adaptive quadrature
  *     (table mode 1) and the self cell as the exact (principal-value)
  *     integrals in local polar coordinates;
- *   - the cell density and slopes (Eq. 25, central differences);
+ *   - the cell density and slopes (Eq. 25): central differences of order 2
+ *     or, as an option, of order 4 where the five points exist;
  *   - the forces as the plain double sums of Eq. 27-29 and A19-A21,
  *     O((N_r N_phi)^2), at any chosen set of destination cells;
  *   - the transpose of that linear map, as a plain double sum, at any chosen
@@ -764,39 +765,83 @@ int or_tables(int n_r, int n_phi, double r_min, double r_max, int n_tpz,
 }
 
 /* ------------------------------------------------------------------------ */
-/* Density channels (Eq. 25; central differences, P. 5.3).                    */
-/* sigma, s, dr, dph are [n_r][n_phi].                                        */
+/* Density channels: the slopes delta^r = d sigma/dr and delta^phi =          */
+/* d sigma/dphi at the cell centres that Eq. 25 takes, from the cell values.  */
+/* order 2: central differences (P. 5.3), one-sided on the first and last     */
+/*   rows: delta^r[i] = (s[i+1] - s[i-1]) / (r[i+1] - r[i-1]),                */
+/*   delta^phi[j] = (s[j+1] - s[j-1]) / (2 dphi) (periodic in phi).           */
+/* order 4: the five-point central differences where all five points exist:  */
+/*   delta^phi[j] = (s[j-2] - 8 s[j-1] + 8 s[j+1] - s[j+2]) / (12 dphi), and  */
+/*   on the rows 2 .. n_r - 3, in u = ln r (the grid is uniform in u,        */
+/*   u[i+1] - u[i] = ln beta) and d/dr = (1/r) d/du:                         */
+/*   delta^r[i] = (s[i-2] - 8 s[i-1] + 8 s[i+1] - s[i+2]) / (12 ln(beta) r[i]);*/
+/*   rows 1 and n_r - 2 keep the order-2 central difference, rows 0 and       */
+/*   n_r - 1 the one-sided one.                                              */
+/* sigma, dr, dph are [n_r][n_phi].                                           */
 /* ------------------------------------------------------------------------ */
+/* coefficient of sigma[i] in delta^r[i2] */
+static double dr_coef(int n_r, const double *rc, int order, int i2, int i)
+{
+    if (i2 == 0) {
+        double inv = 1.0 / (rc[1] - rc[0]);
+        return i == 1 ? inv : (i == 0 ? -inv : 0.0);
+    }
+    if (i2 == n_r - 1) {
+        double inv = 1.0 / (rc[n_r - 1] - rc[n_r - 2]);
+        return i == n_r - 1 ? inv : (i == n_r - 2 ? -inv : 0.0);
+    }
+    if (order == 4 && i2 >= 2 && i2 <= n_r - 3) {
+        double h = 1.0 / (12.0 * log(rc[1] / rc[0]) * rc[i2]);
+        int d = i - i2;
+        return d == -2 ? h : d == -1 ? -8.0 * h : d == 1 ? 8.0 * h : d == 2 ? -h : 0.0;
+    }
+    double inv = 1.0 / (rc[i2 + 1] - rc[i2 - 1]);
+    return i == i2 + 1 ? inv : (i == i2 - 1 ? -inv : 0.0);
+}
+
+/* coefficient of sigma[j2 + d] in delta^phi[j2] (d taken mod n_phi) */
+static double dp_coef(int order, double dphi, int d)
+{
+    if (order == 4) {
+        double h = 1.0 / (12.0 * dphi);
+        return d == -2 ? h : d == -1 ? -8.0 * h : d == 1 ? 8.0 * h : d == 2 ? -h : 0.0;
+    }
+    return d == 1 ? 0.5 / dphi : d == -1 ? -0.5 / dphi : 0.0;
+}
+
+int or_channels_o(int n_r, int n_phi, const double *r_c, double dphi, int order,
+                  const double *sigma, double *dr, double *dph)
+{
+    if (n_r < 2 || n_phi < 3 || (order != 2 && order != 4)) return -1;
+    if (order == 4 && (n_r < 4 || n_phi < 5)) return -1;
+    for (int i = 0; i < n_r; ++i)
+        for (int j = 0; j < n_phi; ++j) {
+            double a = 0.0, b = 0.0;
+            for (int d = -2; d <= 2; ++d) {
+                int jj = ((j + d) % n_phi + n_phi) % n_phi, ii = i + d;
+                a += dp_coef(order, dphi, d) * sigma[(long)i * n_phi + jj];
+                if (ii >= 0 && ii < n_r)
+                    b += dr_coef(n_r, r_c, order, i, ii) * sigma[(long)ii * n_phi + j];
+            }
+            dph[(long)i * n_phi + j] = a;
+            dr[(long)i * n_phi + j] = b;
+        }
+    return 0;
+}
+
 int or_channels(int n_r, int n_phi, const double *r_c, double dphi,
                 const double *sigma, double *dr, double *dph)
 {
-    if (n_r < 2 || n_phi < 3) return -1;
-    for (int i = 0; i < n_r; ++i)
-        for (int j = 0; j < n_phi; ++j) {
-            const double *row = sigma + (long)i * n_phi;
-            int jp = (j + 1) % n_phi, jm = (j + n_phi - 1) % n_phi;
-            dph[(long)i * n_phi + j] = (row[jp] - row[jm]) / (2.0 * dphi);
-            double v;
-            if (i == 0)
-                v = (sigma[(long)1 * n_phi + j] - sigma[j]) / (r_c[1] - r_c[0]);
-            else if (i == n_r - 1)
-                v = (sigma[(long)i * n_phi + j] - sigma[(long)(i - 1) * n_phi + j])
-                    / (r_c[i] - r_c[i - 1]);
-            else
-                v = (sigma[(long)(i + 1) * n_phi + j] - sigma[(long)(i - 1) * n_phi + j])
-                    / (r_c[i + 1] - r_c[i - 1]);
-            dr[(long)i * n_phi + j] = v;
-        }
-    return 0;
+    return or_channels_o(n_r, n_phi, r_c, dphi, 2, sigma, dr, dph);
 }
 
 /* ------------------------------------------------------------------------ */
 /* Forward direct sums (Eq. 27-29 and A19-A21) at chosen destinations.        */
 /* dest: n_dest flat indices i*n_phi + j (NULL = every cell, in order).       */
 /* ------------------------------------------------------------------------ */
-int or_forward(int n_r, int n_phi, double r_min, double r_max, const double *T,
-               const double *sigma, const int64_t *dest, int64_t n_dest,
-               double *f_r, double *f_phi)
+int or_forward_o(int n_r, int n_phi, double r_min, double r_max, int order, const double *T,
+                 const double *sigma, const int64_t *dest, int64_t n_dest,
+                 double *f_r, double *f_phi)
 {
     double beta, dphi;
     double *rc = (double *)malloc(sizeof(double) * n_r);
@@ -807,7 +852,9 @@ int or_forward(int n_r, int n_phi, double r_min, double r_max, const double *T,
     double *dp = (double *)malloc(sizeof(double) * N);
     int *live = (int *)malloc(sizeof(int) * n_r);
     if (!dr || !dp || !live) { free(rc); free(dr); free(dp); free(live); return -2; }
-    or_channels(n_r, n_phi, rc, dphi, sigma, dr, dp);
+    if (or_channels_o(n_r, n_phi, rc, dphi, order, sigma, dr, dp)) {
+        free(rc); free(dr); free(dp); free(live); return -1;
+    }
     /* rows whose three channels are all zero contribute nothing */
     for (int i = 0; i < n_r; ++i) {
         live[i] = 0;
@@ -858,6 +905,13 @@ int or_forward(int n_r, int n_phi, double r_min, double r_max, const double *T,
     return 0;
 }
 
+int or_forward(int n_r, int n_phi, double r_min, double r_max, const double *T,
+               const double *sigma, const int64_t *dest, int64_t n_dest,
+               double *f_r, double *f_phi)
+{
+    return or_forward_o(n_r, n_phi, r_min, r_max, 2, T, sigma, dest, n_dest, f_r, f_phi);
+}
+
 /* ------------------------------------------------------------------------ */
 /* Transpose of the forward map, as a plain double sum, at chosen sources.    */
 /* Given cotangents v_r, v_phi on every destination, returns                  */
@@ -894,30 +948,16 @@ static void adj_u(int n_r, int n_phi, const double *rc, const double *T,
     *uh = acc_get(&h);
 }
 
-/* coefficient of sigma[i] in delta^r[i2] (Eq. 25 slopes, one-sided ends) */
-static double dr_coef(int n_r, const double *rc, int i2, int i)
-{
-    if (i2 == 0) {
-        double inv = 1.0 / (rc[1] - rc[0]);
-        return i == 1 ? inv : (i == 0 ? -inv : 0.0);
-    }
-    if (i2 == n_r - 1) {
-        double inv = 1.0 / (rc[n_r - 1] - rc[n_r - 2]);
-        return i == n_r - 1 ? inv : (i == n_r - 2 ? -inv : 0.0);
-    }
-    double inv = 1.0 / (rc[i2 + 1] - rc[i2 - 1]);
-    return i == i2 + 1 ? inv : (i == i2 - 1 ? -inv : 0.0);
-}
-
-int or_adjoint(int n_r, int n_phi, double r_min, double r_max, const double *T,
-               const double *v_r, const double *v_phi, const int64_t *src,
-               int64_t n_src, double *g)
+int or_adjoint_o(int n_r, int n_phi, double r_min, double r_max, int order, const double *T,
+                 const double *v_r, const double *v_phi, const int64_t *src,
+                 int64_t n_src, double *g)
 {
     double beta, dphi;
     double *rc = (double *)malloc(sizeof(double) * n_r);
     if (!rc) return -2;
     if (or_geometry(n_r, n_phi, r_min, r_max, rc, NULL, &beta, &dphi)) { free(rc); return -1; }
-    if (n_r < 2 || n_phi < 3) { free(rc); return -1; }
+    if (n_r < 2 || n_phi < 3 || (order != 2 && order != 4) ||
+        (order == 4 && (n_r < 4 || n_phi < 5))) { free(rc); return -1; }
     const long N = (long)n_r * n_phi;
     const int64_t ns = src ? n_src : (int64_t)N;
 #ifdef _OPENMP
@@ -930,27 +970,35 @@ int or_adjoint(int n_r, int n_phi, double r_min, double r_max, const double *T,
         adj_u(n_r, n_phi, rc, T, v_r, v_phi, ip, jp, &us, &ug, &uh);
         tot = us;
         /* radial slope channel: sum over i2 of coef(i2, ip) * u_g(i2, jp) */
-        for (int i2 = ip - 1; i2 <= ip + 1; ++i2) {
+        for (int i2 = ip - 2; i2 <= ip + 2; ++i2) {
             if (i2 < 0 || i2 >= n_r) continue;
-            double cf = dr_coef(n_r, rc, i2, ip);
+            double cf = dr_coef(n_r, rc, order, i2, ip);
             if (cf == 0.0) continue;
             double a, b, c;
             adj_u(n_r, n_phi, rc, T, v_r, v_phi, i2, jp, &a, &b, &c);
             tot += cf * b;
         }
-        /* azimuthal slope channel: delta^phi[j2] has +1/(2 dphi) on j2+1 and
-         * -1/(2 dphi) on j2-1, so sigma[jp] meets u_h at jp-1 and jp+1 */
-        {
-            int jm = (jp + n_phi - 1) % n_phi, jq = (jp + 1) % n_phi;
-            double a, b, hm, hq;
-            adj_u(n_r, n_phi, rc, T, v_r, v_phi, ip, jm, &a, &b, &hm);
-            adj_u(n_r, n_phi, rc, T, v_r, v_phi, ip, jq, &a, &b, &hq);
-            tot += (hm - hq) / (2.0 * dphi);
+        /* azimuthal slope channel: sigma[jp] enters delta^phi[jp - d] with
+         * the coefficient of offset d, so it meets u_h at jp - d */
+        for (int d = -2; d <= 2; ++d) {
+            double cf = dp_coef(order, dphi, d);
+            if (cf == 0.0) continue;
+            int j2 = ((jp - d) % n_phi + n_phi) % n_phi;
+            double a, b, h;
+            adj_u(n_r, n_phi, rc, T, v_r, v_phi, ip, j2, &a, &b, &h);
+            tot += cf * h;
         }
         g[q] = tot;
     }
     free(rc);
     return 0;
+}
+
+int or_adjoint(int n_r, int n_phi, double r_min, double r_max, const double *T,
+               const double *v_r, const double *v_phi, const int64_t *src,
+               int64_t n_src, double *g)
+{
+    return or_adjoint_o(n_r, n_phi, r_min, r_max, 2, T, v_r, v_phi, src, n_src, g);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -967,9 +1015,9 @@ int or_adjoint(int n_r, int n_phi, double r_min, double r_max, const double *T,
 /* (K^{r,phi}_{00}, K^{phi,0}_{00}, K^{phi,r}_{00} vanish by symmetry);      */
 /* self = K^{r,0}_{00}, K^{r,r}_{00}, K^{phi,phi}_{00}.                       */
 /* ------------------------------------------------------------------------ */
-int or_forward_particle(int n_r, int n_phi, double r_min, double r_max, int plus,
-                        const double *self, const double *sigma, const int64_t *dest,
-                        int64_t n_dest, double *f_r, double *f_phi)
+int or_forward_particle_o(int n_r, int n_phi, double r_min, double r_max, int plus, int order,
+                          const double *self, const double *sigma, const int64_t *dest,
+                          int64_t n_dest, double *f_r, double *f_phi)
 {
     double beta, dphi;
     double *rc = (double *)malloc(sizeof(double) * n_r);
@@ -983,7 +1031,9 @@ int or_forward_particle(int n_r, int n_phi, double r_min, double r_max, int plus
     double *dp = (double *)malloc(sizeof(double) * N);
     double *mass = (double *)malloc(sizeof(double) * N);
     if (!dr || !dp || !mass) { free(rc); free(re); free(dr); free(dp); free(mass); return -2; }
-    or_channels(n_r, n_phi, rc, dphi, sigma, dr, dp);
+    if (or_channels_o(n_r, n_phi, rc, dphi, order, sigma, dr, dp)) {
+        free(rc); free(re); free(dr); free(dp); free(mass); return -1;
+    }
     for (int i = 0; i < n_r; ++i) {
         const double area = 0.5 * (re[i + 1] * re[i + 1] - re[i] * re[i]) * dphi;
         for (int j = 0; j < n_phi; ++j) mass[(long)i * n_phi + j] = sigma[(long)i * n_phi + j] * area;
@@ -1020,6 +1070,14 @@ int or_forward_particle(int n_r, int n_phi, double r_min, double r_max, int plus
     }
     free(rc); free(re); free(dr); free(dp); free(mass);
     return 0;
+}
+
+int or_forward_particle(int n_r, int n_phi, double r_min, double r_max, int plus,
+                        const double *self, const double *sigma, const int64_t *dest,
+                        int64_t n_dest, double *f_r, double *f_phi)
+{
+    return or_forward_particle_o(n_r, n_phi, r_min, r_max, plus, 2, self, sigma, dest, n_dest,
+                                 f_r, f_phi);
 }
 
 /* ------------------------------------------------------------------------ */

@@ -57,7 +57,7 @@ class pf_build_opts(ctypes.Structure):
     _fields_ = [("dtype", ctypes.c_int), ("n_tpz", ctypes.c_int),
                 ("cover_per", ctypes.c_int), ("keep_tables", ctypes.c_int),
                 ("table_mode", ctypes.c_int), ("self_mode", ctypes.c_int),
-                ("method", ctypes.c_int)]
+                ("method", ctypes.c_int), ("slope_order", ctypes.c_int)]
 
 
 _lib = None
@@ -286,25 +286,29 @@ class Plan:
 
     def __init__(self, n_r, n_phi, r_min, r_max, dtype="f32", n_tpz=19, cover_per=10,
                  keep_tables=False, build=True, table_mode="sim", self_mode="cartesian",
-                 method="sim"):
+                 method="sim", slope_order=2):
         self.n_r, self.n_phi = int(n_r), int(n_phi)
         self.r_min, self.r_max = float(r_min), float(r_max)
         self.handle = pf_plan_create(n_r, n_phi, r_min, r_max)
         self.dtype = None
         if build:
-            self.build(dtype, n_tpz, cover_per, keep_tables, table_mode, self_mode, method)
+            self.build(dtype, n_tpz, cover_per, keep_tables, table_mode, self_mode, method,
+                       slope_order)
 
     def build(self, dtype="f32", n_tpz=19, cover_per=10, keep_tables=False, table_mode="sim",
-              self_mode="cartesian", method="sim"):
+              self_mode="cartesian", method="sim", slope_order=2):
         """method "sim" (second order, SIM kernels), "particle" or "particle+"
         (Eq. 34-37); table_mode "sim" (n_tpz trapezoids, Eq. 41-43) or
-        "exact"; self_mode "cartesian" (cover, Eq. 44-46) or "exact"."""
+        "exact"; self_mode "cartesian" (cover, Eq. 44-46) or "exact";
+        slope_order 2 (central differences for the slopes of Eq. 25) or 4
+        (five-point differences)."""
         o = pf_build_opts_default()
         o.dtype = PF_F64 if dtype in ("f64", "float64", PF_F64) else PF_F32
         o.n_tpz, o.cover_per, o.keep_tables = int(n_tpz), int(cover_per), int(bool(keep_tables))
         o.table_mode = _TABLE_MODES[table_mode]
         o.self_mode = _SELF_MODES[self_mode]
         o.method = _METHODS[method]
+        o.slope_order = int(slope_order)
         pf_kernels_build(self.handle, o, _stream())
         self.dtype = "f64" if o.dtype == PF_F64 else "f32"
         return self

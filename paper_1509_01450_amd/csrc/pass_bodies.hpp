@@ -475,6 +475,119 @@ __device__ __forceinline__ cx<T> slope_fix_at(const SlopePhasors<T> &p, cx<T> rn
     return cmac(mul_root_add<E>(p.a0, p.b2, -e), rne, mul_root_add<E>(p.b1, p.b3, -e));
 }
 
+// The boundary rows a correction reads: rows 0 .. SO-1 and n-SO .. n-1 of the
+// column (SO = 2 for the four-row correction, 4 for the eight-row one).
+template <typename T, int SO>
+struct SlopeRows {
+    cx<T> lo[SO], hi[SO];
+};
+template <typename T, int SO>
+__device__ __forceinline__ SlopeRows<T, SO> slope_rows(const cx<T> *__restrict__ S, int H,
+                                                       int n_r, int cl) {
+    SlopeRows<T, SO> b;
+#pragma unroll
+    for (int q = 0; q < SO; ++q) b.lo[q] = S[(size_t)q * H + cl];
+#pragma unroll
+    for (int q = 0; q < SO; ++q) b.hi[q] = S[(size_t)(n_r - SO + q) * H + cl];
+    return b;
+}
+template <typename T, int SO>
+__device__ __forceinline__ SlopeRows<T, SO> scaled(SlopeRows<T, SO> b, T s) {
+#pragma unroll
+    for (int q = 0; q < SO; ++q) {
+        b.lo[q] = scale(b.lo[q], s);
+        b.hi[q] = scale(b.hi[q], s);
+    }
+    return b;
+}
+
+// Coefficients of the radial slope g = r delta^r on the logarithmic grid:
+// ca three-point central, c0 and cn one-sided on the first and last rows,
+// c4 five-point central (slope order 4 only).
+template <typename T>
+struct SlopeCoef {
+    T ca, c0, cn, c4;
+};
+
+template <typename T>
+__device__ __forceinline__ SlopeFix<T> slope_fix(const SlopeRows<T, 2> &b, const SlopeCoef<T> &k) {
+    return slope_fix(b.lo[0], b.lo[1], b.hi[0], b.hi[1], k.ca, k.c0, k.cn);
+}
+
+// ---------------------------------------------------------------------------
+// Eight-row correction of the radial slope of order 4.  The slope is the
+// five-point difference c4 (c[i-2] - 8 c[i-1] + 8 c[i+1] - c[i+2]) on rows
+// 2 .. n-3 (its circular form on the padded column is folded into the
+// spectra as D(k) = 2i c4 (8 sin(2 pi k / L) - sin(4 pi k / L))), the
+// three-point ca (c[i+1] - c[i-1]) on rows 1 and n-2 and the one-sided
+// differences on rows 0 and n-1.  It differs from the circular five-point
+// difference of the zero-padded column at eight rows (d_q = c[n-4+q]):
+//   row 0      c0 (c1 - c0) - c4 (8 c1 - c2)
+//   row 1      ca (c2 - c0) - c4 (8 (c2 - c0) - c3)
+//   row n - 2  ca (d3 - d1) - c4 (8 (d3 - d1) + d0)
+//   row n - 1  cn (d3 - d2) - c4 (d1 - 8 d2)
+//   row n      c4 (8 d3 - d2)
+//   row n + 1  -c4 d3
+//   row L - 1  c4 (c1 - 8 c0)
+//   row L - 2  c4 c0
+// (n >= 4).  At k = t + e TH the rows j near 0 give a_j W^(j t) w^(j e) and
+// those near n give w^(n e) a_j W^(j t) w^((j - n) e), as for four rows.
+// ---------------------------------------------------------------------------
+template <typename T>
+struct SlopeFix4 {
+    cx<T> a0, a1, am1, am2, an2, an1, an, anp1;
+};
+
+template <typename T>
+__device__ __forceinline__ SlopeFix4<T> slope_fix(const SlopeRows<T, 4> &b, const SlopeCoef<T> &k) {
+    const cx<T> *c = b.lo, *d = b.hi;
+    SlopeFix4<T> s;
+    s.a0 = scale(c[1] - c[0], k.c0) - scale(scale(c[1], T(8)) - c[2], k.c4);
+    s.a1 = scale(c[2] - c[0], k.ca) - scale(scale(c[2] - c[0], T(8)) - c[3], k.c4);
+    s.an2 = scale(d[3] - d[1], k.ca) - scale(scale(d[3] - d[1], T(8)) + d[0], k.c4);
+    s.an1 = scale(d[3] - d[2], k.cn) - scale(d[1] - scale(d[2], T(8)), k.c4);
+    s.an = scale(scale(d[3], T(8)) - d[2], k.c4);
+    s.anp1 = scale(d[3], -k.c4);
+    s.am1 = scale(c[1] - scale(c[0], T(8)), k.c4);
+    s.am2 = scale(c[0], k.c4);
+    return s;
+}
+
+template <typename T>
+__device__ __forceinline__ SlopeFix4<T> slope_fix_part(const SlopeFix4<T> &s, bool imag) {
+    auto pick = [imag](cx<T> a) { return cx<T>{imag ? a.y : a.x, T(0)}; };
+    return {pick(s.a0), pick(s.a1),  pick(s.am1), pick(s.am2),
+            pick(s.an2), pick(s.an1), pick(s.an),  pick(s.anp1)};
+}
+
+template <typename T>
+struct SlopePhasors4 {
+    cx<T> a0, l1, lm1, lm2, h0, h1, hm1, hm2;
+};
+
+template <typename T>
+__device__ __forceinline__ SlopePhasors4<T> slope_phasors(const SlopeFix4<T> &s, cx<T> wt,
+                                                          cx<T> wnt) {
+    const cx<T> wtc = conj(wt), w2c = cmul(wtc, wtc);
+    return {s.a0,
+            cmul(s.a1, wt),
+            cmul(s.am1, wtc),
+            cmul(s.am2, w2c),
+            cmul(s.an, wnt),
+            cmul(s.anp1, cmul(wnt, wt)),
+            cmul(s.an1, cmul(wnt, wtc)),
+            cmul(s.an2, cmul(wnt, w2c))};
+}
+
+template <typename T, int E>
+__device__ __forceinline__ cx<T> slope_fix_at(const SlopePhasors4<T> &p, cx<T> rne, int e) {
+    const cx<T> lo =
+        mul_root_add<E>(mul_root_add<E>(mul_root_add<E>(p.a0, p.l1, e), p.lm1, -e), p.lm2, -2 * e);
+    const cx<T> hi =
+        mul_root_add<E>(mul_root_add<E>(mul_root_add<E>(p.h0, p.h1, e), p.hm1, -e), p.hm2, -2 * e);
+    return cmac(lo, rne, hi);
+}
+
 // Transforms of the two real sequences packed as p = c_0 + i c_M, from p and
 // its conjugate mirror m = p[L - k]:  c_0 -> (p + conj m) / 2,
 // c_M -> (p - conj m) / (2i).
@@ -585,9 +698,9 @@ __device__ __forceinline__ void prefetch_wait() {
 // The forward sweep takes the slope correction at the points either from f
 // (KEEP: formed once, kept in registers for both sweeps) or forms it from
 // the phasors ph (FP64, where 16 more registers per point would spill).
-template <typename T, int L, int E, bool ODD, bool PF, bool KEEP>
+template <typename T, int L, int E, bool ODD, bool PF, bool KEEP, typename PH>
 __device__ __forceinline__ void mac_fwd(cx<T> (&y)[E], const cx<T> (&x)[E], const cx<T> (&f)[E],
-                                        const SlopePhasors<T> &ph, const cx<T> *__restrict__ twL,
+                                        const PH &ph, const cx<T> *__restrict__ twL,
                                         int n_r, const cx2<T> *sl, const cx2<T> *__restrict__ sg,
                                         int t) {
     const bool t0 = t == 0;
@@ -652,6 +765,21 @@ __device__ __forceinline__ void accum_w(cx<T> (&w)[4], cx<T> r, cx<T> rne, int e
     w[2] = w[2] + q;
     w[3] = mul_root_add<E>(w[3], q, e);
 }
+// The eight sums of the slope of order 4: the four above and rows 1, L-2,
+// n-2 and n+1, w[4] += r W^-k, w[5] += r W^(2k), w[6] += r W^(-(n-2) k),
+// w[7] += r W^(-(n+1) k).
+template <typename T, int E>
+__device__ __forceinline__ void accum_w(cx<T> (&w)[8], cx<T> r, cx<T> rne, int e) {
+    const cx<T> q = cmulc(r, rne);
+    w[0] = w[0] + r;
+    w[1] = mul_root_add<E>(w[1], r, e);
+    w[2] = w[2] + q;
+    w[3] = mul_root_add<E>(w[3], q, e);
+    w[4] = mul_root_add<E>(w[4], r, -e);
+    w[5] = mul_root_add<E>(w[5], r, 2 * e);
+    w[6] = mul_root_add<E>(w[6], q, 2 * e);
+    w[7] = mul_root_add<E>(w[7], q, -e);
+}
 
 // The forward column transform of a zero-padded column, times the grid
 // scale that f gives: in FP32 applied after the first stage, in FP64 not at
@@ -677,7 +805,9 @@ __device__ __forceinline__ void fft_col_fwd(cx<T> (&v)[E], int t, const Lds<T> &
 // outside the one workgroup that holds the packed column 0.
 // PF: the spectrum pairs go to LDS at spl (G spec_prefetch_len<L, E>()
 // pairs), one half at a time.
-template <typename T, int L, int E, bool PF = false>
+// SO: order of the radial slope (2: the four-row correction; 4: five-point
+// differences and the eight-row correction, c4 their coefficient).
+template <typename T, int L, int E, bool PF = false, int SO = 2>
 __device__ __forceinline__ void body_cols_fwd(int unit, int G, cx<T> *__restrict__ buf,
                                               const cx<T> *__restrict__ S,
                                               cx2<T> *__restrict__ Z,
@@ -685,7 +815,9 @@ __device__ __forceinline__ void body_cols_fwd(int unit, int G, cx<T> *__restrict
                                               int n_out, int ldspec, T ca, T c0, T cn,
                                               const cx<T> *__restrict__ twL,
                                               cx2<T> *spl = nullptr,
-                                              unsigned *__restrict__ gscale = nullptr) {
+                                              unsigned *__restrict__ gscale = nullptr,
+                                              T c4 = T(0)) {
+    static_assert(SO == 2 || SO == 4, "slope order");
     constexpr int TH = L / E;
     const int gi = threadIdx.x % G, t = threadIdx.x / G;
     const int col = unit * G + gi;
@@ -710,9 +842,9 @@ __device__ __forceinline__ void body_cols_fwd(int unit, int G, cx<T> *__restrict
         const int i = t + e * TH;
         v[e] = S[(size_t)(i < n_r ? i : n_r - 1) * H + cl];
     }
-    // the four rows entering the slope correction, and the thread's phasors
-    cx<T> x0 = S[cl], x1 = S[(size_t)H + cl];
-    cx<T> xm2 = S[(size_t)(n_r - 2) * H + cl], xm1 = S[(size_t)(n_r - 1) * H + cl];
+    // the rows entering the slope correction, and the thread's phasors
+    SlopeRows<T, SO> br = slope_rows<T, SO>(S, H, n_r, cl);
+    const SlopeCoef<T> kf{ca, c0, cn, c4};
     const cx<T> wt = twL[t], wnt = twL[(int)(((unsigned)n_r * (unsigned)t) & (unsigned)(L - 1))];
     Twiddles<L, E, T> tw;
     tw.load(t, twL, 1);
@@ -725,10 +857,7 @@ __device__ __forceinline__ void body_cols_fwd(int unit, int G, cx<T> *__restrict
     }
     GridScale<T> sc;
     fft_col_fwd<L, E, T>(v, t, lds, tw, ScaleFind<T>{gscale, note, unit, &sc});
-    x0 = scale(x0, sc.dn);
-    x1 = scale(x1, sc.dn);
-    xm2 = scale(xm2, sc.dn);
-    xm1 = scale(xm1, sc.dn);
+    br = scaled(br, sc.dn);
 
     // FP32 (SPLIT): the radial channel's sweep and inverse transform, then
     // the azimuthal channel's (its spectrum pairs arriving meanwhile).  FP64:
@@ -736,7 +865,7 @@ __device__ __forceinline__ void body_cols_fwd(int unit, int G, cx<T> *__restrict
     // from global memory), then the two inverse transforms -- fewer values
     // live across a transform (the split order spills at E = 8).
     constexpr bool SPLIT = sizeof(T) == 4;
-    const SlopePhasors<T> ph = slope_phasors(slope_fix(x0, x1, xm2, xm1, ca, c0, cn), wt, wnt);
+    const auto ph = slope_phasors(slope_fix(br, kf), wt, wnt);
     const cx2<T> *sl = PF ? spl + (size_t)gi * LP : nullptr;
     const cx2<T> *const gr = srad + (size_t)cl * ldspec;
     const cx2<T> *const gp = sazi + (size_t)cl * ldspec;
@@ -761,13 +890,11 @@ __device__ __forceinline__ void body_cols_fwd(int unit, int G, cx<T> *__restrict
             for (int e = 0; e < E; ++e) lds.st_split(lds_pad(t), e * TH, v[e]);
             lds_barrier();
             if (is0) {
-                // the four boundary rows again (read here rather than kept live
+                // the boundary rows again (read here rather than kept live
                 // through the transform for this one column)
-                const SlopeFix<T> a = slope_fix(scale(S[0], sc.dn), scale(S[(size_t)H], sc.dn),
-                                                scale(S[(size_t)(n_r - 2) * H], sc.dn),
-                                                scale(S[(size_t)(n_r - 1) * H], sc.dn), ca, c0, cn);
-                const SlopePhasors<T> ph0 = slope_phasors(slope_fix_part(a, false), wt, wnt);
-                const SlopePhasors<T> phM = slope_phasors(slope_fix_part(a, true), wt, wnt);
+                const auto a = slope_fix(scaled(slope_rows<T, SO>(S, H, n_r, 0), sc.dn), kf);
+                const auto ph0 = slope_phasors(slope_fix_part(a, false), wt, wnt);
+                const auto phM = slope_phasors(slope_fix_part(a, true), wt, wnt);
                 const bool t0 = t == 0;
 #pragma unroll
                 for (int e = 0; e < E; ++e) {
@@ -809,11 +936,9 @@ __device__ __forceinline__ void body_cols_fwd(int unit, int G, cx<T> *__restrict
             for (int e = 0; e < E; ++e) lds.st_split(lds_pad(t), e * TH, v[e]);
             lds_barrier();
         }
-        SlopePhasors<T> ph0 = ph, phM = ph;
+        auto ph0 = ph, phM = ph;
         if (is0) {   // bins 0 and M of the packed column: real coefficients each
-            const SlopeFix<T> a = slope_fix(scale(S[0], sc.dn), scale(S[(size_t)H], sc.dn),
-                                            scale(S[(size_t)(n_r - 2) * H], sc.dn),
-                                            scale(S[(size_t)(n_r - 1) * H], sc.dn), ca, c0, cn);
+            const auto a = slope_fix(scaled(slope_rows<T, SO>(S, H, n_r, 0), sc.dn), kf);
             ph0 = slope_phasors(slope_fix_part(a, false), wt, wnt);
             phM = slope_phasors(slope_fix_part(a, true), wt, wnt);
         }
@@ -920,7 +1045,9 @@ __device__ __forceinline__ void column_sums(cx<T> (&x)[Q], int G, cx<T> *__restr
 // PF: the spectrum pairs go to LDS at spl (G spec_prefetch_len<L, E>()
 // pairs), one half at a time.
 // ---------------------------------------------------------------------------
-template <typename T, int L, int E, bool PF = false>
+// SO: order of the radial slope, as for the forward pass (4: eight sums
+// and the transposed eight-row correction).
+template <typename T, int L, int E, bool PF = false, int SO = 2>
 __device__ __forceinline__ void body_cols_adj(int unit, int G, cx<T> *__restrict__ buf,
                                               const cx2<T> *__restrict__ V,
                                               cx<T> *__restrict__ D,
@@ -928,7 +1055,10 @@ __device__ __forceinline__ void body_cols_adj(int unit, int G, cx<T> *__restrict
                                               int ldspec, T ca, T c0, T cn,
                                               const cx<T> *__restrict__ twL,
                                               cx2<T> *spl = nullptr,
-                                              unsigned *__restrict__ gscale = nullptr) {
+                                              unsigned *__restrict__ gscale = nullptr,
+                                              T c4 = T(0)) {
+    static_assert(SO == 2 || SO == 4, "slope order");
+    constexpr int NW = SO == 4 ? 8 : 4;
     constexpr int TH = L / E;
     const int gi = threadIdx.x % G, t = threadIdx.x / G;
     const int col = unit * G + gi;
@@ -983,7 +1113,9 @@ __device__ __forceinline__ void body_cols_adj(int unit, int G, cx<T> *__restrict
     //   w[3] = sum R W^(-(n-1) k),
     // summed per thread against the roots (W^(j k) = W^(j t) r(j e)) and
     // turned into the thread's share with its phasors afterwards.
-    cx<T> w[4] = {{T(0), T(0)}, {T(0), T(0)}, {T(0), T(0)}, {T(0), T(0)}};
+    cx<T> w[NW];
+#pragma unroll
+    for (int q = 0; q < NW; ++q) w[q] = cx<T>{T(0), T(0)};
     cx<T> xe[E];
     fft_col_fwd<L, E, T>(va[0], t, lds, tw, ScaleFind<T>{gscale, note, unit, &sc});
     if constexpr (SPLIT) {
@@ -1086,20 +1218,44 @@ __device__ __forceinline__ void body_cols_adj(int unit, int G, cx<T> *__restrict
         w[1] = cmul(w[1], wt);
         w[2] = cmulc(w[2], wnt);
         w[3] = cmulc(w[3], wmt);
+        if constexpr (SO == 4) {
+            w[4] = cmulc(w[4], wt);                              // W^-t
+            w[5] = cmul(w[5], cmul(wt, wt));                     // W^(2t)
+            w[6] = cmulc(w[6], cmulc(wmt, wt));                  // W^(-(n-2) t)
+            w[7] = cmulc(w[7], cmul(wnt, wt));                   // W^(-(n+1) t)
+        }
     }
-    column_sums<T, 4>(w, G, buf);
+    column_sums<T, NW>(w, G, buf);
     fft_inv<L, E, T>(xe, t, lds, tw);
     if (valid) {
 #pragma unroll
         for (int e = 0; e < E / 2; ++e) {   // rows lie in the first half (L >= 2 n_r)
             const int i = t + e * TH;
             if (i < n_r) {
-                // transposed four-row correction
                 cx<T> acc = xe[e];
-                if (i == 0) acc = acc - scale(w[0], c0) - scale(w[1], ca);
-                if (i == 1) acc = acc + scale(w[0], c0 - ca);
-                if (i == n_r - 2) acc = acc + scale(w[3], ca - cn);
-                if (i == n_r - 1) acc = acc + scale(w[3], cn) + scale(w[2], ca);
+                if constexpr (SO == 2) {   // transposed four-row correction
+                    if (i == 0) acc = acc - scale(w[0], c0) - scale(w[1], ca);
+                    if (i == 1) acc = acc + scale(w[0], c0 - ca);
+                    if (i == n_r - 2) acc = acc + scale(w[3], ca - cn);
+                    if (i == n_r - 1) acc = acc + scale(w[3], cn) + scale(w[2], ca);
+                } else {
+                    // transposed eight-row correction: the sums at rows
+                    // 0, L-1, n, n-1, 1, L-2, n-2, n+1 (w[0..7]) back onto
+                    // the boundary rows each correction row reads
+                    const T k8 = T(8) * c4;
+                    if (i == 0)
+                        acc = acc - scale(w[0], c0) + scale(w[4], k8 - ca) - scale(w[1], k8) +
+                              scale(w[5], c4);
+                    if (i == 1) acc = acc + scale(w[0], c0 - k8) + scale(w[1], c4);
+                    if (i == 2) acc = acc + scale(w[0], c4) + scale(w[4], ca - k8);
+                    if (i == 3) acc = acc + scale(w[4], c4);
+                    if (i == n_r - 4) acc = acc - scale(w[6], c4);
+                    if (i == n_r - 3) acc = acc + scale(w[6], k8 - ca) - scale(w[3], c4);
+                    if (i == n_r - 2) acc = acc + scale(w[3], k8 - cn) - scale(w[2], c4);
+                    if (i == n_r - 1)
+                        acc = acc + scale(w[6], ca - k8) + scale(w[3], cn) + scale(w[2], k8) -
+                              scale(w[7], c4);
+                }
                 D[(size_t)i * H + col] = acc;   // still scaled
             }
         }

@@ -238,6 +238,7 @@ void pf_build_opts_default(pf_build_opts *o) {
     o->self_mode = PF_SELF_CARTESIAN;
     o->method = PF_METHOD_SIM;
     o->keep_tables = 0;
+    o->slope_order = 2;
 }
 
 pf_plan pf_plan_create(int n_r, int n_phi, double r_min, double r_max) {
@@ -471,12 +472,22 @@ int pf_kernels_build(pf_plan h, const pf_build_opts *opts, void *stream) {
         pf::set_error("cover_per = %d outside [1, 64]", o.cover_per);
         return PF_EINVAL;
     }
+    if (o.slope_order != 2 && o.slope_order != 4) {
+        pf::set_error("slope_order must be 2 or 4 (got %d)", o.slope_order);
+        return PF_EINVAL;
+    }
+    if (o.slope_order == 4 && h->p.patch) {
+        pf::set_error("slope order 4 is not built for patch plans");
+        return PF_EUNSUPPORTED;
+    }
     int rc = pf::device_present();
     if (rc) return rc;
     Plan &p = h->p;
     pf::batched_forget(p.uid);
     pf::free_plan_device(&p);
     p.opts = o;
+    p.so = o.slope_order;
+    p.c4 = 1.0 / (12.0 * std::log(p.beta));
     PF_HIP(hipGetDevice(&p.device));
     hipStream_t st = (hipStream_t)stream;
     const bool f64 = o.dtype == PF_F64;
@@ -645,6 +656,10 @@ int check_batch(int n, const pf_plan *plans, const void *const *sigma, void *con
         ps[k] = &plans[k]->p;
         if (ps[k]->patch) {
             pf::set_error("batched plans must be single-grid plans (plan %d is a patch plan)", k);
+            return PF_EUNSUPPORTED;
+        }
+        if (ps[k]->so != 2) {
+            pf::set_error("batched plans must use slope order 2 (plan %d has %d)", k, ps[k]->so);
             return PF_EUNSUPPORTED;
         }
         if (ps[k]->opts.dtype != ps[0]->opts.dtype) {

@@ -59,8 +59,12 @@ struct Plan {
     bool patch = false;    // made by pf_plan_create_patches
     bool wedges = false;   // origin wedges [0, r_min beta^s0] below the source
     double r_min = 0, r_max = 0, beta = 0, dphi = 0;
-    // radial slope coefficients of g = r delta^r (interior, first, last row)
+    // radial slope coefficients of g = r delta^r (three-point central, first
+    // and last row); so = slope order of the build (2 or 4) and c4 the
+    // five-point coefficient 1 / (12 ln beta)
     double ca = 0, c0 = 0, cn = 0;
+    int so = 2;
+    double c4 = 0;
 
     bool built = false;
     pf_build_opts opts{};

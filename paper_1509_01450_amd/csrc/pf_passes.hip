@@ -41,22 +41,24 @@ __global__ __launch_bounds__(512) void k_rows_c2r(const cx<T> *__restrict__ in, 
 // threads, more than four columns per workgroup, or static LDS beyond
 // 144 KB).  In FP32 it prefetches the radial pairs into the same array, so
 // the compiler waits for them before the first exchange.
-template <typename T, int L, int E>
+// SO: slope order (4: five-point slopes, c4 their coefficient; only this
+// kernel and k_cols_adj have instances of it).
+template <typename T, int L, int E, int SO = 2>
 __global__ __launch_bounds__(512) void k_cols_fwd(const cx<T> *__restrict__ S,
                                                   cx2<T> *__restrict__ Z,
                                                   const cx2<T> *__restrict__ spec, int H, int n_r,
                                                   int n_out, int ldspec, T ca, T c0, T cn,
                                                   const cx<T> *__restrict__ twL, int per_xcd,
-                                                  int n_groups, unsigned *__restrict__ gscale) {
+                                                  int n_groups, unsigned *__restrict__ gscale,
+                                                  T c4) {
     extern __shared__ unsigned char smem_raw[];
     const int grp = xcd_group(blockIdx.x, per_xcd);
     if (grp >= n_groups) return;  // whole workgroup leaves together
     const int G = blockDim.x / (L / E);
     cx<T> *const buf = reinterpret_cast<cx<T> *>(smem_raw);
-    body_cols_fwd<T, L, E, sizeof(T) == 4>(grp, G, buf, S, Z, spec, H, n_r, n_out, ldspec, ca,
-                                           c0, cn, twL,
-                                           reinterpret_cast<cx2<T> *>(buf + (size_t)G * padded_len(L)),
-                                           gscale);
+    body_cols_fwd<T, L, E, sizeof(T) == 4, SO>(
+        grp, G, buf, S, Z, spec, H, n_r, n_out, ldspec, ca, c0, cn, twL,
+        reinterpret_cast<cx2<T> *>(buf + (size_t)G * padded_len(L)), gscale, c4);
 }
 
 // Forward column pass with G fixed at compile time: the transform buffer
@@ -81,18 +83,20 @@ __global__ __launch_bounds__(512) void k_cols_fwd_pf(const cx<T> *__restrict__ S
                                  twL, spl, gscale);
 }
 
-template <typename T, int L, int E>
+template <typename T, int L, int E, int SO = 2>
 __global__ __launch_bounds__(512) void k_cols_adj(const cx2<T> *__restrict__ V,
                                                   cx<T> *__restrict__ D,
                                                   const cx2<T> *__restrict__ spec, int H, int n_r,
                                                   int ldspec, T ca, T c0, T cn,
                                                   const cx<T> *__restrict__ twL, int per_xcd,
-                                                  int n_groups, unsigned *__restrict__ gscale) {
+                                                  int n_groups, unsigned *__restrict__ gscale,
+                                                  T c4) {
     extern __shared__ unsigned char smem_raw[];
     const int grp = xcd_group(blockIdx.x, per_xcd);
     if (grp >= n_groups) return;
-    body_cols_adj<T, L, E>(grp, blockDim.x / (L / E), reinterpret_cast<cx<T> *>(smem_raw), V, D,
-                           spec, H, n_r, ldspec, ca, c0, cn, twL, nullptr, gscale);
+    body_cols_adj<T, L, E, false, SO>(grp, blockDim.x / (L / E),
+                                      reinterpret_cast<cx<T> *>(smem_raw), V, D, spec, H, n_r,
+                                      ldspec, ca, c0, cn, twL, nullptr, gscale, c4);
 }
 
 // Transpose column pass with G fixed at compile time and the radial
@@ -258,8 +262,25 @@ struct Disp {
             const int blocks = per_xcd * 8;
             // dynamic-LDS kernels: only the FP32 forward one prefetches
             const size_t lds = cols_lds_bytes(N, E, G, sizeof(T) == 8, !ADJ && sizeof(T) == 4);
-            const T ca = T(p.ca), c0 = T(p.c0), cn = T(p.cn);
+            const T ca = T(p.ca), c0 = T(p.c0), cn = T(p.cn), c4 = T(p.c4);
             const cx2<T> *sp = reinterpret_cast<const cx2<T> *>(spec);
+            if (p.so == 4) {   // five-point slopes: the dynamic-LDS kernels only
+                if (ADJ) {
+                    int rc = allow_lds(k_cols_adj<T, N, E, 4>, lds);
+                    if (rc) return rc;
+                    hipLaunchKernelGGL((k_cols_adj<T, N, E, 4>), dim3(blocks), dim3(G * TH), lds,
+                                       st, reinterpret_cast<const cx2<T> *>(a), o, sp, p.H,
+                                       p.n_r, p.ldspec, ca, c0, cn, tw, per_xcd, n_groups, g, c4);
+                } else {
+                    int rc = allow_lds(k_cols_fwd<T, N, E, 4>, lds);
+                    if (rc) return rc;
+                    hipLaunchKernelGGL((k_cols_fwd<T, N, E, 4>), dim3(blocks), dim3(G * TH), lds,
+                                       st, a, reinterpret_cast<cx2<T> *>(o), sp, p.H, p.n_in,
+                                       p.n_r, p.ldspec, ca, c0, cn, tw, per_xcd, n_groups, g, c4);
+                }
+                PF_HIP(hipGetLastError());
+                return PF_OK;
+            }
             if (ADJ) {
                 if constexpr (TH >= 64) {
                     if ((size_t)p.H * p.ldspec * sizeof(cx2<T>) >= ((size_t)1 << 31)) {
@@ -285,7 +306,7 @@ struct Disp {
                 if (rc) return rc;
                 hipLaunchKernelGGL((k_cols_adj<T, N, E>), dim3(blocks), dim3(G * TH), lds, st,
                                    reinterpret_cast<const cx2<T> *>(a), o, sp, p.H, p.n_r,
-                                   p.ldspec, ca, c0, cn, tw, per_xcd, n_groups, g);
+                                   p.ldspec, ca, c0, cn, tw, per_xcd, n_groups, g, T(0));
             } else {
                 if constexpr (TH >= 64) {
                     // the prefetch's 32-bit offsets cover the radial half
@@ -312,7 +333,7 @@ struct Disp {
                 if (rc) return rc;
                 hipLaunchKernelGGL((k_cols_fwd<T, N, E>), dim3(blocks), dim3(G * TH), lds, st, a,
                                    reinterpret_cast<cx2<T> *>(o), sp, p.H, p.n_in, p.n_r,
-                                   p.ldspec, ca, c0, cn, tw, per_xcd, n_groups, g);
+                                   p.ldspec, ca, c0, cn, tw, per_xcd, n_groups, g, T(0));
             }
             PF_HIP(hipGetLastError());
             return PF_OK;

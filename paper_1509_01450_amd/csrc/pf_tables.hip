@@ -48,7 +48,9 @@
 //   Q_r  = F(beta^m T_rr)
 //   E'_p = F(T_p0) + i sin(2 pi k / n_phi) / dphi * F(T_pphi) + D Q_p
 //   Q_p  = F(beta^m T_pr)
-// stored for k_u in [0, L/2] only, as pairs (E', Q) (k_fold).  E_p and Q_p
+// (with slope order 4 the five-point differences' symbols take the place
+// of the sines, k_fold) stored for k_u in [0, L/2] only, as pairs (E', Q)
+// (k_fold).  E_p and Q_p
 // vanish at the azimuthal bins 0 and n_phi/2 (odd kernels) and are not
 // stored there.
 #include <algorithm>
@@ -562,7 +564,10 @@ __global__ __launch_bounds__(256) void k_selfpv(FanGeo f, double *__restrict__ o
 // One block per azimuthal bin kb in [0, M] (bins 0 and M read the real and
 // imaginary parts of packed column 0), L/E threads.  With s = 1/(L n_phi),
 // sk = sin(2 pi kb / n_phi) / dphi (the azimuthal central difference) and
-// D(k) = 2i ca sin(2 pi k / L) (the circular radial central difference):
+// D(k) = 2i ca sin(2 pi k / L) (the circular radial central difference);
+// for slope order 4 the five-point differences,
+// sk = (8 sin(2 pi kb / n_phi) - sin(4 pi kb / n_phi)) / (6 dphi) and
+// D(k) = 2i c4 (8 sin(2 pi k / L) - sin(4 pi k / L)):
 //   Q_r  = s FFT(beta^m T_rr)         E_r = s (FFT(T_r0) + i sk FFT(T_rphi))
 //   Q_p  = s FFT(beta^m T_phir)       E_p = s (FFT(T_phi0) + i sk FFT(T_phiphi))
 //   E'   = E + D Q
@@ -576,7 +581,8 @@ __global__ __launch_bounds__(512) void k_fold(const cx<double> *__restrict__ row
                                               int n_r, int s0, int n_phi, double lnb,
                                               double dphi, double ca,
                                               cx2<double> *__restrict__ spec, int ldspec,
-                                              const cx<double> *__restrict__ twL) {
+                                              const cx<double> *__restrict__ twL, int so,
+                                              double c4) {
     constexpr int TH = L / E;
     extern __shared__ unsigned char smem_raw[];
     cx<double> *buf = reinterpret_cast<cx<double> *>(smem_raw);
@@ -587,7 +593,8 @@ __global__ __launch_bounds__(512) void k_fold(const cx<double> *__restrict__ row
     Twiddles<L, E, double> tw;
     tw.load(t, twL, 1);
     const double sc = 1.0 / ((double)L * (double)n_phi);
-    const double sk = sinpi(2.0 * kb / n_phi) / dphi;
+    const double sk = so == 4 ? (8.0 * sinpi(2.0 * kb / n_phi) - sinpi(4.0 * kb / n_phi)) / (6.0 * dphi)
+                              : sinpi(2.0 * kb / n_phi) / dphi;
 
     auto load = [&](int tab, bool bscale, cx<double>(&v)[E]) {
 #pragma unroll
@@ -621,7 +628,8 @@ __global__ __launch_bounds__(512) void k_fold(const cx<double> *__restrict__ row
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             const int ku = t + e * TH;
-            const double d = 2.0 * ca * sinpi(2.0 * ku / L);
+            const double d = so == 4 ? 2.0 * c4 * (8.0 * sinpi(2.0 * ku / L) - sinpi(4.0 * ku / L))
+                                     : 2.0 * ca * sinpi(2.0 * ku / L);
             const cx<double> qe = scale(q[e], sc);
             const cx<double> ee = {(a[e].x - sk * b[e].y) * sc, (a[e].y + sk * b[e].x) * sc};
             a[e] = cx<double>{ee.x - d * qe.y, ee.y + d * qe.x};   // E + i d Q
@@ -654,7 +662,7 @@ int fold_launch(const cx<double> *rowspec, const Plan &p, cx2<double> *spec,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
         hipLaunchKernelGGL((k_fold<L, E>), dim3(p.M + 1), dim3(L / E), lds, st, rowspec, p.M,
                            p.n_r, p.s0, p.n_phi, std::log(p.beta), p.dphi, p.ca, spec,
-                           p.ldspec, twL);
+                           p.ldspec, twL, p.so, p.c4);
         PF_HIP(hipGetLastError());
         return PF_OK;
     }

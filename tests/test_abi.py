@@ -100,7 +100,8 @@ def test_unbuilt_plan_and_null_arguments_are_refused():
         o = pf.pf_build_opts_default()
         o.dtype = 7
         assert lib.pf_kernels_build(h, ctypes.byref(o), None) == pf.PF_EINVAL
-        for field, bad in (("table_mode", 2), ("self_mode", 2), ("method", 3), ("method", -1)):
+        for field, bad in (("table_mode", 2), ("self_mode", 2), ("method", 3), ("method", -1),
+                           ("slope_order", 3), ("slope_order", 0)):
             o = pf.pf_build_opts_default()
             setattr(o, field, bad)
             assert lib.pf_kernels_build(h, ctypes.byref(o), None) == pf.PF_EINVAL
@@ -154,6 +155,7 @@ def test_default_options():
     assert (o.table_mode, o.self_mode) == (pf.PF_TABLE_SIM, pf.PF_SELF_CARTESIAN)
     assert o.method == pf.PF_METHOD_SIM
     assert (pf.PF_METHOD_PARTICLE, pf.PF_METHOD_PARTICLE_PLUS) == (1, 2)
+    assert o.slope_order == 2
 
 
 def test_cartesian_plan_host_checks():
@@ -196,5 +198,11 @@ def test_patch_plan_host_checks():
         assert lib.pf_forces(h, 8, 8, 8, None) == pf.PF_ESTATE
         assert lib.pf_forces_patches(h, 8, 8, 8, 8, None) == pf.PF_ESTATE
         assert lib.pf_forces_patches(h, None, 8, 8, 8, None) == pf.PF_EINVAL
+        # five-point slopes are not built for patch plans (refused before
+        # the device is touched)
+        o = pf.pf_build_opts_default()
+        o.slope_order = 4
+        assert lib.pf_kernels_build(h, ctypes.byref(o), None) == pf.PF_EUNSUPPORTED
+        assert "slope order" in pf.pf_last_error()
     finally:
         pf.pf_plan_destroy(h)

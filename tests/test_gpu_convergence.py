@@ -7,12 +7,15 @@ Checks, per component (F_r, F_phi) and norm (L1, L2, L-infinity, Eq. 47-49):
 * FP64: the error norms equal the FP64 oracle's (same tables by an
   independent quadrature, same sums) on the full 64^2 and 128^2 grids, and
   the forces match the oracle on sampled cells at 512^2;
-* FP64: the asymptotic orders (least squares of log E against log N over
-  N = 256, 512, 1024) agree with the SIM column of Table 1
-  (tests/golden/table1_sim_orders.txt) within 0.2, for sigma_D5 and
-  sigma_D2.  Table 1 fits N = 64 ... 1024; that fit is printed too: the
-  steps from 64 and 128 are pre-asymptotic here (the oracle gives the same
-  norms to 1e-12), so the printed orders are met from N = 256 on.  The step
+* FP64, Table 1's fit (least squares of log E against log N over
+  N = 64 ... 1024): with the slopes of Eq. 25 taken by five-point
+  differences (slope order 4) the orders agree with the SIM column of
+  Table 1 (tests/golden/table1_sim_orders.txt) within 0.15 for sigma_D5 and
+  sigma_D2.  With central differences (slope order 2, the default) sigma_D2
+  agrees within 0.15 too, while sigma_D5's orders come out 1.66-1.86
+  against the printed 1.9-2.0 (the oracle gives the same norms); those
+  measured orders are asserted as they are, within 0.05, beside the
+  asymptotic fit over N = 256 ... 1024 (within 0.2 of Table 1).  The step
   to 2048 x 4096 (du halved, dphi quartered) keeps at least second-order
   decay for sigma_D5;
 * FP32: the same norms as FP64 wherever the discretisation error is well
@@ -84,8 +87,8 @@ def _case(n_r, n_phi, n):
     return g, sig, ar, ap
 
 
-def _gpu_forces(n_r, n_phi, sig, dtype):
-    plan = pf.Plan(n_r, n_phi, 0.01, 1.0, dtype=dtype)
+def _gpu_forces(n_r, n_phi, sig, dtype, slope_order=2):
+    plan = pf.Plan(n_r, n_phi, 0.01, 1.0, dtype=dtype, slope_order=slope_order)
     try:
         s = torch.tensor(sig, dtype=plan.torch_dtype, device="cuda")
         fr, fp = plan.forces(s)
@@ -155,9 +158,30 @@ def test_table1_orders_sigma_d5_fp64(sweep_d5):
     full, fit, ref = _fitted_orders(e), _fitted_orders(e, FIT_FROM), _table1("D5")
     _say("sigma_D5 orders fitted 64-1024 %s, 256-1024 %s (Table 1: %s)"
          % (np.array2string(full, precision=2), np.array2string(fit, precision=2), ref))
+    # central-difference slopes: Table 1's window gives these orders (the
+    # five-point slopes of the next test meet the printed ones)
+    measured = np.array([1.83, 1.74, 1.66, 1.86, 1.80, 1.79])
+    assert np.all(np.abs(full - measured) < 0.05), (full, measured)
     assert np.all(np.abs(fit - ref) < 0.2), (fit, ref)
     # 1024^2 -> 2048 x 4096 halves du and quarters dphi
     assert np.all(o[4] > 1.75), o[4]
+
+
+@pytest.mark.parametrize("disk,n", [("D5", 5), ("D2", 2)])
+def test_table1_orders_five_point_slopes_fp64(disk, n):
+    # Table 1's window N = 64 ... 1024 with the slopes of Eq. 25 by
+    # five-point differences (slope order 4)
+    e = []
+    for N in TABLE1_N:
+        g, sig, ar, ap = _case(N, N, n)
+        fr, fp = _gpu_forces(N, N, sig, "f64", slope_order=4)
+        e.append(_norms(fr, fp, ar, ap))
+        _say("sigma_%s %4d slope order 4: %s" % (disk, N, np.array2string(e[-1], precision=3)))
+    e = np.array(e)
+    full, ref = _fitted_orders(e), _table1(disk)
+    _say("sigma_%s slope order 4: orders fitted 64-1024 %s (Table 1: %s)"
+         % (disk, np.array2string(full, precision=2), ref))
+    assert np.all(np.abs(full - ref) < 0.15), (full, ref)
 
 
 def test_fp32_tracks_fp64_sigma_d5(sweep_d5):
@@ -183,7 +207,7 @@ def test_table1_orders_sigma_d2_fp64():
     full, fit, ref = _fitted_orders(e), _fitted_orders(e, FIT_FROM), _table1("D2")
     _say("sigma_D2 orders fitted 64-1024 %s, 256-1024 %s (Table 1: %s)"
          % (np.array2string(full, precision=2), np.array2string(fit, precision=2), ref))
-    assert np.all(np.abs(fit - ref) < 0.2), (fit, ref)
+    assert np.all(np.abs(full - ref) < 0.15), (full, ref)
 
 
 @pytest.mark.parametrize("method", ["particle", "particle+"])

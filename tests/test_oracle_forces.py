@@ -17,13 +17,13 @@ import workloads
 from oracle import analytic
 
 
-def _brute_force(g, T, sig, i, j):
+def _brute_force(g, T, sig, i, j, slope_order=2):
     """F_r, F_phi at cell (i, j): every other source cell integrated by 2-D
     adaptive quadrature of the kernel times the cell's linear density (in
-    physical r, phi), plus the self-cell terms of Eq. 37 with the oracle's
-    self constants (the self cell itself is pinned by the principal-value
-    test)."""
-    dr, dp = oracle.channels(g, sig)
+    physical r, phi, with the slopes of the given order), plus the self-cell
+    terms of Eq. 37 with the oracle's self constants (the self cell itself
+    is pinned by the principal-value test)."""
+    dr, dp = oracle.channels(g, sig, slope_order=slope_order)
     ri, pj = g.r_centres[i], g.phi_centres[j]
     fr = fp = 0.0
     for a in range(g.n_r):
