@@ -42,6 +42,9 @@ HBM_PEAK_GBS = 8000.0
 # Counter summary of the dominant kernel (FETCH_SIZE / WRITE_SIZE per
 # dispatch with their copy-kernel calibration) and the sources it depends on.
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_cols_fwd_pf_f32_1024x2048_traffic.txt")
+# Kernel-trace summary of the same kernel (mean launch duration under the
+# profiler), for the cross-check of the event-timed roofline fraction.
+TRACE_FILE = os.path.join(ROOT, "profiles", "k_cols_fwd_pf_f32_1024x2048_kernel_trace.md")
 KERNEL_SOURCES = ("paper_1509_01450_amd/csrc/fft_core.hpp",
                   "paper_1509_01450_amd/csrc/pass_bodies.hpp",
                   "paper_1509_01450_amd/csrc/pf_passes.hip")
@@ -77,6 +80,81 @@ def measured_traffic(cols_shape):
         return float(kv["traffic_bytes_per_launch"])
     except (KeyError, ValueError):
         return None
+
+
+def profiled_mean_us(path, cols_shape):
+    """Mean duration (us) of the dominant kernel in a committed kernel-trace
+    summary, or None when its kernel sources or launch shape differ."""
+    try:
+        kv = {}
+        with open(path) as fh:
+            for line in fh:
+                if ":" in line and not line.startswith(("|", " ", "#")):
+                    k, v = line.split(":", 1)
+                    kv[k.strip()] = v.strip()
+        if kv.get("source_hash") != kernel_source_hash():
+            return None
+        if [int(x) for x in kv.get("cols_E_G", "").split(",")] != list(cols_shape):
+            return None
+        return float(kv["avg_us"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
+def cold_ms(torch, fn, n=20, flush_bytes=512 << 20):
+    """Mean duration of one call with the caches cold: before each call a
+    512 MiB buffer is written (twice the 256 MB last-level cache) on the same
+    stream, outside the events that bracket the call."""
+    scratch = torch.empty(flush_bytes // 4, dtype=torch.float32, device="cuda:0")
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(n)]
+    fn()
+    for i, (e0, e1) in enumerate(ev):
+        scratch.fill_(float(i))
+        e0.record()
+        fn()
+        e1.record()
+    torch.cuda.synchronize()
+    del scratch
+    return sum(e0.elapsed_time(e1) for e0, e1 in ev) / n
+
+
+def copy_GBs(torch, nbytes, reps=20):
+    """Device-to-device copy bandwidth (bytes read + written per second)."""
+    x = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        y.copy_(x)
+    e1.record()
+    torch.cuda.synchronize()
+    return 2.0 * nbytes * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+
+
+def cpu_model():
+    """CPU model name and the number of physical cores of the host."""
+    name, cores = "unknown", set()
+    try:
+        with open("/proc/cpuinfo") as fh:
+            phys = core = None
+            for line in fh:
+                k, _, v = line.partition(":")
+                k, v = k.strip(), v.strip()
+                if k == "model name":
+                    name = v
+                elif k == "physical id":
+                    phys = v
+                elif k == "core id":
+                    core = v
+                elif not k and phys is not None:
+                    cores.add((phys, core))
+                    phys = core = None
+    except OSError:
+        pass
+    return name, (len(cores) or os.cpu_count())
 
 
 def log(*a):
@@ -177,7 +255,9 @@ def cpu_baseline(sample_seconds=15.0):
     t0 = time.perf_counter()
     oracle.forward(g, T, sig, idx)
     dt = time.perf_counter() - t0
+    model, phys = cpu_model()
     return {"value": n / dt, "unit": "cells/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "cpu_model": model, "physical_cores": phys,
             "sample": "%d random output cells of the 1024x2048 workload (FP64 direct "
                       "O((N_r N_phi)^2) sums, %.1f s)" % (n, dt)}
 
@@ -229,9 +309,14 @@ def main():
     ms32 = time_calls(torch, f32, K, W)
     ms32_graph = time_graph(torch, f32, K, W)
     passes32 = pass_times(p32, s32)
+    ms32_cold = None
+    if not args.forward_only:   # profiled runs: warm launches only
+        log("fp32 forward, caches cold")
+        ms32_cold = cold_ms(torch, f32)
     L = p32_L = 2 * N_R
     bA, bB, bC = path_bytes(N_R, N_PHI, p32_L, 4)
     achieved = bB / (passes32[1] * 1e-3) / 1e9
+    prof_us = profiled_mean_us(TRACE_FILE, p32.schedule()[4:6])
 
     out["value"] = cells / (ms32 * 1e-3)
     out["ms_per_step"] = ms32
@@ -247,6 +332,19 @@ def main():
                            "two inverse u-FFTs; radial spectra prefetched to LDS)",
         "dominant_kernel_source_hash": kernel_source_hash(),
         "step_timing": "K back-to-back pf_forces calls between events on the launch stream",
+        "roofline_timing": "achieved = algorithmic bytes of one pass-B launch / its mean "
+                           "duration from HIP events on the launch stream around 100 "
+                           "back-to-back launches (warm caches)",
+        "roofline_frac_rocprof": (bB / (prof_us * 1e-6) / 1e9 / HBM_PEAK_GBS
+                                  if prof_us else None),
+        "roofline_rocprof_avg_us": prof_us,
+        "cold_ms_per_step_fp32": ms32_cold,
+        "cold_cells_per_s_fp32": cells / (ms32_cold * 1e-3) if ms32_cold else None,
+        "cold_path_frac_of_hbm_peak_fp32": ((bA + bB + bC) / (ms32_cold * 1e-3) / 1e9 / HBM_PEAK_GBS
+                                            if ms32_cold else None),
+        "cold_flush": "512 MiB written on the stream before each timed call, outside its events",
+        "path_frac_of_hbm_peak_fp32": (bA + bB + bC) / (ms32 * 1e-3) / 1e9 / HBM_PEAK_GBS,
+        "pass_sum_ms_fp32": sum(passes32),
         "graph_ms_per_step_fp32": ms32_graph,
         "graph_cells_per_s_fp32": cells / (ms32_graph * 1e-3),
         "schedule_fp32": sched(p32),
@@ -310,8 +408,13 @@ def main():
         msb = time_calls(torch, lambda: pf.forces_batched(plans, sig_b, outs), max(K // 4, 10), 5)
         msg = time_graph(torch, lambda: pf.forces_batched(plans, sig_b, outs), max(K // 4, 10), 5)
         bcells = sum(nr * nphi for nr, nphi in sizes)
+        # transform length along u: the power of two at or above 2 N_r
+        bbytes = sum(sum(path_bytes(nr, nphi, 1 << (2 * nr - 1).bit_length(), 4))
+                     for nr, nphi in sizes)
         batched = {"workload": "64 disks, N_r in {256..1024}, N_phi in {256..2048}, FP32",
                    "cells": bcells, "ms_per_call": msb, "cells_per_s": bcells / (msb * 1e-3),
+                   "path_bytes": bbytes,
+                   "path_frac_of_hbm_peak": bbytes / (msb * 1e-3) / 1e9 / HBM_PEAK_GBS,
                    "graph_ms_per_call": msg, "graph_cells_per_s": bcells / (msg * 1e-3),
                    "table_build_s": build_b}
 
@@ -391,6 +494,12 @@ def main():
 
 
 def finish(torch, out, args):
+    # measured copy bandwidth beside the 8 TB/s peak: 64 MiB (fits the
+    # last-level cache) and 1 GiB (does not); not in profiled runs
+    if not args.forward_only:
+        out["detail"]["copy_GBs"] = {"64MiB": copy_GBs(torch, 64 << 20),
+                                     "1GiB": copy_GBs(torch, 1 << 30, reps=5),
+                                     "peak": HBM_PEAK_GBS}
     if args.copy_reference:
         log("copy reference: 5 x 64 MiB device-to-device")
         x = torch.ones(16 * 1024 * 1024, device="cuda:0")

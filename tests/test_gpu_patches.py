@@ -131,12 +131,21 @@ def _case1(N, method, dtype="f64"):
 
 
 def test_fig4_case1_orders():
+    # Fig. 4 fits "the last four data points"; M_in is quoted at N_d = 8,
+    # the first grid, and read as a figure over N_d = 8 ... 256, so the
+    # fit is over N_d = 32 ... 256.  The fit over 64 ... 512 is printed too:
+    # the errors fall irregularly from grid to grid (the disk edge at
+    # r = alpha lands at a different fraction of a log cell each time), so
+    # the fitted order moves by up to 0.2 with the window.
     Ns = [32, 64, 128, 256, 512]
-    x = np.log(np.array(Ns[1:], dtype=float))
+    fit_of = lambda e, a, b: [-np.polyfit(np.log(np.array(Ns[a:b], dtype=float)),
+                                          np.log(e[a:b, q]), 1)[0] for q in (0, 2)]
     for method, name in (("particle", "particle"), ("yen12", "yen12")):
         e = np.array([_case1(N, method) for N in Ns])
-        fit = [-np.polyfit(x, np.log(e[1:, q]), 1)[0] for q in (0, 2)]
-        _say("case 1 %s L1 %s Linf %s  orders (last four) L1 %.2f Linf %.2f (Fig. 4: %.1f, %.1f)"
+        fit, late = fit_of(e, 0, 4), fit_of(e, 1, 5)
+        ref = (_fig4(name + " L1"), _fig4(name + " Linf"))
+        _say("case 1 %s L1 %s Linf %s  orders N_d 32-256: L1 %.2f Linf %.2f; 64-512: L1 %.2f "
+             "Linf %.2f (Fig. 4: %.1f, %.1f)"
              % (name, np.array2string(e[:, 0], precision=3), np.array2string(e[:, 2], precision=3),
-                fit[0], fit[1], _fig4(name + " L1"), _fig4(name + " Linf")))
-        assert abs(fit[0] - _fig4(name + " L1")) < 0.3 and abs(fit[1] - _fig4(name + " Linf")) < 0.3
+                fit[0], fit[1], late[0], late[1], ref[0], ref[1]))
+        assert abs(fit[0] - ref[0]) < 0.15 and abs(fit[1] - ref[1]) < 0.15
