@@ -74,6 +74,16 @@ def test_unbuilt_plan_and_null_arguments_are_refused():
         assert lib.pf_plan_set_schedule(h, ok8) == pf.PF_EINVAL   # not a whole wave
         ok8 = (ctypes.c_int * 8)(8, 2, 8, 2, 8, 16, 8, 16)  # 64 threads
         assert lib.pf_plan_set_schedule(h, ok8) == pf.PF_ESTATE
+        # whole waves but three columns per workgroup: the transpose's column
+        # sums combine lanes at distances G, 2G, ... (G a power of two)
+        h2 = pf.pf_plan_create(256, 32, 0.1, 10.0)   # L = 512: 64 threads per column at E = 8
+        try:
+            g3 = (ctypes.c_int * 8)(8, 2, 8, 2, 8, 3, 8, 3)
+            assert lib.pf_plan_set_schedule(h2, g3) == pf.PF_EINVAL
+            g4 = (ctypes.c_int * 8)(8, 2, 8, 2, 8, 4, 8, 4)
+            assert lib.pf_plan_set_schedule(h2, g4) == pf.PF_ESTATE
+        finally:
+            pf.pf_plan_destroy(h2)
         assert lib.pf_plan_set_schedule(h, None) == pf.PF_EINVAL
         assert lib.pf_plan_set_schedule(None, out8) == pf.PF_EINVAL
         ms3 = (ctypes.c_float * 3)()
