@@ -51,10 +51,16 @@ KERNEL_SOURCES = ("paper_1509_01450_amd/csrc/fft_core.hpp",
 
 
 def kernel_source_hash():
+    """Hash of the dominant kernel's sources with comments and white space
+    removed (a comment edit does not change the kernel)."""
+    import re
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, f)) as fh:
+            src = fh.read()
+        src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
+        src = re.sub(r"//[^\n]*", " ", src)
+        h.update(" ".join(src.split()).encode())
     return h.hexdigest()[:16]
 
 
@@ -388,6 +394,18 @@ def main():
     msb64 = time_calls(torch, lambda: p64.backward(gr64, gp64, gs64), max(K // 4, 10), W)
     passesb32 = pass_times(p32, gr32, gp32, backward=True)
 
+    # ---- five-point slopes (slope order 4), same workload ----------------------
+    log("slope order 4")
+    so4 = {}
+    for dt, sg in (("fp32", s32), ("fp64", s64)):
+        p4 = pf.Plan(N_R, N_PHI, R_MIN, R_MAX, dtype="f32" if dt == "fp32" else "f64",
+                     slope_order=4)
+        o4 = (torch.empty_like(sg), torch.empty_like(sg))
+        ms4 = time_calls(torch, lambda: p4.forces(sg, o4), max(K // 4, 10), W)
+        so4[dt] = {"ms_per_call": ms4, "cells_per_s": cells / (ms4 * 1e-3),
+                   "pass_ms": pass_times(p4, sg), "schedule": sched(p4)}
+        p4.close()
+
     # ---- batched ------------------------------------------------------------
     batched = None
     if not args.no_batched:
@@ -484,6 +502,7 @@ def main():
                      "fp64_ms": msb64, "fp64_cells_per_s": cells / (msb64 * 1e-3),
                      "fp32_pass_ms": passesb32},
         "batched": batched,
+        "slope_order_4": so4,
     })
     out["detail"]["table_build_s"]["fp64"] = build64
     if not args.no_cpu_baseline:

@@ -68,12 +68,14 @@ __device__ __forceinline__ void store_stream(cx2<T> *p, cx2<T> v) {
 // scales the grid by a power of two, 2^-e with e = floor(log2 max|sigma|):
 //   pass A notes max|sigma| (as float bits, which order like the
 //     magnitudes) in one of 64 words by atomic maximum, one atomic per
-//     wave; the words sit 128 bytes apart (word w at g[32 w]), each in a
-//     cache line of its own, so the atomics of the pass spread over 64
-//     lines instead of queueing on one;
+//     wave (the wave's maximum by lane exchanges first); the words sit 128
+//     bytes apart (word w at g[32 w]), each in a cache line of its own, so
+//     the atomics of the pass spread over 64 lines instead of queueing on
+//     one;
 //   pass B reads the 64 words, scales its column by 2^-e (after the first
 //     stage of the column transform, which sums at most 8 values), stores
-//     its output still scaled and writes e to g[32 * 64];
+//     its output still scaled, and its first workgroup writes e to
+//     g[32 * 64];
 //   pass C reads e, multiplies its outputs by 2^e, and clears the 64 words
 //     for the next call (pass B is done with them).
 // Every pass of a call runs after the previous one on the stream.  Between
@@ -89,10 +91,10 @@ __device__ __forceinline__ void store_stream(cx2<T> *p, cx2<T> v) {
 // (the layout constants kScale* are in fft_core.hpp)
 
 // The maximum of m over a whole wave (all 64 lanes active), uniform (in a
-// scalar register): row
-// shifts by 1, 2, 4 and 8 lanes (lanes before a row's start read 0, the
-// identity of the unsigned maximum) leave each row's maximum in its lane 15;
-// the row broadcasts of lanes 15 and 31 carry them on to lane 63.
+// scalar register): row shifts by 1, 2, 4 and 8 lanes (lanes before a row's
+// start read 0, the identity of the unsigned maximum) leave each row's
+// maximum in its lane 15; the row broadcasts of lanes 15 and 31 carry them
+// on to lane 63.
 __device__ __forceinline__ unsigned wave_max_u32(unsigned m) {
     m = max(m, (unsigned)__builtin_amdgcn_update_dpp(0, (int)m, 0x111, 0xf, 0xf, false));
     m = max(m, (unsigned)__builtin_amdgcn_update_dpp(0, (int)m, 0x112, 0xf, 0xf, false));
@@ -133,8 +135,8 @@ __device__ __forceinline__ GridScale<T> scale_of(int ex) {
 }
 
 // pass B: the first wave loads the 64 notes (lane i reads note i; issued
-// after the column's loads and before the spectrum prefetch) and reduces
-// them while the first stage of the column transform runs; e (clamped to
+// before the column's loads) and reduces them while the first stage of the
+// column transform runs; e (clamped to
 // [-100, 100], 0 within [-kScaleFree, kScaleFree]) reaches the other waves
 // through LDS across that stage's barrier, and the unit-0 workgroup writes
 // it to g[kScaleE] for pass C.

@@ -142,3 +142,30 @@ def test_batched_refuses_order4():
     finally:
         p2.close()
         p4.close()
+
+
+def test_order4_fp32_grid_scale():
+    # the five-point path runs under the same FP32 grid scale: 2^110 sigma
+    # gives 2^110 times the forces bit for bit (normal outputs), forward and
+    # transpose
+    shape = (37, 64, 0.01, 1.0)
+    g = oracle.Grid(*shape)
+    sig = workloads.random_field(g.shape, seed_k=44) + 2.0
+    plan = pf.Plan(*shape, dtype="f32", slope_order=4)
+    try:
+        s = _t(sig, plan)
+        f = 2.0 ** 110
+        fr1, fp1 = [x.clone() for x in plan.forces(s)]
+        fr, fp = plan.forces(s * f)
+        a = _t(workloads.random_field(g.shape, 45), plan)
+        b = _t(workloads.random_field(g.shape, 46), plan)
+        d1 = plan.backward(a, b).clone()
+        d = plan.backward(a * f, b * f)
+        torch.cuda.synchronize()
+        for x, x1 in ((fr, fr1), (fp, fp1), (d, d1)):
+            got = x.double().cpu().numpy()
+            want = x1.double().cpu().numpy() * f
+            assert np.isfinite(got).all()
+            assert np.array_equal(got[want != 0], want[want != 0])
+    finally:
+        plan.close()
