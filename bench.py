@@ -207,6 +207,22 @@ def time_calls(torch, fn, steps, warmup):
     return e0.elapsed_time(e1) / steps  # ms per call
 
 
+def median_call_ms(torch, fn, n=100):
+    """Median over n calls of one call bracketed by its own HIP events
+    (consecutive events on the launch stream; each interval holds one call
+    and one event record)."""
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(n + 1)]
+    for _ in range(10):
+        fn()
+    ev[0].record()
+    for i in range(n):
+        fn()
+        ev[i + 1].record()
+    torch.cuda.synchronize()
+    t = sorted(ev[i].elapsed_time(ev[i + 1]) for i in range(n))
+    return t[n // 2]
+
+
 def sched(plan):
     s = plan.schedule()
     return {"rows1_E_G": list(s[0:2]), "rows2_E_G": list(s[2:4]), "cols_E_G": list(s[4:6]),
@@ -262,8 +278,16 @@ def cpu_baseline(sample_seconds=15.0):
     oracle.forward(g, T, sig, idx)
     dt = time.perf_counter() - t0
     model, phys = cpu_model()
+    # the 128 x 128 grid in full (tables untimed)
+    g1 = oracle.Grid(128, 128, 0.1, 10.0)
+    T1 = oracle.tables(g1, 19)
+    s1 = workloads.single_disk_blobs(g1.r_centres, g1.phi_centres)
+    t0 = time.perf_counter()
+    oracle.forward(g1, T1, s1)
+    dt1 = time.perf_counter() - t0
     return {"value": n / dt, "unit": "cells/s", "cores": oracle.num_threads(), "kind": "oracle",
             "cpu_model": model, "physical_cores": phys,
+            "c1_128x128_full_grid": {"s": dt1, "cells_per_s": 128 * 128 / dt1},
             "sample": "%d random output cells of the 1024x2048 workload (FP64 direct "
                       "O((N_r N_phi)^2) sums, %.1f s)" % (n, dt)}
 
@@ -314,6 +338,7 @@ def main():
     f32 = lambda: p32.forces(s32, (fr32, fp32))
     ms32 = time_calls(torch, f32, K, W)
     ms32_graph = time_graph(torch, f32, K, W)
+    ms32_median = median_call_ms(torch, f32)
     passes32 = pass_times(p32, s32)
     ms32_cold = None
     if not args.forward_only:   # profiled runs: warm launches only
@@ -338,6 +363,8 @@ def main():
                            "two inverse u-FFTs; radial spectra prefetched to LDS)",
         "dominant_kernel_source_hash": kernel_source_hash(),
         "step_timing": "K back-to-back pf_forces calls between events on the launch stream",
+        "median_call_ms_fp32": ms32_median,
+        "median_call_timing": "median over 100 calls of one call between consecutive events",
         "roofline_timing": "achieved = algorithmic bytes of one pass-B launch / its mean "
                            "duration from HIP events on the launch stream around 100 "
                            "back-to-back launches (warm caches)",
@@ -393,6 +420,18 @@ def main():
     gs64 = torch.empty_like(gr64)
     msb64 = time_calls(torch, lambda: p64.backward(gr64, gp64, gs64), max(K // 4, 10), W)
     passesb32 = pass_times(p32, gr32, gp32, backward=True)
+
+    # ---- C1: 128 x 128 on [0.1, 10], FP64 (launch-bound; no roofline claim) ----
+    log("128 x 128 fp64")
+    c1 = pf.Plan(128, 128, 0.1, 10.0, dtype="f64")
+    rc1, _, _ = c1.geometry()
+    ph1 = (np.arange(128) + 0.5) * (2 * np.pi / 128)
+    s1 = torch.tensor(workloads.single_disk_blobs(rc1, ph1), dtype=torch.float64, device=dev)
+    o1 = (torch.empty_like(s1), torch.empty_like(s1))
+    ms_c1 = time_calls(torch, lambda: c1.forces(s1, o1), K, W)
+    c1.close()
+    c1_detail = {"workload": "128 x 128, r in [0.1, 10], (1+r^2)^-3/2 + 8 blobs, FP64",
+                 "ms_per_call": ms_c1, "cells_per_s": 128 * 128 / (ms_c1 * 1e-3)}
 
     # ---- five-point slopes (slope order 4), same workload ----------------------
     log("slope order 4")
@@ -503,6 +542,7 @@ def main():
                      "fp32_pass_ms": passesb32},
         "batched": batched,
         "slope_order_4": so4,
+        "c1_128x128_fp64": c1_detail,
     })
     out["detail"]["table_build_s"]["fp64"] = build64
     if not args.no_cpu_baseline:
@@ -516,9 +556,12 @@ def finish(torch, out, args):
     # measured copy bandwidth beside the 8 TB/s peak: 64 MiB (fits the
     # last-level cache) and 1 GiB (does not); not in profiled runs
     if not args.forward_only:
-        out["detail"]["copy_GBs"] = {"64MiB": copy_GBs(torch, 64 << 20),
-                                     "1GiB": copy_GBs(torch, 1 << 30, reps=5),
-                                     "peak": HBM_PEAK_GBS}
+        cp = {"64MiB": copy_GBs(torch, 64 << 20), "1GiB": copy_GBs(torch, 1 << 30, reps=5),
+              "peak": HBM_PEAK_GBS}
+        out["detail"]["copy_GBs"] = cp
+        # the path and pass B against what a plain copy reaches on this machine
+        out["detail"]["path_frac_of_copy_fp32"] = out["detail"]["path_GBs_fp32"] / cp["1GiB"]
+        out["detail"]["pass_B_frac_of_copy_fp32"] = out["roofline"]["achieved"] / cp["1GiB"]
     if args.copy_reference:
         log("copy reference: 5 x 64 MiB device-to-device")
         x = torch.ones(16 * 1024 * 1024, device="cuda:0")

@@ -873,15 +873,19 @@ __device__ __forceinline__ void body_cols_fwd(int unit, int G, cx<T> *__restrict
     const cx2<T> *const gp = sazi + (size_t)cl * ldspec;
     cx<T> y0[E], y1[E];
     if constexpr (SPLIT) {
-        // transform of the four-row slope correction at the thread's points,
-        // kept for both sweeps
+        // transform of the slope correction at the thread's points, kept for
+        // both sweeps with four rows; with eight rows (its phasors take twice
+        // the registers) formed again in each sweep instead
+        constexpr bool KEEPF = SO == 2;
         cx<T> f[E];
+        if constexpr (KEEPF)
 #pragma unroll
-        for (int e = 0; e < E; ++e) f[e] = slope_fix_at<T, E>(ph, root_ne<T, L, E>(twL, n_r, e), e);
+            for (int e = 0; e < E; ++e)
+                f[e] = slope_fix_at<T, E>(ph, root_ne<T, L, E>(twL, n_r, e), e);
 
         // radial channel: y0 = E'_r X + Q_r B
         if constexpr (PF) prefetch_wait();
-        mac_fwd<T, L, E, false, PF, true>(y0, v, f, ph, twL, n_r, sl, gr, t);
+        mac_fwd<T, L, E, false, PF, KEEPF>(y0, v, f, ph, twL, n_r, sl, gr, t);
         if (packed) {
             // column 0 holds bins 0 and M packed as c_0 + i c_M: its radial
             // channel is y_0 + i y_M, from the bin-0 radial pairs (at the
@@ -928,7 +932,7 @@ __device__ __forceinline__ void body_cols_fwd(int unit, int G, cx<T> *__restrict
         // azimuthal channel: y1 = E'_p X + Q_p B (zero for column 0: the
         // azimuthal spectra vanish at bins 0 and M)
         if constexpr (PF) prefetch_wait();
-        mac_fwd<T, L, E, true, PF, true>(y1, v, f, ph, twL, n_r, sl, gp, t);
+        mac_fwd<T, L, E, true, PF, KEEPF>(y1, v, f, ph, twL, n_r, sl, gp, t);
 #pragma unroll
         for (int e = 0; e < E; ++e) y1[e] = is0 ? cx<T>{T(0), T(0)} : y1[e];
         fft_inv<L, E, T>(y1, t, lds, tw);
@@ -938,6 +942,8 @@ __device__ __forceinline__ void body_cols_fwd(int unit, int G, cx<T> *__restrict
             for (int e = 0; e < E; ++e) lds.st_split(lds_pad(t), e * TH, v[e]);
             lds_barrier();
         }
+        // ph0 serves every column (ph is not kept beside it): the packed
+        // column's lanes replace it and phM by the two bins' phasors
         auto ph0 = ph, phM = ph;
         if (is0) {   // bins 0 and M of the packed column: real coefficients each
             const auto a = slope_fix(scaled(slope_rows<T, SO>(S, H, n_r, 0), sc.dn), kf);
@@ -974,7 +980,7 @@ __device__ __forceinline__ void body_cols_fwd(int unit, int G, cx<T> *__restrict
                     y0[e] = cx<T>{ya.x - yb.y, ya.y + yb.x};   // ya + i yb
                     y1[e] = cx<T>{T(0), T(0)};
                 } else {
-                    const cx<T> f = slope_fix_at<T, E>(ph, rne, e);
+                    const cx<T> f = slope_fix_at<T, E>(ph0, rne, e);
                     y0[e] = spec_mac<T, E, false, false>(
                         spec_mul<T, E, false, false>(pr[j].a, v[e], e, t0), pr[j].b, f, e, t0);
                     y1[e] = spec_mac<T, E, true, false>(

@@ -140,10 +140,12 @@ int tune_t(Plan &p, hipStream_t st) {
                              std::to_string(p.n_r);
     const std::string krow2 = pre + "rows2|M=" + std::to_string(p.M) + "|rows=" +
                               std::to_string(p.n_r);
+    // the column kernels of slope order 4 are other kernels: their own keys
+    const std::string so = p.so == 4 ? "|so=4" : "";
     const std::string kcol = pre + "cols|L=" + std::to_string(p.L) + "|H=" + std::to_string(p.H) +
-                             "|n_r=" + std::to_string(p.n_r);
+                             "|n_r=" + std::to_string(p.n_r) + so;
     const std::string kadj = pre + "adj|L=" + std::to_string(p.L) + "|H=" + std::to_string(p.H) +
-                             "|n_r=" + std::to_string(p.n_r);
+                             "|n_r=" + std::to_string(p.n_r) + so;
     {
         std::lock_guard<std::mutex> g(g_tune_mu);
         load_cache();

@@ -131,6 +131,11 @@ def test_force_matching_gradient_central_differences():
 
 
 def test_autograd_gradcheck_small():
+    # the map is linear, so central differences carry no truncation error
+    # whatever the step; a step of 1e-3 keeps their rounding (ulp(F) / step)
+    # far below atol also for the Jacobian entries that vanish (with 1e-6 it
+    # reached ~1e-9 on some draws of the input)
     plan = pf.Plan(6, 8, 0.5, 2.0, dtype="f64")
-    s = torch.randn(6, 8, dtype=torch.float64, device="cuda", requires_grad=True)
-    assert torch.autograd.gradcheck(lambda x: pf.forces(x, plan), (s,), eps=1e-6, atol=1e-9)
+    gen = torch.Generator().manual_seed(1509)
+    s = torch.randn(6, 8, dtype=torch.float64, generator=gen).cuda().requires_grad_(True)
+    assert torch.autograd.gradcheck(lambda x: pf.forces(x, plan), (s,), eps=1e-3, atol=1e-9)
