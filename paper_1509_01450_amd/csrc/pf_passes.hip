@@ -67,20 +67,20 @@ __global__ __launch_bounds__(512) void k_cols_fwd(const cx<T> *__restrict__ S,
 // compiler sees that the transform's LDS accesses cannot touch the
 // prefetch region; with one dynamic LDS array it waits for the prefetch
 // before the first exchange).
-template <typename T, int L, int E, int G>
+template <typename T, int L, int E, int G, int SO = 2>
 __global__ __launch_bounds__(512) void k_cols_fwd_pf(const cx<T> *__restrict__ S,
                                                      cx2<T> *__restrict__ Z,
                                                      const cx2<T> *__restrict__ spec, int H,
                                                      int n_r, int n_out, int ldspec, T ca, T c0,
                                                      T cn, const cx<T> *__restrict__ twL,
                                                      int per_xcd, int n_groups,
-                                                     unsigned *__restrict__ gscale) {
+                                                     unsigned *__restrict__ gscale, T c4) {
     __shared__ cx<T> fbuf[G * padded_len(L)];
     __shared__ cx2<T> spl[G * spec_prefetch_len<L, E>()];
     const int grp = xcd_group(blockIdx.x, per_xcd);
     if (grp >= n_groups) return;  // whole workgroup leaves together
-    body_cols_fwd<T, L, E, true>(grp, G, fbuf, S, Z, spec, H, n_r, n_out, ldspec, ca, c0, cn,
-                                 twL, spl, gscale);
+    body_cols_fwd<T, L, E, true, SO>(grp, G, fbuf, S, Z, spec, H, n_r, n_out, ldspec, ca, c0,
+                                     cn, twL, spl, gscale, c4);
 }
 
 template <typename T, int L, int E, int SO = 2>
@@ -101,20 +101,20 @@ __global__ __launch_bounds__(512) void k_cols_adj(const cx2<T> *__restrict__ V,
 
 // Transpose column pass with G fixed at compile time and the radial
 // spectrum prefetch in a static LDS array of its own (as k_cols_fwd_pf).
-template <typename T, int L, int E, int G>
+template <typename T, int L, int E, int G, int SO = 2>
 __global__ __launch_bounds__(512) void k_cols_adj_pf(const cx2<T> *__restrict__ V,
                                                      cx<T> *__restrict__ D,
                                                      const cx2<T> *__restrict__ spec, int H,
                                                      int n_r, int ldspec, T ca, T c0, T cn,
                                                      const cx<T> *__restrict__ twL, int per_xcd,
                                                      int n_groups,
-                                                     unsigned *__restrict__ gscale) {
+                                                     unsigned *__restrict__ gscale, T c4) {
     __shared__ cx<T> fbuf[G * padded_len(L)];
     __shared__ cx2<T> spl[G * spec_prefetch_len<L, E>()];
     const int grp = xcd_group(blockIdx.x, per_xcd);
     if (grp >= n_groups) return;  // whole workgroup leaves together
-    body_cols_adj<T, L, E, true>(grp, G, fbuf, V, D, spec, H, n_r, ldspec, ca, c0, cn, twL, spl,
-                                 gscale);
+    body_cols_adj<T, L, E, true, SO>(grp, G, fbuf, V, D, spec, H, n_r, ldspec, ca, c0, cn, twL,
+                                     spl, gscale, c4);
 }
 
 // ---------------------------------------------------------------------------
@@ -191,26 +191,35 @@ constexpr bool cols_pf_fits() {
                                      (size_t)144 * 1024;
 }
 
-template <typename T, int N, int E, int G>
+// Slope order 4 has static-LDS instances for the points per thread its
+// precision tunes to (FP32 E = 16, FP64 E = 8) only; other shapes take the
+// dynamic-LDS kernels.
+template <typename T, int E, int SO>
+constexpr bool so_pf_instance() {
+    return SO == 2 || (sizeof(T) == 4 ? E == 16 : E == 8);
+}
+
+template <typename T, int N, int E, int G, int SO>
 bool launch_cols_pf(dim3 grid, hipStream_t st, const cx<T> *S, cx2<T> *Z, const cx2<T> *spec,
-                    const Plan &p, T ca, T c0, T cn, const cx<T> *tw, int per_xcd,
+                    const Plan &p, T ca, T c0, T cn, T c4, const cx<T> *tw, int per_xcd,
                     int n_groups, unsigned *g) {
-    if constexpr (cols_pf_fits<T, N, E, G>()) {
-        hipLaunchKernelGGL((k_cols_fwd_pf<T, N, E, G>), grid, dim3(G * (N / E)), 0, st, S, Z,
-                           spec, p.H, p.n_in, p.n_r, p.ldspec, ca, c0, cn, tw, per_xcd, n_groups,
-                           g);
+    if constexpr (cols_pf_fits<T, N, E, G>() && so_pf_instance<T, E, SO>()) {
+        hipLaunchKernelGGL((k_cols_fwd_pf<T, N, E, G, SO>), grid, dim3(G * (N / E)), 0, st, S,
+                           Z, spec, p.H, p.n_in, p.n_r, p.ldspec, ca, c0, cn, tw, per_xcd,
+                           n_groups, g, c4);
         return true;
     }
     return false;
 }
 
-template <typename T, int N, int E, int G>
+template <typename T, int N, int E, int G, int SO>
 bool launch_cols_adj_pf(dim3 grid, hipStream_t st, const cx2<T> *V, cx<T> *D,
-                        const cx2<T> *spec, const Plan &p, T ca, T c0, T cn, const cx<T> *tw,
-                        int per_xcd, int n_groups, unsigned *g) {
-    if constexpr (cols_pf_fits<T, N, E, G>()) {
-        hipLaunchKernelGGL((k_cols_adj_pf<T, N, E, G>), grid, dim3(G * (N / E)), 0, st, V, D,
-                           spec, p.H, p.n_r, p.ldspec, ca, c0, cn, tw, per_xcd, n_groups, g);
+                        const cx2<T> *spec, const Plan &p, T ca, T c0, T cn, T c4,
+                        const cx<T> *tw, int per_xcd, int n_groups, unsigned *g) {
+    if constexpr (cols_pf_fits<T, N, E, G>() && so_pf_instance<T, E, SO>()) {
+        hipLaunchKernelGGL((k_cols_adj_pf<T, N, E, G, SO>), grid, dim3(G * (N / E)), 0, st, V,
+                           D, spec, p.H, p.n_r, p.ldspec, ca, c0, cn, tw, per_xcd, n_groups, g,
+                           c4);
         return true;
     }
     return false;
@@ -255,6 +264,12 @@ struct Disp {
     template <int N, int E, bool ADJ>
     static int cols(const Plan &p, const cx<T> *a, cx<T> *o, const cx<T> *spec, const cx<T> *tw,
                     int G, hipStream_t st, unsigned *g) {
+        return p.so == 4 ? cols_so<N, E, ADJ, 4>(p, a, o, spec, tw, G, st, g)
+                         : cols_so<N, E, ADJ, 2>(p, a, o, spec, tw, G, st, g);
+    }
+    template <int N, int E, bool ADJ, int SO>
+    static int cols_so(const Plan &p, const cx<T> *a, cx<T> *o, const cx<T> *spec,
+                       const cx<T> *tw, int G, hipStream_t st, unsigned *g) {
         if constexpr (E <= N) {
             constexpr int TH = N / E;
             const int n_groups = (p.H + G - 1) / G;
@@ -264,76 +279,56 @@ struct Disp {
             const size_t lds = cols_lds_bytes(N, E, G, sizeof(T) == 8, !ADJ && sizeof(T) == 4);
             const T ca = T(p.ca), c0 = T(p.c0), cn = T(p.cn), c4 = T(p.c4);
             const cx2<T> *sp = reinterpret_cast<const cx2<T> *>(spec);
-            if (p.so == 4) {   // five-point slopes: the dynamic-LDS kernels only
-                if (ADJ) {
-                    int rc = allow_lds(k_cols_adj<T, N, E, 4>, lds);
-                    if (rc) return rc;
-                    hipLaunchKernelGGL((k_cols_adj<T, N, E, 4>), dim3(blocks), dim3(G * TH), lds,
-                                       st, reinterpret_cast<const cx2<T> *>(a), o, sp, p.H,
-                                       p.n_r, p.ldspec, ca, c0, cn, tw, per_xcd, n_groups, g, c4);
-                } else {
-                    int rc = allow_lds(k_cols_fwd<T, N, E, 4>, lds);
-                    if (rc) return rc;
-                    hipLaunchKernelGGL((k_cols_fwd<T, N, E, 4>), dim3(blocks), dim3(G * TH), lds,
-                                       st, a, reinterpret_cast<cx2<T> *>(o), sp, p.H, p.n_in,
-                                       p.n_r, p.ldspec, ca, c0, cn, tw, per_xcd, n_groups, g, c4);
+            if constexpr (TH >= 64) {
+                // the prefetch's 32-bit offsets cover a spectrum half
+                if ((size_t)p.H * p.ldspec * sizeof(cx2<T>) >= ((size_t)1 << 31)) {
+                    set_error("spectra too large for the column pass prefetch");
+                    return PF_EUNSUPPORTED;
                 }
-                PF_HIP(hipGetLastError());
-                return PF_OK;
+                const dim3 grid(blocks);
+                bool done;
+                if (ADJ) {
+                    const cx2<T> *v = reinterpret_cast<const cx2<T> *>(a);
+                    done = G == 1   ? launch_cols_adj_pf<T, N, E, 1, SO>(grid, st, v, o, sp, p, ca,
+                                                                         c0, cn, c4, tw, per_xcd,
+                                                                         n_groups, g)
+                           : G == 2 ? launch_cols_adj_pf<T, N, E, 2, SO>(grid, st, v, o, sp, p, ca,
+                                                                         c0, cn, c4, tw, per_xcd,
+                                                                         n_groups, g)
+                           : G == 4 ? launch_cols_adj_pf<T, N, E, 4, SO>(grid, st, v, o, sp, p, ca,
+                                                                         c0, cn, c4, tw, per_xcd,
+                                                                         n_groups, g)
+                                    : false;
+                } else {
+                    cx2<T> *z = reinterpret_cast<cx2<T> *>(o);
+                    done = G == 1   ? launch_cols_pf<T, N, E, 1, SO>(grid, st, a, z, sp, p, ca, c0,
+                                                                     cn, c4, tw, per_xcd, n_groups,
+                                                                     g)
+                           : G == 2 ? launch_cols_pf<T, N, E, 2, SO>(grid, st, a, z, sp, p, ca, c0,
+                                                                     cn, c4, tw, per_xcd, n_groups,
+                                                                     g)
+                           : G == 4 ? launch_cols_pf<T, N, E, 4, SO>(grid, st, a, z, sp, p, ca, c0,
+                                                                     cn, c4, tw, per_xcd, n_groups,
+                                                                     g)
+                                    : false;
+                }
+                if (done) {
+                    PF_HIP(hipGetLastError());
+                    return PF_OK;
+                }
             }
             if (ADJ) {
-                if constexpr (TH >= 64) {
-                    if ((size_t)p.H * p.ldspec * sizeof(cx2<T>) >= ((size_t)1 << 31)) {
-                        set_error("spectra too large for the column pass prefetch");
-                        return PF_EUNSUPPORTED;
-                    }
-                    const dim3 grid(blocks);
-                    const cx2<T> *v = reinterpret_cast<const cx2<T> *>(a);
-                    const bool done =
-                        G == 1   ? launch_cols_adj_pf<T, N, E, 1>(grid, st, v, o, sp, p, ca, c0,
-                                                                  cn, tw, per_xcd, n_groups, g)
-                        : G == 2 ? launch_cols_adj_pf<T, N, E, 2>(grid, st, v, o, sp, p, ca, c0,
-                                                                  cn, tw, per_xcd, n_groups, g)
-                        : G == 4 ? launch_cols_adj_pf<T, N, E, 4>(grid, st, v, o, sp, p, ca, c0,
-                                                                  cn, tw, per_xcd, n_groups, g)
-                                 : false;
-                    if (done) {
-                        PF_HIP(hipGetLastError());
-                        return PF_OK;
-                    }
-                }
-                int rc = allow_lds(k_cols_adj<T, N, E>, lds);
+                int rc = allow_lds(k_cols_adj<T, N, E, SO>, lds);
                 if (rc) return rc;
-                hipLaunchKernelGGL((k_cols_adj<T, N, E>), dim3(blocks), dim3(G * TH), lds, st,
+                hipLaunchKernelGGL((k_cols_adj<T, N, E, SO>), dim3(blocks), dim3(G * TH), lds, st,
                                    reinterpret_cast<const cx2<T> *>(a), o, sp, p.H, p.n_r,
-                                   p.ldspec, ca, c0, cn, tw, per_xcd, n_groups, g, T(0));
+                                   p.ldspec, ca, c0, cn, tw, per_xcd, n_groups, g, c4);
             } else {
-                if constexpr (TH >= 64) {
-                    // the prefetch's 32-bit offsets cover the radial half
-                    if ((size_t)p.H * p.ldspec * sizeof(cx2<T>) >= ((size_t)1 << 31)) {
-                        set_error("spectra too large for the column pass prefetch");
-                        return PF_EUNSUPPORTED;
-                    }
-                    const dim3 grid(blocks);
-                    cx2<T> *z = reinterpret_cast<cx2<T> *>(o);
-                    const bool done =
-                        G == 1   ? launch_cols_pf<T, N, E, 1>(grid, st, a, z, sp, p, ca, c0, cn,
-                                                              tw, per_xcd, n_groups, g)
-                        : G == 2 ? launch_cols_pf<T, N, E, 2>(grid, st, a, z, sp, p, ca, c0, cn,
-                                                              tw, per_xcd, n_groups, g)
-                        : G == 4 ? launch_cols_pf<T, N, E, 4>(grid, st, a, z, sp, p, ca, c0, cn,
-                                                              tw, per_xcd, n_groups, g)
-                                 : false;
-                    if (done) {
-                        PF_HIP(hipGetLastError());
-                        return PF_OK;
-                    }
-                }
-                int rc = allow_lds(k_cols_fwd<T, N, E>, lds);
+                int rc = allow_lds(k_cols_fwd<T, N, E, SO>, lds);
                 if (rc) return rc;
-                hipLaunchKernelGGL((k_cols_fwd<T, N, E>), dim3(blocks), dim3(G * TH), lds, st, a,
-                                   reinterpret_cast<cx2<T> *>(o), sp, p.H, p.n_in, p.n_r,
-                                   p.ldspec, ca, c0, cn, tw, per_xcd, n_groups, g, T(0));
+                hipLaunchKernelGGL((k_cols_fwd<T, N, E, SO>), dim3(blocks), dim3(G * TH), lds, st,
+                                   a, reinterpret_cast<cx2<T> *>(o), sp, p.H, p.n_in, p.n_r,
+                                   p.ldspec, ca, c0, cn, tw, per_xcd, n_groups, g, c4);
             }
             PF_HIP(hipGetLastError());
             return PF_OK;
