@@ -205,10 +205,12 @@ int pf_forces_backward(pf_plan plan, const void *g_fr, const void *g_fphi,
 
 /* Forward map for n independent disks, each with its own built plan (all of
  * one precision, sizes may differ), on `stream`: the disks are grouped per
- * pass into classes of equal transform length and tuned launch shape (each
- * plan's pf_plan_schedule), and each class is one launch covering every
- * disk in it -- pass A of all disks, then pass B, then pass C.  The results
- * equal pf_forces on each plan bit for bit.  Arrays sigma[k], f_r[k],
+ * pass into classes of equal transform length and tuned points per thread
+ * (from each plan's pf_plan_schedule), and each class is one launch covering
+ * every disk in it, at the tuned shape of its disk with the most rows or
+ * columns -- pass A of all disks, then pass B, then pass C.  The results
+ * equal pf_forces on each plan bit for bit (the rows or columns per
+ * workgroup change no arithmetic).  Arrays sigma[k], f_r[k],
  * f_phi[k] follow plan[k]'s layout.  Sizes: 128 <= n_phi <= 4096 and
  * 33 <= n_r <= 2048; other plans give PF_EUNSUPPORTED.  A plan may appear
  * once per batch (PF_EINVAL otherwise).  Plans of a batch share internal

@@ -1,18 +1,20 @@
 // pf_batched.hip -- the many-disk forward map: grouped launches over all disks
-// of a batch, each disk at the launch shapes tuned for its sizes.
+// of a batch, each disk at the points per thread tuned for its sizes.
 //
 // The disks of a batch (sizes may differ, one precision) are grouped per
-// pass into classes of equal transform length and launch shape: for pass A
-// the one-channel row shape of the disk's schedule, for pass C the
-// two-channel one, for pass B the column shape.  Each class is one launch
-// whose workgroups cover every unit (G rows or G columns) of every disk of
-// the class; a workgroup finds its disk by a binary search over the class's
+// pass into classes of equal transform length and points per thread (E):
+// for pass A those of the one-channel row shape of the disk's schedule, for
+// pass C the two-channel one, for pass B the column shape.  Each class is
+// one launch, at the tuned shape of its disk with the most units, whose
+// workgroups cover every unit (G rows or G columns) of every disk of the
+// class; a workgroup finds its disk by a binary search over the class's
 // entry table (disk, first block), then runs the pass body of the
-// single-disk kernels at that shape.  Pass A of every class, then pass B,
-// then pass C: the launch boundaries order the passes.  For the 64-disk
-// workload (N_r in {256 ... 1024}, N_phi in {256 ... 2048}) that is up to
-// four row classes and three column classes per pass instead of one kernel
-// holding every size at one register budget.
+// single-disk kernels at that shape.  The units per workgroup change no
+// arithmetic, so every disk's forces are bit for bit those of its own plan.
+// Pass A of every class, then pass B, then pass C: the launch boundaries
+// order the passes.  For the 64-disk workload (N_r in {256 ... 1024}, N_phi
+// in {256 ... 2048}) that is 15 launches (23 when the classes also split by
+// tuned G) instead of one kernel holding every size at one register budget.
 //
 // The tables (one descriptor per disk and the three entry tables) go to the
 // device through small upload kernels that take the bytes as kernel
@@ -183,8 +185,13 @@ Shape pass_shape(const Plan &p, int pass) {
 
 // The tables of one batch from the plans' tuned schedules: for each pass q,
 // the entries ent[q n ... q n + n - 1] ordered by class (transform length,
-// then shape), and the classes, cls[0 ... *n_cls - 1].  order[n] is working
-// space.  Allocates nothing (an insertion sort: batches are small).
+// then points per thread), and the classes, cls[0 ... *n_cls - 1].  A class
+// runs its disks with the tuned shape of its disk with the most units (rows
+// or columns): the number of units per workgroup (G) changes no arithmetic
+// of these forward passes, the points per thread (E) do, so disks of one
+// length with the same E share a launch and every disk's result stays bit
+// for bit that of its own plan.  order[n] is working space.  Allocates
+// nothing (an insertion sort: batches are small).
 void make_layout(const Plan *const *plans, int n, GEntry *ent, GClass *cls, int *n_cls,
                  int *order) {
     int nc = 0;
@@ -192,8 +199,9 @@ void make_layout(const Plan *const *plans, int n, GEntry *ent, GClass *cls, int 
         auto key = [&](int k) {
             const Shape s = pass_shape(*plans[k], q);
             const int len = q == 1 ? plans[k]->L : plans[k]->M;
-            return std::make_tuple(len, s.E, s.G, k);
+            return std::make_tuple(len, s.E, 0, k);
         };
+        auto units = [&](int k) { return q == 1 ? plans[k]->H : plans[k]->n_r; };
         for (int k = 0; k < n; ++k) {
             int j = k;
             while (j > 0 && key(k) < key(order[j - 1])) {
@@ -213,7 +221,10 @@ void make_layout(const Plan *const *plans, int n, GEntry *ent, GClass *cls, int 
             GClass c;
             c.pass = q;
             c.n = q == 1 ? plans[order[i]]->L : plans[order[i]]->M;
-            c.s = pass_shape(*plans[order[i]], q);
+            int big = order[i];
+            for (int m = i; m < n && same(order[m], order[i]); ++m)
+                if (units(order[m]) > units(big)) big = order[m];
+            c.s = pass_shape(*plans[big], q);
             c.e0 = q * n + i;
             int blocks = 0;
             while (j < n && same(order[j], order[i])) {
