@@ -163,8 +163,9 @@ pf_plan pf_plan_create(int n_r, int n_phi, double r_min, double r_max);
  * (no azimuthal offset between the patches).  Build with pf_kernels_build;
  * pf_forces takes sigma [n_src][n_phi] and writes f_r, f_phi
  * [n_dst][n_phi] (no wedges), pf_forces_patches also the wedge densities.
- * The transpose, the batched path and the autotuner are for single-grid
- * plans (PF_EUNSUPPORTED).  Sizes: 4 <= n_src <= 4096,
+ * The transpose takes patch plans without wedges (pf_forces_backward); the
+ * batched path and the autotuner are for single-grid plans
+ * (PF_EUNSUPPORTED).  Sizes: 4 <= n_src <= 4096,
  * |src_row0| <= 65536, n_dst and n_phi as for pf_plan_create.             */
 pf_plan pf_plan_create_patches(int n_src, int src_row0, int n_dst, int n_phi, double r_min,
                                double r_max, int wedges);
@@ -199,7 +200,10 @@ int pf_forces_patches(pf_plan plan, const void *sigma_src, const void *sigma_wed
 /* Transpose of the forward map: g_sigma = A^T [g_fr; g_fphi], i.e. the
  * gradient of any scalar loss L(F_r, F_phi) with respect to sigma, given
  * dL/dF_r = g_fr and dL/dF_phi = g_fphi.  Overwrites g_sigma.  Not in the
- * paper: it is the exact transpose of the linear map Eq. 26-29.  Async.    */
+ * paper: it is the exact transpose of the linear map Eq. 26-29.  Async.
+ * Patch plans without origin wedges: g_fr, g_fphi [n_dst][n_phi] on the
+ * destination patch, g_sigma [n_src][n_phi] on the source patch; plans with
+ * wedges give PF_EUNSUPPORTED (the wedges' transpose is not built).        */
 int pf_forces_backward(pf_plan plan, const void *g_fr, const void *g_fphi,
                        void *g_sigma, void *stream);
 

@@ -64,6 +64,7 @@ def _load():
     lib.or_patch_tables.argtypes = [i, i, i, i, d, d, i, i, P, P]
     lib.or_wedge_tables.argtypes = [i, i, d, d, i, i, P]
     lib.or_patch_forward.argtypes = [i, i, i, i, d, d, P, P, P, P, P, i64, P, P]
+    lib.or_patch_adjoint.argtypes = [i, i, i, i, d, d, P, P, P, P, i64, P]
     lib.or_patch_particle.argtypes = [i, i, i, i, d, d, i, P, P, P, P, i64, P, P]
     lib.or_cart_tables.argtypes = [i, i, d, d, i, P]
     lib.or_cart_slopes.argtypes = [i, i, d, d, P, P, P]
@@ -72,7 +73,7 @@ def _load():
               "or_table_entry", "or_tables", "or_channels", "or_forward",
               "or_adjoint", "or_forward_particle", "or_channels_o", "or_forward_o",
               "or_adjoint_o", "or_forward_particle_o", "or_patch_tables", "or_wedge_tables",
-              "or_patch_forward", "or_patch_particle", "or_cart_tables", "or_cart_slopes",
+              "or_patch_forward", "or_patch_adjoint", "or_patch_particle", "or_cart_tables", "or_cart_slopes",
               "or_cart_forward", "or_num_threads"):
         getattr(lib, f).restype = i
     _lib = lib
@@ -350,6 +351,23 @@ def patch_forward(grid: Grid, n_src: int, s0: int, T, sigma_src, Tw=None, sigma_
                                 _p(fp)):
         raise RuntimeError("or_patch_forward failed")
     return fr, fp
+
+
+def patch_adjoint(grid: Grid, n_src: int, s0: int, T, v_r, v_phi, src=None):
+    """Transpose of :func:`patch_forward` without wedges: cotangents on the
+    destination patch -> gradient on the source patch [n_src][n_phi] (or at
+    the flat source indices ``src``), plain double sums."""
+    vr, vp, T = _f64(v_r), _f64(v_phi), _f64(T)
+    assert vr.shape == grid.shape and vp.shape == grid.shape
+    if src is None:
+        s, ns, g = None, 0, np.empty((n_src, grid.n_phi))
+    else:
+        s = np.ascontiguousarray(src, dtype=np.int64)
+        ns, g = s.size, np.empty(s.size)
+    if _load().or_patch_adjoint(int(n_src), int(s0), grid.n_r, grid.n_phi, grid.r_min,
+                                grid.r_max, _p(T), _p(vr), _p(vp), _p(s), ns, _p(g)):
+        raise RuntimeError("or_patch_adjoint failed")
+    return g
 
 
 def patch_particle(grid: Grid, n_src: int, s0: int, sigma_src, sigma_w=None, plus=False,

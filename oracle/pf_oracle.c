@@ -1297,6 +1297,89 @@ done:
     return rcode;
 }
 
+/* Transpose of or_patch_forward without wedges, as a plain double sum at
+ * chosen source cells: g[p] = sum over destination cells q of
+ * v_r[q] dF_r[q]/dsigma_src[p] + v_phi[q] dF_phi[q]/dsigma_src[p], with the
+ * slopes taken inside the source patch (order 2, as the forward).
+ * v_r, v_phi: [n_dst][n_phi]; src: flat source indices (NULL = all). */
+static void adj_u_patch(int n_src, int n_dst, int n_phi, const double *rd, const double *T,
+                        const double *v_r, const double *v_p, int ip, int jp, double *us,
+                        double *ug, double *uh)
+{
+    const long rows = (long)n_src + n_dst - 1;
+    const long plane = rows * (long)n_phi;
+    acc_t s = {0, 0}, g = {0, 0}, h = {0, 0};
+    for (int i = 0; i < n_dst; ++i) {
+        const long row = (long)(i - ip) + (n_src - 1);
+        const double *t0 = T + row * n_phi, *tr = T + plane + row * n_phi,
+                     *tp = T + 2 * plane + row * n_phi;
+        const double *u0 = T + 3 * plane + row * n_phi, *ur = T + 4 * plane + row * n_phi,
+                     *up = T + 5 * plane + row * n_phi;
+        const double *vr = v_r + (long)i * n_phi, *vp = v_p + (long)i * n_phi;
+        double xs = 0, xg = 0, xh = 0;
+        for (int j = 0; j < n_phi; ++j) {
+            int n = j - jp;
+            if (n < 0) n += n_phi;
+            xs += vr[j] * t0[n] + vp[j] * u0[n];
+            xg += vr[j] * tr[n] + vp[j] * ur[n];
+            xh += vr[j] * tp[n] + vp[j] * up[n];
+        }
+        acc_add(&s, xs);
+        acc_add(&g, rd[i] * xg);
+        acc_add(&h, xh);
+    }
+    *us = acc_get(&s);
+    *ug = acc_get(&g);
+    *uh = acc_get(&h);
+}
+
+int or_patch_adjoint(int n_src, int s0, int n_dst, int n_phi, double r_min, double r_max,
+                     const double *T, const double *v_r, const double *v_phi,
+                     const int64_t *src, int64_t n_idx, double *g)
+{
+    double beta, dphi;
+    double *rd = (double *)malloc(sizeof(double) * n_dst);
+    double *rs = (double *)malloc(sizeof(double) * n_src);
+    int rcode = 0;
+    if (!rd || !rs) { rcode = -2; goto done; }
+    if (or_geometry(n_dst, n_phi, r_min, r_max, rd, NULL, &beta, &dphi) || n_src < 2 ||
+        n_phi < 3) {
+        rcode = -1;
+        goto done;
+    }
+    for (int k = 0; k < n_src; ++k) rs[k] = r_min * pow(beta, s0 + k) * 0.5 * (1.0 + beta);
+    {
+        const long N = (long)n_src * n_phi;
+        const long ns = src ? (long)n_idx : N;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 1)
+#endif
+        for (long q = 0; q < ns; ++q) {
+            const long p = src ? (long)src[q] : q;
+            const int ip = (int)(p / n_phi), jp = (int)(p % n_phi);
+            double us, ug, uh, a, b, c;
+            adj_u_patch(n_src, n_dst, n_phi, rd, T, v_r, v_phi, ip, jp, &us, &ug, &uh);
+            double tot = us;
+            for (int i2 = ip - 1; i2 <= ip + 1; ++i2) {
+                if (i2 < 0 || i2 >= n_src) continue;
+                const double cf = dr_coef(n_src, rs, 2, i2, ip);
+                if (cf == 0.0) continue;
+                adj_u_patch(n_src, n_dst, n_phi, rd, T, v_r, v_phi, i2, jp, &a, &b, &c);
+                tot += cf * b;
+            }
+            for (int d = -1; d <= 1; d += 2) {
+                const int j2 = ((jp - d) % n_phi + n_phi) % n_phi;
+                adj_u_patch(n_src, n_dst, n_phi, rd, T, v_r, v_phi, ip, j2, &a, &b, &c);
+                tot += dp_coef(2, dphi, d) * c;
+            }
+            g[q] = tot;
+        }
+    }
+done:
+    free(rd); free(rs);
+    return rcode;
+}
+
 /* Particle and modified particle methods between patches, in physical
  * coordinates: source cells are point masses sigma r dr dphi at their
  * centres, wedges (if sigma_w) point masses sigma r_w^2 dphi / 2 at

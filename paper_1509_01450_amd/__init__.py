@@ -570,3 +570,19 @@ class PatchPlan(Plan):
                           sigma_wedge.data_ptr() if sigma_wedge is not None else 0,
                           fr.data_ptr(), fp.data_ptr(), _stream())
         return fr, fp
+
+    def backward(self, g_fr, g_fphi, out=None):
+        """Transpose (plans without wedges): cotangents on the destination
+        patch [n_dst][n_phi] -> gradient on the source patch [n_src][n_phi]."""
+        import torch
+        self._check_field(g_fr, "g_fr")
+        self._check_field(g_fphi, "g_fphi")
+        gs = out if out is not None else torch.empty(self.src_shape, dtype=self.torch_dtype,
+                                                     device=g_fr.device)
+        if (not isinstance(gs, torch.Tensor) or not gs.is_cuda or gs.dtype != self.torch_dtype
+                or tuple(gs.shape) != self.src_shape or not gs.is_contiguous()):
+            raise TypeError("out must be a contiguous %s CUDA tensor of shape %s"
+                            % (self.torch_dtype, self.src_shape))
+        pf_forces_backward(self.handle, g_fr.data_ptr(), g_fphi.data_ptr(), gs.data_ptr(),
+                           _stream())
+        return gs

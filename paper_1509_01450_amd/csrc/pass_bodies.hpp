@@ -1046,7 +1046,9 @@ __device__ __forceinline__ void column_sums(cx<T> (&x)[Q], int G, cx<T> *__restr
 // the transposed slope: the transposed central difference is in E'; the
 // four-row correction needs the inverse transform of R = conj(Q_r) V_r +
 // conj(Q_p) V_p at rows 0, n-1, n and L-1 only, four sums over k.
-// V: [n_r][H] pairs (Vr, Vp); D: [n_r][H] complex.  LDS buf: G*padded_len(L)
+// V: [n_v][H] pairs (Vr, Vp) (the destination rows; n_v = n_r for one
+// grid); D: [n_r][H] complex (the source rows, whose slopes the correction
+// differences).  LDS buf: G*padded_len(L)
 // complex.  As the forward pass, one spectrum half at a time: the radial
 // pairs meet V_r's transform, and the azimuthal pairs arrive while V_p is
 // transformed.
@@ -1064,9 +1066,10 @@ __device__ __forceinline__ void body_cols_adj(int unit, int G, cx<T> *__restrict
                                               const cx<T> *__restrict__ twL,
                                               cx2<T> *spl = nullptr,
                                               unsigned *__restrict__ gscale = nullptr,
-                                              T c4 = T(0)) {
+                                              T c4 = T(0), int n_v = 0) {
     static_assert(SO == 2 || SO == 4, "slope order");
     constexpr int NW = SO == 4 ? 8 : 4;
+    if (n_v <= 0) n_v = n_r;
     constexpr int TH = L / E;
     const int gi = threadIdx.x % G, t = threadIdx.x / G;
     const int col = unit * G + gi;
@@ -1083,12 +1086,12 @@ __device__ __forceinline__ void body_cols_adj(int unit, int G, cx<T> *__restrict
     // wait for it (after the first transform stage) waits for no later load.
     const unsigned note = scale_load<T>(gscale);
     // clamped, always valid addresses so the loads issue back to back; only
-    // the first E/2 points of a thread can be data rows (L >= 2 n_r)
+    // the first E/2 points of a thread can be data rows (L >= 2 n_v)
     cx<T> va[2][E];   // va[0]: V_r, va[1]: V_p
 #pragma unroll
     for (int e = 0; e < E / 2; ++e) {
         const int i = t + e * TH;
-        const cx2<T> q = V[(size_t)(i < n_r ? i : n_r - 1) * H + cl];
+        const cx2<T> q = V[(size_t)(i < n_v ? i : n_v - 1) * H + cl];
         va[0][e] = q.a;
         va[1][e] = q.b;
     }
@@ -1099,7 +1102,7 @@ __device__ __forceinline__ void body_cols_adj(int unit, int G, cx<T> *__restrict
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         const int i = t + e * TH;
-        if (e >= E / 2 || !valid || i >= n_r) {
+        if (e >= E / 2 || !valid || i >= n_v) {
             va[0][e] = cx<T>{T(0), T(0)};
             va[1][e] = cx<T>{T(0), T(0)};
         }

@@ -168,17 +168,19 @@ int forces_t(const Plan &p, const T *sigma, const T *sigma_w, T *fr, T *fp, hipS
 }
 
 template <typename T>
+// Transpose: pass A on the n_r destination rows of both cotangents, the
+// transposed column pass to the n_in source rows, pass C on those.
 int backward_t(const Plan &p, const T *gr, const T *gp, T *gs, hipStream_t st) {
     using C = pf::cx<T>;
-    C *V = (C *)p.ws;                        // (Vr, Vp) pairs
-    C *D = V + 2 * (size_t)p.n_r * p.H;
+    C *V = (C *)p.ws;                        // (Vr, Vp) pairs, n_r rows
+    C *D = V + 2 * (size_t)p.n_r * p.H;      // n_in rows
     unsigned *g = p.gscale ? p.gscale + pf::kScaleSet : nullptr;   // the transpose's words
     int rc = pf::launch_rows_r2c<T>(p, gr, gp, p.n_r, V, (const C *)p.twN, p.sched.rows2, st, g);
     if (rc) return rc;
     rc = pf::launch_cols_adj<T>(p, V, D, (const C *)p.spec, (const C *)p.twL, p.sched.cols_adj,
                                 st, g);
     if (rc) return rc;
-    return pf::launch_rows_c2r<T>(p, D, p.n_r, gs, nullptr, (const C *)p.twN, p.sched.rows, st,
+    return pf::launch_rows_c2r<T>(p, D, p.n_in, gs, nullptr, (const C *)p.twN, p.sched.rows, st,
                                   g);
 }
 
@@ -193,9 +195,9 @@ int timed_t(const Plan &p, bool bwd, const void *in0, const void *in1, void *out
     unsigned *g = p.gscale ? p.gscale + (bwd ? pf::kScaleSet : 0) : nullptr;
     PF_HIP(hipEventRecord(ev[0], st));
     for (int k = 0; k < reps && !rc; ++k)
-        rc = pf::launch_rows_r2c<T>(p, (const T *)in0, bwd ? (const T *)in1 : nullptr, p.n_in,
-                                    W0, (const C *)p.twN, bwd ? p.sched.rows2 : p.sched.rows, st,
-                                    g);
+        rc = pf::launch_rows_r2c<T>(p, (const T *)in0, bwd ? (const T *)in1 : nullptr,
+                                    bwd ? p.n_r : p.n_in, W0, (const C *)p.twN,
+                                    bwd ? p.sched.rows2 : p.sched.rows, st, g);
     if (rc) return rc;
     PF_HIP(hipEventRecord(ev[1], st));
     for (int k = 0; k < reps && !rc; ++k) {
@@ -213,7 +215,7 @@ int timed_t(const Plan &p, bool bwd, const void *in0, const void *in1, void *out
             rc = pf::launch_rows_c2r<T>(p, W1, p.n_r, (T *)out0, (T *)out1, (const C *)p.twN,
                                         p.sched.rows2, st, g);
         else
-            rc = pf::launch_rows_c2r<T>(p, W2, p.n_r, (T *)out0, nullptr, (const C *)p.twN,
+            rc = pf::launch_rows_c2r<T>(p, W2, p.n_in, (T *)out0, nullptr, (const C *)p.twN,
                                         p.sched.rows, st, g);
     }
     if (rc) return rc;
@@ -581,8 +583,8 @@ int pf_forces_backward(pf_plan h, const void *g_fr, const void *g_fphi, void *g_
     int rc = check_call(h, g_fr, g_fphi, g_sigma);
     if (rc) return rc;
     const Plan &p = h->p;
-    if (p.patch) {
-        pf::set_error("the transpose is built for single-grid plans only");
+    if (p.wedges) {
+        pf::set_error("the transpose of the origin wedges is not built (plans with wedges)");
         return PF_EUNSUPPORTED;
     }
     hipStream_t st = (hipStream_t)stream;

@@ -83,6 +83,7 @@ __global__ __launch_bounds__(512) void k_cols_fwd_pf(const cx<T> *__restrict__ S
                                      cn, twL, spl, gscale, c4);
 }
 
+// n_r: rows of D (source rows), n_v: rows of V (destination rows).
 template <typename T, int L, int E, int SO = 2>
 __global__ __launch_bounds__(512) void k_cols_adj(const cx2<T> *__restrict__ V,
                                                   cx<T> *__restrict__ D,
@@ -90,13 +91,13 @@ __global__ __launch_bounds__(512) void k_cols_adj(const cx2<T> *__restrict__ V,
                                                   int ldspec, T ca, T c0, T cn,
                                                   const cx<T> *__restrict__ twL, int per_xcd,
                                                   int n_groups, unsigned *__restrict__ gscale,
-                                                  T c4) {
+                                                  T c4, int n_v) {
     extern __shared__ unsigned char smem_raw[];
     const int grp = xcd_group(blockIdx.x, per_xcd);
     if (grp >= n_groups) return;
     body_cols_adj<T, L, E, false, SO>(grp, blockDim.x / (L / E),
                                       reinterpret_cast<cx<T> *>(smem_raw), V, D, spec, H, n_r,
-                                      ldspec, ca, c0, cn, twL, nullptr, gscale, c4);
+                                      ldspec, ca, c0, cn, twL, nullptr, gscale, c4, n_v);
 }
 
 // Transpose column pass with G fixed at compile time and the radial
@@ -108,13 +109,14 @@ __global__ __launch_bounds__(512) void k_cols_adj_pf(const cx2<T> *__restrict__ 
                                                      int n_r, int ldspec, T ca, T c0, T cn,
                                                      const cx<T> *__restrict__ twL, int per_xcd,
                                                      int n_groups,
-                                                     unsigned *__restrict__ gscale, T c4) {
+                                                     unsigned *__restrict__ gscale, T c4,
+                                                     int n_v) {
     __shared__ cx<T> fbuf[G * padded_len(L)];
     __shared__ cx2<T> spl[G * spec_prefetch_len<L, E>()];
     const int grp = xcd_group(blockIdx.x, per_xcd);
     if (grp >= n_groups) return;  // whole workgroup leaves together
     body_cols_adj<T, L, E, true, SO>(grp, G, fbuf, V, D, spec, H, n_r, ldspec, ca, c0, cn, twL,
-                                     spl, gscale, c4);
+                                     spl, gscale, c4, n_v);
 }
 
 // ---------------------------------------------------------------------------
@@ -218,8 +220,8 @@ bool launch_cols_adj_pf(dim3 grid, hipStream_t st, const cx2<T> *V, cx<T> *D,
                         const cx<T> *tw, int per_xcd, int n_groups, unsigned *g) {
     if constexpr (cols_pf_fits<T, N, E, G>() && so_pf_instance<T, E, SO>()) {
         hipLaunchKernelGGL((k_cols_adj_pf<T, N, E, G, SO>), grid, dim3(G * (N / E)), 0, st, V,
-                           D, spec, p.H, p.n_r, p.ldspec, ca, c0, cn, tw, per_xcd, n_groups, g,
-                           c4);
+                           D, spec, p.H, p.n_in, p.ldspec, ca, c0, cn, tw, per_xcd, n_groups, g,
+                           c4, p.n_r);
         return true;
     }
     return false;
@@ -321,8 +323,8 @@ struct Disp {
                 int rc = allow_lds(k_cols_adj<T, N, E, SO>, lds);
                 if (rc) return rc;
                 hipLaunchKernelGGL((k_cols_adj<T, N, E, SO>), dim3(blocks), dim3(G * TH), lds, st,
-                                   reinterpret_cast<const cx2<T> *>(a), o, sp, p.H, p.n_r,
-                                   p.ldspec, ca, c0, cn, tw, per_xcd, n_groups, g, c4);
+                                   reinterpret_cast<const cx2<T> *>(a), o, sp, p.H, p.n_in,
+                                   p.ldspec, ca, c0, cn, tw, per_xcd, n_groups, g, c4, p.n_r);
             } else {
                 int rc = allow_lds(k_cols_fwd<T, N, E, SO>, lds);
                 if (rc) return rc;

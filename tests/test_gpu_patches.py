@@ -8,7 +8,8 @@ destination [0.01, 1].
 Parity bars: relative L2 <= 1e-11 (FP64) and 1e-5 (FP32) on both force
 components, for source patches below (adjacent and with a gap), above and
 overlapping the destination, ragged sizes, all methods, with and without
-wedges."""
+wedges; the transpose of wedge-free patch plans against the oracle's
+transposed sums."""
 import os
 import sys
 
@@ -86,6 +87,66 @@ def test_patch_parity(case, method):
         a, b = _rel(fr, o_r), _rel(fp, o_p)
         _say("  %s rel-L2 F_r %.2e F_phi %.2e" % (dt, a, b))
         assert a < tol and b < tol, (case, method, dt, a, b)
+
+
+TRANSPOSE_CASES = [c[:4] for c in CASES if not c[4]] + [(10, -10, 24, 32), (33, -33, 40, 128)]
+
+
+@pytest.mark.parametrize("case", TRANSPOSE_CASES)
+def test_patch_transpose_matches_oracle(case):
+    # the transpose of a patch plan without wedges: cotangents on the
+    # destination patch -> gradient on the source patch
+    n_src, s0, n_dst, n_phi = case
+    g = oracle.Grid(n_dst, n_phi, 0.05, 2.0)
+    vr = workloads.random_field(g.shape, 81 + n_src)
+    vp = workloads.random_field(g.shape, 91 + n_src)
+    _say("patch transpose %s" % (case,))
+    T = oracle.patch_tables(g, n_src, s0, 19)
+    want = oracle.patch_adjoint(g, n_src, s0, T, vr, vp)
+    for dt, tol in (("f64", 1e-11), ("f32", 1e-5)):
+        plan = pf.PatchPlan(n_src, s0, n_dst, n_phi, g.r_min, g.r_max, dtype=dt)
+        try:
+            a = torch.tensor(vr, dtype=plan.torch_dtype, device="cuda")
+            b = torch.tensor(vp, dtype=plan.torch_dtype, device="cuda")
+            got = plan.backward(a, b)
+            torch.cuda.synchronize()
+            assert tuple(got.shape) == (n_src, n_phi)
+            e = _rel(got.double().cpu().numpy(), want)
+        finally:
+            plan.close()
+        _say("  %s rel-L2 %.2e" % (dt, e))
+        assert e < tol, (case, dt, e)
+
+
+@pytest.mark.parametrize("method", ["particle", "particle+"])
+def test_patch_transpose_dot_product_particle_methods(method):
+    # the particle methods go through the same passes: <v, A s> = <A^T v, s>
+    n_src, s0, n_dst, n_phi = 12, -3, 20, 32
+    plan = pf.PatchPlan(n_src, s0, n_dst, n_phi, 0.05, 2.0, dtype="f64", method=method)
+    try:
+        s = torch.tensor(workloads.random_field((n_src, n_phi), 7), device="cuda")
+        vr = torch.tensor(workloads.random_field((n_dst, n_phi), 8), device="cuda")
+        vp = torch.tensor(workloads.random_field((n_dst, n_phi), 9), device="cuda")
+        fr, fp = plan.forces(s)
+        gs = plan.backward(vr, vp)
+        torch.cuda.synchronize()
+        lhs = float((fr * vr).sum() + (fp * vp).sum())
+        rhs = float((gs * s).sum())
+        ref = float((fr * vr).abs().sum() + (fp * vp).abs().sum())
+    finally:
+        plan.close()
+    _say("%s patch transpose dot product: %.3e vs %.3e" % (method, lhs, rhs))
+    assert abs(lhs - rhs) < 1e-12 * ref
+
+
+def test_patch_transpose_with_wedges_is_refused():
+    plan = pf.PatchPlan(10, -10, 24, 32, 0.05, 2.0, wedges=True, dtype="f32")
+    try:
+        a = torch.zeros(24, 32, device="cuda")
+        with pytest.raises(pf.PFError, match="wedges"):
+            plan.backward(a, a)
+    finally:
+        plan.close()
 
 
 def test_patch_with_one_trapezoid_and_wedges():

@@ -111,3 +111,61 @@ def test_uniform_wedges_are_a_uniform_disk():
     Tp = oracle.wedge_tables(g, s0, "particle")
     for i in (0, 5):
         assert abs(Tp[0, i].sum() / Tw[0, i].sum() - 1) < 2 * (r_w / g.r_centres[i]) ** 2
+
+
+@pytest.mark.parametrize("s0", [-9, -6, -3, 2])
+def test_patch_adjoint_dot_product(s0):
+    # the transpose of the patch map (no wedges): <v, A sigma> = <A^T v, sigma>
+    # for any source density (edge rows included) and cotangents
+    g = oracle.Grid(7, 16, 0.3, 2.0)
+    n_src = 6
+    T = oracle.patch_tables(g, n_src, s0, 19)
+    sig = workloads.random_field((n_src, g.n_phi), 31 + s0)
+    vr = workloads.random_field(g.shape, 41 + s0)
+    vp = workloads.random_field(g.shape, 51 + s0)
+    fr, fp = oracle.patch_forward(g, n_src, s0, T, sig)
+    gs = oracle.patch_adjoint(g, n_src, s0, T, vr, vp)
+    assert gs.shape == (n_src, g.n_phi)
+    lhs = (fr * vr).sum() + (fp * vp).sum()
+    rhs = (gs * sig).sum()
+    assert abs(lhs - rhs) < 1e-12 * (np.abs(fr * vr).sum() + np.abs(fp * vp).sum())
+
+
+def test_patch_adjoint_equals_union_grid_adjoint():
+    # on the union grid the patch is a block of the single-grid map: with
+    # cotangents zero outside the destination rows, the union transpose on
+    # the source rows equals the patch transpose wherever the source's edge
+    # rows do not enter (the slopes inside the patch and on the union differ
+    # only there)
+    g = oracle.Grid(7, 16, 0.3, 2.0)
+    n_src, s0 = 8, -3
+    u, lo = _union(g, n_src, s0)
+    sk = oracle.selfcell_cover(g.beta, g.dphi, 10)[:3]
+    T = oracle.patch_tables(g, n_src, s0, 19, self_k=sk)
+    Tu = oracle.tables(u, 19, self_k=sk)
+    vr = workloads.random_field(g.shape, 61)
+    vp = workloads.random_field(g.shape, 62)
+    vr_u, vp_u = np.zeros(u.shape), np.zeros(u.shape)
+    vr_u[-lo:-lo + g.n_r], vp_u[-lo:-lo + g.n_r] = vr, vp
+    gu = oracle.adjoint(u, Tu, vr_u, vp_u)[s0 - lo:s0 - lo + n_src]
+    gp = oracle.patch_adjoint(g, n_src, s0, T, vr, vp)
+    # rows 2 .. n_src - 3: every slope stencil that reads them is a central
+    # difference in both
+    inner = slice(2, n_src - 2)
+    assert gp[inner].size == (n_src - 4) * g.n_phi
+    scale = np.abs(gu).max()
+    np.testing.assert_allclose(gp[inner], gu[inner], rtol=0, atol=1e-12 * scale)
+    # the source's last row is an end of the patch but not of the union
+    # grid: there the one-sided difference of the patch makes them differ
+    assert np.abs(gp[-1] - gu[-1]).max() > 1e-6 * scale
+
+
+def test_patch_adjoint_sampled_equals_full():
+    g = oracle.Grid(6, 12, 0.5, 3.0)
+    T = oracle.patch_tables(g, 5, -5, 3)
+    vr = workloads.random_field(g.shape, 71)
+    vp = workloads.random_field(g.shape, 72)
+    full = oracle.patch_adjoint(g, 5, -5, T, vr, vp)
+    idx = np.array([0, 7, 30, 59])
+    part = oracle.patch_adjoint(g, 5, -5, T, vr, vp, src=idx)
+    np.testing.assert_array_equal(part, full.ravel()[idx])
