@@ -64,7 +64,7 @@ def _load():
     lib.or_patch_tables.argtypes = [i, i, i, i, d, d, i, i, P, P]
     lib.or_wedge_tables.argtypes = [i, i, d, d, i, i, P]
     lib.or_patch_forward.argtypes = [i, i, i, i, d, d, P, P, P, P, P, i64, P, P]
-    lib.or_patch_adjoint.argtypes = [i, i, i, i, d, d, P, P, P, P, i64, P]
+    lib.or_patch_adjoint.argtypes = [i, i, i, i, d, d, P, P, P, P, i64, P, P, P]
     lib.or_patch_particle.argtypes = [i, i, i, i, d, d, i, P, P, P, P, i64, P, P]
     lib.or_cart_tables.argtypes = [i, i, d, d, i, P]
     lib.or_cart_slopes.argtypes = [i, i, d, d, P, P, P]
@@ -353,21 +353,27 @@ def patch_forward(grid: Grid, n_src: int, s0: int, T, sigma_src, Tw=None, sigma_
     return fr, fp
 
 
-def patch_adjoint(grid: Grid, n_src: int, s0: int, T, v_r, v_phi, src=None):
-    """Transpose of :func:`patch_forward` without wedges: cotangents on the
-    destination patch -> gradient on the source patch [n_src][n_phi] (or at
-    the flat source indices ``src``), plain double sums."""
+def patch_adjoint(grid: Grid, n_src: int, s0: int, T, v_r, v_phi, src=None, Tw=None):
+    """Transpose of :func:`patch_forward`: cotangents on the destination
+    patch -> gradient on the source patch [n_src][n_phi] (or at the flat
+    source indices ``src``), plain double sums.  With the wedge tables Tw
+    (full source grid only) also the gradient with respect to the wedge
+    densities: returns (g_src, g_wedge)."""
     vr, vp, T = _f64(v_r), _f64(v_phi), _f64(T)
     assert vr.shape == grid.shape and vp.shape == grid.shape
+    assert Tw is None or src is None
     if src is None:
         s, ns, g = None, 0, np.empty((n_src, grid.n_phi))
     else:
         s = np.ascontiguousarray(src, dtype=np.int64)
         ns, g = s.size, np.empty(s.size)
+    Tw = _f64(Tw) if Tw is not None else None
+    gw = np.empty(grid.n_phi) if Tw is not None else None
     if _load().or_patch_adjoint(int(n_src), int(s0), grid.n_r, grid.n_phi, grid.r_min,
-                                grid.r_max, _p(T), _p(vr), _p(vp), _p(s), ns, _p(g)):
+                                grid.r_max, _p(T), _p(vr), _p(vp), _p(s), ns, _p(g), _p(Tw),
+                                _p(gw)):
         raise RuntimeError("or_patch_adjoint failed")
-    return g
+    return (g, gw) if Tw is not None else g
 
 
 def patch_particle(grid: Grid, n_src: int, s0: int, sigma_src, sigma_w=None, plus=False,

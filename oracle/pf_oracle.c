@@ -1297,11 +1297,15 @@ done:
     return rcode;
 }
 
-/* Transpose of or_patch_forward without wedges, as a plain double sum at
- * chosen source cells: g[p] = sum over destination cells q of
+/* Transpose of or_patch_forward, as a plain double sum at chosen source
+ * cells: g[p] = sum over destination cells q of
  * v_r[q] dF_r[q]/dsigma_src[p] + v_phi[q] dF_phi[q]/dsigma_src[p], with the
  * slopes taken inside the source patch (order 2, as the forward).
- * v_r, v_phi: [n_dst][n_phi]; src: flat source indices (NULL = all). */
+ * v_r, v_phi: [n_dst][n_phi]; src: flat source indices (NULL = all).
+ * With the wedge tables Tw (NULL: no wedges) also gw[n_phi], the gradient
+ * with respect to the wedge densities (all of them), and the wedges' radial
+ * slope -- the difference towards the first source row -- adds to the
+ * gradient of that row (to g only where src is NULL, i.e. the full grid). */
 static void adj_u_patch(int n_src, int n_dst, int n_phi, const double *rd, const double *T,
                         const double *v_r, const double *v_p, int ip, int jp, double *us,
                         double *ug, double *uh)
@@ -1333,9 +1337,37 @@ static void adj_u_patch(int n_src, int n_dst, int n_phi, const double *rd, const
     *uh = acc_get(&h);
 }
 
+/* sums of the cotangents against the wedge tables for wedge jp */
+static void adj_u_wedge(int n_dst, int n_phi, const double *rd, const double *Tw,
+                        const double *v_r, const double *v_p, int jp, double *us, double *ug,
+                        double *uh)
+{
+    const long wplane = (long)n_dst * n_phi;
+    acc_t s = {0, 0}, g = {0, 0}, h = {0, 0};
+    for (int i = 0; i < n_dst; ++i) {
+        const double *vr = v_r + (long)i * n_phi, *vp = v_p + (long)i * n_phi;
+        double xs = 0, xg = 0, xh = 0;
+        for (int j = 0; j < n_phi; ++j) {
+            int n = j - jp;
+            if (n < 0) n += n_phi;
+            const long t = (long)i * n_phi + n;
+            xs += vr[j] * Tw[t] + vp[j] * Tw[3 * wplane + t];
+            xg += vr[j] * Tw[wplane + t] + vp[j] * Tw[4 * wplane + t];
+            xh += vr[j] * Tw[2 * wplane + t] + vp[j] * Tw[5 * wplane + t];
+        }
+        acc_add(&s, xs);
+        acc_add(&g, rd[i] * xg);
+        acc_add(&h, xh);
+    }
+    *us = acc_get(&s);
+    *ug = acc_get(&g);
+    *uh = acc_get(&h);
+}
+
 int or_patch_adjoint(int n_src, int s0, int n_dst, int n_phi, double r_min, double r_max,
                      const double *T, const double *v_r, const double *v_phi,
-                     const int64_t *src, int64_t n_idx, double *g)
+                     const int64_t *src, int64_t n_idx, double *g, const double *Tw,
+                     double *gw)
 {
     double beta, dphi;
     double *rd = (double *)malloc(sizeof(double) * n_dst);
@@ -1374,6 +1406,29 @@ int or_patch_adjoint(int n_src, int s0, int n_dst, int n_phi, double r_min, doub
             }
             g[q] = tot;
         }
+    }
+    if (Tw && gw) {
+        const double rh = 0.5 * r_min * pow(beta, s0), inv = 1.0 / (rs[0] - rh);
+        double *ug0 = (double *)malloc(sizeof(double) * n_phi);
+        double *us0 = (double *)malloc(sizeof(double) * n_phi);
+        double *uh0 = (double *)malloc(sizeof(double) * n_phi);
+        if (!ug0 || !us0 || !uh0) { free(ug0); free(us0); free(uh0); rcode = -2; goto done; }
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 1)
+#endif
+        for (int jp = 0; jp < n_phi; ++jp)
+            adj_u_wedge(n_dst, n_phi, rd, Tw, v_r, v_phi, jp, &us0[jp], &ug0[jp], &uh0[jp]);
+        for (int jp = 0; jp < n_phi; ++jp) {
+            /* sigma_w[jp] enters the wedge density, its radial slope
+             * (sigma_src[0] - sigma_w) / (r_0 - r_w / 2) and its periodic
+             * azimuthal slope */
+            double tot = us0[jp] - inv * ug0[jp];
+            for (int d = -1; d <= 1; d += 2)
+                tot += dp_coef(2, dphi, d) * uh0[((jp - d) % n_phi + n_phi) % n_phi];
+            gw[jp] = tot;
+            if (!src) g[jp] += inv * ug0[jp];   /* the first source row */
+        }
+        free(ug0); free(us0); free(uh0);
     }
 done:
     free(rd); free(rs);

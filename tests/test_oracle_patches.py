@@ -169,3 +169,55 @@ def test_patch_adjoint_sampled_equals_full():
     idx = np.array([0, 7, 30, 59])
     part = oracle.patch_adjoint(g, 5, -5, T, vr, vp, src=idx)
     np.testing.assert_array_equal(part, full.ravel()[idx])
+
+
+@pytest.mark.parametrize("s0,method", [(-6, "sim"), (-3, "sim"), (0, "sim"), (-2, "particle")])
+def test_patch_adjoint_with_wedges_dot_product(s0, method):
+    # the transpose with the origin wedges: <v, A (sigma, sigma_w)> =
+    # <g_src, sigma> + <g_w, sigma_w>; the wedges couple to the first source
+    # row through their radial slope, so a dropped or mis-signed slope term
+    # breaks the identity on random inputs
+    g = oracle.Grid(7, 16, 0.3, 2.0)
+    n_src = 6
+    T = oracle.patch_tables(g, n_src, s0, 19)
+    Tw = oracle.wedge_tables(g, s0, method)
+    sig = workloads.random_field((n_src, g.n_phi), 81 - s0)
+    sw = workloads.random_field((g.n_phi,), 82 - s0)
+    vr = workloads.random_field(g.shape, 83 - s0)
+    vp = workloads.random_field(g.shape, 84 - s0)
+    fr, fp = oracle.patch_forward(g, n_src, s0, T, sig, Tw=Tw, sigma_w=sw)
+    gs, gw = oracle.patch_adjoint(g, n_src, s0, T, vr, vp, Tw=Tw)
+    assert gs.shape == (n_src, g.n_phi) and gw.shape == (g.n_phi,)
+    lhs = (fr * vr).sum() + (fp * vp).sum()
+    rhs = (gs * sig).sum() + (gw * sw).sum()
+    assert abs(lhs - rhs) < 1e-12 * (np.abs(fr * vr).sum() + np.abs(fp * vp).sum())
+    # the wedge part alone (zero source patch) and the source part alone
+    fr0, fp0 = oracle.patch_forward(g, n_src, s0, T, np.zeros_like(sig), Tw=Tw, sigma_w=sw)
+    lw = (fr0 * vr).sum() + (fp0 * vp).sum()
+    assert abs(lw - (gw * sw).sum()) < 1e-12 * (np.abs(fr0 * vr).sum() + np.abs(fp0 * vp).sum())
+    # the wedges' slope reaches the first source row: it differs from the
+    # transpose without wedges there and only there
+    g0 = oracle.patch_adjoint(g, n_src, s0, T, vr, vp)
+    if method == "sim":
+        assert np.abs(gs[0] - g0[0]).max() > 1e-6 * np.abs(g0).max()
+    else:
+        np.testing.assert_array_equal(gs[0], g0[0])
+    np.testing.assert_array_equal(gs[1:], g0[1:])
+
+
+def test_patch_adjoint_wedge_gradient_by_unit_wedges():
+    # g_w[j] = <v, A (0, e_j)>: the forward map of one unit wedge at a time
+    g = oracle.Grid(5, 8, 0.2, 1.0)
+    n_src, s0 = 4, -2
+    T = oracle.patch_tables(g, n_src, s0, 19)
+    Tw = oracle.wedge_tables(g, s0)
+    vr = workloads.random_field(g.shape, 91)
+    vp = workloads.random_field(g.shape, 92)
+    _, gw = oracle.patch_adjoint(g, n_src, s0, T, vr, vp, Tw=Tw)
+    z = np.zeros((n_src, g.n_phi))
+    for j in range(g.n_phi):
+        e = np.zeros(g.n_phi)
+        e[j] = 1.0
+        fr, fp = oracle.patch_forward(g, n_src, s0, T, z, Tw=Tw, sigma_w=e)
+        want = (fr * vr).sum() + (fp * vp).sum()
+        assert abs(gw[j] - want) < 1e-12 * (np.abs(fr * vr).sum() + np.abs(fp * vp).sum())
