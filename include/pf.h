@@ -163,7 +163,8 @@ pf_plan pf_plan_create(int n_r, int n_phi, double r_min, double r_max);
  * (no azimuthal offset between the patches).  Build with pf_kernels_build;
  * pf_forces takes sigma [n_src][n_phi] and writes f_r, f_phi
  * [n_dst][n_phi] (no wedges), pf_forces_patches also the wedge densities.
- * The transpose takes patch plans without wedges (pf_forces_backward); the
+ * The transpose: pf_forces_backward (no wedges) or
+ * pf_forces_patches_backward (also the wedge gradient); the
  * batched path and the autotuner are for single-grid plans
  * (PF_EUNSUPPORTED).  Sizes: 4 <= n_src <= 4096,
  * |src_row0| <= 65536, n_dst and n_phi as for pf_plan_create.             */
@@ -203,9 +204,22 @@ int pf_forces_patches(pf_plan plan, const void *sigma_src, const void *sigma_wed
  * paper: it is the exact transpose of the linear map Eq. 26-29.  Async.
  * Patch plans without origin wedges: g_fr, g_fphi [n_dst][n_phi] on the
  * destination patch, g_sigma [n_src][n_phi] on the source patch; plans with
- * wedges give PF_EUNSUPPORTED (the wedges' transpose is not built).        */
+ * wedges give PF_EINVAL (they take pf_forces_patches_backward).           */
 int pf_forces_backward(pf_plan plan, const void *g_fr, const void *g_fphi,
                        void *g_sigma, void *stream);
+
+/* Transpose of pf_forces_patches (Sec. 3.2.1 with the slopes of Eq. 25; not
+ * in the paper: the exact transpose of that linear map): cotangents g_fr,
+ * g_fphi [n_dst][n_phi] -> g_sigma_src [n_src][n_phi] (overwritten) and,
+ * for plans with origin wedges, g_sigma_wedge [n_phi] (overwritten; NULL
+ * otherwise, and then the call is pf_forces_backward).  A wedge density
+ * enters its own wedge's terms and, through the wedge's radial slope (the
+ * difference towards the first source row), that row too: the first source
+ * row's gradient holds that share.  Device pointers, the plan's precision;
+ * PF_EINVAL for a wedge argument that does not match the plan.  Four more
+ * small launches than the transpose without wedges.  Asynchronous.        */
+int pf_forces_patches_backward(pf_plan plan, const void *g_fr, const void *g_fphi,
+                               void *g_sigma_src, void *g_sigma_wedge, void *stream);
 
 /* Forward map for n independent disks, each with its own built plan (all of
  * one precision, sizes may differ), on `stream`: the disks are grouped per

@@ -43,6 +43,7 @@ EXPORTS = ("pf_build_opts_default", "pf_plan_create", "pf_kernels_build", "pf_fo
            "pf_plan_schedule", "pf_plan_set_schedule", "pf_plan_selfcell", "pf_plan_tables",
            "pf_plan_destroy",
            "pf_last_error", "pf_version", "pf_plan_create_patches", "pf_forces_patches",
+           "pf_forces_patches_backward",
            "pf_cart_create", "pf_cart_build", "pf_cart_forces",
            "pf_cart_forces_timed", "pf_cart_geometry", "pf_cart_destroy")
 
@@ -106,6 +107,8 @@ def load():
     lib.pf_plan_create_patches.restype = P
     lib.pf_forces_patches.argtypes = [P, P, P, P, P, P]
     lib.pf_forces_patches.restype = I
+    lib.pf_forces_patches_backward.argtypes = [P, P, P, P, P, P]
+    lib.pf_forces_patches_backward.restype = I
     lib.pf_cart_create.argtypes = [I, I, D, D]
     lib.pf_cart_create.restype = P
     lib.pf_cart_build.argtypes = [P, I, I, P]
@@ -238,6 +241,12 @@ def pf_forces_patches(plan: int, sigma_src: int, sigma_wedge: int, f_r: int, f_p
                       stream: int = 0) -> None:
     _check(load().pf_forces_patches(plan, sigma_src, sigma_wedge or None, f_r, f_phi,
                                     stream or None))
+
+
+def pf_forces_patches_backward(plan: int, g_fr: int, g_fphi: int, g_sigma_src: int,
+                               g_sigma_wedge: int, stream: int = 0) -> None:
+    _check(load().pf_forces_patches_backward(plan, g_fr, g_fphi, g_sigma_src,
+                                             g_sigma_wedge or None, stream or None))
 
 
 def pf_cart_create(n_x: int, n_y: int, dx: float, dy: float) -> int:
@@ -572,17 +581,26 @@ class PatchPlan(Plan):
         return fr, fp
 
     def backward(self, g_fr, g_fphi, out=None):
-        """Transpose (plans without wedges): cotangents on the destination
-        patch [n_dst][n_phi] -> gradient on the source patch [n_src][n_phi]."""
+        """Transpose: cotangents on the destination patch [n_dst][n_phi] ->
+        gradient on the source patch [n_src][n_phi]; plans with origin
+        wedges return (g_src, g_wedge), g_wedge [n_phi] the gradient with
+        respect to the wedge densities (out: that pair)."""
         import torch
         self._check_field(g_fr, "g_fr")
         self._check_field(g_fphi, "g_fphi")
-        gs = out if out is not None else torch.empty(self.src_shape, dtype=self.torch_dtype,
-                                                     device=g_fr.device)
-        if (not isinstance(gs, torch.Tensor) or not gs.is_cuda or gs.dtype != self.torch_dtype
-                or tuple(gs.shape) != self.src_shape or not gs.is_contiguous()):
-            raise TypeError("out must be a contiguous %s CUDA tensor of shape %s"
-                            % (self.torch_dtype, self.src_shape))
-        pf_forces_backward(self.handle, g_fr.data_ptr(), g_fphi.data_ptr(), gs.data_ptr(),
-                           _stream())
-        return gs
+        shapes = [self.src_shape] + ([(self.n_phi,)] if self.wedges else [])
+        if out is None:
+            outs = [torch.empty(sh, dtype=self.torch_dtype, device=g_fr.device) for sh in shapes]
+        else:
+            outs = list(out) if self.wedges else [out]
+        if len(outs) != len(shapes):
+            raise TypeError("out must be a pair (g_src, g_wedge) for plans with wedges")
+        for o, sh in zip(outs, shapes):
+            if (not isinstance(o, torch.Tensor) or not o.is_cuda or o.dtype != self.torch_dtype
+                    or tuple(o.shape) != sh or not o.is_contiguous()):
+                raise TypeError("out must be a contiguous %s CUDA tensor of shape %s"
+                                % (self.torch_dtype, sh))
+        pf_forces_patches_backward(self.handle, g_fr.data_ptr(), g_fphi.data_ptr(),
+                                   outs[0].data_ptr(),
+                                   outs[1].data_ptr() if self.wedges else 0, _stream())
+        return tuple(outs) if self.wedges else outs[0]

@@ -167,10 +167,11 @@ int forces_t(const Plan &p, const T *sigma, const T *sigma_w, T *fr, T *fp, hipS
     return pf::launch_rows_c2r<T>(p, Z, p.n_r, fr, fp, (const C *)p.twN, p.sched.rows2, st, g);
 }
 
-template <typename T>
 // Transpose: pass A on the n_r destination rows of both cotangents, the
-// transposed column pass to the n_in source rows, pass C on those.
-int backward_t(const Plan &p, const T *gr, const T *gp, T *gs, hipStream_t st) {
+// transposed column pass to the n_in source rows, pass C on those; plans
+// with wedges then the wedges' transpose from the same row spectra.
+template <typename T>
+int backward_t(const Plan &p, const T *gr, const T *gp, T *gs, T *gw, hipStream_t st) {
     using C = pf::cx<T>;
     C *V = (C *)p.ws;                        // (Vr, Vp) pairs, n_r rows
     C *D = V + 2 * (size_t)p.n_r * p.H;      // n_in rows
@@ -180,8 +181,9 @@ int backward_t(const Plan &p, const T *gr, const T *gp, T *gs, hipStream_t st) {
     rc = pf::launch_cols_adj<T>(p, V, D, (const C *)p.spec, (const C *)p.twL, p.sched.cols_adj,
                                 st, g);
     if (rc) return rc;
-    return pf::launch_rows_c2r<T>(p, D, p.n_in, gs, nullptr, (const C *)p.twN, p.sched.rows, st,
-                                  g);
+    rc = pf::launch_rows_c2r<T>(p, D, p.n_in, gs, nullptr, (const C *)p.twN, p.sched.rows, st, g);
+    if (rc || !p.wedges) return rc;
+    return pf::launch_wedge_adjoint<T>(p, V, gs, gw, st, g);
 }
 
 template <typename T>
@@ -584,14 +586,34 @@ int pf_forces_backward(pf_plan h, const void *g_fr, const void *g_fphi, void *g_
     if (rc) return rc;
     const Plan &p = h->p;
     if (p.wedges) {
-        pf::set_error("the transpose of the origin wedges is not built (plans with wedges)");
-        return PF_EUNSUPPORTED;
+        pf::set_error("the plan has origin wedges: call pf_forces_patches_backward");
+        return PF_EINVAL;
     }
     hipStream_t st = (hipStream_t)stream;
     if (p.opts.dtype == PF_F64)
         return backward_t<double>(p, (const double *)g_fr, (const double *)g_fphi,
-                                  (double *)g_sigma, st);
-    return backward_t<float>(p, (const float *)g_fr, (const float *)g_fphi, (float *)g_sigma, st);
+                                  (double *)g_sigma, nullptr, st);
+    return backward_t<float>(p, (const float *)g_fr, (const float *)g_fphi, (float *)g_sigma,
+                             nullptr, st);
+}
+
+int pf_forces_patches_backward(pf_plan h, const void *g_fr, const void *g_fphi,
+                               void *g_sigma_src, void *g_sigma_wedge, void *stream) {
+    pf::clear_error();
+    int rc = check_call(h, g_fr, g_fphi, g_sigma_src);
+    if (rc) return rc;
+    const Plan &p = h->p;
+    if (p.wedges != (g_sigma_wedge != nullptr)) {
+        pf::set_error(p.wedges ? "the plan has origin wedges: g_sigma_wedge is required"
+                               : "the plan has no origin wedges: g_sigma_wedge must be NULL");
+        return PF_EINVAL;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    if (p.opts.dtype == PF_F64)
+        return backward_t<double>(p, (const double *)g_fr, (const double *)g_fphi,
+                                  (double *)g_sigma_src, (double *)g_sigma_wedge, st);
+    return backward_t<float>(p, (const float *)g_fr, (const float *)g_fphi,
+                             (float *)g_sigma_src, (float *)g_sigma_wedge, st);
 }
 
 int pf_forces_timed(pf_plan h, int backward, const void *in0, const void *in1, void *out0,

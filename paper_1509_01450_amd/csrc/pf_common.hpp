@@ -122,6 +122,13 @@ int build_wedge_spectra(Plan &p, hipStream_t st);
 template <typename T>
 int launch_wedge_terms(const Plan &p, const T *sigma_src, const T *sigma_w, cx<T> *Z,
                        hipStream_t st, const unsigned *g = nullptr);
+// Transpose of the wedge terms, from the cotangents' row spectra V (pass A
+// of the transpose, (V_r, V_p) pairs on the n_r destination rows; run after
+// the transpose's column pass and pass C): writes g_w[n_phi] and adds the
+// wedges' radial-slope share to the first source row g_src[0][:].
+template <typename T>
+int launch_wedge_adjoint(const Plan &p, const cx<T> *V, T *g_src, T *g_w, hipStream_t st,
+                         unsigned *g);
 
 // ---- host helpers -------------------------------------------------------------
 // exp(-2 pi i j / n) for j in [0, n), computed in long double

@@ -984,6 +984,100 @@ __global__ void k_wedge_add(cx2<T> *__restrict__ Z, const cx2<T> *__restrict__ w
     Z[idx] = z;
 }
 
+// Transpose of the wedge terms.  The forward adds A[i][k] w[k] (radial) and
+// B[i][k] w[k] (azimuthal) to row i's spectra, w = (sigma_w^, delta^r^);
+// its transpose takes the cotangents' row spectra V[i][k] = (V_r, V_p) to
+//   wbar[k] = sum over destination rows i of conj(A) V_r + conj(B) V_p
+// (pair by pair: the sigma_w part and the delta^r part), bins 0 and
+// n_phi/2 real and packed as in the forward.  Stage 1: workgroup (x, y)
+// sums the rows of chunk y for bins [64 x, 64 x + 64), four row lanes per
+// bin, reduced through LDS in a fixed order; stage 2 sums the chunks in
+// order, so the result does not depend on timing.  FP32: V is the pass-A
+// output (unscaled); it is taken times 2^-e (e from the transpose's scale
+// words, written by its column pass), so wbar carries the same scale as
+// the column pass's output and the row transform that follows restores it.
+constexpr int kWedgeLanes = 4;
+template <typename T>
+__global__ __launch_bounds__(64 * kWedgeLanes) void k_wedge_adj_part(
+    const cx2<T> *__restrict__ V, const cx2<T> *__restrict__ wspec, int n_r, int H, int rows,
+    cx2<T> *__restrict__ part, const unsigned *__restrict__ g) {
+    const int k = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int lane = threadIdx.x >> 6;
+    const int i0 = blockIdx.y * rows, i1 = min(n_r, i0 + rows);
+    T s = T(1);
+    if (g) {
+        const int ex = (int)g[kScaleE];
+        s = (T)__uint_as_float((unsigned)(127 - ex) << 23);
+    }
+    cx2<T> acc = {{T(0), T(0)}, {T(0), T(0)}};
+    if (k < H) {
+        for (int i = i0 + lane; i < i1; i += kWedgeLanes) {
+            const size_t idx = (size_t)i * H + k;
+            const cx2<T> a = wspec[idx], b = wspec[(size_t)n_r * H + idx];
+            cx2<T> v = V[idx];
+            v = cx2<T>{scale(v.a, s), scale(v.b, s)};
+            if (k == 0) {   // bins 0 and n_phi/2: real parts, radial force only
+                acc.a.x = fmadd(a.a.x, v.a.x, acc.a.x);
+                acc.a.y = fmadd(b.a.x, v.a.y, acc.a.y);
+                acc.b.x = fmadd(a.b.x, v.a.x, acc.b.x);
+                acc.b.y = fmadd(b.b.x, v.a.y, acc.b.y);
+            } else {
+                acc.a = cmacc(cmacc(acc.a, v.a, a.a), v.b, b.a);
+                acc.b = cmacc(cmacc(acc.b, v.a, a.b), v.b, b.b);
+            }
+        }
+    }
+    __shared__ cx2<T> red[kWedgeLanes][64];
+    red[lane][threadIdx.x & 63] = acc;
+    __syncthreads();
+    if (lane == 0 && k < H) {
+#pragma unroll
+        for (int l = 1; l < kWedgeLanes; ++l) {
+            const cx2<T> o = red[l][threadIdx.x];
+            acc.a = acc.a + o.a;
+            acc.b = acc.b + o.b;
+        }
+        part[(size_t)blockIdx.y * H + k] = acc;
+    }
+}
+
+template <typename T>
+__global__ void k_wedge_adj_sum(const cx2<T> *__restrict__ part, int chunks, int H,
+                                cx2<T> *__restrict__ wbar) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= H) return;
+    cx2<T> acc = part[k];
+    for (int c = 1; c < chunks; ++c) {
+        const cx2<T> o = part[(size_t)c * H + k];
+        acc.a = acc.a + o.a;
+        acc.b = acc.b + o.b;
+    }
+    wbar[k] = acc;
+}
+
+// From the row transforms x = C2R(wbar.a), y = C2R(wbar.b): the wedge
+// gradient x - y / (r_0 - r_w / 2) (sigma_w enters its own density and,
+// negatively, its radial slope) and the first source row's share of that
+// slope, + y / (r_0 - r_w / 2)
+template <typename T>
+__global__ void k_wedge_adj_fin(const T *__restrict__ x, const T *__restrict__ y, int n_phi,
+                                T inv_dr, T *__restrict__ g_w, T *__restrict__ g_src0) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n_phi) return;
+    const T d = y[j] * inv_dr;
+    g_w[j] = x[j] - d;
+    g_src0[j] += d;
+}
+
+// Row chunks of the wedge transpose's first stage: enough workgroups to
+// spread the row sums over the chip, at least four rows per lane
+static void wedge_adj_chunks(int n_r, int H, int *rows, int *chunks) {
+    const int bx = (H + 63) / 64;
+    int c = std::max(1, std::min((1024 + bx - 1) / bx, (n_r + 4 * kWedgeLanes - 1) / (4 * kWedgeLanes)));
+    *rows = (n_r + c - 1) / c;
+    *chunks = (n_r + *rows - 1) / *rows;
+}
+
 int build_wedge_spectra(Plan &p, hipStream_t st) {
     const bool f64 = p.opts.dtype == PF_F64;
     DevBuf tab, rowspec, w64, twN64;
@@ -1018,8 +1112,15 @@ int build_wedge_spectra(Plan &p, hipStream_t st) {
                            (cx<float> *)p.wspec, (long)(2 * nw));
         PF_HIP(hipGetLastError());
     }
-    // workspace: the slope row (n_phi values), then the row's spectra (H pairs)
-    PF_HIP(hipMalloc(&p.wws, (size_t)p.n_phi * (f64 ? 8 : 4) + (size_t)p.H * (f64 ? 32 : 16)));
+    // workspace.  Forward: the slope row (n_phi values), then the row's
+    // spectra (H pairs).  Transpose: two rows of n_phi values, wbar (H
+    // pairs), then the stage-1 partial sums (chunks x H pairs).
+    int rows, chunks;
+    wedge_adj_chunks(p.n_r, p.H, &rows, &chunks);
+    const size_t tb = f64 ? 8 : 4, pb = f64 ? 32 : 16;
+    const size_t fwd = (size_t)p.n_phi * tb + (size_t)p.H * pb;
+    const size_t bwd = 2 * (size_t)p.n_phi * tb + (size_t)(1 + chunks) * p.H * pb;
+    PF_HIP(hipMalloc(&p.wws, std::max(fwd, bwd)));
     PF_HIP(hipStreamSynchronize(st));
     return PF_OK;
 }
@@ -1047,6 +1148,39 @@ int launch_wedge_terms(const Plan &p, const T *sigma_src, const T *sigma_w, cx<T
     PF_HIP(hipGetLastError());
     return PF_OK;
 }
+
+template <typename T>
+int launch_wedge_adjoint(const Plan &p, const cx<T> *V, T *g_src, T *g_w, hipStream_t st,
+                         unsigned *g) {
+    int rows, chunks;
+    wedge_adj_chunks(p.n_r, p.H, &rows, &chunks);
+    T *x = (T *)p.wws;
+    T *y = x + p.n_phi;
+    cx2<T> *wbar = reinterpret_cast<cx2<T> *>(y + p.n_phi);
+    cx2<T> *part = wbar + p.H;
+    const unsigned *gs = sizeof(T) == 4 ? g : nullptr;
+    hipLaunchKernelGGL(k_wedge_adj_part<T>, dim3((unsigned)((p.H + 63) / 64), (unsigned)chunks),
+                       dim3(64 * kWedgeLanes), 0, st, reinterpret_cast<const cx2<T> *>(V),
+                       (const cx2<T> *)p.wspec, p.n_r, p.H, rows, part, gs);
+    PF_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_wedge_adj_sum<T>, dim3((unsigned)((p.H + 255) / 256)), dim3(256), 0, st,
+                       (const cx2<T> *)part, chunks, p.H, wbar);
+    PF_HIP(hipGetLastError());
+    int rc = launch_rows_c2r<T>(p, reinterpret_cast<const cx<T> *>(wbar), 1, x, y,
+                                (const cx<T> *)p.twN, p.sched.rows2, st, g);
+    if (rc) return rc;
+    const double rc0 = p.r_min * std::pow(p.beta, p.s0) * 0.5 * (1.0 + p.beta);
+    const double rh = 0.5 * p.r_min * std::pow(p.beta, p.s0);
+    hipLaunchKernelGGL(k_wedge_adj_fin<T>, dim3((p.n_phi + 255) / 256), dim3(256), 0, st, x, y,
+                       p.n_phi, T(1.0 / (rc0 - rh)), g_w, g_src);
+    PF_HIP(hipGetLastError());
+    return PF_OK;
+}
+
+template int launch_wedge_adjoint<float>(const Plan &, const cx<float> *, float *, float *,
+                                         hipStream_t, unsigned *);
+template int launch_wedge_adjoint<double>(const Plan &, const cx<double> *, double *, double *,
+                                          hipStream_t, unsigned *);
 
 template int launch_wedge_terms<float>(const Plan &, const float *, const float *, cx<float> *,
                                        hipStream_t, const unsigned *);

@@ -8,8 +8,8 @@ destination [0.01, 1].
 Parity bars: relative L2 <= 1e-11 (FP64) and 1e-5 (FP32) on both force
 components, for source patches below (adjacent and with a gap), above and
 overlapping the destination, ragged sizes, all methods, with and without
-wedges; the transpose of wedge-free patch plans against the oracle's
-transposed sums."""
+wedges; the transpose of patch plans, with and without wedges, against the
+oracle's transposed sums."""
 import os
 import sys
 
@@ -139,14 +139,122 @@ def test_patch_transpose_dot_product_particle_methods(method):
     assert abs(lhs - rhs) < 1e-12 * ref
 
 
-def test_patch_transpose_with_wedges_is_refused():
-    plan = pf.PatchPlan(10, -10, 24, 32, 0.05, 2.0, wedges=True, dtype="f32")
+WEDGE_TRANSPOSE_CASES = [(10, -10, 24, 32), (33, -33, 40, 128), (6, -2, 9, 8)]
+
+
+@pytest.mark.parametrize("case", WEDGE_TRANSPOSE_CASES)
+def test_patch_transpose_with_wedges_matches_oracle(case):
+    # cotangents on the destination -> gradient on the source patch and on
+    # the wedge densities; the wedges' radial slope puts a share on the
+    # first source row.  The transforms spread their rounding over the whole
+    # field, so the first row (the innermost, whose gradient is far below
+    # the field's norm) is held to the field's norm, and its wedge share
+    # (the difference to the transpose without wedges) to 1e-2 of itself
+    n_src, s0, n_dst, n_phi = case
+    g = oracle.Grid(n_dst, n_phi, 0.05, 2.0)
+    vr = workloads.random_field(g.shape, 101 + n_src)
+    vp = workloads.random_field(g.shape, 111 + n_src)
+    _say("patch transpose with wedges %s" % (case,))
+    T = oracle.patch_tables(g, n_src, s0, 19)
+    Tw = oracle.wedge_tables(g, s0)
+    ws, ww = oracle.patch_adjoint(g, n_src, s0, T, vr, vp, Tw=Tw)
+    share = np.linalg.norm(ws[0] - oracle.patch_adjoint(g, n_src, s0, T, vr, vp)[0])
+    for dt, tol in (("f64", 1e-11), ("f32", 1e-5)):
+        plan = pf.PatchPlan(n_src, s0, n_dst, n_phi, g.r_min, g.r_max, wedges=True, dtype=dt)
+        try:
+            a = torch.tensor(vr, dtype=plan.torch_dtype, device="cuda")
+            b = torch.tensor(vp, dtype=plan.torch_dtype, device="cuda")
+            gs, gw = plan.backward(a, b)
+            torch.cuda.synchronize()
+            assert tuple(gs.shape) == (n_src, n_phi) and tuple(gw.shape) == (n_phi,)
+            got = gs.double().cpu().numpy()
+            e1 = _rel(got, ws)
+            e2 = _rel(gw.double().cpu().numpy(), ww)
+            d0 = np.linalg.norm(got[0] - ws[0])
+        finally:
+            plan.close()
+        e0, f0 = d0 / np.linalg.norm(ws), d0 / share
+        _say("  %s rel-L2 source %.2e (first row %.2e, of its wedge share %.2e) wedges %.2e"
+             % (dt, e1, e0, f0, e2))
+        assert e1 < tol and e2 < tol and e0 < tol and f0 < 1e-2, (case, dt, e1, e0, f0, e2)
+
+
+@pytest.mark.parametrize("method", ["particle", "particle+"])
+def test_patch_transpose_with_wedges_dot_product_particle_methods(method):
+    # <v, A (s, s_w)> = <g_src, s> + <g_w, s_w> through the GPU forward and
+    # transpose
+    n_src, s0, n_dst, n_phi = 12, -12, 20, 32
+    plan = pf.PatchPlan(n_src, s0, n_dst, n_phi, 0.05, 2.0, wedges=True, dtype="f64",
+                        method=method)
     try:
-        a = torch.zeros(24, 32, device="cuda")
-        with pytest.raises(pf.PFError, match="wedges"):
-            plan.backward(a, a)
+        s = torch.tensor(workloads.random_field((n_src, n_phi), 17), device="cuda")
+        w = torch.tensor(workloads.random_field((n_phi,), 18), device="cuda")
+        vr = torch.tensor(workloads.random_field((n_dst, n_phi), 19), device="cuda")
+        vp = torch.tensor(workloads.random_field((n_dst, n_phi), 20), device="cuda")
+        fr, fp = plan.forces(s, w)
+        gs, gw = plan.backward(vr, vp)
+        torch.cuda.synchronize()
+        lhs = float((fr * vr).sum() + (fp * vp).sum())
+        rhs = float((gs * s).sum() + (gw * w).sum())
+        ref = float((fr * vr).abs().sum() + (fp * vp).abs().sum())
     finally:
         plan.close()
+    _say("%s patch transpose with wedges, dot product: %.3e vs %.3e" % (method, lhs, rhs))
+    assert abs(lhs - rhs) < 1e-12 * ref
+
+
+def test_patch_transpose_with_wedges_fp32_scale():
+    # the wedge transpose runs under the transpose's FP32 grid scale:
+    # 2^110 cotangents give 2^110 times both gradients bit for bit, and
+    # 2^-100 ones 2^-100 times (normal outputs)
+    n_src, s0, n_dst, n_phi = 10, -10, 24, 32
+    plan = pf.PatchPlan(n_src, s0, n_dst, n_phi, 0.05, 2.0, wedges=True, dtype="f32")
+    try:
+        a = torch.tensor(workloads.random_field((n_dst, n_phi), 21), dtype=torch.float32,
+                         device="cuda")
+        b = torch.tensor(workloads.random_field((n_dst, n_phi), 22), dtype=torch.float32,
+                         device="cuda")
+        base = [x.clone() for x in plan.backward(a, b)]
+        for f in (2.0 ** 110, 2.0 ** -100):
+            got = plan.backward(a * f, b * f)
+            torch.cuda.synchronize()
+            for x, x1 in zip(got, base):
+                g_ = x.double().cpu().numpy()
+                want = x1.double().cpu().numpy() * f
+                assert np.isfinite(g_).all()
+                assert np.array_equal(g_[want != 0], want[want != 0]), f
+    finally:
+        plan.close()
+
+
+def test_patch_transpose_wedge_arguments():
+    plan = pf.PatchPlan(10, -10, 24, 32, 0.05, 2.0, wedges=True, dtype="f32")
+    plain = pf.PatchPlan(10, -10, 24, 32, 0.05, 2.0, dtype="f32")
+    try:
+        a = torch.zeros(24, 32, device="cuda")
+        gs = torch.empty(10, 32, device="cuda")
+        gw = torch.empty(32, device="cuda")
+        with pytest.raises(pf.PFError, match="pf_forces_patches_backward"):
+            pf.pf_forces_backward(plan.handle, a.data_ptr(), a.data_ptr(), gs.data_ptr())
+        with pytest.raises(pf.PFError, match="g_sigma_wedge is required"):
+            pf.pf_forces_patches_backward(plan.handle, a.data_ptr(), a.data_ptr(),
+                                          gs.data_ptr(), 0)
+        with pytest.raises(pf.PFError, match="must be NULL"):
+            pf.pf_forces_patches_backward(plain.handle, a.data_ptr(), a.data_ptr(),
+                                          gs.data_ptr(), gw.data_ptr())
+        # without wedges the call is pf_forces_backward
+        vr = torch.tensor(workloads.random_field((24, 32), 23), dtype=torch.float32,
+                          device="cuda")
+        vp = torch.tensor(workloads.random_field((24, 32), 24), dtype=torch.float32,
+                          device="cuda")
+        pf.pf_forces_patches_backward(plain.handle, vr.data_ptr(), vp.data_ptr(),
+                                      gs.data_ptr(), 0)
+        want = plain.backward(vr, vp)
+        torch.cuda.synchronize()
+        assert torch.equal(gs, want)
+    finally:
+        plan.close()
+        plain.close()
 
 
 def test_patch_with_one_trapezoid_and_wedges():
