@@ -63,9 +63,9 @@ def _load():
     lib.or_forward_particle_o.argtypes = [i, i, d, d, i, i, P, P, P, i64, P, P]
     lib.or_patch_tables.argtypes = [i, i, i, i, d, d, i, i, P, P]
     lib.or_wedge_tables.argtypes = [i, i, d, d, i, i, P]
-    lib.or_patch_forward.argtypes = [i, i, i, i, d, d, P, P, P, P, P, i64, P, P]
-    lib.or_patch_adjoint.argtypes = [i, i, i, i, d, d, P, P, P, P, i64, P, P, P]
-    lib.or_patch_particle.argtypes = [i, i, i, i, d, d, i, P, P, P, P, i64, P, P]
+    lib.or_patch_forward.argtypes = [i, i, i, i, i, d, d, P, P, P, P, P, i64, P, P]
+    lib.or_patch_adjoint.argtypes = [i, i, i, i, i, d, d, P, P, P, P, i64, P, P, P]
+    lib.or_patch_particle.argtypes = [i, i, i, i, i, d, d, i, P, P, P, P, i64, P, P]
     lib.or_cart_tables.argtypes = [i, i, d, d, i, P]
     lib.or_cart_slopes.argtypes = [i, i, d, d, P, P, P]
     lib.or_cart_forward.argtypes = [i, i, d, d, P, P, P, i64, P, P]
@@ -337,23 +337,25 @@ def _dest(grid, dest):
 
 
 def patch_forward(grid: Grid, n_src: int, s0: int, T, sigma_src, Tw=None, sigma_w=None,
-                  dest=None):
+                  dest=None, col0: int = 0):
     """F_r, F_phi on the destination patch from the source patch (and the
-    origin wedges when Tw and sigma_w are given), plain double sums."""
+    origin wedges when Tw and sigma_w are given), plain double sums; col0
+    turns the source (and its wedges) by that many whole cells in phi."""
     s = _f64(sigma_src)
     assert s.shape == (n_src, grid.n_phi)
     T = _f64(T)
     Tw = _f64(Tw) if Tw is not None else None
     sw = _f64(sigma_w) if sigma_w is not None else None
     d, nd, fr, fp = _dest(grid, dest)
-    if _load().or_patch_forward(int(n_src), int(s0), grid.n_r, grid.n_phi, grid.r_min,
+    if _load().or_patch_forward(int(n_src), int(s0), int(col0), grid.n_r, grid.n_phi, grid.r_min,
                                 grid.r_max, _p(T), _p(s), _p(Tw), _p(sw), _p(d), nd, _p(fr),
                                 _p(fp)):
         raise RuntimeError("or_patch_forward failed")
     return fr, fp
 
 
-def patch_adjoint(grid: Grid, n_src: int, s0: int, T, v_r, v_phi, src=None, Tw=None):
+def patch_adjoint(grid: Grid, n_src: int, s0: int, T, v_r, v_phi, src=None, Tw=None,
+                  col0: int = 0):
     """Transpose of :func:`patch_forward`: cotangents on the destination
     patch -> gradient on the source patch [n_src][n_phi] (or at the flat
     source indices ``src``), plain double sums.  With the wedge tables Tw
@@ -369,7 +371,7 @@ def patch_adjoint(grid: Grid, n_src: int, s0: int, T, v_r, v_phi, src=None, Tw=N
         ns, g = s.size, np.empty(s.size)
     Tw = _f64(Tw) if Tw is not None else None
     gw = np.empty(grid.n_phi) if Tw is not None else None
-    if _load().or_patch_adjoint(int(n_src), int(s0), grid.n_r, grid.n_phi, grid.r_min,
+    if _load().or_patch_adjoint(int(n_src), int(s0), int(col0), grid.n_r, grid.n_phi, grid.r_min,
                                 grid.r_max, _p(T), _p(vr), _p(vp), _p(s), ns, _p(g), _p(Tw),
                                 _p(gw)):
         raise RuntimeError("or_patch_adjoint failed")
@@ -377,7 +379,7 @@ def patch_adjoint(grid: Grid, n_src: int, s0: int, T, v_r, v_phi, src=None, Tw=N
 
 
 def patch_particle(grid: Grid, n_src: int, s0: int, sigma_src, sigma_w=None, plus=False,
-                   self_k=None, dest=None):
+                   self_k=None, dest=None, col0: int = 0):
     """Particle (plus=False) or modified particle method between patches,
     point masses in physical coordinates, wedges as point masses."""
     s = _f64(sigma_src)
@@ -386,7 +388,7 @@ def patch_particle(grid: Grid, n_src: int, s0: int, sigma_src, sigma_w=None, plu
     sk = _f64(self_k)
     sw = _f64(sigma_w) if sigma_w is not None else None
     d, nd, fr, fp = _dest(grid, dest)
-    if _load().or_patch_particle(int(n_src), int(s0), grid.n_r, grid.n_phi, grid.r_min,
+    if _load().or_patch_particle(int(n_src), int(s0), int(col0), grid.n_r, grid.n_phi, grid.r_min,
                                  grid.r_max, int(bool(plus)), _p(sk), _p(s), _p(sw), _p(d), nd,
                                  _p(fr), _p(fp)):
         raise RuntimeError("or_patch_particle failed")

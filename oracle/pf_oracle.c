@@ -1213,8 +1213,17 @@ int or_wedge_tables(int n_dst, int n_phi, double r_min, double r_max, int s0, in
 
 /* Forces on the destination patch from the source patch (tables T of
  * or_patch_tables) and, when Tw and sigma_w are given, from the origin
- * wedges (tables Tw of or_wedge_tables, wedge densities sigma_w[N_phi]). */
-int or_patch_forward(int n_src, int s0, int n_dst, int n_phi, double r_min, double r_max,
+ * wedges (tables Tw of or_wedge_tables, wedge densities sigma_w[N_phi]).
+ * c0: the source patch and its wedges turned by c0 whole cells in phi
+ * (source column j' centred at (j' + c0 + 1/2) dphi): the tables are taken
+ * at the offset j - j' - c0 (mod N_phi). */
+static int wrap_n(long n, int n_phi)
+{
+    n %= n_phi;
+    return (int)(n < 0 ? n + n_phi : n);
+}
+
+int or_patch_forward(int n_src, int s0, int c0, int n_dst, int n_phi, double r_min, double r_max,
                      const double *T, const double *sigma_src, const double *Tw,
                      const double *sigma_w, const int64_t *dest, int64_t n_dest, double *f_r,
                      double *f_phi)
@@ -1259,9 +1268,7 @@ int or_patch_forward(int n_src, int s0, int n_dst, int n_phi, double r_min, doub
                              *gp = dp + (long)ip * n_phi;
                 double x0 = 0, xr = 0, xp = 0, y0 = 0, yr = 0, yp = 0;
                 for (int jp = 0; jp < n_phi; ++jp) {
-                    int n = j - jp;
-                    if (n < 0) n += n_phi;
-                    const long t = row * n_phi + n;
+                    const long t = row * n_phi + wrap_n((long)j - jp - c0, n_phi);
                     x0 += sg[jp] * T[t];
                     xr += gr[jp] * T[plane + t];
                     xp += gp[jp] * T[2 * plane + t];
@@ -1275,9 +1282,7 @@ int or_patch_forward(int n_src, int s0, int n_dst, int n_phi, double r_min, doub
             if (Tw && sigma_w) {
                 double x0 = 0, xr = 0, xp = 0, y0 = 0, yr = 0, yp = 0;
                 for (int jp = 0; jp < n_phi; ++jp) {
-                    int n = j - jp;
-                    if (n < 0) n += n_phi;
-                    const long t = (long)i * n_phi + n;
+                    const long t = (long)i * n_phi + wrap_n((long)j - jp - c0, n_phi);
                     x0 += sigma_w[jp] * Tw[t];
                     xr += wr[jp] * Tw[wplane + t];
                     xp += wp[jp] * Tw[2 * wplane + t];
@@ -1307,8 +1312,8 @@ done:
  * slope -- the difference towards the first source row -- adds to the
  * gradient of that row (to g only where src is NULL, i.e. the full grid). */
 static void adj_u_patch(int n_src, int n_dst, int n_phi, const double *rd, const double *T,
-                        const double *v_r, const double *v_p, int ip, int jp, double *us,
-                        double *ug, double *uh)
+                        const double *v_r, const double *v_p, int ip, int jp, int c0,
+                        double *us, double *ug, double *uh)
 {
     const long rows = (long)n_src + n_dst - 1;
     const long plane = rows * (long)n_phi;
@@ -1322,8 +1327,7 @@ static void adj_u_patch(int n_src, int n_dst, int n_phi, const double *rd, const
         const double *vr = v_r + (long)i * n_phi, *vp = v_p + (long)i * n_phi;
         double xs = 0, xg = 0, xh = 0;
         for (int j = 0; j < n_phi; ++j) {
-            int n = j - jp;
-            if (n < 0) n += n_phi;
+            const int n = wrap_n((long)j - jp - c0, n_phi);
             xs += vr[j] * t0[n] + vp[j] * u0[n];
             xg += vr[j] * tr[n] + vp[j] * ur[n];
             xh += vr[j] * tp[n] + vp[j] * up[n];
@@ -1339,8 +1343,8 @@ static void adj_u_patch(int n_src, int n_dst, int n_phi, const double *rd, const
 
 /* sums of the cotangents against the wedge tables for wedge jp */
 static void adj_u_wedge(int n_dst, int n_phi, const double *rd, const double *Tw,
-                        const double *v_r, const double *v_p, int jp, double *us, double *ug,
-                        double *uh)
+                        const double *v_r, const double *v_p, int jp, int c0, double *us,
+                        double *ug, double *uh)
 {
     const long wplane = (long)n_dst * n_phi;
     acc_t s = {0, 0}, g = {0, 0}, h = {0, 0};
@@ -1348,9 +1352,7 @@ static void adj_u_wedge(int n_dst, int n_phi, const double *rd, const double *Tw
         const double *vr = v_r + (long)i * n_phi, *vp = v_p + (long)i * n_phi;
         double xs = 0, xg = 0, xh = 0;
         for (int j = 0; j < n_phi; ++j) {
-            int n = j - jp;
-            if (n < 0) n += n_phi;
-            const long t = (long)i * n_phi + n;
+            const long t = (long)i * n_phi + wrap_n((long)j - jp - c0, n_phi);
             xs += vr[j] * Tw[t] + vp[j] * Tw[3 * wplane + t];
             xg += vr[j] * Tw[wplane + t] + vp[j] * Tw[4 * wplane + t];
             xh += vr[j] * Tw[2 * wplane + t] + vp[j] * Tw[5 * wplane + t];
@@ -1364,7 +1366,7 @@ static void adj_u_wedge(int n_dst, int n_phi, const double *rd, const double *Tw
     *uh = acc_get(&h);
 }
 
-int or_patch_adjoint(int n_src, int s0, int n_dst, int n_phi, double r_min, double r_max,
+int or_patch_adjoint(int n_src, int s0, int c0, int n_dst, int n_phi, double r_min, double r_max,
                      const double *T, const double *v_r, const double *v_phi,
                      const int64_t *src, int64_t n_idx, double *g, const double *Tw,
                      double *gw)
@@ -1390,18 +1392,18 @@ int or_patch_adjoint(int n_src, int s0, int n_dst, int n_phi, double r_min, doub
             const long p = src ? (long)src[q] : q;
             const int ip = (int)(p / n_phi), jp = (int)(p % n_phi);
             double us, ug, uh, a, b, c;
-            adj_u_patch(n_src, n_dst, n_phi, rd, T, v_r, v_phi, ip, jp, &us, &ug, &uh);
+            adj_u_patch(n_src, n_dst, n_phi, rd, T, v_r, v_phi, ip, jp, c0, &us, &ug, &uh);
             double tot = us;
             for (int i2 = ip - 1; i2 <= ip + 1; ++i2) {
                 if (i2 < 0 || i2 >= n_src) continue;
                 const double cf = dr_coef(n_src, rs, 2, i2, ip);
                 if (cf == 0.0) continue;
-                adj_u_patch(n_src, n_dst, n_phi, rd, T, v_r, v_phi, i2, jp, &a, &b, &c);
+                adj_u_patch(n_src, n_dst, n_phi, rd, T, v_r, v_phi, i2, jp, c0, &a, &b, &c);
                 tot += cf * b;
             }
             for (int d = -1; d <= 1; d += 2) {
                 const int j2 = ((jp - d) % n_phi + n_phi) % n_phi;
-                adj_u_patch(n_src, n_dst, n_phi, rd, T, v_r, v_phi, ip, j2, &a, &b, &c);
+                adj_u_patch(n_src, n_dst, n_phi, rd, T, v_r, v_phi, ip, j2, c0, &a, &b, &c);
                 tot += dp_coef(2, dphi, d) * c;
             }
             g[q] = tot;
@@ -1417,7 +1419,7 @@ int or_patch_adjoint(int n_src, int s0, int n_dst, int n_phi, double r_min, doub
 #pragma omp parallel for schedule(dynamic, 1)
 #endif
         for (int jp = 0; jp < n_phi; ++jp)
-            adj_u_wedge(n_dst, n_phi, rd, Tw, v_r, v_phi, jp, &us0[jp], &ug0[jp], &uh0[jp]);
+            adj_u_wedge(n_dst, n_phi, rd, Tw, v_r, v_phi, jp, c0, &us0[jp], &ug0[jp], &uh0[jp]);
         for (int jp = 0; jp < n_phi; ++jp) {
             /* sigma_w[jp] enters the wedge density, its radial slope
              * (sigma_src[0] - sigma_w) / (r_0 - r_w / 2) and its periodic
@@ -1440,8 +1442,10 @@ done:
  * centres, wedges (if sigma_w) point masses sigma r_w^2 dphi / 2 at
  * (r_w / 2, phi_j'); a destination cell that coincides with a source cell
  * feels no force from it, and plus = 1 adds there the self-cell correction
- * of Eq. 34-37 with the source patch's slopes. */
-int or_patch_particle(int n_src, int s0, int n_dst, int n_phi, double r_min, double r_max,
+ * of Eq. 34-37 with the source patch's slopes.  c0: the source patch and
+ * its wedges turned by c0 whole cells (source column j' at azimuth
+ * (j' + c0 + 1/2) dphi). */
+int or_patch_particle(int n_src, int s0, int c0, int n_dst, int n_phi, double r_min, double r_max,
                       int plus, const double *self, const double *sigma_src,
                       const double *sigma_w, const int64_t *dest, int64_t n_dest, double *f_r,
                       double *f_phi)
@@ -1477,10 +1481,10 @@ int or_patch_particle(int n_src, int s0, int n_dst, int n_phi, double r_min, dou
                 const double area = 0.5 * (pow(beta, 2.0 * (k + 1)) - pow(beta, 2.0 * k)) *
                                     r_min * r_min * dphi;
                 for (int jp = 0; jp < n_phi; ++jp) {
-                    if (k == i && jp == j) continue;
+                    if (k == i && wrap_n((long)jp + c0 - j, n_phi) == 0) continue;
                     const double M = sigma_src[(long)ip * n_phi + jp] * area;
                     if (M == 0.0) continue;
-                    const double d = (jp - j) * dphi;
+                    const double d = ((long)jp + c0 - j) * dphi;
                     const double sh = sin(0.5 * d);
                     const double D = (ri - r2) * (ri - r2) + 4.0 * ri * r2 * sh * sh;
                     const double w = M / (D * sqrt(D));
@@ -1493,7 +1497,7 @@ int or_patch_particle(int n_src, int s0, int n_dst, int n_phi, double r_min, dou
                 for (int jp = 0; jp < n_phi; ++jp) {
                     const double M = sigma_w[jp] * area;
                     if (M == 0.0) continue;
-                    const double d = (jp - j) * dphi;
+                    const double d = ((long)jp + c0 - j) * dphi;
                     const double sh = sin(0.5 * d);
                     const double D = (ri - r2) * (ri - r2) + 4.0 * ri * r2 * sh * sh;
                     const double w = M / (D * sqrt(D));
@@ -1504,7 +1508,7 @@ int or_patch_particle(int n_src, int s0, int n_dst, int n_phi, double r_min, dou
             double fr = acc_get(&ar), fp = acc_get(&ap);
             const int ip = i - s0;
             if (plus && ip >= 0 && ip < n_src) {
-                const long c = (long)ip * n_phi + j;
+                const long c = (long)ip * n_phi + wrap_n((long)j - c0, n_phi);
                 fr += sigma_src[c] * self[0] + ri * dr[c] * self[1];
                 fp += dp[c] * self[2];
             }

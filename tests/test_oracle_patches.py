@@ -221,3 +221,82 @@ def test_patch_adjoint_wedge_gradient_by_unit_wedges():
         fr, fp = oracle.patch_forward(g, n_src, s0, T, z, Tw=Tw, sigma_w=e)
         want = (fr * vr).sum() + (fp * vp).sum()
         assert abs(gw[j] - want) < 1e-12 * (np.abs(fr * vr).sum() + np.abs(fp * vp).sum())
+
+
+def _mirror_field(shape, j0, seed):
+    # symmetric about the centre of column j0: s[:, j0 + d] = s[:, j0 - d]
+    s = workloads.random_field(shape, seed) + 0.5
+    n = shape[-1]
+    j = np.arange(n)
+    return 0.5 * (s + s[..., (2 * j0 - j) % n])
+
+
+@pytest.mark.parametrize("c0", [3, -5, 21])
+def test_turned_patch_mirror_line(c0):
+    # a source (patch and wedges) mirror-symmetric about its column j0, turned
+    # by c0 cells, is mirror-symmetric about destination column j0 + c0: F_phi
+    # vanishes there and F_r is even about it.  A wrong sign or size of the
+    # turn moves the line
+    g = oracle.Grid(7, 16, 0.3, 2.0)
+    n_src, s0, j0 = 6, -6, 2
+    T = oracle.patch_tables(g, n_src, s0, 19)
+    Tw = oracle.wedge_tables(g, s0)
+    sig = _mirror_field((n_src, g.n_phi), j0, 121)
+    sw = _mirror_field((g.n_phi,), j0, 122)
+    jm = (j0 + c0) % g.n_phi
+    j = np.arange(g.n_phi)
+    for fr, fp in (oracle.patch_forward(g, n_src, s0, T, sig, Tw=Tw, sigma_w=sw, col0=c0),
+                   oracle.patch_particle(g, n_src, s0, sig, sw, col0=c0)):
+        scale = np.abs(fp).max()
+        assert scale > 1e-3 * np.abs(fr).max()
+        np.testing.assert_allclose(fp[:, jm], 0.0, atol=1e-13 * scale)
+        np.testing.assert_allclose(fr, fr[:, (2 * jm - j) % g.n_phi], rtol=1e-13)
+        np.testing.assert_allclose(fp, -fp[:, (2 * jm - j) % g.n_phi], atol=1e-13 * scale)
+        # and not about the unturned column
+        if jm != j0:
+            assert np.abs(fp[:, j0]).max() > 1e-3 * scale
+
+
+@pytest.mark.parametrize("plus", [False, True])
+def test_turned_patch_equals_rolled_source(plus):
+    # turning the source by c0 cells equals rolling its columns by c0 (the
+    # tables' own periodicity), for overlapping patches too, where the turn
+    # moves the singular self cell with the source
+    g = oracle.Grid(7, 16, 0.3, 2.0)
+    for n_src, s0, c0 in ((6, -6, 3), (8, -3, -7)):
+        T = oracle.patch_tables(g, n_src, s0, 19)
+        Tw = oracle.wedge_tables(g, s0) if s0 + n_src <= 0 else None
+        sig = workloads.random_field((n_src, g.n_phi), 131) + 0.5
+        sw = workloads.random_field((g.n_phi,), 132) + 0.5 if Tw is not None else None
+        roll = lambda a: None if a is None else np.roll(a, c0, axis=-1)
+        a = oracle.patch_forward(g, n_src, s0, T, sig, Tw=Tw, sigma_w=sw, col0=c0)
+        b = oracle.patch_forward(g, n_src, s0, T, roll(sig), Tw=Tw, sigma_w=roll(sw))
+        # (the same terms summed from another starting column)
+        np.testing.assert_allclose(a[0], b[0], rtol=1e-14, atol=1e-15 * np.abs(b[0]).max())
+        np.testing.assert_allclose(a[1], b[1], rtol=1e-14, atol=1e-15 * np.abs(b[1]).max())
+        a = oracle.patch_particle(g, n_src, s0, sig, sw, plus=plus, col0=c0)
+        b = oracle.patch_particle(g, n_src, s0, roll(sig), roll(sw), plus=plus)
+        np.testing.assert_allclose(a[0], b[0], rtol=1e-13, atol=1e-13 * np.abs(b[0]).max())
+        np.testing.assert_allclose(a[1], b[1], rtol=1e-13, atol=1e-13 * np.abs(b[1]).max())
+
+
+@pytest.mark.parametrize("c0", [5, -9])
+def test_turned_patch_adjoint_dot_product(c0):
+    g = oracle.Grid(7, 16, 0.3, 2.0)
+    n_src, s0 = 6, -6
+    T = oracle.patch_tables(g, n_src, s0, 19)
+    Tw = oracle.wedge_tables(g, s0)
+    sig = workloads.random_field((n_src, g.n_phi), 141)
+    sw = workloads.random_field((g.n_phi,), 142)
+    vr = workloads.random_field(g.shape, 143)
+    vp = workloads.random_field(g.shape, 144)
+    fr, fp = oracle.patch_forward(g, n_src, s0, T, sig, Tw=Tw, sigma_w=sw, col0=c0)
+    gs, gw = oracle.patch_adjoint(g, n_src, s0, T, vr, vp, Tw=Tw, col0=c0)
+    lhs = (fr * vr).sum() + (fp * vp).sum()
+    rhs = (gs * sig).sum() + (gw * sw).sum()
+    assert abs(lhs - rhs) < 1e-12 * (np.abs(fr * vr).sum() + np.abs(fp * vp).sum())
+    # the transpose of a turn is the opposite roll of the unturned transpose
+    gs0, gw0 = oracle.patch_adjoint(g, n_src, s0, T, vr, vp, Tw=Tw)
+    np.testing.assert_allclose(gs, np.roll(gs0, -c0, axis=1), rtol=1e-12,
+                               atol=1e-13 * np.abs(gs0).max())
+    np.testing.assert_allclose(gw, np.roll(gw0, -c0), rtol=1e-12, atol=1e-13 * np.abs(gw0).max())
