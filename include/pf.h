@@ -171,6 +171,18 @@ pf_plan pf_plan_create(int n_r, int n_phi, double r_min, double r_max);
 pf_plan pf_plan_create_patches(int n_src, int src_row0, int n_dst, int n_phi, double r_min,
                                double r_max, int wedges);
 
+/* Turn the source patch of a patch plan, and its origin wedges, by
+ * src_col0 whole cells in phi: source column j' is then centred at
+ * (j' + src_col0 + 1/2) dphi (Sec. 3.2.1: a constant shift between two
+ * patches that share beta and dphi is a constant phase in the Fourier
+ * domain; here exp(-2 pi i k src_col0 / n_phi) on azimuthal bin k, applied
+ * by the forward's last pass, and its conjugate by the transpose's).  Any
+ * integer (taken modulo n_phi); 0 (the default) for no turn.  Takes effect
+ * for the calls enqueued after it, built or not; no rebuild.  PF_EINVAL for
+ * a plan that is not a patch plan.  A shift that is not a whole number of
+ * cells is not built: it would break the kernels' parity in phi.        */
+int pf_plan_set_src_col0(pf_plan plan, int src_col0);
+
 /* Build the kernel tables and their spectra on the current device
  * (Eq. 30-33, 41-46, A22-A35): one-time work, FP64 throughout, enqueued on
  * `stream` and synchronised before returning.  opts == NULL means defaults.

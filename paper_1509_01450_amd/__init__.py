@@ -43,7 +43,7 @@ EXPORTS = ("pf_build_opts_default", "pf_plan_create", "pf_kernels_build", "pf_fo
            "pf_plan_schedule", "pf_plan_set_schedule", "pf_plan_selfcell", "pf_plan_tables",
            "pf_plan_destroy",
            "pf_last_error", "pf_version", "pf_plan_create_patches", "pf_forces_patches",
-           "pf_forces_patches_backward",
+           "pf_forces_patches_backward", "pf_plan_set_src_col0",
            "pf_cart_create", "pf_cart_build", "pf_cart_forces",
            "pf_cart_forces_timed", "pf_cart_geometry", "pf_cart_destroy")
 
@@ -109,6 +109,8 @@ def load():
     lib.pf_forces_patches.restype = I
     lib.pf_forces_patches_backward.argtypes = [P, P, P, P, P, P]
     lib.pf_forces_patches_backward.restype = I
+    lib.pf_plan_set_src_col0.argtypes = [P, I]
+    lib.pf_plan_set_src_col0.restype = I
     lib.pf_cart_create.argtypes = [I, I, D, D]
     lib.pf_cart_create.restype = P
     lib.pf_cart_build.argtypes = [P, I, I, P]
@@ -241,6 +243,10 @@ def pf_forces_patches(plan: int, sigma_src: int, sigma_wedge: int, f_r: int, f_p
                       stream: int = 0) -> None:
     _check(load().pf_forces_patches(plan, sigma_src, sigma_wedge or None, f_r, f_phi,
                                     stream or None))
+
+
+def pf_plan_set_src_col0(plan: int, src_col0: int) -> None:
+    _check(load().pf_plan_set_src_col0(plan, int(src_col0)))
 
 
 def pf_forces_patches_backward(plan: int, g_fr: int, g_fphi: int, g_sigma_src: int,
@@ -532,16 +538,18 @@ class PatchPlan(Plan):
     """The force of a source patch (rows src_row0 .. src_row0 + n_src - 1 of
     the log-polar grid of the destination patch [r_min, r_max], n_dst rows)
     on the destination patch, optionally with the origin wedges below the
-    source (Sec. 3.2.1, Eq. 27-29)."""
+    source (Sec. 3.2.1, Eq. 27-29); src_col0 turns the source and its
+    wedges by that many whole cells in phi (``set_src_col0`` changes it)."""
 
     def __init__(self, n_src, src_row0, n_dst, n_phi, r_min, r_max, wedges=False, dtype="f32",
                  n_tpz=19, cover_per=10, build=True, table_mode="sim", self_mode="cartesian",
-                 method="sim", keep_tables=False):
+                 method="sim", keep_tables=False, src_col0=0):
         self.n_r, self.n_phi = int(n_dst), int(n_phi)
         self.n_src, self.src_row0 = int(n_src), int(src_row0)
         self.r_min, self.r_max = float(r_min), float(r_max)
         self.wedges = bool(wedges)
         self.handle = pf_plan_create_patches(n_src, src_row0, n_dst, n_phi, r_min, r_max, wedges)
+        self.set_src_col0(src_col0)
         self.dtype = None
         if build:
             self.build(dtype, n_tpz, cover_per, keep_tables, table_mode, self_mode, method)
@@ -579,6 +587,11 @@ class PatchPlan(Plan):
                           sigma_wedge.data_ptr() if sigma_wedge is not None else 0,
                           fr.data_ptr(), fp.data_ptr(), _stream())
         return fr, fp
+
+    def set_src_col0(self, src_col0):
+        """Turn the source (and wedges) by src_col0 whole cells in phi."""
+        pf_plan_set_src_col0(self.handle, src_col0)
+        self.src_col0 = int(src_col0)
 
     def backward(self, g_fr, g_fphi, out=None):
         """Transpose: cotangents on the destination patch [n_dst][n_phi] ->

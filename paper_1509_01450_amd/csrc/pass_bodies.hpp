@@ -288,13 +288,17 @@ __device__ __forceinline__ void body_rows_r2c(int unit, int G, cx<T> *__restrict
 }
 
 // Pass C: packed half rows (in: [n_rows][M] complex for C = 1, pairs for
-// C = 2) -> real rows of out0 (and out1), unnormalised inverse.
+// C = 2) -> real rows of out0 (and out1), unnormalised inverse.  turn in
+// [0, N): the rows come out turned by that many points (out[j] is the
+// inverse at j - turn), bin k taken times exp(-2 pi i k turn / N) -- the
+// constant phase of a whole-cell shift in phi; 0 for no turn.
 template <typename T, int M, int E, int C>
 __device__ __forceinline__ void body_rows_c2r(int unit, int G, cx<T> *__restrict__ buf,
                                               const cx<T> *__restrict__ in, int n_rows,
                                               T *__restrict__ out0, T *__restrict__ out1,
                                               const cx<T> *__restrict__ twN,
-                                              unsigned *__restrict__ gscale = nullptr) {
+                                              unsigned *__restrict__ gscale = nullptr,
+                                              int turn = 0) {
     constexpr int TH = M / E;
     constexpr int N = 2 * M;
     const int gi = threadIdx.x / TH, t = threadIdx.x % TH;
@@ -320,6 +324,20 @@ __device__ __forceinline__ void body_rows_c2r(int unit, int G, cx<T> *__restrict
             xk[C - 1][e] = a.b;
         }
         wk[e] = twN[k];   // exp(-2 pi i k / N)
+    }
+    if (turn) {   // uniform
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int k = t + e * TH;
+            const cx<T> ph = twN[(k * turn) & (N - 1)];
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                if (k == 0)   // packed (X_0, X_M): X_M times (-1)^turn
+                    xk[c][e].y = (turn & 1) ? -xk[c][e].y : xk[c][e].y;
+                else
+                    xk[c][e] = cmul(xk[c][e], ph);
+            }
+        }
     }
 #pragma unroll
     for (int c = 0; c < C; ++c)

@@ -164,7 +164,8 @@ int forces_t(const Plan &p, const T *sigma, const T *sigma_w, T *fr, T *fp, hipS
         rc = pf::launch_wedge_terms<T>(p, sigma, sigma_w, Z, st, g);
         if (rc) return rc;
     }
-    return pf::launch_rows_c2r<T>(p, Z, p.n_r, fr, fp, (const C *)p.twN, p.sched.rows2, st, g);
+    return pf::launch_rows_c2r<T>(p, Z, p.n_r, fr, fp, (const C *)p.twN, p.sched.rows2, st, g,
+                                  p.col0);
 }
 
 // Transpose: pass A on the n_r destination rows of both cotangents, the
@@ -181,7 +182,8 @@ int backward_t(const Plan &p, const T *gr, const T *gp, T *gs, T *gw, hipStream_
     rc = pf::launch_cols_adj<T>(p, V, D, (const C *)p.spec, (const C *)p.twL, p.sched.cols_adj,
                                 st, g);
     if (rc) return rc;
-    rc = pf::launch_rows_c2r<T>(p, D, p.n_in, gs, nullptr, (const C *)p.twN, p.sched.rows, st, g);
+    rc = pf::launch_rows_c2r<T>(p, D, p.n_in, gs, nullptr, (const C *)p.twN, p.sched.rows, st, g,
+                                -p.col0);
     if (rc || !p.wedges) return rc;
     return pf::launch_wedge_adjoint<T>(p, V, gs, gw, st, g);
 }
@@ -215,10 +217,10 @@ int timed_t(const Plan &p, bool bwd, const void *in0, const void *in1, void *out
     for (int k = 0; k < reps && !rc; ++k) {
         if (!bwd)
             rc = pf::launch_rows_c2r<T>(p, W1, p.n_r, (T *)out0, (T *)out1, (const C *)p.twN,
-                                        p.sched.rows2, st, g);
+                                        p.sched.rows2, st, g, p.col0);
         else
             rc = pf::launch_rows_c2r<T>(p, W2, p.n_in, (T *)out0, nullptr, (const C *)p.twN,
-                                        p.sched.rows, st, g);
+                                        p.sched.rows, st, g, -p.col0);
     }
     if (rc) return rc;
     PF_HIP(hipEventRecord(ev[3], st));
@@ -317,6 +319,21 @@ pf_plan pf_plan_create_patches(int n_src, int src_row0, int n_dst, int n_phi, do
     p.L = L;
     p.ldspec = L / 2 + 1;
     return h;
+}
+
+int pf_plan_set_src_col0(pf_plan h, int src_col0) {
+    pf::clear_error();
+    if (!h) {
+        pf::set_error("null plan");
+        return PF_EINVAL;
+    }
+    if (!h->p.patch) {
+        pf::set_error("an azimuthal turn needs a patch plan");
+        return PF_EINVAL;
+    }
+    const int n = h->p.n_phi;
+    h->p.col0 = ((src_col0 % n) + n) % n;
+    return PF_OK;
 }
 
 void pf_plan_destroy(pf_plan h) {

@@ -58,6 +58,7 @@ struct Plan {
     int n_in = 0, s0 = 0;
     bool patch = false;    // made by pf_plan_create_patches
     bool wedges = false;   // origin wedges [0, r_min beta^s0] below the source
+    int col0 = 0;          // patch plans: source (and wedges) turned by col0 cells in phi
     double r_min = 0, r_max = 0, beta = 0, dphi = 0;
     // radial slope coefficients of g = r delta^r (three-point central, first
     // and last row); so = slope order of the build (2 or 4) and c4 the
@@ -101,7 +102,8 @@ int launch_rows_r2c(const Plan &p, const T *in0, const T *in1, int n_rows, cx<T>
                     const cx<T> *twN, Shape s, hipStream_t st, unsigned *g = nullptr);
 template <typename T>
 int launch_rows_c2r(const Plan &p, const cx<T> *in, int n_rows, T *out0, T *out1,
-                    const cx<T> *twN, Shape s, hipStream_t st, unsigned *g = nullptr);
+                    const cx<T> *twN, Shape s, hipStream_t st, unsigned *g = nullptr,
+                    int turn = 0);
 // Column pass of the forward map (u-FFT, spectral multiply-accumulate with
 // the spectral radial slope, inverse u-FFTs, crop): S ([n_in][H]) -> pairs
 // Z ([n_r][H]); g: the scale words pass A noted (nullptr: unscaled).

@@ -29,11 +29,11 @@ template <typename T, int M, int E, int C>
 __global__ __launch_bounds__(512) void k_rows_c2r(const cx<T> *__restrict__ in, int n_rows,
                                                   T *__restrict__ out0, T *__restrict__ out1,
                                                   const cx<T> *__restrict__ twN,
-                                                  unsigned *__restrict__ gscale) {
+                                                  unsigned *__restrict__ gscale, int turn) {
     extern __shared__ unsigned char smem_raw[];
     body_rows_c2r<T, M, E, C>(blockIdx.x, blockDim.x / (M / E),
                               reinterpret_cast<cx<T> *>(smem_raw), in, n_rows, out0, out1, twN,
-                              gscale);
+                              gscale, turn);
 }
 
 // Forward column pass for any G, with one dynamic LDS array: used where the
@@ -248,7 +248,7 @@ struct Disp {
     }
     template <int N, int E, int C>
     static int c2r(const cx<T> *in, int n_rows, T *o0, T *o1, const cx<T> *tw, int G,
-                   hipStream_t st, unsigned *g) {
+                   hipStream_t st, unsigned *g, int turn) {
         if constexpr (E <= N) {
             constexpr int TH = N / E;
             const int blocks = (n_rows + G - 1) / G;
@@ -256,7 +256,7 @@ struct Disp {
             int rc = allow_lds(k_rows_c2r<T, N, E, C>, lds);
             if (rc) return rc;
             hipLaunchKernelGGL((k_rows_c2r<T, N, E, C>), dim3(blocks), dim3(G * TH), lds, st, in,
-                               n_rows, o0, o1, tw, g);
+                               n_rows, o0, o1, tw, g, turn);
             PF_HIP(hipGetLastError());
             return PF_OK;
         }
@@ -359,18 +359,18 @@ struct Disp {
     }
     template <int N>
     static int c2r_e(int E, const cx<T> *in, int n_rows, T *o0, T *o1, const cx<T> *tw, int G,
-                     hipStream_t st, unsigned *g) {
+                     hipStream_t st, unsigned *g, int turn) {
         if (o1) {
             switch (E) {
-                case 4: return c2r<N, 4, 2>(in, n_rows, o0, o1, tw, G, st, g);
-                case 8: return c2r<N, 8, 2>(in, n_rows, o0, o1, tw, G, st, g);
-                case 16: return c2r<N, 16, 2>(in, n_rows, o0, o1, tw, G, st, g);
+                case 4: return c2r<N, 4, 2>(in, n_rows, o0, o1, tw, G, st, g, turn);
+                case 8: return c2r<N, 8, 2>(in, n_rows, o0, o1, tw, G, st, g, turn);
+                case 16: return c2r<N, 16, 2>(in, n_rows, o0, o1, tw, G, st, g, turn);
             }
         } else {
             switch (E) {
-                case 4: return c2r<N, 4, 1>(in, n_rows, o0, o1, tw, G, st, g);
-                case 8: return c2r<N, 8, 1>(in, n_rows, o0, o1, tw, G, st, g);
-                case 16: return c2r<N, 16, 1>(in, n_rows, o0, o1, tw, G, st, g);
+                case 4: return c2r<N, 4, 1>(in, n_rows, o0, o1, tw, G, st, g, turn);
+                case 8: return c2r<N, 8, 1>(in, n_rows, o0, o1, tw, G, st, g, turn);
+                case 16: return c2r<N, 16, 1>(in, n_rows, o0, o1, tw, G, st, g, turn);
             }
         }
         set_error("bad points per thread %d", E);
@@ -416,7 +416,7 @@ int launch_rows_r2c(const Plan &p, const T *in0, const T *in1, int n_rows, cx<T>
 
 template <typename T>
 int launch_rows_c2r(const Plan &p, const cx<T> *in, int n_rows, T *out0, T *out1,
-                    const cx<T> *twN, Shape s, hipStream_t st, unsigned *g) {
+                    const cx<T> *twN, Shape s, hipStream_t st, unsigned *g, int turn) {
     if (sizeof(T) == 4 && !g) {
         set_error("FP32 passes need the plan's scale words");
         return PF_EINVAL;
@@ -425,7 +425,10 @@ int launch_rows_c2r(const Plan &p, const cx<T> *in, int n_rows, T *out0, T *out1
         set_error("invalid row shape E=%d G=%d for M=%d", s.E, s.G, p.M);
         return PF_EINVAL;
     }
-    PF_SWITCH_POW2(p.M, Disp<T>::template c2r_e, s.E, in, n_rows, out0, out1, twN, s.G, st, g);
+    turn %= p.n_phi;
+    if (turn < 0) turn += p.n_phi;
+    PF_SWITCH_POW2(p.M, Disp<T>::template c2r_e, s.E, in, n_rows, out0, out1, twN, s.G, st, g,
+                   turn);
 }
 
 template <typename T>
@@ -460,7 +463,7 @@ int launch_cols_adj(const Plan &p, const cx<T> *V, cx<T> *D, const cx<T> *spec,
     template int launch_rows_r2c<T>(const Plan &, const T *, const T *, int, cx<T> *,          \
                                     const cx<T> *, Shape, hipStream_t, unsigned *);             \
     template int launch_rows_c2r<T>(const Plan &, const cx<T> *, int, T *, T *, const cx<T> *,  \
-                                    Shape, hipStream_t, unsigned *);                            \
+                                    Shape, hipStream_t, unsigned *, int);                       \
     template int launch_cols_fwd<T>(const Plan &, const cx<T> *, cx<T> *, const cx<T> *,        \
                                     const cx<T> *, Shape, hipStream_t, unsigned *);             \
     template int launch_cols_adj<T>(const Plan &, const cx<T> *, cx<T> *, const cx<T> *,        \

@@ -1167,7 +1167,7 @@ int launch_wedge_adjoint(const Plan &p, const cx<T> *V, T *g_src, T *g_w, hipStr
                        (const cx2<T> *)part, chunks, p.H, wbar);
     PF_HIP(hipGetLastError());
     int rc = launch_rows_c2r<T>(p, reinterpret_cast<const cx<T> *>(wbar), 1, x, y,
-                                (const cx<T> *)p.twN, p.sched.rows2, st, g);
+                                (const cx<T> *)p.twN, p.sched.rows2, st, g, -p.col0);
     if (rc) return rc;
     const double rc0 = p.r_min * std::pow(p.beta, p.s0) * 0.5 * (1.0 + p.beta);
     const double rh = 0.5 * p.r_min * std::pow(p.beta, p.s0);

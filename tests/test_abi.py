@@ -214,5 +214,17 @@ def test_patch_plan_host_checks():
         o.slope_order = 4
         assert lib.pf_kernels_build(h, ctypes.byref(o), None) == pf.PF_EUNSUPPORTED
         assert "slope order" in pf.pf_last_error()
+        # the azimuthal turn: any integer on a patch plan, unbuilt too; the
+        # transpose with wedges, unbuilt, is a state error
+        for c in (0, 5, -37, 1 << 30):
+            assert lib.pf_plan_set_src_col0(h, c) == pf.PF_OK
+        assert lib.pf_forces_patches_backward(h, 8, 8, 8, 8, None) == pf.PF_ESTATE
     finally:
         pf.pf_plan_destroy(h)
+    g = pf.pf_plan_create(16, 32, 0.1, 1.0)
+    try:
+        assert lib.pf_plan_set_src_col0(g, 3) == pf.PF_EINVAL
+        assert "patch plan" in pf.pf_last_error()
+    finally:
+        pf.pf_plan_destroy(g)
+    assert lib.pf_plan_set_src_col0(None, 3) == pf.PF_EINVAL

@@ -8,8 +8,9 @@ destination [0.01, 1].
 Parity bars: relative L2 <= 1e-11 (FP64) and 1e-5 (FP32) on both force
 components, for source patches below (adjacent and with a gap), above and
 overlapping the destination, ragged sizes, all methods, with and without
-wedges; the transpose of patch plans, with and without wedges, against the
-oracle's transposed sums."""
+wedges, with the source turned by whole cells in phi; the transpose of patch
+plans, with and without wedges and turns, against the oracle's transposed
+sums."""
 import os
 import sys
 
@@ -255,6 +256,100 @@ def test_patch_transpose_wedge_arguments():
     finally:
         plan.close()
         plain.close()
+
+
+TURN_CASES = [
+    # (n_src, s0, n_dst, n_phi, wedges, src_col0)
+    (10, -10, 24, 32, True, 5),
+    (12, -3, 20, 32, False, -7),      # overlapping: the self cells turn with the source
+    (33, -33, 40, 128, True, 77),
+    (9, 26, 24, 16, False, 8),        # half a turn
+]
+
+
+@pytest.mark.parametrize("method", ["sim", "particle+"])
+@pytest.mark.parametrize("case", TURN_CASES)
+def test_turned_patch_parity(case, method):
+    # the source patch and its wedges turned by whole cells in phi: the
+    # forward against the oracle's sums at the turned offsets, FP64 and FP32
+    n_src, s0, n_dst, n_phi, wedges, c0 = case
+    g = oracle.Grid(n_dst, n_phi, 0.05, 2.0)
+    sig = workloads.random_field((n_src, n_phi), 151 + n_src) + 0.3
+    sig_w = (workloads.random_field((n_phi,), 152 + n_phi) + 0.5) if wedges else None
+    _say("turned patch parity %s %s" % (case, method))
+    if method == "sim":
+        T = oracle.patch_tables(g, n_src, s0, 19)
+        Tw = oracle.wedge_tables(g, s0) if wedges else None
+        o_r, o_p = oracle.patch_forward(g, n_src, s0, T, sig, Tw, sig_w, col0=c0)
+    else:
+        o_r, o_p = oracle.patch_particle(g, n_src, s0, sig, sig_w, plus=True, col0=c0)
+    for dt, tol in (("f64", 1e-11), ("f32", 1e-5)):
+        plan = pf.PatchPlan(n_src, s0, n_dst, n_phi, g.r_min, g.r_max, wedges=wedges, dtype=dt,
+                            method=method, src_col0=c0)
+        try:
+            s = torch.tensor(sig, dtype=plan.torch_dtype, device="cuda")
+            w = torch.tensor(sig_w, dtype=plan.torch_dtype, device="cuda") if wedges else None
+            fr, fp = plan.forces(s, w)
+            torch.cuda.synchronize()
+            a = _rel(fr.double().cpu().numpy(), o_r)
+            b = _rel(fp.double().cpu().numpy(), o_p)
+        finally:
+            plan.close()
+        _say("  %s rel-L2 F_r %.2e F_phi %.2e" % (dt, a, b))
+        assert a < tol and b < tol, (case, method, dt, a, b)
+
+
+@pytest.mark.parametrize("case", [c for c in TURN_CASES])
+def test_turned_patch_transpose_matches_oracle(case):
+    n_src, s0, n_dst, n_phi, wedges, c0 = case
+    g = oracle.Grid(n_dst, n_phi, 0.05, 2.0)
+    vr = workloads.random_field(g.shape, 161 + n_src)
+    vp = workloads.random_field(g.shape, 162 + n_src)
+    _say("turned patch transpose %s" % (case,))
+    T = oracle.patch_tables(g, n_src, s0, 19)
+    Tw = oracle.wedge_tables(g, s0) if wedges else None
+    want = oracle.patch_adjoint(g, n_src, s0, T, vr, vp, Tw=Tw, col0=c0)
+    ws, ww = want if wedges else (want, None)
+    for dt, tol in (("f64", 1e-11), ("f32", 1e-5)):
+        plan = pf.PatchPlan(n_src, s0, n_dst, n_phi, g.r_min, g.r_max, wedges=wedges, dtype=dt,
+                            src_col0=c0)
+        try:
+            a = torch.tensor(vr, dtype=plan.torch_dtype, device="cuda")
+            b = torch.tensor(vp, dtype=plan.torch_dtype, device="cuda")
+            got = plan.backward(a, b)
+            torch.cuda.synchronize()
+            gs, gw = got if wedges else (got, None)
+            e1 = _rel(gs.double().cpu().numpy(), ws)
+            e2 = _rel(gw.double().cpu().numpy(), ww) if wedges else 0.0
+        finally:
+            plan.close()
+        _say("  %s rel-L2 source %.2e wedges %.2e" % (dt, e1, e2))
+        assert e1 < tol and e2 < tol, (case, dt, e1, e2)
+
+
+def test_turn_changes_without_rebuild():
+    # set_src_col0 on a built plan: a turn and its undoing; the untouched
+    # plan's results come back bit for bit, and a turn by c0 equals the
+    # unturned forces rolled by c0 columns within FP32 rounding
+    n_src, s0, n_dst, n_phi = 10, -10, 24, 32
+    plan = pf.PatchPlan(n_src, s0, n_dst, n_phi, 0.05, 2.0, wedges=True, dtype="f32")
+    try:
+        s = torch.tensor(workloads.random_field((n_src, n_phi), 171) + 0.5, dtype=torch.float32,
+                         device="cuda")
+        w = torch.tensor(workloads.random_field((n_phi,), 172) + 0.5, dtype=torch.float32,
+                         device="cuda")
+        base = [x.clone() for x in plan.forces(s, w)]
+        plan.set_src_col0(-3)
+        turned = [x.clone() for x in plan.forces(s, w)]
+        plan.set_src_col0(n_phi)   # a whole turn
+        again = plan.forces(s, w)
+        torch.cuda.synchronize()
+        for x, y, z in zip(base, turned, again):
+            assert torch.equal(x, z)
+            ref = torch.roll(x, -3, dims=1)
+            assert float((y - ref).norm() / ref.norm()) < 1e-6
+    finally:
+        plan.close()
 
 
 def test_patch_with_one_trapezoid_and_wedges():
