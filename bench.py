@@ -445,6 +445,20 @@ def main():
                    "pass_ms": pass_times(p4, sg), "schedule": sched(p4)}
         p4.close()
 
+    # ---- an azimuthal count of three times a power of two --------------------
+    log("1024 x 1536")
+    three_p = {"workload": "1024 x 1536 (N_phi = 3 x 512), r in [0.01, 100], spiral disk"}
+    for dt in ("fp32", "fp64"):
+        p3 = pf.Plan(N_R, 1536, R_MIN, R_MAX, dtype="f32" if dt == "fp32" else "f64")
+        r3, _, _ = p3.geometry()
+        ph3 = (np.arange(1536) + 0.5) * (2 * np.pi / 1536)
+        s3 = torch.tensor(workloads.spiral_disk(r3, ph3), dtype=p3.torch_dtype, device=dev)
+        o3 = (torch.empty_like(s3), torch.empty_like(s3))
+        ms3 = time_calls(torch, lambda: p3.forces(s3, o3), max(K // 4, 10), W)
+        three_p[dt] = {"ms_per_call": ms3, "cells_per_s": N_R * 1536 / (ms3 * 1e-3),
+                       "pass_ms": pass_times(p3, s3), "schedule": sched(p3)}
+        p3.close()
+
     # ---- batched ------------------------------------------------------------
     batched = None
     if not args.no_batched:
@@ -543,6 +557,7 @@ def main():
         "batched": batched,
         "slope_order_4": so4,
         "c1_128x128_fp64": c1_detail,
+        "n_phi_1536": three_p,
     })
     out["detail"]["table_build_s"]["fp64"] = build64
     if not args.no_cpu_baseline:

@@ -23,7 +23,7 @@ BUILD = os.path.join(HERE, "_build")
 ARCH = os.environ.get("PF_OFFLOAD_ARCH", "gfx950")
 
 SOURCES = ["pf_api.hip", "pf_passes.hip", "pf_tables.hip", "pf_batched.hip", "pf_tune.hip",
-           "pf_cart.hip"]
+           "pf_cart.hip", "pf_rows3.hip"]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH, "-ffp-contract=on",

@@ -66,10 +66,14 @@ int upload_twiddles(int n, bool f64, void **dst) {
 Schedule default_schedule(int n_phi, int L, bool f64) {
     Schedule s;
     const int M = n_phi / 2;
-    s.rows.E = M >= 2048 ? 16 : (M < 8 ? M : 8);
-    if (s.rows.E < 4) s.rows.E = 4;
+    if (!is_pow2_int(M)) {   // M = 3 P: 4 points per thread (three transforms per channel)
+        s.rows.E = 4;
+    } else {
+        s.rows.E = M >= 2048 ? 16 : (M < 8 ? M : 8);
+        if (s.rows.E < 4) s.rows.E = 4;
+    }
     {
-        const int th = M / s.rows.E;
+        const int th = row_threads(M, s.rows.E);
         s.rows.G = th >= 256 ? 1 : 256 / th;
         while (s.rows.G > 1 && !valid_shape_rows(M, s.rows, f64)) s.rows.G /= 2;
     }
@@ -253,8 +257,11 @@ pf_plan pf_plan_create(int n_r, int n_phi, double r_min, double r_max) {
         pf::set_error("n_r = %d outside [4, 4096]", n_r);
         return nullptr;
     }
-    if (!pf::is_pow2(n_phi) || n_phi < 8 || n_phi > 8192) {
-        pf::set_error("n_phi = %d must be a power of two in [8, 8192]", n_phi);
+    const bool three = n_phi % 6 == 0 && pf::is_pow2(n_phi / 6);
+    if (!((pf::is_pow2(n_phi) && n_phi >= 8 && n_phi <= 8192) ||
+          (three && n_phi >= 24 && n_phi <= 6144))) {
+        pf::set_error("n_phi = %d must be a power of two in [8, 8192] or three times one "
+                      "in [24, 6144]", n_phi);
         return nullptr;
     }
     if (!std::isfinite(r_min) || !std::isfinite(r_max) || !(r_min > 0) || !(r_max > r_min)) {

@@ -157,7 +157,7 @@ namespace {
 // ===========================================================================
 // Sizes the grouped kernels instantiate.
 bool batch_size_ok(const Plan &p) {
-    return p.M >= 64 && p.M <= 2048 && p.L >= 128 && p.L <= 4096;
+    return is_pow2_int(p.M) && p.M >= 64 && p.M <= 2048 && p.L >= 128 && p.L <= 4096;
 }
 
 // One class launch: a kernel shape and the range [e0, e1) of its pass's
@@ -430,7 +430,8 @@ size_t desc_size(bool f64, int n) {
 int check_plans(const Plan *const *plans, int n) {
     for (int k = 0; k < n; ++k) {
         if (!batch_size_ok(*plans[k])) {
-            set_error("batched path needs 128 <= n_phi <= 4096 and 33 <= n_r <= 2048 "
+            set_error("batched path needs n_phi a power of two in [128, 4096] and "
+                      "33 <= n_r <= 2048 "
                       "(disk %d: %d x %d)", k, plans[k]->n_r, plans[k]->n_phi);
             return PF_EUNSUPPORTED;
         }

@@ -104,6 +104,20 @@ template <typename T>
 int launch_rows_c2r(const Plan &p, const cx<T> *in, int n_rows, T *out0, T *out1,
                     const cx<T> *twN, Shape s, hipStream_t st, unsigned *g = nullptr,
                     int turn = 0);
+// Rows of n_phi = 6 P points, P a power of two (pf_rows3.hip): M = 3 P.
+template <typename T>
+int launch_rows_r2c3(int M, const T *in0, const T *in1, int n_rows, cx<T> *out,
+                     const cx<T> *twN, Shape s, hipStream_t st, unsigned *g);
+template <typename T>
+int launch_rows_c2r3(int M, const cx<T> *in, int n_rows, T *out0, T *out1, const cx<T> *twN,
+                     Shape s, hipStream_t st, unsigned *g, int turn);
+size_t rows3_lds_bytes(int P, int G, int C, bool f64);
+// The row transforms' M = n_phi / 2 complex points: a power of two, or
+// three times one (then three sub-transforms of M / 3 points); the points
+// of one sub-transform and the threads per row at E points per thread.
+inline bool is_pow2_int(int v) { return v > 0 && (v & (v - 1)) == 0; }
+inline int row_sub(int M) { return is_pow2_int(M) ? M : M / 3; }
+inline int row_threads(int M, int E) { return row_sub(M) / E; }
 // Column pass of the forward map (u-FFT, spectral multiply-accumulate with
 // the spectral radial slope, inverse u-FFTs, crop): S ([n_in][H]) -> pairs
 // Z ([n_r][H]); g: the scale words pass A noted (nullptr: unscaled).

@@ -196,8 +196,8 @@ int tune_t(Plan &p, hipStream_t st) {
     for (int sweep = 0; sweep < 2; ++sweep)
         for (int E : {4, 8, 16})
             for (int thr : {64, 128, 256, 512}) {
-                if (E > p.M || (p.M / E) > thr) continue;
-                Shape s{E, thr / (p.M / E)};
+                if (E > row_sub(p.M) || row_threads(p.M, E) > thr) continue;
+                Shape s{E, thr / row_threads(p.M, E)};
                 if (!valid_shape_rows(p.M, s, f64)) continue;
                 rc = time_ms(
                     [&]() {

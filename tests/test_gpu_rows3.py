@@ -1,0 +1,186 @@
+"""GPU parity of grids whose azimuthal count is three times a power of two
+(N_phi = 6 P: the row transforms split into three P-point transforms and a
+radix-3 step) against the FP64 oracle: forward map and transpose, full grids
+from the smallest such grid (N_phi = 24) up to several row tiles with a
+ragged radial count, the largest (N_phi = 6144) on sampled cells, the
+particle method, patch plans with wedges and turns, the FP32 grid scale,
+and the refusal of the batched path.  Bars: relative L2 1e-11 (FP64) and
+1e-5 (FP32) per component."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+import paper_1509_01450_amd as pf  # noqa: E402
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    pf.load()
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def _t(x, plan):
+    return torch.tensor(x, dtype=plan.torch_dtype, device="cuda")
+
+
+SHAPES = [(4, 24, 0.5, 2.0), (9, 48, 0.2, 5.0), (37, 96, 0.01, 1.0), (20, 192, 0.1, 10.0),
+          (5, 768, 0.3, 3.0)]
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("dt,tol", [("f64", 1e-11), ("f32", 1e-5)])
+def test_forward_matches_oracle(shape, dt, tol):
+    _say("3P forward", shape, dt)
+    g = oracle.Grid(*shape)
+    T = oracle.tables(g, 19)
+    sig = workloads.random_field(g.shape, seed_k=71) + 2.0
+    fr_o, fp_o = oracle.forward(g, T, sig)
+    plan = pf.Plan(*shape, dtype=dt)
+    try:
+        fr, fp = plan.forces(_t(sig, plan))
+        torch.cuda.synchronize()
+        e1 = _rel(fr.double().cpu().numpy(), fr_o)
+        e2 = _rel(fp.double().cpu().numpy(), fp_o)
+    finally:
+        plan.close()
+    _say("  rel-L2 F_r %.3e F_phi %.3e" % (e1, e2))
+    assert e1 <= tol and e2 <= tol
+
+
+@pytest.mark.parametrize("shape", SHAPES[:4])
+@pytest.mark.parametrize("dt,tol", [("f64", 1e-11), ("f32", 1e-5)])
+def test_transpose_matches_oracle(shape, dt, tol):
+    _say("3P transpose", shape, dt)
+    g = oracle.Grid(*shape)
+    T = oracle.tables(g, 19)
+    vr = workloads.random_field(g.shape, 72)
+    vp = workloads.random_field(g.shape, 73)
+    want = oracle.adjoint(g, T, vr, vp)
+    plan = pf.Plan(*shape, dtype=dt)
+    try:
+        got = plan.backward(_t(vr, plan), _t(vp, plan))
+        torch.cuda.synchronize()
+        e = _rel(got.double().cpu().numpy(), want)
+    finally:
+        plan.close()
+    _say("  rel-L2 %.3e" % e)
+    assert e <= tol
+
+
+@pytest.mark.parametrize("n_r,n_phi", [(512, 1536), (24, 6144)])
+def test_large_sampled(n_r, n_phi):
+    # the largest P (1024) and a C2-like size, on sampled cells incl. the
+    # first and last columns
+    a, b = 0.01, 100.0
+    g = oracle.Grid(n_r, n_phi, a, b)
+    sig = workloads.spiral_disk(g.r_centres, g.phi_centres)
+    rng = np.random.default_rng(74)
+    idx = np.unique(np.concatenate([
+        rng.choice(n_r * n_phi, 160, replace=False),
+        np.array([0, n_phi - 1, n_phi // 3, (n_r - 1) * n_phi + n_phi // 2])]))
+    T = oracle.tables(g, 19)
+    fr_o, fp_o = oracle.forward(g, T, sig, dest=idx)
+    for dt, tol in (("f64", 1e-11), ("f32", 1e-5)):
+        plan = pf.Plan(n_r, n_phi, a, b, dtype=dt)
+        try:
+            fr, fp = plan.forces(_t(sig, plan))
+            torch.cuda.synchronize()
+            e1 = _rel(fr.double().cpu().numpy().ravel()[idx], fr_o)
+            e2 = _rel(fp.double().cpu().numpy().ravel()[idx], fp_o)
+        finally:
+            plan.close()
+        _say("3P %d x %d %s sampled rel-L2 F_r %.3e F_phi %.3e" % (n_r, n_phi, dt, e1, e2))
+        assert e1 <= tol and e2 <= tol
+
+
+def test_particle_plus_matches_oracle():
+    shape = (37, 96, 0.01, 1.0)
+    g = oracle.Grid(*shape)
+    sig = workloads.single_disk_blobs(g.r_centres, g.phi_centres, 0.01, 1.0)
+    fr_o, fp_o = oracle.forward_particle(g, sig, plus=True)
+    for dt, tol in (("f64", 1e-11), ("f32", 1e-5)):
+        plan = pf.Plan(*shape, dtype=dt, method="particle+")
+        try:
+            fr, fp = plan.forces(_t(sig, plan))
+            torch.cuda.synchronize()
+            e1 = _rel(fr.double().cpu().numpy(), fr_o)
+            e2 = _rel(fp.double().cpu().numpy(), fp_o)
+        finally:
+            plan.close()
+        _say("3P particle+ %s rel-L2 F_r %.3e F_phi %.3e" % (dt, e1, e2))
+        assert e1 <= tol and e2 <= tol
+
+
+@pytest.mark.parametrize("c0", [0, 7])
+def test_patch_with_wedges_and_turn(c0):
+    n_src, s0, n_dst, n_phi = 10, -10, 24, 48
+    g = oracle.Grid(n_dst, n_phi, 0.05, 2.0)
+    T = oracle.patch_tables(g, n_src, s0, 19)
+    Tw = oracle.wedge_tables(g, s0)
+    sig = workloads.random_field((n_src, n_phi), 75) + 0.3
+    sw = workloads.random_field((n_phi,), 76) + 0.5
+    vr = workloads.random_field(g.shape, 77)
+    vp = workloads.random_field(g.shape, 78)
+    o_r, o_p = oracle.patch_forward(g, n_src, s0, T, sig, Tw, sw, col0=c0)
+    ws, ww = oracle.patch_adjoint(g, n_src, s0, T, vr, vp, Tw=Tw, col0=c0)
+    for dt, tol in (("f64", 1e-11), ("f32", 1e-5)):
+        plan = pf.PatchPlan(n_src, s0, n_dst, n_phi, g.r_min, g.r_max, wedges=True, dtype=dt,
+                            src_col0=c0)
+        try:
+            fr, fp = plan.forces(_t(sig, plan), _t(sw, plan))
+            gs, gw = plan.backward(_t(vr, plan), _t(vp, plan))
+            torch.cuda.synchronize()
+            e = [_rel(fr.double().cpu().numpy(), o_r), _rel(fp.double().cpu().numpy(), o_p),
+                 _rel(gs.double().cpu().numpy(), ws), _rel(gw.double().cpu().numpy(), ww)]
+        finally:
+            plan.close()
+        _say("3P patch turn %d %s rel-L2 %s" % (c0, dt, " ".join("%.2e" % x for x in e)))
+        assert max(e) <= tol
+
+
+def test_fp32_grid_scale():
+    # 2^110 and 2^-100 sigma: forces scaled bit for bit (normal outputs)
+    shape = (37, 96, 0.01, 1.0)
+    g = oracle.Grid(*shape)
+    sig = workloads.random_field(g.shape, seed_k=79) + 2.0
+    plan = pf.Plan(*shape, dtype="f32")
+    try:
+        s = _t(sig, plan)
+        base = [x.clone() for x in plan.forces(s)]
+        for f in (2.0 ** 110, 2.0 ** -100):
+            got = plan.forces(s * f)
+            torch.cuda.synchronize()
+            for x, x1 in zip(got, base):
+                a = x.double().cpu().numpy()
+                want = x1.double().cpu().numpy() * f
+                assert np.isfinite(a).all()
+                assert np.array_equal(a[want != 0], want[want != 0]), f
+    finally:
+        plan.close()
+
+
+def test_batched_refuses_three_p():
+    p = pf.Plan(64, 192, 0.1, 10.0, dtype="f32")
+    try:
+        s = torch.ones(64, 192, device="cuda")
+        with pytest.raises(pf.PFError, match="power of two"):
+            pf.forces_batched([p], [s])
+    finally:
+        p.close()
