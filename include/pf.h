@@ -137,8 +137,9 @@ void pf_build_opts_default(pf_build_opts *opts);
 
 /* Create a plan for an n_r x n_phi grid on [r_min, r_max] (Sec. 3.2.1).
  * Host only; touches no GPU.  Requirements: 4 <= n_r <= 4096;
- * n_phi a power of two in [8, 8192] or three times one in [24, 6144] (the
- * batched path takes powers of two only); 0 < r_min < r_max, both finite.
+ * n_phi a power of two in [8, 8192], three times one in [24, 6144] or nine
+ * times one in [72, 4608] (the batched path takes powers of two only);
+ * 0 < r_min < r_max, both finite.
  * Returns NULL on failure (see pf_last_error()); PF_EUNSUPPORTED-type size
  * failures are reported the same way.                                      */
 pf_plan pf_plan_create(int n_r, int n_phi, double r_min, double r_max);

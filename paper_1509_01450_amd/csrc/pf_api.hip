@@ -66,8 +66,8 @@ int upload_twiddles(int n, bool f64, void **dst) {
 Schedule default_schedule(int n_phi, int L, bool f64) {
     Schedule s;
     const int M = n_phi / 2;
-    if (!is_pow2_int(M)) {   // M = 3 P: 4 points per thread (three transforms per channel)
-        s.rows.E = 4;
+    if (!is_pow2_int(M)) {   // M = Q P: 4 points per thread (2 for Q = 9)
+        s.rows.E = row_factor(M) == 9 ? 2 : 4;
     } else {
         s.rows.E = M >= 2048 ? 16 : (M < 8 ? M : 8);
         if (s.rows.E < 4) s.rows.E = 4;
@@ -258,10 +258,11 @@ pf_plan pf_plan_create(int n_r, int n_phi, double r_min, double r_max) {
         return nullptr;
     }
     const bool three = n_phi % 6 == 0 && pf::is_pow2(n_phi / 6);
+    const bool nine = n_phi % 18 == 0 && pf::is_pow2(n_phi / 18);
     if (!((pf::is_pow2(n_phi) && n_phi >= 8 && n_phi <= 8192) ||
-          (three && n_phi >= 24 && n_phi <= 6144))) {
-        pf::set_error("n_phi = %d must be a power of two in [8, 8192] or three times one "
-                      "in [24, 6144]", n_phi);
+          (three && n_phi >= 24 && n_phi <= 6144) || (nine && n_phi >= 72 && n_phi <= 4608))) {
+        pf::set_error("n_phi = %d must be a power of two in [8, 8192], three times one in "
+                      "[24, 6144] or nine times one in [72, 4608]", n_phi);
         return nullptr;
     }
     if (!std::isfinite(r_min) || !std::isfinite(r_max) || !(r_min > 0) || !(r_max > r_min)) {

@@ -104,19 +104,28 @@ template <typename T>
 int launch_rows_c2r(const Plan &p, const cx<T> *in, int n_rows, T *out0, T *out1,
                     const cx<T> *twN, Shape s, hipStream_t st, unsigned *g = nullptr,
                     int turn = 0);
-// Rows of n_phi = 6 P points, P a power of two (pf_rows3.hip): M = 3 P.
+// Rows of n_phi = 2 Q P points, Q = 3 or 9, P a power of two (pf_rows3.hip):
+// M = Q P.
 template <typename T>
-int launch_rows_r2c3(int M, const T *in0, const T *in1, int n_rows, cx<T> *out,
+int launch_rows_r2cq(int M, const T *in0, const T *in1, int n_rows, cx<T> *out,
                      const cx<T> *twN, Shape s, hipStream_t st, unsigned *g);
 template <typename T>
-int launch_rows_c2r3(int M, const cx<T> *in, int n_rows, T *out0, T *out1, const cx<T> *twN,
+int launch_rows_c2rq(int M, const cx<T> *in, int n_rows, T *out0, T *out1, const cx<T> *twN,
                      Shape s, hipStream_t st, unsigned *g, int turn);
-size_t rows3_lds_bytes(int P, int G, int C, bool f64);
+size_t rowsq_lds_bytes(int P, int Q, int G, int C, bool f64);
 // The row transforms' M = n_phi / 2 complex points: a power of two, or
-// three times one (then three sub-transforms of M / 3 points); the points
-// of one sub-transform and the threads per row at E points per thread.
+// three or nine times one (then Q sub-transforms of M / Q points);
+// row_factor gives Q (1 for a power of two, 0 for other M), row_sub the
+// points of one sub-transform, row_threads the threads per row at E points
+// per thread.
 inline bool is_pow2_int(int v) { return v > 0 && (v & (v - 1)) == 0; }
-inline int row_sub(int M) { return is_pow2_int(M) ? M : M / 3; }
+inline int row_factor(int M) {
+    if (is_pow2_int(M)) return 1;
+    if (M % 3 == 0 && is_pow2_int(M / 3)) return 3;
+    if (M % 9 == 0 && is_pow2_int(M / 9)) return 9;
+    return 0;
+}
+inline int row_sub(int M) { return row_factor(M) ? M / row_factor(M) : 0; }
 inline int row_threads(int M, int E) { return row_sub(M) / E; }
 // Column pass of the forward map (u-FFT, spectral multiply-accumulate with
 // the spectral radial slope, inverse u-FFTs, crop): S ([n_in][H]) -> pairs

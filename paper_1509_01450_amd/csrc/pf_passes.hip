@@ -125,13 +125,16 @@ __global__ __launch_bounds__(512) void k_cols_adj_pf(const cx2<T> *__restrict__ 
 // Row shapes are checked for the two-channel passes (the larger LDS need):
 // 2 G padded_len(M) complex within 144 KB.
 bool valid_shape_rows(int M, Shape s, bool f64) {
-    if (!is_pow2_int(M)) {   // M = 3 P: three P-point transforms per channel
-        const int P = M / 3;
-        if (3 * P != M || !is_pow2_int(P) || P < 4 || P > 1024) return false;
-        // (FP64 at 8 points per thread spills: 4 only)
-        if (!(s.E == 4 || (s.E == 8 && !f64)) || s.E > P) return false;
+    const int Q = row_factor(M);
+    if (Q == 0) return false;
+    if (Q > 1) {   // M = Q P: Q P-point transforms per channel
+        const int P = M / Q;
+        if (P < 4 || P > (Q == 3 ? 1024 : 256)) return false;
+        // points per thread: 4, or 8 in FP32 (Q = 3); 2 (Q = 9): more spill
+        if (Q == 3 ? !(s.E == 4 || (s.E == 8 && !f64)) : s.E != 2) return false;
+        if (s.E > P) return false;
         if (s.G < 1 || (P / s.E) * s.G > 512) return false;
-        return rows3_lds_bytes(P, s.G, 2, f64) <= 144 * 1024;
+        return rowsq_lds_bytes(P, Q, s.G, 2, f64) <= 144 * 1024;
     }
     if (!(s.E == 4 || s.E == 8 || s.E == 16) || s.E > M) return false;
     const int th = M / s.E;
@@ -420,7 +423,7 @@ int launch_rows_r2c(const Plan &p, const T *in0, const T *in1, int n_rows, cx<T>
         return PF_EINVAL;
     }
     if (!is_pow2_int(p.M))
-        return launch_rows_r2c3<T>(p.M, in0, in1, n_rows, out, twN, s, st, g);
+        return launch_rows_r2cq<T>(p.M, in0, in1, n_rows, out, twN, s, st, g);
     PF_SWITCH_POW2(p.M, Disp<T>::template r2c_e, s.E, in0, in1, n_rows, out, twN, s.G, st, g);
 }
 
@@ -438,7 +441,7 @@ int launch_rows_c2r(const Plan &p, const cx<T> *in, int n_rows, T *out0, T *out1
     turn %= p.n_phi;
     if (turn < 0) turn += p.n_phi;
     if (!is_pow2_int(p.M))
-        return launch_rows_c2r3<T>(p.M, in, n_rows, out0, out1, twN, s, st, g, turn);
+        return launch_rows_c2rq<T>(p.M, in, n_rows, out0, out1, twN, s, st, g, turn);
     PF_SWITCH_POW2(p.M, Disp<T>::template c2r_e, s.E, in, n_rows, out0, out1, twN, s.G, st, g,
                    turn);
 }

@@ -1,22 +1,23 @@
-// pf_rows3.hip -- the row transforms along phi for N_phi = 6 P (P a power of
-// two): pass A and pass C of grids whose azimuthal count is three times a
-// power of two.  Power-of-two rows take the kernels of pf_passes.hip.
+// pf_rows3.hip -- the row transforms along phi for N_phi = 2 Q P with Q = 3
+// or 9 and P a power of two: pass A and pass C of grids whose azimuthal
+// count is three or nine times a power of two.  Power-of-two rows take the
+// kernels of pf_passes.hip.
 //
-// A real row of N = 2 M points, M = 3 P, goes through the M-point complex
+// A real row of N = 2 M points, M = Q P, goes through the M-point complex
 // transform of z[m] = x[2m] + i x[2m+1], as in the power-of-two rows; that
-// transform is split by decimation in time into three P-point transforms
-// Y_r of z[3n + r] (r = 0, 1, 2), run by the power-of-two stages of
-// fft_core.hpp as six (or three) transforms held together, and one radix-3
-// step in registers:
-//   Z[k + jP] = sum_r (W_M^(r k) Y_r[k]) W_3^(r j),   k in [0, P), j = 0, 1, 2,
-// W_M = exp(-2 pi i / M), W_3 = exp(-2 pi i / 3).  Thread t holds the points
-// k = t + e TH (TH = P / E) of all three Y_r, so it forms Z at k, k + P and
-// k + 2P itself.  The packed half spectrum (bin 0 = (X_0, X_M)) then follows
+// transform is split by decimation in time into Q P-point transforms Y_r
+// of z[Qn + r] (r in [0, Q)), run by the power-of-two stages of fft_core.hpp
+// as Q C transforms held together, and one radix-Q step in registers:
+//   Z[k + jP] = sum_r (W_M^(r k) Y_r[k]) W_Q^(r j),   k in [0, P), j in [0, Q),
+// W_M = exp(-2 pi i / M) (a radix-9 step as two radix-3 steps with the
+// twiddles W_9^(n2 k1) between them).  Thread t holds the points
+// k = t + e TH (TH = P / E) of all Q sub-transforms, so it forms Z at
+// k + jP itself.  The packed half spectrum (bin 0 = (X_0, X_M)) then follows
 // from Z and its mirror bins M - k as in the power-of-two rows.  The
 // inverse (pass C) runs the same steps backwards:
-//   z[3n + r] = sum_k' W_P^(-n k') [W_M^(-r k') sum_j Z[k' + jP] W_3^(-r j)].
-// Workgroup: G rows x TH threads; LDS: C G row3_len(P) complex, per channel
-// and row the three P-point regions, reused for the mirror exchange.
+//   z[Qn + r] = sum_k' W_P^(-n k') [W_M^(-r k') sum_j Z[k' + jP] W_Q^(-r j)].
+// Workgroup: G rows x TH threads; LDS: C G rowq_len(P, Q) complex, per
+// channel and row the Q P-point regions, reused for the mirror exchange.
 #include "pass_bodies.hpp"
 #include "pf_common.hpp"
 
@@ -24,10 +25,10 @@ namespace pf {
 
 namespace {
 
-// LDS slots per row and channel: three padded P-point regions, or one padded
-// 3P-point region for the mirror exchange, whichever is longer
-__host__ __device__ constexpr int row3_len(int P) {
-    return 3 * padded_len(P) > padded_len(3 * P) ? 3 * padded_len(P) : padded_len(3 * P);
+// LDS slots per row and channel: Q padded P-point regions, or one padded
+// QP-point region for the mirror exchange, whichever is longer
+__host__ __device__ constexpr int rowq_len(int P, int Q) {
+    return Q * padded_len(P) > padded_len(Q * P) ? Q * padded_len(P) : padded_len(Q * P);
 }
 
 // sqrt(3) / 2
@@ -50,106 +51,149 @@ __device__ __forceinline__ void dft3(cx<T> a0, cx<T> a1, cx<T> a2, cx<T> &y0, cx
     y2 = m - ihd;
 }
 
-template <typename T, int P, int C>
-__device__ __forceinline__ void row3_sub_lds(cx<T> *buf, int gi, int G, Lds<T> (&lds)[3 * C]) {
+// In place: a_j <- sum_r a_r W_Q^(s r j) (s = -1 forward, +1 inverse).
+// w9[m] = W_9^m for m = 1, 2, 4 (Q = 9 only).  Q = 9: r = 3 n1 + n2 and
+// j = k1 + 3 k2; the three-point transforms over n1, the twiddles
+// W_9^(n2 k1), the three-point transforms over n2.
+template <typename T, int Q, bool INV>
+__device__ __forceinline__ void dftq(cx<T> (&a)[Q], const cx<T> (&w9)[5]) {
+    if constexpr (Q == 3) {
+        cx<T> y0, y1, y2;
+        dft3<T, INV>(a[0], a[1], a[2], y0, y1, y2);
+        a[0] = y0;
+        a[1] = y1;
+        a[2] = y2;
+    } else {
+        static_assert(Q == 9, "radix 3 or 9");
+        cx<T> b[3][3];
+#pragma unroll
+        for (int n2 = 0; n2 < 3; ++n2)
+            dft3<T, INV>(a[n2], a[3 + n2], a[6 + n2], b[n2][0], b[n2][1], b[n2][2]);
+#pragma unroll
+        for (int n2 = 1; n2 < 3; ++n2)
+#pragma unroll
+            for (int k1 = 1; k1 < 3; ++k1)
+                b[n2][k1] = INV ? cmulc(b[n2][k1], w9[n2 * k1]) : cmul(b[n2][k1], w9[n2 * k1]);
+#pragma unroll
+        for (int k1 = 0; k1 < 3; ++k1)
+            dft3<T, INV>(b[0][k1], b[1][k1], b[2][k1], a[k1], a[k1 + 3], a[k1 + 6]);
+    }
+}
+
+// W_9^m = exp(-2 pi i m / 9) from the N-point table (N = 18 P): twN[2 P m]
+template <typename T, int P, int Q>
+__device__ __forceinline__ void load_w9(const cx<T> *__restrict__ twN, cx<T> (&w9)[5]) {
+#pragma unroll
+    for (int m = 0; m < 5; ++m) w9[m] = cx<T>{T(1), T(0)};
+    if constexpr (Q == 9) {
+        w9[1] = twN[2 * P];
+        w9[2] = twN[4 * P];
+        w9[4] = twN[8 * P];
+    }
+}
+
+template <typename T, int P, int Q, int C>
+__device__ __forceinline__ void rowq_sub_lds(cx<T> *buf, int gi, int G, Lds<T> (&lds)[Q * C]) {
 #pragma unroll
     for (int c = 0; c < C; ++c)
 #pragma unroll
-        for (int r = 0; r < 3; ++r)
-            lds[3 * c + r] = Lds<T>{buf, (c * G + gi) * row3_len(P) + r * padded_len(P), 1};
+        for (int r = 0; r < Q; ++r)
+            lds[Q * c + r] = Lds<T>{buf, (c * G + gi) * rowq_len(P, Q) + r * padded_len(P), 1};
 }
 
-template <typename T, int P>
-__device__ __forceinline__ Lds<T> row3_mirror_lds(cx<T> *buf, int gi, int G, int c) {
-    return Lds<T>{buf, (c * G + gi) * row3_len(P), 1};
+template <typename T, int P, int Q>
+__device__ __forceinline__ Lds<T> rowq_mirror_lds(cx<T> *buf, int gi, int G, int c) {
+    return Lds<T>{buf, (c * G + gi) * rowq_len(P, Q), 1};
 }
 
 // Pass A: rows of in0 (and in1 for C = 2) -> packed half spectra
 // (out: [n_rows][M] complex for C = 1, pairs for C = 2).
-template <typename T, int P, int E, int C>
-__device__ __forceinline__ void body_rows_r2c3(int unit, int G, cx<T> *__restrict__ buf,
+template <typename T, int P, int Q, int E, int C>
+__device__ __forceinline__ void body_rows_r2cq(int unit, int G, cx<T> *__restrict__ buf,
                                                const T *__restrict__ in0,
                                                const T *__restrict__ in1, int n_rows,
                                                cx<T> *__restrict__ out,
                                                const cx<T> *__restrict__ twN,
                                                unsigned *__restrict__ gscale) {
     constexpr int TH = P / E;
-    constexpr int M = 3 * P;
+    constexpr int M = Q * P;
     constexpr int N = 2 * M;
     const int gi = threadIdx.x / TH, t = threadIdx.x % TH;
     const int row = unit * G + gi;
     const bool active = row < n_rows;
     const int i = active ? row : 0;   // inactive lanes read row 0
-    Lds<T> lds[3 * C];
-    row3_sub_lds<T, P, C>(buf, gi, G, lds);
+    Lds<T> lds[Q * C];
+    rowq_sub_lds<T, P, Q, C>(buf, gi, G, lds);
 
-    // z[3n + r] for n = t + e TH: three neighbouring complex values
-    cx<T> v[3 * C][E];
+    // z[Qn + r] for n = t + e TH: Q neighbouring complex values
+    cx<T> v[Q * C][E];
 #pragma unroll
     for (int c = 0; c < C; ++c) {
         const cx<T> *xz = reinterpret_cast<const cx<T> *>((c == 0 ? in0 : in1) + (size_t)i * N);
 #pragma unroll
         for (int e = 0; e < E; ++e)
 #pragma unroll
-            for (int r = 0; r < 3; ++r) v[3 * c + r][e] = xz[3 * (t + e * TH) + r];
+            for (int r = 0; r < Q; ++r) v[Q * c + r][e] = xz[Q * (t + e * TH) + r];
     }
     Twiddles<P, E, T> tw;
-    tw.load(t, twN, 6);   // the P-point table inside the N-point one
+    tw.load(t, twN, 2 * Q);   // the P-point table inside the N-point one
+    cx<T> w9[5];
+    load_w9<T, P, Q>(twN, w9);
 #pragma unroll
-    for (int a = 0; a < 3 * C; ++a)
+    for (int a = 0; a < Q * C; ++a)
 #pragma unroll
         for (int e = 0; e < E; ++e)
             if (!active) v[a][e] = cx<T>{T(0), T(0)};
-    scale_note<T, E, 3 * C>(gscale, v);
-    fft_fwd<P, E, 3 * C, T>(v, t, lds, tw);
+    scale_note<T, E, Q * C>(gscale, v);
+    fft_fwd<P, E, Q * C, T>(v, t, lds, tw);
 
-    // the radix-3 step: Z at k, k + P, k + 2P, in place of Y_0, Y_1, Y_2
+    // the radix-Q step: Z at k + jP in place of Y_j
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         const int k = t + e * TH;
-        const cx<T> w1 = twN[2 * k], w2 = twN[4 * k];   // W_M^k, W_M^(2k)
 #pragma unroll
         for (int c = 0; c < C; ++c) {
-            cx<T> z0, z1, z2;
-            dft3<T, false>(v[3 * c][e], cmul(v[3 * c + 1][e], w1), cmul(v[3 * c + 2][e], w2), z0,
-                           z1, z2);
-            v[3 * c][e] = z0;
-            v[3 * c + 1][e] = z1;
-            v[3 * c + 2][e] = z2;
+            cx<T> a[Q];
+            a[0] = v[Q * c][e];
+#pragma unroll
+            for (int r = 1; r < Q; ++r) a[r] = cmul(v[Q * c + r][e], twN[2 * r * k]);   // W_M^(rk)
+            dftq<T, Q, false>(a, w9);
+#pragma unroll
+            for (int j = 0; j < Q; ++j) v[Q * c + j][e] = a[j];
         }
     }
     // mirror bins through LDS (the transforms' last reads are behind their
     // final barrier; a one-stage transform read nothing)
 #pragma unroll
     for (int c = 0; c < C; ++c) {
-        const Lds<T> mir = row3_mirror_lds<T, P>(buf, gi, G, c);
+        const Lds<T> mir = rowq_mirror_lds<T, P, Q>(buf, gi, G, c);
 #pragma unroll
-        for (int j = 0; j < 3; ++j)
+        for (int j = 0; j < Q; ++j)
 #pragma unroll
-            for (int e = 0; e < E; ++e) mir.st(t + e * TH + j * P, v[3 * c + j][e]);
+            for (int e = 0; e < E; ++e) mir.st(t + e * TH + j * P, v[Q * c + j][e]);
     }
     __syncthreads();
     // the packed half spectrum, in place
 #pragma unroll
     for (int c = 0; c < C; ++c) {
-        const Lds<T> mir = row3_mirror_lds<T, P>(buf, gi, G, c);
+        const Lds<T> mir = rowq_mirror_lds<T, P, Q>(buf, gi, G, c);
 #pragma unroll
-        for (int j = 0; j < 3; ++j)
+        for (int j = 0; j < Q; ++j)
 #pragma unroll
             for (int e = 0; e < E; ++e) {
                 const int k = t + e * TH + j * P;
-                const cx<T> zk = v[3 * c + j][e], zm = mir.ld(k == 0 ? 0 : M - k);
+                const cx<T> zk = v[Q * c + j][e], zm = mir.ld(k == 0 ? 0 : M - k);
                 const cx<T> ev = {T(0.5) * (zk.x + zm.x), T(0.5) * (zk.y - zm.y)};
                 // (zk - conj zm) / (2i)
                 const cx<T> od = {T(0.5) * (zk.y + zm.y), -T(0.5) * (zk.x - zm.x)};
                 cx<T> x = cmac(ev, twN[k], od);
                 if (k == 0) x = cx<T>{zk.x + zk.y, zk.x - zk.y};   // (X_0, X_M), both real
-                v[3 * c + j][e] = x;
+                v[Q * c + j][e] = x;
             }
     }
     if (active) {
 #pragma unroll
-        for (int j = 0; j < 3; ++j)
+        for (int j = 0; j < Q; ++j)
 #pragma unroll
             for (int e = 0; e < E; ++e) {
                 const int k = t + e * TH + j * P;
@@ -157,7 +201,7 @@ __device__ __forceinline__ void body_rows_r2c3(int unit, int G, cx<T> *__restric
                     store_stream(&out[(size_t)i * M + k], v[j][e]);
                 } else {
                     cx2<T> *orow = reinterpret_cast<cx2<T> *>(out) + (size_t)i * M;
-                    store_stream(&orow[k], cx2<T>{v[j][e], v[3 + j][e]});
+                    store_stream(&orow[k], cx2<T>{v[j][e], v[Q + j][e]});
                 }
             }
     }
@@ -166,24 +210,24 @@ __device__ __forceinline__ void body_rows_r2c3(int unit, int G, cx<T> *__restric
 // Pass C: packed half rows -> real rows of out0 (and out1), unnormalised
 // inverse; turn in [0, N) turns the rows by that many points (bin k times
 // exp(-2 pi i k turn / N)), as the power-of-two rows.
-template <typename T, int P, int E, int C>
-__device__ __forceinline__ void body_rows_c2r3(int unit, int G, cx<T> *__restrict__ buf,
+template <typename T, int P, int Q, int E, int C>
+__device__ __forceinline__ void body_rows_c2rq(int unit, int G, cx<T> *__restrict__ buf,
                                                const cx<T> *__restrict__ in, int n_rows,
                                                T *__restrict__ out0, T *__restrict__ out1,
                                                const cx<T> *__restrict__ twN,
                                                unsigned *__restrict__ gscale, int turn) {
     constexpr int TH = P / E;
-    constexpr int M = 3 * P;
+    constexpr int M = Q * P;
     constexpr int N = 2 * M;
     const int gi = threadIdx.x / TH, t = threadIdx.x % TH;
     const int row = unit * G + gi;
     const bool active = row < n_rows;
     const int i = active ? row : 0;   // inactive lanes read row 0
 
-    // bins k = t + e TH + j P of channel c at v[3c + j][e]
-    cx<T> v[3 * C][E];
+    // bins k = t + e TH + j P of channel c at v[Qc + j][e]
+    cx<T> v[Q * C][E];
 #pragma unroll
-    for (int j = 0; j < 3; ++j)
+    for (int j = 0; j < Q; ++j)
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             const int k = t + e * TH + j * P;
@@ -192,19 +236,19 @@ __device__ __forceinline__ void body_rows_c2r3(int unit, int G, cx<T> *__restric
             } else {
                 const cx2<T> a = reinterpret_cast<const cx2<T> *>(in)[(size_t)i * M + k];
                 v[j][e] = a.a;
-                v[3 + j][e] = a.b;
+                v[Q + j][e] = a.b;
             }
         }
     if (turn) {   // uniform
 #pragma unroll
-        for (int j = 0; j < 3; ++j)
+        for (int j = 0; j < Q; ++j)
 #pragma unroll
             for (int e = 0; e < E; ++e) {
                 const int k = t + e * TH + j * P;
                 const cx<T> ph = twN[(k * turn) % N];
 #pragma unroll
                 for (int c = 0; c < C; ++c) {
-                    cx<T> &x = v[3 * c + j][e];
+                    cx<T> &x = v[Q * c + j][e];
                     if (k == 0)   // packed (X_0, X_M): X_M times (-1)^turn
                         x.y = (turn & 1) ? -x.y : x.y;
                     else
@@ -214,23 +258,25 @@ __device__ __forceinline__ void body_rows_c2r3(int unit, int G, cx<T> *__restric
     }
 #pragma unroll
     for (int c = 0; c < C; ++c) {
-        const Lds<T> mir = row3_mirror_lds<T, P>(buf, gi, G, c);
+        const Lds<T> mir = rowq_mirror_lds<T, P, Q>(buf, gi, G, c);
 #pragma unroll
-        for (int j = 0; j < 3; ++j)
+        for (int j = 0; j < Q; ++j)
 #pragma unroll
-            for (int e = 0; e < E; ++e) mir.st(t + e * TH + j * P, v[3 * c + j][e]);
+            for (int e = 0; e < E; ++e) mir.st(t + e * TH + j * P, v[Q * c + j][e]);
     }
     __syncthreads();
+    cx<T> w9[5];
+    load_w9<T, P, Q>(twN, w9);
 #pragma unroll
     for (int c = 0; c < C; ++c) {
-        const Lds<T> mir = row3_mirror_lds<T, P>(buf, gi, G, c);
+        const Lds<T> mir = rowq_mirror_lds<T, P, Q>(buf, gi, G, c);
         // Z[k] of the complex transform, in place
 #pragma unroll
-        for (int j = 0; j < 3; ++j)
+        for (int j = 0; j < Q; ++j)
 #pragma unroll
             for (int e = 0; e < E; ++e) {
                 const int k = t + e * TH + j * P;
-                cx<T> a = v[3 * c + j][e], m = mir.ld(k == 0 ? 0 : M - k);
+                cx<T> a = v[Q * c + j][e], m = mir.ld(k == 0 ? 0 : M - k);
                 if (k == 0) {   // unpack bin 0 = (X_0, X_M)
                     m = cx<T>{a.y, T(0)};
                     a = cx<T>{a.x, T(0)};
@@ -239,31 +285,32 @@ __device__ __forceinline__ void body_rows_c2r3(int unit, int G, cx<T> *__restric
                 const cx<T> d = {a.x - m.x, a.y + m.y};   // X[k] - conj X[M-k]
                 const cx<T> w = twN[k];
                 const cx<T> iw = {w.y, w.x};   // s + i d exp(+2 pi i k / N)
-                v[3 * c + j][e] = cmac(s, d, iw);
+                v[Q * c + j][e] = cmac(s, d, iw);
             }
-        // the inverse radix-3 step: U_r[k'] = W_M^(-r k') sum_j Z[k' + jP] W_3^(-r j),
+        // the inverse radix-Q step: U_r[k'] = W_M^(-r k') sum_j Z[k' + jP] W_Q^(-r j),
         // in place of Z at k' + rP
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             const int k = t + e * TH;
-            const cx<T> w1 = twN[2 * k], w2 = twN[4 * k];
-            cx<T> b0, b1, b2;
-            dft3<T, true>(v[3 * c][e], v[3 * c + 1][e], v[3 * c + 2][e], b0, b1, b2);
-            v[3 * c][e] = b0;
-            v[3 * c + 1][e] = cmulc(b1, w1);
-            v[3 * c + 2][e] = cmulc(b2, w2);
+            cx<T> a[Q];
+#pragma unroll
+            for (int j = 0; j < Q; ++j) a[j] = v[Q * c + j][e];
+            dftq<T, Q, true>(a, w9);
+            v[Q * c][e] = a[0];
+#pragma unroll
+            for (int r = 1; r < Q; ++r) v[Q * c + r][e] = cmulc(a[r], twN[2 * r * k]);
         }
     }
     __syncthreads();   // mirror reads done before the transforms reuse buf
-    Lds<T> lds[3 * C];
-    row3_sub_lds<T, P, C>(buf, gi, G, lds);
+    Lds<T> lds[Q * C];
+    rowq_sub_lds<T, P, Q, C>(buf, gi, G, lds);
     Twiddles<P, E, T> tw;
-    tw.load(t, twN, 6);
-    fft_inv<P, E, 3 * C, T>(v, t, lds, tw);
+    tw.load(t, twN, 2 * Q);
+    fft_inv<P, E, Q * C, T>(v, t, lds, tw);
     const T up = scale_finish<T>(gscale, unit);
     if (up != T(1))
 #pragma unroll
-        for (int a = 0; a < 3 * C; ++a)
+        for (int a = 0; a < Q * C; ++a)
 #pragma unroll
             for (int e = 0; e < E; ++e) v[a][e] = scale(v[a][e], up);
     if (active) {
@@ -273,58 +320,58 @@ __device__ __forceinline__ void body_rows_c2r3(int unit, int G, cx<T> *__restric
 #pragma unroll
             for (int e = 0; e < E; ++e)
 #pragma unroll
-                for (int r = 0; r < 3; ++r) store_stream(&yz[3 * (t + e * TH) + r], v[3 * c + r][e]);
+                for (int r = 0; r < Q; ++r) store_stream(&yz[Q * (t + e * TH) + r], v[Q * c + r][e]);
         }
     }
 }
 
-template <typename T, int P, int E, int C>
-__global__ __launch_bounds__(512) void k_rows_r2c3(const T *__restrict__ in0,
+template <typename T, int P, int Q, int E, int C>
+__global__ __launch_bounds__(512) void k_rows_r2cq(const T *__restrict__ in0,
                                                    const T *__restrict__ in1, int n_rows,
                                                    cx<T> *__restrict__ out,
                                                    const cx<T> *__restrict__ twN,
                                                    unsigned *__restrict__ gscale) {
     extern __shared__ unsigned char smem_raw[];
-    body_rows_r2c3<T, P, E, C>(blockIdx.x, blockDim.x / (P / E),
-                               reinterpret_cast<cx<T> *>(smem_raw), in0, in1, n_rows, out, twN,
-                               gscale);
+    body_rows_r2cq<T, P, Q, E, C>(blockIdx.x, blockDim.x / (P / E),
+                                  reinterpret_cast<cx<T> *>(smem_raw), in0, in1, n_rows, out, twN,
+                                  gscale);
 }
 
-template <typename T, int P, int E, int C>
-__global__ __launch_bounds__(512) void k_rows_c2r3(const cx<T> *__restrict__ in, int n_rows,
+template <typename T, int P, int Q, int E, int C>
+__global__ __launch_bounds__(512) void k_rows_c2rq(const cx<T> *__restrict__ in, int n_rows,
                                                    T *__restrict__ out0, T *__restrict__ out1,
                                                    const cx<T> *__restrict__ twN,
                                                    unsigned *__restrict__ gscale, int turn) {
     extern __shared__ unsigned char smem_raw[];
-    body_rows_c2r3<T, P, E, C>(blockIdx.x, blockDim.x / (P / E),
-                               reinterpret_cast<cx<T> *>(smem_raw), in, n_rows, out0, out1, twN,
-                               gscale, turn);
+    body_rows_c2rq<T, P, Q, E, C>(blockIdx.x, blockDim.x / (P / E),
+                                  reinterpret_cast<cx<T> *>(smem_raw), in, n_rows, out0, out1,
+                                  twN, gscale, turn);
 }
 
 template <typename K>
-int allow_lds3(K kern, size_t lds) {
+int allow_ldsq(K kern, size_t lds) {
     if (lds > 64 * 1024)
         PF_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     return PF_OK;
 }
 
-template <typename T>
-struct Disp3 {
+template <typename T, int Q>
+struct DispQ {
     template <int P, int E, int C>
     static int r2c(const T *in0, const T *in1, int n_rows, cx<T> *out, const cx<T> *tw, int G,
                    hipStream_t st, unsigned *g) {
         if constexpr (E <= P) {
             const int blocks = (n_rows + G - 1) / G;
-            const size_t lds = (size_t)C * G * row3_len(P) * sizeof(cx<T>);
-            int rc = allow_lds3(k_rows_r2c3<T, P, E, C>, lds);
+            const size_t lds = (size_t)C * G * rowq_len(P, Q) * sizeof(cx<T>);
+            int rc = allow_ldsq(k_rows_r2cq<T, P, Q, E, C>, lds);
             if (rc) return rc;
-            hipLaunchKernelGGL((k_rows_r2c3<T, P, E, C>), dim3(blocks), dim3(G * (P / E)), lds, st,
-                               in0, in1, n_rows, out, tw, g);
+            hipLaunchKernelGGL((k_rows_r2cq<T, P, Q, E, C>), dim3(blocks), dim3(G * (P / E)), lds,
+                               st, in0, in1, n_rows, out, tw, g);
             PF_HIP(hipGetLastError());
             return PF_OK;
         }
-        set_error("row transform of 3 x %d points cannot take %d points per thread", P, E);
+        set_error("row transform of %d x %d points cannot take %d points per thread", Q, P, E);
         return PF_EUNSUPPORTED;
     }
     template <int P, int E, int C>
@@ -332,26 +379,28 @@ struct Disp3 {
                    hipStream_t st, unsigned *g, int turn) {
         if constexpr (E <= P) {
             const int blocks = (n_rows + G - 1) / G;
-            const size_t lds = (size_t)C * G * row3_len(P) * sizeof(cx<T>);
-            int rc = allow_lds3(k_rows_c2r3<T, P, E, C>, lds);
+            const size_t lds = (size_t)C * G * rowq_len(P, Q) * sizeof(cx<T>);
+            int rc = allow_ldsq(k_rows_c2rq<T, P, Q, E, C>, lds);
             if (rc) return rc;
-            hipLaunchKernelGGL((k_rows_c2r3<T, P, E, C>), dim3(blocks), dim3(G * (P / E)), lds, st,
-                               in, n_rows, o0, o1, tw, g, turn);
+            hipLaunchKernelGGL((k_rows_c2rq<T, P, Q, E, C>), dim3(blocks), dim3(G * (P / E)), lds,
+                               st, in, n_rows, o0, o1, tw, g, turn);
             PF_HIP(hipGetLastError());
             return PF_OK;
         }
-        set_error("row transform of 3 x %d points cannot take %d points per thread", P, E);
+        set_error("row transform of %d x %d points cannot take %d points per thread", Q, P, E);
         return PF_EUNSUPPORTED;
     }
+    // points per thread: 4 or 8 with Q = 3, 2 with Q = 9
     template <int P>
     static int r2c_e(int E, const T *in0, const T *in1, int n_rows, cx<T> *out, const cx<T> *tw,
                      int G, hipStream_t st, unsigned *g) {
+        constexpr int EA = Q == 3 ? 4 : 2, EB = Q == 3 ? 8 : 2;
         if (in1) {
-            if (E == 4) return r2c<P, 4, 2>(in0, in1, n_rows, out, tw, G, st, g);
-            if (E == 8) return r2c<P, 8, 2>(in0, in1, n_rows, out, tw, G, st, g);
+            if (E == EA) return r2c<P, EA, 2>(in0, in1, n_rows, out, tw, G, st, g);
+            if (E == EB) return r2c<P, EB, 2>(in0, in1, n_rows, out, tw, G, st, g);
         } else {
-            if (E == 4) return r2c<P, 4, 1>(in0, in1, n_rows, out, tw, G, st, g);
-            if (E == 8) return r2c<P, 8, 1>(in0, in1, n_rows, out, tw, G, st, g);
+            if (E == EA) return r2c<P, EA, 1>(in0, in1, n_rows, out, tw, G, st, g);
+            if (E == EB) return r2c<P, EB, 1>(in0, in1, n_rows, out, tw, G, st, g);
         }
         set_error("bad points per thread %d", E);
         return PF_EUNSUPPORTED;
@@ -359,60 +408,91 @@ struct Disp3 {
     template <int P>
     static int c2r_e(int E, const cx<T> *in, int n_rows, T *o0, T *o1, const cx<T> *tw, int G,
                      hipStream_t st, unsigned *g, int turn) {
+        constexpr int EA = Q == 3 ? 4 : 2, EB = Q == 3 ? 8 : 2;
         if (o1) {
-            if (E == 4) return c2r<P, 4, 2>(in, n_rows, o0, o1, tw, G, st, g, turn);
-            if (E == 8) return c2r<P, 8, 2>(in, n_rows, o0, o1, tw, G, st, g, turn);
+            if (E == EA) return c2r<P, EA, 2>(in, n_rows, o0, o1, tw, G, st, g, turn);
+            if (E == EB) return c2r<P, EB, 2>(in, n_rows, o0, o1, tw, G, st, g, turn);
         } else {
-            if (E == 4) return c2r<P, 4, 1>(in, n_rows, o0, o1, tw, G, st, g, turn);
-            if (E == 8) return c2r<P, 8, 1>(in, n_rows, o0, o1, tw, G, st, g, turn);
+            if (E == EA) return c2r<P, EA, 1>(in, n_rows, o0, o1, tw, G, st, g, turn);
+            if (E == EB) return c2r<P, EB, 1>(in, n_rows, o0, o1, tw, G, st, g, turn);
         }
         set_error("bad points per thread %d", E);
         return PF_EUNSUPPORTED;
     }
 };
 
-#define PF_SWITCH_P3(v, F, ...)                            \
-    switch (v) {                                           \
-        case 4: return F<4>(__VA_ARGS__);                  \
-        case 8: return F<8>(__VA_ARGS__);                  \
-        case 16: return F<16>(__VA_ARGS__);                \
-        case 32: return F<32>(__VA_ARGS__);                \
-        case 64: return F<64>(__VA_ARGS__);                \
-        case 128: return F<128>(__VA_ARGS__);              \
-        case 256: return F<256>(__VA_ARGS__);              \
-        case 512: return F<512>(__VA_ARGS__);              \
-        case 1024: return F<1024>(__VA_ARGS__);            \
-        default:                                           \
+#define PF_SWITCH_P3(v, F, ...)                                \
+    switch (v) {                                               \
+        case 4: return F<4>(__VA_ARGS__);                      \
+        case 8: return F<8>(__VA_ARGS__);                      \
+        case 16: return F<16>(__VA_ARGS__);                    \
+        case 32: return F<32>(__VA_ARGS__);                    \
+        case 64: return F<64>(__VA_ARGS__);                    \
+        case 128: return F<128>(__VA_ARGS__);                  \
+        case 256: return F<256>(__VA_ARGS__);                  \
+        case 512: return F<512>(__VA_ARGS__);                  \
+        case 1024: return F<1024>(__VA_ARGS__);                \
+        default:                                               \
             set_error("no row transform of 3 x %d points", v); \
-            return PF_EUNSUPPORTED;                        \
+            return PF_EUNSUPPORTED;                            \
+    }
+#define PF_SWITCH_P9(v, F, ...)                                \
+    switch (v) {                                               \
+        case 4: return F<4>(__VA_ARGS__);                      \
+        case 8: return F<8>(__VA_ARGS__);                      \
+        case 16: return F<16>(__VA_ARGS__);                    \
+        case 32: return F<32>(__VA_ARGS__);                    \
+        case 64: return F<64>(__VA_ARGS__);                    \
+        case 128: return F<128>(__VA_ARGS__);                  \
+        case 256: return F<256>(__VA_ARGS__);                  \
+        default:                                               \
+            set_error("no row transform of 9 x %d points", v); \
+            return PF_EUNSUPPORTED;                            \
     }
 
 }  // namespace
 
-size_t rows3_lds_bytes(int P, int G, int C, bool f64) {
-    return (size_t)C * G * row3_len(P) * (f64 ? 16 : 8);
+size_t rowsq_lds_bytes(int P, int Q, int G, int C, bool f64) {
+    return (size_t)C * G * rowq_len(P, Q) * (f64 ? 16 : 8);
 }
 
 template <typename T>
-int launch_rows_r2c3(int M, const T *in0, const T *in1, int n_rows, cx<T> *out,
+int launch_rows_r2cq(int M, const T *in0, const T *in1, int n_rows, cx<T> *out,
                      const cx<T> *twN, Shape s, hipStream_t st, unsigned *g) {
-    PF_SWITCH_P3(M / 3, Disp3<T>::template r2c_e, s.E, in0, in1, n_rows, out, twN, s.G, st, g);
+    using D3 = DispQ<T, 3>;
+    using D9 = DispQ<T, 9>;
+    if (row_factor(M) == 3)
+        PF_SWITCH_P3(M / 3, D3::template r2c_e, s.E, in0, in1, n_rows, out, twN, s.G,
+                     st, g);
+    if (row_factor(M) == 9)
+        PF_SWITCH_P9(M / 9, D9::template r2c_e, s.E, in0, in1, n_rows, out, twN, s.G,
+                     st, g);
+    set_error("no row transform of %d points", M);
+    return PF_EUNSUPPORTED;
 }
 
 template <typename T>
-int launch_rows_c2r3(int M, const cx<T> *in, int n_rows, T *out0, T *out1, const cx<T> *twN,
+int launch_rows_c2rq(int M, const cx<T> *in, int n_rows, T *out0, T *out1, const cx<T> *twN,
                      Shape s, hipStream_t st, unsigned *g, int turn) {
-    PF_SWITCH_P3(M / 3, Disp3<T>::template c2r_e, s.E, in, n_rows, out0, out1, twN, s.G, st, g,
-                 turn);
+    using D3 = DispQ<T, 3>;
+    using D9 = DispQ<T, 9>;
+    if (row_factor(M) == 3)
+        PF_SWITCH_P3(M / 3, D3::template c2r_e, s.E, in, n_rows, out0, out1, twN, s.G,
+                     st, g, turn);
+    if (row_factor(M) == 9)
+        PF_SWITCH_P9(M / 9, D9::template c2r_e, s.E, in, n_rows, out0, out1, twN, s.G,
+                     st, g, turn);
+    set_error("no row transform of %d points", M);
+    return PF_EUNSUPPORTED;
 }
 
-template int launch_rows_r2c3<float>(int, const float *, const float *, int, cx<float> *,
+template int launch_rows_r2cq<float>(int, const float *, const float *, int, cx<float> *,
                                      const cx<float> *, Shape, hipStream_t, unsigned *);
-template int launch_rows_r2c3<double>(int, const double *, const double *, int, cx<double> *,
+template int launch_rows_r2cq<double>(int, const double *, const double *, int, cx<double> *,
                                       const cx<double> *, Shape, hipStream_t, unsigned *);
-template int launch_rows_c2r3<float>(int, const cx<float> *, int, float *, float *,
+template int launch_rows_c2rq<float>(int, const cx<float> *, int, float *, float *,
                                      const cx<float> *, Shape, hipStream_t, unsigned *, int);
-template int launch_rows_c2r3<double>(int, const cx<double> *, int, double *, double *,
+template int launch_rows_c2rq<double>(int, const cx<double> *, int, double *, double *,
                                       const cx<double> *, Shape, hipStream_t, unsigned *, int);
 
 }  // namespace pf

@@ -194,7 +194,7 @@ int tune_t(Plan &p, hipStream_t st) {
     float tbest = 1e30f, tbest2 = 1e30f, t = 0.f;
     int rc = PF_OK;
     for (int sweep = 0; sweep < 2; ++sweep)
-        for (int E : {4, 8, 16})
+        for (int E : {2, 4, 8, 16})
             for (int thr : {64, 128, 256, 512}) {
                 if (E > row_sub(p.M) || row_threads(p.M, E) > thr) continue;
                 Shape s{E, thr / row_threads(p.M, E)};

@@ -35,6 +35,7 @@ def test_library_exports_every_declared_symbol():
 
 @pytest.mark.parametrize("args", [(3, 64, 0.1, 10.0), (5000, 64, 0.1, 10.0), (16, 36, 0.1, 10.0),
                                   (16, 40, 0.1, 10.0), (16, 12, 0.1, 10.0), (16, 12288, 0.1, 10.0),
+                                  (16, 54, 0.1, 10.0), (16, 9216, 0.1, 10.0), (16, 108, 0.1, 10.0),
                                   (16, 4, 0.1, 10.0), (16, 16384, 0.1, 10.0),
                                   (16, 64, 0.0, 10.0), (16, 64, 1.0, 1.0),
                                   (16, 64, float("nan"), 10.0), (16, 64, 0.1, float("inf"))])
@@ -45,9 +46,9 @@ def test_plan_create_rejects_bad_grids(args):
     assert pf.pf_last_error()
 
 
-@pytest.mark.parametrize("n_phi", [8, 24, 48, 96, 1536, 6144, 8192])
+@pytest.mark.parametrize("n_phi", [8, 24, 48, 72, 96, 144, 1536, 4608, 6144, 8192])
 def test_plan_create_accepts_azimuthal_counts(n_phi):
-    # powers of two and three times powers of two
+    # powers of two, three and nine times powers of two
     h = pf.pf_plan_create(16, n_phi, 0.1, 10.0)
     try:
         rc, re_, dphi = pf.pf_plan_geometry(h, 16)

@@ -1,11 +1,11 @@
-"""GPU parity of grids whose azimuthal count is three times a power of two
-(N_phi = 6 P: the row transforms split into three P-point transforms and a
-radix-3 step) against the FP64 oracle: forward map and transpose, full grids
-from the smallest such grid (N_phi = 24) up to several row tiles with a
-ragged radial count, the largest (N_phi = 6144) on sampled cells, the
-particle method, patch plans with wedges and turns, the FP32 grid scale,
-and the refusal of the batched path.  Bars: relative L2 1e-11 (FP64) and
-1e-5 (FP32) per component."""
+"""GPU parity of grids whose azimuthal count is three or nine times a power
+of two (N_phi = 2 Q P: the row transforms split into Q P-point transforms
+and a radix-Q step, Q = 3 or 9) against the FP64 oracle: forward map and
+transpose, full grids from the smallest such grids (N_phi = 24, 72) up to
+several row tiles with a ragged radial count, the largest (N_phi = 6144,
+4608) on sampled cells, the particle method, patch plans with wedges and
+turns, the FP32 grid scale, and the refusal of the batched path.  Bars:
+relative L2 1e-11 (FP64) and 1e-5 (FP32) per component."""
 import sys
 
 import numpy as np
@@ -41,7 +41,8 @@ def _t(x, plan):
 
 
 SHAPES = [(4, 24, 0.5, 2.0), (9, 48, 0.2, 5.0), (37, 96, 0.01, 1.0), (20, 192, 0.1, 10.0),
-          (5, 768, 0.3, 3.0)]
+          (5, 768, 0.3, 3.0), (4, 72, 0.5, 2.0), (21, 144, 0.05, 3.0), (6, 576, 0.2, 4.0)]
+TRANSPOSE_SHAPES = [SHAPES[i] for i in (0, 1, 2, 3, 5, 6)]
 
 
 @pytest.mark.parametrize("shape", SHAPES)
@@ -64,7 +65,7 @@ def test_forward_matches_oracle(shape, dt, tol):
     assert e1 <= tol and e2 <= tol
 
 
-@pytest.mark.parametrize("shape", SHAPES[:4])
+@pytest.mark.parametrize("shape", TRANSPOSE_SHAPES)
 @pytest.mark.parametrize("dt,tol", [("f64", 1e-11), ("f32", 1e-5)])
 def test_transpose_matches_oracle(shape, dt, tol):
     _say("3P transpose", shape, dt)
@@ -84,10 +85,10 @@ def test_transpose_matches_oracle(shape, dt, tol):
     assert e <= tol
 
 
-@pytest.mark.parametrize("n_r,n_phi", [(512, 1536), (24, 6144)])
+@pytest.mark.parametrize("n_r,n_phi", [(512, 1536), (24, 6144), (16, 4608)])
 def test_large_sampled(n_r, n_phi):
-    # the largest P (1024) and a C2-like size, on sampled cells incl. the
-    # first and last columns
+    # the largest P (1024 with Q = 3, 256 with Q = 9) and a C2-like size, on
+    # sampled cells incl. the first and last columns
     a, b = 0.01, 100.0
     g = oracle.Grid(n_r, n_phi, a, b)
     sig = workloads.spiral_disk(g.r_centres, g.phi_centres)
@@ -110,8 +111,9 @@ def test_large_sampled(n_r, n_phi):
         assert e1 <= tol and e2 <= tol
 
 
-def test_particle_plus_matches_oracle():
-    shape = (37, 96, 0.01, 1.0)
+@pytest.mark.parametrize("n_phi", [96, 144])
+def test_particle_plus_matches_oracle(n_phi):
+    shape = (37, n_phi, 0.01, 1.0)
     g = oracle.Grid(*shape)
     sig = workloads.single_disk_blobs(g.r_centres, g.phi_centres, 0.01, 1.0)
     fr_o, fp_o = oracle.forward_particle(g, sig, plus=True)
@@ -128,9 +130,9 @@ def test_particle_plus_matches_oracle():
         assert e1 <= tol and e2 <= tol
 
 
-@pytest.mark.parametrize("c0", [0, 7])
-def test_patch_with_wedges_and_turn(c0):
-    n_src, s0, n_dst, n_phi = 10, -10, 24, 48
+@pytest.mark.parametrize("c0,n_phi", [(0, 48), (7, 48), (-11, 72)])
+def test_patch_with_wedges_and_turn(c0, n_phi):
+    n_src, s0, n_dst = 10, -10, 24
     g = oracle.Grid(n_dst, n_phi, 0.05, 2.0)
     T = oracle.patch_tables(g, n_src, s0, 19)
     Tw = oracle.wedge_tables(g, s0)
@@ -155,9 +157,10 @@ def test_patch_with_wedges_and_turn(c0):
         assert max(e) <= tol
 
 
-def test_fp32_grid_scale():
+@pytest.mark.parametrize("n_phi", [96, 144])
+def test_fp32_grid_scale(n_phi):
     # 2^110 and 2^-100 sigma: forces scaled bit for bit (normal outputs)
-    shape = (37, 96, 0.01, 1.0)
+    shape = (37, n_phi, 0.01, 1.0)
     g = oracle.Grid(*shape)
     sig = workloads.random_field(g.shape, seed_k=79) + 2.0
     plan = pf.Plan(*shape, dtype="f32")
