@@ -539,8 +539,12 @@ def main():
         op = (torch.empty((ND, ND), dtype=pp.torch_dtype, device=dev),
               torch.empty((ND, ND), dtype=pp.torch_dtype, device=dev))
         msp = time_calls(torch, lambda: pp.forces(ss, sw, op), max(K // 2, 10), W)
+        # the transpose with the wedges: cotangents on the destination ->
+        # gradients on the source annulus and the wedge densities
+        gb = (torch.empty_like(ss), torch.empty_like(sw))
+        msb = time_calls(torch, lambda: pp.backward(op[0], op[1], gb), max(K // 2, 10), W)
         patches[dt] = {"ms_per_call": msp, "destination_cells_per_s": ND * ND / (msp * 1e-3),
-                       "table_build_s": bp}
+                       "transpose_ms_per_call": msb, "table_build_s": bp}
         pp.close()
 
     out["detail"].update({
