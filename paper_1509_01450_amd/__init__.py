@@ -450,7 +450,26 @@ def _make_function():
                 g_fphi = torch.zeros(plan.shape, dtype=plan.torch_dtype, device=g_fr.device)
             return plan.backward(g_fr.contiguous(), g_fphi.contiguous()), z
 
-    return _Forces
+    class _PatchForces(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, sigma_src, sigma_wedge, plan):
+            ctx.plan = plan
+            w = sigma_wedge.contiguous() if sigma_wedge is not None else None
+            return plan.forces(sigma_src.contiguous(), w)
+
+        @staticmethod
+        def backward(ctx, g_fr, g_fphi):
+            plan = ctx.plan
+            if g_fr is None:
+                g_fr = torch.zeros(plan.shape, dtype=plan.torch_dtype, device=g_fphi.device)
+            if g_fphi is None:
+                g_fphi = torch.zeros(plan.shape, dtype=plan.torch_dtype, device=g_fr.device)
+            g = plan.backward(g_fr.contiguous(), g_fphi.contiguous())
+            if plan.wedges:
+                return g[0], g[1], None
+            return g, None, None
+
+    return _Forces, _PatchForces
 
 
 _FN = None
@@ -461,7 +480,17 @@ def forces(sigma, plan: Plan):
     global _FN
     if _FN is None:
         _FN = _make_function()
-    return _FN.apply(sigma, plan)
+    return _FN[0].apply(sigma, plan)
+
+
+def patch_forces(sigma_src, plan, sigma_wedge=None):
+    """(F_r, F_phi) on a patch plan's destination from its source patch (and
+    wedge densities for plans with wedges), differentiable in both (backward
+    = the patch transpose)."""
+    global _FN
+    if _FN is None:
+        _FN = _make_function()
+    return _FN[1].apply(sigma_src, sigma_wedge, plan)
 
 
 class CartPlan:

@@ -413,3 +413,23 @@ def test_fig4_case1_orders():
              % (name, np.array2string(e[:, 0], precision=3), np.array2string(e[:, 2], precision=3),
                 fit[0], fit[1], late[0], late[1], ref[0], ref[1]))
         assert abs(fit[0] - ref[0]) < 0.15 and abs(fit[1] - ref[1]) < 0.15
+
+
+@pytest.mark.parametrize("wedges", [False, True])
+def test_patch_autograd_gradcheck(wedges):
+    # pf.patch_forces is differentiable in the source densities and the wedge
+    # densities (the map is linear: central differences of step 1e-3 carry
+    # rounding only), turned source included
+    plan = pf.PatchPlan(5, -5, 6, 8, 0.5, 2.0, wedges=wedges, dtype="f64", src_col0=3)
+    try:
+        gen = torch.Generator().manual_seed(1509)
+        s = torch.randn(5, 8, dtype=torch.float64, generator=gen).cuda().requires_grad_(True)
+        if wedges:
+            w = torch.randn(8, dtype=torch.float64, generator=gen).cuda().requires_grad_(True)
+            assert torch.autograd.gradcheck(lambda a, b: pf.patch_forces(a, plan, b), (s, w),
+                                            eps=1e-3, atol=1e-9)
+        else:
+            assert torch.autograd.gradcheck(lambda a: pf.patch_forces(a, plan), (s,),
+                                            eps=1e-3, atol=1e-9)
+    finally:
+        plan.close()
