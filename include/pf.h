@@ -243,8 +243,9 @@ int pf_forces_patches_backward(pf_plan plan, const void *g_fr, const void *g_fph
  * columns -- pass A of all disks, then pass B, then pass C.  The results
  * equal pf_forces on each plan bit for bit (the rows or columns per
  * workgroup change no arithmetic).  Arrays sigma[k], f_r[k],
- * f_phi[k] follow plan[k]'s layout.  Sizes: 128 <= n_phi <= 4096 and
- * 33 <= n_r <= 2048; other plans give PF_EUNSUPPORTED.  A plan may appear
+ * f_phi[k] follow plan[k]'s layout.  Sizes: n_phi a power of two in
+ * [128, 4096] and 33 <= n_r <= 2048; other plans give PF_EUNSUPPORTED.  A
+ * plan may appear
  * once per batch (PF_EINVAL otherwise).  Plans of a batch share internal
  * state: do not run two batches with common plans at once.  The first call
  * for a set of plans allocates the batch's device tables (released with the
