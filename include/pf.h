@@ -245,9 +245,9 @@ int pf_forces_patches_backward(pf_plan plan, const void *g_fr, const void *g_fph
  * workgroup change no arithmetic).  Arrays sigma[k], f_r[k],
  * f_phi[k] follow plan[k]'s layout.  Sizes: n_phi a power of two in
  * [128, 4096] and 33 <= n_r <= 2048; other plans give PF_EUNSUPPORTED.  A
- * plan may appear
- * once per batch (PF_EINVAL otherwise).  Plans of a batch share internal
- * state: do not run two batches with common plans at once.  The first call
+ * plan may appear once per batch (PF_EINVAL otherwise).  Plans of a batch
+ * share internal state: do not run two batches with common plans at once.
+ * The first call
  * for a set of plans allocates the batch's device tables (released with the
  * plans); a call whose field pointers differ from the previous call's
  * enqueues their upload (kernel arguments, nothing waits); otherwise the call
