@@ -247,12 +247,11 @@ int pf_forces_patches_backward(pf_plan plan, const void *g_fr, const void *g_fph
  * [128, 4096] and 33 <= n_r <= 2048; other plans give PF_EUNSUPPORTED.  A
  * plan may appear once per batch (PF_EINVAL otherwise).  Plans of a batch
  * share internal state: do not run two batches with common plans at once.
- * The first call
- * for a set of plans allocates the batch's device tables (released with the
- * plans); a call whose field pointers differ from the previous call's
- * enqueues their upload (kernel arguments, nothing waits); otherwise the call
- * only enqueues the class launches (asynchronous, and it may be captured
- * into a HIP graph).  The launches read the batch's pointer table at run
+ * The first call for a set of plans allocates the batch's device tables
+ * (released with the plans); a call whose field pointers differ from the
+ * previous call's enqueues their upload (kernel arguments, nothing waits);
+ * otherwise the call only enqueues the class launches (asynchronous, and it
+ * may be captured into a HIP graph).  The launches read the batch's pointer table at run
  * time: a graph replay writes to the fields of the most recent call for
  * that set of plans.  1 <= n <= 4096.                                       */
 int pf_forces_batched(int n, const pf_plan *plans, const void *const *sigma,
