@@ -74,6 +74,22 @@ def test_forward_matches_brute_force_quadrature():
     assert 3.5 < ratio < 4.8, ratio
 
 
+@pytest.mark.parametrize("n_phi", [12, 18])
+def test_forward_matches_brute_force_three_smooth(n_phi):
+    # the sums do not assume a power-of-two azimuthal count: on grids of
+    # 3 x 4 and 9 x 2 cells the oracle agrees with the brute-force
+    # quadrature to its N_tpz trapezoid error (N_tpz = 399)
+    g = oracle.Grid(3, n_phi, 0.5, 2.0)
+    sig = workloads.random_field(g.shape, seed_k=12)
+    sk = oracle.selfcell_cover(g.beta, g.dphi)[:3]
+    cells = [(0, 1), (2, n_phi - 2)]
+    dest = [i * g.n_phi + j for i, j in cells]
+    fr, fp = oracle.forward(g, oracle.tables(g, 399, self_k=sk), sig, dest)
+    T = oracle.tables(g, 19, self_k=sk)
+    bf = np.array([_brute_force(g, T, sig, i, j) for i, j in cells])
+    assert np.abs(np.stack([fr, fp], 1) - bf).max() < 2e-6 * np.abs(bf).max()
+
+
 @pytest.fixture(scope="module")
 def small():
     g = oracle.Grid(24, 32, 0.1, 10.0)
