@@ -313,14 +313,25 @@ __device__ __forceinline__ void body_rows_c2rq(int unit, int G, cx<T> *__restric
         for (int a = 0; a < Q * C; ++a)
 #pragma unroll
             for (int e = 0; e < E; ++e) v[a][e] = scale(v[a][e], up);
+    // z[Qn + r] back in order through LDS (the transforms' last reads are
+    // behind their final barrier), so that each store writes consecutive
+    // points
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        const Lds<T> mir = rowq_mirror_lds<T, P, Q>(buf, gi, G, c);
+#pragma unroll
+        for (int e = 0; e < E; ++e)
+#pragma unroll
+            for (int r = 0; r < Q; ++r) mir.st(Q * (t + e * TH) + r, v[Q * c + r][e]);
+    }
+    __syncthreads();
     if (active) {
 #pragma unroll
         for (int c = 0; c < C; ++c) {
+            const Lds<T> mir = rowq_mirror_lds<T, P, Q>(buf, gi, G, c);
             cx<T> *yz = reinterpret_cast<cx<T> *>((c == 0 ? out0 : out1) + (size_t)i * N);
 #pragma unroll
-            for (int e = 0; e < E; ++e)
-#pragma unroll
-                for (int r = 0; r < Q; ++r) store_stream(&yz[Q * (t + e * TH) + r], v[Q * c + r][e]);
+            for (int u = 0; u < Q * E; ++u) store_stream(&yz[t + u * TH], mir.ld(t + u * TH));
         }
     }
 }
