@@ -165,7 +165,7 @@ int forces_t(const Plan &p, const T *sigma, const T *sigma_w, T *fr, T *fp, hipS
                                 g);
     if (rc) return rc;
     if (p.wedges) {
-        rc = pf::launch_wedge_terms<T>(p, sigma, sigma_w, Z, st, g);
+        rc = pf::launch_wedge_terms<T>(p, S, sigma_w, Z, st, g);
         if (rc) return rc;
     }
     return pf::launch_rows_c2r<T>(p, Z, p.n_r, fr, fp, (const C *)p.twN, p.sched.rows2, st, g,
@@ -174,7 +174,8 @@ int forces_t(const Plan &p, const T *sigma, const T *sigma_w, T *fr, T *fp, hipS
 
 // Transpose: pass A on the n_r destination rows of both cotangents, the
 // transposed column pass to the n_in source rows, pass C on those; plans
-// with wedges then the wedges' transpose from the same row spectra.
+// with wedges add the wedges' sums from the same row spectra before pass C
+// and their row transform after it.
 template <typename T>
 int backward_t(const Plan &p, const T *gr, const T *gp, T *gs, T *gw, hipStream_t st) {
     using C = pf::cx<T>;
@@ -186,10 +187,14 @@ int backward_t(const Plan &p, const T *gr, const T *gp, T *gs, T *gw, hipStream_
     rc = pf::launch_cols_adj<T>(p, V, D, (const C *)p.spec, (const C *)p.twL, p.sched.cols_adj,
                                 st, g);
     if (rc) return rc;
+    if (p.wedges) {
+        rc = pf::launch_wedge_adjoint_sums<T>(p, V, D, st, g);
+        if (rc) return rc;
+    }
     rc = pf::launch_rows_c2r<T>(p, D, p.n_in, gs, nullptr, (const C *)p.twN, p.sched.rows, st, g,
                                 -p.col0);
     if (rc || !p.wedges) return rc;
-    return pf::launch_wedge_adjoint<T>(p, V, gs, gw, st, g);
+    return pf::launch_wedge_adjoint_rows<T>(p, gw, st, g);
 }
 
 template <typename T>

@@ -142,18 +142,22 @@ int launch_cols_adj(const Plan &p, const cx<T> *V, cx<T> *D, const cx<T> *spec,
 int build_tables_and_spectra(Plan &p, hipStream_t st);
 // Origin-wedge spectra (plans with wedges) and the per-call wedge terms:
 // Z += the wedges' contribution, from the wedge densities sigma_w[n_phi] and
-// the first source row.
+// the first source row's spectrum S[0] (pass A's output).
 int build_wedge_spectra(Plan &p, hipStream_t st);
 template <typename T>
-int launch_wedge_terms(const Plan &p, const T *sigma_src, const T *sigma_w, cx<T> *Z,
-                       hipStream_t st, const unsigned *g = nullptr);
-// Transpose of the wedge terms, from the cotangents' row spectra V (pass A
-// of the transpose, (V_r, V_p) pairs on the n_r destination rows; run after
-// the transpose's column pass and pass C): writes g_w[n_phi] and adds the
-// wedges' radial-slope share to the first source row g_src[0][:].
+int launch_wedge_terms(const Plan &p, const cx<T> *S, const T *sigma_w, cx<T> *Z, hipStream_t st,
+                       const unsigned *g = nullptr);
+// Transpose of the wedge terms, in two parts.  Sums (after the transpose's
+// column pass, before its pass C): from the cotangents' row spectra V
+// ((V_r, V_p) pairs on the n_r destination rows), the wedge row's spectrum
+// into the plan's wedge workspace, and the first source row's share of the
+// wedges' radial slope added to D[0] (the source spectra pass C reads).
+// Rows (after that pass C): the wedge gradient g_w[n_phi] from that spectrum.
 template <typename T>
-int launch_wedge_adjoint(const Plan &p, const cx<T> *V, T *g_src, T *g_w, hipStream_t st,
-                         unsigned *g);
+int launch_wedge_adjoint_sums(const Plan &p, const cx<T> *V, cx<T> *D, hipStream_t st,
+                              unsigned *g);
+template <typename T>
+int launch_wedge_adjoint_rows(const Plan &p, T *g_w, hipStream_t st, unsigned *g);
 
 // ---- host helpers -------------------------------------------------------------
 // exp(-2 pi i j / n) for j in [0, n), computed in long double

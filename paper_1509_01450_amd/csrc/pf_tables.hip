@@ -947,24 +947,20 @@ __global__ void k_wedge_fold(const cx<double> *__restrict__ rowspec, WedgeGeo g,
     }
 }
 
-// delta^r of the wedges: towards the centre of the first source row
-template <typename T>
-__global__ void k_wedge_slope(const T *__restrict__ sigma_src, const T *__restrict__ sigma_w,
-                              int n_phi, T inv_dr, T *__restrict__ out) {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j < n_phi) out[j] = (sigma_src[j] - sigma_w[j]) * inv_dr;
-}
-
-// Z[i][k] += wedge terms, from the row spectra w[k] = (sigma_w^, delta^r^)
+// Z[i][k] += wedge terms.  w[k] = sigma_w^ (the wedge row's spectrum); the
+// wedges' radial slope (sigma_src[0] - sigma_w) / (r_0 - r_w / 2) is linear,
+// so its spectrum is (S[0][k] - w[k]) inv_dr with S[0] the first source
+// row's spectrum from pass A (bins 0 and n_phi/2 packed alike).
 template <typename T>
 __global__ void k_wedge_add(cx2<T> *__restrict__ Z, const cx2<T> *__restrict__ wspec,
-                            const cx2<T> *__restrict__ w, int n_r, int H,
-                            const unsigned *__restrict__ g) {
+                            const cx<T> *__restrict__ w, const cx<T> *__restrict__ S0,
+                            T inv_dr, int n_r, int H, const unsigned *__restrict__ g) {
     const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= (long)n_r * H) return;
     const int k = (int)(idx % H);
     const cx2<T> a = wspec[idx], b = wspec[(size_t)n_r * H + idx];
-    cx2<T> x = w[k];
+    const cx<T> ws = w[k], s0 = S0[k];
+    cx2<T> x = {ws, scale(s0 - ws, inv_dr)};
     if (g) {
         // FP32 calls: Z holds the column pass's output scaled by 2^-e (e in
         // the scale words, after the 64 notes); the wedge terms join it at
@@ -992,10 +988,12 @@ __global__ void k_wedge_add(cx2<T> *__restrict__ Z, const cx2<T> *__restrict__ w
 // n_phi/2 real and packed as in the forward.  Stage 1: workgroup (x, y)
 // sums the rows of chunk y for bins [64 x, 64 x + 64), four row lanes per
 // bin, reduced through LDS in a fixed order; stage 2 sums the chunks in
-// order, so the result does not depend on timing.  FP32: V is the pass-A
-// output (unscaled); it is taken times 2^-e (e from the transpose's scale
-// words, written by its column pass), so wbar carries the same scale as
-// the column pass's output and the row transform that follows restores it.
+// order, so the result does not depend on timing, and splits wbar into
+// the wedge row's spectrum and the first source row's share.  FP32: V is
+// the pass-A output (unscaled); it is taken times 2^-e (e from the
+// transpose's scale words, written by its column pass), so wbar carries the
+// same scale as the column pass's output D, and the row transforms that
+// follow (pass C, the wedge row's) restore it.
 constexpr int kWedgeLanes = 4;
 template <typename T>
 __global__ __launch_bounds__(64 * kWedgeLanes) void k_wedge_adj_part(
@@ -1041,9 +1039,14 @@ __global__ __launch_bounds__(64 * kWedgeLanes) void k_wedge_adj_part(
     }
 }
 
+// Stage 2: wbar = (wbar_s, wbar_d) summed over the chunks in order; the
+// wedge row's spectrum gets wbar_s - inv_dr wbar_d (sigma_w enters its own
+// density and, negatively, its radial slope) and the first source row's
+// spectrum D[0] (the column pass's output, before pass C) its share of that
+// slope, + inv_dr wbar_d.
 template <typename T>
-__global__ void k_wedge_adj_sum(const cx2<T> *__restrict__ part, int chunks, int H,
-                                cx2<T> *__restrict__ wbar) {
+__global__ void k_wedge_adj_sum(const cx2<T> *__restrict__ part, int chunks, int H, T inv_dr,
+                                cx<T> *__restrict__ wg, cx<T> *__restrict__ D0) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= H) return;
     cx2<T> acc = part[k];
@@ -1052,21 +1055,9 @@ __global__ void k_wedge_adj_sum(const cx2<T> *__restrict__ part, int chunks, int
         acc.a = acc.a + o.a;
         acc.b = acc.b + o.b;
     }
-    wbar[k] = acc;
-}
-
-// From the row transforms x = C2R(wbar.a), y = C2R(wbar.b): the wedge
-// gradient x - y / (r_0 - r_w / 2) (sigma_w enters its own density and,
-// negatively, its radial slope) and the first source row's share of that
-// slope, + y / (r_0 - r_w / 2)
-template <typename T>
-__global__ void k_wedge_adj_fin(const T *__restrict__ x, const T *__restrict__ y, int n_phi,
-                                T inv_dr, T *__restrict__ g_w, T *__restrict__ g_src0) {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= n_phi) return;
-    const T d = y[j] * inv_dr;
-    g_w[j] = x[j] - d;
-    g_src0[j] += d;
+    const cx<T> d = scale(acc.b, inv_dr);
+    wg[k] = acc.a - d;
+    D0[k] = D0[k] + d;
 }
 
 // Row chunks of the wedge transpose's first stage: enough workgroups to
@@ -1112,79 +1103,72 @@ int build_wedge_spectra(Plan &p, hipStream_t st) {
                            (cx<float> *)p.wspec, (long)(2 * nw));
         PF_HIP(hipGetLastError());
     }
-    // workspace.  Forward: the slope row (n_phi values), then the row's
-    // spectra (H pairs).  Transpose: two rows of n_phi values, wbar (H
-    // pairs), then the stage-1 partial sums (chunks x H pairs).
+    // workspace: the wedge row's spectrum (H complex), then (transpose) the
+    // stage-1 partial sums (chunks x H pairs)
     int rows, chunks;
     wedge_adj_chunks(p.n_r, p.H, &rows, &chunks);
-    const size_t tb = f64 ? 8 : 4, pb = f64 ? 32 : 16;
-    const size_t fwd = (size_t)p.n_phi * tb + (size_t)p.H * pb;
-    const size_t bwd = 2 * (size_t)p.n_phi * tb + (size_t)(1 + chunks) * p.H * pb;
-    PF_HIP(hipMalloc(&p.wws, std::max(fwd, bwd)));
+    const size_t cb = f64 ? 16 : 8;
+    PF_HIP(hipMalloc(&p.wws, (size_t)p.H * cb + (size_t)chunks * p.H * 2 * cb));
     PF_HIP(hipStreamSynchronize(st));
     return PF_OK;
 }
 
 template <typename T>
-int launch_wedge_terms(const Plan &p, const T *sigma_src, const T *sigma_w, cx<T> *Z,
-                       hipStream_t st, const unsigned *g) {
-    T *slope = (T *)p.wws;
-    cx<T> *wrow = (cx<T> *)((char *)p.wws + (size_t)p.n_phi * sizeof(T));
+int launch_wedge_terms(const Plan &p, const cx<T> *S, const T *sigma_w, cx<T> *Z, hipStream_t st,
+                       const unsigned *g) {
+    cx<T> *wrow = (cx<T> *)p.wws;
     const double rc0 = p.r_min * std::pow(p.beta, p.s0) * 0.5 * (1.0 + p.beta);
     const double rh = 0.5 * p.r_min * std::pow(p.beta, p.s0);
-    hipLaunchKernelGGL(k_wedge_slope<T>, dim3((p.n_phi + 255) / 256), dim3(256), 0, st,
-                       sigma_src, sigma_w, p.n_phi, T(1.0 / (rc0 - rh)), slope);
-    PF_HIP(hipGetLastError());
     // (the forward's scale words: the note lands after pass B has read the
     // notes, and pass C clears it)
-    int rc = launch_rows_r2c<T>(p, sigma_w, slope, 1, wrow, (const cx<T> *)p.twN, p.sched.rows2,
+    int rc = launch_rows_r2c<T>(p, sigma_w, nullptr, 1, wrow, (const cx<T> *)p.twN, p.sched.rows,
                                 st, p.gscale);
     if (rc) return rc;
     const long n = (long)p.n_r * p.H;
     hipLaunchKernelGGL(k_wedge_add<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st,
                        reinterpret_cast<cx2<T> *>(Z), (const cx2<T> *)p.wspec,
-                       reinterpret_cast<const cx2<T> *>(wrow), p.n_r, p.H,
+                       (const cx<T> *)wrow, S, T(1.0 / (rc0 - rh)), p.n_r, p.H,
                        sizeof(T) == 4 ? g : nullptr);
     PF_HIP(hipGetLastError());
     return PF_OK;
 }
 
 template <typename T>
-int launch_wedge_adjoint(const Plan &p, const cx<T> *V, T *g_src, T *g_w, hipStream_t st,
-                         unsigned *g) {
+int launch_wedge_adjoint_sums(const Plan &p, const cx<T> *V, cx<T> *D, hipStream_t st,
+                              unsigned *g) {
     int rows, chunks;
     wedge_adj_chunks(p.n_r, p.H, &rows, &chunks);
-    T *x = (T *)p.wws;
-    T *y = x + p.n_phi;
-    cx2<T> *wbar = reinterpret_cast<cx2<T> *>(y + p.n_phi);
-    cx2<T> *part = wbar + p.H;
+    cx<T> *wg = (cx<T> *)p.wws;
+    cx2<T> *part = reinterpret_cast<cx2<T> *>(wg + p.H);
+    const double rc0 = p.r_min * std::pow(p.beta, p.s0) * 0.5 * (1.0 + p.beta);
+    const double rh = 0.5 * p.r_min * std::pow(p.beta, p.s0);
     const unsigned *gs = sizeof(T) == 4 ? g : nullptr;
     hipLaunchKernelGGL(k_wedge_adj_part<T>, dim3((unsigned)((p.H + 63) / 64), (unsigned)chunks),
                        dim3(64 * kWedgeLanes), 0, st, reinterpret_cast<const cx2<T> *>(V),
                        (const cx2<T> *)p.wspec, p.n_r, p.H, rows, part, gs);
     PF_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_wedge_adj_sum<T>, dim3((unsigned)((p.H + 255) / 256)), dim3(256), 0, st,
-                       (const cx2<T> *)part, chunks, p.H, wbar);
-    PF_HIP(hipGetLastError());
-    int rc = launch_rows_c2r<T>(p, reinterpret_cast<const cx<T> *>(wbar), 1, x, y,
-                                (const cx<T> *)p.twN, p.sched.rows2, st, g, -p.col0);
-    if (rc) return rc;
-    const double rc0 = p.r_min * std::pow(p.beta, p.s0) * 0.5 * (1.0 + p.beta);
-    const double rh = 0.5 * p.r_min * std::pow(p.beta, p.s0);
-    hipLaunchKernelGGL(k_wedge_adj_fin<T>, dim3((p.n_phi + 255) / 256), dim3(256), 0, st, x, y,
-                       p.n_phi, T(1.0 / (rc0 - rh)), g_w, g_src);
+                       (const cx2<T> *)part, chunks, p.H, T(1.0 / (rc0 - rh)), wg, D);
     PF_HIP(hipGetLastError());
     return PF_OK;
 }
 
-template int launch_wedge_adjoint<float>(const Plan &, const cx<float> *, float *, float *,
-                                         hipStream_t, unsigned *);
-template int launch_wedge_adjoint<double>(const Plan &, const cx<double> *, double *, double *,
-                                          hipStream_t, unsigned *);
+template <typename T>
+int launch_wedge_adjoint_rows(const Plan &p, T *g_w, hipStream_t st, unsigned *g) {
+    return launch_rows_c2r<T>(p, (const cx<T> *)p.wws, 1, g_w, nullptr, (const cx<T> *)p.twN,
+                              p.sched.rows, st, g, -p.col0);
+}
 
-template int launch_wedge_terms<float>(const Plan &, const float *, const float *, cx<float> *,
-                                       hipStream_t, const unsigned *);
-template int launch_wedge_terms<double>(const Plan &, const double *, const double *,
+template int launch_wedge_adjoint_sums<float>(const Plan &, const cx<float> *, cx<float> *,
+                                              hipStream_t, unsigned *);
+template int launch_wedge_adjoint_sums<double>(const Plan &, const cx<double> *, cx<double> *,
+                                               hipStream_t, unsigned *);
+template int launch_wedge_adjoint_rows<float>(const Plan &, float *, hipStream_t, unsigned *);
+template int launch_wedge_adjoint_rows<double>(const Plan &, double *, hipStream_t, unsigned *);
+
+template int launch_wedge_terms<float>(const Plan &, const cx<float> *, const float *,
+                                       cx<float> *, hipStream_t, const unsigned *);
+template int launch_wedge_terms<double>(const Plan &, const cx<double> *, const double *,
                                         cx<double> *, hipStream_t, const unsigned *);
 
 }  // namespace pf
