@@ -1039,25 +1039,41 @@ __global__ __launch_bounds__(64 * kWedgeLanes) void k_wedge_adj_part(
     }
 }
 
-// Stage 2: wbar = (wbar_s, wbar_d) summed over the chunks in order; the
-// wedge row's spectrum gets wbar_s - inv_dr wbar_d (sigma_w enters its own
-// density and, negatively, its radial slope) and the first source row's
-// spectrum D[0] (the column pass's output, before pass C) its share of that
-// slope, + inv_dr wbar_d.
+// Stage 2: wbar = (wbar_s, wbar_d) summed over the chunks: sixteen lanes per
+// bin (sixteen bins per workgroup), lane l taking chunks l, l + 16, ... in
+// order, then the lanes in order (a fixed order); the wedge row's spectrum
+// gets wbar_s - inv_dr wbar_d (sigma_w enters its own density and,
+// negatively, its radial slope) and the first source row's spectrum D[0]
+// (the column pass's output, before pass C) its share of that slope,
+// + inv_dr wbar_d.
+constexpr int kSumLanes = 16;
 template <typename T>
-__global__ void k_wedge_adj_sum(const cx2<T> *__restrict__ part, int chunks, int H, T inv_dr,
-                                cx<T> *__restrict__ wg, cx<T> *__restrict__ D0) {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= H) return;
-    cx2<T> acc = part[k];
-    for (int c = 1; c < chunks; ++c) {
-        const cx2<T> o = part[(size_t)c * H + k];
-        acc.a = acc.a + o.a;
-        acc.b = acc.b + o.b;
+__global__ __launch_bounds__(16 * kSumLanes) void k_wedge_adj_sum(
+    const cx2<T> *__restrict__ part, int chunks, int H, T inv_dr, cx<T> *__restrict__ wg,
+    cx<T> *__restrict__ D0) {
+    const int k = blockIdx.x * 16 + (threadIdx.x & 15);
+    const int lane = threadIdx.x >> 4;
+    cx2<T> acc = {{T(0), T(0)}, {T(0), T(0)}};
+    if (k < H)
+        for (int c = lane; c < chunks; c += kSumLanes) {
+            const cx2<T> o = part[(size_t)c * H + k];
+            acc.a = acc.a + o.a;
+            acc.b = acc.b + o.b;
+        }
+    __shared__ cx2<T> red[kSumLanes][16];
+    red[lane][threadIdx.x & 15] = acc;
+    __syncthreads();
+    if (lane == 0 && k < H) {
+#pragma unroll
+        for (int l = 1; l < kSumLanes; ++l) {
+            const cx2<T> o = red[l][threadIdx.x];
+            acc.a = acc.a + o.a;
+            acc.b = acc.b + o.b;
+        }
+        const cx<T> d = scale(acc.b, inv_dr);
+        wg[k] = acc.a - d;
+        D0[k] = D0[k] + d;
     }
-    const cx<T> d = scale(acc.b, inv_dr);
-    wg[k] = acc.a - d;
-    D0[k] = D0[k] + d;
 }
 
 // Row chunks of the wedge transpose's first stage: enough workgroups to
@@ -1147,8 +1163,9 @@ int launch_wedge_adjoint_sums(const Plan &p, const cx<T> *V, cx<T> *D, hipStream
                        dim3(64 * kWedgeLanes), 0, st, reinterpret_cast<const cx2<T> *>(V),
                        (const cx2<T> *)p.wspec, p.n_r, p.H, rows, part, gs);
     PF_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_wedge_adj_sum<T>, dim3((unsigned)((p.H + 255) / 256)), dim3(256), 0, st,
-                       (const cx2<T> *)part, chunks, p.H, T(1.0 / (rc0 - rh)), wg, D);
+    hipLaunchKernelGGL(k_wedge_adj_sum<T>, dim3((unsigned)((p.H + 15) / 16)),
+                       dim3(16 * kSumLanes), 0, st, (const cx2<T> *)part, chunks, p.H,
+                       T(1.0 / (rc0 - rh)), wg, D);
     PF_HIP(hipGetLastError());
     return PF_OK;
 }
