@@ -138,7 +138,7 @@ void pf_build_opts_default(pf_build_opts *opts);
 /* Create a plan for an n_r x n_phi grid on [r_min, r_max] (Sec. 3.2.1).
  * Host only; touches no GPU.  Requirements: 4 <= n_r <= 4096;
  * n_phi a power of two in [8, 8192], three times one in [24, 6144] or nine
- * times one in [72, 4608] (the batched path takes powers of two only);
+ * times one in [72, 4608] (the batched path: n_phi in [128, 4096]);
  * 0 < r_min < r_max, both finite.
  * Returns NULL on failure (see pf_last_error()); PF_EUNSUPPORTED-type size
  * failures are reported the same way.                                      */
@@ -243,8 +243,9 @@ int pf_forces_patches_backward(pf_plan plan, const void *g_fr, const void *g_fph
  * columns -- pass A of all disks, then pass B, then pass C.  The results
  * equal pf_forces on each plan bit for bit (the rows or columns per
  * workgroup change no arithmetic).  Arrays sigma[k], f_r[k],
- * f_phi[k] follow plan[k]'s layout.  Sizes: n_phi a power of two in
- * [128, 4096] and 33 <= n_r <= 2048; other plans give PF_EUNSUPPORTED.  A
+ * f_phi[k] follow plan[k]'s layout.  Sizes: n_phi in [128, 4096] (a power
+ * of two, or three or nine times one) and 33 <= n_r <= 2048; other plans
+ * give PF_EUNSUPPORTED.  A
  * plan may appear once per batch (PF_EINVAL otherwise).  Plans of a batch
  * share internal state: do not run two batches with common plans at once.
  * The first call for a set of plans allocates the batch's device tables

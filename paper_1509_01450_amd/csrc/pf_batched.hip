@@ -31,6 +31,7 @@
 #include <vector>
 
 #include "pass_bodies.hpp"
+#include "rows_q.hpp"
 #include "pf_batched.hpp"
 
 namespace pf {
@@ -88,6 +89,25 @@ __global__ __launch_bounds__(512) void k_grp_rows(const GDisk<T> *__restrict__ d
     else
         body_rows_c2r<T, M, E, 2>(unit, G, buf, reinterpret_cast<const cx<T> *>(d.Z), d.n_r,
                                   d.fr, d.fp, d.twN, d.gscale);
+}
+
+// The same for rows of N_phi = 2 Q P points (Q = 3 or 9, rows_q.hpp):
+// G = blockDim.x / (P / E), LDS C G rowq_len(P, Q) complex.
+template <typename T, int P, int Q, int E, int C>
+__global__ __launch_bounds__(512) void k_grp_rowsq(const GDisk<T> *__restrict__ desc,
+                                                   const GEntry *__restrict__ ent, int n_ent) {
+    extern __shared__ unsigned char smem_raw[];
+    const GEntry en = find_entry(ent, n_ent);
+    const GDisk<T> &d = desc[en.disk];
+    const int unit = blockIdx.x - en.first;
+    const int G = blockDim.x / (P / E);
+    cx<T> *const buf = reinterpret_cast<cx<T> *>(smem_raw);
+    if constexpr (C == 1)
+        body_rows_r2cq<T, P, Q, E, 1>(unit, G, buf, d.sigma, nullptr, d.n_r, d.S, d.twN,
+                                      d.gscale);
+    else
+        body_rows_c2rq<T, P, Q, E, 2>(unit, G, buf, reinterpret_cast<const cx<T> *>(d.Z), d.n_r,
+                                      d.fr, d.fp, d.twN, d.gscale, 0);
 }
 
 // Column groups of a disk are remapped as in the single-disk kernels: a
@@ -157,7 +177,7 @@ namespace {
 // ===========================================================================
 // Sizes the grouped kernels instantiate.
 bool batch_size_ok(const Plan &p) {
-    return is_pow2_int(p.M) && p.M >= 64 && p.M <= 2048 && p.L >= 128 && p.L <= 4096;
+    return row_factor(p.M) != 0 && p.M >= 64 && p.M <= 2048 && p.L >= 128 && p.L <= 4096;
 }
 
 // One class launch: a kernel shape and the range [e0, e1) of its pass's
@@ -327,6 +347,41 @@ struct GLaunch {
     int rows1(Shape s) { return rows_e<M, 1>(s); }
     template <int M>
     int rows2(Shape s) { return rows_e<M, 2>(s); }
+    template <int P, int Q, int E, int C>
+    int rowsq(int G) {
+        if constexpr (E <= P) {
+            const size_t lds = (size_t)C * G * rowq_len(P, Q) * sizeof(cx<T>);
+            int rc = allow_lds(k_grp_rowsq<T, P, Q, E, C>, lds);
+            if (rc) return rc;
+            hipLaunchKernelGGL((k_grp_rowsq<T, P, Q, E, C>), dim3(blocks), dim3(G * (P / E)), lds,
+                               st, desc, ent, n_ent);
+            PF_HIP(hipGetLastError());
+            return PF_OK;
+        }
+        set_error("row transform of %d x %d points cannot take %d points per thread", Q, P, E);
+        return PF_EUNSUPPORTED;
+    }
+    // points per thread as the standalone kernels take them: 4 or 8 (Q = 3),
+    // 2 (Q = 9)
+    template <int P, int Q, int C>
+    int rowsq_e(Shape s) {
+        if constexpr (Q == 3) {
+            if (s.E == 4) return rowsq<P, 3, 4, C>(s.G);
+            if (s.E == 8) return rowsq<P, 3, 8, C>(s.G);
+        } else {
+            if (s.E == 2) return rowsq<P, 9, 2, C>(s.G);
+        }
+        set_error("bad points per thread %d", s.E);
+        return PF_EUNSUPPORTED;
+    }
+    template <int P>
+    int rows1q3(Shape s) { return rowsq_e<P, 3, 1>(s); }
+    template <int P>
+    int rows2q3(Shape s) { return rowsq_e<P, 3, 2>(s); }
+    template <int P>
+    int rows1q9(Shape s) { return rowsq_e<P, 9, 1>(s); }
+    template <int P>
+    int rows2q9(Shape s) { return rowsq_e<P, 9, 2>(s); }
     template <int L, int E, int G>
     bool cols_pf() {
         constexpr int TH = L / E;
@@ -381,6 +436,25 @@ struct GLaunch {
         case 2048: return F<2048>(__VA_ARGS__);                                          \
         default: set_error("unsupported batched row length %d", v); return PF_EUNSUPPORTED; \
     }
+// sub-transform lengths of the batched rows M = 3 P and M = 9 P, M in [64, 2048]
+#define PF_SWITCH_P3B(v, F, ...)                                                         \
+    switch (v) {                                                                         \
+        case 32: return F<32>(__VA_ARGS__);                                              \
+        case 64: return F<64>(__VA_ARGS__);                                              \
+        case 128: return F<128>(__VA_ARGS__);                                            \
+        case 256: return F<256>(__VA_ARGS__);                                            \
+        case 512: return F<512>(__VA_ARGS__);                                            \
+        default: set_error("unsupported batched row length 3 x %d", v); return PF_EUNSUPPORTED; \
+    }
+#define PF_SWITCH_P9B(v, F, ...)                                                         \
+    switch (v) {                                                                         \
+        case 8: return F<8>(__VA_ARGS__);                                                \
+        case 16: return F<16>(__VA_ARGS__);                                              \
+        case 32: return F<32>(__VA_ARGS__);                                              \
+        case 64: return F<64>(__VA_ARGS__);                                              \
+        case 128: return F<128>(__VA_ARGS__);                                            \
+        default: set_error("unsupported batched row length 9 x %d", v); return PF_EUNSUPPORTED; \
+    }
 #define PF_SWITCH_COLS(v, F, ...)                                                        \
     switch (v) {                                                                         \
         case 128: return F<128>(__VA_ARGS__);                                            \
@@ -397,6 +471,18 @@ int launch_class(const GClass &c, const void *desc, const GEntry *ent, hipStream
     GLaunch<T> g{(const GDisk<T> *)desc, ent + c.e0, c.e1 - c.e0, c.blocks, st};
     if (c.pass == 1) {
         PF_SWITCH_COLS(c.n, g.template cols_e, c.s);
+    }
+    if (row_factor(c.n) == 3) {
+        if (c.pass == 0) {
+            PF_SWITCH_P3B(c.n / 3, g.template rows1q3, c.s);
+        }
+        PF_SWITCH_P3B(c.n / 3, g.template rows2q3, c.s);
+    }
+    if (row_factor(c.n) == 9) {
+        if (c.pass == 0) {
+            PF_SWITCH_P9B(c.n / 9, g.template rows1q9, c.s);
+        }
+        PF_SWITCH_P9B(c.n / 9, g.template rows2q9, c.s);
     }
     if (c.pass == 0) {
         PF_SWITCH_ROWS(c.n, g.template rows1, c.s);
@@ -430,8 +516,8 @@ size_t desc_size(bool f64, int n) {
 int check_plans(const Plan *const *plans, int n) {
     for (int k = 0; k < n; ++k) {
         if (!batch_size_ok(*plans[k])) {
-            set_error("batched path needs n_phi a power of two in [128, 4096] and "
-                      "33 <= n_r <= 2048 "
+            set_error("batched path needs n_phi in [128, 4096] (a power of two, or three or "
+                      "nine times one) and 33 <= n_r <= 2048 "
                       "(disk %d: %d x %d)", k, plans[k]->n_r, plans[k]->n_phi);
             return PF_EUNSUPPORTED;
         }

@@ -55,6 +55,34 @@ def _check_against_single(plans, sig, outs, tol=1e-6):
     return worst
 
 
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_three_and_nine_split_rows_in_a_batch(dtype):
+    # disks with N_phi three or nine times a power of two (split row
+    # transforms) batched with power-of-two disks: each equals its own plan
+    # bit for bit, the split-row classes included, and the oracle on a
+    # small one
+    sizes = [(64, 192), (40, 256), (100, 144), (33, 1536), (70, 2304), (64, 128)]
+    plans, sig = _disks(sizes, dtype=dtype)
+    _say("split-row disks in a batch (%s)" % dtype)
+    try:
+        outs = pf.forces_batched(plans, sig)
+        torch.cuda.synchronize()
+        worst = _check_against_single(plans, sig, outs)
+        _say("  vs single-disk worst rel-L2 %.3e" % worst)
+        g = oracle.Grid(64, 192, 0.01, 100.0)
+        T = oracle.tables(g, 19)
+        fr_o, fp_o = oracle.forward(g, T, sig[0].double().cpu().numpy())
+        fr, fp = outs[0]
+        e1 = float(np.linalg.norm(fr.double().cpu().numpy() - fr_o) / np.linalg.norm(fr_o))
+        e2 = float(np.linalg.norm(fp.double().cpu().numpy() - fp_o) / np.linalg.norm(fp_o))
+        _say("  64 x 192 vs oracle rel-L2 %.3e %.3e" % (e1, e2))
+        tol = 1e-11 if dtype == "f64" else 1e-5
+        assert e1 <= tol and e2 <= tol
+    finally:
+        for p in plans:
+            p.close()
+
+
 def test_two_small_disks():
     plans, sig = _disks([(64, 128), (40, 256)])
     _say("two small disks: batched call")

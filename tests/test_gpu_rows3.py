@@ -4,7 +4,7 @@ and a radix-Q step, Q = 3 or 9) against the FP64 oracle: forward map and
 transpose, full grids from the smallest such grids (N_phi = 24, 72) up to
 several row tiles with a ragged radial count, the largest (N_phi = 6144,
 4608) on sampled cells, the particle method, patch plans with wedges and
-turns, the FP32 grid scale, and the refusal of the batched path.  Bars:
+turns, the FP32 grid scale, and the batched path's size limits.  Bars:
 relative L2 1e-11 (FP64) and 1e-5 (FP32) per component."""
 import sys
 
@@ -179,11 +179,13 @@ def test_fp32_grid_scale(n_phi):
         plan.close()
 
 
-def test_batched_refuses_three_p():
-    p = pf.Plan(64, 192, 0.1, 10.0, dtype="f32")
+def test_batched_refuses_other_counts():
+    # the batched path takes the split rows too, within its row lengths:
+    # n_phi = 48 (M = 24) is below them
+    p = pf.Plan(64, 48, 0.1, 10.0, dtype="f32")
     try:
-        s = torch.ones(64, 192, device="cuda")
-        with pytest.raises(pf.PFError, match="power of two"):
+        s = torch.ones(64, 48, device="cuda")
+        with pytest.raises(pf.PFError, match="batched path needs"):
             pf.forces_batched([p], [s])
     finally:
         p.close()
