@@ -57,6 +57,27 @@ def test_plan_create_accepts_azimuthal_counts(n_phi):
         pf.pf_plan_destroy(h)
 
 
+def test_split_row_shapes_are_validated():
+    # rows of n_phi = 2 Q P points take 4 or 8 points per thread (Q = 3; 8
+    # only in FP32: the plan is unbuilt, so the FP32 default precision
+    # applies) or 2 (Q = 9), at most P points; fitting shapes on an unbuilt
+    # plan are a state error, the others invalid
+    lib = pf.load()
+    cols = (16, 1, 16, 1)   # L = 256 at n_r = 100: 16 threads per column -> G = 4 below
+    for n_phi, good, bad in ((96, [(4, 4), (8, 8), (4, 64)], [(2, 8), (16, 2), (4, 256)]),
+                             (144, [(2, 8), (2, 16)], [(4, 4), (8, 2), (16, 1)])):
+        h = pf.pf_plan_create(100, n_phi, 0.1, 10.0)
+        try:
+            for E, G in good:
+                arr = (ctypes.c_int * 8)(E, G, E, G, 16, 4, 16, 4)
+                assert lib.pf_plan_set_schedule(h, arr) == pf.PF_ESTATE, (n_phi, E, G)
+            for E, G in bad:
+                arr = (ctypes.c_int * 8)(E, G, E, G, 16, 4, 16, 4)
+                assert lib.pf_plan_set_schedule(h, arr) == pf.PF_EINVAL, (n_phi, E, G)
+        finally:
+            pf.pf_plan_destroy(h)
+
+
 def test_plan_geometry_matches_grid_definition():
     h = pf.pf_plan_create(40, 64, 0.01, 100.0)
     try:
