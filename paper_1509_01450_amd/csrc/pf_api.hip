@@ -158,14 +158,16 @@ int forces_t(const Plan &p, const T *sigma, const T *sigma_w, T *fr, T *fp, hipS
     C *S = (C *)p.ws;
     C *Z = S + (size_t)p.n_in * p.H;   // (Zr, Zp) pairs
     unsigned *g = p.gscale;   // the forward map's scale words
+    // plans with wedges: the wedge row's transform rides in pass A's launch
+    C *wrow = p.wedges ? (C *)p.wws : nullptr;
     int rc = pf::launch_rows_r2c<T>(p, sigma, nullptr, p.n_in, S, (const C *)p.twN, p.sched.rows,
-                                    st, g);
+                                    st, g, p.wedges ? sigma_w : nullptr, wrow);
     if (rc) return rc;
     rc = pf::launch_cols_fwd<T>(p, S, Z, (const C *)p.spec, (const C *)p.twL, p.sched.cols, st,
                                 g);
     if (rc) return rc;
     if (p.wedges) {
-        rc = pf::launch_wedge_terms<T>(p, S, sigma_w, Z, st, g);
+        rc = pf::launch_wedge_terms<T>(p, S, wrow, Z, st, g);
         if (rc) return rc;
     }
     return pf::launch_rows_c2r<T>(p, Z, p.n_r, fr, fp, (const C *)p.twN, p.sched.rows2, st, g,
@@ -174,8 +176,8 @@ int forces_t(const Plan &p, const T *sigma, const T *sigma_w, T *fr, T *fp, hipS
 
 // Transpose: pass A on the n_r destination rows of both cotangents, the
 // transposed column pass to the n_in source rows, pass C on those; plans
-// with wedges add the wedges' sums from the same row spectra before pass C
-// and their row transform after it.
+// with wedges add the wedges' sums from the same row spectra before pass C,
+// whose launch also transforms the wedge row.
 template <typename T>
 int backward_t(const Plan &p, const T *gr, const T *gp, T *gs, T *gw, hipStream_t st) {
     using C = pf::cx<T>;
@@ -191,10 +193,9 @@ int backward_t(const Plan &p, const T *gr, const T *gp, T *gs, T *gw, hipStream_
         rc = pf::launch_wedge_adjoint_sums<T>(p, V, D, st, g);
         if (rc) return rc;
     }
-    rc = pf::launch_rows_c2r<T>(p, D, p.n_in, gs, nullptr, (const C *)p.twN, p.sched.rows, st, g,
-                                -p.col0);
-    if (rc || !p.wedges) return rc;
-    return pf::launch_wedge_adjoint_rows<T>(p, gw, st, g);
+    return pf::launch_rows_c2r<T>(p, D, p.n_in, gs, nullptr, (const C *)p.twN, p.sched.rows, st,
+                                  g, -p.col0, p.wedges ? (const C *)p.wws : nullptr,
+                                  p.wedges ? gw : nullptr);
 }
 
 template <typename T>

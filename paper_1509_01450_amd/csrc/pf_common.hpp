@@ -96,22 +96,27 @@ struct Plan {
 // ([n_rows][M] pairs).  c2r: the inverse, from complex rows to out0, or from
 // pairs to out0 and out1 when out1 is given.  g: the call's FP32 scale
 // words (pass_bodies.hpp: r2c notes the largest magnitude in them, c2r
-// clears them; nullptr: no scaling).
+// clears them; nullptr: no scaling).  xin -> xout: one extra row of its own
+// buffers in the same launch (one-channel transforms only; the origin
+// wedges' row).
 template <typename T>
 int launch_rows_r2c(const Plan &p, const T *in0, const T *in1, int n_rows, cx<T> *out,
-                    const cx<T> *twN, Shape s, hipStream_t st, unsigned *g = nullptr);
+                    const cx<T> *twN, Shape s, hipStream_t st, unsigned *g = nullptr,
+                    const T *xin = nullptr, cx<T> *xout = nullptr);
 template <typename T>
 int launch_rows_c2r(const Plan &p, const cx<T> *in, int n_rows, T *out0, T *out1,
                     const cx<T> *twN, Shape s, hipStream_t st, unsigned *g = nullptr,
-                    int turn = 0);
+                    int turn = 0, const cx<T> *xin = nullptr, T *xout = nullptr);
 // Rows of n_phi = 2 Q P points, Q = 3 or 9, P a power of two (pf_rows3.hip):
 // M = Q P.
 template <typename T>
 int launch_rows_r2cq(int M, const T *in0, const T *in1, int n_rows, cx<T> *out,
-                     const cx<T> *twN, Shape s, hipStream_t st, unsigned *g);
+                     const cx<T> *twN, Shape s, hipStream_t st, unsigned *g, const T *xin,
+                     cx<T> *xout);
 template <typename T>
 int launch_rows_c2rq(int M, const cx<T> *in, int n_rows, T *out0, T *out1, const cx<T> *twN,
-                     Shape s, hipStream_t st, unsigned *g, int turn);
+                     Shape s, hipStream_t st, unsigned *g, int turn, const cx<T> *xin,
+                     T *xout);
 size_t rowsq_lds_bytes(int P, int Q, int G, int C, bool f64);
 // The row transforms' M = n_phi / 2 complex points: a power of two, or
 // three or nine times one (then Q sub-transforms of M / Q points);
@@ -141,23 +146,22 @@ int launch_cols_adj(const Plan &p, const cx<T> *V, cx<T> *D, const cx<T> *spec,
 // ---- kernels (pf_tables.hip) ------------------------------------------------
 int build_tables_and_spectra(Plan &p, hipStream_t st);
 // Origin-wedge spectra (plans with wedges) and the per-call wedge terms:
-// Z += the wedges' contribution, from the wedge densities sigma_w[n_phi] and
-// the first source row's spectrum S[0] (pass A's output).
+// Z += the wedges' contribution, from the wedge row's spectrum wrow (pass A
+// transforms sigma_w into the plan's wedge workspace) and the first source
+// row's spectrum S[0].
 int build_wedge_spectra(Plan &p, hipStream_t st);
 template <typename T>
-int launch_wedge_terms(const Plan &p, const cx<T> *S, const T *sigma_w, cx<T> *Z, hipStream_t st,
-                       const unsigned *g = nullptr);
-// Transpose of the wedge terms, in two parts.  Sums (after the transpose's
-// column pass, before its pass C): from the cotangents' row spectra V
-// ((V_r, V_p) pairs on the n_r destination rows), the wedge row's spectrum
-// into the plan's wedge workspace, and the first source row's share of the
-// wedges' radial slope added to D[0] (the source spectra pass C reads).
-// Rows (after that pass C): the wedge gradient g_w[n_phi] from that spectrum.
+int launch_wedge_terms(const Plan &p, const cx<T> *S, const cx<T> *wrow, cx<T> *Z,
+                       hipStream_t st, const unsigned *g = nullptr);
+// Transpose of the wedge terms (after the transpose's column pass, before
+// its pass C): from the cotangents' row spectra V ((V_r, V_p) pairs on the
+// n_r destination rows), the wedge row's spectrum into the plan's wedge
+// workspace (pass C's launch transforms it into the wedge gradient), and the
+// first source row's share of the wedges' radial slope added to D[0] (the
+// source spectra pass C reads).
 template <typename T>
 int launch_wedge_adjoint_sums(const Plan &p, const cx<T> *V, cx<T> *D, hipStream_t st,
                               unsigned *g);
-template <typename T>
-int launch_wedge_adjoint_rows(const Plan &p, T *g_w, hipStream_t st, unsigned *g);
 
 // ---- host helpers -------------------------------------------------------------
 // exp(-2 pi i j / n) for j in [0, n), computed in long double

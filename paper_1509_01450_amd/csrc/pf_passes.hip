@@ -13,27 +13,46 @@ namespace pf {
 // columns share cache lines of the row-major intermediates.
 __device__ __forceinline__ int xcd_group(int b, int per_xcd) { return (b & 7) * per_xcd + (b >> 3); }
 
+// The one-channel row kernels take one extra row of its own buffers (xin ->
+// xout, the origin wedges' row) in one more workgroup (n_x = 1), the first
+// of the grid so that it does not trail the others, and so that it costs no
+// launch of its own.
 template <typename T, int M, int E, int C>
 __global__ __launch_bounds__(512) void k_rows_r2c(const T *__restrict__ in0,
                                                   const T *__restrict__ in1, int n_rows,
                                                   cx<T> *__restrict__ out,
                                                   const cx<T> *__restrict__ twN,
-                                                  unsigned *__restrict__ gscale) {
+                                                  unsigned *__restrict__ gscale,
+                                                  const T *__restrict__ xin,
+                                                  cx<T> *__restrict__ xout, int n_x) {
     extern __shared__ unsigned char smem_raw[];
-    body_rows_r2c<T, M, E, C>(blockIdx.x, blockDim.x / (M / E),
-                              reinterpret_cast<cx<T> *>(smem_raw), in0, in1, n_rows, out, twN,
-                              gscale);
+    const int G = blockDim.x / (M / E);
+    cx<T> *const buf = reinterpret_cast<cx<T> *>(smem_raw);
+    if constexpr (C == 1)
+        if (n_x && blockIdx.x == 0) {   // workgroup-uniform
+            body_rows_r2c<T, M, E, 1>(0, G, buf, xin, nullptr, 1, xout, twN, gscale);
+            return;
+        }
+    body_rows_r2c<T, M, E, C>(blockIdx.x - n_x, G, buf, in0, in1, n_rows, out, twN, gscale);
 }
 
 template <typename T, int M, int E, int C>
 __global__ __launch_bounds__(512) void k_rows_c2r(const cx<T> *__restrict__ in, int n_rows,
                                                   T *__restrict__ out0, T *__restrict__ out1,
                                                   const cx<T> *__restrict__ twN,
-                                                  unsigned *__restrict__ gscale, int turn) {
+                                                  unsigned *__restrict__ gscale, int turn,
+                                                  const cx<T> *__restrict__ xin,
+                                                  T *__restrict__ xout, int n_x) {
     extern __shared__ unsigned char smem_raw[];
-    body_rows_c2r<T, M, E, C>(blockIdx.x, blockDim.x / (M / E),
-                              reinterpret_cast<cx<T> *>(smem_raw), in, n_rows, out0, out1, twN,
-                              gscale, turn);
+    const int G = blockDim.x / (M / E);
+    cx<T> *const buf = reinterpret_cast<cx<T> *>(smem_raw);
+    if constexpr (C == 1)
+        if (n_x && blockIdx.x == 0) {   // workgroup-uniform
+            body_rows_c2r<T, M, E, 1>(0, G, buf, xin, 1, xout, nullptr, twN, gscale, turn);
+            return;
+        }
+    body_rows_c2r<T, M, E, C>(blockIdx.x - n_x, G, buf, in, n_rows, out0, out1, twN, gscale,
+                              turn);
 }
 
 // Forward column pass for any G, with one dynamic LDS array: used where the
@@ -242,15 +261,16 @@ template <typename T>
 struct Disp {
     template <int N, int E, int C>
     static int r2c(const T *in0, const T *in1, int n_rows, cx<T> *out, const cx<T> *tw, int G,
-                   hipStream_t st, unsigned *g) {
+                   hipStream_t st, unsigned *g, const T *xin, cx<T> *xout) {
         if constexpr (E <= N) {
             constexpr int TH = N / E;
             const int blocks = (n_rows + G - 1) / G;
             const size_t lds = (size_t)C * G * padded_len(N) * sizeof(cx<T>);
             int rc = allow_lds(k_rows_r2c<T, N, E, C>, lds);
             if (rc) return rc;
-            hipLaunchKernelGGL((k_rows_r2c<T, N, E, C>), dim3(blocks), dim3(G * TH), lds, st, in0,
-                               in1, n_rows, out, tw, g);
+            hipLaunchKernelGGL((k_rows_r2c<T, N, E, C>), dim3(blocks + (xin ? 1 : 0)),
+                               dim3(G * TH), lds, st, in0, in1, n_rows, out, tw, g, xin, xout,
+                               xin ? 1 : 0);
             PF_HIP(hipGetLastError());
             return PF_OK;
         }
@@ -259,15 +279,16 @@ struct Disp {
     }
     template <int N, int E, int C>
     static int c2r(const cx<T> *in, int n_rows, T *o0, T *o1, const cx<T> *tw, int G,
-                   hipStream_t st, unsigned *g, int turn) {
+                   hipStream_t st, unsigned *g, int turn, const cx<T> *xin, T *xout) {
         if constexpr (E <= N) {
             constexpr int TH = N / E;
             const int blocks = (n_rows + G - 1) / G;
             const size_t lds = (size_t)C * G * padded_len(N) * sizeof(cx<T>);
             int rc = allow_lds(k_rows_c2r<T, N, E, C>, lds);
             if (rc) return rc;
-            hipLaunchKernelGGL((k_rows_c2r<T, N, E, C>), dim3(blocks), dim3(G * TH), lds, st, in,
-                               n_rows, o0, o1, tw, g, turn);
+            hipLaunchKernelGGL((k_rows_c2r<T, N, E, C>), dim3(blocks + (xin ? 1 : 0)),
+                               dim3(G * TH), lds, st, in, n_rows, o0, o1, tw, g, turn, xin,
+                               xout, xin ? 1 : 0);
             PF_HIP(hipGetLastError());
             return PF_OK;
         }
@@ -351,18 +372,18 @@ struct Disp {
     }
     template <int N>
     static int r2c_e(int E, const T *in0, const T *in1, int n_rows, cx<T> *out, const cx<T> *tw,
-                     int G, hipStream_t st, unsigned *g) {
+                     int G, hipStream_t st, unsigned *g, const T *xin, cx<T> *xout) {
         if (in1) {
             switch (E) {
-                case 4: return r2c<N, 4, 2>(in0, in1, n_rows, out, tw, G, st, g);
-                case 8: return r2c<N, 8, 2>(in0, in1, n_rows, out, tw, G, st, g);
-                case 16: return r2c<N, 16, 2>(in0, in1, n_rows, out, tw, G, st, g);
+                case 4: return r2c<N, 4, 2>(in0, in1, n_rows, out, tw, G, st, g, xin, xout);
+                case 8: return r2c<N, 8, 2>(in0, in1, n_rows, out, tw, G, st, g, xin, xout);
+                case 16: return r2c<N, 16, 2>(in0, in1, n_rows, out, tw, G, st, g, xin, xout);
             }
         } else {
             switch (E) {
-                case 4: return r2c<N, 4, 1>(in0, in1, n_rows, out, tw, G, st, g);
-                case 8: return r2c<N, 8, 1>(in0, in1, n_rows, out, tw, G, st, g);
-                case 16: return r2c<N, 16, 1>(in0, in1, n_rows, out, tw, G, st, g);
+                case 4: return r2c<N, 4, 1>(in0, in1, n_rows, out, tw, G, st, g, xin, xout);
+                case 8: return r2c<N, 8, 1>(in0, in1, n_rows, out, tw, G, st, g, xin, xout);
+                case 16: return r2c<N, 16, 1>(in0, in1, n_rows, out, tw, G, st, g, xin, xout);
             }
         }
         set_error("bad points per thread %d", E);
@@ -370,18 +391,19 @@ struct Disp {
     }
     template <int N>
     static int c2r_e(int E, const cx<T> *in, int n_rows, T *o0, T *o1, const cx<T> *tw, int G,
-                     hipStream_t st, unsigned *g, int turn) {
+                     hipStream_t st, unsigned *g, int turn, const cx<T> *xin,
+                     T *xout) {
         if (o1) {
             switch (E) {
-                case 4: return c2r<N, 4, 2>(in, n_rows, o0, o1, tw, G, st, g, turn);
-                case 8: return c2r<N, 8, 2>(in, n_rows, o0, o1, tw, G, st, g, turn);
-                case 16: return c2r<N, 16, 2>(in, n_rows, o0, o1, tw, G, st, g, turn);
+                case 4: return c2r<N, 4, 2>(in, n_rows, o0, o1, tw, G, st, g, turn, xin, xout);
+                case 8: return c2r<N, 8, 2>(in, n_rows, o0, o1, tw, G, st, g, turn, xin, xout);
+                case 16: return c2r<N, 16, 2>(in, n_rows, o0, o1, tw, G, st, g, turn, xin, xout);
             }
         } else {
             switch (E) {
-                case 4: return c2r<N, 4, 1>(in, n_rows, o0, o1, tw, G, st, g, turn);
-                case 8: return c2r<N, 8, 1>(in, n_rows, o0, o1, tw, G, st, g, turn);
-                case 16: return c2r<N, 16, 1>(in, n_rows, o0, o1, tw, G, st, g, turn);
+                case 4: return c2r<N, 4, 1>(in, n_rows, o0, o1, tw, G, st, g, turn, xin, xout);
+                case 8: return c2r<N, 8, 1>(in, n_rows, o0, o1, tw, G, st, g, turn, xin, xout);
+                case 16: return c2r<N, 16, 1>(in, n_rows, o0, o1, tw, G, st, g, turn, xin, xout);
             }
         }
         set_error("bad points per thread %d", E);
@@ -413,7 +435,12 @@ struct Disp {
 
 template <typename T>
 int launch_rows_r2c(const Plan &p, const T *in0, const T *in1, int n_rows, cx<T> *out,
-                    const cx<T> *twN, Shape s, hipStream_t st, unsigned *g) {
+                    const cx<T> *twN, Shape s, hipStream_t st, unsigned *g, const T *xin,
+                    cx<T> *xout) {
+    if (xin && in1) {
+        set_error("an extra row goes with one-channel row transforms only");
+        return PF_EINVAL;
+    }
     if (sizeof(T) == 4 && !g) {
         set_error("FP32 passes need the plan's scale words");
         return PF_EINVAL;
@@ -423,13 +450,19 @@ int launch_rows_r2c(const Plan &p, const T *in0, const T *in1, int n_rows, cx<T>
         return PF_EINVAL;
     }
     if (!is_pow2_int(p.M))
-        return launch_rows_r2cq<T>(p.M, in0, in1, n_rows, out, twN, s, st, g);
-    PF_SWITCH_POW2(p.M, Disp<T>::template r2c_e, s.E, in0, in1, n_rows, out, twN, s.G, st, g);
+        return launch_rows_r2cq<T>(p.M, in0, in1, n_rows, out, twN, s, st, g, xin, xout);
+    PF_SWITCH_POW2(p.M, Disp<T>::template r2c_e, s.E, in0, in1, n_rows, out, twN, s.G, st, g, xin,
+                   xout);
 }
 
 template <typename T>
 int launch_rows_c2r(const Plan &p, const cx<T> *in, int n_rows, T *out0, T *out1,
-                    const cx<T> *twN, Shape s, hipStream_t st, unsigned *g, int turn) {
+                    const cx<T> *twN, Shape s, hipStream_t st, unsigned *g, int turn,
+                    const cx<T> *xin, T *xout) {
+    if (xin && out1) {
+        set_error("an extra row goes with one-channel row transforms only");
+        return PF_EINVAL;
+    }
     if (sizeof(T) == 4 && !g) {
         set_error("FP32 passes need the plan's scale words");
         return PF_EINVAL;
@@ -441,9 +474,9 @@ int launch_rows_c2r(const Plan &p, const cx<T> *in, int n_rows, T *out0, T *out1
     turn %= p.n_phi;
     if (turn < 0) turn += p.n_phi;
     if (!is_pow2_int(p.M))
-        return launch_rows_c2rq<T>(p.M, in, n_rows, out0, out1, twN, s, st, g, turn);
+        return launch_rows_c2rq<T>(p.M, in, n_rows, out0, out1, twN, s, st, g, turn, xin, xout);
     PF_SWITCH_POW2(p.M, Disp<T>::template c2r_e, s.E, in, n_rows, out0, out1, twN, s.G, st, g,
-                   turn);
+                   turn, xin, xout);
 }
 
 template <typename T>
@@ -476,9 +509,10 @@ int launch_cols_adj(const Plan &p, const cx<T> *V, cx<T> *D, const cx<T> *spec,
 
 #define PF_INSTANTIATE(T)                                                                      \
     template int launch_rows_r2c<T>(const Plan &, const T *, const T *, int, cx<T> *,          \
-                                    const cx<T> *, Shape, hipStream_t, unsigned *);             \
+                                    const cx<T> *, Shape, hipStream_t, unsigned *, const T *,   \
+                                    cx<T> *);                                                   \
     template int launch_rows_c2r<T>(const Plan &, const cx<T> *, int, T *, T *, const cx<T> *,  \
-                                    Shape, hipStream_t, unsigned *, int);                       \
+                                    Shape, hipStream_t, unsigned *, int, const cx<T> *, T *);   \
     template int launch_cols_fwd<T>(const Plan &, const cx<T> *, cx<T> *, const cx<T> *,        \
                                     const cx<T> *, Shape, hipStream_t, unsigned *);             \
     template int launch_cols_adj<T>(const Plan &, const cx<T> *, cx<T> *, const cx<T> *,        \

@@ -1130,21 +1130,14 @@ int build_wedge_spectra(Plan &p, hipStream_t st) {
 }
 
 template <typename T>
-int launch_wedge_terms(const Plan &p, const cx<T> *S, const T *sigma_w, cx<T> *Z, hipStream_t st,
-                       const unsigned *g) {
-    cx<T> *wrow = (cx<T> *)p.wws;
+int launch_wedge_terms(const Plan &p, const cx<T> *S, const cx<T> *wrow, cx<T> *Z,
+                       hipStream_t st, const unsigned *g) {
     const double rc0 = p.r_min * std::pow(p.beta, p.s0) * 0.5 * (1.0 + p.beta);
     const double rh = 0.5 * p.r_min * std::pow(p.beta, p.s0);
-    // (the forward's scale words: the note lands after pass B has read the
-    // notes, and pass C clears it)
-    int rc = launch_rows_r2c<T>(p, sigma_w, nullptr, 1, wrow, (const cx<T> *)p.twN, p.sched.rows,
-                                st, p.gscale);
-    if (rc) return rc;
     const long n = (long)p.n_r * p.H;
     hipLaunchKernelGGL(k_wedge_add<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st,
-                       reinterpret_cast<cx2<T> *>(Z), (const cx2<T> *)p.wspec,
-                       (const cx<T> *)wrow, S, T(1.0 / (rc0 - rh)), p.n_r, p.H,
-                       sizeof(T) == 4 ? g : nullptr);
+                       reinterpret_cast<cx2<T> *>(Z), (const cx2<T> *)p.wspec, wrow, S,
+                       T(1.0 / (rc0 - rh)), p.n_r, p.H, sizeof(T) == 4 ? g : nullptr);
     PF_HIP(hipGetLastError());
     return PF_OK;
 }
@@ -1170,22 +1163,14 @@ int launch_wedge_adjoint_sums(const Plan &p, const cx<T> *V, cx<T> *D, hipStream
     return PF_OK;
 }
 
-template <typename T>
-int launch_wedge_adjoint_rows(const Plan &p, T *g_w, hipStream_t st, unsigned *g) {
-    return launch_rows_c2r<T>(p, (const cx<T> *)p.wws, 1, g_w, nullptr, (const cx<T> *)p.twN,
-                              p.sched.rows, st, g, -p.col0);
-}
-
 template int launch_wedge_adjoint_sums<float>(const Plan &, const cx<float> *, cx<float> *,
                                               hipStream_t, unsigned *);
 template int launch_wedge_adjoint_sums<double>(const Plan &, const cx<double> *, cx<double> *,
                                                hipStream_t, unsigned *);
-template int launch_wedge_adjoint_rows<float>(const Plan &, float *, hipStream_t, unsigned *);
-template int launch_wedge_adjoint_rows<double>(const Plan &, double *, hipStream_t, unsigned *);
 
-template int launch_wedge_terms<float>(const Plan &, const cx<float> *, const float *,
+template int launch_wedge_terms<float>(const Plan &, const cx<float> *, const cx<float> *,
                                        cx<float> *, hipStream_t, const unsigned *);
-template int launch_wedge_terms<double>(const Plan &, const cx<double> *, const double *,
+template int launch_wedge_terms<double>(const Plan &, const cx<double> *, const cx<double> *,
                                         cx<double> *, hipStream_t, const unsigned *);
 
 }  // namespace pf
