@@ -230,7 +230,7 @@ int pf_forces_backward(pf_plan plan, const void *g_fr, const void *g_fphi,
  * enters its own wedge's terms and, through the wedge's radial slope (the
  * difference towards the first source row), that row too: the first source
  * row's gradient holds that share.  Device pointers, the plan's precision;
- * PF_EINVAL for a wedge argument that does not match the plan.  Three more
+ * PF_EINVAL for a wedge argument that does not match the plan.  Two more
  * small launches than the transpose without wedges.  Asynchronous.        */
 int pf_forces_patches_backward(pf_plan plan, const void *g_fr, const void *g_fphi,
                                void *g_sigma_src, void *g_sigma_wedge, void *stream);
