@@ -959,16 +959,18 @@ __global__ void k_wedge_add(cx2<T> *__restrict__ Z, const cx2<T> *__restrict__ w
     if (idx >= (long)n_r * H) return;
     const int k = (int)(idx % H);
     const cx2<T> a = wspec[idx], b = wspec[(size_t)n_r * H + idx];
-    const cx<T> ws = w[k], s0 = S0[k];
-    cx2<T> x = {ws, scale(s0 - ws, inv_dr)};
+    cx<T> ws = w[k], s0 = S0[k];
     if (g) {
         // FP32 calls: Z holds the column pass's output scaled by 2^-e (e in
         // the scale words, after the 64 notes); the wedge terms join it at
-        // the same scale
+        // the same scale, applied before the slope's 1 / (r_0 - r_w / 2) so
+        // that no unscaled product leaves the range
         const int ex = (int)g[kScaleE];
         const T s = (T)__uint_as_float((unsigned)(127 - ex) << 23);
-        x = cx2<T>{scale(x.a, s), scale(x.b, s)};
+        ws = scale(ws, s);
+        s0 = scale(s0, s);
     }
+    const cx2<T> x = {ws, scale(s0 - ws, inv_dr)};
     cx2<T> z = Z[idx];
     if (k == 0) {   // bins 0 and n_phi/2: real parts, radial force only
         z.a.x += a.a.x * x.a.x + a.b.x * x.b.x;

@@ -228,6 +228,37 @@ def test_patch_transpose_with_wedges_fp32_scale():
         plan.close()
 
 
+@pytest.mark.parametrize("c0,n_phi", [(0, 32), (5, 48)])
+def test_patch_forward_with_wedges_fp32_scale(c0, n_phi):
+    # the forward with wedges under the FP32 grid scale (the wedge row is
+    # transformed in pass A's launch, so its magnitude enters the scale):
+    # source and wedge densities times 2^110 or 2^-100 give the forces times
+    # the same power bit for bit (normal outputs), turned sources included;
+    # also a wedge row 2^40 times the source patch (max |sigma| N_phi stays
+    # below 2^127, the range the scale covers, while the wedges' radial
+    # slope 1 / (r_0 - r_w / 2) ~ 2^7 would leave it without the scale)
+    n_src, s0, n_dst = 10, -10, 24
+    plan = pf.PatchPlan(n_src, s0, n_dst, n_phi, 0.05, 2.0, wedges=True, dtype="f32",
+                        src_col0=c0)
+    try:
+        s = torch.tensor(workloads.random_field((n_src, n_phi), 31) + 0.5, dtype=torch.float32,
+                         device="cuda")
+        for wf in (1.0, 2.0 ** 40):
+            w = torch.tensor((workloads.random_field((n_phi,), 32) + 0.5) * wf,
+                             dtype=torch.float32, device="cuda")
+            base = [x.clone() for x in plan.forces(s, w)]
+            for f in (2.0 ** 80, 2.0 ** -100):
+                got = plan.forces(s * f, w * f)
+                torch.cuda.synchronize()
+                for x, x1 in zip(got, base):
+                    a = x.double().cpu().numpy()
+                    want = x1.double().cpu().numpy() * f
+                    assert np.isfinite(a).all()
+                    assert np.array_equal(a[want != 0], want[want != 0]), (wf, f)
+    finally:
+        plan.close()
+
+
 def test_patch_transpose_wedge_arguments():
     plan = pf.PatchPlan(10, -10, 24, 32, 0.05, 2.0, wedges=True, dtype="f32")
     plain = pf.PatchPlan(10, -10, 24, 32, 0.05, 2.0, dtype="f32")
