@@ -360,7 +360,9 @@ pf_cart pf_cart_create(int n_x, int n_y, double dx, double dy);
  * or PF_F64; method: a pf_cart_method.  May be called again.              */
 int pf_cart_build(pf_cart plan, int dtype, int method, void *stream);
 
-/* sigma [N_x][N_y] -> f_x, f_y [N_x][N_y].  Asynchronous.                 */
+/* sigma [N_x][N_y] -> f_x, f_y [N_x][N_y].  FP32 plans scale each call by
+ * a power of two as the polar plans do (the forces of 2^k sigma are 2^k
+ * times those of sigma wherever they are normal numbers).  Asynchronous.  */
 int pf_cart_forces(pf_cart plan, const void *sigma, void *f_x, void *f_y, void *stream);
 
 /* Diagnostic form of pf_cart_forces: each of the three passes launched

@@ -252,11 +252,16 @@ __device__ __forceinline__ T cart_dy(int j, int n_y, T l, T c, T r, T idy) {
     return (r - l) * (T(0.5) * idy);
 }
 
+// gscale: the FP32 grid scale's words (pass_bodies.hpp), as in the polar
+// passes: pass A notes the largest magnitude of its rows (sigma and its
+// y-slope), pass B scales its columns by 2^-e after the first transform
+// stage, pass C restores 2^e and clears the notes; nullptr in FP64.
 template <typename T, int M, int E>
 __device__ __forceinline__ void body_cart_rows(int unit, int G, cx<T> *__restrict__ buf,
                                                const T *__restrict__ sigma, int n_x, int n_y,
                                                T idy, cx2<T> *__restrict__ out,
-                                               const cx<T> *__restrict__ twN) {
+                                               const cx<T> *__restrict__ twN,
+                                               unsigned *__restrict__ gscale) {
     constexpr int TH = M / E;
     const int gi = threadIdx.x / TH, t = threadIdx.x % TH;
     const int row = unit * G + gi;
@@ -284,6 +289,7 @@ __device__ __forceinline__ void body_cart_rows(int unit, int G, cx<T> *__restric
 #pragma unroll
         for (int e = 0; e < E; ++e)
             if (e >= E / 2 || !active) v[c][e] = cx<T>{T(0), T(0)};
+    scale_note<T, E, 2>(gscale, v);
     Twiddles<M, E, T> tw;
     tw.load(t, twN, 2);
     fft_fwd<M, E, 2, T, true>(v, t, lds, tw);
@@ -317,7 +323,8 @@ template <typename T, int M, int E>
 __device__ __forceinline__ void body_cart_c2r(int unit, int G, cx<T> *__restrict__ buf,
                                               const cx2<T> *__restrict__ in, int n_x, int n_y,
                                               T *__restrict__ out0, T *__restrict__ out1,
-                                              const cx<T> *__restrict__ twN) {
+                                              const cx<T> *__restrict__ twN,
+                                              unsigned *__restrict__ gscale) {
     constexpr int TH = M / E;
     const int gi = threadIdx.x / TH, t = threadIdx.x % TH;
     const int row = unit * G + gi;
@@ -368,6 +375,12 @@ __device__ __forceinline__ void body_cart_c2r(int unit, int G, cx<T> *__restrict
             v[c][e] = active ? cx<T>{s.x - dw.y, s.y + dw.x} : cx<T>{T(0), T(0)};
         }
     fft_inv<M, E, 2, T>(v, t, lds, tw);
+    const T up = scale_finish<T>(gscale, unit);
+    if (up != T(1))
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+#pragma unroll
+            for (int e = 0; e < E; ++e) v[c][e] = scale(v[c][e], up);
     if (active) {
 #pragma unroll
         for (int c = 0; c < 2; ++c) {
@@ -398,7 +411,8 @@ __device__ __forceinline__ void body_cart_cols(int unit, int G, cx<T> *__restric
                                                const cx<T> *__restrict__ rsp, int H, int n_x,
                                                int ldspec, T ca, T c0, T cn,
                                                const cx<T> *__restrict__ twL,
-                                               cx2<T> *spl = nullptr) {
+                                               cx2<T> *spl = nullptr,
+                                               unsigned *__restrict__ gscale = nullptr) {
     constexpr int TH = L / E;
     const int gi = threadIdx.x % G, t = threadIdx.x / G;
     const int col = unit * G + gi;
@@ -409,6 +423,8 @@ __device__ __forceinline__ void body_cart_cols(int unit, int G, cx<T> *__restric
     const Lds<T> lS{buf, gi, G};
     const Lds<T> lD{buf + (size_t)G * padded_len(L), gi, G};
 
+    // the scale note first (loads complete in order)
+    const unsigned note = scale_load<T>(gscale);
     cx<T> v[2][E];   // v[0]: S column, v[1]: Dy column
 #pragma unroll
     for (int e = 0; e < E / 2; ++e) {
@@ -432,8 +448,9 @@ __device__ __forceinline__ void body_cart_cols(int unit, int G, cx<T> *__restric
             v[1][e] = cx<T>{T(0), T(0)};
         }
     }
-    fft_fwd<L, E, T, true>(v[0], t, lS, tw);
-    fft_fwd<L, E, T, true>(v[1], t, lD, tw);
+    GridScale<T> sc;
+    fft_col_fwd<L, E, T>(v[0], t, lS, tw, ScaleFind<T>{gscale, note, unit, &sc});
+    fft_col_fwd<L, E, T>(v[1], t, lD, tw, ScaleKnown<T>{sc.dn});
     if (packed) {   // column 0 reads the conjugate mirror points from LDS
 #pragma unroll
         for (int e = 0; e < E; ++e) {
@@ -454,7 +471,8 @@ __device__ __forceinline__ void body_cart_cols(int unit, int G, cx<T> *__restric
     const cx2<T> *s1 = spec + (size_t)(H + cl) * ldspec;    // (E'_y, Q_y)
     const cx<T> *r0 = rsp + (size_t)cl * ldspec;            // R_x
     const cx<T> *r1 = rsp + (size_t)(H + cl) * ldspec;      // R_y
-    const SlopeFix<T> a = slope_fix(x0, x1, xm2, xm1, ca, c0, cn);
+    const SlopeFix<T> a = slope_fix(scale(x0, sc.dn), scale(x1, sc.dn), scale(xm2, sc.dn),
+                                    scale(xm1, sc.dn), ca, c0, cn);
     const SlopePhasors<T> ph = slope_phasors(a, wt, wnt);
     SlopePhasors<T> ph0 = ph, phM = ph;
     if (is0) {
@@ -530,20 +548,22 @@ __device__ __forceinline__ int cart_xcd_group(int b, int per_xcd) {
 template <typename T, int M, int E>
 __global__ __launch_bounds__(512) void k_cart_rows(const T *__restrict__ sigma, int n_x, int n_y,
                                                    T idy, cx2<T> *__restrict__ out,
-                                                   const cx<T> *__restrict__ twN) {
+                                                   const cx<T> *__restrict__ twN,
+                                                   unsigned *__restrict__ gscale) {
     extern __shared__ unsigned char smem_raw[];
     body_cart_rows<T, M, E>(blockIdx.x, blockDim.x / (M / E), reinterpret_cast<cx<T> *>(smem_raw),
-                            sigma, n_x, n_y, idy, out, twN);
+                            sigma, n_x, n_y, idy, out, twN, gscale);
 }
 
 template <typename T, int M, int E>
 __global__ __launch_bounds__(512) void k_cart_c2r(const cx2<T> *__restrict__ in, int n_x,
                                                   int n_y, T *__restrict__ out0,
                                                   T *__restrict__ out1,
-                                                  const cx<T> *__restrict__ twN) {
+                                                  const cx<T> *__restrict__ twN,
+                                                  unsigned *__restrict__ gscale) {
     extern __shared__ unsigned char smem_raw[];
     body_cart_c2r<T, M, E>(blockIdx.x, blockDim.x / (M / E), reinterpret_cast<cx<T> *>(smem_raw),
-                           in, n_x, n_y, out0, out1, twN);
+                           in, n_x, n_y, out0, out1, twN, gscale);
 }
 
 template <typename T, int L, int E>
@@ -553,12 +573,12 @@ __global__ __launch_bounds__(512) void k_cart_cols(const cx2<T> *__restrict__ SD
                                                    const cx<T> *__restrict__ rsp, int H, int n_x,
                                                    int ldspec, T ca, T c0, T cn,
                                                    const cx<T> *__restrict__ twL, int per_xcd,
-                                                   int n_groups) {
+                                                   int n_groups, unsigned *__restrict__ gscale) {
     extern __shared__ unsigned char smem_raw[];
     const int grp = cart_xcd_group(blockIdx.x, per_xcd);
     if (grp >= n_groups) return;   // whole workgroup leaves together
     body_cart_cols<T, L, E>(grp, blockDim.x / (L / E), reinterpret_cast<cx<T> *>(smem_raw), SD,
-                            Z, spec, rsp, H, n_x, ldspec, ca, c0, cn, twL);
+                            Z, spec, rsp, H, n_x, ldspec, ca, c0, cn, twL, nullptr, gscale);
 }
 
 // Column workgroup size of the Cartesian pass: one column of L / E threads,
@@ -583,14 +603,14 @@ __global__ __launch_bounds__(512) void k_cart_cols_pf(const cx2<T> *__restrict__
                                                       const cx<T> *__restrict__ rsp, int H,
                                                       int n_x, int ldspec, T ca, T c0, T cn,
                                                       const cx<T> *__restrict__ twL, int per_xcd,
-                                                      int n_groups) {
+                                                      int n_groups, unsigned *__restrict__ gscale) {
     constexpr int G = cart_cols_g(L, E);
     __shared__ cx<T> fbuf[2 * G * padded_len(L)];
     __shared__ cx2<T> spl[G * spec_prefetch_len<L, E>()];
     const int grp = cart_xcd_group(blockIdx.x, per_xcd);
     if (grp >= n_groups) return;   // whole workgroup leaves together
     body_cart_cols<T, L, E, true>(grp, G, fbuf, SD, Z, spec, rsp, H, n_x, ldspec, ca, c0, cn, twL,
-                                  spl);
+                                  spl, gscale);
 }
 
 }  // namespace
@@ -607,7 +627,9 @@ struct CartPlan {
     void *rsp = nullptr;    // [2][H][ldspec] complex R, plan precision
     void *twN = nullptr;    // L_y-point twiddles
     void *twL = nullptr;    // L_x-point twiddles
-    void *ws = nullptr;     // (S, Dy) pairs then (Zx, Zy) pairs, 2 N_x H each
+    void *ws = nullptr;     // (S, Dy) pairs then (Zx, Zy) pairs, 2 N_x H each, then
+                            // (FP32) the grid scale's words
+    unsigned *gscale = nullptr;
     Shape rows, cols;
 };
 
@@ -625,6 +647,7 @@ void free_cart(CartPlan &c) {
         if (*q) (void)hipFree(*q);
         *q = nullptr;
     }
+    c.gscale = nullptr;   // inside ws
     c.built = false;
 }
 
@@ -704,12 +727,14 @@ int rows_m(const CartPlan &c, bool pass_c, const void *in, void *o0, void *o1, h
         int rc = allow_lds_cart(k_cart_rows<T, M, E>, lds);
         if (rc) return rc;
         hipLaunchKernelGGL((k_cart_rows<T, M, E>), dim3(blocks), dim3(s.G * (M / E)), lds, st,
-                           (const T *)in, c.n_x, c.n_y, T(1.0 / c.dy), (cx2<T> *)o0, tw);
+                           (const T *)in, c.n_x, c.n_y, T(1.0 / c.dy), (cx2<T> *)o0, tw,
+                           sizeof(T) == 4 ? c.gscale : nullptr);
     } else {
         int rc = allow_lds_cart(k_cart_c2r<T, M, E>, lds);
         if (rc) return rc;
         hipLaunchKernelGGL((k_cart_c2r<T, M, E>), dim3(blocks), dim3(s.G * (M / E)), lds, st,
-                           (const cx2<T> *)in, c.n_x, c.n_y, (T *)o0, (T *)o1, tw);
+                           (const cx2<T> *)in, c.n_x, c.n_y, (T *)o0, (T *)o1, tw,
+                           sizeof(T) == 4 ? c.gscale : nullptr);
     }
     PF_HIP(hipGetLastError());
     return PF_OK;
@@ -749,7 +774,8 @@ int cols_l(const CartPlan &c, const void *SD, void *Z, hipStream_t st) {
         hipLaunchKernelGGL((k_cart_cols_pf<T, L, E>), dim3(per_xcd * 8), dim3(s.G * (L / E)), 0,
                            st, (const cx2<T> *)SD, (cx2<T> *)Z, (const cx2<T> *)c.spec,
                            (const cx<T> *)c.rsp, c.H, c.n_x, c.ldspec, T(0.5 / c.dx),
-                           T(1.0 / c.dx), T(1.0 / c.dx), (const cx<T> *)c.twL, per_xcd, n_groups);
+                           T(1.0 / c.dx), T(1.0 / c.dx), (const cx<T> *)c.twL, per_xcd, n_groups,
+                           sizeof(T) == 4 ? c.gscale : nullptr);
         PF_HIP(hipGetLastError());
         return PF_OK;
     }
@@ -759,7 +785,8 @@ int cols_l(const CartPlan &c, const void *SD, void *Z, hipStream_t st) {
     hipLaunchKernelGGL((k_cart_cols<T, L, E>), dim3(per_xcd * 8), dim3(s.G * (L / E)), lds, st,
                        (const cx2<T> *)SD, (cx2<T> *)Z, (const cx2<T> *)c.spec,
                        (const cx<T> *)c.rsp, c.H, c.n_x, c.ldspec, T(0.5 / c.dx), T(1.0 / c.dx),
-                       T(1.0 / c.dx), (const cx<T> *)c.twL, per_xcd, n_groups);
+                       T(1.0 / c.dx), (const cx<T> *)c.twL, per_xcd, n_groups,
+                       sizeof(T) == 4 ? c.gscale : nullptr);
     PF_HIP(hipGetLastError());
     return PF_OK;
 }
@@ -889,10 +916,16 @@ int cart_build(CartPlan &c, int dtype, int method, hipStream_t st) {
         if (!rc) rc = upload_twiddles(c.Lx, false, &c.twL);
         if (rc) return rc;
     }
-    if (hipMalloc(&c.ws, (size_t)2 * c.n_x * c.H * (f64 ? sizeof(cx2<double>) : sizeof(cx2<float>))) !=
-        hipSuccess) {
+    const size_t wsb = ((size_t)2 * c.n_x * c.H * (f64 ? sizeof(cx2<double>) : sizeof(cx2<float>)) +
+                        255) / 256 * 256;
+    if (hipMalloc(&c.ws, wsb + kScaleSet * sizeof(unsigned)) != hipSuccess) {
         set_error("Cartesian workspace allocation failed");
         return PF_ENOMEM;
+    }
+    c.gscale = nullptr;
+    if (!f64) {   // the notes start at zero; pass C leaves them so
+        c.gscale = (unsigned *)((unsigned char *)c.ws + wsb);
+        PF_HIP(hipMemsetAsync(c.gscale, 0, kScaleSet * sizeof(unsigned), st));
     }
     PF_HIP(hipStreamSynchronize(st));
     c.rows = cart_rows_shape(c.H);

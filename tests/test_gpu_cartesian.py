@@ -127,3 +127,40 @@ def test_fig3_orders_sigma_d2():
              % (method, np.array2string(e, precision=3), order, _fig3(method)))
         assert abs(order - _fig3(method)) < 0.15, (method, order)
     assert np.all(errs["second"] < errs["particle+"]) and np.all(errs["particle+"] < errs["particle"])
+
+
+FLT_MIN = float(np.finfo(np.float32).tiny)
+
+
+@pytest.mark.parametrize("method", ["second", "particle+"])
+@pytest.mark.parametrize("shape", [(37, 100), (128, 128), (512, 512)])
+def test_fp32_grid_scale(shape, method):
+    # the FP32 grid scale of the Cartesian passes: 2^110 sigma gives 2^110
+    # times the forces bit for bit (no overflow), 2^-100 sigma 2^-100 times
+    # them wherever that is a normal number (no flush of the small values),
+    # and the scaled forces still match the oracle
+    g = oracle.CartGrid(shape[0], shape[1], 1.0 / shape[0], 1.3 / shape[1], -0.5, -0.6)
+    sig = _density(g, 21 + shape[0])
+    plan = pf.CartPlan(g.n_x, g.n_y, g.dx, g.dy, dtype="f32", method=method)
+    try:
+        s = torch.tensor(sig, dtype=torch.float32, device="cuda")
+        base = [x.clone() for x in plan.forces(s)]
+        torch.cuda.synchronize()
+        for f in (2.0 ** 110, 2.0 ** -100):
+            got = plan.forces(s * f)
+            torch.cuda.synchronize()
+            for x, x1 in zip(got, base):
+                a = x.double().cpu().numpy()
+                want = x1.double().cpu().numpy() * f
+                assert np.isfinite(a).all(), f
+                normal = np.abs(want) >= FLT_MIN
+                assert np.array_equal(a[normal], want[normal]), f
+                assert np.all(np.abs(a[~normal] - want[~normal]) <= 2.0 ** -150), f
+    finally:
+        plan.close()
+    if shape[0] <= 128:
+        ox, oy = oracle.cart_forward(g, oracle.cart_tables(g, method), sig)
+        fx, fy = [x.double().cpu().numpy() for x in base]
+        _say("cartesian fp32 scale %s %s: rel-L2 F_x %.2e F_y %.2e" % (shape, method,
+                                                                        _rel(fx, ox), _rel(fy, oy)))
+        assert _rel(fx, ox) < 1e-5 and _rel(fy, oy) < 1e-5
