@@ -189,3 +189,61 @@ def test_batched_refuses_other_counts():
             pf.forces_batched([p], [s])
     finally:
         p.close()
+
+
+@pytest.mark.parametrize("n_phi", [96, 144])
+def test_fp32_grid_scale_transpose(n_phi):
+    # the transpose's scale words through the split rows: 2^110 and 2^-100
+    # cotangents give the gradient times the same power bit for bit
+    # (normal outputs)
+    shape = (37, n_phi, 0.01, 1.0)
+    g = oracle.Grid(*shape)
+    plan = pf.Plan(*shape, dtype="f32")
+    try:
+        a = _t(workloads.random_field(g.shape, 81), plan)
+        b = _t(workloads.random_field(g.shape, 82), plan)
+        base = plan.backward(a, b).clone()
+        for f in (2.0 ** 110, 2.0 ** -100):
+            got = plan.backward(a * f, b * f)
+            torch.cuda.synchronize()
+            x = got.double().cpu().numpy()
+            want = base.double().cpu().numpy() * f
+            normal = np.abs(want) >= float(np.finfo(np.float32).tiny)
+            assert np.isfinite(x).all(), f
+            assert np.array_equal(x[normal], want[normal]), f
+    finally:
+        plan.close()
+
+
+@pytest.mark.parametrize("n_phi", [96, 144])
+def test_slope_order4_and_exact_tables(n_phi):
+    # the split rows with five-point slopes, and with the exact table and
+    # self-cell modes, against the oracle's sums of the same reading
+    shape = (20, n_phi, 0.1, 10.0)
+    g = oracle.Grid(*shape)
+    sig = workloads.random_field(g.shape, seed_k=83) + 2.0
+    T = oracle.tables(g, 19)
+    fr_o, fp_o = oracle.forward(g, T, sig, slope_order=4)
+    for dt, tol in (("f64", 1e-11), ("f32", 1e-5)):
+        plan = pf.Plan(*shape, dtype=dt, slope_order=4)
+        try:
+            fr, fp = plan.forces(_t(sig, plan))
+            torch.cuda.synchronize()
+            e1 = _rel(fr.double().cpu().numpy(), fr_o)
+            e2 = _rel(fp.double().cpu().numpy(), fp_o)
+        finally:
+            plan.close()
+        _say("split rows, slope order 4, %s: rel-L2 %.2e %.2e" % (dt, e1, e2))
+        assert e1 <= tol and e2 <= tol
+    Te = oracle.tables(g, table_mode="exact", self_mode="exact")
+    fr_o, fp_o = oracle.forward(g, Te, sig)
+    plan = pf.Plan(*shape, dtype="f64", table_mode="exact", self_mode="exact")
+    try:
+        fr, fp = plan.forces(_t(sig, plan))
+        torch.cuda.synchronize()
+        e1 = _rel(fr.cpu().numpy(), fr_o)
+        e2 = _rel(fp.cpu().numpy(), fp_o)
+    finally:
+        plan.close()
+    _say("split rows, exact tables: rel-L2 %.2e %.2e" % (e1, e2))
+    assert e1 <= 1e-11 and e2 <= 1e-11
