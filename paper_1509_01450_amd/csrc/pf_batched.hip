@@ -78,7 +78,7 @@ __device__ __forceinline__ GEntry find_entry(const GEntry *__restrict__ ent, int
 template <typename T, int M, int E, int C>
 __global__ __launch_bounds__(512) void k_grp_rows(const GDisk<T> *__restrict__ desc,
                                                   const GEntry *__restrict__ ent, int n_ent) {
-    extern __shared__ unsigned char smem_raw[];
+    extern __shared__ __align__(16) unsigned char smem_raw[];
     const GEntry en = find_entry(ent, n_ent);
     const GDisk<T> &d = desc[en.disk];
     const int unit = blockIdx.x - en.first;
@@ -96,7 +96,7 @@ __global__ __launch_bounds__(512) void k_grp_rows(const GDisk<T> *__restrict__ d
 template <typename T, int P, int Q, int E, int C>
 __global__ __launch_bounds__(512) void k_grp_rowsq(const GDisk<T> *__restrict__ desc,
                                                    const GEntry *__restrict__ ent, int n_ent) {
-    extern __shared__ unsigned char smem_raw[];
+    extern __shared__ __align__(16) unsigned char smem_raw[];
     const GEntry en = find_entry(ent, n_ent);
     const GDisk<T> &d = desc[en.disk];
     const int unit = blockIdx.x - en.first;
@@ -140,7 +140,7 @@ __global__ __launch_bounds__(512) void k_grp_cols_pf(const GDisk<T> *__restrict_
 template <typename T, int L, int E>
 __global__ __launch_bounds__(512) void k_grp_cols(const GDisk<T> *__restrict__ desc,
                                                   const GEntry *__restrict__ ent, int n_ent) {
-    extern __shared__ unsigned char smem_raw[];
+    extern __shared__ __align__(16) unsigned char smem_raw[];
     const GEntry en = find_entry(ent, n_ent);
     const GDisk<T> &d = desc[en.disk];
     const int G = blockDim.x / (L / E);

@@ -165,7 +165,7 @@ __global__ __launch_bounds__(512) void k_cart_fold(const cx<double> *__restrict_
                                                    cx<double> *__restrict__ rsp, int ldspec,
                                                    const cx<double> *__restrict__ twL) {
     constexpr int TH = L / E;
-    extern __shared__ unsigned char smem_raw[];
+    extern __shared__ __align__(16) unsigned char smem_raw[];
     cx<double> *buf = reinterpret_cast<cx<double> *>(smem_raw);
     const int kb = blockIdx.x, t = threadIdx.x;
     const int src = kb == H ? 0 : kb;
@@ -550,7 +550,7 @@ __global__ __launch_bounds__(512) void k_cart_rows(const T *__restrict__ sigma, 
                                                    T idy, cx2<T> *__restrict__ out,
                                                    const cx<T> *__restrict__ twN,
                                                    unsigned *__restrict__ gscale) {
-    extern __shared__ unsigned char smem_raw[];
+    extern __shared__ __align__(16) unsigned char smem_raw[];
     body_cart_rows<T, M, E>(blockIdx.x, blockDim.x / (M / E), reinterpret_cast<cx<T> *>(smem_raw),
                             sigma, n_x, n_y, idy, out, twN, gscale);
 }
@@ -561,7 +561,7 @@ __global__ __launch_bounds__(512) void k_cart_c2r(const cx2<T> *__restrict__ in,
                                                   T *__restrict__ out1,
                                                   const cx<T> *__restrict__ twN,
                                                   unsigned *__restrict__ gscale) {
-    extern __shared__ unsigned char smem_raw[];
+    extern __shared__ __align__(16) unsigned char smem_raw[];
     body_cart_c2r<T, M, E>(blockIdx.x, blockDim.x / (M / E), reinterpret_cast<cx<T> *>(smem_raw),
                            in, n_x, n_y, out0, out1, twN, gscale);
 }
@@ -574,7 +574,7 @@ __global__ __launch_bounds__(512) void k_cart_cols(const cx2<T> *__restrict__ SD
                                                    int ldspec, T ca, T c0, T cn,
                                                    const cx<T> *__restrict__ twL, int per_xcd,
                                                    int n_groups, unsigned *__restrict__ gscale) {
-    extern __shared__ unsigned char smem_raw[];
+    extern __shared__ __align__(16) unsigned char smem_raw[];
     const int grp = cart_xcd_group(blockIdx.x, per_xcd);
     if (grp >= n_groups) return;   // whole workgroup leaves together
     body_cart_cols<T, L, E>(grp, blockDim.x / (L / E), reinterpret_cast<cx<T> *>(smem_raw), SD,

@@ -25,7 +25,7 @@ __global__ __launch_bounds__(512) void k_rows_r2c(const T *__restrict__ in0,
                                                   unsigned *__restrict__ gscale,
                                                   const T *__restrict__ xin,
                                                   cx<T> *__restrict__ xout, int n_x) {
-    extern __shared__ unsigned char smem_raw[];
+    extern __shared__ __align__(16) unsigned char smem_raw[];
     const int G = blockDim.x / (M / E);
     cx<T> *const buf = reinterpret_cast<cx<T> *>(smem_raw);
     if constexpr (C == 1)
@@ -43,7 +43,7 @@ __global__ __launch_bounds__(512) void k_rows_c2r(const cx<T> *__restrict__ in, 
                                                   unsigned *__restrict__ gscale, int turn,
                                                   const cx<T> *__restrict__ xin,
                                                   T *__restrict__ xout, int n_x) {
-    extern __shared__ unsigned char smem_raw[];
+    extern __shared__ __align__(16) unsigned char smem_raw[];
     const int G = blockDim.x / (M / E);
     cx<T> *const buf = reinterpret_cast<cx<T> *>(smem_raw);
     if constexpr (C == 1)
@@ -70,7 +70,7 @@ __global__ __launch_bounds__(512) void k_cols_fwd(const cx<T> *__restrict__ S,
                                                   const cx<T> *__restrict__ twL, int per_xcd,
                                                   int n_groups, unsigned *__restrict__ gscale,
                                                   T c4) {
-    extern __shared__ unsigned char smem_raw[];
+    extern __shared__ __align__(16) unsigned char smem_raw[];
     const int grp = xcd_group(blockIdx.x, per_xcd);
     if (grp >= n_groups) return;  // whole workgroup leaves together
     const int G = blockDim.x / (L / E);
@@ -111,7 +111,7 @@ __global__ __launch_bounds__(512) void k_cols_adj(const cx2<T> *__restrict__ V,
                                                   const cx<T> *__restrict__ twL, int per_xcd,
                                                   int n_groups, unsigned *__restrict__ gscale,
                                                   T c4, int n_v) {
-    extern __shared__ unsigned char smem_raw[];
+    extern __shared__ __align__(16) unsigned char smem_raw[];
     const int grp = xcd_group(blockIdx.x, per_xcd);
     if (grp >= n_groups) return;
     body_cols_adj<T, L, E, false, SO>(grp, blockDim.x / (L / E),

@@ -23,7 +23,7 @@ __global__ __launch_bounds__(512) void k_rows_r2cq(const T *__restrict__ in0,
                                                    unsigned *__restrict__ gscale,
                                                    const T *__restrict__ xin,
                                                    cx<T> *__restrict__ xout, int n_x) {
-    extern __shared__ unsigned char smem_raw[];
+    extern __shared__ __align__(16) unsigned char smem_raw[];
     const int G = blockDim.x / (P / E);
     cx<T> *const buf = reinterpret_cast<cx<T> *>(smem_raw);
     if constexpr (C == 1)
@@ -41,7 +41,7 @@ __global__ __launch_bounds__(512) void k_rows_c2rq(const cx<T> *__restrict__ in,
                                                    unsigned *__restrict__ gscale, int turn,
                                                    const cx<T> *__restrict__ xin,
                                                    T *__restrict__ xout, int n_x) {
-    extern __shared__ unsigned char smem_raw[];
+    extern __shared__ __align__(16) unsigned char smem_raw[];
     const int G = blockDim.x / (P / E);
     cx<T> *const buf = reinterpret_cast<cx<T> *>(smem_raw);
     if constexpr (C == 1)

@@ -584,7 +584,7 @@ __global__ __launch_bounds__(512) void k_fold(const cx<double> *__restrict__ row
                                               const cx<double> *__restrict__ twL, int so,
                                               double c4) {
     constexpr int TH = L / E;
-    extern __shared__ unsigned char smem_raw[];
+    extern __shared__ __align__(16) unsigned char smem_raw[];
     cx<double> *buf = reinterpret_cast<cx<double> *>(smem_raw);
     const int kb = blockIdx.x, t = threadIdx.x;
     const int src = kb == M ? 0 : kb;
