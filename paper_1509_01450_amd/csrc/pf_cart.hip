@@ -765,8 +765,12 @@ int cols_l(const CartPlan &c, const void *SD, void *Z, hipStream_t st) {
     const Shape s = cart_cols_shape(L, sizeof(T) == 8);
     const int n_groups = (c.H + s.G - 1) / s.G;
     const int per_xcd = (n_groups + 7) / 8;
-    if constexpr (sizeof(T) == 4 && L / E >= 64 && cart_cols_pf_lds<T, L, E>() <= 80 * 1024) {
-        // FP32 with the (E'_x, Q_x) prefetch (32-bit offsets over that half)
+    // The (E'_x, Q_x) prefetch where its LDS keeps the occupancy the
+    // registers allow: FP32 within 80 KB (two workgroups per CU), and any
+    // column of 512 threads (one workgroup per CU either way) within 144 KB.
+    constexpr size_t kPfLds = L / E >= 512 ? 144 * 1024 : (sizeof(T) == 4 ? 80 * 1024 : 0);
+    if constexpr (L / E >= 64 && cart_cols_pf_lds<T, L, E>() <= kPfLds) {
+        // 32-bit offsets over that half
         if ((size_t)c.H * c.ldspec * sizeof(cx2<T>) >= ((size_t)1 << 31)) {
             set_error("Cartesian spectra too large for the column pass prefetch");
             return PF_EUNSUPPORTED;
