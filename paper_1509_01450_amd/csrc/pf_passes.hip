@@ -213,14 +213,17 @@ int allow_lds(K kern, size_t lds) {
     return PF_OK;
 }
 
-// The static-LDS forward column kernel for a compile-time G, when its LDS
+// The static-LDS column kernel for a compile-time G, when its LDS
 // (transform buffer and prefetch region) fits the 144 KB the shape check
-// allows; false (nothing launched) otherwise.
+// allows, or 159 KB for a workgroup of 512 threads (one per CU whatever its
+// LDS: the registers of a column body allow no more); false (nothing
+// launched) otherwise.
 template <typename T, int N, int E, int G>
 constexpr bool cols_pf_fits() {
-    return G * (N / E) <= 512 && (size_t)G * padded_len(N) * sizeof(cx<T>) +
-                                         (size_t)G * spec_prefetch_len<N, E>() * sizeof(cx2<T>) <=
-                                     (size_t)144 * 1024;
+    return G * (N / E) <= 512 &&
+           (size_t)G * padded_len(N) * sizeof(cx<T>) +
+                   (size_t)G * spec_prefetch_len<N, E>() * sizeof(cx2<T>) <=
+               (size_t)(G * (N / E) == 512 ? 159 : 144) * 1024;
 }
 
 // Slope order 4 has static-LDS instances for the points per thread its
