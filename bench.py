@@ -292,6 +292,36 @@ def cpu_baseline(sample_seconds=15.0):
                       "O((N_r N_phi)^2) sums, %.1f s)" % (n, dt)}
 
 
+def cartesian_detail(pf, torch, np, dev, NC, K, W):
+    """Cartesian NC x NC grid (second-order method, sigma_D2 disk), FP32 and
+    FP64: call time and the three passes' times, bytes and rates."""
+    log("cartesian %d x %d" % (NC, NC))
+    cart = {}
+    xc = (np.arange(NC) + 0.5) / NC - 0.5
+    Xc, Yc = np.meshgrid(xc, xc, indexing="ij")
+    sig_c = np.clip(1.0 - (Xc ** 2 + Yc ** 2) / 0.25 ** 2, 0.0, None) ** 1.5
+    for dt in ("f32", "f64"):
+        t0 = time.perf_counter()
+        pc = pf.CartPlan(NC, NC, 1.0 / NC, 1.0 / NC, dtype=dt, method="second")
+        torch.cuda.synchronize()
+        bc = time.perf_counter() - t0
+        sc = torch.tensor(sig_c, dtype=pc.torch_dtype, device=dev)
+        oc = (torch.empty_like(sc), torch.empty_like(sc))
+        msc = time_calls(torch, lambda: pc.forces(sc, oc), max(K // 2, 10), W)
+        pmc = pc.timed(sc, reps=100)
+        _, _, Lx, Ly = pc.geometry()
+        bts = cart_path_bytes(NC, NC, Lx, Ly, 4 if dt == "f32" else 8)
+        cart[dt] = {"ms_per_call": msc, "cells_per_s": NC * NC / (msc * 1e-3), "pass_ms": pmc,
+                    "pass_bytes": list(bts),
+                    "pass_GBs": [b / (t * 1e-3) / 1e9 for b, t in zip(bts, pmc)],
+                    "pass_B_frac_of_hbm_peak": bts[1] / (pmc[1] * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                    "table_build_s": bc}
+        pc.close()
+    cart["workload"] = ("Cartesian %d x %d cells on [-0.5, 0.5]^2, sigma_D2 disk "
+                        "(alpha = 0.25), second-order method" % (NC, NC))
+    return cart
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -302,6 +332,8 @@ def main():
     ap.add_argument("--forward-only", action="store_true")
     ap.add_argument("--transpose", action="store_true")
     ap.add_argument("--copy-reference", action="store_true")
+    ap.add_argument("--cartesian", type=int, default=0, metavar="N",
+                    help="time only the Cartesian N x N plans (profiling runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the single-disk and batched paths run on "
@@ -319,6 +351,9 @@ def main():
         return 1
     dev = torch.device("cuda:0")
     K, W = args.steps, args.warmup
+    if args.cartesian:
+        print(json.dumps(cartesian_detail(pf, torch, np, dev, args.cartesian, K, W)))
+        return 0
     cells = N_R * N_PHI
     out = {"metric": METRIC, "unit": "cells/s", "n_gpus": 1, "steps": K, "warmup": W,
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
@@ -490,31 +525,7 @@ def main():
                    "table_build_s": build_b}
 
     # ---- Cartesian grid (second-order method, sigma_D2 disk) -----------------
-    log("cartesian 1024 x 1024")
-    cart = {}
-    NC = 1024
-    xc = (np.arange(NC) + 0.5) / NC - 0.5
-    Xc, Yc = np.meshgrid(xc, xc, indexing="ij")
-    sig_c = np.clip(1.0 - (Xc ** 2 + Yc ** 2) / 0.25 ** 2, 0.0, None) ** 1.5
-    for dt in ("f32", "f64"):
-        t0 = time.perf_counter()
-        pc = pf.CartPlan(NC, NC, 1.0 / NC, 1.0 / NC, dtype=dt, method="second")
-        torch.cuda.synchronize()
-        bc = time.perf_counter() - t0
-        sc = torch.tensor(sig_c, dtype=pc.torch_dtype, device=dev)
-        oc = (torch.empty_like(sc), torch.empty_like(sc))
-        msc = time_calls(torch, lambda: pc.forces(sc, oc), max(K // 2, 10), W)
-        pmc = pc.timed(sc, reps=100)
-        _, _, Lx, Ly = pc.geometry()
-        bts = cart_path_bytes(NC, NC, Lx, Ly, 4 if dt == "f32" else 8)
-        cart[dt] = {"ms_per_call": msc, "cells_per_s": NC * NC / (msc * 1e-3), "pass_ms": pmc,
-                    "pass_bytes": list(bts),
-                    "pass_GBs": [b / (t * 1e-3) / 1e9 for b, t in zip(bts, pmc)],
-                    "pass_B_frac_of_hbm_peak": bts[1] / (pmc[1] * 1e-3) / 1e9 / HBM_PEAK_GBS,
-                    "table_build_s": bc}
-        pc.close()
-    cart["workload"] = ("Cartesian 1024 x 1024 cells on [-0.5, 0.5]^2, sigma_D2 disk "
-                        "(alpha = 0.25), second-order method")
+    cart = cartesian_detail(pf, torch, np, dev, 1024, K, W)
 
     # ---- patches: the paper's polar case 1 at N_d = 1024 ---------------------
     log("patches: polar case 1, 1024 x 1024 destination")
