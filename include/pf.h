@@ -306,9 +306,11 @@ int pf_plan_schedule(pf_plan plan, int out[8]);
 /* Set the launch shapes of a built plan, in[8] in the layout of
  * pf_plan_schedule, in place of the autotuned or default ones (for
  * reproducible shapes without tuning, or to run a given kernel variant).
- * Each shape must fit its transform: points per thread 4, 8 or 16 for the
- * rows and 8 or 16 for the columns, at most the transform length, at most
- * 512 threads per workgroup, and the workgroup's LDS within 144 KB; a
+ * Each shape must fit its transform: points per thread 4, 8 or 16 for
+ * power-of-two rows (rows of n_phi = 2 Q P points: 4, or 8 in FP32, for
+ * Q = 3 and 2 for Q = 9, at most P) and 8 or 16 for the columns, at most
+ * the transform length, at most 512 threads per workgroup, and the
+ * workgroup's LDS within 144 KB; a
  * column shape also needs a power-of-two number of columns per workgroup
  * and a workgroup of whole 64-lane waves.  Otherwise PF_EINVAL (checked
  * first, against the plan's current precision, built or not) and the plan
