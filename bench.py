@@ -15,11 +15,14 @@ cores.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
                        [--no-batched] [--forward-only [--transpose]] [--copy-reference]
+                       [--cartesian N] [--batched-only]
 --forward-only runs only the FP32 forward (headline, pass times, roofline),
 for profiler runs, and with --transpose the FP32 transpose of the same plan
 as well; --copy-reference adds five 64 MiB device-to-device copies
 at the end, the known-size reference that calibrates the FETCH_SIZE and
-WRITE_SIZE counters.  Prints one JSON line on stdout.
+WRITE_SIZE counters; --cartesian N and --batched-only time only the
+Cartesian N x N plans or only the 64-disk batch (profiler runs).  Prints one
+JSON line on stdout.
 """
 from __future__ import annotations
 
@@ -292,6 +295,38 @@ def cpu_baseline(sample_seconds=15.0):
                       "O((N_r N_phi)^2) sums, %.1f s)" % (n, dt)}
 
 
+def batched_detail(pf, torch, np, workloads, dev, K):
+    """The 64-disk FP32 batch: eager and graph-replayed call times, cells/s,
+    path bytes and their fraction of the HBM peak."""
+    log("batched: 64 disks")
+    sizes = workloads.batch_sizes(64)
+    plans, sig_b = [], []
+    t0 = time.perf_counter()
+    for d, (nr, nphi) in enumerate(sizes):
+        pb = pf.Plan(nr, nphi, 0.01, 100.0, dtype="f32")
+        r_b, _, _ = pb.geometry()
+        ph_b = (np.arange(nphi) + 0.5) * (2 * np.pi / nphi)
+        plans.append(pb)
+        sig_b.append(torch.tensor(workloads.multiarm_disk(r_b, ph_b, d), dtype=torch.float32,
+                                  device=dev))
+    torch.cuda.synchronize()
+    build_b = time.perf_counter() - t0
+    outs = [(torch.empty_like(s), torch.empty_like(s)) for s in sig_b]
+    msb = time_calls(torch, lambda: pf.forces_batched(plans, sig_b, outs), max(K // 4, 10), 5)
+    msg = time_graph(torch, lambda: pf.forces_batched(plans, sig_b, outs), max(K // 4, 10), 5)
+    bcells = sum(nr * nphi for nr, nphi in sizes)
+    # transform length along u: the power of two at or above 2 N_r
+    bbytes = sum(sum(path_bytes(nr, nphi, 1 << (2 * nr - 1).bit_length(), 4))
+                 for nr, nphi in sizes)
+    batched = {"workload": "64 disks, N_r in {256..1024}, N_phi in {256..2048}, FP32",
+               "cells": bcells, "ms_per_call": msb, "cells_per_s": bcells / (msb * 1e-3),
+               "path_bytes": bbytes,
+               "path_frac_of_hbm_peak": bbytes / (msb * 1e-3) / 1e9 / HBM_PEAK_GBS,
+               "graph_ms_per_call": msg, "graph_cells_per_s": bcells / (msg * 1e-3),
+               "table_build_s": build_b}
+    return batched
+
+
 def cartesian_detail(pf, torch, np, dev, NC, K, W):
     """Cartesian NC x NC grid (second-order method, sigma_D2 disk), FP32 and
     FP64: call time and the three passes' times, bytes and rates."""
@@ -334,6 +369,8 @@ def main():
     ap.add_argument("--copy-reference", action="store_true")
     ap.add_argument("--cartesian", type=int, default=0, metavar="N",
                     help="time only the Cartesian N x N plans (profiling runs)")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="time only the 64-disk batch (profiling runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the single-disk and batched paths run on "
@@ -353,6 +390,9 @@ def main():
     K, W = args.steps, args.warmup
     if args.cartesian:
         print(json.dumps(cartesian_detail(pf, torch, np, dev, args.cartesian, K, W)))
+        return 0
+    if args.batched_only:
+        print(json.dumps(batched_detail(pf, torch, np, workloads, dev, K)))
         return 0
     cells = N_R * N_PHI
     out = {"metric": METRIC, "unit": "cells/s", "n_gpus": 1, "steps": K, "warmup": W,
@@ -497,32 +537,7 @@ def main():
     # ---- batched ------------------------------------------------------------
     batched = None
     if not args.no_batched:
-        log("batched: 64 disks")
-        sizes = workloads.batch_sizes(64)
-        plans, sig_b = [], []
-        t0 = time.perf_counter()
-        for d, (nr, nphi) in enumerate(sizes):
-            pb = pf.Plan(nr, nphi, 0.01, 100.0, dtype="f32")
-            r_b, _, _ = pb.geometry()
-            ph_b = (np.arange(nphi) + 0.5) * (2 * np.pi / nphi)
-            plans.append(pb)
-            sig_b.append(torch.tensor(workloads.multiarm_disk(r_b, ph_b, d), dtype=torch.float32,
-                                      device=dev))
-        torch.cuda.synchronize()
-        build_b = time.perf_counter() - t0
-        outs = [(torch.empty_like(s), torch.empty_like(s)) for s in sig_b]
-        msb = time_calls(torch, lambda: pf.forces_batched(plans, sig_b, outs), max(K // 4, 10), 5)
-        msg = time_graph(torch, lambda: pf.forces_batched(plans, sig_b, outs), max(K // 4, 10), 5)
-        bcells = sum(nr * nphi for nr, nphi in sizes)
-        # transform length along u: the power of two at or above 2 N_r
-        bbytes = sum(sum(path_bytes(nr, nphi, 1 << (2 * nr - 1).bit_length(), 4))
-                     for nr, nphi in sizes)
-        batched = {"workload": "64 disks, N_r in {256..1024}, N_phi in {256..2048}, FP32",
-                   "cells": bcells, "ms_per_call": msb, "cells_per_s": bcells / (msb * 1e-3),
-                   "path_bytes": bbytes,
-                   "path_frac_of_hbm_peak": bbytes / (msb * 1e-3) / 1e9 / HBM_PEAK_GBS,
-                   "graph_ms_per_call": msg, "graph_cells_per_s": bcells / (msg * 1e-3),
-                   "table_build_s": build_b}
+        batched = batched_detail(pf, torch, np, workloads, dev, K)
 
     # ---- Cartesian grid (second-order method, sigma_D2 disk) -----------------
     cart = cartesian_detail(pf, torch, np, dev, 1024, K, W)
